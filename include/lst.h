@@ -1,0 +1,208 @@
+/*
+ * lst.h -- C ABI of the MI355X Line Segment Tracking object-building engine.
+ *
+ * The engine takes the hits of a double-sensor outer tracker plus inner-tracker
+ * track seeds ("pixel line segments", pLS) and returns the objects of the Line
+ * Segment Tracking chain (Sec. 1 of the paper): mini-doublets (MD, one hit on
+ * each sensor of a module), line segments (LS, two MDs on connected modules,
+ * linked over a precomputed module connection map), T3 (two LSs sharing an MD),
+ * T5 (two T3s sharing an MD), pT3 / pT5 (a pLS linked to a T3 / T5) and the
+ * track candidates (TC): pT5s, pT3s, T5s and unlinked pLSs (Sec. 1, list of
+ * propagated objects).
+ *
+ * Conventions
+ *   - Every function returns lst_status: 0 = OK, 1 = PENDING, < 0 = error.
+ *     No C++ exception crosses this interface.
+ *   - After a device (HIP) error a context is failed for good: every later
+ *     call on it returns LST_ERR_DEVICE; destroy it.
+ *   - Units: cm, GeV, T.  Azimuth in radians.  Hit coordinates are IEEE
+ *     binary32.  Geometry is binary64.
+ *   - Object lists are in canonical order -- MDs by (module, lower hit, upper
+ *     hit), every other list lexicographic in its constituent indices -- and
+ *     every index is local to its event: hit indices refer to the
+ *     caller's input order, MD/LS/T3/T5/pLS indices to the lists of the same
+ *     output.  A result is therefore identical whether the event ran alone, in
+ *     a batch or in the served mix.
+ *   - lst_run_event / lst_run_batch / lst_batch_* are serialised per context
+ *     (do not call them concurrently on one context); lst_submit / lst_poll
+ *     are thread-safe.
+ */
+#ifndef LST_H
+#define LST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lst_status;
+#define LST_OK 0
+#define LST_PENDING 1
+#define LST_ERR_INVALID_ARG -1
+#define LST_ERR_DEVICE -2
+#define LST_ERR_NO_GEOMETRY -3
+#define LST_ERR_BAD_GEOMETRY -4
+#define LST_ERR_BAD_MODULE -5
+#define LST_ERR_NONFINITE -6
+#define LST_ERR_OOM -7
+#define LST_ERR_TOO_LARGE -8
+#define LST_ERR_QUEUE_FULL -9
+#define LST_ERR_UNKNOWN_TICKET -10
+
+typedef struct lst_ctx lst_ctx;
+
+/* Engine parameters.  The window constants derive from a prompt helix with
+ * curvature up to kappa_max = 0.299792458e-2 * B / pt_min (the pT threshold
+ * that tunes the hit-pair search windows, Sec. 1) and a vertex within +/- L
+ * along the beam, widened by n_sigma times the hit resolutions. */
+typedef struct {
+    int32_t device;          /* HIP device ordinal */
+    double B;                /* field along +z [T] (default 3.8) */
+    double pt_min;           /* pT threshold [GeV] (default 0.8) */
+    double L;                /* luminous-region half length [cm] (default 15) */
+    double sig_rphi;         /* hit resolution along r-phi [cm] (default 30e-4) */
+    double sig_c;            /* z (barrel) / r (endcap) resolution [cm] (default 0.1) */
+    double n_sigma;          /* window width in resolutions (default 3) */
+    uint32_t flags;          /* LST_FLAG_* (default LST_FLAG_BEND) */
+    uint32_t max_batch;      /* largest number of events per launch (default 64) */
+    uint32_t n_slots;        /* served path: device arenas / streams working in parallel (default 2) */
+    uint32_t queue_depth;    /* served path: most events waiting or in flight (default 1024) */
+    uint64_t mem_budget;     /* device bytes the served path may hold (0 = 32 GiB) */
+} lst_params;
+
+#define LST_FLAG_BEND 1u     /* line segments: MD bend consistent with the segment's (barrel pairs) */
+
+/* One double-sensor module.  Modules must be listed with consecutive ids
+ * 0..n-1 in this array.  Barrel modules are cylinder patches, endcap modules
+ * are annulus sectors on planes z = const.  "Lower" is the sensor nearer the
+ * interaction point. */
+typedef struct {
+    uint32_t kind;           /* LST_BARREL or LST_ENDCAP */
+    uint32_t layer;          /* barrel layer / disk index, increasing outward from 0 */
+    int32_t side;            /* 0 for barrel; +1 / -1 for the endcap at +z / -z */
+    uint32_t pad;
+    double s_lo, s_hi;       /* sensor radii (barrel) or signed plane z (endcap) */
+    double c_min, c_max;     /* z extent (barrel) or r extent (endcap) */
+    double phi_min, phi_max; /* azimuth range [phi_min, phi_max), within [0, 2 pi] */
+} lst_module_desc;
+
+#define LST_BARREL 0u
+#define LST_ENDCAP 1u
+
+/* Input of one event.  Host pointers unless flags & LST_DEVICE_PTRS (device
+ * pointers, e.g. from torch tensors on the context's device).  Borrowed for
+ * the duration of the call (lst_submit copies them before returning). */
+typedef struct {
+    uint32_t n_hits;
+    uint32_t n_pls;
+    const float *x, *y, *z;  /* hit positions */
+    const uint32_t *module;  /* module id of each hit */
+    const uint8_t *sensor;   /* 0 = lower, 1 = upper sensor */
+    const float *pls_par;    /* 5 per seed: q/pT [1/GeV], phi0, cot(theta), d0 [cm], z0 [cm] */
+    const float *pls_cov;    /* 15 per seed: upper triangle of the 5x5 covariance, row major */
+    uint32_t flags;          /* LST_DEVICE_PTRS */
+    uint32_t pad;
+} lst_event_in;
+
+#define LST_DEVICE_PTRS 1u
+
+/* Track-candidate types, in output order */
+#define LST_TC_PT5 0u
+#define LST_TC_PT3 1u
+#define LST_TC_T5 2u
+#define LST_TC_PLS 3u
+
+/* Result of one event, owned by the library (free with lst_free_output).
+ * Pairs are stored flat: element 2*i and 2*i+1. */
+typedef struct {
+    uint32_t n_md, n_ls, n_t3, n_t5, n_pt3, n_pt5, n_tc;
+    uint32_t status;         /* lst_status of this event (served path) */
+    uint32_t *md;            /* (hit on lower sensor, hit on upper sensor) */
+    uint32_t *ls;            /* (inner MD, outer MD) */
+    uint32_t *t3;            /* (inner LS, outer LS); inner LS's outer MD = outer LS's inner MD */
+    uint32_t *t5;            /* (inner T3, outer T3); inner T3's outer MD = outer T3's inner MD */
+    uint32_t *pt3;           /* (pLS, T3) */
+    uint32_t *pt5;           /* (pLS, T5) */
+    uint32_t *tc;            /* (type LST_TC_*, index into pt5 / pt3 / t5 / pLS) */
+    float *t3_kappa;         /* signed transverse curvature of each T3 [1/cm] */
+    double latency_us;       /* served path: completion minus submission */
+    uint64_t ticket;
+} lst_event_out;
+
+void lst_default_params(lst_params *p);
+
+/* Create a context on p->device (p = NULL: defaults).  Errors: INVALID_ARG,
+ * DEVICE. */
+lst_status lst_create(const lst_params *p, lst_ctx **out);
+
+/* Load the detector: validates the module table, derives per-module and
+ * per-module-pair window constants in binary64 (rounded once to binary32),
+ * builds the module connection map (Sec. 1: "precomputed connection maps")
+ * and the seed-lookup surface table, and uploads them.  m is borrowed for the
+ * call.  Errors: INVALID_ARG, BAD_GEOMETRY, OOM, DEVICE. */
+lst_status lst_load_geometry(lst_ctx *ctx, const lst_module_desc *m, uint32_t n);
+
+/* The connection map in CSR form: module A connects to dst[begin[A] ..
+ * begin[A+1]).  Pointers into library-owned host memory, valid until the next
+ * lst_load_geometry or lst_destroy.  Errors: NO_GEOMETRY. */
+lst_status lst_get_connection_map(lst_ctx *ctx, const uint32_t **begin,
+                                  const uint32_t **dst, uint32_t *n_edges);
+
+/* Host-only variant (no device needed): builds the connection map of a module
+ * table with parameters p into newly allocated arrays; release with
+ * lst_free_map.  Errors: INVALID_ARG, BAD_GEOMETRY, OOM. */
+lst_status lst_build_connection_map(const lst_params *p, const lst_module_desc *m, uint32_t n,
+                                    uint32_t **begin, uint32_t **dst, uint32_t *n_edges);
+void lst_free_map(uint32_t *begin, uint32_t *dst);
+
+/* Run one event synchronously (the plain per-event path).  *out is allocated
+ * by the library.  Errors: NO_GEOMETRY, BAD_MODULE (module id out of range or
+ * sensor > 1), NONFINITE (NaN/inf coordinate or seed parameter), OOM,
+ * TOO_LARGE (event above the device memory budget), DEVICE. */
+lst_status lst_run_event(lst_ctx *ctx, const lst_event_in *ev, lst_event_out **out);
+
+/* Run n events in one launch of the chain (the batched path); outs[i] receives
+ * event i.  Same errors as lst_run_event; INVALID_ARG if n > max_batch. */
+lst_status lst_run_batch(lst_ctx *ctx, const lst_event_in *evs, uint32_t n, lst_event_out **outs);
+
+/* Served path.  lst_submit copies the event and returns a ticket at once;
+ * a scheduler admits waiting events into free device slots by their predicted
+ * device-memory footprint, forms micro-batches and runs them on parallel
+ * streams.  lst_poll returns LST_OK and hands over the output once (the ticket
+ * is then consumed) or LST_PENDING; timeout_us = 0 does not wait, -1 waits.
+ * Errors: QUEUE_FULL, TOO_LARGE, UNKNOWN_TICKET, DEVICE, input errors. */
+lst_status lst_submit(lst_ctx *ctx, const lst_event_in *ev, uint64_t *ticket);
+lst_status lst_poll(lst_ctx *ctx, uint64_t ticket, int64_t timeout_us, lst_event_out **out);
+
+/* Device-resident benchmarking path: lst_batch_upload copies n events into the
+ * plain path's device arena (sizing it); lst_batch_execute runs the whole chain
+ * on them `repeats` times (use_graph: replay a captured hipGraph) and returns
+ * the device time of all repeats in *ms; with timing on it also accumulates
+ * per-kernel durations, read by lst_kernel_times (names, total ms, launches;
+ * arrays of length at least *n on input, number written on output);
+ * lst_batch_download returns the outputs of the last execute.
+ * Errors: as lst_run_batch. */
+lst_status lst_batch_upload(lst_ctx *ctx, const lst_event_in *evs, uint32_t n);
+lst_status lst_batch_execute(lst_ctx *ctx, uint32_t repeats, int32_t use_graph, int32_t timing,
+                             double *ms);
+lst_status lst_kernel_times(lst_ctx *ctx, const char **names, double *total_ms,
+                            uint32_t *launches, uint32_t *n);
+lst_status lst_batch_download(lst_ctx *ctx, lst_event_out **outs);
+/* Object totals of the last execute over the whole batch: md, ls, t3, t5,
+ * pt3, pt5, tc, and candidate counts of the md, ls, t3, t5, pt3 and pt5
+ * stages (13 values). */
+lst_status lst_batch_counts(lst_ctx *ctx, uint64_t counts[13]);
+
+void lst_free_output(lst_event_out *out);
+
+/* Drains in-flight served events, then frees everything. */
+void lst_destroy(lst_ctx *ctx);
+
+const char *lst_status_str(lst_status s);
+const char *lst_last_error(const lst_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LST_H */

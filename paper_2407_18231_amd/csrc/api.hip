@@ -1,0 +1,1140 @@
+// api.hip -- the C ABI of liblst: contexts, device arenas, the per-event,
+// batched and device-resident paths, output assembly, and the served path
+// (submit / poll with a scheduler thread and parallel device slots).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+#include "engine.h"
+#include "lst.h"
+
+namespace lst {
+namespace {
+
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Caps {
+    uint32_t ev = 0, hits = 0, pls = 0, md = 0, ls = 0, t3 = 0, t5 = 0, pt3 = 0, pt5 = 0;
+};
+
+uint32_t clamp32(uint64_t v) { return v > 0xFFFFFFF0ull ? 0xFFFFFFF0u : (uint32_t)v; }
+
+// Initial capacities from the batch size; measured ratios at PU200-PU300 are
+// MD ~0.25, LS ~1.5-2.5, T3 ~0.6-1 per hit, pT3 ~3 and pT5 ~1 per seed.
+Caps plan_caps(uint32_t n_ev, uint64_t hits, uint64_t pls)
+{
+    Caps c;
+    c.ev = n_ev;
+    c.hits = clamp32(hits);
+    c.pls = clamp32(pls);
+    c.md = clamp32(hits / 2 + 1024);
+    c.ls = clamp32(3 * hits + 4096);
+    c.t3 = clamp32(2 * hits + 4096);
+    c.t5 = clamp32(hits / 2 + 4096);
+    c.pt3 = clamp32(8 * pls + 4096);
+    c.pt5 = clamp32(4 * pls + 4096);
+    return c;
+}
+
+// Sub-allocates the device arena; with base == nullptr only sums the sizes.
+struct Carver {
+    char *base;
+    size_t off = 0;
+    template <typename T>
+    T *take(size_t n)
+    {
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += align_up(n * sizeof(T) + 16);
+        return p;
+    }
+};
+
+void carve_inputs(Carver &cv, Batch &b)
+{
+    b.in_x = cv.take<float>(b.cap_hits);
+    b.in_y = cv.take<float>(b.cap_hits);
+    b.in_z = cv.take<float>(b.cap_hits);
+    b.in_mod = cv.take<uint32_t>(b.cap_hits);
+    b.in_sen = cv.take<uint8_t>(b.cap_hits);
+    b.in_par = cv.take<float>(5ull * b.cap_pls);
+    b.in_cov = cv.take<float>(15ull * b.cap_pls);
+    b.ev_hit_off = cv.take<uint32_t>(b.cap_ev + 1);
+    b.ev_pls_off = cv.take<uint32_t>(b.cap_ev + 1);
+}
+
+void carve_work(Carver &cv, Batch &b, uint32_t n_mod, uint32_t n_surf, uint32_t nphi)
+{
+    const size_t bins = (size_t)b.cap_ev * 2 * n_mod;
+    const size_t units = (size_t)b.cap_ev * n_mod;
+    const size_t bk = (size_t)b.cap_ev * n_surf * nphi;
+    const size_t tcu = (size_t)b.cap_pt3 + b.cap_t5 + b.cap_pls;
+    b.bin_cnt = cv.take<uint32_t>(bins + 1);
+    b.bin_off = cv.take<uint32_t>(bins + 1);
+    b.hbin = cv.take<uint32_t>(b.cap_hits);
+    b.hrank = cv.take<uint32_t>(b.cap_hits);
+    b.perm = cv.take<uint32_t>(b.cap_hits);
+    b.hx = cv.take<float>(b.cap_hits);
+    b.hy = cv.take<float>(b.cap_hits);
+    b.hz = cv.take<float>(b.cap_hits);
+    b.hr = cv.take<float>(b.cap_hits);
+    b.hin = cv.take<uint32_t>(b.cap_hits);
+    b.md_cnt = cv.take<uint32_t>(units + 1);
+    b.md_off = cv.take<uint32_t>(units + 1);
+    b.md_x = cv.take<float>(b.cap_md);
+    b.md_y = cv.take<float>(b.cap_md);
+    b.md_z = cv.take<float>(b.cap_md);
+    b.md_r = cv.take<float>(b.cap_md);
+    b.md_beta = cv.take<float>(b.cap_md);
+    b.md_u = cv.take<uint32_t>(b.cap_md);
+    b.md_hlo = cv.take<uint32_t>(b.cap_md);
+    b.md_hup = cv.take<uint32_t>(b.cap_md);
+    b.ls_cnt = cv.take<uint32_t>((size_t)b.cap_md + 1);
+    b.ls_off = cv.take<uint32_t>((size_t)b.cap_md + 1);
+    b.ls_a = cv.take<uint32_t>(b.cap_ls);
+    b.ls_b = cv.take<uint32_t>(b.cap_ls);
+    b.t3_cnt = cv.take<uint32_t>((size_t)b.cap_ls + 1);
+    b.t3_off = cv.take<uint32_t>((size_t)b.cap_ls + 1);
+    b.t3_l1 = cv.take<uint32_t>(b.cap_t3);
+    b.t3_l2 = cv.take<uint32_t>(b.cap_t3);
+    b.t3_a = cv.take<uint32_t>(b.cap_t3);
+    b.t3_c = cv.take<uint32_t>(b.cap_t3);
+    b.t3_k = cv.take<float>(b.cap_t3);
+    b.t3_sk = cv.take<float>(b.cap_t3);
+    b.t5_cnt = cv.take<uint32_t>((size_t)b.cap_t3 + 1);
+    b.t5_off = cv.take<uint32_t>((size_t)b.cap_t3 + 1);
+    b.t5_u = cv.take<uint32_t>(b.cap_t5);
+    b.t5_w = cv.take<uint32_t>(b.cap_t5);
+    b.t5_k = cv.take<float>(b.cap_t5);
+    b.t5_sk = cv.take<float>(b.cap_t5);
+    b.bk3_cnt = cv.take<uint32_t>(bk + 1);
+    b.bk3_off = cv.take<uint32_t>(bk + 1);
+    b.bk3_id = cv.take<uint32_t>(b.cap_t3);
+    b.bk3_rank = cv.take<uint32_t>(b.cap_t3);
+    b.bk3_items = cv.take<uint32_t>(b.cap_t3);
+    b.bk5_cnt = cv.take<uint32_t>(bk + 1);
+    b.bk5_off = cv.take<uint32_t>(bk + 1);
+    b.bk5_id = cv.take<uint32_t>(b.cap_t5);
+    b.bk5_rank = cv.take<uint32_t>(b.cap_t5);
+    b.bk5_items = cv.take<uint32_t>(b.cap_t5);
+    b.pt3_cnt = cv.take<uint32_t>((size_t)b.cap_pls + 1);
+    b.pt3_off = cv.take<uint32_t>((size_t)b.cap_pls + 1);
+    b.pt3_p = cv.take<uint32_t>(b.cap_pt3);
+    b.pt3_o = cv.take<uint32_t>(b.cap_pt3);
+    b.pt5_cnt = cv.take<uint32_t>((size_t)b.cap_pls + 1);
+    b.pt5_off = cv.take<uint32_t>((size_t)b.cap_pls + 1);
+    b.pt5_p = cv.take<uint32_t>(b.cap_pt5);
+    b.pt5_o = cv.take<uint32_t>(b.cap_pt5);
+    b.pls_used5 = cv.take<uint8_t>(b.cap_pls);
+    b.pls_used3 = cv.take<uint8_t>(b.cap_pls);
+    b.t5_used = cv.take<uint8_t>(b.cap_t5);
+    b.tc_cnt = cv.take<uint32_t>(tcu + 1);
+    b.tc_off = cv.take<uint32_t>(tcu + 1);
+    b.tc_type = cv.take<uint32_t>(tcu);
+    b.tc_idx = cv.take<uint32_t>(tcu);
+    b.ev_tab = cv.take<uint32_t>(((size_t)b.cap_ev + 1) * kEvTabCols);
+}
+
+}  // namespace
+
+// One device slot: a stream, the arenas of one batch and its captured graph.
+struct Slot {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    void *in_arena = nullptr, *work_arena = nullptr;
+    size_t in_bytes = 0, work_bytes = 0;
+    Batch b{};
+    Totals *d_tot = nullptr, *h_tot = nullptr;
+    uint32_t *d_part = nullptr;
+    char *h_stage = nullptr;
+    size_t stage_bytes = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool graph_valid = false;
+    Launcher L;
+    // host view of the staged batch
+    uint32_t n_ev = 0;
+    std::vector<uint32_t> hit_off, pls_off;
+    hipEvent_t done = nullptr;
+    std::vector<uint64_t> tickets;   // served path
+    std::vector<std::chrono::steady_clock::time_point> t_submit;
+};
+
+}  // namespace lst
+
+struct ServedEvent {
+    uint64_t ticket;
+    std::vector<float> x, y, z, par, cov;
+    std::vector<uint32_t> mod;
+    std::vector<uint8_t> sen;
+    uint64_t footprint;
+    std::chrono::steady_clock::time_point t_submit;
+};
+
+struct lst_ctx {
+    lst_params p{};
+    int device = 0;
+    std::atomic<bool> failed{false};
+    mutable std::mutex err_mu;
+    std::string last_error;
+    bool has_geom = false;
+    lst::Geometry geom;
+    lst::DevGeom dg{};
+    void *geom_mem = nullptr;
+    std::unique_ptr<lst::Slot> plain;   // per-event / batched / device-resident path
+    std::map<std::string, std::pair<double, uint32_t>> ktimes;
+    std::mutex run_mu;                  // serialises the plain path
+    // served path
+    std::vector<std::unique_ptr<lst::Slot>> slots;
+    std::mutex q_mu;
+    std::condition_variable q_cv, done_cv;
+    std::deque<std::unique_ptr<ServedEvent>> waiting;
+    std::unordered_map<uint64_t, lst_event_out *> finished;
+    std::unordered_map<uint64_t, int> state;   // 1 waiting / running, 2 finished
+    uint64_t next_ticket = 1;
+    size_t in_system = 0;
+    uint64_t mem_in_use = 0;
+    std::thread worker;
+    bool stop = false;
+    bool worker_started = false;
+};
+
+using lst::Batch;
+using lst::Slot;
+
+namespace {
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            fail(ctx, std::string(#expr) + ": " + hipGetErrorString(e_));              \
+            return LST_ERR_DEVICE;                                                     \
+        }                                                                              \
+    } while (0)
+
+void fail(lst_ctx *ctx, const std::string &msg)
+{
+    std::lock_guard<std::mutex> g(ctx->err_mu);
+    ctx->failed = true;
+    ctx->last_error = msg;
+}
+
+lst_status set_err(lst_ctx *ctx, lst_status s, const std::string &msg)
+{
+    std::lock_guard<std::mutex> g(ctx->err_mu);
+    ctx->last_error = msg;
+    return s;
+}
+
+void free_slot_arenas(Slot &s)
+{
+    if (s.gexec) { (void)hipGraphExecDestroy(s.gexec); s.gexec = nullptr; }
+    if (s.graph) { (void)hipGraphDestroy(s.graph); s.graph = nullptr; }
+    s.graph_valid = false;
+    if (s.in_arena) { (void)hipFree(s.in_arena); s.in_arena = nullptr; }
+    if (s.work_arena) { (void)hipFree(s.work_arena); s.work_arena = nullptr; }
+    if (s.h_stage) { (void)hipHostFree(s.h_stage); s.h_stage = nullptr; }
+    s.in_bytes = s.work_bytes = s.stage_bytes = 0;
+}
+
+void destroy_slot(Slot &s)
+{
+    free_slot_arenas(s);
+    if (s.d_tot) (void)hipFree(s.d_tot);
+    if (s.h_tot) (void)hipHostFree(s.h_tot);
+    if (s.d_part) (void)hipFree(s.d_part);
+    for (hipEvent_t e : s.L.pool) (void)hipEventDestroy(e);
+    if (s.done) (void)hipEventDestroy(s.done);
+    if (s.stream) (void)hipStreamDestroy(s.stream);
+}
+
+lst_status make_slot(lst_ctx *ctx, std::unique_ptr<Slot> &out)
+{
+    auto s = std::make_unique<Slot>();
+    s->device = ctx->device;
+    HIP_TRY(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+    HIP_TRY(hipMalloc(&s->d_tot, sizeof(lst::Totals)));
+    HIP_TRY(hipHostMalloc((void **)&s->h_tot, sizeof(lst::Totals), hipHostMallocDefault));
+    HIP_TRY(hipMalloc(&s->d_part, sizeof(uint32_t) * lst::kScanGrid));
+    HIP_TRY(hipEventCreateWithFlags(&s->done, hipEventDisableTiming));
+    s->L.stream = s->stream;
+    s->L.part = s->d_part;
+    out = std::move(s);
+    return LST_OK;
+}
+
+// Ensure the slot's arenas hold a batch with these capacities (inputs and
+// work are separate so that growing the work arena keeps staged inputs).
+lst_status ensure_inputs(lst_ctx *ctx, Slot &s, uint32_t n_ev, uint64_t hits, uint64_t pls)
+{
+    Batch &b = s.b;
+    if (s.in_arena && n_ev <= b.cap_ev && hits <= b.cap_hits && pls <= b.cap_pls) return LST_OK;
+    lst::Caps c = lst::plan_caps(std::max(n_ev, b.cap_ev), std::max<uint64_t>(hits, b.cap_hits),
+                                 std::max<uint64_t>(pls, b.cap_pls));
+    // keep work capacities at least as large as before
+    c.md = std::max(c.md, b.cap_md); c.ls = std::max(c.ls, b.cap_ls); c.t3 = std::max(c.t3, b.cap_t3);
+    c.t5 = std::max(c.t5, b.cap_t5); c.pt3 = std::max(c.pt3, b.cap_pt3); c.pt5 = std::max(c.pt5, b.cap_pt5);
+    free_slot_arenas(s);
+    b.cap_ev = c.ev; b.cap_hits = std::max<uint32_t>(c.hits, 1); b.cap_pls = std::max<uint32_t>(c.pls, 1);
+    b.cap_md = c.md; b.cap_ls = c.ls; b.cap_t3 = c.t3; b.cap_t5 = c.t5; b.cap_pt3 = c.pt3; b.cap_pt5 = c.pt5;
+    b.cap_tc = b.cap_pt3 + b.cap_t5 + b.cap_pls;
+    lst::Carver ci{nullptr};
+    lst::carve_inputs(ci, b);
+    s.in_bytes = ci.off;
+    hipError_t e = hipMalloc(&s.in_arena, s.in_bytes);
+    if (e != hipSuccess) { s.in_arena = nullptr; return set_err(ctx, LST_ERR_OOM, "input arena allocation failed"); }
+    lst::Carver ci2{(char *)s.in_arena};
+    lst::carve_inputs(ci2, b);
+    s.stage_bytes = s.in_bytes;
+    HIP_TRY(hipHostMalloc((void **)&s.h_stage, s.stage_bytes, hipHostMallocDefault));
+    return LST_OK;
+}
+
+lst_status ensure_work(lst_ctx *ctx, Slot &s)
+{
+    if (s.work_arena) return LST_OK;
+    Batch &b = s.b;
+    b.cap_tc = b.cap_pt3 + b.cap_t5 + b.cap_pls;
+    const lst::Consts &c = ctx->geom.c;
+    lst::Carver cw{nullptr};
+    lst::carve_work(cw, b, c.n_mod, c.n_surf, c.nphi);
+    s.work_bytes = cw.off;
+    hipError_t e = hipMalloc(&s.work_arena, s.work_bytes);
+    if (e != hipSuccess) { s.work_arena = nullptr; return set_err(ctx, LST_ERR_OOM, "work arena allocation failed"); }
+    lst::Carver cw2{(char *)s.work_arena};
+    lst::carve_work(cw2, b, c.n_mod, c.n_surf, c.nphi);
+    s.graph_valid = false;
+    return LST_OK;
+}
+
+lst_status check_event(lst_ctx *ctx, const lst_event_in &ev)
+{
+    if (ev.n_hits && (!ev.x || !ev.y || !ev.z || !ev.module || !ev.sensor))
+        return set_err(ctx, LST_ERR_INVALID_ARG, "null hit array");
+    if (ev.n_pls && (!ev.pls_par || !ev.pls_cov)) return set_err(ctx, LST_ERR_INVALID_ARG, "null seed array");
+    return LST_OK;
+}
+
+// Stage n events into the slot's input arena (async on the slot stream).
+lst_status stage_inputs(lst_ctx *ctx, Slot &s, const lst_event_in *evs, uint32_t n)
+{
+    uint64_t hits = 0, pls = 0;
+    for (uint32_t i = 0; i < n; i++) {
+        lst_status st = check_event(ctx, evs[i]);
+        if (st != LST_OK) return st;
+        hits += evs[i].n_hits;
+        pls += evs[i].n_pls;
+    }
+    if (hits > 0x7FFFFFFFull || pls > 0x7FFFFFFFull) return set_err(ctx, LST_ERR_TOO_LARGE, "batch too large");
+    lst_status st = ensure_inputs(ctx, s, n, hits, pls);
+    if (st != LST_OK) return st;
+    st = ensure_work(ctx, s);
+    if (st != LST_OK) return st;
+    Batch &b = s.b;
+    s.n_ev = n;
+    s.hit_off.assign(n + 1, 0);
+    s.pls_off.assign(n + 1, 0);
+    for (uint32_t i = 0; i < n; i++) {
+        s.hit_off[i + 1] = s.hit_off[i] + evs[i].n_hits;
+        s.pls_off[i + 1] = s.pls_off[i] + evs[i].n_pls;
+    }
+    // host-pointer events go through the pinned stage, laid out like the arena
+    char *hs = s.h_stage;
+    struct Arr { void *dev; size_t elt; int which; };
+    const Arr arrs[] = {{b.in_x, 4, 0}, {b.in_y, 4, 1}, {b.in_z, 4, 2}, {b.in_mod, 4, 3},
+                        {b.in_sen, 1, 4}, {b.in_par, 20, 5}, {b.in_cov, 60, 6}};
+    for (const Arr &a : arrs) {
+        size_t base_off = (char *)a.dev - (char *)s.in_arena;
+        const std::vector<uint32_t> &offs = a.which < 5 ? s.hit_off : s.pls_off;
+        for (uint32_t i = 0; i < n; i++) {
+            const lst_event_in &ev = evs[i];
+            size_t cnt = a.which < 5 ? ev.n_hits : ev.n_pls;
+            if (!cnt) continue;
+            const void *src = a.which == 0 ? (const void *)ev.x : a.which == 1 ? (const void *)ev.y
+                            : a.which == 2 ? (const void *)ev.z : a.which == 3 ? (const void *)ev.module
+                            : a.which == 4 ? (const void *)ev.sensor : a.which == 5 ? (const void *)ev.pls_par
+                            : (const void *)ev.pls_cov;
+            size_t at = (size_t)offs[i] * a.elt;
+            if (ev.flags & LST_DEVICE_PTRS) {
+                HIP_TRY(hipMemcpyAsync((char *)a.dev + at, src, cnt * a.elt, hipMemcpyDeviceToDevice, s.stream));
+            } else {
+                std::memcpy(hs + base_off + at, src, cnt * a.elt);
+            }
+        }
+    }
+    // one host->device copy per array for the host-pointer events
+    for (const Arr &a : arrs) {
+        size_t base_off = (char *)a.dev - (char *)s.in_arena;
+        const std::vector<uint32_t> &offs = a.which < 5 ? s.hit_off : s.pls_off;
+        // copy contiguous runs of host-pointer events
+        uint32_t i = 0;
+        while (i < n) {
+            if (evs[i].flags & LST_DEVICE_PTRS) { i++; continue; }
+            uint32_t j = i;
+            while (j < n && !(evs[j].flags & LST_DEVICE_PTRS)) j++;
+            size_t lo = (size_t)offs[i] * a.elt, hi = (size_t)offs[j] * a.elt;
+            if (hi > lo)
+                HIP_TRY(hipMemcpyAsync((char *)a.dev + lo, hs + base_off + lo, hi - lo, hipMemcpyHostToDevice,
+                                       s.stream));
+            i = j;
+        }
+    }
+    // event offsets and the host-written counters
+    size_t hoff_at = (char *)b.ev_hit_off - (char *)s.in_arena;
+    size_t poff_at = (char *)b.ev_pls_off - (char *)s.in_arena;
+    std::memcpy(hs + hoff_at, s.hit_off.data(), (n + 1) * 4);
+    std::memcpy(hs + poff_at, s.pls_off.data(), (n + 1) * 4);
+    HIP_TRY(hipMemcpyAsync(b.ev_hit_off, hs + hoff_at, (n + 1) * 4, hipMemcpyHostToDevice, s.stream));
+    HIP_TRY(hipMemcpyAsync(b.ev_pls_off, hs + poff_at, (n + 1) * 4, hipMemcpyHostToDevice, s.stream));
+    s.h_tot->n_ev = n;
+    s.h_tot->n_hits = (uint32_t)hits;
+    s.h_tot->n_pls = (uint32_t)pls;
+    HIP_TRY(hipMemcpyAsync(s.d_tot, s.h_tot, 3 * sizeof(uint32_t), hipMemcpyHostToDevice, s.stream));
+    return LST_OK;
+}
+
+lst_status enqueue(lst_ctx *ctx, Slot &s, bool use_graph, bool timing, bool stats)
+{
+    if (use_graph && !timing && !stats) {
+        if (!s.graph_valid) {
+            if (s.gexec) { (void)hipGraphExecDestroy(s.gexec); s.gexec = nullptr; }
+            if (s.graph) { (void)hipGraphDestroy(s.graph); s.graph = nullptr; }
+            HIP_TRY(hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal));
+            s.L.timing = false;
+            s.L.err = hipSuccess;
+            lst::enqueue_chain(s.L, s.b, s.d_tot, ctx->dg, ctx->geom.c, 0);
+            hipGraph_t g = nullptr;
+            HIP_TRY(hipStreamEndCapture(s.stream, &g));
+            s.graph = g;
+            if (s.L.err != hipSuccess) {
+                fail(ctx, std::string("kernel launch during capture: ") + hipGetErrorString(s.L.err));
+                return LST_ERR_DEVICE;
+            }
+            HIP_TRY(hipGraphInstantiate(&s.gexec, s.graph, nullptr, nullptr, 0));
+            s.graph_valid = true;
+        }
+        HIP_TRY(hipGraphLaunch(s.gexec, s.stream));
+        return LST_OK;
+    }
+    s.L.timing = timing;
+    s.L.err = hipSuccess;
+    lst::enqueue_chain(s.L, s.b, s.d_tot, ctx->dg, ctx->geom.c, stats ? 1 : 0);
+    if (s.L.err != hipSuccess) {
+        fail(ctx, std::string("kernel launch: ") + hipGetErrorString(s.L.err));
+        return LST_ERR_DEVICE;
+    }
+    return LST_OK;
+}
+
+// After the chain: fetch the counters; grow the work arena where a list
+// overflowed (the caller re-runs).  Returns 1 when a re-run is needed.
+int overflowed(Slot &s)
+{
+    const lst::Totals &t = *s.h_tot;
+    Batch &b = s.b;
+    auto grow = [](uint32_t need, uint32_t &cap) {
+        if (need <= cap) return false;
+        cap = lst::clamp32((uint64_t)need + need / 4 + 1024);
+        return true;
+    };
+    bool g = false;
+    g |= grow(t.n_md, b.cap_md);
+    g |= grow(t.n_ls, b.cap_ls);
+    g |= grow(t.n_t3, b.cap_t3);
+    g |= grow(t.n_t5, b.cap_t5);
+    g |= grow(t.n_pt3, b.cap_pt3);
+    g |= grow(t.n_pt5, b.cap_pt5);
+    return g ? 1 : 0;
+}
+
+lst_status finish_run(lst_ctx *ctx, Slot &s, bool stats)
+{
+    HIP_TRY(hipMemcpyAsync(s.h_tot, s.d_tot, sizeof(lst::Totals), hipMemcpyDeviceToHost, s.stream));
+    HIP_TRY(hipStreamSynchronize(s.stream));
+    (void)stats;
+    if (s.L.timing) {
+        for (auto &r : s.L.recs) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, r.second.first, r.second.second) == hipSuccess) {
+                auto &kt = ctx->ktimes[r.first];
+                kt.first += ms;
+                kt.second += 1;
+            }
+        }
+        s.L.recs.clear();
+        s.L.used = 0;
+    }
+    if (s.h_tot->err & lst::kErrBadModule) return set_err(ctx, LST_ERR_BAD_MODULE, "hit with module id out of range or sensor > 1");
+    if (s.h_tot->err & lst::kErrNonFinite) return set_err(ctx, LST_ERR_NONFINITE, "non-finite hit coordinate or seed parameter");
+    return LST_OK;
+}
+
+// Run the staged batch to completion, growing arenas on overflow.
+lst_status run_staged(lst_ctx *ctx, Slot &s, bool use_graph, bool timing, bool stats)
+{
+    for (int attempt = 0; attempt < 12; attempt++) {
+        lst_status st = enqueue(ctx, s, use_graph, timing, stats);
+        if (st != LST_OK) return st;
+        st = finish_run(ctx, s, stats);
+        if (st != LST_OK) return st;
+        if (!overflowed(s)) return LST_OK;
+        // grow the work arena; staged inputs stay valid
+        if (s.gexec) { (void)hipGraphExecDestroy(s.gexec); s.gexec = nullptr; }
+        if (s.graph) { (void)hipGraphDestroy(s.graph); s.graph = nullptr; }
+        s.graph_valid = false;
+        if (s.work_arena) { (void)hipFree(s.work_arena); s.work_arena = nullptr; }
+        st = ensure_work(ctx, s);
+        if (st != LST_OK) return st;
+    }
+    return set_err(ctx, LST_ERR_OOM, "object lists kept overflowing");
+}
+
+// Copy the results of the staged batch to host memory, one output per event.
+lst_status download(lst_ctx *ctx, Slot &s, lst_event_out **outs)
+{
+    const uint32_t n = s.n_ev;
+    const lst::Totals &t = *s.h_tot;
+    const Batch &b = s.b;
+    std::vector<uint32_t> tab((size_t)(n + 1) * lst::kEvTabCols);
+    HIP_TRY(hipMemcpyAsync(tab.data(), b.ev_tab, tab.size() * 4, hipMemcpyDeviceToHost, s.stream));
+    const uint32_t nmd = t.n_md, nls = t.n_ls, nt3 = t.n_t3, nt5 = t.n_t5, np3 = t.n_pt3, np5 = t.n_pt5, ntc = t.n_tc;
+    std::vector<uint32_t> hlo(nmd), hup(nmd), la(nls), lb(nls), u1(nt3), u2(nt3), w1(nt5), w2(nt5);
+    std::vector<uint32_t> p3(np3), o3(np3), p5(np5), o5(np5), tty(ntc), tix(ntc);
+    std::vector<float> k3(nt3);
+    auto get = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
+        if (!bytes) return hipSuccess;
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s.stream);
+    };
+    HIP_TRY(get(hlo.data(), b.md_hlo, nmd * 4ull));
+    HIP_TRY(get(hup.data(), b.md_hup, nmd * 4ull));
+    HIP_TRY(get(la.data(), b.ls_a, nls * 4ull));
+    HIP_TRY(get(lb.data(), b.ls_b, nls * 4ull));
+    HIP_TRY(get(u1.data(), b.t3_l1, nt3 * 4ull));
+    HIP_TRY(get(u2.data(), b.t3_l2, nt3 * 4ull));
+    HIP_TRY(get(k3.data(), b.t3_k, nt3 * 4ull));
+    HIP_TRY(get(w1.data(), b.t5_u, nt5 * 4ull));
+    HIP_TRY(get(w2.data(), b.t5_w, nt5 * 4ull));
+    HIP_TRY(get(p3.data(), b.pt3_p, np3 * 4ull));
+    HIP_TRY(get(o3.data(), b.pt3_o, np3 * 4ull));
+    HIP_TRY(get(p5.data(), b.pt5_p, np5 * 4ull));
+    HIP_TRY(get(o5.data(), b.pt5_o, np5 * 4ull));
+    HIP_TRY(get(tty.data(), b.tc_type, ntc * 4ull));
+    HIP_TRY(get(tix.data(), b.tc_idx, ntc * 4ull));
+    HIP_TRY(hipStreamSynchronize(s.stream));
+    for (uint32_t e = 0; e < n; e++) {
+        const uint32_t *r0 = &tab[(size_t)e * lst::kEvTabCols], *r1 = r0 + lst::kEvTabCols;
+        const uint32_t pls0 = r0[1], md0 = r0[2], ls0 = r0[3], t30 = r0[4], t50 = r0[5], p30 = r0[6], p50 = r0[7];
+        const uint32_t cmd = r1[2] - md0, cls = r1[3] - ls0, ct3 = r1[4] - t30, ct5 = r1[5] - t50;
+        const uint32_t cp3 = r1[6] - p30, cp5 = r1[7] - p50;
+        const uint32_t ctc3 = r1[8] - r0[8], ctc5 = r1[9] - r0[9], ctcp = r1[10] - r0[10];
+        const uint32_t ctc = cp5 + ctc3 + ctc5 + ctcp;
+        size_t words = 2ull * (cmd + cls + ct3 + ct5 + cp3 + cp5 + ctc) + ct3;
+        size_t bytes = sizeof(lst_event_out) + 4 * words + 64;
+        char *mem = (char *)std::malloc(bytes);
+        if (!mem) return set_err(ctx, LST_ERR_OOM, "host allocation of outputs failed");
+        lst_event_out *o = (lst_event_out *)mem;
+        std::memset(o, 0, sizeof *o);
+        uint32_t *w = (uint32_t *)(mem + sizeof(lst_event_out));
+        o->n_md = cmd; o->n_ls = cls; o->n_t3 = ct3; o->n_t5 = ct5; o->n_pt3 = cp3; o->n_pt5 = cp5; o->n_tc = ctc;
+        o->md = w; w += 2 * cmd;
+        o->ls = w; w += 2 * cls;
+        o->t3 = w; w += 2 * ct3;
+        o->t5 = w; w += 2 * ct5;
+        o->pt3 = w; w += 2 * cp3;
+        o->pt5 = w; w += 2 * cp5;
+        o->tc = w; w += 2 * ctc;
+        o->t3_kappa = (float *)w;
+        for (uint32_t i = 0; i < cmd; i++) { o->md[2 * i] = hlo[md0 + i]; o->md[2 * i + 1] = hup[md0 + i]; }
+        for (uint32_t i = 0; i < cls; i++) { o->ls[2 * i] = la[ls0 + i] - md0; o->ls[2 * i + 1] = lb[ls0 + i] - md0; }
+        for (uint32_t i = 0; i < ct3; i++) {
+            o->t3[2 * i] = u1[t30 + i] - ls0; o->t3[2 * i + 1] = u2[t30 + i] - ls0;
+            o->t3_kappa[i] = k3[t30 + i];
+        }
+        for (uint32_t i = 0; i < ct5; i++) { o->t5[2 * i] = w1[t50 + i] - t30; o->t5[2 * i + 1] = w2[t50 + i] - t30; }
+        for (uint32_t i = 0; i < cp3; i++) { o->pt3[2 * i] = p3[p30 + i] - pls0; o->pt3[2 * i + 1] = o3[p30 + i] - t30; }
+        for (uint32_t i = 0; i < cp5; i++) { o->pt5[2 * i] = p5[p50 + i] - pls0; o->pt5[2 * i + 1] = o5[p50 + i] - t50; }
+        uint32_t k = 0;
+        for (uint32_t i = 0; i < cp5; i++) { o->tc[2 * k] = LST_TC_PT5; o->tc[2 * k + 1] = i; k++; }
+        for (uint32_t i = r0[8]; i < r1[8]; i++) { o->tc[2 * k] = tty[i]; o->tc[2 * k + 1] = tix[i] - p30; k++; }
+        for (uint32_t i = r0[9]; i < r1[9]; i++) { o->tc[2 * k] = tty[i]; o->tc[2 * k + 1] = tix[i] - t50; k++; }
+        for (uint32_t i = r0[10]; i < r1[10]; i++) { o->tc[2 * k] = tty[i]; o->tc[2 * k + 1] = tix[i] - pls0; k++; }
+        o->status = LST_OK;
+        outs[e] = o;
+    }
+    return LST_OK;
+}
+
+lst_status check_ctx(lst_ctx *ctx, bool need_geom)
+{
+    if (!ctx) return LST_ERR_INVALID_ARG;
+    if (ctx->failed) return LST_ERR_DEVICE;
+    if (need_geom && !ctx->has_geom) return set_err(ctx, LST_ERR_NO_GEOMETRY, "no geometry loaded");
+    return LST_OK;
+}
+
+lst_status ensure_plain(lst_ctx *ctx)
+{
+    if (ctx->plain) return LST_OK;
+    return make_slot(ctx, ctx->plain);
+}
+
+}  // namespace
+
+// ======================================================================
+// served path: scheduler thread
+// ======================================================================
+namespace {
+
+uint64_t predict_footprint(uint64_t hits, uint64_t pls, uint32_t n_mod)
+{
+    // device bytes of one event in a slot: inputs + work lists at planned capacity
+    lst::Caps c = lst::plan_caps(1, hits, pls);
+    uint64_t b = 0;
+    b += 49ull * c.hits + 80ull * c.pls + 16ull * n_mod;
+    b += 40ull * c.md + 16ull * c.ls + 44ull * c.t3 + 28ull * c.t5;
+    b += 8ull * (c.pt3 + c.pt5) + 24ull * c.pls + 16ull * (c.pt3 + c.t5 + c.pls);
+    return b;
+}
+
+void worker_main(lst_ctx *ctx);
+
+}  // namespace
+
+namespace {
+
+void worker_main(lst_ctx *ctx)
+{
+    (void)hipSetDevice(ctx->device);
+    const uint32_t n_slots = (uint32_t)ctx->slots.size();
+    std::vector<bool> busy(n_slots, false);
+    std::vector<uint64_t> slot_mem(n_slots, 0);
+    std::vector<std::vector<std::unique_ptr<ServedEvent>>> held(n_slots);
+    std::unique_lock<std::mutex> lk(ctx->q_mu);
+    while (true) {
+        // 1) complete finished slots
+        bool progressed = false;
+        for (uint32_t i = 0; i < n_slots; i++) {
+            if (!busy[i]) continue;
+            Slot &s = *ctx->slots[i];
+            if (hipEventQuery(s.done) == hipErrorNotReady) continue;
+            lk.unlock();
+            lst_status st = finish_run(ctx, s, false);
+            std::vector<lst_event_out *> outs(s.n_ev, nullptr);
+            if (st == LST_OK && overflowed(s)) {
+                if (s.work_arena) { (void)hipFree(s.work_arena); s.work_arena = nullptr; }
+                if (s.gexec) { (void)hipGraphExecDestroy(s.gexec); s.gexec = nullptr; }
+                if (s.graph) { (void)hipGraphDestroy(s.graph); s.graph = nullptr; }
+                s.graph_valid = false;
+                st = ensure_work(ctx, s);
+                if (st == LST_OK) st = run_staged(ctx, s, true, false, false);
+            }
+            if (st == LST_OK) st = download(ctx, s, outs.data());
+            auto now = std::chrono::steady_clock::now();
+            lk.lock();
+            for (uint32_t e = 0; e < s.n_ev; e++) {
+                lst_event_out *o = outs[e];
+                if (!o) {
+                    o = (lst_event_out *)std::calloc(1, sizeof(lst_event_out));
+                    if (o) o->status = (uint32_t)(st == LST_OK ? LST_ERR_DEVICE : st);
+                }
+                if (o) {
+                    o->ticket = s.tickets[e];
+                    o->latency_us = std::chrono::duration<double, std::micro>(now - s.t_submit[e]).count();
+                }
+                ctx->finished[s.tickets[e]] = o;
+                ctx->state[s.tickets[e]] = 2;
+            }
+            ctx->in_system -= s.n_ev;
+            ctx->mem_in_use -= slot_mem[i];
+            slot_mem[i] = 0;
+            held[i].clear();
+            busy[i] = false;
+            progressed = true;
+            ctx->done_cv.notify_all();
+        }
+        if (ctx->stop && ctx->waiting.empty() &&
+            std::none_of(busy.begin(), busy.end(), [](bool b) { return b; }))
+            break;
+        // 2) admit waiting events into free slots (continuous batching)
+        for (uint32_t i = 0; i < n_slots && !ctx->waiting.empty(); i++) {
+            if (busy[i]) continue;
+            std::vector<std::unique_ptr<ServedEvent>> take;
+            uint64_t mem = 0;
+            const uint64_t budget = ctx->p.mem_budget ? ctx->p.mem_budget : (32ull << 30);
+            while (!ctx->waiting.empty() && take.size() < ctx->p.max_batch) {
+                uint64_t f = ctx->waiting.front()->footprint;
+                if (!take.empty() && ctx->mem_in_use + mem + f > budget) break;
+                mem += f;
+                take.push_back(std::move(ctx->waiting.front()));
+                ctx->waiting.pop_front();
+            }
+            if (take.empty()) break;
+            ctx->mem_in_use += mem;
+            lk.unlock();
+            Slot &s = *ctx->slots[i];
+            std::vector<lst_event_in> evs(take.size());
+            s.tickets.resize(take.size());
+            s.t_submit.resize(take.size());
+            for (size_t k = 0; k < take.size(); k++) {
+                const ServedEvent &se = *take[k];
+                lst_event_in &ev = evs[k];
+                std::memset(&ev, 0, sizeof ev);
+                ev.n_hits = (uint32_t)se.x.size();
+                ev.n_pls = (uint32_t)(se.par.size() / 5);
+                ev.x = se.x.data(); ev.y = se.y.data(); ev.z = se.z.data();
+                ev.module = se.mod.data(); ev.sensor = se.sen.data();
+                ev.pls_par = se.par.data(); ev.pls_cov = se.cov.data();
+                s.tickets[k] = se.ticket;
+                s.t_submit[k] = se.t_submit;
+            }
+            lst_status st = stage_inputs(ctx, s, evs.data(), (uint32_t)evs.size());
+            if (st == LST_OK) st = enqueue(ctx, s, true, false, false);
+            if (st == LST_OK && hipEventRecord(s.done, s.stream) != hipSuccess) st = LST_ERR_DEVICE;
+            lk.lock();
+            if (st != LST_OK) {
+                for (auto &se : take) {
+                    lst_event_out *o = (lst_event_out *)std::calloc(1, sizeof(lst_event_out));
+                    if (o) { o->status = (uint32_t)st; o->ticket = se->ticket; }
+                    ctx->finished[se->ticket] = o;
+                    ctx->state[se->ticket] = 2;
+                }
+                ctx->in_system -= take.size();
+                ctx->mem_in_use -= mem;
+                ctx->done_cv.notify_all();
+                continue;
+            }
+            slot_mem[i] = mem;
+            held[i] = std::move(take);
+            busy[i] = true;
+            progressed = true;
+        }
+        if (!progressed) {
+            bool any_busy = std::any_of(busy.begin(), busy.end(), [](bool b) { return b; });
+            if (any_busy) {
+                lk.unlock();
+                std::this_thread::sleep_for(std::chrono::microseconds(20));
+                lk.lock();
+            } else {
+                ctx->q_cv.wait(lk, [&] { return ctx->stop || !ctx->waiting.empty(); });
+            }
+        }
+    }
+}
+
+}  // namespace
+
+// ======================================================================
+// C ABI
+// ======================================================================
+extern "C" {
+
+void lst_default_params(lst_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->device = 0;
+    p->B = 3.8;
+    p->pt_min = 0.8;
+    p->L = 15.0;
+    p->sig_rphi = 30e-4;
+    p->sig_c = 0.1;
+    p->n_sigma = 3.0;
+    p->flags = LST_FLAG_BEND;
+    p->max_batch = 64;
+    p->n_slots = 2;
+    p->queue_depth = 1024;
+    p->mem_budget = 0;
+}
+
+lst_status lst_create(const lst_params *p, lst_ctx **out)
+{
+    if (!out) return LST_ERR_INVALID_ARG;
+    *out = nullptr;
+    lst_params prm;
+    if (p) prm = *p;
+    else lst_default_params(&prm);
+    if (prm.max_batch == 0 || prm.max_batch > 4096 || prm.n_slots == 0 || prm.n_slots > 8 ||
+        prm.queue_depth == 0)
+        return LST_ERR_INVALID_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || prm.device < 0 || prm.device >= ndev) return LST_ERR_DEVICE;
+    if (hipSetDevice(prm.device) != hipSuccess) return LST_ERR_DEVICE;
+    lst_ctx *ctx = new (std::nothrow) lst_ctx();
+    if (!ctx) return LST_ERR_OOM;
+    ctx->p = prm;
+    ctx->device = prm.device;
+    *out = ctx;
+    return LST_OK;
+}
+
+lst_status lst_load_geometry(lst_ctx *ctx, const lst_module_desc *m, uint32_t n)
+{
+    lst_status st = check_ctx(ctx, false);
+    if (st != LST_OK) return st;
+    std::lock_guard<std::mutex> g(ctx->run_mu);
+    HIP_TRY(hipSetDevice(ctx->device));
+    lst::Geometry geom;
+    std::string err;
+    st = lst::build_geometry(ctx->p, m, n, geom, err);
+    if (st != LST_OK) return set_err(ctx, st, err);
+    // device copy: one allocation
+    const size_t nm = geom.n_mod, ne = geom.edge_dst.size(), nc = std::max<size_t>(geom.classes.size(), 1);
+    const size_t ns = geom.surfaces.size();
+    size_t off_kind = 0;
+    size_t off_surf = lst::align_up(off_kind + 4 * nm);
+    size_t off_mdc = lst::align_up(off_surf + 4 * nm);
+    size_t off_eb = lst::align_up(off_mdc + 16 * nm);
+    size_t off_edge = lst::align_up(off_eb + 4 * (nm + 1));
+    size_t off_cls = lst::align_up(off_edge + 8 * std::max<size_t>(ne, 1));
+    size_t off_sf = lst::align_up(off_cls + sizeof(lst::LsClass) * nc);
+    size_t total = lst::align_up(off_sf + sizeof(lst::Surface) * std::max<size_t>(ns, 1));
+    std::vector<char> host(total, 0);
+    std::memcpy(&host[off_kind], geom.kind.data(), 4 * nm);
+    std::memcpy(&host[off_surf], geom.surf.data(), 4 * nm);
+    std::memcpy(&host[off_mdc], geom.mdc.data(), 16 * nm);
+    std::memcpy(&host[off_eb], geom.edge_begin.data(), 4 * (nm + 1));
+    for (size_t i = 0; i < ne; i++) {
+        uint32_t v[2] = {geom.edge_dst[i], geom.edge_cls[i]};
+        std::memcpy(&host[off_edge + 8 * i], v, 8);
+    }
+    if (!geom.classes.empty()) std::memcpy(&host[off_cls], geom.classes.data(), sizeof(lst::LsClass) * geom.classes.size());
+    if (ns) std::memcpy(&host[off_sf], geom.surfaces.data(), sizeof(lst::Surface) * ns);
+    void *dmem = nullptr;
+    if (hipMalloc(&dmem, total) != hipSuccess) return set_err(ctx, LST_ERR_OOM, "geometry allocation failed");
+    hipError_t e = hipMemcpy(dmem, host.data(), total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(dmem);
+        fail(ctx, std::string("geometry upload: ") + hipGetErrorString(e));
+        return LST_ERR_DEVICE;
+    }
+    if (ctx->geom_mem) (void)hipFree(ctx->geom_mem);
+    ctx->geom_mem = dmem;
+    char *d = (char *)dmem;
+    ctx->dg.mod_kind = (const uint32_t *)(d + off_kind);
+    ctx->dg.mod_surf = (const uint32_t *)(d + off_surf);
+    ctx->dg.mdc = (const float4 *)(d + off_mdc);
+    ctx->dg.edge_begin = (const uint32_t *)(d + off_eb);
+    ctx->dg.edge = (const uint2 *)(d + off_edge);
+    ctx->dg.cls = (const lst::LsClass *)(d + off_cls);
+    ctx->dg.surf = (const lst::Surface *)(d + off_sf);
+    ctx->geom = std::move(geom);
+    ctx->has_geom = true;
+    // arenas depend on the module count
+    if (ctx->plain) free_slot_arenas(*ctx->plain);
+    for (auto &s : ctx->slots) free_slot_arenas(*s);
+    return LST_OK;
+}
+
+lst_status lst_get_connection_map(lst_ctx *ctx, const uint32_t **begin, const uint32_t **dst, uint32_t *n_edges)
+{
+    if (!ctx || !begin || !dst || !n_edges) return LST_ERR_INVALID_ARG;
+    if (!ctx->has_geom) return set_err(ctx, LST_ERR_NO_GEOMETRY, "no geometry loaded");
+    *begin = ctx->geom.edge_begin.data();
+    *dst = ctx->geom.edge_dst.data();
+    *n_edges = (uint32_t)ctx->geom.edge_dst.size();
+    return LST_OK;
+}
+
+lst_status lst_build_connection_map(const lst_params *p, const lst_module_desc *m, uint32_t n,
+                                    uint32_t **begin, uint32_t **dst, uint32_t *n_edges)
+{
+    if (!begin || !dst || !n_edges) return LST_ERR_INVALID_ARG;
+    lst_params prm;
+    if (p) prm = *p;
+    else lst_default_params(&prm);
+    lst::Geometry g;
+    std::string err;
+    lst_status st = lst::build_geometry(prm, m, n, g, err);
+    if (st != LST_OK) return st;
+    *begin = (uint32_t *)std::malloc(4 * (g.n_mod + 1));
+    *dst = (uint32_t *)std::malloc(4 * std::max<size_t>(g.edge_dst.size(), 1));
+    if (!*begin || !*dst) {
+        std::free(*begin); std::free(*dst);
+        *begin = *dst = nullptr;
+        return LST_ERR_OOM;
+    }
+    std::memcpy(*begin, g.edge_begin.data(), 4 * (g.n_mod + 1));
+    if (!g.edge_dst.empty()) std::memcpy(*dst, g.edge_dst.data(), 4 * g.edge_dst.size());
+    *n_edges = (uint32_t)g.edge_dst.size();
+    return LST_OK;
+}
+
+void lst_free_map(uint32_t *begin, uint32_t *dst)
+{
+    std::free(begin);
+    std::free(dst);
+}
+
+lst_status lst_run_batch(lst_ctx *ctx, const lst_event_in *evs, uint32_t n, lst_event_out **outs)
+{
+    lst_status st = check_ctx(ctx, true);
+    if (st != LST_OK) return st;
+    if (!evs || !outs || n == 0) return set_err(ctx, LST_ERR_INVALID_ARG, "no events");
+    if (n > ctx->p.max_batch) return set_err(ctx, LST_ERR_INVALID_ARG, "more events than max_batch");
+    std::lock_guard<std::mutex> g(ctx->run_mu);
+    HIP_TRY(hipSetDevice(ctx->device));
+    st = ensure_plain(ctx);
+    if (st != LST_OK) return st;
+    Slot &s = *ctx->plain;
+    st = stage_inputs(ctx, s, evs, n);
+    if (st != LST_OK) return st;
+    st = run_staged(ctx, s, true, false, false);
+    if (st != LST_OK) return st;
+    for (uint32_t i = 0; i < n; i++) outs[i] = nullptr;
+    st = download(ctx, s, outs);
+    if (st != LST_OK) {
+        for (uint32_t i = 0; i < n; i++) { std::free(outs[i]); outs[i] = nullptr; }
+    }
+    return st;
+}
+
+lst_status lst_run_event(lst_ctx *ctx, const lst_event_in *ev, lst_event_out **out)
+{
+    if (!ev || !out) return LST_ERR_INVALID_ARG;
+    return lst_run_batch(ctx, ev, 1, out);
+}
+
+lst_status lst_batch_upload(lst_ctx *ctx, const lst_event_in *evs, uint32_t n)
+{
+    lst_status st = check_ctx(ctx, true);
+    if (st != LST_OK) return st;
+    if (!evs || n == 0) return set_err(ctx, LST_ERR_INVALID_ARG, "no events");
+    if (n > ctx->p.max_batch) return set_err(ctx, LST_ERR_INVALID_ARG, "more events than max_batch");
+    std::lock_guard<std::mutex> g(ctx->run_mu);
+    HIP_TRY(hipSetDevice(ctx->device));
+    st = ensure_plain(ctx);
+    if (st != LST_OK) return st;
+    Slot &s = *ctx->plain;
+    st = stage_inputs(ctx, s, evs, n);
+    if (st != LST_OK) return st;
+    HIP_TRY(hipStreamSynchronize(s.stream));
+    // size the work arena with one untimed run
+    return run_staged(ctx, s, false, false, false);
+}
+
+lst_status lst_batch_execute(lst_ctx *ctx, uint32_t repeats, int32_t use_graph, int32_t timing, double *ms)
+{
+    lst_status st = check_ctx(ctx, true);
+    if (st != LST_OK) return st;
+    if (!ctx->plain || !ctx->plain->n_ev) return set_err(ctx, LST_ERR_INVALID_ARG, "no staged batch");
+    std::lock_guard<std::mutex> g(ctx->run_mu);
+    HIP_TRY(hipSetDevice(ctx->device));
+    Slot &s = *ctx->plain;
+    if (timing) ctx->ktimes.clear();
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, s.stream));
+    for (uint32_t r = 0; r < repeats; r++) {
+        st = enqueue(ctx, s, use_graph != 0, timing != 0, false);
+        if (st != LST_OK) break;
+        if (timing) {
+            // drain the event records of this repeat so the pool stays small
+            HIP_TRY(hipStreamSynchronize(s.stream));
+            for (auto &rec : s.L.recs) {
+                float t = 0.f;
+                if (hipEventElapsedTime(&t, rec.second.first, rec.second.second) == hipSuccess) {
+                    auto &kt = ctx->ktimes[rec.first];
+                    kt.first += t;
+                    kt.second += 1;
+                }
+            }
+            s.L.recs.clear();
+            s.L.used = 0;
+        }
+    }
+    HIP_TRY(hipEventRecord(e1, s.stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (ms) *ms = t;
+    if (st != LST_OK) return st;
+    bool was_timing = s.L.timing;
+    s.L.timing = false;
+    st = finish_run(ctx, s, false);
+    s.L.timing = was_timing;
+    if (st != LST_OK) return st;
+    if (overflowed(s)) return set_err(ctx, LST_ERR_OOM, "object list overflow during execute");
+    return LST_OK;
+}
+
+lst_status lst_kernel_times(lst_ctx *ctx, const char **names, double *total_ms, uint32_t *launches, uint32_t *n)
+{
+    if (!ctx || !n) return LST_ERR_INVALID_ARG;
+    uint32_t cap = *n, k = 0;
+    for (auto &kv : ctx->ktimes) {
+        if (k < cap) {
+            if (names) {
+                // names point at string literals of the launch sites
+                static thread_local std::vector<std::string> keep;
+                if (keep.size() < cap) keep.resize(cap);
+                keep[k] = kv.first;
+                names[k] = keep[k].c_str();
+            }
+            if (total_ms) total_ms[k] = kv.second.first;
+            if (launches) launches[k] = kv.second.second;
+        }
+        k++;
+    }
+    *n = std::min(k, cap);
+    return LST_OK;
+}
+
+lst_status lst_batch_download(lst_ctx *ctx, lst_event_out **outs)
+{
+    lst_status st = check_ctx(ctx, true);
+    if (st != LST_OK) return st;
+    if (!outs || !ctx->plain || !ctx->plain->n_ev) return set_err(ctx, LST_ERR_INVALID_ARG, "no staged batch");
+    std::lock_guard<std::mutex> g(ctx->run_mu);
+    HIP_TRY(hipSetDevice(ctx->device));
+    return download(ctx, *ctx->plain, outs);
+}
+
+lst_status lst_batch_counts(lst_ctx *ctx, uint64_t counts[13])
+{
+    if (!ctx || !counts) return LST_ERR_INVALID_ARG;
+    if (!ctx->plain || !ctx->plain->h_tot) return set_err(ctx, LST_ERR_INVALID_ARG, "no staged batch");
+    std::lock_guard<std::mutex> g(ctx->run_mu);
+    Slot &s = *ctx->plain;
+    // re-run once with candidate statistics
+    HIP_TRY(hipSetDevice(ctx->device));
+    lst_status st = enqueue(ctx, s, false, false, true);
+    if (st != LST_OK) return st;
+    st = finish_run(ctx, s, true);
+    if (st != LST_OK) return st;
+    const lst::Totals &t = *s.h_tot;
+    const uint64_t v[13] = {t.n_md, t.n_ls, t.n_t3, t.n_t5, t.n_pt3, t.n_pt5, t.n_tc + t.n_pt5,
+                            t.cand[0], t.cand[1], t.cand[2], t.cand[3], t.cand[4], t.cand[5]};
+    std::memcpy(counts, v, sizeof v);
+    return LST_OK;
+}
+
+lst_status lst_submit(lst_ctx *ctx, const lst_event_in *ev, uint64_t *ticket)
+{
+    lst_status st = check_ctx(ctx, true);
+    if (st != LST_OK) return st;
+    if (!ev || !ticket) return LST_ERR_INVALID_ARG;
+    st = check_event(ctx, *ev);
+    if (st != LST_OK) return st;
+    if (ev->flags & LST_DEVICE_PTRS) return set_err(ctx, LST_ERR_INVALID_ARG, "served events take host pointers");
+    const uint64_t budget = ctx->p.mem_budget ? ctx->p.mem_budget : (32ull << 30);
+    uint64_t f = predict_footprint(ev->n_hits, ev->n_pls, ctx->geom.n_mod);
+    if (f > budget) return set_err(ctx, LST_ERR_TOO_LARGE, "event above the device memory budget");
+    auto se = std::make_unique<ServedEvent>();
+    se->x.assign(ev->x, ev->x + ev->n_hits);
+    se->y.assign(ev->y, ev->y + ev->n_hits);
+    se->z.assign(ev->z, ev->z + ev->n_hits);
+    se->mod.assign(ev->module, ev->module + ev->n_hits);
+    se->sen.assign(ev->sensor, ev->sensor + ev->n_hits);
+    se->par.assign(ev->pls_par, ev->pls_par + 5ull * ev->n_pls);
+    se->cov.assign(ev->pls_cov, ev->pls_cov + 15ull * ev->n_pls);
+    se->footprint = f;
+    se->t_submit = std::chrono::steady_clock::now();
+    std::lock_guard<std::mutex> g(ctx->q_mu);
+    if (ctx->in_system >= ctx->p.queue_depth) return set_err(ctx, LST_ERR_QUEUE_FULL, "queue full");
+    if (!ctx->worker_started) {
+        ctx->slots.clear();
+        for (uint32_t i = 0; i < ctx->p.n_slots; i++) {
+            std::unique_ptr<Slot> s;
+            st = make_slot(ctx, s);
+            if (st != LST_OK) return st;
+            ctx->slots.push_back(std::move(s));
+        }
+        ctx->worker = std::thread(worker_main, ctx);
+        ctx->worker_started = true;
+    }
+    se->ticket = ctx->next_ticket++;
+    *ticket = se->ticket;
+    ctx->state[se->ticket] = 1;
+    ctx->in_system++;
+    ctx->waiting.push_back(std::move(se));
+    ctx->q_cv.notify_all();
+    return LST_OK;
+}
+
+lst_status lst_poll(lst_ctx *ctx, uint64_t ticket, int64_t timeout_us, lst_event_out **out)
+{
+    if (!ctx || !out) return LST_ERR_INVALID_ARG;
+    *out = nullptr;
+    std::unique_lock<std::mutex> lk(ctx->q_mu);
+    auto it = ctx->state.find(ticket);
+    if (it == ctx->state.end()) return set_err(ctx, LST_ERR_UNKNOWN_TICKET, "unknown or consumed ticket");
+    auto ready = [&] { return ctx->state[ticket] == 2; };
+    if (!ready()) {
+        if (timeout_us == 0) return LST_PENDING;
+        if (timeout_us < 0) ctx->done_cv.wait(lk, ready);
+        else if (!ctx->done_cv.wait_for(lk, std::chrono::microseconds(timeout_us), ready)) return LST_PENDING;
+    }
+    lst_event_out *o = ctx->finished[ticket];
+    ctx->finished.erase(ticket);
+    ctx->state.erase(ticket);
+    *out = o;
+    if (!o) return LST_ERR_OOM;
+    if (o->status != (uint32_t)LST_OK) return (lst_status)(int32_t)o->status;
+    return LST_OK;
+}
+
+void lst_free_output(lst_event_out *out) { std::free(out); }
+
+void lst_destroy(lst_ctx *ctx)
+{
+    if (!ctx) return;
+    {
+        std::lock_guard<std::mutex> g(ctx->q_mu);
+        ctx->stop = true;
+        ctx->q_cv.notify_all();
+    }
+    if (ctx->worker.joinable()) ctx->worker.join();
+    for (auto &kv : ctx->finished) std::free(kv.second);
+    (void)hipSetDevice(ctx->device);
+    for (auto &s : ctx->slots) destroy_slot(*s);
+    if (ctx->plain) destroy_slot(*ctx->plain);
+    if (ctx->geom_mem) (void)hipFree(ctx->geom_mem);
+    delete ctx;
+}
+
+const char *lst_status_str(lst_status s)
+{
+    switch (s) {
+    case LST_OK: return "ok";
+    case LST_PENDING: return "pending";
+    case LST_ERR_INVALID_ARG: return "invalid argument";
+    case LST_ERR_DEVICE: return "device error";
+    case LST_ERR_NO_GEOMETRY: return "no geometry loaded";
+    case LST_ERR_BAD_GEOMETRY: return "bad geometry";
+    case LST_ERR_BAD_MODULE: return "hit with bad module id or sensor";
+    case LST_ERR_NONFINITE: return "non-finite input";
+    case LST_ERR_OOM: return "out of memory";
+    case LST_ERR_TOO_LARGE: return "event too large";
+    case LST_ERR_QUEUE_FULL: return "queue full";
+    case LST_ERR_UNKNOWN_TICKET: return "unknown ticket";
+    default: return "unknown status";
+    }
+}
+
+const char *lst_last_error(const lst_ctx *ctx)
+{
+    if (!ctx) return "null context";
+    static thread_local std::string copy;
+    std::lock_guard<std::mutex> g(ctx->err_mu);
+    copy = ctx->last_error;
+    return copy.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,135 @@
+// engine.h -- device-side data layout of liblst (library-internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "lst_internal.h"
+
+namespace lst {
+
+constexpr uint32_t kInvalid = 0xFFFFFFFFu;
+constexpr uint32_t kDiskBit = 0x80000000u;   // md_u: anchor on an endcap module
+constexpr uint32_t kUnitMask = 0x7FFFFFFFu;  // md_u: (event, module) unit
+constexpr uint32_t kErrBadModule = 1u;
+constexpr uint32_t kErrNonFinite = 2u;
+constexpr int kScanGrid = 256;
+constexpr unsigned kMaxGrid = 2048;
+constexpr int kEvTabCols = 12;
+
+// Device copy of the geometry (read-only).
+struct DevGeom {
+    const uint32_t *mod_kind;   // n_mod
+    const uint32_t *mod_surf;   // n_mod
+    const float4 *mdc;          // n_mod: (S, G, K, D)
+    const uint32_t *edge_begin; // n_mod + 1
+    const uint2 *edge;          // (destination module, class)
+    const LsClass *cls;
+    const Surface *surf;        // n_surf
+};
+
+// Counters of one batch in device memory.  n_ev / n_hits / n_pls are written
+// by the host before the chain runs; every other count by the chain itself.
+struct Totals {
+    uint32_t n_ev, n_hits, n_pls;
+    uint32_t n_bins, n_md_units, n_bk, n_sorted;
+    uint32_t n_md, n_ls, n_t3, n_t5, n_pt3, n_pt5;
+    uint32_t n_bk3, n_bk5, n_tcu, n_tc;
+    uint32_t err;
+    uint32_t pad[2];
+    unsigned long long cand[6];  // candidates examined: md, ls, t3, t5, pt3, pt5
+};
+
+// Device arena of one slot: inputs, intermediate and output lists of a batch.
+// Capacities bound every list; a stage whose total exceeds its capacity writes
+// nothing past it and the host re-runs the batch with larger arrays.
+struct Batch {
+    uint32_t cap_ev, cap_hits, cap_pls, cap_md, cap_ls, cap_t3, cap_t5, cap_pt3, cap_pt5, cap_tc;
+    // inputs (event-major concatenation)
+    float *in_x, *in_y, *in_z;
+    uint32_t *in_mod;
+    uint8_t *in_sen;
+    float *in_par, *in_cov;
+    uint32_t *ev_hit_off, *ev_pls_off;  // cap_ev + 1
+    // a1: hits sorted by (event, module, sensor)
+    uint32_t *bin_cnt, *bin_off, *hbin, *hrank, *perm;
+    float *hx, *hy, *hz, *hr;
+    uint32_t *hin;                      // event-local input index of each sorted hit
+    // a2: mini-doublets (anchor = hit on the lower sensor)
+    uint32_t *md_cnt, *md_off;          // per (event, module) unit
+    float *md_x, *md_y, *md_z, *md_r, *md_beta;
+    uint32_t *md_u, *md_hlo, *md_hup;
+    // a3: line segments
+    uint32_t *ls_cnt, *ls_off;          // per inner MD
+    uint32_t *ls_a, *ls_b;
+    // a4: T3
+    uint32_t *t3_cnt, *t3_off;          // per inner LS
+    uint32_t *t3_l1, *t3_l2, *t3_a, *t3_c;
+    float *t3_k, *t3_sk;
+    // a5: T5
+    uint32_t *t5_cnt, *t5_off;          // per inner T3
+    uint32_t *t5_u, *t5_w;
+    float *t5_k, *t5_sk;
+    // a6: seed lookup buckets of T3s / T5s
+    uint32_t *bk3_cnt, *bk3_off, *bk3_id, *bk3_rank, *bk3_items;
+    uint32_t *bk5_cnt, *bk5_off, *bk5_id, *bk5_rank, *bk5_items;
+    // a7: pT3 / pT5 (seed, object)
+    uint32_t *pt3_cnt, *pt3_off, *pt3_p, *pt3_o;
+    uint32_t *pt5_cnt, *pt5_off, *pt5_p, *pt5_o;
+    // a8: track candidates over [pT3 | T5 | pLS]
+    uint8_t *pls_used5, *pls_used3, *t5_used;
+    uint32_t *tc_cnt, *tc_off, *tc_type, *tc_idx;
+    uint32_t *ev_tab;                   // (cap_ev + 1) x kEvTabCols
+};
+
+// Launches kernels on one stream; optionally brackets each launch with HIP
+// events to time it.
+struct Launcher {
+    hipStream_t stream = nullptr;
+    uint32_t *part = nullptr;           // scan partials, kScanGrid entries
+    bool timing = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<std::pair<const char *, std::pair<hipEvent_t, hipEvent_t>>> recs;
+    hipError_t err = hipSuccess;
+
+    hipEvent_t next_event()
+    {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+
+    template <typename... KArgs, typename... Args>
+    void launch(const char *name, void (*kernel)(KArgs...), dim3 grid, dim3 block, Args... args)
+    {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (timing) {
+            e0 = next_event();
+            e1 = next_event();
+            if (e0) (void)hipEventRecord(e0, stream);
+        }
+        kernel<<<grid, block, 0, stream>>>(args...);
+        hipError_t le = hipGetLastError();
+        if (le != hipSuccess && err == hipSuccess) err = le;
+        if (timing && e1) {
+            (void)hipEventRecord(e1, stream);
+            recs.push_back({name, {e0, e1}});
+        }
+    }
+
+    void scan(const uint32_t *in, uint32_t *out, const uint32_t *n_ptr, uint32_t cap, uint32_t *total,
+              const char *name);
+};
+
+void launch_setup(Launcher &L, Totals *t, const Consts &c);
+void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, const Consts &c, int stats);
+
+}  // namespace lst

@@ -1,0 +1,938 @@
+// kernels.hip -- gfx950 kernels of the Line Segment Tracking chain.
+//
+// Every stage follows count -> device-wide exclusive scan -> fill, so each
+// object list comes out compacted and in canonical order without global
+// atomics on the output path, and a stage's scan doubles as the CSR index the
+// next stage walks:
+//   hits sorted by (event, module, sensor)          -> per-module hit ranges
+//   MDs per (event, module)                          -> per-module MD ranges
+//   LSs per inner MD                                 -> "segments starting at MD b"
+//   T3s per inner LS (hence grouped by inner MD)     -> "T3s starting at MD c"
+//   T5s per inner T3; pT3 / pT5 per pixel seed.
+// A batch of events is one flat index space (event-major), so one launch of
+// the chain serves any number of events.  Unit counts live in device memory
+// (struct Totals) and kernels walk them with grid-stride loops: the launch
+// sequence is independent of the data and can be captured in a hipGraph.
+//
+// Cut arithmetic: IEEE binary32 with the expression order written out below
+// (no contraction: built with -ffp-contract=off), pixel-seed cuts in binary64.
+#include <hip/hip_runtime.h>
+
+#include "engine.h"
+
+namespace lst {
+
+// ------------------------------------------------------------------ scan ---
+
+constexpr int kScanBlock = 256;
+constexpr int kScanTile = 4 * kScanBlock;
+
+__device__ inline uint32_t wave_incl_scan(uint32_t v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// exclusive scan of one value per thread across a 256-thread block
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t &total)
+{
+    __shared__ uint32_t ws[kScanBlock / 64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint32_t inc = wave_incl_scan(v);
+    if (lane == 63) ws[w] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kScanBlock / 64; i++) {
+        uint32_t t = ws[i];
+        off += (i < w) ? t : 0u;
+        tot += t;
+    }
+    __syncthreads();
+    total = tot;
+    return off + inc - v;
+}
+
+__device__ inline uint32_t scan_chunk(uint32_t n)
+{
+    uint32_t per = (n + kScanGrid - 1) / kScanGrid;
+    return (per + kScanTile - 1) / kScanTile * kScanTile;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_up(const uint32_t *__restrict__ in,
+                                                        const uint32_t *n_ptr, uint32_t cap,
+                                                        uint32_t *__restrict__ part)
+{
+    const uint32_t n = min(*n_ptr, cap);
+    const uint32_t chunk = scan_chunk(n);
+    const uint32_t start = blockIdx.x * chunk;
+    const uint32_t end = min(start + chunk, n);
+    uint32_t s = 0;
+    for (uint32_t base = start; base < end; base += kScanTile) {
+        uint32_t i = base + 4 * threadIdx.x;
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            if (i + k < end) s += in[i + k];
+    }
+    uint32_t tot;
+    block_excl_scan(s, tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_mid(uint32_t *__restrict__ part,
+                                                         const uint32_t *n_ptr, uint32_t cap,
+                                                         uint32_t *__restrict__ out,
+                                                         uint32_t *total_out)
+{
+    static_assert(kScanGrid == kScanBlock, "one partial per thread");
+    const uint32_t n = min(*n_ptr, cap);
+    uint32_t v = part[threadIdx.x];
+    uint32_t tot;
+    uint32_t ex = block_excl_scan(v, tot);
+    part[threadIdx.x] = ex;
+    if (threadIdx.x == 0) {
+        out[n] = tot;
+        *total_out = tot;
+    }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_down(const uint32_t *__restrict__ in,
+                                                          const uint32_t *n_ptr, uint32_t cap,
+                                                          const uint32_t *__restrict__ part,
+                                                          uint32_t *__restrict__ out)
+{
+    const uint32_t n = min(*n_ptr, cap);
+    const uint32_t chunk = scan_chunk(n);
+    const uint32_t start = blockIdx.x * chunk;
+    const uint32_t end = min(start + chunk, n);
+    uint32_t carry = part[blockIdx.x];
+    for (uint32_t base = start; base < end; base += kScanTile) {
+        uint32_t i = base + 4 * threadIdx.x;
+        uint32_t v[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) v[k] = (i + k < end) ? in[i + k] : 0u;
+        uint32_t s = v[0] + v[1] + v[2] + v[3];
+        uint32_t tot;
+        uint32_t ex = block_excl_scan(s, tot) + carry;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            if (i + k < end) out[i + k] = ex;
+            ex += v[k];
+        }
+        carry += tot;
+    }
+}
+
+// --------------------------------------------------------------- helpers ---
+
+#define GRID_STRIDE(i, n) \
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += gridDim.x * blockDim.x)
+
+__device__ inline uint32_t find_event(const uint32_t *__restrict__ off, uint32_t n_ev, uint32_t i)
+{
+    uint32_t lo = 0, hi = n_ev;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_zero_u32(uint32_t *__restrict__ p, const uint32_t *n_ptr, uint32_t cap, uint32_t extra)
+{
+    const uint32_t n = min(*n_ptr, cap) + extra;
+    GRID_STRIDE(i, n) p[i] = 0u;
+}
+
+__global__ void k_zero_u8(uint8_t *__restrict__ p, const uint32_t *n_ptr, uint32_t cap)
+{
+    const uint32_t n = min(*n_ptr, cap);
+    GRID_STRIDE(i, n) p[i] = 0u;
+}
+
+// derive the per-batch unit counts; clear error flags and statistics
+__global__ void k_setup(Totals *t, uint32_t n_mod, uint32_t n_surf, uint32_t nphi)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        t->n_bins = t->n_ev * 2u * n_mod;
+        t->n_md_units = t->n_ev * n_mod;
+        t->n_bk = t->n_ev * n_surf * nphi;
+        t->err = 0;
+        for (int i = 0; i < 6; i++) t->cand[i] = 0ull;
+    }
+}
+
+// ------------------------------------------------------ a1: hit ingest ---
+
+__global__ void k_hit_hist(const Batch b, Totals *t, uint32_t n_mod)
+{
+    const uint32_t n_ev = t->n_ev, n = min(t->n_hits, b.cap_hits);
+    GRID_STRIDE(h, n) {
+        uint32_t e = find_event(b.ev_hit_off, n_ev, h);
+        uint32_t m = b.in_mod[h];
+        uint32_t s = b.in_sen[h];
+        float x = b.in_x[h], y = b.in_y[h], z = b.in_z[h];
+        uint32_t bad = 0;
+        if (m >= n_mod || s > 1u) bad |= kErrBadModule;
+        if (!isfinite(x) || !isfinite(y) || !isfinite(z)) bad |= kErrNonFinite;
+        if (bad) {
+            atomicOr(&t->err, bad);
+            b.hbin[h] = kInvalid;
+            continue;
+        }
+        uint32_t bin = e * 2u * n_mod + 2u * m + s;
+        b.hbin[h] = bin;
+        b.hrank[h] = atomicAdd(&b.bin_cnt[bin], 1u);
+    }
+}
+
+__global__ void k_pls_check(const Batch b, Totals *t)
+{
+    const uint32_t n = min(t->n_pls, b.cap_pls);
+    GRID_STRIDE(p, n) {
+        bool ok = true;
+        for (int k = 0; k < 5; k++) ok = ok && isfinite(b.in_par[5 * p + k]);
+        for (int k = 0; k < 15; k++) ok = ok && isfinite(b.in_cov[15 * p + k]);
+        if (!ok) atomicOr(&t->err, kErrNonFinite);
+    }
+}
+
+__global__ void k_hit_scatter(const Batch b, const Totals *t)
+{
+    const uint32_t n = min(t->n_hits, b.cap_hits);
+    GRID_STRIDE(h, n) {
+        uint32_t bin = b.hbin[h];
+        if (bin == kInvalid) continue;
+        b.perm[b.bin_off[bin] + b.hrank[h]] = h;
+    }
+}
+
+// per (event, module, sensor) bin: restore input order (the scatter above
+// used atomic slots) and write the sorted SoA with r = sqrt(x^2 + y^2)
+__global__ void k_hit_gather(const Batch b, const Totals *t, uint32_t n_mod)
+{
+    const uint32_t nb = t->n_bins;
+    GRID_STRIDE(bin, nb) {
+        const uint32_t beg = b.bin_off[bin], end = b.bin_off[bin + 1];
+        for (uint32_t i = beg + 1; i < end; i++) {
+            uint32_t v = b.perm[i];
+            uint32_t j = i;
+            while (j > beg && b.perm[j - 1] > v) {
+                b.perm[j] = b.perm[j - 1];
+                j--;
+            }
+            b.perm[j] = v;
+        }
+        const uint32_t e = bin / (2u * n_mod);
+        const uint32_t h0 = b.ev_hit_off[e];
+        for (uint32_t i = beg; i < end; i++) {
+            uint32_t h = b.perm[i];
+            float x = b.in_x[h], y = b.in_y[h];
+            b.hx[i] = x;
+            b.hy[i] = y;
+            b.hz[i] = b.in_z[h];
+            b.hr[i] = sqrtf(x * x + y * y);
+            b.hin[i] = h - h0;
+        }
+    }
+}
+
+// ------------------------------------------------------ a2: mini-doublets ---
+
+struct MdOut {
+    float beta;
+};
+
+__device__ inline bool md_cut(const float4 mc, bool barrel, float L,
+                              float xi, float yi, float zi, float ri,
+                              float xj, float yj, float zj, float rj, float &beta)
+{
+    float dx = xj - xi, dy = yj - yi;
+    float c = xi * dy - yi * dx;
+    float d = xi * xj + yi * yj;
+    float rr = ri * rj;
+    if (!(d > 0.0f)) return false;
+    if (!(fabsf(c) <= mc.x * rr)) return false;
+    if (barrel) {
+        if (!(fabsf(zj - zi) * ri <= mc.y * (fabsf(zi) + L) + mc.z * ri)) return false;
+    } else {
+        if (!(fabsf(rj - ri) <= mc.w)) return false;
+    }
+    beta = c / rr;
+    return true;
+}
+
+template <bool kFill>
+__global__ __launch_bounds__(256) void k_md(const Batch b, Totals *t, const DevGeom g, const Consts c,
+                                            int stats)
+{
+    const uint32_t nu = t->n_md_units;
+    const uint32_t n_mod = c.n_mod;
+    uint64_t cand = 0;
+    GRID_STRIDE(u, nu) {
+        const uint32_t e = u / n_mod, m = u - e * n_mod;
+        const uint32_t b0 = e * 2u * n_mod + 2u * m;
+        const uint32_t lo0 = b.bin_off[b0], lo1 = b.bin_off[b0 + 1], up1 = b.bin_off[b0 + 2];
+        if (lo0 == lo1 || lo1 == up1) {
+            if (!kFill) b.md_cnt[u] = 0;
+            continue;
+        }
+        const float4 mc = g.mdc[m];
+        const bool barrel = g.mod_kind[m] == LST_BARREL;
+        uint32_t k = kFill ? b.md_off[u] : 0u;
+        const uint32_t disk_bit = barrel ? 0u : kDiskBit;
+        for (uint32_t i = lo0; i < lo1; i++) {
+            const float xi = b.hx[i], yi = b.hy[i], zi = b.hz[i], ri = b.hr[i];
+            for (uint32_t j = lo1; j < up1; j++) {
+                float beta;
+                if (!kFill) cand++;
+                if (!md_cut(mc, barrel, c.L, xi, yi, zi, ri, b.hx[j], b.hy[j], b.hz[j], b.hr[j], beta))
+                    continue;
+                if (kFill) {
+                    if (k < b.cap_md) {
+                        b.md_x[k] = xi;
+                        b.md_y[k] = yi;
+                        b.md_z[k] = zi;
+                        b.md_r[k] = ri;
+                        b.md_beta[k] = beta;
+                        b.md_u[k] = u | disk_bit;
+                        b.md_hlo[k] = b.hin[i];
+                        b.md_hup[k] = b.hin[j];
+                    }
+                }
+                k++;
+            }
+        }
+        if (!kFill) b.md_cnt[u] = k;
+    }
+    if (!kFill && stats) atomicAdd(&t->cand[0], (unsigned long long)cand);
+}
+
+// ------------------------------------------------------ a3: line segments ---
+
+__device__ inline bool ls_cut(const LsClass &k, const Consts &c, bool bend,
+                              float xa, float ya, float za, float ra, float beta_a,
+                              float xb, float yb, float zb, float rb)
+{
+    float dx = xb - xa, dy = yb - ya;
+    float cr = xa * dy - ya * dx;
+    float d = xa * xb + ya * yb;
+    float rr = ra * rb;
+    if (!(d > 0.0f)) return false;
+    if (!(fabsf(cr) <= k.S * rr)) return false;
+    if (k.type == 0u) {
+        const float rho[2] = {k.rho_lo, k.rho_hi};
+        const float vv[2] = {-c.L, c.L};
+        const float zp[2] = {za - c.ec, za + c.ec};
+        float lo = rho[0] * (zp[0] - vv[0]) + vv[0];
+        float hi = lo;
+#pragma unroll
+        for (int i = 0; i < 2; i++)
+#pragma unroll
+            for (int j = 0; j < 2; j++)
+#pragma unroll
+                for (int l = 0; l < 2; l++) {
+                    if (i == 0 && j == 0 && l == 0) continue;
+                    float w = rho[i] * (zp[l] - vv[j]) + vv[j];
+                    lo = fminf(lo, w);
+                    hi = fmaxf(hi, w);
+                }
+        float mid = 0.5f * (lo + hi), half = 0.5f * (hi - lo) + c.ec;
+        if (!(fabsf(zb - mid) <= half)) return false;
+        if (bend) {
+            float sab = cr / rr;
+            float p1 = k.lam_lo * beta_a, p2 = k.lam_hi * beta_a;
+            float blo = fminf(p1, p2) - k.tau, bhi = fmaxf(p1, p2) + k.tau;
+            float bmid = 0.5f * (blo + bhi), bhalf = 0.5f * (bhi - blo);
+            if (!(fabsf(sab - bmid) <= bhalf)) return false;
+        }
+        return true;
+    }
+    if (k.type == 1u) {
+        float lo = k.lo_fac * (ra - c.ec) - c.ec;
+        float hi = k.hi_fac * (ra + c.ec) + c.ec;
+        float mid = 0.5f * (lo + hi), half = 0.5f * (hi - lo);
+        return fabsf(rb - mid) <= half;
+    }
+    float zap = k.zs * za;
+    float dhi = (zap + c.ec) + c.L;
+    if (!(dhi > 0.0f)) return false;
+    float lo = (k.cf * (k.zbpl / dhi)) * ra - c.ec;
+    float dlo = (zap - c.ec) - c.L;
+    if (dlo > 0.0f) {
+        float hi = (k.zbml / dlo) * ra + c.ec;
+        float mid = 0.5f * (lo + hi), half = 0.5f * (hi - lo);
+        return fabsf(rb - mid) <= half;
+    }
+    return lo <= rb;
+}
+
+template <bool kFill>
+__global__ __launch_bounds__(256) void k_ls(const Batch b, Totals *t, const DevGeom g, const Consts c,
+                                            int stats)
+{
+    const uint32_t n = min(t->n_md, b.cap_md);
+    const uint32_t n_mod = c.n_mod;
+    const bool bend = (c.flags & LST_FLAG_BEND) != 0u;
+    uint64_t cand = 0;
+    GRID_STRIDE(a, n) {
+        const uint32_t u = b.md_u[a] & kUnitMask;
+        const uint32_t m = u % n_mod;
+        const uint32_t base = u - m;
+        const float xa = b.md_x[a], ya = b.md_y[a], za = b.md_z[a], ra = b.md_r[a], ba = b.md_beta[a];
+        uint32_t k = kFill ? b.ls_off[a] : 0u;
+        const uint32_t e1 = g.edge_begin[m + 1];
+        for (uint32_t e = g.edge_begin[m]; e < e1; e++) {
+            const uint2 ed = g.edge[e];
+            const uint32_t bb = min(b.md_off[base + ed.x], b.cap_md);
+            const uint32_t be = min(b.md_off[base + ed.x + 1], b.cap_md);
+            if (bb == be) continue;
+            const LsClass kc = g.cls[ed.y];
+            for (uint32_t q = bb; q < be; q++) {
+                if (!kFill) cand++;
+                if (!ls_cut(kc, c, bend, xa, ya, za, ra, ba, b.md_x[q], b.md_y[q], b.md_z[q], b.md_r[q]))
+                    continue;
+                if (kFill && k < b.cap_ls) {
+                    b.ls_a[k] = a;
+                    b.ls_b[k] = q;
+                }
+                k++;
+            }
+        }
+        if (!kFill) b.ls_cnt[a] = k;
+    }
+    if (!kFill && stats) atomicAdd(&t->cand[1], (unsigned long long)cand);
+}
+
+// ------------------------------------------------------------ a4: T3 ----
+
+struct Anchor {
+    float x, y, z, r;
+    bool disk;
+};
+
+__device__ inline Anchor load_anchor(const Batch &b, uint32_t i)
+{
+    Anchor A;
+    A.x = b.md_x[i];
+    A.y = b.md_y[i];
+    A.z = b.md_z[i];
+    A.r = b.md_r[i];
+    A.disk = (b.md_u[i] & kDiskBit) != 0u;
+    return A;
+}
+
+// curvature of the circle through three transverse points (positive for a
+// clockwise turn) and its resolution; also returns the chords A-B and B-C
+__device__ inline void kappa3(const Consts &c, const Anchor &A, const Anchor &B, const Anchor &C,
+                              float &kap, float &sk, float &d1, float &d2)
+{
+    float dx1 = B.x - A.x, dy1 = B.y - A.y;
+    float dx2 = C.x - B.x, dy2 = C.y - B.y;
+    float dx3 = C.x - A.x, dy3 = C.y - A.y;
+    float cr = dx1 * dy2 - dy1 * dx2;
+    d1 = sqrtf(dx1 * dx1 + dy1 * dy1);
+    d2 = sqrtf(dx2 * dx2 + dy2 * dy2);
+    float d3 = sqrtf(dx3 * dx3 + dy3 * dy3);
+    kap = (-2.0f * cr) / ((d1 * d2) * d3);
+    float hC = fminf(1.0f, C.r * c.khalf);
+    float sdisk = c.srp + c.sc * hC;
+    float sA = A.disk ? sdisk : c.srp;
+    float sB = B.disk ? sdisk : c.srp;
+    float sC = C.disk ? sdisk : c.srp;
+    sk = (2.0f * sqrtf((sA * sA + sB * sB) + sC * sC)) / (d1 * d2);
+}
+
+// straight line in (arc length, z) through three anchors, up to resolution
+// and the arc-vs-chord bias
+__device__ inline bool rz3(const Consts &c, const Anchor &A, const Anchor &B, const Anchor &C,
+                           float d1, float d2)
+{
+    float E = (B.z - A.z) * d2 - (C.z - B.z) * d1;
+    float szA = A.disk ? 0.0f : c.sc, szB = B.disk ? 0.0f : c.sc, szC = C.disk ? 0.0f : c.sc;
+    float stA = A.disk ? c.sc : c.srp, stB = B.disk ? c.sc : c.srp, stC = C.disk ? c.sc : c.srp;
+    float res = (((szA * d2 + szB * (d1 + d2)) + szC * d1) + fabsf(B.z - A.z) * (stB + stC)) +
+                fabsf(C.z - B.z) * (stA + stB);
+    float bias = ((c.Kb * (fabsf(C.z - A.z) / (d1 + d2))) * (d1 * d2)) * fabsf(d1 * d1 - d2 * d2);
+    return fabsf(E) <= c.ns * res + bias;
+}
+
+template <bool kFill>
+__global__ __launch_bounds__(256) void k_t3(const Batch b, Totals *t, const Consts c, int stats)
+{
+    const uint32_t n = min(t->n_ls, b.cap_ls);
+    uint64_t cand = 0;
+    GRID_STRIDE(l1, n) {
+        const uint32_t ia = b.ls_a[l1], ib = b.ls_b[l1];
+        const uint32_t q0 = min(b.ls_off[ib], b.cap_ls), q1 = min(b.ls_off[ib + 1], b.cap_ls);
+        uint32_t k = kFill ? b.t3_off[l1] : 0u;
+        if (q0 == q1) {
+            if (!kFill) b.t3_cnt[l1] = 0;
+            continue;
+        }
+        const Anchor A = load_anchor(b, ia), B = load_anchor(b, ib);
+        for (uint32_t l2 = q0; l2 < q1; l2++) {
+            const uint32_t ic = b.ls_b[l2];
+            const Anchor C = load_anchor(b, ic);
+            float kap, sk, d1, d2;
+            if (!kFill) cand++;
+            kappa3(c, A, B, C, kap, sk, d1, d2);
+            if (!(fabsf(kap) <= c.kmaxf + c.ns * sk)) continue;
+            if (!rz3(c, A, B, C, d1, d2)) continue;
+            if (kFill && k < b.cap_t3) {
+                b.t3_l1[k] = l1;
+                b.t3_l2[k] = l2;
+                b.t3_a[k] = ia;
+                b.t3_c[k] = ic;
+                b.t3_k[k] = kap;
+                b.t3_sk[k] = sk;
+            }
+            k++;
+        }
+        if (!kFill) b.t3_cnt[l1] = k;
+    }
+    if (!kFill && stats) atomicAdd(&t->cand[2], (unsigned long long)cand);
+}
+
+// ------------------------------------------------------------ a5: T5 ----
+
+template <bool kFill>
+__global__ __launch_bounds__(256) void k_t5(const Batch b, Totals *t, const Consts c, int stats)
+{
+    const uint32_t n = min(t->n_t3, b.cap_t3);
+    uint64_t cand = 0;
+    GRID_STRIDE(u, n) {
+        const uint32_t ia = b.t3_a[u], ic = b.t3_c[u];
+        // T3s whose inner MD is ic: those built from segments starting at ic
+        const uint32_t w0 = min(b.t3_off[min(b.ls_off[ic], b.cap_ls)], b.cap_t3);
+        const uint32_t w1 = min(b.t3_off[min(b.ls_off[ic + 1], b.cap_ls)], b.cap_t3);
+        uint32_t k = kFill ? b.t5_off[u] : 0u;
+        if (w0 == w1) {
+            if (!kFill) b.t5_cnt[u] = 0;
+            continue;
+        }
+        const Anchor A = load_anchor(b, ia), C = load_anchor(b, ic);
+        const float k1 = b.t3_k[u], sk1 = b.t3_sk[u];
+        for (uint32_t w = w0; w < w1; w++) {
+            const Anchor E = load_anchor(b, b.t3_c[w]);
+            const float k2 = b.t3_k[w], sk2 = b.t3_sk[w];
+            float k3, sk3, d1, d2;
+            if (!kFill) cand++;
+            kappa3(c, A, C, E, k3, sk3, d1, d2);
+            if (!(fabsf(k1 - k2) <= c.ns * (sk1 + sk2))) continue;
+            if (!(fabsf(k1 - k3) <= c.ns * (sk1 + sk3))) continue;
+            if (!(fabsf(k2 - k3) <= c.ns * (sk2 + sk3))) continue;
+            if (!rz3(c, A, C, E, d1, d2)) continue;
+            if (kFill && k < b.cap_t5) {
+                b.t5_u[k] = u;
+                b.t5_w[k] = w;
+                b.t5_k[k] = k3;
+                b.t5_sk[k] = sk3;
+            }
+            k++;
+        }
+        if (!kFill) b.t5_cnt[u] = k;
+    }
+    if (!kFill && stats) atomicAdd(&t->cand[3], (unsigned long long)cand);
+}
+
+// --------------------------------------------- a6: seed lookup buckets ----
+// T3s (resp. T5s) are bucketed by (event, surface of the inner anchor,
+// azimuth bin of the inner anchor); a pixel seed then visits only the
+// buckets its helix band can reach.
+
+constexpr float kPiF = 3.14159265358979f;
+constexpr double kPiD = 3.14159265358979323846;
+
+__device__ inline uint32_t phi_bin(float x, float y, uint32_t nphi)
+{
+    float ph = atan2f(y, x);
+    int bi = (int)((ph + kPiF) * ((float)nphi / (2.0f * kPiF)));
+    bi = bi < 0 ? 0 : (bi >= (int)nphi ? (int)nphi - 1 : bi);
+    return (uint32_t)bi;
+}
+
+// kind 0: T3 objects, 1: T5 objects
+template <int kKind>
+__global__ void k_bucket_hist(const Batch b, Totals *t, const DevGeom g, const Consts c)
+{
+    const uint32_t n = kKind == 0 ? min(t->n_t3, b.cap_t3) : min(t->n_t5, b.cap_t5);
+    uint32_t *cnt = kKind == 0 ? b.bk3_cnt : b.bk5_cnt;
+    uint32_t *id = kKind == 0 ? b.bk3_id : b.bk5_id;
+    uint32_t *rank = kKind == 0 ? b.bk3_rank : b.bk5_rank;
+    GRID_STRIDE(i, n) {
+        const uint32_t a = kKind == 0 ? b.t3_a[i] : b.t3_a[b.t5_u[i]];
+        const uint32_t u = b.md_u[a] & kUnitMask;
+        const uint32_t e = u / c.n_mod, m = u - e * c.n_mod;
+        const uint32_t bk = (e * c.n_surf + g.mod_surf[m]) * c.nphi + phi_bin(b.md_x[a], b.md_y[a], c.nphi);
+        id[i] = bk;
+        rank[i] = atomicAdd(&cnt[bk], 1u);
+    }
+}
+
+template <int kKind>
+__global__ void k_bucket_scatter(const Batch b, const Totals *t)
+{
+    const uint32_t n = kKind == 0 ? min(t->n_t3, b.cap_t3) : min(t->n_t5, b.cap_t5);
+    const uint32_t *off = kKind == 0 ? b.bk3_off : b.bk5_off;
+    const uint32_t *id = kKind == 0 ? b.bk3_id : b.bk5_id;
+    const uint32_t *rank = kKind == 0 ? b.bk3_rank : b.bk5_rank;
+    uint32_t *items = kKind == 0 ? b.bk3_items : b.bk5_items;
+    GRID_STRIDE(i, n) items[off[id[i]] + rank[i]] = i;
+}
+
+// ------------------------------------------------- a7: pT3 / pT5 --------
+
+struct Seed {
+    double kp, skp, phi0, cot, z0, s11, s22, s44;
+};
+
+__device__ inline Seed load_seed(const Batch &b, const Consts &c, uint32_t p)
+{
+    Seed s;
+    const float *par = b.in_par + 5 * (size_t)p;
+    const float *cov = b.in_cov + 15 * (size_t)p;
+    s.kp = (double)par[0] * c.kB;
+    s.skp = c.kB * sqrt((double)cov[0]);
+    s.phi0 = par[1];
+    s.cot = par[2];
+    s.z0 = par[4];
+    s.s11 = sqrt((double)cov[5]);
+    s.s22 = sqrt((double)cov[9]);
+    s.s44 = sqrt((double)cov[14]);
+    return s;
+}
+
+// binary64 seed-object compatibility: curvature, then azimuth and z (barrel)
+// or r (disk) of the helix at the object's inner and outer anchors
+__device__ inline bool p_cut(const Consts &c, const Seed &s, float kobj, float skobj,
+                             const Anchor &in, const Anchor &out)
+{
+    const double ns = c.n_sigma;
+    if (!(fabs(s.kp - (double)kobj) <= ns * (s.skp + (double)skobj))) return false;
+    for (int i = 0; i < 2; i++) {
+        const Anchor &a = i == 0 ? in : out;
+        double x = a.x, y = a.y, z = a.z;
+        double r = sqrt(x * x + y * y);
+        double u = r * s.kp / 2.0;
+        if (!(fabs(u) < 1.0)) return false;
+        double dphi = atan2(y, x) - (s.phi0 - asin(u));
+        dphi = fmod(dphi + kPiD, 2.0 * kPiD);
+        if (dphi < 0.0) dphi += 2.0 * kPiD;
+        dphi -= kPiD;
+        double sr = a.disk ? c.sig_c : 0.0;
+        double W = ns * (s.s11 + (r * s.skp + sr * fabs(s.kp)) / (2.0 * sqrt(1.0 - u * u)) + c.sig_rphi / r);
+        if (!(fabs(dphi) <= W)) return false;
+        if (!a.disk) {
+            double sa = (u == 0.0) ? r : r * asin(u) / u;
+            double zp = s.z0 + s.cot * sa;
+            if (!(fabs(z - zp) <= ns * (s.s44 + sa * s.s22 + c.sig_c))) return false;
+        } else {
+            if (s.cot == 0.0) return false;
+            double sa = (z - s.z0) / s.cot;
+            if (!(sa > 0.0)) return false;
+            double w = fabs(s.kp) * sa / 2.0;
+            if (!(w < kPiD / 2)) return false;
+            double rp = (w == 0.0) ? sa : sa * sin(w) / w;
+            if (!(fabs(r - rp) <= ns * ((s.s44 + sa * s.s22) / fabs(s.cot) + c.sig_c))) return false;
+        }
+    }
+    return true;
+}
+
+// Azimuth bins of surface sf that can hold the inner anchor of an object
+// linked to seed s; returns false when the helix band misses the surface.
+// Conservative bounds of the seed cuts over the surface's anchor radii.
+__device__ inline bool seed_road(const Consts &c, const Seed &s, const Surface &sf,
+                                 int &b0, int &b1)
+{
+    const double ns = c.n_sigma;
+    const double ak = fabs(s.kp);
+    double ra, rb;
+    if (sf.kind == LST_BARREL) {
+        ra = sf.r1;
+        rb = sf.r2;
+        if (ak > 0.0 && ra * ak / 2.0 >= 1.0) return false;
+        if (ak > 0.0) rb = fmin(rb, 2.0 / ak);
+        double ua = ra * s.kp / 2.0, ub = rb * s.kp / 2.0;
+        double sa = (ua == 0.0) ? ra : ra * asin(ua) / ua;
+        double sb = (ub == 0.0) ? rb : rb * asin(ub) / ub;
+        double za = s.z0 + s.cot * sa, zb = s.z0 + s.cot * sb;
+        double wz = ns * (s.s44 + sb * s.s22 + c.sig_c) + 1e-3;
+        if (fmax(za, zb) + wz < sf.z1 || fmin(za, zb) - wz > sf.z2) return false;
+    } else {
+        if (s.cot == 0.0) return false;
+        double sa = ((double)sf.z1 - s.z0) / s.cot;
+        if (!(sa > 0.0)) return false;
+        double w = ak * sa / 2.0;
+        if (!(w < kPiD / 2)) return false;
+        double rp = (w == 0.0) ? sa : sa * sin(w) / w;
+        double wr = ns * ((s.s44 + sa * s.s22) / fabs(s.cot) + c.sig_c) + 0.01 / fabs(s.cot) + 0.01;
+        ra = fmax((double)sf.r1, rp - wr);
+        rb = fmin((double)sf.r2, rp + wr);
+        if (ak > 0.0) rb = fmin(rb, 2.0 / ak);
+        if (!(ra <= rb)) return false;
+    }
+    double ua = ra * s.kp / 2.0, ub = rb * s.kp / 2.0;
+    if (fabs(ua) >= 1.0) return false;
+    double pa = s.phi0 - asin(ua);
+    double pb = fabs(ub) >= 1.0 ? s.phi0 - (ub > 0 ? kPiD / 2 : -kPiD / 2) : s.phi0 - asin(ub);
+    double lo = fmin(pa, pb), hi = fmax(pa, pb);
+    double um = fmin(fabs(ub), 1.0);
+    double sr = sf.kind == LST_BARREL ? 0.0 : c.sig_c;
+    double den = 2.0 * sqrt(fmax(1.0 - um * um, 0.0));
+    double W = den > 1e-6 ? ns * (s.s11 + (rb * s.skp + sr * ak) / den + c.sig_rphi / ra) : 10.0;
+    double pad = W + 1e-3;
+    lo -= pad;
+    hi += pad;
+    if (hi - lo >= 2.0 * kPiD) {
+        b0 = 0;
+        b1 = (int)c.nphi - 1;
+        return true;
+    }
+    const double scale = (double)c.nphi / (2.0 * kPiD);
+    b0 = (int)floor((lo + kPiD) * scale);
+    b1 = (int)floor((hi + kPiD) * scale);
+    if (b1 - b0 >= (int)c.nphi) b1 = b0 + (int)c.nphi - 1;
+    return true;
+}
+
+template <int kKind, bool kFill>
+__global__ __launch_bounds__(256) void k_pt(const Batch b, Totals *t, const DevGeom g, const Consts c,
+                                            int stats)
+{
+    const uint32_t n = min(t->n_pls, b.cap_pls);
+    const uint32_t n_ev = t->n_ev;
+    const uint32_t *bk_off = kKind == 0 ? b.bk3_off : b.bk5_off;
+    const uint32_t *bk_items = kKind == 0 ? b.bk3_items : b.bk5_items;
+    uint32_t *cnt = kKind == 0 ? b.pt3_cnt : b.pt5_cnt;
+    const uint32_t *off = kKind == 0 ? b.pt3_off : b.pt5_off;
+    uint32_t *out_p = kKind == 0 ? b.pt3_p : b.pt5_p;
+    uint32_t *out_o = kKind == 0 ? b.pt3_o : b.pt5_o;
+    const uint32_t cap = kKind == 0 ? b.cap_pt3 : b.cap_pt5;
+    uint64_t cand = 0;
+    GRID_STRIDE(p, n) {
+        const uint32_t e = find_event(b.ev_pls_off, n_ev, p);
+        const Seed s = load_seed(b, c, p);
+        const uint32_t k0 = kFill ? off[p] : 0u;
+        uint32_t k = k0;
+        for (uint32_t sfi = 0; sfi < c.n_surf; sfi++) {
+            const Surface sf = g.surf[sfi];
+            if (sf.kind > 1u) continue;
+            int b0, b1;
+            if (!seed_road(c, s, sf, b0, b1)) continue;
+            const uint32_t row = (e * c.n_surf + sfi) * c.nphi;
+            for (int bi = b0; bi <= b1; bi++) {
+                const uint32_t bin = (uint32_t)(((bi % (int)c.nphi) + (int)c.nphi) % (int)c.nphi);
+                const uint32_t i0 = bk_off[row + bin], i1 = bk_off[row + bin + 1];
+                for (uint32_t i = i0; i < i1; i++) {
+                    const uint32_t o = bk_items[i];
+                    uint32_t ia, io;
+                    float ko, sko;
+                    if (kKind == 0) {
+                        ia = b.t3_a[o];
+                        io = b.t3_c[o];
+                        ko = b.t3_k[o];
+                        sko = b.t3_sk[o];
+                    } else {
+                        ia = b.t3_a[b.t5_u[o]];
+                        io = b.t3_c[b.t5_w[o]];
+                        ko = b.t5_k[o];
+                        sko = b.t5_sk[o];
+                    }
+                    if (!kFill) cand++;
+                    if (!p_cut(c, s, ko, sko, load_anchor(b, ia), load_anchor(b, io))) continue;
+                    if (kFill && k < cap) {
+                        out_p[k] = p;
+                        out_o[k] = o;
+                    }
+                    k++;
+                }
+            }
+        }
+        if (!kFill) {
+            cnt[p] = k;
+        } else {
+            // canonical order within the seed: by object index
+            const uint32_t k1 = min(k, cap);
+            for (uint32_t i = k0 + 1; i < k1; i++) {
+                uint32_t v = out_o[i];
+                uint32_t j = i;
+                while (j > k0 && out_o[j - 1] > v) {
+                    out_o[j] = out_o[j - 1];
+                    j--;
+                }
+                out_o[j] = v;
+            }
+        }
+    }
+    if (!kFill && stats) atomicAdd(&t->cand[4 + kKind], (unsigned long long)cand);
+}
+
+// ------------------------------------------------ a8: track candidates ----
+
+__global__ void k_tc_mark(const Batch b, const Totals *t)
+{
+    const uint32_t n5 = min(t->n_pt5, b.cap_pt5), n3 = min(t->n_pt3, b.cap_pt3);
+    GRID_STRIDE(i, n5) {
+        b.pls_used5[b.pt5_p[i]] = 1u;
+        b.t5_used[b.pt5_o[i]] = 1u;
+    }
+    GRID_STRIDE(i, n3) b.pls_used3[b.pt3_p[i]] = 1u;
+}
+
+// keep flags over [pT3 | T5 | pLS]: pT3 whose seed has no pT5, T5 in no pT5,
+// seeds in neither (every pT5 is a track candidate)
+__global__ void k_tc_keep(const Batch b, Totals *t)
+{
+    const uint32_t n3 = min(t->n_pt3, b.cap_pt3), n5 = min(t->n_t5, b.cap_t5), np = min(t->n_pls, b.cap_pls);
+    const uint32_t n = n3 + n5 + np;
+    if (blockIdx.x == 0 && threadIdx.x == 0) t->n_tcu = n;
+    GRID_STRIDE(i, n) {
+        uint32_t keep;
+        if (i < n3) keep = b.pls_used5[b.pt3_p[i]] ? 0u : 1u;
+        else if (i < n3 + n5) keep = b.t5_used[i - n3] ? 0u : 1u;
+        else {
+            uint32_t p = i - n3 - n5;
+            keep = (b.pls_used5[p] | b.pls_used3[p]) ? 0u : 1u;
+        }
+        b.tc_cnt[i] = keep;
+    }
+}
+
+__global__ void k_tc_write(const Batch b, const Totals *t)
+{
+    const uint32_t n = t->n_tcu;
+    const uint32_t n3 = min(t->n_pt3, b.cap_pt3), n5 = min(t->n_t5, b.cap_t5);
+    GRID_STRIDE(i, n) {
+        if (!b.tc_cnt[i]) continue;
+        uint32_t k = b.tc_off[i];
+        if (k >= b.cap_tc) continue;
+        uint32_t type, idx;
+        if (i < n3) { type = LST_TC_PT3; idx = i; }
+        else if (i < n3 + n5) { type = LST_TC_T5; idx = i - n3; }
+        else { type = LST_TC_PLS; idx = i - n3 - n5; }
+        b.tc_type[k] = type;
+        b.tc_idx[k] = idx;
+    }
+}
+
+// per-event first index of every list (row n_ev holds the totals)
+__global__ void k_event_table(const Batch b, const Totals *t, uint32_t n_mod)
+{
+    const uint32_t n_ev = t->n_ev;
+    const uint32_t n3 = min(t->n_pt3, b.cap_pt3), n5 = min(t->n_t5, b.cap_t5);
+    GRID_STRIDE(e, n_ev + 1) {
+        uint32_t *row = b.ev_tab + (size_t)e * kEvTabCols;
+        uint32_t hit = b.ev_hit_off[e], pls = b.ev_pls_off[e];
+        uint32_t md = min(b.md_off[e * n_mod], b.cap_md);
+        uint32_t ls = min(b.ls_off[md], b.cap_ls);
+        uint32_t t3 = min(b.t3_off[ls], b.cap_t3);
+        uint32_t t5 = min(b.t5_off[t3], b.cap_t5);
+        uint32_t p3 = min(b.pt3_off[pls], b.cap_pt3);
+        uint32_t p5 = min(b.pt5_off[pls], b.cap_pt5);
+        row[0] = hit;
+        row[1] = pls;
+        row[2] = md;
+        row[3] = ls;
+        row[4] = t3;
+        row[5] = t5;
+        row[6] = p3;
+        row[7] = p5;
+        row[8] = b.tc_off[min(p3, n3)];
+        row[9] = b.tc_off[n3 + min(t5, n5)];
+        row[10] = b.tc_off[n3 + n5 + pls];
+        row[11] = 0;
+    }
+}
+
+// ----------------------------------------------------------- launchers ----
+
+void Launcher::scan(const uint32_t *in, uint32_t *out, const uint32_t *n_ptr, uint32_t cap,
+                    uint32_t *total, const char *name)
+{
+    launch(name, k_scan_up, dim3(kScanGrid), dim3(kScanBlock), in, n_ptr, cap, part);
+    launch(name, k_scan_mid, dim3(1), dim3(kScanBlock), part, n_ptr, cap, out, total);
+    launch(name, k_scan_down, dim3(kScanGrid), dim3(kScanBlock), in, n_ptr, cap, (const uint32_t *)part, out);
+}
+
+static inline dim3 grid_for(uint64_t units)
+{
+    uint64_t g = (units + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > kMaxGrid) g = kMaxGrid;
+    return dim3((unsigned)g);
+}
+
+void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, const Consts &c, int stats)
+{
+    const dim3 blk(256);
+    const uint32_t n_mod = c.n_mod;
+    // a1: hit ingest & sort by (event, module, sensor)
+    launch_setup(L, t, c);
+    L.launch("zero", k_zero_u32, grid_for((uint64_t)b.cap_ev * 2 * n_mod + 1), blk, b.bin_cnt, &t->n_bins,
+             b.cap_ev * 2u * n_mod, 1u);
+    L.launch("hit_hist", k_hit_hist, grid_for(b.cap_hits), blk, b, t, n_mod);
+    L.launch("pls_check", k_pls_check, grid_for(b.cap_pls), blk, b, t);
+    L.scan(b.bin_cnt, b.bin_off, &t->n_bins, b.cap_ev * 2u * n_mod, &t->n_sorted, "scan_hits");
+    L.launch("hit_scatter", k_hit_scatter, grid_for(b.cap_hits), blk, b, (const Totals *)t);
+    L.launch("hit_gather", k_hit_gather, grid_for((uint64_t)b.cap_ev * 2 * n_mod), blk, b, (const Totals *)t,
+             n_mod);
+    // a2: mini-doublets
+    const dim3 gmd = grid_for((uint64_t)b.cap_ev * n_mod);
+    L.launch("md_count", k_md<false>, gmd, blk, b, t, g, c, stats);
+    L.scan(b.md_cnt, b.md_off, &t->n_md_units, b.cap_ev * n_mod, &t->n_md, "scan_md");
+    L.launch("md_fill", k_md<true>, gmd, blk, b, t, g, c, 0);
+    // a3: line segments over the connection map
+    L.launch("ls_count", k_ls<false>, grid_for(b.cap_md), blk, b, t, g, c, stats);
+    L.scan(b.ls_cnt, b.ls_off, &t->n_md, b.cap_md, &t->n_ls, "scan_ls");
+    L.launch("ls_fill", k_ls<true>, grid_for(b.cap_md), blk, b, t, g, c, 0);
+    // a4: T3
+    L.launch("t3_count", k_t3<false>, grid_for(b.cap_ls), blk, b, t, c, stats);
+    L.scan(b.t3_cnt, b.t3_off, &t->n_ls, b.cap_ls, &t->n_t3, "scan_t3");
+    L.launch("t3_fill", k_t3<true>, grid_for(b.cap_ls), blk, b, t, c, 0);
+    // a5: T5
+    L.launch("t5_count", k_t5<false>, grid_for(b.cap_t3), blk, b, t, c, stats);
+    L.scan(b.t5_cnt, b.t5_off, &t->n_t3, b.cap_t3, &t->n_t5, "scan_t5");
+    L.launch("t5_fill", k_t5<true>, grid_for(b.cap_t3), blk, b, t, c, 0);
+    // a6: seed lookup buckets
+    const uint32_t cap_bk = b.cap_ev * c.n_surf * c.nphi;
+    L.launch("zero", k_zero_u32, grid_for((uint64_t)cap_bk + 1), blk, b.bk3_cnt, &t->n_bk, cap_bk, 1u);
+    L.launch("zero", k_zero_u32, grid_for((uint64_t)cap_bk + 1), blk, b.bk5_cnt, &t->n_bk, cap_bk, 1u);
+    L.launch("bucket_hist", k_bucket_hist<0>, grid_for(b.cap_t3), blk, b, t, g, c);
+    L.launch("bucket_hist", k_bucket_hist<1>, grid_for(b.cap_t5), blk, b, t, g, c);
+    L.scan(b.bk3_cnt, b.bk3_off, &t->n_bk, cap_bk, &t->n_bk3, "scan_bucket");
+    L.scan(b.bk5_cnt, b.bk5_off, &t->n_bk, cap_bk, &t->n_bk5, "scan_bucket");
+    L.launch("bucket_scatter", k_bucket_scatter<0>, grid_for(b.cap_t3), blk, b, (const Totals *)t);
+    L.launch("bucket_scatter", k_bucket_scatter<1>, grid_for(b.cap_t5), blk, b, (const Totals *)t);
+    // a7: pT3 / pT5
+    L.launch("pt3_count", k_pt<0, false>, grid_for(b.cap_pls), blk, b, t, g, c, stats);
+    L.scan(b.pt3_cnt, b.pt3_off, &t->n_pls, b.cap_pls, &t->n_pt3, "scan_pt");
+    L.launch("pt3_fill", k_pt<0, true>, grid_for(b.cap_pls), blk, b, t, g, c, 0);
+    L.launch("pt5_count", k_pt<1, false>, grid_for(b.cap_pls), blk, b, t, g, c, stats);
+    L.scan(b.pt5_cnt, b.pt5_off, &t->n_pls, b.cap_pls, &t->n_pt5, "scan_pt");
+    L.launch("pt5_fill", k_pt<1, true>, grid_for(b.cap_pls), blk, b, t, g, c, 0);
+    // a8: track candidates
+    L.launch("zero8", k_zero_u8, grid_for(b.cap_pls), blk, b.pls_used5, &t->n_pls, b.cap_pls);
+    L.launch("zero8", k_zero_u8, grid_for(b.cap_pls), blk, b.pls_used3, &t->n_pls, b.cap_pls);
+    L.launch("zero8", k_zero_u8, grid_for(b.cap_t5), blk, b.t5_used, &t->n_t5, b.cap_t5);
+    L.launch("tc_mark", k_tc_mark, grid_for(std::max(b.cap_pt3, b.cap_pt5)), blk, b, (const Totals *)t);
+    L.launch("tc_keep", k_tc_keep, grid_for((uint64_t)b.cap_pt3 + b.cap_t5 + b.cap_pls), blk, b, t);
+    L.scan(b.tc_cnt, b.tc_off, &t->n_tcu, b.cap_pt3 + b.cap_t5 + b.cap_pls, &t->n_tc, "scan_tc");
+    L.launch("tc_write", k_tc_write, grid_for((uint64_t)b.cap_pt3 + b.cap_t5 + b.cap_pls), blk, b,
+             (const Totals *)t);
+    L.launch("event_table", k_event_table, grid_for(b.cap_ev + 1), blk, b, (const Totals *)t, n_mod);
+}
+
+void launch_setup(Launcher &L, Totals *t, const Consts &c)
+{
+    L.launch("setup", k_setup, dim3(1), dim3(64), t, c.n_mod, c.n_surf, c.nphi);
+}
+
+}  // namespace lst

@@ -1,0 +1,82 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every function
+include/lst.h declares, and its host-only connection map is conservative
+(every segment the brute-force oracle builds lies on a map edge)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2407_18231_amd import lst, synth as s
+from truth import _surface_ids, _is_next
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(lst.LIB_PATH):
+        from paper_2407_18231_amd import build
+        build.build()
+    return lst.load()
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "lst.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lst_\w+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings(lib):
+    for code in lst.STATUS:
+        assert lib.lst_status_str(code)
+
+
+def test_default_params(lib):
+    p = lst.default_params()
+    assert p.B == 3.8 and p.pt_min == 0.8 and p.L == 15.0 and p.n_sigma == 3.0
+    assert p.flags == lst.LST_FLAG_BEND and p.max_batch == 64 and p.n_slots == 2
+
+
+def test_bad_geometry_rejected(lib):
+    g = s.make_geometry("tiny")
+    m = lst.module_table(g)
+    m["s_hi"][5] = m["s_lo"][5] - 1.0
+    with pytest.raises(lst.LstError) as e:
+        lst.build_connection_map(m)
+    assert e.value.name == "BAD_GEOMETRY"
+    m = lst.module_table(g)
+    m["s_lo"][100] += 0.5           # one module of layer 1 off its surface
+    with pytest.raises(lst.LstError):
+        lst.build_connection_map(m)
+
+
+@pytest.mark.parametrize("kind", ["tiny", "pu200"])
+def test_connection_map_holds_every_oracle_segment(lib, kind):
+    g, ev = s.standard_event(kind)
+    begin, dst = lst.build_connection_map(g)
+    assert begin.shape == (g.n_mod + 1,) and begin[-1] == dst.size
+    # edges only to the next surface
+    sid, nb, nd = _surface_ids(g)
+    src = np.repeat(np.arange(g.n_mod), np.diff(begin))
+    assert all(_is_next(nb, nd, int(sid[a]), int(sid[b])) for a, b in zip(src[::97], dst[::97]))
+    edges = set(zip(src.tolist(), dst.tolist()))
+    r = oracle.run(g, ev)
+    md_mod = ev["module"][r["md"][:, 0]]
+    pairs = {(int(md_mod[a]), int(md_mod[b])) for a, b in r["ls"]}
+    assert len(pairs) > 100
+    missing = pairs - edges
+    assert not missing, list(missing)[:5]
+    # and the map is selective: far fewer edges than next-surface module pairs
+    n_pairs = sum(int((sid == t).sum()) for a in range(g.n_mod)
+                  for t in set(range(nb + 2 * nd)) if _is_next(nb, nd, int(sid[a]), t)) if kind == "tiny" else None
+    if n_pairs:
+        assert dst.size < 0.5 * n_pairs

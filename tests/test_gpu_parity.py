@@ -1,0 +1,217 @@
+"""GPU parity: the HIP chain against the CPU oracle, through the C ABI.
+
+Bar: outside flagged borderline candidates (within 1e-5 relative of a cut
+boundary, counted by the oracle) the object lists are identical, as sets of
+expanded input-hit keys, at every stage (MD, LS, T3, T5, pT3, pT5, TC).  Also:
+outputs are canonical (sorted, no duplicates), deterministic, identical
+alone / in a batch / through device pointers / in the served mix, and bad
+inputs return the documented error codes.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2407_18231_amd import lst, synth as s
+
+pytestmark = pytest.mark.gpu
+
+STAGES = ("md", "ls", "t3", "t5", "pt3", "pt5", "tc")
+
+
+@pytest.fixture(scope="module")
+def geo():
+    return {k: s.make_geometry(k) for k in ("tiny", "pu200")}
+
+
+@pytest.fixture(scope="module")
+def ctx(geo):
+    c = lst.Context()
+    c.load_geometry(geo["pu200"])
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def ctx_tiny(geo):
+    c = lst.Context()
+    c.load_geometry(geo["tiny"])
+    yield c
+    c.close()
+
+
+def check_parity(geom, ev, res, flag_budget=1e-3):
+    kd = oracle.keyed(oracle.run(geom, ev))
+    got = lst.result_keys(res)
+    for k in STAGES:
+        assert len(set(got[k])) == len(got[k]), f"duplicates in {k}"
+    rep = oracle.compare(kd, got)
+    for k in STAGES:
+        r = rep[k]
+        print(k, {q: r[q] for q in ("got", "total", "flagged", "missing", "extra")}, flush=True)
+        assert r["missing"] == 0 and r["extra"] == 0, (k, r)
+        assert r["flagged"] <= max(3, flag_budget * r["total"]), (k, r)
+    return rep
+
+
+def check_canonical(res, ev):
+    md = res["md"].astype(np.int64)
+    if len(md) > 1:
+        key = np.lexsort((md[:, 1], md[:, 0], ev["module"][md[:, 0]]))
+        assert np.array_equal(key, np.arange(len(md))), "md order"
+    for k in ("ls", "t3", "t5", "pt3", "pt5"):
+        a = res[k].astype(np.int64)
+        if len(a) > 1:
+            key = a[:, 0] * (1 << 32) + a[:, 1]
+            assert np.all(np.diff(key) > 0), k
+
+
+def test_parity_tiny(ctx_tiny, geo):
+    g = geo["tiny"]
+    ev = s.gen_event(g, s.config_tiny(), s.event_seed(1, 0))
+    res = ctx_tiny.run_event(ev)
+    check_canonical(res, ev)
+    check_parity(g, ev, res)
+    assert len(res["t5"]) > 50
+
+
+@pytest.mark.parametrize("i", [0, 1])
+def test_parity_pu200(ctx, geo, i):
+    g = geo["pu200"]
+    ev = s.gen_event(g, s.config_pu(200), s.event_seed(2, i))
+    res = ctx.run_event(ev)
+    check_canonical(res, ev)
+    check_parity(g, ev, res)
+    assert len(res["pt5"]) > 500 and len(res["ls"]) > 50_000
+
+
+def test_parity_pu300_stress(ctx, geo):
+    g = geo["pu200"]
+    ev = s.gen_event(g, s.config_pu(300, noise_frac=0.4, fake_frac=0.05), s.event_seed(5, 0))
+    res = ctx.run_event(ev)
+    check_canonical(res, ev)
+    check_parity(g, ev, res)
+
+
+def test_parity_edge_cases(ctx, geo):
+    g = geo["pu200"]
+    empty = dict(x=np.zeros(0, np.float32), y=np.zeros(0, np.float32), z=np.zeros(0, np.float32),
+                 module=np.zeros(0, np.uint32), sensor=np.zeros(0, np.uint8),
+                 pls_par=np.zeros((0, 5), np.float32), pls_cov=np.zeros((0, 15), np.float32))
+    res = ctx.run_event(empty)
+    assert all(len(res[k]) == 0 for k in STAGES)
+    # seeds only: every seed is an unlinked track candidate
+    ev = s.gen_event(g, s.config_pu(5), 77)
+    seeds_only = dict(empty, pls_par=ev["pls_par"], pls_cov=ev["pls_cov"])
+    res = ctx.run_event(seeds_only)
+    assert len(res["tc"]) == len(ev["pls_par"])
+    assert np.all(res["tc"][:, 0] == lst.TC_PLS)
+    # hits only, and a single-track event, against the oracle
+    hits_only = dict(ev, pls_par=np.zeros((0, 5), np.float32), pls_cov=np.zeros((0, 15), np.float32))
+    check_parity(g, hits_only, ctx.run_event(hits_only))
+    one = s.gen_event(g, s.config_pu(1, n_tracks=1, pt_mode="uniform", pt_lo=2, pt_hi=3, eta_max=0.5,
+                                     n_pls=1, fake_frac=0.0, noise_frac=0.0, ineff=0.0), 5)
+    check_parity(g, one, ctx.run_event(one))
+
+
+def test_batch_matches_single_events(ctx, geo):
+    g = geo["pu200"]
+    evs = s.batch_events(6, g)
+    evs.insert(3, dict(x=np.zeros(0, np.float32), y=np.zeros(0, np.float32), z=np.zeros(0, np.float32),
+                       module=np.zeros(0, np.uint32), sensor=np.zeros(0, np.uint8),
+                       pls_par=np.zeros((0, 5), np.float32), pls_cov=np.zeros((0, 15), np.float32)))
+    batch = ctx.run_batch(evs)
+    for ev, rb in zip(evs, batch):
+        r1 = ctx.run_event(ev)
+        for k in STAGES:
+            assert np.array_equal(r1[k], rb[k]), k
+    check_parity(g, evs[0], batch[0])
+
+
+def test_deterministic(ctx, geo):
+    g = geo["pu200"]
+    ev = s.gen_event(g, s.config_pu(200), s.event_seed(2, 3))
+    a = ctx.run_event(ev)
+    for _ in range(3):
+        b = ctx.run_event(ev)
+        for k in STAGES:
+            assert np.array_equal(a[k], b[k]), k
+        assert np.array_equal(a["t3_kappa"].view(np.uint32), b["t3_kappa"].view(np.uint32))
+
+
+def test_device_pointer_inputs(ctx, geo):
+    torch = pytest.importorskip("torch")
+    g = geo["pu200"]
+    ev = s.gen_event(g, s.config_pu(100), 91)
+    ref = ctx.run_event(ev)
+    dev = {k: torch.from_numpy(np.ascontiguousarray(ev[k])).to("cuda:0")
+           for k in ("x", "y", "z", "pls_par", "pls_cov", "sensor")}
+    dev["module"] = torch.from_numpy(ev["module"].astype(np.int32)).to("cuda:0")
+    torch.cuda.synchronize()
+    got = ctx.run_event(dev)
+    for k in STAGES:
+        assert np.array_equal(ref[k], got[k]), k
+
+
+def test_served_mix_matches_alone(geo):
+    g = geo["pu200"]
+    evs = s.batch_events(10, g, pu_lo=140, pu_hi=200, seed_base=4)
+    with lst.Context(max_batch=4, n_slots=2) as c:
+        c.load_geometry(g)
+        alone = [c.run_event(ev) for ev in evs]
+        tickets = [c.submit(ev) for ev in evs]
+        outs = {}
+        for t in tickets:
+            outs[t] = c.poll(t, -1)
+        for ev, t, a in zip(evs, tickets, alone):
+            o = outs[t]
+            assert o["ticket"] == t and o["latency_us"] > 0
+            for k in STAGES:
+                assert np.array_equal(a[k], o[k]), k
+        with pytest.raises(lst.LstError) as e:
+            c.poll(tickets[0], 0)
+        assert e.value.name == "UNKNOWN_TICKET"
+
+
+def test_error_codes(ctx, geo):
+    g = geo["pu200"]
+    ev = s.gen_event(g, s.config_pu(10), 3)
+    bad = dict(ev, module=ev["module"].copy())
+    bad["module"][7] = g.n_mod + 5
+    with pytest.raises(lst.LstError) as e:
+        ctx.run_event(bad)
+    assert e.value.name == "BAD_MODULE"
+    bad = dict(ev, x=ev["x"].copy())
+    bad["x"][3] = np.nan
+    with pytest.raises(lst.LstError) as e:
+        ctx.run_event(bad)
+    assert e.value.name == "NONFINITE"
+    bad = dict(ev, pls_par=ev["pls_par"].copy())
+    bad["pls_par"][0, 1] = np.inf
+    with pytest.raises(lst.LstError) as e:
+        ctx.run_event(bad)
+    assert e.value.name == "NONFINITE"
+    # the context still works after input errors
+    check_parity(g, ev, ctx.run_event(ev))
+    with lst.Context() as c:
+        with pytest.raises(lst.LstError) as e:
+            c.run_event(ev)
+        assert e.value.name == "NO_GEOMETRY"
+
+
+def test_regrow_after_overflow(geo):
+    """A batch far larger than the first one forces the object lists to grow;
+    results equal a fresh run."""
+    g = geo["pu200"]
+    small = s.gen_event(g, s.config_pu(20), 1)
+    big = s.gen_event(g, s.config_pu(300, noise_frac=0.4), 2)
+    with lst.Context() as c:
+        c.load_geometry(g)
+        c.run_event(small)
+        r_big = c.run_event(big)
+    with lst.Context() as c:
+        c.load_geometry(g)
+        r_ref = c.run_event(big)
+    for k in STAGES:
+        assert np.array_equal(r_big[k], r_ref[k]), k
