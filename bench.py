@@ -1,0 +1,239 @@
+"""Benchmark of the LST object-building chain on one MI355X.
+
+Workload: PU200-like events (6 barrel layers + 2 x 5 disks, 12 800 modules,
+4000 tracks with dN/dpT ~ pT^-3 above 0.5 GeV, |eta| < 2.4, 10% hit
+inefficiency, 20% noise hits, 2000 pixel seeds with 2% fakes), synthetic and
+seeded (event i uses seed 2000 + i).  One step = the whole chain (hit sort,
+MD, LS, T3, T5, seed lookup, pT3/pT5, TC) over one batch of events already
+resident in device memory.
+
+Printed JSON line: value = events/s of the batched path (64 events per
+launch); beside it the plain one-event-per-launch path (events/s, p50/p99
+latency on device and end to end), a mixed-pileup batch, the roofline of the
+dominant kernel (HIP events on the library's stream over the timed region),
+and the CPU oracle on the host as a reported baseline.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch 64]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# Algorithmic bytes per unit of work of each kernel (what the method must move
+# at least once per launch; re-reads that a kernel serves from cache are not
+# counted).  Sizes: hit 17 B in (x, y, z, module, sensor), sorted hit 20 B,
+# MD anchor 24 B (x, y, z, r, beta, unit), MD record 32 B, pair 8 B.
+def algorithmic_bytes(name: str, c: dict, n_hits: int, n_pls: int, n_units: int, n_edges_used: int) -> float:
+    if name == "ls_count":
+        # every MD's anchor once, the MD ranges of the (event, module) units,
+        # the edges leaving modules that hold MDs and one count per MD
+        return 24.0 * c["md"] + 4.0 * n_units + 8.0 * n_edges_used + 4.0 * c["md"]
+    if name == "ls_fill":
+        return 24.0 * c["md"] + 4.0 * n_units + 8.0 * n_edges_used + 4.0 * c["md"] + 8.0 * c["ls"]
+    if name in ("md_count", "md_fill"):
+        return 20.0 * n_hits + 8.0 * n_units + (32.0 * c["md"] if name == "md_fill" else 4.0 * n_units)
+    if name in ("t3_count", "t3_fill"):
+        out = 24.0 * c["t3"] if name == "t3_fill" else 4.0 * c["ls"]
+        return 8.0 * c["ls"] + 4.0 * c["md"] + 17.0 * c["md"] + out
+    if name in ("t5_count", "t5_fill"):
+        out = 16.0 * c["t5"] if name == "t5_fill" else 4.0 * c["t3"]
+        return 16.0 * c["t3"] + 4.0 * c["ls"] + 17.0 * c["md"] + out
+    if name in ("pt3_count", "pt3_fill", "pt5_count", "pt5_fill"):
+        obj = c["t3"] if name.startswith("pt3") else c["t5"]
+        return 80.0 * n_pls + 16.0 * obj + 17.0 * c["md"] + 4.0 * n_pls
+    return 0.0
+
+
+def cpu_baseline(n_events: int, budget_s: float):
+    import oracle
+    from paper_2407_18231_amd import synth
+    g = synth.make_geometry("pu200")
+    oracle.build(force=False)
+    times = []
+    t_all = time.perf_counter()
+    for i in range(n_events):
+        ev = synth.gen_event(g, synth.config_pu(200), synth.event_seed(2, i))
+        t0 = time.perf_counter()
+        oracle.run(g, ev)
+        times.append(time.perf_counter() - t0)
+        if time.perf_counter() - t_all > budget_s:
+            break
+    tot = sum(times)
+    return dict(value=len(times) / tot, unit="events/s", cores=1, kind="oracle",
+                sample=f"{len(times)} PU200-like events (seeds 2000..{1999 + len(times)}), "
+                       f"one thread, {tot:.1f} s of oracle time")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-events", type=int, default=8)
+    ap.add_argument("--cpu-budget", type=float, default=25.0)
+    ap.add_argument("--quick", action="store_true", help="only the batched path (profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU: the events of a batch shard across GPUs with no "
+              f"exchange, so there is no multi-GPU path to time (asked for --gpus {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2407_18231_amd import lst, synth
+
+    g = synth.make_geometry("pu200")
+    B = args.batch
+    t0 = time.perf_counter()
+    events = [synth.gen_event(g, synth.config_pu(200), synth.event_seed(2, i)) for i in range(B)]
+    log(f"generated {B} events in {time.perf_counter() - t0:.1f} s")
+    n_hits = int(sum(e["x"].size for e in events))
+    n_pls = int(sum(e["pls_par"].shape[0] for e in events))
+
+    ctx = lst.Context(max_batch=max(B, 64))
+    ctx.load_geometry(g)
+    begin, dst = ctx.connection_map()
+
+    # ---- batched path: B events per launch --------------------------------
+    ctx.batch_upload(events)
+    counts = ctx.batch_counts()
+    log("object totals:", counts)
+    for _ in range(args.warmup):
+        ctx.batch_execute(1, graph=False, timing=False)
+    # timed region: K steps, each kernel bracketed by HIP events on the
+    # library's stream (the source of the per-kernel durations below)
+    t0 = time.perf_counter()
+    dev_ms = ctx.batch_execute(args.steps, graph=False, timing=True)
+    wall = time.perf_counter() - t0
+    ktimes = ctx.kernel_times()
+    ms_per_step = 1e3 * wall / args.steps
+    value = B / (wall / args.steps)
+    log(f"batched: {ms_per_step:.3f} ms/step, {value:.1f} events/s (device {dev_ms / args.steps:.3f} ms/step)")
+    # graph replay of the same chain
+    ctx.batch_execute(2, graph=True)
+    t0 = time.perf_counter()
+    ctx.batch_execute(args.steps, graph=True)
+    graph_rate = B / ((time.perf_counter() - t0) / args.steps)
+    log(f"batched, graph replay: {graph_rate:.1f} events/s")
+
+    # dominant kernel and its roofline
+    per = {k: v[0] / max(v[1], 1) for k, v in ktimes.items()}
+    step_ms = {k: v[0] / args.steps for k, v in ktimes.items()}
+    dom = max(step_ms, key=step_ms.get)
+    md_units = B * g.n_mod
+    # edges leaving modules that hold at least one MD: count from the map
+    edges_used = float(np.diff(begin).mean()) * min(counts["md"], md_units)
+    alg = algorithmic_bytes(dom, counts, n_hits, n_pls, md_units, int(edges_used))
+    avg_ms = per[dom]
+    achieved = alg / (avg_ms * 1e-3) / 1e9 if alg else 0.0
+    roofline = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    avg_launch_ms=round(avg_ms, 4), algorithmic_bytes=int(alg))
+    stages = {k: round(v, 4) for k, v in sorted(step_ms.items(), key=lambda kv: -kv[1])}
+    log("ms per step by kernel:", stages)
+
+    result = dict(metric="events/sec at PU200-like load, batched vs per-event; p50/p99 event latency",
+                  value=round(value, 2), unit="events/s", n_gpus=1, steps=args.steps,
+                  warmup=args.warmup, ms_per_step=round(ms_per_step, 4), higher_is_better=True,
+                  scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
+                  config=dict(workload=f"{B} PU200-like events per launch (single-event PU200 shape, "
+                                       f"seeds 2000+i), batched path, inputs resident in HBM",
+                              events_per_step=B, pileup=200, modules=g.n_mod,
+                              hits_per_event=round(n_hits / B, 1), seeds_per_event=round(n_pls / B, 1)),
+                  batched_graph_events_per_s=round(graph_rate, 2),
+                  roofline=roofline, kernel_ms_per_step=stages,
+                  objects_per_event={k: round(counts[k] / B, 1) for k in ("md", "ls", "t3", "t5", "pt3", "pt5", "tc")})
+
+    if not args.quick:
+        # ---- plain path: one event per launch --------------------------------
+        lat = []
+        for i in range(min(B, 32)):
+            ctx.batch_upload([events[i]])
+            ctx.batch_execute(1, graph=True)
+            for _ in range(3):
+                t1 = time.perf_counter()
+                ctx.batch_execute(1, graph=True)
+                lat.append(time.perf_counter() - t1)
+        lat_us = np.array(lat) * 1e6
+        per_event_rate = 1e6 / lat_us.mean()
+        # end to end: host inputs in, host outputs back (lst_run_event)
+        e2e = []
+        for i in range(min(B, 32)):
+            t1 = time.perf_counter()
+            ctx.run_event(events[i])
+            e2e.append(time.perf_counter() - t1)
+        e2e_us = np.array(e2e[2:]) * 1e6
+        result["per_event"] = dict(events_per_s=round(per_event_rate, 2),
+                                   latency_us_p50=round(float(np.percentile(lat_us, 50)), 1),
+                                   latency_us_p99=round(float(np.percentile(lat_us, 99)), 1),
+                                   e2e_events_per_s=round(1e6 / e2e_us.mean(), 2),
+                                   e2e_latency_us_p50=round(float(np.percentile(e2e_us, 50)), 1),
+                                   e2e_latency_us_p99=round(float(np.percentile(e2e_us, 99)), 1))
+        result["batched_over_per_event"] = round(value / per_event_rate, 2)
+        log("per-event:", result["per_event"])
+        # ---- mixed-pileup batch: 64 events, PU ~ U[50, 250] --------------------
+        mixed = synth.batch_events(64, g)
+        ctx.batch_upload(mixed)
+        ctx.batch_execute(2, graph=True)
+        t1 = time.perf_counter()
+        ctx.batch_execute(args.steps, graph=True)
+        result["mixed_pu50_250_batch64_events_per_s"] = round(64 / ((time.perf_counter() - t1) / args.steps), 2)
+        log("mixed batch:", result["mixed_pu50_250_batch64_events_per_s"])
+        # ---- served path: Poisson arrivals -------------------------------------
+        result["served"] = served(ctx, g, synth)
+        log("served:", result["served"])
+    ctx.close()
+
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(args.cpu_events, args.cpu_budget)
+        log("cpu baseline:", result["cpu_baseline"])
+    print(json.dumps(result), flush=True)
+
+
+def served(ctx, g, synth, rate_hz=500.0, n=600):
+    """Events with PU ~ U[140, 200] arriving as a Poisson stream (seed 99) at
+    rate_hz; latency = completion - submission, from the library."""
+    rng = np.random.default_rng(99)
+    pool = []
+    for i in range(48):
+        pu = float(rng.uniform(140, 200))
+        pool.append(synth.gen_event(g, synth.config_pu(pu), synth.event_seed(4, i)))
+    gaps = rng.exponential(1.0 / rate_hz, n)
+    tickets = []
+    t_start = time.perf_counter()
+    t_next = t_start
+    for i in range(n):
+        t_next += gaps[i]
+        while time.perf_counter() < t_next:
+            pass
+        tickets.append(ctx.submit(pool[i % len(pool)]))
+    lat = []
+    for t in tickets:
+        o = ctx.poll(t, -1)
+        lat.append(o["latency_us"])
+    t_end = time.perf_counter()
+    lat = np.array(lat)
+    return dict(rate_hz=rate_hz, events=n, events_per_s=round(n / (t_end - t_start), 1),
+                latency_us_p50=round(float(np.percentile(lat, 50)), 1),
+                latency_us_p99=round(float(np.percentile(lat, 99)), 1))
+
+
+if __name__ == "__main__":
+    main()

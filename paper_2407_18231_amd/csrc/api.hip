@@ -28,7 +28,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Caps {
-    uint32_t ev = 0, hits = 0, pls = 0, md = 0, ls = 0, t3 = 0, t5 = 0, pt3 = 0, pt5 = 0;
+    uint32_t ev = 0, hits = 0, pls = 0, md = 0, ls = 0, t3 = 0, t5 = 0, pt3 = 0, pt5 = 0, ptc3 = 0, ptc5 = 0;
 };
 
 uint32_t clamp32(uint64_t v) { return v > 0xFFFFFFF0ull ? 0xFFFFFFF0u : (uint32_t)v; }
@@ -47,6 +47,8 @@ Caps plan_caps(uint32_t n_ev, uint64_t hits, uint64_t pls)
     c.t5 = clamp32(hits / 2 + 4096);
     c.pt3 = clamp32(8 * pls + 4096);
     c.pt5 = clamp32(4 * pls + 4096);
+    c.ptc3 = clamp32(64 * pls + 4096);
+    c.ptc5 = clamp32(16 * pls + 4096);
     return c;
 }
 
@@ -76,11 +78,13 @@ void carve_inputs(Carver &cv, Batch &b)
     b.ev_pls_off = cv.take<uint32_t>(b.cap_ev + 1);
 }
 
-void carve_work(Carver &cv, Batch &b, uint32_t n_mod, uint32_t n_surf, uint32_t nphi)
+void carve_work(Carver &cv, Batch &b, uint32_t n_mod, uint32_t n_surf, uint32_t nphi, uint32_t nkb)
 {
     const size_t bins = (size_t)b.cap_ev * 2 * n_mod;
     const size_t units = (size_t)b.cap_ev * n_mod;
-    const size_t bk = (size_t)b.cap_ev * n_surf * nphi;
+    const size_t rows = (size_t)b.cap_ev * n_surf * nphi;
+    const size_t bk = rows * (nkb + 1);
+    const size_t pt_units = (size_t)b.cap_pls * n_surf;
     const size_t tcu = (size_t)b.cap_pt3 + b.cap_t5 + b.cap_pls;
     b.bin_cnt = cv.take<uint32_t>(bins + 1);
     b.bin_off = cv.take<uint32_t>(bins + 1);
@@ -130,12 +134,20 @@ void carve_work(Carver &cv, Batch &b, uint32_t n_mod, uint32_t n_surf, uint32_t 
     b.bk5_id = cv.take<uint32_t>(b.cap_t5);
     b.bk5_rank = cv.take<uint32_t>(b.cap_t5);
     b.bk5_items = cv.take<uint32_t>(b.cap_t5);
-    b.pt3_cnt = cv.take<uint32_t>((size_t)b.cap_pls + 1);
-    b.pt3_off = cv.take<uint32_t>((size_t)b.cap_pls + 1);
+    b.ptc3_cnt = cv.take<uint32_t>(pt_units + 1);
+    b.ptc3_off = cv.take<uint32_t>(pt_units + 1);
+    b.ptc3_p = cv.take<uint32_t>(b.cap_ptc3);
+    b.ptc3_o = cv.take<uint32_t>(b.cap_ptc3);
+    b.pt3_keep = cv.take<uint32_t>((size_t)b.cap_ptc3 + 1);
+    b.pt3_koff = cv.take<uint32_t>((size_t)b.cap_ptc3 + 1);
+    b.ptc5_cnt = cv.take<uint32_t>(pt_units + 1);
+    b.ptc5_off = cv.take<uint32_t>(pt_units + 1);
+    b.ptc5_p = cv.take<uint32_t>(b.cap_ptc5);
+    b.ptc5_o = cv.take<uint32_t>(b.cap_ptc5);
+    b.pt5_keep = cv.take<uint32_t>((size_t)b.cap_ptc5 + 1);
+    b.pt5_koff = cv.take<uint32_t>((size_t)b.cap_ptc5 + 1);
     b.pt3_p = cv.take<uint32_t>(b.cap_pt3);
     b.pt3_o = cv.take<uint32_t>(b.cap_pt3);
-    b.pt5_cnt = cv.take<uint32_t>((size_t)b.cap_pls + 1);
-    b.pt5_off = cv.take<uint32_t>((size_t)b.cap_pls + 1);
     b.pt5_p = cv.take<uint32_t>(b.cap_pt5);
     b.pt5_o = cv.take<uint32_t>(b.cap_pt5);
     b.pls_used5 = cv.take<uint8_t>(b.cap_pls);
@@ -288,9 +300,11 @@ lst_status ensure_inputs(lst_ctx *ctx, Slot &s, uint32_t n_ev, uint64_t hits, ui
     // keep work capacities at least as large as before
     c.md = std::max(c.md, b.cap_md); c.ls = std::max(c.ls, b.cap_ls); c.t3 = std::max(c.t3, b.cap_t3);
     c.t5 = std::max(c.t5, b.cap_t5); c.pt3 = std::max(c.pt3, b.cap_pt3); c.pt5 = std::max(c.pt5, b.cap_pt5);
+    c.ptc3 = std::max(c.ptc3, b.cap_ptc3); c.ptc5 = std::max(c.ptc5, b.cap_ptc5);
     free_slot_arenas(s);
     b.cap_ev = c.ev; b.cap_hits = std::max<uint32_t>(c.hits, 1); b.cap_pls = std::max<uint32_t>(c.pls, 1);
     b.cap_md = c.md; b.cap_ls = c.ls; b.cap_t3 = c.t3; b.cap_t5 = c.t5; b.cap_pt3 = c.pt3; b.cap_pt5 = c.pt5;
+    b.cap_ptc3 = c.ptc3; b.cap_ptc5 = c.ptc5;
     b.cap_tc = b.cap_pt3 + b.cap_t5 + b.cap_pls;
     lst::Carver ci{nullptr};
     lst::carve_inputs(ci, b);
@@ -311,12 +325,12 @@ lst_status ensure_work(lst_ctx *ctx, Slot &s)
     b.cap_tc = b.cap_pt3 + b.cap_t5 + b.cap_pls;
     const lst::Consts &c = ctx->geom.c;
     lst::Carver cw{nullptr};
-    lst::carve_work(cw, b, c.n_mod, c.n_surf, c.nphi);
+    lst::carve_work(cw, b, c.n_mod, c.n_surf, c.nphi, c.nkb);
     s.work_bytes = cw.off;
     hipError_t e = hipMalloc(&s.work_arena, s.work_bytes);
     if (e != hipSuccess) { s.work_arena = nullptr; return set_err(ctx, LST_ERR_OOM, "work arena allocation failed"); }
     lst::Carver cw2{(char *)s.work_arena};
-    lst::carve_work(cw2, b, c.n_mod, c.n_surf, c.nphi);
+    lst::carve_work(cw2, b, c.n_mod, c.n_surf, c.nphi, c.nkb);
     s.graph_valid = false;
     return LST_OK;
 }
@@ -458,6 +472,8 @@ int overflowed(Slot &s)
     g |= grow(t.n_t5, b.cap_t5);
     g |= grow(t.n_pt3, b.cap_pt3);
     g |= grow(t.n_pt5, b.cap_pt5);
+    g |= grow(t.n_ptc3, b.cap_ptc3);
+    g |= grow(t.n_ptc5, b.cap_ptc5);
     return g ? 1 : 0;
 }
 
@@ -599,14 +615,17 @@ lst_status ensure_plain(lst_ctx *ctx)
 // ======================================================================
 namespace {
 
-uint64_t predict_footprint(uint64_t hits, uint64_t pls, uint32_t n_mod)
+uint64_t predict_footprint(uint64_t hits, uint64_t pls, const lst::Consts &k)
 {
-    // device bytes of one event in a slot: inputs + work lists at planned capacity
+    // device bytes of one event in a slot: inputs + work lists at planned
+    // capacity + the per-event bins of the sort and of the seed lookup
     lst::Caps c = lst::plan_caps(1, hits, pls);
     uint64_t b = 0;
-    b += 49ull * c.hits + 80ull * c.pls + 16ull * n_mod;
+    b += 49ull * c.hits + 80ull * c.pls + 24ull * k.n_mod;
     b += 40ull * c.md + 16ull * c.ls + 44ull * c.t3 + 28ull * c.t5;
-    b += 8ull * (c.pt3 + c.pt5) + 24ull * c.pls + 16ull * (c.pt3 + c.t5 + c.pls);
+    b += 8ull * (c.pt3 + c.pt5) + 16ull * c.pls * k.n_surf + 3ull * c.pls + 16ull * (c.pt3 + c.t5 + c.pls);
+    b += 16ull * (c.ptc3 + c.ptc5);
+    b += 2ull * 8ull * k.n_surf * k.nphi * (k.nkb + 1);
     return b;
 }
 
@@ -1034,7 +1053,7 @@ lst_status lst_submit(lst_ctx *ctx, const lst_event_in *ev, uint64_t *ticket)
     if (st != LST_OK) return st;
     if (ev->flags & LST_DEVICE_PTRS) return set_err(ctx, LST_ERR_INVALID_ARG, "served events take host pointers");
     const uint64_t budget = ctx->p.mem_budget ? ctx->p.mem_budget : (32ull << 30);
-    uint64_t f = predict_footprint(ev->n_hits, ev->n_pls, ctx->geom.n_mod);
+    uint64_t f = predict_footprint(ev->n_hits, ev->n_pls, ctx->geom.c);
     if (f > budget) return set_err(ctx, LST_ERR_TOO_LARGE, "event above the device memory budget");
     auto se = std::make_unique<ServedEvent>();
     se->x.assign(ev->x, ev->x + ev->n_hits);

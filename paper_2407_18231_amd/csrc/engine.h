@@ -36,11 +36,11 @@ struct DevGeom {
 // by the host before the chain runs; every other count by the chain itself.
 struct Totals {
     uint32_t n_ev, n_hits, n_pls;
-    uint32_t n_bins, n_md_units, n_bk, n_sorted;
+    uint32_t n_bins, n_md_units, n_bk, n_sorted, n_rows, n_pt_units;
     uint32_t n_md, n_ls, n_t3, n_t5, n_pt3, n_pt5;
     uint32_t n_bk3, n_bk5, n_tcu, n_tc;
+    uint32_t n_ptc3, n_ptc5;      // seed-object candidates after the curvature test
     uint32_t err;
-    uint32_t pad[2];
     unsigned long long cand[6];  // candidates examined: md, ls, t3, t5, pt3, pt5
 };
 
@@ -49,6 +49,7 @@ struct Totals {
 // nothing past it and the host re-runs the batch with larger arrays.
 struct Batch {
     uint32_t cap_ev, cap_hits, cap_pls, cap_md, cap_ls, cap_t3, cap_t5, cap_pt3, cap_pt5, cap_tc;
+    uint32_t cap_ptc3, cap_ptc5;
     // inputs (event-major concatenation)
     float *in_x, *in_y, *in_z;
     uint32_t *in_mod;
@@ -74,12 +75,17 @@ struct Batch {
     uint32_t *t5_cnt, *t5_off;          // per inner T3
     uint32_t *t5_u, *t5_w;
     float *t5_k, *t5_sk;
-    // a6: seed lookup buckets of T3s / T5s
+    // a6: seed lookup buckets of T3s / T5s by (event, surface, azimuth bin,
+    // curvature bin); the last curvature bin of a row holds the objects with
+    // a wide curvature resolution
     uint32_t *bk3_cnt, *bk3_off, *bk3_id, *bk3_rank, *bk3_items;
     uint32_t *bk5_cnt, *bk5_off, *bk5_id, *bk5_rank, *bk5_items;
-    // a7: pT3 / pT5 (seed, object)
-    uint32_t *pt3_cnt, *pt3_off, *pt3_p, *pt3_o;
-    uint32_t *pt5_cnt, *pt5_off, *pt5_p, *pt5_o;
+    // a7: seed-object candidates per (seed, surface) unit, their keep flags,
+    // and the pT3 / pT5 lists (seed, object)
+    uint32_t *ptc3_cnt, *ptc3_off, *ptc3_p, *ptc3_o, *pt3_keep, *pt3_koff;
+    uint32_t *ptc5_cnt, *ptc5_off, *ptc5_p, *ptc5_o, *pt5_keep, *pt5_koff;
+    uint32_t *pt3_p, *pt3_o;
+    uint32_t *pt5_p, *pt5_o;
     // a8: track candidates over [pT3 | T5 | pLS]
     uint8_t *pls_used5, *pls_used3, *t5_used;
     uint32_t *tc_cnt, *tc_off, *tc_type, *tc_idx;

@@ -157,12 +157,14 @@ __global__ void k_zero_u8(uint8_t *__restrict__ p, const uint32_t *n_ptr, uint32
 }
 
 // derive the per-batch unit counts; clear error flags and statistics
-__global__ void k_setup(Totals *t, uint32_t n_mod, uint32_t n_surf, uint32_t nphi)
+__global__ void k_setup(Totals *t, uint32_t n_mod, uint32_t n_surf, uint32_t nphi, uint32_t nkb)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         t->n_bins = t->n_ev * 2u * n_mod;
         t->n_md_units = t->n_ev * n_mod;
-        t->n_bk = t->n_ev * n_surf * nphi;
+        t->n_rows = t->n_ev * n_surf * nphi;
+        t->n_bk = t->n_rows * (nkb + 1u);
+        t->n_pt_units = t->n_pls * n_surf;
         t->err = 0;
         for (int i = 0; i < 6; i++) t->cand[i] = 0ull;
     }
@@ -544,8 +546,11 @@ __global__ __launch_bounds__(256) void k_t5(const Batch b, Totals *t, const Cons
 
 // --------------------------------------------- a6: seed lookup buckets ----
 // T3s (resp. T5s) are bucketed by (event, surface of the inner anchor,
-// azimuth bin of the inner anchor); a pixel seed then visits only the
-// buckets its helix band can reach.
+// azimuth bin of the inner anchor, curvature bin).  Buckets of one (event,
+// surface, azimuth bin) row are contiguous in curvature order, so a pixel
+// seed reads one contiguous item range per row it can reach: the rows its
+// helix band crosses, restricted to the curvature bins its curvature cut can
+// accept (bounded with the row's largest object resolution).
 
 constexpr float kPiF = 3.14159265358979f;
 constexpr double kPiD = 3.14159265358979323846;
@@ -558,6 +563,22 @@ __device__ inline uint32_t phi_bin(float x, float y, uint32_t nphi)
     return (uint32_t)bi;
 }
 
+__device__ inline uint32_t kappa_bin(float k, const Consts &c)
+{
+    float t = (k + c.kspan) * ((float)c.nkb / (2.0f * c.kspan));
+    if (!(t > 0.0f)) return 0u;
+    if (t >= (float)c.nkb) return c.nkb - 1u;
+    return (uint32_t)t;
+}
+
+__device__ inline int kappa_bin_d(double k, const Consts &c)
+{
+    double t = (k + (double)c.kspan) * ((double)c.nkb / (2.0 * (double)c.kspan));
+    if (!(t > 0.0)) return 0;
+    if (t >= (double)c.nkb) return (int)c.nkb - 1;
+    return (int)t;
+}
+
 // kind 0: T3 objects, 1: T5 objects
 template <int kKind>
 __global__ void k_bucket_hist(const Batch b, Totals *t, const DevGeom g, const Consts c)
@@ -568,9 +589,14 @@ __global__ void k_bucket_hist(const Batch b, Totals *t, const DevGeom g, const C
     uint32_t *rank = kKind == 0 ? b.bk3_rank : b.bk5_rank;
     GRID_STRIDE(i, n) {
         const uint32_t a = kKind == 0 ? b.t3_a[i] : b.t3_a[b.t5_u[i]];
+        const float k = kKind == 0 ? b.t3_k[i] : b.t5_k[i];
+        const float sk = kKind == 0 ? b.t3_sk[i] : b.t5_sk[i];
         const uint32_t u = b.md_u[a] & kUnitMask;
         const uint32_t e = u / c.n_mod, m = u - e * c.n_mod;
-        const uint32_t bk = (e * c.n_surf + g.mod_surf[m]) * c.nphi + phi_bin(b.md_x[a], b.md_y[a], c.nphi);
+        const uint32_t row = (e * c.n_surf + g.mod_surf[m]) * c.nphi + phi_bin(b.md_x[a], b.md_y[a], c.nphi);
+        // narrow objects by curvature bin; wide ones (or a NaN resolution) in the last bin
+        const uint32_t kb = (sk <= c.sk_wide) ? kappa_bin(k, c) : c.nkb;
+        const uint32_t bk = row * (c.nkb + 1u) + kb;
         id[i] = bk;
         rank[i] = atomicAdd(&cnt[bk], 1u);
     }
@@ -661,8 +687,8 @@ __device__ inline bool seed_road(const Consts &c, const Seed &s, const Surface &
         if (ak > 0.0 && ra * ak / 2.0 >= 1.0) return false;
         if (ak > 0.0) rb = fmin(rb, 2.0 / ak);
         double ua = ra * s.kp / 2.0, ub = rb * s.kp / 2.0;
-        double sa = (ua == 0.0) ? ra : ra * asin(ua) / ua;
-        double sb = (ub == 0.0) ? rb : rb * asin(ub) / ub;
+        double sa = (ua == 0.0) ? ra : ra * asin(fmax(-1.0, fmin(1.0, ua))) / ua;
+        double sb = (ub == 0.0) ? rb : rb * asin(fmax(-1.0, fmin(1.0, ub))) / ub;
         double za = s.z0 + s.cot * sa, zb = s.z0 + s.cot * sb;
         double wz = ns * (s.s44 + sb * s.s22 + c.sig_c) + 1e-3;
         if (fmax(za, zb) + wz < sf.z1 || fmin(za, zb) - wz > sf.z2) return false;
@@ -691,7 +717,7 @@ __device__ inline bool seed_road(const Consts &c, const Seed &s, const Surface &
     double pad = W + 1e-3;
     lo -= pad;
     hi += pad;
-    if (hi - lo >= 2.0 * kPiD) {
+    if (!(hi - lo < 2.0 * kPiD)) {
         b0 = 0;
         b1 = (int)c.nphi - 1;
         return true;
@@ -703,76 +729,144 @@ __device__ inline bool seed_road(const Consts &c, const Seed &s, const Surface &
     return true;
 }
 
+// Candidates: one thread per (seed, surface) walks the buckets of the
+// seed's road and keeps the objects that pass the (exact, binary64)
+// curvature test; the other seed cuts run in k_pt_eval, one thread per
+// candidate.
 template <int kKind, bool kFill>
-__global__ __launch_bounds__(256) void k_pt(const Batch b, Totals *t, const DevGeom g, const Consts c,
-                                            int stats)
+__global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const DevGeom g, const Consts c,
+                                             int stats)
 {
-    const uint32_t n = min(t->n_pls, b.cap_pls);
+    const uint32_t n = min(t->n_pls, b.cap_pls) * c.n_surf;
     const uint32_t n_ev = t->n_ev;
     const uint32_t *bk_off = kKind == 0 ? b.bk3_off : b.bk5_off;
     const uint32_t *bk_items = kKind == 0 ? b.bk3_items : b.bk5_items;
-    uint32_t *cnt = kKind == 0 ? b.pt3_cnt : b.pt5_cnt;
-    const uint32_t *off = kKind == 0 ? b.pt3_off : b.pt5_off;
+    const float *ok = kKind == 0 ? b.t3_k : b.t5_k;
+    const float *osk = kKind == 0 ? b.t3_sk : b.t5_sk;
+    uint32_t *cnt = kKind == 0 ? b.ptc3_cnt : b.ptc5_cnt;
+    const uint32_t *off = kKind == 0 ? b.ptc3_off : b.ptc5_off;
+    uint32_t *out_p = kKind == 0 ? b.ptc3_p : b.ptc5_p;
+    uint32_t *out_o = kKind == 0 ? b.ptc3_o : b.ptc5_o;
+    const uint32_t cap = kKind == 0 ? b.cap_ptc3 : b.cap_ptc5;
+    const uint32_t nkb1 = c.nkb + 1u;
+    uint64_t cand = 0;
+    GRID_STRIDE(unit, n) {
+        const uint32_t p = unit / c.n_surf, sfi = unit - p * c.n_surf;
+        uint32_t k = kFill ? off[unit] : 0u;
+        const Surface sf = g.surf[sfi];
+        int b0 = 0, b1 = -1;
+        if (sf.kind <= 1u) {
+            const Seed s = load_seed(b, c, p);
+            if (seed_road(c, s, sf, b0, b1)) {
+                const uint32_t e = find_event(b.ev_pls_off, n_ev, p);
+                const uint32_t row0 = (e * c.n_surf + sfi) * c.nphi;
+                // narrow objects: curvature within the seed's window widened by
+                // the largest narrow resolution
+                const double wide = c.n_sigma * (s.skp + (double)c.sk_wide) + 1e-6;
+                const int k0 = kappa_bin_d(s.kp - wide, c), k1 = kappa_bin_d(s.kp + wide, c);
+                for (int bi = b0; bi <= b1; bi++) {
+                    const uint32_t row = row0 + (uint32_t)(((bi % (int)c.nphi) + (int)c.nphi) % (int)c.nphi);
+                    for (int part = 0; part < 2; part++) {
+                        const uint32_t lo = part == 0 ? row * nkb1 + (uint32_t)k0 : row * nkb1 + c.nkb;
+                        const uint32_t hi = part == 0 ? row * nkb1 + (uint32_t)k1 + 1u : row * nkb1 + nkb1;
+                        const uint32_t i0 = bk_off[lo], i1 = bk_off[hi];
+                        for (uint32_t i = i0; i < i1; i++) {
+                            const uint32_t o = bk_items[i];
+                            if (!kFill) cand++;
+                            if (!(fabs(s.kp - (double)ok[o]) <= c.n_sigma * (s.skp + (double)osk[o]))) continue;
+                            if (kFill && k < cap) {
+                                out_p[k] = p;
+                                out_o[k] = o;
+                            }
+                            k++;
+                        }
+                    }
+                }
+            }
+        }
+        if (!kFill) cnt[unit] = k;
+    }
+    if (!kFill && stats) atomicAdd(&t->cand[4 + kKind], (unsigned long long)cand);
+}
+
+// full seed cuts, one thread per candidate
+template <int kKind>
+__global__ __launch_bounds__(256) void k_pt_eval(const Batch b, const Totals *t, const Consts c)
+{
+    const uint32_t n = kKind == 0 ? min(t->n_ptc3, b.cap_ptc3) : min(t->n_ptc5, b.cap_ptc5);
+    const uint32_t *cp = kKind == 0 ? b.ptc3_p : b.ptc5_p;
+    const uint32_t *co = kKind == 0 ? b.ptc3_o : b.ptc5_o;
+    uint32_t *keep = kKind == 0 ? b.pt3_keep : b.pt5_keep;
+    GRID_STRIDE(i, n) {
+        const uint32_t p = cp[i], o = co[i];
+        uint32_t ia, io;
+        float ko, sko;
+        if (kKind == 0) {
+            ia = b.t3_a[o];
+            io = b.t3_c[o];
+            ko = b.t3_k[o];
+            sko = b.t3_sk[o];
+        } else {
+            ia = b.t3_a[b.t5_u[o]];
+            io = b.t3_c[b.t5_w[o]];
+            ko = b.t5_k[o];
+            sko = b.t5_sk[o];
+        }
+        const Seed s = load_seed(b, c, p);
+        keep[i] = p_cut(c, s, ko, sko, load_anchor(b, ia), load_anchor(b, io)) ? 1u : 0u;
+    }
+}
+
+template <int kKind>
+__global__ void k_pt_compact(const Batch b, const Totals *t)
+{
+    const uint32_t n = kKind == 0 ? min(t->n_ptc3, b.cap_ptc3) : min(t->n_ptc5, b.cap_ptc5);
+    const uint32_t *cp = kKind == 0 ? b.ptc3_p : b.ptc5_p;
+    const uint32_t *co = kKind == 0 ? b.ptc3_o : b.ptc5_o;
+    const uint32_t *keep = kKind == 0 ? b.pt3_keep : b.pt5_keep;
+    const uint32_t *koff = kKind == 0 ? b.pt3_koff : b.pt5_koff;
     uint32_t *out_p = kKind == 0 ? b.pt3_p : b.pt5_p;
     uint32_t *out_o = kKind == 0 ? b.pt3_o : b.pt5_o;
     const uint32_t cap = kKind == 0 ? b.cap_pt3 : b.cap_pt5;
-    uint64_t cand = 0;
-    GRID_STRIDE(p, n) {
-        const uint32_t e = find_event(b.ev_pls_off, n_ev, p);
-        const Seed s = load_seed(b, c, p);
-        const uint32_t k0 = kFill ? off[p] : 0u;
-        uint32_t k = k0;
-        for (uint32_t sfi = 0; sfi < c.n_surf; sfi++) {
-            const Surface sf = g.surf[sfi];
-            if (sf.kind > 1u) continue;
-            int b0, b1;
-            if (!seed_road(c, s, sf, b0, b1)) continue;
-            const uint32_t row = (e * c.n_surf + sfi) * c.nphi;
-            for (int bi = b0; bi <= b1; bi++) {
-                const uint32_t bin = (uint32_t)(((bi % (int)c.nphi) + (int)c.nphi) % (int)c.nphi);
-                const uint32_t i0 = bk_off[row + bin], i1 = bk_off[row + bin + 1];
-                for (uint32_t i = i0; i < i1; i++) {
-                    const uint32_t o = bk_items[i];
-                    uint32_t ia, io;
-                    float ko, sko;
-                    if (kKind == 0) {
-                        ia = b.t3_a[o];
-                        io = b.t3_c[o];
-                        ko = b.t3_k[o];
-                        sko = b.t3_sk[o];
-                    } else {
-                        ia = b.t3_a[b.t5_u[o]];
-                        io = b.t3_c[b.t5_w[o]];
-                        ko = b.t5_k[o];
-                        sko = b.t5_sk[o];
-                    }
-                    if (!kFill) cand++;
-                    if (!p_cut(c, s, ko, sko, load_anchor(b, ia), load_anchor(b, io))) continue;
-                    if (kFill && k < cap) {
-                        out_p[k] = p;
-                        out_o[k] = o;
-                    }
-                    k++;
-                }
-            }
-        }
-        if (!kFill) {
-            cnt[p] = k;
-        } else {
-            // canonical order within the seed: by object index
-            const uint32_t k1 = min(k, cap);
-            for (uint32_t i = k0 + 1; i < k1; i++) {
-                uint32_t v = out_o[i];
-                uint32_t j = i;
-                while (j > k0 && out_o[j - 1] > v) {
-                    out_o[j] = out_o[j - 1];
-                    j--;
-                }
-                out_o[j] = v;
-            }
+    GRID_STRIDE(i, n) {
+        if (!keep[i]) continue;
+        const uint32_t k = koff[i];
+        if (k < cap) {
+            out_p[k] = cp[i];
+            out_o[k] = co[i];
         }
     }
-    if (!kFill && stats) atomicAdd(&t->cand[4 + kKind], (unsigned long long)cand);
+}
+
+// first pT index of seed p (seeds p <= n_pls)
+template <int kKind>
+__device__ inline uint32_t pt_first(const Batch &b, const Consts &c, uint32_t p)
+{
+    const uint32_t *off = kKind == 0 ? b.ptc3_off : b.ptc5_off;
+    const uint32_t *koff = kKind == 0 ? b.pt3_koff : b.pt5_koff;
+    const uint32_t capc = kKind == 0 ? b.cap_ptc3 : b.cap_ptc5;
+    const uint32_t cap = kKind == 0 ? b.cap_pt3 : b.cap_pt5;
+    return min(koff[min(off[p * c.n_surf], capc)], cap);
+}
+
+// canonical order within each seed: by object index
+template <int kKind>
+__global__ void k_pt_sort(const Batch b, const Totals *t, const Consts c)
+{
+    const uint32_t n = min(t->n_pls, b.cap_pls);
+    uint32_t *out_o = kKind == 0 ? b.pt3_o : b.pt5_o;
+    GRID_STRIDE(p, n) {
+        const uint32_t k0 = pt_first<kKind>(b, c, p), k1 = pt_first<kKind>(b, c, p + 1);
+        for (uint32_t i = k0 + 1; i < k1; i++) {
+            uint32_t v = out_o[i];
+            uint32_t j = i;
+            while (j > k0 && out_o[j - 1] > v) {
+                out_o[j] = out_o[j - 1];
+                j--;
+            }
+            out_o[j] = v;
+        }
+    }
 }
 
 // ------------------------------------------------ a8: track candidates ----
@@ -824,8 +918,9 @@ __global__ void k_tc_write(const Batch b, const Totals *t)
 }
 
 // per-event first index of every list (row n_ev holds the totals)
-__global__ void k_event_table(const Batch b, const Totals *t, uint32_t n_mod)
+__global__ void k_event_table(const Batch b, const Totals *t, const Consts c)
 {
+    const uint32_t n_mod = c.n_mod;
     const uint32_t n_ev = t->n_ev;
     const uint32_t n3 = min(t->n_pt3, b.cap_pt3), n5 = min(t->n_t5, b.cap_t5);
     GRID_STRIDE(e, n_ev + 1) {
@@ -835,8 +930,8 @@ __global__ void k_event_table(const Batch b, const Totals *t, uint32_t n_mod)
         uint32_t ls = min(b.ls_off[md], b.cap_ls);
         uint32_t t3 = min(b.t3_off[ls], b.cap_t3);
         uint32_t t5 = min(b.t5_off[t3], b.cap_t5);
-        uint32_t p3 = min(b.pt3_off[pls], b.cap_pt3);
-        uint32_t p5 = min(b.pt5_off[pls], b.cap_pt5);
+        uint32_t p3 = pt_first<0>(b, c, pls);
+        uint32_t p5 = pt_first<1>(b, c, pls);
         row[0] = hit;
         row[1] = pls;
         row[2] = md;
@@ -902,7 +997,8 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     L.scan(b.t5_cnt, b.t5_off, &t->n_t3, b.cap_t3, &t->n_t5, "scan_t5");
     L.launch("t5_fill", k_t5<true>, grid_for(b.cap_t3), blk, b, t, c, 0);
     // a6: seed lookup buckets
-    const uint32_t cap_bk = b.cap_ev * c.n_surf * c.nphi;
+    const uint32_t cap_rows = b.cap_ev * c.n_surf * c.nphi;
+    const uint32_t cap_bk = cap_rows * (c.nkb + 1);
     L.launch("zero", k_zero_u32, grid_for((uint64_t)cap_bk + 1), blk, b.bk3_cnt, &t->n_bk, cap_bk, 1u);
     L.launch("zero", k_zero_u32, grid_for((uint64_t)cap_bk + 1), blk, b.bk5_cnt, &t->n_bk, cap_bk, 1u);
     L.launch("bucket_hist", k_bucket_hist<0>, grid_for(b.cap_t3), blk, b, t, g, c);
@@ -911,13 +1007,22 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     L.scan(b.bk5_cnt, b.bk5_off, &t->n_bk, cap_bk, &t->n_bk5, "scan_bucket");
     L.launch("bucket_scatter", k_bucket_scatter<0>, grid_for(b.cap_t3), blk, b, (const Totals *)t);
     L.launch("bucket_scatter", k_bucket_scatter<1>, grid_for(b.cap_t5), blk, b, (const Totals *)t);
-    // a7: pT3 / pT5
-    L.launch("pt3_count", k_pt<0, false>, grid_for(b.cap_pls), blk, b, t, g, c, stats);
-    L.scan(b.pt3_cnt, b.pt3_off, &t->n_pls, b.cap_pls, &t->n_pt3, "scan_pt");
-    L.launch("pt3_fill", k_pt<0, true>, grid_for(b.cap_pls), blk, b, t, g, c, 0);
-    L.launch("pt5_count", k_pt<1, false>, grid_for(b.cap_pls), blk, b, t, g, c, stats);
-    L.scan(b.pt5_cnt, b.pt5_off, &t->n_pls, b.cap_pls, &t->n_pt5, "scan_pt");
-    L.launch("pt5_fill", k_pt<1, true>, grid_for(b.cap_pls), blk, b, t, g, c, 0);
+    // a7: pT3 / pT5: candidates, seed cuts, compaction, per-seed order
+    const uint64_t cap_pu = (uint64_t)b.cap_pls * c.n_surf;
+    L.launch("ptc_count", k_ptc<0, false>, grid_for(cap_pu), blk, b, t, g, c, stats);
+    L.launch("ptc_count", k_ptc<1, false>, grid_for(cap_pu), blk, b, t, g, c, stats);
+    L.scan(b.ptc3_cnt, b.ptc3_off, &t->n_pt_units, (uint32_t)cap_pu, &t->n_ptc3, "scan_pt");
+    L.scan(b.ptc5_cnt, b.ptc5_off, &t->n_pt_units, (uint32_t)cap_pu, &t->n_ptc5, "scan_pt");
+    L.launch("ptc_fill", k_ptc<0, true>, grid_for(cap_pu), blk, b, t, g, c, 0);
+    L.launch("ptc_fill", k_ptc<1, true>, grid_for(cap_pu), blk, b, t, g, c, 0);
+    L.launch("pt_eval", k_pt_eval<0>, grid_for(b.cap_ptc3), blk, b, (const Totals *)t, c);
+    L.launch("pt_eval", k_pt_eval<1>, grid_for(b.cap_ptc5), blk, b, (const Totals *)t, c);
+    L.scan(b.pt3_keep, b.pt3_koff, &t->n_ptc3, b.cap_ptc3, &t->n_pt3, "scan_pt");
+    L.scan(b.pt5_keep, b.pt5_koff, &t->n_ptc5, b.cap_ptc5, &t->n_pt5, "scan_pt");
+    L.launch("pt_compact", k_pt_compact<0>, grid_for(b.cap_ptc3), blk, b, (const Totals *)t);
+    L.launch("pt_compact", k_pt_compact<1>, grid_for(b.cap_ptc5), blk, b, (const Totals *)t);
+    L.launch("pt_sort", k_pt_sort<0>, grid_for(b.cap_pls), blk, b, (const Totals *)t, c);
+    L.launch("pt_sort", k_pt_sort<1>, grid_for(b.cap_pls), blk, b, (const Totals *)t, c);
     // a8: track candidates
     L.launch("zero8", k_zero_u8, grid_for(b.cap_pls), blk, b.pls_used5, &t->n_pls, b.cap_pls);
     L.launch("zero8", k_zero_u8, grid_for(b.cap_pls), blk, b.pls_used3, &t->n_pls, b.cap_pls);
@@ -927,12 +1032,12 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     L.scan(b.tc_cnt, b.tc_off, &t->n_tcu, b.cap_pt3 + b.cap_t5 + b.cap_pls, &t->n_tc, "scan_tc");
     L.launch("tc_write", k_tc_write, grid_for((uint64_t)b.cap_pt3 + b.cap_t5 + b.cap_pls), blk, b,
              (const Totals *)t);
-    L.launch("event_table", k_event_table, grid_for(b.cap_ev + 1), blk, b, (const Totals *)t, n_mod);
+    L.launch("event_table", k_event_table, grid_for(b.cap_ev + 1), blk, b, (const Totals *)t, c);
 }
 
 void launch_setup(Launcher &L, Totals *t, const Consts &c)
 {
-    L.launch("setup", k_setup, dim3(1), dim3(64), t, c.n_mod, c.n_surf, c.nphi);
+    L.launch("setup", k_setup, dim3(1), dim3(64), t, c.n_mod, c.n_surf, c.nphi, c.nkb);
 }
 
 }  // namespace lst
