@@ -90,18 +90,14 @@ void carve_work(Carver &cv, Batch &b, uint32_t n_mod, uint32_t n_surf, uint32_t 
     b.bin_off = cv.take<uint32_t>(bins + 1);
     b.hbin = cv.take<uint32_t>(b.cap_hits);
     b.hrank = cv.take<uint32_t>(b.cap_hits);
-    b.perm = cv.take<uint32_t>(b.cap_hits);
-    b.hx = cv.take<float>(b.cap_hits);
-    b.hy = cv.take<float>(b.cap_hits);
-    b.hz = cv.take<float>(b.cap_hits);
-    b.hr = cv.take<float>(b.cap_hits);
+    b.hrec = cv.take<float4>(b.cap_hits);
+    b.hpos = cv.take<float4>(b.cap_hits);
     b.hin = cv.take<uint32_t>(b.cap_hits);
-    b.md_cnt = cv.take<uint32_t>(units + 1);
+    b.hbin_s = cv.take<uint32_t>(b.cap_hits);
+    b.md_cnt = cv.take<uint32_t>((size_t)b.cap_hits + 1);
+    b.md_hoff = cv.take<uint32_t>((size_t)b.cap_hits + 1);
     b.md_off = cv.take<uint32_t>(units + 1);
-    b.md_x = cv.take<float>(b.cap_md);
-    b.md_y = cv.take<float>(b.cap_md);
-    b.md_z = cv.take<float>(b.cap_md);
-    b.md_r = cv.take<float>(b.cap_md);
+    b.md_pos = cv.take<float4>(b.cap_md);
     b.md_beta = cv.take<float>(b.cap_md);
     b.md_u = cv.take<uint32_t>(b.cap_md);
     b.md_hlo = cv.take<uint32_t>(b.cap_md);
@@ -114,26 +110,26 @@ void carve_work(Carver &cv, Batch &b, uint32_t n_mod, uint32_t n_surf, uint32_t 
     b.t3_off = cv.take<uint32_t>((size_t)b.cap_ls + 1);
     b.t3_l1 = cv.take<uint32_t>(b.cap_t3);
     b.t3_l2 = cv.take<uint32_t>(b.cap_t3);
-    b.t3_a = cv.take<uint32_t>(b.cap_t3);
-    b.t3_c = cv.take<uint32_t>(b.cap_t3);
-    b.t3_k = cv.take<float>(b.cap_t3);
-    b.t3_sk = cv.take<float>(b.cap_t3);
+    b.t3_ac = cv.take<uint2>(b.cap_t3);
+    b.t3_ks = cv.take<float2>(b.cap_t3);
     b.t5_cnt = cv.take<uint32_t>((size_t)b.cap_t3 + 1);
     b.t5_off = cv.take<uint32_t>((size_t)b.cap_t3 + 1);
     b.t5_u = cv.take<uint32_t>(b.cap_t5);
     b.t5_w = cv.take<uint32_t>(b.cap_t5);
-    b.t5_k = cv.take<float>(b.cap_t5);
-    b.t5_sk = cv.take<float>(b.cap_t5);
+    b.t5_ks = cv.take<float2>(b.cap_t5);
     b.bk3_cnt = cv.take<uint32_t>(bk + 1);
     b.bk3_off = cv.take<uint32_t>(bk + 1);
     b.bk3_id = cv.take<uint32_t>(b.cap_t3);
     b.bk3_rank = cv.take<uint32_t>(b.cap_t3);
     b.bk3_items = cv.take<uint32_t>(b.cap_t3);
+    b.bk3_ks = cv.take<float2>(b.cap_t3);
     b.bk5_cnt = cv.take<uint32_t>(bk + 1);
     b.bk5_off = cv.take<uint32_t>(bk + 1);
     b.bk5_id = cv.take<uint32_t>(b.cap_t5);
     b.bk5_rank = cv.take<uint32_t>(b.cap_t5);
     b.bk5_items = cv.take<uint32_t>(b.cap_t5);
+    b.bk5_ks = cv.take<float2>(b.cap_t5);
+    b.road = cv.take<uint2>(pt_units);
     b.ptc3_cnt = cv.take<uint32_t>(pt_units + 1);
     b.ptc3_off = cv.take<uint32_t>(pt_units + 1);
     b.ptc3_p = cv.take<uint32_t>(b.cap_ptc3);
@@ -530,7 +526,7 @@ lst_status download(lst_ctx *ctx, Slot &s, lst_event_out **outs)
     const uint32_t nmd = t.n_md, nls = t.n_ls, nt3 = t.n_t3, nt5 = t.n_t5, np3 = t.n_pt3, np5 = t.n_pt5, ntc = t.n_tc;
     std::vector<uint32_t> hlo(nmd), hup(nmd), la(nls), lb(nls), u1(nt3), u2(nt3), w1(nt5), w2(nt5);
     std::vector<uint32_t> p3(np3), o3(np3), p5(np5), o5(np5), tty(ntc), tix(ntc);
-    std::vector<float> k3(nt3);
+    std::vector<float2> k3(nt3);
     auto get = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
         if (!bytes) return hipSuccess;
         return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s.stream);
@@ -541,7 +537,7 @@ lst_status download(lst_ctx *ctx, Slot &s, lst_event_out **outs)
     HIP_TRY(get(lb.data(), b.ls_b, nls * 4ull));
     HIP_TRY(get(u1.data(), b.t3_l1, nt3 * 4ull));
     HIP_TRY(get(u2.data(), b.t3_l2, nt3 * 4ull));
-    HIP_TRY(get(k3.data(), b.t3_k, nt3 * 4ull));
+    HIP_TRY(get(k3.data(), b.t3_ks, nt3 * 8ull));
     HIP_TRY(get(w1.data(), b.t5_u, nt5 * 4ull));
     HIP_TRY(get(w2.data(), b.t5_w, nt5 * 4ull));
     HIP_TRY(get(p3.data(), b.pt3_p, np3 * 4ull));
@@ -578,7 +574,7 @@ lst_status download(lst_ctx *ctx, Slot &s, lst_event_out **outs)
         for (uint32_t i = 0; i < cls; i++) { o->ls[2 * i] = la[ls0 + i] - md0; o->ls[2 * i + 1] = lb[ls0 + i] - md0; }
         for (uint32_t i = 0; i < ct3; i++) {
             o->t3[2 * i] = u1[t30 + i] - ls0; o->t3[2 * i + 1] = u2[t30 + i] - ls0;
-            o->t3_kappa[i] = k3[t30 + i];
+            o->t3_kappa[i] = k3[t30 + i].x;
         }
         for (uint32_t i = 0; i < ct5; i++) { o->t5[2 * i] = w1[t50 + i] - t30; o->t5[2 * i + 1] = w2[t50 + i] - t30; }
         for (uint32_t i = 0; i < cp3; i++) { o->pt3[2 * i] = p3[p30 + i] - pls0; o->pt3[2 * i + 1] = o3[p30 + i] - t30; }
@@ -621,9 +617,9 @@ uint64_t predict_footprint(uint64_t hits, uint64_t pls, const lst::Consts &k)
     // capacity + the per-event bins of the sort and of the seed lookup
     lst::Caps c = lst::plan_caps(1, hits, pls);
     uint64_t b = 0;
-    b += 49ull * c.hits + 80ull * c.pls + 24ull * k.n_mod;
-    b += 40ull * c.md + 16ull * c.ls + 44ull * c.t3 + 28ull * c.t5;
-    b += 8ull * (c.pt3 + c.pt5) + 16ull * c.pls * k.n_surf + 3ull * c.pls + 16ull * (c.pt3 + c.t5 + c.pls);
+    b += 73ull * c.hits + 80ull * c.pls + 24ull * k.n_mod;
+    b += 40ull * c.md + 16ull * c.ls + 52ull * c.t3 + 36ull * c.t5;
+    b += 8ull * (c.pt3 + c.pt5) + 24ull * c.pls * k.n_surf + 3ull * c.pls + 16ull * (c.pt3 + c.t5 + c.pls);
     b += 16ull * (c.ptc3 + c.ptc5);
     b += 2ull * 8ull * k.n_surf * k.nphi * (k.nkb + 1);
     return b;

@@ -57,30 +57,39 @@ struct Batch {
     float *in_par, *in_cov;
     uint32_t *ev_hit_off, *ev_pls_off;  // cap_ev + 1
     // a1: hits sorted by (event, module, sensor)
-    uint32_t *bin_cnt, *bin_off, *hbin, *hrank, *perm;
-    float *hx, *hy, *hz, *hr;
+    uint32_t *bin_cnt, *bin_off, *hbin, *hrank;
+    float4 *hrec;                       // (x, y, z, input index bits) scattered by bin
+    float4 *hpos;                       // (x, y, z, r) of each sorted hit
     uint32_t *hin;                      // event-local input index of each sorted hit
+    uint32_t *hbin_s;                   // bin of each sorted hit
     // a2: mini-doublets (anchor = hit on the lower sensor)
-    uint32_t *md_cnt, *md_off;          // per (event, module) unit
-    float *md_x, *md_y, *md_z, *md_r, *md_beta;
+    uint32_t *md_cnt, *md_hoff;         // per sorted hit (MDs of a lower-sensor hit)
+    uint32_t *md_off;                   // per (event, module) unit
+    float4 *md_pos;                     // anchor (x, y, z, r)
+    float *md_beta;
     uint32_t *md_u, *md_hlo, *md_hup;
     // a3: line segments
     uint32_t *ls_cnt, *ls_off;          // per inner MD
     uint32_t *ls_a, *ls_b;
     // a4: T3
     uint32_t *t3_cnt, *t3_off;          // per inner LS
-    uint32_t *t3_l1, *t3_l2, *t3_a, *t3_c;
-    float *t3_k, *t3_sk;
+    uint32_t *t3_l1, *t3_l2;
+    uint2 *t3_ac;                       // inner and outer MD
+    float2 *t3_ks;                      // curvature and its resolution
     // a5: T5
     uint32_t *t5_cnt, *t5_off;          // per inner T3
     uint32_t *t5_u, *t5_w;
-    float *t5_k, *t5_sk;
+    float2 *t5_ks;                      // curvature through (A, C, E) and its resolution
     // a6: seed lookup buckets of T3s / T5s by (event, surface, azimuth bin,
     // curvature bin); the last curvature bin of a row holds the objects with
     // a wide curvature resolution
     uint32_t *bk3_cnt, *bk3_off, *bk3_id, *bk3_rank, *bk3_items;
     uint32_t *bk5_cnt, *bk5_off, *bk5_id, *bk5_rank, *bk5_items;
-    // a7: seed-object candidates per (seed, surface) unit, their keep flags,
+    float2 *bk3_ks, *bk5_ks;            // curvature and resolution of each bucketed object
+    // a7: road of each (seed, surface) unit: first azimuth bin | bin count << 16,
+    // curvature bins k0 | k1 << 8 | valid << 31
+    uint2 *road;
+    // seed-object candidates per (seed, surface) unit, their keep flags,
     // and the pT3 / pT5 lists (seed, object)
     uint32_t *ptc3_cnt, *ptc3_off, *ptc3_p, *ptc3_o, *pt3_keep, *pt3_koff;
     uint32_t *ptc5_cnt, *ptc5_off, *ptc5_p, *ptc5_o, *pt5_keep, *pt5_koff;

@@ -205,42 +205,41 @@ __global__ void k_pls_check(const Batch b, Totals *t)
     }
 }
 
+// each hit's record to its bin (coalesced reads, one 16-byte write per hit)
 __global__ void k_hit_scatter(const Batch b, const Totals *t)
 {
     const uint32_t n = min(t->n_hits, b.cap_hits);
     GRID_STRIDE(h, n) {
         uint32_t bin = b.hbin[h];
         if (bin == kInvalid) continue;
-        b.perm[b.bin_off[bin] + b.hrank[h]] = h;
+        b.hrec[b.bin_off[bin] + b.hrank[h]] = make_float4(b.in_x[h], b.in_y[h], b.in_z[h], __uint_as_float(h));
     }
 }
 
-// per (event, module, sensor) bin: restore input order (the scatter above
-// used atomic slots) and write the sorted SoA with r = sqrt(x^2 + y^2)
+// per (event, module, sensor) bin: restore input order (the scatter used
+// atomic slots) and write the sorted SoA with r = sqrt(x^2 + y^2)
 __global__ void k_hit_gather(const Batch b, const Totals *t, uint32_t n_mod)
 {
     const uint32_t nb = t->n_bins;
     GRID_STRIDE(bin, nb) {
         const uint32_t beg = b.bin_off[bin], end = b.bin_off[bin + 1];
         for (uint32_t i = beg + 1; i < end; i++) {
-            uint32_t v = b.perm[i];
+            const float4 v = b.hrec[i];
+            const uint32_t key = __float_as_uint(v.w);
             uint32_t j = i;
-            while (j > beg && b.perm[j - 1] > v) {
-                b.perm[j] = b.perm[j - 1];
+            while (j > beg && __float_as_uint(b.hrec[j - 1].w) > key) {
+                b.hrec[j] = b.hrec[j - 1];
                 j--;
             }
-            b.perm[j] = v;
+            b.hrec[j] = v;
         }
         const uint32_t e = bin / (2u * n_mod);
         const uint32_t h0 = b.ev_hit_off[e];
         for (uint32_t i = beg; i < end; i++) {
-            uint32_t h = b.perm[i];
-            float x = b.in_x[h], y = b.in_y[h];
-            b.hx[i] = x;
-            b.hy[i] = y;
-            b.hz[i] = b.in_z[h];
-            b.hr[i] = sqrtf(x * x + y * y);
-            b.hin[i] = h - h0;
+            const float4 v = b.hrec[i];
+            b.hpos[i] = make_float4(v.x, v.y, v.z, sqrtf(v.x * v.x + v.y * v.y));
+            b.hin[i] = __float_as_uint(v.w) - h0;
+            b.hbin_s[i] = bin;
         }
     }
 }
@@ -270,50 +269,56 @@ __device__ inline bool md_cut(const float4 mc, bool barrel, float L,
     return true;
 }
 
+// one thread per sorted hit: a hit on a lower sensor pairs with every hit on
+// the upper sensor of its module (hits of upper sensors count zero)
 template <bool kFill>
 __global__ __launch_bounds__(256) void k_md(const Batch b, Totals *t, const DevGeom g, const Consts c,
                                             int stats)
 {
-    const uint32_t nu = t->n_md_units;
+    const uint32_t n = t->n_sorted;
     const uint32_t n_mod = c.n_mod;
     uint64_t cand = 0;
-    GRID_STRIDE(u, nu) {
-        const uint32_t e = u / n_mod, m = u - e * n_mod;
-        const uint32_t b0 = e * 2u * n_mod + 2u * m;
-        const uint32_t lo0 = b.bin_off[b0], lo1 = b.bin_off[b0 + 1], up1 = b.bin_off[b0 + 2];
-        if (lo0 == lo1 || lo1 == up1) {
-            if (!kFill) b.md_cnt[u] = 0;
-            continue;
-        }
-        const float4 mc = g.mdc[m];
-        const bool barrel = g.mod_kind[m] == LST_BARREL;
-        uint32_t k = kFill ? b.md_off[u] : 0u;
-        const uint32_t disk_bit = barrel ? 0u : kDiskBit;
-        for (uint32_t i = lo0; i < lo1; i++) {
-            const float xi = b.hx[i], yi = b.hy[i], zi = b.hz[i], ri = b.hr[i];
-            for (uint32_t j = lo1; j < up1; j++) {
-                float beta;
-                if (!kFill) cand++;
-                if (!md_cut(mc, barrel, c.L, xi, yi, zi, ri, b.hx[j], b.hy[j], b.hz[j], b.hr[j], beta))
-                    continue;
-                if (kFill) {
-                    if (k < b.cap_md) {
-                        b.md_x[k] = xi;
-                        b.md_y[k] = yi;
-                        b.md_z[k] = zi;
-                        b.md_r[k] = ri;
+    GRID_STRIDE(i, n) {
+        const uint32_t bin = b.hbin_s[i];
+        uint32_t k = kFill ? b.md_hoff[i] : 0u;
+        if (!(bin & 1u)) {
+            const uint32_t up0 = b.bin_off[bin + 1], up1 = b.bin_off[bin + 2];
+            if (up0 != up1) {
+                const uint32_t u = bin >> 1;
+                const uint32_t m = u % n_mod;
+                const float4 mc = g.mdc[m];
+                const bool barrel = g.mod_kind[m] == LST_BARREL;
+                const uint32_t disk_bit = barrel ? 0u : kDiskBit;
+                const float4 hi = b.hpos[i];
+                for (uint32_t j = up0; j < up1; j++) {
+                    float beta;
+                    if (!kFill) cand++;
+                    const float4 hj = b.hpos[j];
+                    if (!md_cut(mc, barrel, c.L, hi.x, hi.y, hi.z, hi.w, hj.x, hj.y, hj.z, hj.w, beta))
+                        continue;
+                    if (kFill && k < b.cap_md) {
+                        // the sign of r marks an anchor on a disk (r > 0)
+                        b.md_pos[k] = make_float4(hi.x, hi.y, hi.z, barrel ? hi.w : -hi.w);
                         b.md_beta[k] = beta;
                         b.md_u[k] = u | disk_bit;
                         b.md_hlo[k] = b.hin[i];
                         b.md_hup[k] = b.hin[j];
                     }
+                    k++;
                 }
-                k++;
             }
         }
-        if (!kFill) b.md_cnt[u] = k;
+        if (!kFill) b.md_cnt[i] = k;
     }
     if (!kFill && stats) atomicAdd(&t->cand[0], (unsigned long long)cand);
+}
+
+// MD range of every (event, module) unit: the MDs of its lower-sensor hits
+__global__ void k_md_units(const Batch b, const Totals *t)
+{
+    const uint32_t nu = t->n_md_units;
+    // bin_off has 2 nu + 1 entries and its values index md_hoff (n_sorted + 1)
+    GRID_STRIDE(u, nu + 1) b.md_off[u] = b.md_hoff[b.bin_off[2u * u]];
 }
 
 // ------------------------------------------------------ a3: line segments ---
@@ -375,6 +380,24 @@ __device__ inline bool ls_cut(const LsClass &k, const Consts &c, bool bend,
     return lo <= rb;
 }
 
+// Wave-cooperative: a wave takes two consecutive MDs; for each, 32 lanes take
+// one edge of the MD's module each (chunks of 32 for larger degrees) and test
+// the MDs of the edge's destination module.  Half-wave prefix sums give each
+// lane its place, so segments come out ordered by (inner MD, edge, outer MD),
+// which is (inner MD, outer MD) because edges are sorted by destination.
+constexpr uint32_t kLsLanes = 32;
+
+__device__ inline uint32_t half_incl_scan(uint32_t v)
+{
+    const uint32_t w = threadIdx.x & (kLsLanes - 1);
+#pragma unroll
+    for (uint32_t d = 1; d < kLsLanes; d <<= 1) {
+        uint32_t t = __shfl_up(v, d, kLsLanes);
+        if (w >= d) v += t;
+    }
+    return v;
+}
+
 template <bool kFill>
 __global__ __launch_bounds__(256) void k_ls(const Batch b, Totals *t, const DevGeom g, const Consts c,
                                             int stats)
@@ -382,32 +405,63 @@ __global__ __launch_bounds__(256) void k_ls(const Batch b, Totals *t, const DevG
     const uint32_t n = min(t->n_md, b.cap_md);
     const uint32_t n_mod = c.n_mod;
     const bool bend = (c.flags & LST_FLAG_BEND) != 0u;
+    const uint32_t half = (threadIdx.x >> 5) & 1u, w = threadIdx.x & (kLsLanes - 1);
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
     uint64_t cand = 0;
-    GRID_STRIDE(a, n) {
+    for (uint32_t a0 = 2 * wave; a0 < n; a0 += 2 * n_waves) {
+        const uint32_t a = a0 + half;
+        if (a >= n) continue;
         const uint32_t u = b.md_u[a] & kUnitMask;
         const uint32_t m = u % n_mod;
         const uint32_t base = u - m;
-        const float xa = b.md_x[a], ya = b.md_y[a], za = b.md_z[a], ra = b.md_r[a], ba = b.md_beta[a];
-        uint32_t k = kFill ? b.ls_off[a] : 0u;
-        const uint32_t e1 = g.edge_begin[m + 1];
-        for (uint32_t e = g.edge_begin[m]; e < e1; e++) {
-            const uint2 ed = g.edge[e];
-            const uint32_t bb = min(b.md_off[base + ed.x], b.cap_md);
-            const uint32_t be = min(b.md_off[base + ed.x + 1], b.cap_md);
-            if (bb == be) continue;
-            const LsClass kc = g.cls[ed.y];
-            for (uint32_t q = bb; q < be; q++) {
-                if (!kFill) cand++;
-                if (!ls_cut(kc, c, bend, xa, ya, za, ra, ba, b.md_x[q], b.md_y[q], b.md_z[q], b.md_r[q]))
-                    continue;
-                if (kFill && k < b.cap_ls) {
-                    b.ls_a[k] = a;
-                    b.ls_b[k] = q;
-                }
-                k++;
+        const float4 pa = b.md_pos[a];
+        const float xa = pa.x, ya = pa.y, za = pa.z, ra = fabsf(pa.w), ba = b.md_beta[a];
+        const uint32_t e0 = g.edge_begin[m], e1 = g.edge_begin[m + 1];
+        uint32_t carry = kFill ? b.ls_off[a] : 0u;
+        for (uint32_t eb = e0; eb < e1; eb += kLsLanes) {
+            const uint32_t e = eb + w;
+            uint32_t bb = 0, be = 0;
+            LsClass kc;
+            if (e < e1) {
+                const uint2 ed = g.edge[e];
+                bb = min(b.md_off[base + ed.x], b.cap_md);
+                be = min(b.md_off[base + ed.x + 1], b.cap_md);
+                if (bb < be) kc = g.cls[ed.y];
             }
+            // pass mask of this lane's candidates (up to 32; beyond, re-test)
+            uint32_t cnt = 0, mask = 0;
+            for (uint32_t q = bb; q < be; q++) {
+                const float4 pq = b.md_pos[q];
+                if (ls_cut(kc, c, bend, xa, ya, za, ra, ba, pq.x, pq.y, pq.z, fabsf(pq.w))) {
+                    if (q - bb < 32u) mask |= 1u << (q - bb);
+                    cnt++;
+                }
+            }
+            if (!kFill) cand += be - bb;
+            const uint32_t incl = half_incl_scan(cnt);
+            const uint32_t tot = __shfl(incl, kLsLanes - 1, kLsLanes);
+            if (kFill) {
+                uint32_t k = carry + incl - cnt;
+                for (uint32_t q = bb; q < be; q++) {
+                    bool pass;
+                    if (q - bb < 32u) {
+                        pass = (mask >> (q - bb)) & 1u;
+                    } else {
+                        const float4 pq = b.md_pos[q];
+                        pass = ls_cut(kc, c, bend, xa, ya, za, ra, ba, pq.x, pq.y, pq.z, fabsf(pq.w));
+                    }
+                    if (!pass) continue;
+                    if (k < b.cap_ls) {
+                        b.ls_a[k] = a;
+                        b.ls_b[k] = q;
+                    }
+                    k++;
+                }
+            }
+            carry += tot;
         }
-        if (!kFill) b.ls_cnt[a] = k;
+        if (!kFill && w == 0) b.ls_cnt[a] = carry;
     }
     if (!kFill && stats) atomicAdd(&t->cand[1], (unsigned long long)cand);
 }
@@ -422,11 +476,12 @@ struct Anchor {
 __device__ inline Anchor load_anchor(const Batch &b, uint32_t i)
 {
     Anchor A;
-    A.x = b.md_x[i];
-    A.y = b.md_y[i];
-    A.z = b.md_z[i];
-    A.r = b.md_r[i];
-    A.disk = (b.md_u[i] & kDiskBit) != 0u;
+    const float4 p = b.md_pos[i];
+    A.x = p.x;
+    A.y = p.y;
+    A.z = p.z;
+    A.r = fabsf(p.w);
+    A.disk = p.w < 0.0f;
     return A;
 }
 
@@ -490,10 +545,8 @@ __global__ __launch_bounds__(256) void k_t3(const Batch b, Totals *t, const Cons
             if (kFill && k < b.cap_t3) {
                 b.t3_l1[k] = l1;
                 b.t3_l2[k] = l2;
-                b.t3_a[k] = ia;
-                b.t3_c[k] = ic;
-                b.t3_k[k] = kap;
-                b.t3_sk[k] = sk;
+                b.t3_ac[k] = make_uint2(ia, ic);
+                b.t3_ks[k] = make_float2(kap, sk);
             }
             k++;
         }
@@ -510,7 +563,8 @@ __global__ __launch_bounds__(256) void k_t5(const Batch b, Totals *t, const Cons
     const uint32_t n = min(t->n_t3, b.cap_t3);
     uint64_t cand = 0;
     GRID_STRIDE(u, n) {
-        const uint32_t ia = b.t3_a[u], ic = b.t3_c[u];
+        const uint2 ac = b.t3_ac[u];
+        const uint32_t ia = ac.x, ic = ac.y;
         // T3s whose inner MD is ic: those built from segments starting at ic
         const uint32_t w0 = min(b.t3_off[min(b.ls_off[ic], b.cap_ls)], b.cap_t3);
         const uint32_t w1 = min(b.t3_off[min(b.ls_off[ic + 1], b.cap_ls)], b.cap_t3);
@@ -520,10 +574,12 @@ __global__ __launch_bounds__(256) void k_t5(const Batch b, Totals *t, const Cons
             continue;
         }
         const Anchor A = load_anchor(b, ia), C = load_anchor(b, ic);
-        const float k1 = b.t3_k[u], sk1 = b.t3_sk[u];
+        const float2 ks1 = b.t3_ks[u];
+        const float k1 = ks1.x, sk1 = ks1.y;
         for (uint32_t w = w0; w < w1; w++) {
-            const Anchor E = load_anchor(b, b.t3_c[w]);
-            const float k2 = b.t3_k[w], sk2 = b.t3_sk[w];
+            const Anchor E = load_anchor(b, b.t3_ac[w].y);
+            const float2 ks2 = b.t3_ks[w];
+            const float k2 = ks2.x, sk2 = ks2.y;
             float k3, sk3, d1, d2;
             if (!kFill) cand++;
             kappa3(c, A, C, E, k3, sk3, d1, d2);
@@ -534,8 +590,7 @@ __global__ __launch_bounds__(256) void k_t5(const Batch b, Totals *t, const Cons
             if (kFill && k < b.cap_t5) {
                 b.t5_u[k] = u;
                 b.t5_w[k] = w;
-                b.t5_k[k] = k3;
-                b.t5_sk[k] = sk3;
+                b.t5_ks[k] = make_float2(k3, sk3);
             }
             k++;
         }
@@ -588,12 +643,13 @@ __global__ void k_bucket_hist(const Batch b, Totals *t, const DevGeom g, const C
     uint32_t *id = kKind == 0 ? b.bk3_id : b.bk5_id;
     uint32_t *rank = kKind == 0 ? b.bk3_rank : b.bk5_rank;
     GRID_STRIDE(i, n) {
-        const uint32_t a = kKind == 0 ? b.t3_a[i] : b.t3_a[b.t5_u[i]];
-        const float k = kKind == 0 ? b.t3_k[i] : b.t5_k[i];
-        const float sk = kKind == 0 ? b.t3_sk[i] : b.t5_sk[i];
+        const uint32_t a = kKind == 0 ? b.t3_ac[i].x : b.t3_ac[b.t5_u[i]].x;
+        const float2 ks = kKind == 0 ? b.t3_ks[i] : b.t5_ks[i];
+        const float k = ks.x, sk = ks.y;
         const uint32_t u = b.md_u[a] & kUnitMask;
         const uint32_t e = u / c.n_mod, m = u - e * c.n_mod;
-        const uint32_t row = (e * c.n_surf + g.mod_surf[m]) * c.nphi + phi_bin(b.md_x[a], b.md_y[a], c.nphi);
+        const float4 pa = b.md_pos[a];
+        const uint32_t row = (e * c.n_surf + g.mod_surf[m]) * c.nphi + phi_bin(pa.x, pa.y, c.nphi);
         // narrow objects by curvature bin; wide ones (or a NaN resolution) in the last bin
         const uint32_t kb = (sk <= c.sk_wide) ? kappa_bin(k, c) : c.nkb;
         const uint32_t bk = row * (c.nkb + 1u) + kb;
@@ -610,7 +666,13 @@ __global__ void k_bucket_scatter(const Batch b, const Totals *t)
     const uint32_t *id = kKind == 0 ? b.bk3_id : b.bk5_id;
     const uint32_t *rank = kKind == 0 ? b.bk3_rank : b.bk5_rank;
     uint32_t *items = kKind == 0 ? b.bk3_items : b.bk5_items;
-    GRID_STRIDE(i, n) items[off[id[i]] + rank[i]] = i;
+    float2 *bks = kKind == 0 ? b.bk3_ks : b.bk5_ks;
+    const float2 *ks = kKind == 0 ? b.t3_ks : b.t5_ks;
+    GRID_STRIDE(i, n) {
+        const uint32_t pos = off[id[i]] + rank[i];
+        items[pos] = i;
+        bks[pos] = ks[i];
+    }
 }
 
 // ------------------------------------------------- a7: pT3 / pT5 --------
@@ -706,9 +768,12 @@ __device__ inline bool seed_road(const Consts &c, const Seed &s, const Surface &
         if (!(ra <= rb)) return false;
     }
     double ua = ra * s.kp / 2.0, ub = rb * s.kp / 2.0;
-    if (fabs(ua) >= 1.0) return false;
-    double pa = s.phi0 - asin(ua);
-    double pb = fabs(ub) >= 1.0 ? s.phi0 - (ub > 0 ? kPiD / 2 : -kPiD / 2) : s.phi0 - asin(ub);
+    if (!(fabs(ua) < 1.0)) return false;
+    // azimuth of the seed reduced to [0, 2 pi) so that the bins stay bounded
+    double phi0 = fmod(s.phi0, 2.0 * kPiD);
+    if (phi0 < 0.0) phi0 += 2.0 * kPiD;
+    double pa = phi0 - asin(ua);
+    double pb = fabs(ub) >= 1.0 ? phi0 - (ub > 0 ? kPiD / 2 : -kPiD / 2) : phi0 - asin(ub);
     double lo = fmin(pa, pb), hi = fmax(pa, pb);
     double um = fmin(fabs(ub), 1.0);
     double sr = sf.kind == LST_BARREL ? 0.0 : c.sig_c;
@@ -717,11 +782,12 @@ __device__ inline bool seed_road(const Consts &c, const Seed &s, const Surface &
     double pad = W + 1e-3;
     lo -= pad;
     hi += pad;
-    if (!(hi - lo < 2.0 * kPiD)) {
+    if (!(hi - lo < 2.0 * kPiD) || !(lo > -3.0 * kPiD) || !(hi < 4.0 * kPiD)) {
         b0 = 0;
         b1 = (int)c.nphi - 1;
         return true;
     }
+    // lo, hi lie within [-3 pi, 4 pi] here
     const double scale = (double)c.nphi / (2.0 * kPiD);
     b0 = (int)floor((lo + kPiD) * scale);
     b1 = (int)floor((hi + kPiD) * scale);
@@ -729,20 +795,44 @@ __device__ inline bool seed_road(const Consts &c, const Seed &s, const Surface &
     return true;
 }
 
-// Candidates: one thread per (seed, surface) walks the buckets of the
-// seed's road and keeps the objects that pass the (exact, binary64)
-// curvature test; the other seed cuts run in k_pt_eval, one thread per
-// candidate.
+// Road of every (seed, surface) unit: the azimuth bins and curvature bins
+// of the buckets that can hold objects linked to the seed (binary64, once
+// per unit; shared by the T3 and the T5 lookup).
+__global__ __launch_bounds__(256) void k_road(const Batch b, const Totals *t, const DevGeom g, const Consts c)
+{
+    const uint32_t n = min(t->n_pls, b.cap_pls) * c.n_surf;
+    GRID_STRIDE(unit, n) {
+        const uint32_t p = unit / c.n_surf, sfi = unit - p * c.n_surf;
+        const Surface sf = g.surf[sfi];
+        uint2 r = make_uint2(0u, 0u);
+        int b0 = 0, b1 = -1;
+        if (sf.kind <= 1u) {
+            const Seed s = load_seed(b, c, p);
+            if (seed_road(c, s, sf, b0, b1)) {
+                // narrow objects: curvature within the seed's window widened by
+                // the largest narrow resolution
+                const double wide = c.n_sigma * (s.skp + (double)c.sk_wide) + 1e-6;
+                const int k0 = kappa_bin_d(s.kp - wide, c), k1 = kappa_bin_d(s.kp + wide, c);
+                const int first = ((b0 % (int)c.nphi) + (int)c.nphi) % (int)c.nphi;
+                r.x = (uint32_t)first | ((uint32_t)(b1 - b0 + 1) << 16);
+                r.y = (uint32_t)k0 | ((uint32_t)k1 << 8) | 0x80000000u;
+            }
+        }
+        b.road[unit] = r;
+    }
+}
+
+// Candidates: one thread per (seed, surface) walks the buckets of its road
+// and keeps the objects that pass the (exact, binary64) curvature test; the
+// other seed cuts run in k_pt_eval, one thread per candidate.
 template <int kKind, bool kFill>
-__global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const DevGeom g, const Consts c,
-                                             int stats)
+__global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Consts c, int stats)
 {
     const uint32_t n = min(t->n_pls, b.cap_pls) * c.n_surf;
     const uint32_t n_ev = t->n_ev;
     const uint32_t *bk_off = kKind == 0 ? b.bk3_off : b.bk5_off;
     const uint32_t *bk_items = kKind == 0 ? b.bk3_items : b.bk5_items;
-    const float *ok = kKind == 0 ? b.t3_k : b.t5_k;
-    const float *osk = kKind == 0 ? b.t3_sk : b.t5_sk;
+    const float2 *bks = kKind == 0 ? b.bk3_ks : b.bk5_ks;
     uint32_t *cnt = kKind == 0 ? b.ptc3_cnt : b.ptc5_cnt;
     const uint32_t *off = kKind == 0 ? b.ptc3_off : b.ptc5_off;
     uint32_t *out_p = kKind == 0 ? b.ptc3_p : b.ptc5_p;
@@ -751,35 +841,35 @@ __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Dev
     const uint32_t nkb1 = c.nkb + 1u;
     uint64_t cand = 0;
     GRID_STRIDE(unit, n) {
-        const uint32_t p = unit / c.n_surf, sfi = unit - p * c.n_surf;
         uint32_t k = kFill ? off[unit] : 0u;
-        const Surface sf = g.surf[sfi];
-        int b0 = 0, b1 = -1;
-        if (sf.kind <= 1u) {
-            const Seed s = load_seed(b, c, p);
-            if (seed_road(c, s, sf, b0, b1)) {
-                const uint32_t e = find_event(b.ev_pls_off, n_ev, p);
-                const uint32_t row0 = (e * c.n_surf + sfi) * c.nphi;
-                // narrow objects: curvature within the seed's window widened by
-                // the largest narrow resolution
-                const double wide = c.n_sigma * (s.skp + (double)c.sk_wide) + 1e-6;
-                const int k0 = kappa_bin_d(s.kp - wide, c), k1 = kappa_bin_d(s.kp + wide, c);
-                for (int bi = b0; bi <= b1; bi++) {
-                    const uint32_t row = row0 + (uint32_t)(((bi % (int)c.nphi) + (int)c.nphi) % (int)c.nphi);
-                    for (int part = 0; part < 2; part++) {
-                        const uint32_t lo = part == 0 ? row * nkb1 + (uint32_t)k0 : row * nkb1 + c.nkb;
-                        const uint32_t hi = part == 0 ? row * nkb1 + (uint32_t)k1 + 1u : row * nkb1 + nkb1;
-                        const uint32_t i0 = bk_off[lo], i1 = bk_off[hi];
-                        for (uint32_t i = i0; i < i1; i++) {
-                            const uint32_t o = bk_items[i];
-                            if (!kFill) cand++;
-                            if (!(fabs(s.kp - (double)ok[o]) <= c.n_sigma * (s.skp + (double)osk[o]))) continue;
-                            if (kFill && k < cap) {
-                                out_p[k] = p;
-                                out_o[k] = o;
-                            }
-                            k++;
+        const uint2 r = b.road[unit];
+        if (r.y & 0x80000000u) {
+            const uint32_t p = unit / c.n_surf, sfi = unit - p * c.n_surf;
+            const float *par = b.in_par + 5 * (size_t)p;
+            const float *cov = b.in_cov + 15 * (size_t)p;
+            const double kp = (double)par[0] * c.kB;
+            const double skp = c.kB * sqrt((double)cov[0]);
+            const uint32_t e = find_event(b.ev_pls_off, n_ev, p);
+            const uint32_t row0 = (e * c.n_surf + sfi) * c.nphi;
+            const uint32_t first = r.x & 0xFFFFu, nbins = r.x >> 16;
+            const uint32_t k0 = r.y & 0xFFu, k1 = (r.y >> 8) & 0xFFu;
+            for (uint32_t j = 0; j < nbins; j++) {
+                uint32_t bin = first + j;
+                if (bin >= c.nphi) bin -= c.nphi;
+                const uint32_t row = row0 + bin;
+                for (int part = 0; part < 2; part++) {
+                    const uint32_t lo = part == 0 ? row * nkb1 + k0 : row * nkb1 + c.nkb;
+                    const uint32_t hi = part == 0 ? row * nkb1 + k1 + 1u : row * nkb1 + nkb1;
+                    const uint32_t i0 = bk_off[lo], i1 = bk_off[hi];
+                    for (uint32_t i = i0; i < i1; i++) {
+                        const float2 ks = bks[i];
+                        if (!kFill) cand++;
+                        if (!(fabs(kp - (double)ks.x) <= c.n_sigma * (skp + (double)ks.y))) continue;
+                        if (kFill && k < cap) {
+                            out_p[k] = p;
+                            out_o[k] = bk_items[i];
                         }
+                        k++;
                     }
                 }
             }
@@ -801,17 +891,19 @@ __global__ __launch_bounds__(256) void k_pt_eval(const Batch b, const Totals *t,
         const uint32_t p = cp[i], o = co[i];
         uint32_t ia, io;
         float ko, sko;
+        float2 ks;
         if (kKind == 0) {
-            ia = b.t3_a[o];
-            io = b.t3_c[o];
-            ko = b.t3_k[o];
-            sko = b.t3_sk[o];
+            const uint2 ac = b.t3_ac[o];
+            ia = ac.x;
+            io = ac.y;
+            ks = b.t3_ks[o];
         } else {
-            ia = b.t3_a[b.t5_u[o]];
-            io = b.t3_c[b.t5_w[o]];
-            ko = b.t5_k[o];
-            sko = b.t5_sk[o];
+            ia = b.t3_ac[b.t5_u[o]].x;
+            io = b.t3_ac[b.t5_w[o]].y;
+            ks = b.t5_ks[o];
         }
+        ko = ks.x;
+        sko = ks.y;
         const Seed s = load_seed(b, c, p);
         keep[i] = p_cut(c, s, ko, sko, load_anchor(b, ia), load_anchor(b, io)) ? 1u : 0u;
     }
@@ -849,23 +941,27 @@ __device__ inline uint32_t pt_first(const Batch &b, const Consts &c, uint32_t p)
     return min(koff[min(off[p * c.n_surf], capc)], cap);
 }
 
-// canonical order within each seed: by object index
-template <int kKind>
+__device__ inline void sort_range(uint32_t *v, uint32_t k0, uint32_t k1)
+{
+    for (uint32_t i = k0 + 1; i < k1; i++) {
+        const uint32_t x = v[i];
+        uint32_t j = i;
+        while (j > k0 && v[j - 1] > x) {
+            v[j] = v[j - 1];
+            j--;
+        }
+        v[j] = x;
+    }
+}
+
+// canonical order within each seed (pT3 and pT5 lists): by object index
 __global__ void k_pt_sort(const Batch b, const Totals *t, const Consts c)
 {
     const uint32_t n = min(t->n_pls, b.cap_pls);
-    uint32_t *out_o = kKind == 0 ? b.pt3_o : b.pt5_o;
-    GRID_STRIDE(p, n) {
-        const uint32_t k0 = pt_first<kKind>(b, c, p), k1 = pt_first<kKind>(b, c, p + 1);
-        for (uint32_t i = k0 + 1; i < k1; i++) {
-            uint32_t v = out_o[i];
-            uint32_t j = i;
-            while (j > k0 && out_o[j - 1] > v) {
-                out_o[j] = out_o[j - 1];
-                j--;
-            }
-            out_o[j] = v;
-        }
+    GRID_STRIDE(q, 2 * n) {
+        const uint32_t p = q >> 1;
+        if (q & 1u) sort_range(b.pt5_o, pt_first<1>(b, c, p), pt_first<1>(b, c, p + 1));
+        else sort_range(b.pt3_o, pt_first<0>(b, c, p), pt_first<0>(b, c, p + 1));
     }
 }
 
@@ -980,14 +1076,15 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     L.launch("hit_gather", k_hit_gather, grid_for((uint64_t)b.cap_ev * 2 * n_mod), blk, b, (const Totals *)t,
              n_mod);
     // a2: mini-doublets
-    const dim3 gmd = grid_for((uint64_t)b.cap_ev * n_mod);
+    const dim3 gmd = grid_for(b.cap_hits);
     L.launch("md_count", k_md<false>, gmd, blk, b, t, g, c, stats);
-    L.scan(b.md_cnt, b.md_off, &t->n_md_units, b.cap_ev * n_mod, &t->n_md, "scan_md");
+    L.scan(b.md_cnt, b.md_hoff, &t->n_sorted, b.cap_hits, &t->n_md, "scan_md");
     L.launch("md_fill", k_md<true>, gmd, blk, b, t, g, c, 0);
+    L.launch("md_units", k_md_units, grid_for((uint64_t)b.cap_ev * n_mod + 1), blk, b, (const Totals *)t);
     // a3: line segments over the connection map
-    L.launch("ls_count", k_ls<false>, grid_for(b.cap_md), blk, b, t, g, c, stats);
+    L.launch("ls_count", k_ls<false>, grid_for(32ull * b.cap_md), blk, b, t, g, c, stats);
     L.scan(b.ls_cnt, b.ls_off, &t->n_md, b.cap_md, &t->n_ls, "scan_ls");
-    L.launch("ls_fill", k_ls<true>, grid_for(b.cap_md), blk, b, t, g, c, 0);
+    L.launch("ls_fill", k_ls<true>, grid_for(32ull * b.cap_md), blk, b, t, g, c, 0);
     // a4: T3
     L.launch("t3_count", k_t3<false>, grid_for(b.cap_ls), blk, b, t, c, stats);
     L.scan(b.t3_cnt, b.t3_off, &t->n_ls, b.cap_ls, &t->n_t3, "scan_t3");
@@ -1009,20 +1106,20 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     L.launch("bucket_scatter", k_bucket_scatter<1>, grid_for(b.cap_t5), blk, b, (const Totals *)t);
     // a7: pT3 / pT5: candidates, seed cuts, compaction, per-seed order
     const uint64_t cap_pu = (uint64_t)b.cap_pls * c.n_surf;
-    L.launch("ptc_count", k_ptc<0, false>, grid_for(cap_pu), blk, b, t, g, c, stats);
-    L.launch("ptc_count", k_ptc<1, false>, grid_for(cap_pu), blk, b, t, g, c, stats);
+    L.launch("road", k_road, grid_for(cap_pu), blk, b, (const Totals *)t, g, c);
+    L.launch("ptc_count", k_ptc<0, false>, grid_for(cap_pu), blk, b, t, c, stats);
+    L.launch("ptc_count", k_ptc<1, false>, grid_for(cap_pu), blk, b, t, c, stats);
     L.scan(b.ptc3_cnt, b.ptc3_off, &t->n_pt_units, (uint32_t)cap_pu, &t->n_ptc3, "scan_pt");
     L.scan(b.ptc5_cnt, b.ptc5_off, &t->n_pt_units, (uint32_t)cap_pu, &t->n_ptc5, "scan_pt");
-    L.launch("ptc_fill", k_ptc<0, true>, grid_for(cap_pu), blk, b, t, g, c, 0);
-    L.launch("ptc_fill", k_ptc<1, true>, grid_for(cap_pu), blk, b, t, g, c, 0);
+    L.launch("ptc_fill", k_ptc<0, true>, grid_for(cap_pu), blk, b, t, c, 0);
+    L.launch("ptc_fill", k_ptc<1, true>, grid_for(cap_pu), blk, b, t, c, 0);
     L.launch("pt_eval", k_pt_eval<0>, grid_for(b.cap_ptc3), blk, b, (const Totals *)t, c);
     L.launch("pt_eval", k_pt_eval<1>, grid_for(b.cap_ptc5), blk, b, (const Totals *)t, c);
     L.scan(b.pt3_keep, b.pt3_koff, &t->n_ptc3, b.cap_ptc3, &t->n_pt3, "scan_pt");
     L.scan(b.pt5_keep, b.pt5_koff, &t->n_ptc5, b.cap_ptc5, &t->n_pt5, "scan_pt");
     L.launch("pt_compact", k_pt_compact<0>, grid_for(b.cap_ptc3), blk, b, (const Totals *)t);
     L.launch("pt_compact", k_pt_compact<1>, grid_for(b.cap_ptc5), blk, b, (const Totals *)t);
-    L.launch("pt_sort", k_pt_sort<0>, grid_for(b.cap_pls), blk, b, (const Totals *)t, c);
-    L.launch("pt_sort", k_pt_sort<1>, grid_for(b.cap_pls), blk, b, (const Totals *)t, c);
+    L.launch("pt_sort", k_pt_sort, grid_for(2ull * b.cap_pls), blk, b, (const Totals *)t, c);
     // a8: track candidates
     L.launch("zero8", k_zero_u8, grid_for(b.cap_pls), blk, b.pls_used5, &t->n_pls, b.cap_pls);
     L.launch("zero8", k_zero_u8, grid_for(b.cap_pls), blk, b.pls_used3, &t->n_pls, b.cap_pls);
