@@ -80,6 +80,32 @@ def cpu_baseline(n_events: int, budget_s: float):
                        f"one thread, {tot:.1f} s of oracle time")
 
 
+def _oracle_one(i):
+    import oracle
+    from paper_2407_18231_amd import synth
+    g = synth.make_geometry("pu200")
+    ev = synth.gen_event(g, synth.config_pu(200), synth.event_seed(2, i))
+    t0 = time.perf_counter()
+    oracle.run(g, ev)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline_all_cores(budget_s: float):
+    """The oracle on every host core at once, one event per worker process
+    (events are independent)."""
+    import multiprocessing as mp
+    import oracle
+    oracle.build(force=False)
+    cores = len(os.sched_getaffinity(0))
+    n = cores
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        pool.map(_oracle_one, range(n))
+    wall = time.perf_counter() - t0
+    return dict(value=n / wall, unit="events/s", cores=cores, kind="oracle",
+                sample=f"{n} PU200-like events, one per process on {cores} cores, {wall:.1f} s wall")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,7 +116,14 @@ def main():
     ap.add_argument("--cpu-events", type=int, default=8)
     ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--quick", action="store_true", help="only the batched path (profiling runs)")
+    ap.add_argument("--chain-only", type=int, default=0, metavar="N",
+                    help="counter runs: upload one batch, run the chain N times, print nothing else")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
+                    help="counter calibration: one device-to-device copy of MB megabytes (torch)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: the events of a batch shard across GPUs with no "
               f"exchange, so there is no multi-GPU path to time (asked for --gpus {args.gpus})",
@@ -113,6 +146,11 @@ def main():
 
     # ---- batched path: B events per launch --------------------------------
     ctx.batch_upload(events)
+    if args.chain_only:
+        ctx.batch_execute(args.chain_only, graph=False, timing=False)
+        log(f"chain run {args.chain_only} times on {B} events")
+        ctx.close()
+        return
     counts = ctx.batch_counts()
     log("object totals:", counts)
     for _ in range(args.warmup):
@@ -204,7 +242,21 @@ def main():
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(args.cpu_events, args.cpu_budget)
         log("cpu baseline:", result["cpu_baseline"])
+        result["cpu_baseline_all_cores"] = cpu_baseline_all_cores(args.cpu_budget)
+        log("cpu baseline, all cores:", result["cpu_baseline_all_cores"])
     print(json.dumps(result), flush=True)
+
+
+def copy_probe(mb: int):
+    """A plain copy kernel of known size: reads and writes mb * 2^20 bytes."""
+    import torch
+    n = mb * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copied {mb} MiB")
 
 
 def served(ctx, g, synth, rate_hz=500.0, n=600):

@@ -83,7 +83,7 @@ void carve_work(Carver &cv, Batch &b, uint32_t n_mod, uint32_t n_surf, uint32_t 
     const size_t bins = (size_t)b.cap_ev * 2 * n_mod;
     const size_t units = (size_t)b.cap_ev * n_mod;
     const size_t rows = (size_t)b.cap_ev * n_surf * nphi;
-    const size_t bk = rows * (nkb + 1);
+    const size_t bk = rows * (3 * nkb + 1);
     const size_t pt_units = (size_t)b.cap_pls * n_surf;
     const size_t tcu = (size_t)b.cap_pt3 + b.cap_t5 + b.cap_pls;
     b.bin_cnt = cv.take<uint32_t>(bins + 1);
@@ -129,7 +129,7 @@ void carve_work(Carver &cv, Batch &b, uint32_t n_mod, uint32_t n_surf, uint32_t 
     b.bk5_rank = cv.take<uint32_t>(b.cap_t5);
     b.bk5_items = cv.take<uint32_t>(b.cap_t5);
     b.bk5_ks = cv.take<float2>(b.cap_t5);
-    b.road = cv.take<uint2>(pt_units);
+    b.road = cv.take<uint4>(pt_units);
     b.ptc3_cnt = cv.take<uint32_t>(pt_units + 1);
     b.ptc3_off = cv.take<uint32_t>(pt_units + 1);
     b.ptc3_p = cv.take<uint32_t>(b.cap_ptc3);
@@ -619,9 +619,9 @@ uint64_t predict_footprint(uint64_t hits, uint64_t pls, const lst::Consts &k)
     uint64_t b = 0;
     b += 73ull * c.hits + 80ull * c.pls + 24ull * k.n_mod;
     b += 40ull * c.md + 16ull * c.ls + 52ull * c.t3 + 36ull * c.t5;
-    b += 8ull * (c.pt3 + c.pt5) + 24ull * c.pls * k.n_surf + 3ull * c.pls + 16ull * (c.pt3 + c.t5 + c.pls);
+    b += 8ull * (c.pt3 + c.pt5) + 32ull * c.pls * k.n_surf + 3ull * c.pls + 16ull * (c.pt3 + c.t5 + c.pls);
     b += 16ull * (c.ptc3 + c.ptc5);
-    b += 2ull * 8ull * k.n_surf * k.nphi * (k.nkb + 1);
+    b += 2ull * 8ull * k.n_surf * k.nphi * (3 * k.nkb + 1);
     return b;
 }
 

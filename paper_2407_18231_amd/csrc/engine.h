@@ -81,14 +81,15 @@ struct Batch {
     uint32_t *t5_u, *t5_w;
     float2 *t5_ks;                      // curvature through (A, C, E) and its resolution
     // a6: seed lookup buckets of T3s / T5s by (event, surface, azimuth bin,
-    // curvature bin); the last curvature bin of a row holds the objects with
-    // a wide curvature resolution
+    // resolution class, curvature bin); the last bucket of a row holds the
+    // objects with a wide curvature resolution
     uint32_t *bk3_cnt, *bk3_off, *bk3_id, *bk3_rank, *bk3_items;
     uint32_t *bk5_cnt, *bk5_off, *bk5_id, *bk5_rank, *bk5_items;
     float2 *bk3_ks, *bk5_ks;            // curvature and resolution of each bucketed object
-    // a7: road of each (seed, surface) unit: first azimuth bin | bin count << 16,
-    // curvature bins k0 | k1 << 8 | valid << 31
-    uint2 *road;
+    // a7: road of each (seed, surface) unit: x = first azimuth bin | bin count
+    // << 16; y, z = curvature bin ranges of the resolution classes (k0 | k1 << 8
+    // per class, class 2 in z), valid << 31 in z
+    uint4 *road;
     // seed-object candidates per (seed, surface) unit, their keep flags,
     // and the pT3 / pT5 lists (seed, object)
     uint32_t *ptc3_cnt, *ptc3_off, *ptc3_p, *ptc3_o, *pt3_keep, *pt3_koff;

@@ -163,7 +163,7 @@ __global__ void k_setup(Totals *t, uint32_t n_mod, uint32_t n_surf, uint32_t nph
         t->n_bins = t->n_ev * 2u * n_mod;
         t->n_md_units = t->n_ev * n_mod;
         t->n_rows = t->n_ev * n_surf * nphi;
-        t->n_bk = t->n_rows * (nkb + 1u);
+        t->n_bk = t->n_rows * (3u * nkb + 1u);
         t->n_pt_units = t->n_pls * n_surf;
         t->err = 0;
         for (int i = 0; i < 6; i++) t->cand[i] = 0ull;
@@ -380,22 +380,40 @@ __device__ inline bool ls_cut(const LsClass &k, const Consts &c, bool bend,
     return lo <= rb;
 }
 
-// Wave-cooperative: a wave takes two consecutive MDs; for each, 32 lanes take
-// one edge of the MD's module each (chunks of 32 for larger degrees) and test
-// the MDs of the edge's destination module.  Half-wave prefix sums give each
-// lane its place, so segments come out ordered by (inner MD, edge, outer MD),
-// which is (inner MD, outer MD) because edges are sorted by destination.
-constexpr uint32_t kLsLanes = 32;
+// One thread per inner MD a: every MD of every module a's module connects to.
+// Edges are read in groups of 8 so that their MD ranges load together.
+constexpr int kEdgeGroup = 8;
 
-__device__ inline uint32_t half_incl_scan(uint32_t v)
+template <typename Visit>
+__device__ inline void ls_walk(const Batch &b, const DevGeom &g, const Consts &c, bool bend, uint32_t m,
+                               uint32_t base, const float4 &pa, float ba, Visit visit)
 {
-    const uint32_t w = threadIdx.x & (kLsLanes - 1);
+    const float xa = pa.x, ya = pa.y, za = pa.z, ra = fabsf(pa.w);
+    const uint32_t e0 = g.edge_begin[m], e1 = g.edge_begin[m + 1];
+    for (uint32_t eb = e0; eb < e1; eb += kEdgeGroup) {
+        uint32_t bq[kEdgeGroup], eq[kEdgeGroup], cl[kEdgeGroup];
 #pragma unroll
-    for (uint32_t d = 1; d < kLsLanes; d <<= 1) {
-        uint32_t t = __shfl_up(v, d, kLsLanes);
-        if (w >= d) v += t;
+        for (int j = 0; j < kEdgeGroup; j++) {
+            bq[j] = 0;
+            eq[j] = 0;
+            cl[j] = 0;
+            if (eb + j < e1) {
+                const uint2 ed = g.edge[eb + j];
+                bq[j] = min(b.md_off[base + ed.x], b.cap_md);
+                eq[j] = min(b.md_off[base + ed.x + 1], b.cap_md);
+                cl[j] = ed.y;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kEdgeGroup; j++) {
+            if (bq[j] >= eq[j]) continue;
+            const LsClass kc = g.cls[cl[j]];
+            for (uint32_t q = bq[j]; q < eq[j]; q++) {
+                const float4 pq = b.md_pos[q];
+                visit(q, ls_cut(kc, c, bend, xa, ya, za, ra, ba, pq.x, pq.y, pq.z, fabsf(pq.w)));
+            }
+        }
     }
-    return v;
 }
 
 template <bool kFill>
@@ -405,63 +423,23 @@ __global__ __launch_bounds__(256) void k_ls(const Batch b, Totals *t, const DevG
     const uint32_t n = min(t->n_md, b.cap_md);
     const uint32_t n_mod = c.n_mod;
     const bool bend = (c.flags & LST_FLAG_BEND) != 0u;
-    const uint32_t half = (threadIdx.x >> 5) & 1u, w = threadIdx.x & (kLsLanes - 1);
-    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
     uint64_t cand = 0;
-    for (uint32_t a0 = 2 * wave; a0 < n; a0 += 2 * n_waves) {
-        const uint32_t a = a0 + half;
-        if (a >= n) continue;
+    GRID_STRIDE(a, n) {
         const uint32_t u = b.md_u[a] & kUnitMask;
         const uint32_t m = u % n_mod;
-        const uint32_t base = u - m;
         const float4 pa = b.md_pos[a];
-        const float xa = pa.x, ya = pa.y, za = pa.z, ra = fabsf(pa.w), ba = b.md_beta[a];
-        const uint32_t e0 = g.edge_begin[m], e1 = g.edge_begin[m + 1];
-        uint32_t carry = kFill ? b.ls_off[a] : 0u;
-        for (uint32_t eb = e0; eb < e1; eb += kLsLanes) {
-            const uint32_t e = eb + w;
-            uint32_t bb = 0, be = 0;
-            LsClass kc;
-            if (e < e1) {
-                const uint2 ed = g.edge[e];
-                bb = min(b.md_off[base + ed.x], b.cap_md);
-                be = min(b.md_off[base + ed.x + 1], b.cap_md);
-                if (bb < be) kc = g.cls[ed.y];
+        const float ba = b.md_beta[a];
+        uint32_t k = kFill ? b.ls_off[a] : 0u;
+        ls_walk(b, g, c, bend, m, u - m, pa, ba, [&](uint32_t q, bool pass) {
+            if (!kFill) cand++;
+            if (!pass) return;
+            if (kFill && k < b.cap_ls) {
+                b.ls_a[k] = a;
+                b.ls_b[k] = q;
             }
-            // pass mask of this lane's candidates (up to 32; beyond, re-test)
-            uint32_t cnt = 0, mask = 0;
-            for (uint32_t q = bb; q < be; q++) {
-                const float4 pq = b.md_pos[q];
-                if (ls_cut(kc, c, bend, xa, ya, za, ra, ba, pq.x, pq.y, pq.z, fabsf(pq.w))) {
-                    if (q - bb < 32u) mask |= 1u << (q - bb);
-                    cnt++;
-                }
-            }
-            if (!kFill) cand += be - bb;
-            const uint32_t incl = half_incl_scan(cnt);
-            const uint32_t tot = __shfl(incl, kLsLanes - 1, kLsLanes);
-            if (kFill) {
-                uint32_t k = carry + incl - cnt;
-                for (uint32_t q = bb; q < be; q++) {
-                    bool pass;
-                    if (q - bb < 32u) {
-                        pass = (mask >> (q - bb)) & 1u;
-                    } else {
-                        const float4 pq = b.md_pos[q];
-                        pass = ls_cut(kc, c, bend, xa, ya, za, ra, ba, pq.x, pq.y, pq.z, fabsf(pq.w));
-                    }
-                    if (!pass) continue;
-                    if (k < b.cap_ls) {
-                        b.ls_a[k] = a;
-                        b.ls_b[k] = q;
-                    }
-                    k++;
-                }
-            }
-            carry += tot;
-        }
-        if (!kFill && w == 0) b.ls_cnt[a] = carry;
+            k++;
+        });
+        if (!kFill) b.ls_cnt[a] = k;
     }
     if (!kFill && stats) atomicAdd(&t->cand[1], (unsigned long long)cand);
 }
@@ -650,9 +628,13 @@ __global__ void k_bucket_hist(const Batch b, Totals *t, const DevGeom g, const C
         const uint32_t e = u / c.n_mod, m = u - e * c.n_mod;
         const float4 pa = b.md_pos[a];
         const uint32_t row = (e * c.n_surf + g.mod_surf[m]) * c.nphi + phi_bin(pa.x, pa.y, c.nphi);
-        // narrow objects by curvature bin; wide ones (or a NaN resolution) in the last bin
-        const uint32_t kb = (sk <= c.sk_wide) ? kappa_bin(k, c) : c.nkb;
-        const uint32_t bk = row * (c.nkb + 1u) + kb;
+        // objects by resolution class and curvature bin; wide ones (or a NaN
+        // resolution) in the last bucket of the row
+        uint32_t kb = 3u * c.nkb;
+        if (sk <= c.sk_cls[0]) kb = kappa_bin(k, c);
+        else if (sk <= c.sk_cls[1]) kb = c.nkb + kappa_bin(k, c);
+        else if (sk <= c.sk_cls[2]) kb = 2u * c.nkb + kappa_bin(k, c);
+        const uint32_t bk = row * (3u * c.nkb + 1u) + kb;
         id[i] = bk;
         rank[i] = atomicAdd(&cnt[bk], 1u);
     }
@@ -804,18 +786,23 @@ __global__ __launch_bounds__(256) void k_road(const Batch b, const Totals *t, co
     GRID_STRIDE(unit, n) {
         const uint32_t p = unit / c.n_surf, sfi = unit - p * c.n_surf;
         const Surface sf = g.surf[sfi];
-        uint2 r = make_uint2(0u, 0u);
+        uint4 r = make_uint4(0u, 0u, 0u, 0u);
         int b0 = 0, b1 = -1;
         if (sf.kind <= 1u) {
             const Seed s = load_seed(b, c, p);
             if (seed_road(c, s, sf, b0, b1)) {
-                // narrow objects: curvature within the seed's window widened by
-                // the largest narrow resolution
-                const double wide = c.n_sigma * (s.skp + (double)c.sk_wide) + 1e-6;
-                const int k0 = kappa_bin_d(s.kp - wide, c), k1 = kappa_bin_d(s.kp + wide, c);
+                // objects of resolution class i: curvature within the seed's
+                // window widened by the class's largest resolution
+                uint32_t kr[3];
+                for (int i = 0; i < 3; i++) {
+                    const double wide = c.n_sigma * (s.skp + (double)c.sk_cls[i]) + 1e-6;
+                    const int k0 = kappa_bin_d(s.kp - wide, c), k1 = kappa_bin_d(s.kp + wide, c);
+                    kr[i] = (uint32_t)k0 | ((uint32_t)k1 << 8);
+                }
                 const int first = ((b0 % (int)c.nphi) + (int)c.nphi) % (int)c.nphi;
                 r.x = (uint32_t)first | ((uint32_t)(b1 - b0 + 1) << 16);
-                r.y = (uint32_t)k0 | ((uint32_t)k1 << 8) | 0x80000000u;
+                r.y = kr[0] | (kr[1] << 16);
+                r.z = kr[2] | 0x80000000u;
             }
         }
         b.road[unit] = r;
@@ -838,12 +825,12 @@ __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Con
     uint32_t *out_p = kKind == 0 ? b.ptc3_p : b.ptc5_p;
     uint32_t *out_o = kKind == 0 ? b.ptc3_o : b.ptc5_o;
     const uint32_t cap = kKind == 0 ? b.cap_ptc3 : b.cap_ptc5;
-    const uint32_t nkb1 = c.nkb + 1u;
+    const uint32_t per_row = 3u * c.nkb + 1u;
     uint64_t cand = 0;
     GRID_STRIDE(unit, n) {
         uint32_t k = kFill ? off[unit] : 0u;
-        const uint2 r = b.road[unit];
-        if (r.y & 0x80000000u) {
+        const uint4 r = b.road[unit];
+        if (r.z & 0x80000000u) {
             const uint32_t p = unit / c.n_surf, sfi = unit - p * c.n_surf;
             const float *par = b.in_par + 5 * (size_t)p;
             const float *cov = b.in_cov + 15 * (size_t)p;
@@ -852,14 +839,15 @@ __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Con
             const uint32_t e = find_event(b.ev_pls_off, n_ev, p);
             const uint32_t row0 = (e * c.n_surf + sfi) * c.nphi;
             const uint32_t first = r.x & 0xFFFFu, nbins = r.x >> 16;
-            const uint32_t k0 = r.y & 0xFFu, k1 = (r.y >> 8) & 0xFFu;
+            const uint32_t kr[3] = {r.y & 0xFFFFu, r.y >> 16, r.z & 0xFFFFu};
             for (uint32_t j = 0; j < nbins; j++) {
                 uint32_t bin = first + j;
                 if (bin >= c.nphi) bin -= c.nphi;
-                const uint32_t row = row0 + bin;
-                for (int part = 0; part < 2; part++) {
-                    const uint32_t lo = part == 0 ? row * nkb1 + k0 : row * nkb1 + c.nkb;
-                    const uint32_t hi = part == 0 ? row * nkb1 + k1 + 1u : row * nkb1 + nkb1;
+                const uint32_t rb = (row0 + bin) * per_row;
+                for (int part = 0; part < 4; part++) {
+                    // parts 0-2: the curvature range of each resolution class; 3: wide objects
+                    const uint32_t lo = part < 3 ? rb + part * c.nkb + (kr[part] & 0xFFu) : rb + 3u * c.nkb;
+                    const uint32_t hi = part < 3 ? rb + part * c.nkb + (kr[part] >> 8) + 1u : rb + per_row;
                     const uint32_t i0 = bk_off[lo], i1 = bk_off[hi];
                     for (uint32_t i = i0; i < i1; i++) {
                         const float2 ks = bks[i];
@@ -1082,9 +1070,9 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     L.launch("md_fill", k_md<true>, gmd, blk, b, t, g, c, 0);
     L.launch("md_units", k_md_units, grid_for((uint64_t)b.cap_ev * n_mod + 1), blk, b, (const Totals *)t);
     // a3: line segments over the connection map
-    L.launch("ls_count", k_ls<false>, grid_for(32ull * b.cap_md), blk, b, t, g, c, stats);
+    L.launch("ls_count", k_ls<false>, grid_for(b.cap_md), blk, b, t, g, c, stats);
     L.scan(b.ls_cnt, b.ls_off, &t->n_md, b.cap_md, &t->n_ls, "scan_ls");
-    L.launch("ls_fill", k_ls<true>, grid_for(32ull * b.cap_md), blk, b, t, g, c, 0);
+    L.launch("ls_fill", k_ls<true>, grid_for(b.cap_md), blk, b, t, g, c, 0);
     // a4: T3
     L.launch("t3_count", k_t3<false>, grid_for(b.cap_ls), blk, b, t, c, stats);
     L.scan(b.t3_cnt, b.t3_off, &t->n_ls, b.cap_ls, &t->n_t3, "scan_t3");
@@ -1095,7 +1083,7 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     L.launch("t5_fill", k_t5<true>, grid_for(b.cap_t3), blk, b, t, c, 0);
     // a6: seed lookup buckets
     const uint32_t cap_rows = b.cap_ev * c.n_surf * c.nphi;
-    const uint32_t cap_bk = cap_rows * (c.nkb + 1);
+    const uint32_t cap_bk = cap_rows * (3 * c.nkb + 1);
     L.launch("zero", k_zero_u32, grid_for((uint64_t)cap_bk + 1), blk, b.bk3_cnt, &t->n_bk, cap_bk, 1u);
     L.launch("zero", k_zero_u32, grid_for((uint64_t)cap_bk + 1), blk, b.bk5_cnt, &t->n_bk, cap_bk, 1u);
     L.launch("bucket_hist", k_bucket_hist<0>, grid_for(b.cap_t3), blk, b, t, g, c);

@@ -49,9 +49,9 @@ struct Consts {
     float L, ec, kmaxf, khalf, ns, srp, sc, Kb;
     double B, n_sigma, sig_rphi, sig_c, kB;
     uint32_t n_mod, n_surf, flags, nphi;
-    uint32_t nkb;            // curvature bins of the seed-lookup buckets
+    uint32_t nkb;            // curvature bins of the seed-lookup buckets (per resolution class)
     float kspan;             // curvature bins cover [-kspan, kspan]
-    float sk_wide;           // objects with a larger curvature resolution go to the wide bin
+    float sk_cls[3];         // resolution classes: sigma_kappa <= sk_cls[i]; larger ones go to the wide bin
 };
 
 struct Geometry {
