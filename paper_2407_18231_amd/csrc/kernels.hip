@@ -444,6 +444,94 @@ __global__ __launch_bounds__(256) void k_ls(const Batch b, Totals *t, const DevG
     if (!kFill && stats) atomicAdd(&t->cand[1], (unsigned long long)cand);
 }
 
+// Latency variant for small batches (a few events): a wave takes two
+// consecutive MDs; for each, 32 lanes take
+// one edge of the MD's module each (chunks of 32 for larger degrees) and test
+// the MDs of the edge's destination module.  Half-wave prefix sums give each
+// lane its place, so segments come out ordered by (inner MD, edge, outer MD),
+// which is (inner MD, outer MD) because edges are sorted by destination.
+constexpr uint32_t kLsLanes = 32;
+constexpr uint32_t kLsWaveMaxMd = 1u << 17;   // MD capacity up to which the latency variant runs
+
+__device__ inline uint32_t half_incl_scan(uint32_t v)
+{
+    const uint32_t w = threadIdx.x & (kLsLanes - 1);
+#pragma unroll
+    for (uint32_t d = 1; d < kLsLanes; d <<= 1) {
+        uint32_t t = __shfl_up(v, d, kLsLanes);
+        if (w >= d) v += t;
+    }
+    return v;
+}
+
+template <bool kFill>
+__global__ __launch_bounds__(256) void k_ls_wave(const Batch b, Totals *t, const DevGeom g, const Consts c,
+                                            int stats)
+{
+    const uint32_t n = min(t->n_md, b.cap_md);
+    const uint32_t n_mod = c.n_mod;
+    const bool bend = (c.flags & LST_FLAG_BEND) != 0u;
+    const uint32_t half = (threadIdx.x >> 5) & 1u, w = threadIdx.x & (kLsLanes - 1);
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
+    uint64_t cand = 0;
+    for (uint32_t a0 = 2 * wave; a0 < n; a0 += 2 * n_waves) {
+        const uint32_t a = a0 + half;
+        if (a >= n) continue;
+        const uint32_t u = b.md_u[a] & kUnitMask;
+        const uint32_t m = u % n_mod;
+        const uint32_t base = u - m;
+        const float4 pa = b.md_pos[a];
+        const float xa = pa.x, ya = pa.y, za = pa.z, ra = fabsf(pa.w), ba = b.md_beta[a];
+        const uint32_t e0 = g.edge_begin[m], e1 = g.edge_begin[m + 1];
+        uint32_t carry = kFill ? b.ls_off[a] : 0u;
+        for (uint32_t eb = e0; eb < e1; eb += kLsLanes) {
+            const uint32_t e = eb + w;
+            uint32_t bb = 0, be = 0;
+            LsClass kc;
+            if (e < e1) {
+                const uint2 ed = g.edge[e];
+                bb = min(b.md_off[base + ed.x], b.cap_md);
+                be = min(b.md_off[base + ed.x + 1], b.cap_md);
+                if (bb < be) kc = g.cls[ed.y];
+            }
+            // pass mask of this lane's candidates (up to 32; beyond, re-test)
+            uint32_t cnt = 0, mask = 0;
+            for (uint32_t q = bb; q < be; q++) {
+                const float4 pq = b.md_pos[q];
+                if (ls_cut(kc, c, bend, xa, ya, za, ra, ba, pq.x, pq.y, pq.z, fabsf(pq.w))) {
+                    if (q - bb < 32u) mask |= 1u << (q - bb);
+                    cnt++;
+                }
+            }
+            if (!kFill) cand += be - bb;
+            const uint32_t incl = half_incl_scan(cnt);
+            const uint32_t tot = __shfl(incl, kLsLanes - 1, kLsLanes);
+            if (kFill) {
+                uint32_t k = carry + incl - cnt;
+                for (uint32_t q = bb; q < be; q++) {
+                    bool pass;
+                    if (q - bb < 32u) {
+                        pass = (mask >> (q - bb)) & 1u;
+                    } else {
+                        const float4 pq = b.md_pos[q];
+                        pass = ls_cut(kc, c, bend, xa, ya, za, ra, ba, pq.x, pq.y, pq.z, fabsf(pq.w));
+                    }
+                    if (!pass) continue;
+                    if (k < b.cap_ls) {
+                        b.ls_a[k] = a;
+                        b.ls_b[k] = q;
+                    }
+                    k++;
+                }
+            }
+            carry += tot;
+        }
+        if (!kFill && w == 0) b.ls_cnt[a] = carry;
+    }
+    if (!kFill && stats) atomicAdd(&t->cand[1], (unsigned long long)cand);
+}
+
 // ------------------------------------------------------------ a4: T3 ----
 
 struct Anchor {
@@ -1070,9 +1158,16 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     L.launch("md_fill", k_md<true>, gmd, blk, b, t, g, c, 0);
     L.launch("md_units", k_md_units, grid_for((uint64_t)b.cap_ev * n_mod + 1), blk, b, (const Totals *)t);
     // a3: line segments over the connection map
-    L.launch("ls_count", k_ls<false>, grid_for(b.cap_md), blk, b, t, g, c, stats);
-    L.scan(b.ls_cnt, b.ls_off, &t->n_md, b.cap_md, &t->n_ls, "scan_ls");
-    L.launch("ls_fill", k_ls<true>, grid_for(b.cap_md), blk, b, t, g, c, 0);
+    // small batches: 32 lanes per MD for latency; large ones: a thread per MD
+    if (b.cap_md <= kLsWaveMaxMd) {
+        L.launch("ls_count", k_ls_wave<false>, grid_for(32ull * b.cap_md), blk, b, t, g, c, stats);
+        L.scan(b.ls_cnt, b.ls_off, &t->n_md, b.cap_md, &t->n_ls, "scan_ls");
+        L.launch("ls_fill", k_ls_wave<true>, grid_for(32ull * b.cap_md), blk, b, t, g, c, 0);
+    } else {
+        L.launch("ls_count", k_ls<false>, grid_for(b.cap_md), blk, b, t, g, c, stats);
+        L.scan(b.ls_cnt, b.ls_off, &t->n_md, b.cap_md, &t->n_ls, "scan_ls");
+        L.launch("ls_fill", k_ls<true>, grid_for(b.cap_md), blk, b, t, g, c, 0);
+    }
     // a4: T3
     L.launch("t3_count", k_t3<false>, grid_for(b.cap_ls), blk, b, t, c, stats);
     L.scan(b.t3_cnt, b.t3_off, &t->n_ls, b.cap_ls, &t->n_t3, "scan_t3");
