@@ -35,29 +35,60 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# Algorithmic bytes per unit of work of each kernel (what the method must move
-# at least once per launch; re-reads that a kernel serves from cache are not
-# counted).  Sizes: hit 17 B in (x, y, z, module, sensor), sorted hit 20 B,
-# MD anchor 24 B (x, y, z, r, beta, unit), MD record 32 B, pair 8 B.
-def algorithmic_bytes(name: str, c: dict, n_hits: int, n_pls: int, n_units: int, n_edges_used: int) -> float:
-    if name == "ls_count":
-        # every MD's anchor once, the MD ranges of the (event, module) units,
-        # the edges leaving modules that hold MDs and one count per MD
-        return 24.0 * c["md"] + 4.0 * n_units + 8.0 * n_edges_used + 4.0 * c["md"]
-    if name == "ls_fill":
-        return 24.0 * c["md"] + 4.0 * n_units + 8.0 * n_edges_used + 4.0 * c["md"] + 8.0 * c["ls"]
-    if name in ("md_count", "md_fill"):
-        return 20.0 * n_hits + 8.0 * n_units + (32.0 * c["md"] if name == "md_fill" else 4.0 * n_units)
-    if name in ("t3_count", "t3_fill"):
-        out = 24.0 * c["t3"] if name == "t3_fill" else 4.0 * c["ls"]
-        return 8.0 * c["ls"] + 4.0 * c["md"] + 17.0 * c["md"] + out
-    if name in ("t5_count", "t5_fill"):
-        out = 16.0 * c["t5"] if name == "t5_fill" else 4.0 * c["t3"]
-        return 16.0 * c["t3"] + 4.0 * c["ls"] + 17.0 * c["md"] + out
-    if name in ("pt3_count", "pt3_fill", "pt5_count", "pt5_fill"):
-        obj = c["t3"] if name.startswith("pt3") else c["t5"]
-        return 80.0 * n_pls + 16.0 * obj + 17.0 * c["md"] + 4.0 * n_pls
-    return 0.0
+# Algorithmic bytes of one step, per kernel name: the per-unit figures of the
+# method (hit 17 B in / 20 B sorted, MD anchor 20 B, index pair 8 B, seed
+# 80 B, candidate 24 B) times the units of this batch.  Candidates are what
+# each stage examines; S_B is the number of outer-MD gathers one pass over the
+# connection map needs (per edge leaving a module that holds MDs, the MDs of
+# its destination), E_used the number of such edges.
+def step_bytes(c: dict, n_hits: int, n_pls: int, n_units: int, s_b: int, e_used: int) -> dict:
+    nmd, nls, nt3, nt5 = c["md"], c["ls"], c["t3"], c["t5"]
+    ls = 20.0 * nmd + 20.0 * s_b + 6.0 * e_used + 4.0 * nmd
+    t3 = 8.0 * nls + 8.0 * nmd + 24.0 * c["cand_t3"]
+    t5 = 8.0 * nt3 + 8.0 * nmd + 24.0 * c["cand_t5"]
+    pt = 80.0 * n_pls * 2 + 24.0 * (c["cand_pt3"] + c["cand_pt5"])
+    return {
+        "hit_hist": 17.0 * n_hits + 8.0 * n_hits,
+        "hit_scatter": 25.0 * n_hits + 16.0 * n_hits,
+        "hit_gather": 16.0 * n_hits + 24.0 * n_hits,
+        "md_count": 16.0 * n_hits + 12.0 * n_units + 4.0 * n_hits,
+        "md_fill": 16.0 * n_hits + 12.0 * n_units + 28.0 * nmd,
+        "ls_count": ls,
+        "ls_fill": ls + 8.0 * nls,
+        "t3_count": t3 + 4.0 * nls,
+        "t3_fill": t3 + 8.0 * nt3 + 16.0 * nt3,
+        "t5_count": t5 + 4.0 * nt3,
+        "t5_fill": t5 + 16.0 * nt5,
+        "ptc_count": pt,
+        "ptc_fill": pt + 8.0 * (c["pt3"] + c["pt5"]),
+    }
+
+
+def outer_gathers(events, results, begin, dst):
+    """S_B and E_used of the batch from the MD lists the chain returned."""
+    src = np.repeat(np.arange(begin.size - 1), np.diff(begin))
+    s_b = e_used = 0
+    for ev, r in zip(events, results):
+        n = np.bincount(ev["module"][r["md"][:, 0]], minlength=begin.size - 1) if len(r["md"]) else \
+            np.zeros(begin.size - 1, np.int64)
+        has = n[src] > 0
+        s_b += int(n[dst][has].sum())
+        e_used += int(has.sum())
+    return s_b, e_used
+
+
+def traffic_of(kernel: str):
+    """HBM bytes per launch measured with rocprofv3 counters (FETCH_SIZE,
+    WRITE_SIZE, each scaled by what the counter reads for a plain copy of
+    known size), stored beside the profile summaries; null when absent."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    v = t.get("kernels", {}).get(kernel)
+    return None if v is None else v.get("bytes_per_launch")
 
 
 def cpu_baseline(n_events: int, budget_s: float):
@@ -174,16 +205,19 @@ def main():
     # dominant kernel and its roofline
     per = {k: v[0] / max(v[1], 1) for k, v in ktimes.items()}
     step_ms = {k: v[0] / args.steps for k, v in ktimes.items()}
+    launches = {k: v[1] / args.steps for k, v in ktimes.items()}
     dom = max(step_ms, key=step_ms.get)
-    md_units = B * g.n_mod
-    # edges leaving modules that hold at least one MD: count from the map
-    edges_used = float(np.diff(begin).mean()) * min(counts["md"], md_units)
-    alg = algorithmic_bytes(dom, counts, n_hits, n_pls, md_units, int(edges_used))
+    s_b, e_used = outer_gathers(events, ctx.batch_download(B), begin, dst)
+    sb = step_bytes(counts, n_hits, n_pls, B * g.n_mod, s_b, e_used)
+    alg = sb.get(dom, 0.0) / max(launches[dom], 1.0)     # per launch
     avg_ms = per[dom]
     achieved = alg / (avg_ms * 1e-3) / 1e9 if alg else 0.0
     roofline = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                    avg_launch_ms=round(avg_ms, 4), algorithmic_bytes=int(alg))
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic_of(dom),
+                    avg_launch_ms=round(avg_ms, 4), algorithmic_bytes_per_launch=int(alg))
+    effective = {k: round(sb[k] / max(launches[k], 1.0) / (per[k] * 1e-3) / 1e9, 1)
+                 for k in sb if k in per and per[k] > 0}
+    log("effective GB/s by kernel:", effective)
     stages = {k: round(v, 4) for k, v in sorted(step_ms.items(), key=lambda kv: -kv[1])}
     log("ms per step by kernel:", stages)
 
@@ -196,7 +230,7 @@ def main():
                               events_per_step=B, pileup=200, modules=g.n_mod,
                               hits_per_event=round(n_hits / B, 1), seeds_per_event=round(n_pls / B, 1)),
                   batched_graph_events_per_s=round(graph_rate, 2),
-                  roofline=roofline, kernel_ms_per_step=stages,
+                  roofline=roofline, kernel_ms_per_step=stages, effective_gbs_by_kernel=effective,
                   objects_per_event={k: round(counts[k] / B, 1) for k in ("md", "ls", "t3", "t5", "pt3", "pt5", "tc")})
 
     if not args.quick:

@@ -106,10 +106,12 @@ void carve_work(Carver &cv, Batch &b, uint32_t n_mod, uint32_t n_surf, uint32_t 
     b.ls_off = cv.take<uint32_t>((size_t)b.cap_md + 1);
     b.ls_a = cv.take<uint32_t>(b.cap_ls);
     b.ls_b = cv.take<uint32_t>(b.cap_ls);
+    b.ls_keep = cv.take<uint32_t>((size_t)b.cap_md * kKeepLs);
     b.t3_cnt = cv.take<uint32_t>((size_t)b.cap_ls + 1);
     b.t3_off = cv.take<uint32_t>((size_t)b.cap_ls + 1);
     b.t3_l1 = cv.take<uint32_t>(b.cap_t3);
     b.t3_l2 = cv.take<uint32_t>(b.cap_t3);
+    b.t3_keep = cv.take<uint32_t>((size_t)b.cap_ls * kKeepT3);
     b.t3_ac = cv.take<uint2>(b.cap_t3);
     b.t3_ks = cv.take<float2>(b.cap_t3);
     b.t5_cnt = cv.take<uint32_t>((size_t)b.cap_t3 + 1);
@@ -142,6 +144,8 @@ void carve_work(Carver &cv, Batch &b, uint32_t n_mod, uint32_t n_surf, uint32_t 
     b.ptc5_o = cv.take<uint32_t>(b.cap_ptc5);
     b.pt5_keep = cv.take<uint32_t>((size_t)b.cap_ptc5 + 1);
     b.pt5_koff = cv.take<uint32_t>((size_t)b.cap_ptc5 + 1);
+    b.ptc3_keep = cv.take<uint32_t>(pt_units * kKeepPt);
+    b.ptc5_keep = cv.take<uint32_t>(pt_units * kKeepPt);
     b.pt3_p = cv.take<uint32_t>(b.cap_pt3);
     b.pt3_o = cv.take<uint32_t>(b.cap_pt3);
     b.pt5_p = cv.take<uint32_t>(b.cap_pt5);
@@ -169,6 +173,8 @@ struct Slot {
     uint32_t *d_part = nullptr;
     char *h_stage = nullptr;
     size_t stage_bytes = 0;
+    char *h_out = nullptr;              // pinned landing buffer of the results
+    size_t out_bytes = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     bool graph_valid = false;
@@ -256,7 +262,8 @@ void free_slot_arenas(Slot &s)
     if (s.in_arena) { (void)hipFree(s.in_arena); s.in_arena = nullptr; }
     if (s.work_arena) { (void)hipFree(s.work_arena); s.work_arena = nullptr; }
     if (s.h_stage) { (void)hipHostFree(s.h_stage); s.h_stage = nullptr; }
-    s.in_bytes = s.work_bytes = s.stage_bytes = 0;
+    if (s.h_out) { (void)hipHostFree(s.h_out); s.h_out = nullptr; }
+    s.in_bytes = s.work_bytes = s.stage_bytes = s.out_bytes = 0;
 }
 
 void destroy_slot(Slot &s)
@@ -516,38 +523,42 @@ lst_status run_staged(lst_ctx *ctx, Slot &s, bool use_graph, bool timing, bool s
 }
 
 // Copy the results of the staged batch to host memory, one output per event.
+// Copy the results of the staged batch to host memory, one output per event:
+// one pinned landing buffer per slot, then per-event assembly (on several
+// host threads for larger batches).
 lst_status download(lst_ctx *ctx, Slot &s, lst_event_out **outs)
 {
     const uint32_t n = s.n_ev;
     const lst::Totals &t = *s.h_tot;
     const Batch &b = s.b;
-    std::vector<uint32_t> tab((size_t)(n + 1) * lst::kEvTabCols);
-    HIP_TRY(hipMemcpyAsync(tab.data(), b.ev_tab, tab.size() * 4, hipMemcpyDeviceToHost, s.stream));
     const uint32_t nmd = t.n_md, nls = t.n_ls, nt3 = t.n_t3, nt5 = t.n_t5, np3 = t.n_pt3, np5 = t.n_pt5, ntc = t.n_tc;
-    std::vector<uint32_t> hlo(nmd), hup(nmd), la(nls), lb(nls), u1(nt3), u2(nt3), w1(nt5), w2(nt5);
-    std::vector<uint32_t> p3(np3), o3(np3), p5(np5), o5(np5), tty(ntc), tix(ntc);
-    std::vector<float2> k3(nt3);
-    auto get = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
-        if (!bytes) return hipSuccess;
-        return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s.stream);
-    };
-    HIP_TRY(get(hlo.data(), b.md_hlo, nmd * 4ull));
-    HIP_TRY(get(hup.data(), b.md_hup, nmd * 4ull));
-    HIP_TRY(get(la.data(), b.ls_a, nls * 4ull));
-    HIP_TRY(get(lb.data(), b.ls_b, nls * 4ull));
-    HIP_TRY(get(u1.data(), b.t3_l1, nt3 * 4ull));
-    HIP_TRY(get(u2.data(), b.t3_l2, nt3 * 4ull));
-    HIP_TRY(get(k3.data(), b.t3_ks, nt3 * 8ull));
-    HIP_TRY(get(w1.data(), b.t5_u, nt5 * 4ull));
-    HIP_TRY(get(w2.data(), b.t5_w, nt5 * 4ull));
-    HIP_TRY(get(p3.data(), b.pt3_p, np3 * 4ull));
-    HIP_TRY(get(o3.data(), b.pt3_o, np3 * 4ull));
-    HIP_TRY(get(p5.data(), b.pt5_p, np5 * 4ull));
-    HIP_TRY(get(o5.data(), b.pt5_o, np5 * 4ull));
-    HIP_TRY(get(tty.data(), b.tc_type, ntc * 4ull));
-    HIP_TRY(get(tix.data(), b.tc_idx, ntc * 4ull));
+    struct Part { const void *src; size_t bytes; size_t at; };
+    Part parts[] = {{b.ev_tab, (size_t)(n + 1) * lst::kEvTabCols * 4, 0},
+                    {b.md_hlo, nmd * 4ull, 0}, {b.md_hup, nmd * 4ull, 0},
+                    {b.ls_a, nls * 4ull, 0}, {b.ls_b, nls * 4ull, 0},
+                    {b.t3_l1, nt3 * 4ull, 0}, {b.t3_l2, nt3 * 4ull, 0}, {b.t3_ks, nt3 * 8ull, 0},
+                    {b.t5_u, nt5 * 4ull, 0}, {b.t5_w, nt5 * 4ull, 0},
+                    {b.pt3_p, np3 * 4ull, 0}, {b.pt3_o, np3 * 4ull, 0},
+                    {b.pt5_p, np5 * 4ull, 0}, {b.pt5_o, np5 * 4ull, 0},
+                    {b.tc_type, ntc * 4ull, 0}, {b.tc_idx, ntc * 4ull, 0}};
+    size_t total = 0;
+    for (Part &p : parts) { p.at = total; total += lst::align_up(p.bytes); }
+    if (total > s.out_bytes) {
+        if (s.h_out) { (void)hipHostFree(s.h_out); s.h_out = nullptr; s.out_bytes = 0; }
+        size_t want = total + total / 4;
+        HIP_TRY(hipHostMalloc((void **)&s.h_out, want, hipHostMallocDefault));
+        s.out_bytes = want;
+    }
+    for (const Part &p : parts)
+        if (p.bytes) HIP_TRY(hipMemcpyAsync(s.h_out + p.at, p.src, p.bytes, hipMemcpyDeviceToHost, s.stream));
     HIP_TRY(hipStreamSynchronize(s.stream));
-    for (uint32_t e = 0; e < n; e++) {
+    auto arr = [&](int i) { return (const uint32_t *)(s.h_out + parts[i].at); };
+    const uint32_t *tab = arr(0), *hlo = arr(1), *hup = arr(2), *la = arr(3), *lb = arr(4), *u1 = arr(5);
+    const uint32_t *u2 = arr(6), *w1 = arr(8), *w2 = arr(9), *p3 = arr(10), *o3 = arr(11), *p5 = arr(12);
+    const uint32_t *o5 = arr(13), *tty = arr(14), *tix = arr(15);
+    const float2 *k3 = (const float2 *)(s.h_out + parts[7].at);
+    std::vector<int> failed(n, 0);
+    auto build = [&](uint32_t e) {
         const uint32_t *r0 = &tab[(size_t)e * lst::kEvTabCols], *r1 = r0 + lst::kEvTabCols;
         const uint32_t pls0 = r0[1], md0 = r0[2], ls0 = r0[3], t30 = r0[4], t50 = r0[5], p30 = r0[6], p50 = r0[7];
         const uint32_t cmd = r1[2] - md0, cls = r1[3] - ls0, ct3 = r1[4] - t30, ct5 = r1[5] - t50;
@@ -557,7 +568,7 @@ lst_status download(lst_ctx *ctx, Slot &s, lst_event_out **outs)
         size_t words = 2ull * (cmd + cls + ct3 + ct5 + cp3 + cp5 + ctc) + ct3;
         size_t bytes = sizeof(lst_event_out) + 4 * words + 64;
         char *mem = (char *)std::malloc(bytes);
-        if (!mem) return set_err(ctx, LST_ERR_OOM, "host allocation of outputs failed");
+        if (!mem) { failed[e] = 1; return; }
         lst_event_out *o = (lst_event_out *)mem;
         std::memset(o, 0, sizeof *o);
         uint32_t *w = (uint32_t *)(mem + sizeof(lst_event_out));
@@ -586,7 +597,18 @@ lst_status download(lst_ctx *ctx, Slot &s, lst_event_out **outs)
         for (uint32_t i = r0[10]; i < r1[10]; i++) { o->tc[2 * k] = tty[i]; o->tc[2 * k + 1] = tix[i] - pls0; k++; }
         o->status = LST_OK;
         outs[e] = o;
+    };
+    const uint32_t n_threads = std::min<uint32_t>(n >= 4 ? 8u : 1u, n);
+    if (n_threads <= 1) {
+        for (uint32_t e = 0; e < n; e++) build(e);
+    } else {
+        std::vector<std::thread> pool;
+        for (uint32_t w = 0; w < n_threads; w++)
+            pool.emplace_back([&, w] { for (uint32_t e = w; e < n; e += n_threads) build(e); });
+        for (auto &th : pool) th.join();
     }
+    for (uint32_t e = 0; e < n; e++)
+        if (failed[e]) return set_err(ctx, LST_ERR_OOM, "host allocation of outputs failed");
     return LST_OK;
 }
 
@@ -618,8 +640,8 @@ uint64_t predict_footprint(uint64_t hits, uint64_t pls, const lst::Consts &k)
     lst::Caps c = lst::plan_caps(1, hits, pls);
     uint64_t b = 0;
     b += 73ull * c.hits + 80ull * c.pls + 24ull * k.n_mod;
-    b += 40ull * c.md + 16ull * c.ls + 52ull * c.t3 + 36ull * c.t5;
-    b += 8ull * (c.pt3 + c.pt5) + 32ull * c.pls * k.n_surf + 3ull * c.pls + 16ull * (c.pt3 + c.t5 + c.pls);
+    b += (40ull + 4ull * lst::kKeepLs) * c.md + (16ull + 4ull * lst::kKeepT3) * c.ls + 52ull * c.t3 + 36ull * c.t5;
+    b += 8ull * (c.pt3 + c.pt5) + (32ull + 8ull * lst::kKeepPt) * c.pls * k.n_surf + 3ull * c.pls + 16ull * (c.pt3 + c.t5 + c.pls);
     b += 16ull * (c.ptc3 + c.ptc5);
     b += 2ull * 8ull * k.n_surf * k.nphi * (3 * k.nkb + 1);
     return b;

@@ -20,6 +20,9 @@ constexpr uint32_t kErrNonFinite = 2u;
 constexpr int kScanGrid = 256;
 constexpr unsigned kMaxGrid = 2048;
 constexpr int kEvTabCols = 12;
+// survivors a count pass records per unit, so that the fill pass copies them
+// instead of walking the candidates again (units with more walk again)
+constexpr uint32_t kKeepLs = 8, kKeepT3 = 2, kKeepPt = 8;
 
 // Device copy of the geometry (read-only).
 struct DevGeom {
@@ -71,9 +74,11 @@ struct Batch {
     // a3: line segments
     uint32_t *ls_cnt, *ls_off;          // per inner MD
     uint32_t *ls_a, *ls_b;
+    uint32_t *ls_keep;                  // kKeepLs outer MDs per inner MD
     // a4: T3
     uint32_t *t3_cnt, *t3_off;          // per inner LS
     uint32_t *t3_l1, *t3_l2;
+    uint32_t *t3_keep;                  // kKeepT3 outer LSs per inner LS
     uint2 *t3_ac;                       // inner and outer MD
     float2 *t3_ks;                      // curvature and its resolution
     // a5: T5
@@ -94,6 +99,7 @@ struct Batch {
     // and the pT3 / pT5 lists (seed, object)
     uint32_t *ptc3_cnt, *ptc3_off, *ptc3_p, *ptc3_o, *pt3_keep, *pt3_koff;
     uint32_t *ptc5_cnt, *ptc5_off, *ptc5_p, *ptc5_o, *pt5_keep, *pt5_koff;
+    uint32_t *ptc3_keep, *ptc5_keep;    // kKeepPt objects per (seed, surface)
     uint32_t *pt3_p, *pt3_o;
     uint32_t *pt5_p, *pt5_o;
     // a8: track candidates over [pT3 | T5 | pLS]

@@ -425,14 +425,28 @@ __global__ __launch_bounds__(256) void k_ls(const Batch b, Totals *t, const DevG
     const bool bend = (c.flags & LST_FLAG_BEND) != 0u;
     uint64_t cand = 0;
     GRID_STRIDE(a, n) {
+        uint32_t k = kFill ? b.ls_off[a] : 0u;
+        if (kFill) {
+            // the count pass kept the first kKeepLs outer MDs
+            const uint32_t cnt = b.ls_off[a + 1] - k;
+            if (cnt <= kKeepLs) {
+                for (uint32_t i = 0; i < cnt; i++) {
+                    if (k + i < b.cap_ls) {
+                        b.ls_a[k + i] = a;
+                        b.ls_b[k + i] = b.ls_keep[(size_t)a * kKeepLs + i];
+                    }
+                }
+                continue;
+            }
+        }
         const uint32_t u = b.md_u[a] & kUnitMask;
         const uint32_t m = u % n_mod;
         const float4 pa = b.md_pos[a];
         const float ba = b.md_beta[a];
-        uint32_t k = kFill ? b.ls_off[a] : 0u;
         ls_walk(b, g, c, bend, m, u - m, pa, ba, [&](uint32_t q, bool pass) {
             if (!kFill) cand++;
             if (!pass) return;
+            if (!kFill && k < kKeepLs) b.ls_keep[(size_t)a * kKeepLs + k] = q;
             if (kFill && k < b.cap_ls) {
                 b.ls_a[k] = a;
                 b.ls_b[k] = q;
@@ -485,6 +499,16 @@ __global__ __launch_bounds__(256) void k_ls_wave(const Batch b, Totals *t, const
         const float xa = pa.x, ya = pa.y, za = pa.z, ra = fabsf(pa.w), ba = b.md_beta[a];
         const uint32_t e0 = g.edge_begin[m], e1 = g.edge_begin[m + 1];
         uint32_t carry = kFill ? b.ls_off[a] : 0u;
+        if (kFill) {
+            const uint32_t cnt_a = b.ls_off[a + 1] - carry;
+            if (cnt_a <= kKeepLs) {
+                if (w < cnt_a && carry + w < b.cap_ls) {
+                    b.ls_a[carry + w] = a;
+                    b.ls_b[carry + w] = b.ls_keep[(size_t)a * kKeepLs + w];
+                }
+                continue;
+            }
+        }
         for (uint32_t eb = e0; eb < e1; eb += kLsLanes) {
             const uint32_t e = eb + w;
             uint32_t bb = 0, be = 0;
@@ -507,6 +531,20 @@ __global__ __launch_bounds__(256) void k_ls_wave(const Batch b, Totals *t, const
             if (!kFill) cand += be - bb;
             const uint32_t incl = half_incl_scan(cnt);
             const uint32_t tot = __shfl(incl, kLsLanes - 1, kLsLanes);
+            if (!kFill && carry + incl - cnt < kKeepLs) {
+                // record this lane's survivors among the MD's first kKeepLs
+                uint32_t k = carry + incl - cnt;
+                for (uint32_t q = bb; q < be && k < kKeepLs; q++) {
+                    bool pass;
+                    if (q - bb < 32u) {
+                        pass = (mask >> (q - bb)) & 1u;
+                    } else {
+                        const float4 pq = b.md_pos[q];
+                        pass = ls_cut(kc, c, bend, xa, ya, za, ra, ba, pq.x, pq.y, pq.z, fabsf(pq.w));
+                    }
+                    if (pass) b.ls_keep[(size_t)a * kKeepLs + k++] = q;
+                }
+            }
             if (kFill) {
                 uint32_t k = carry + incl - cnt;
                 for (uint32_t q = bb; q < be; q++) {
@@ -592,9 +630,29 @@ __global__ __launch_bounds__(256) void k_t3(const Batch b, Totals *t, const Cons
     const uint32_t n = min(t->n_ls, b.cap_ls);
     uint64_t cand = 0;
     GRID_STRIDE(l1, n) {
-        const uint32_t ia = b.ls_a[l1], ib = b.ls_b[l1];
-        const uint32_t q0 = min(b.ls_off[ib], b.cap_ls), q1 = min(b.ls_off[ib + 1], b.cap_ls);
         uint32_t k = kFill ? b.t3_off[l1] : 0u;
+        const uint32_t cnt = kFill ? b.t3_off[l1 + 1] - k : 0u;
+        if (kFill && cnt == 0) continue;
+        const uint32_t ia = b.ls_a[l1], ib = b.ls_b[l1];
+        if (kFill && cnt <= kKeepT3) {
+            // the count pass kept the outer LSs of this T3 list
+            const Anchor A = load_anchor(b, ia), B = load_anchor(b, ib);
+            for (uint32_t i = 0; i < cnt; i++) {
+                const uint32_t l2 = b.t3_keep[(size_t)l1 * kKeepT3 + i];
+                const uint32_t ic = b.ls_b[l2];
+                const Anchor C = load_anchor(b, ic);
+                float kap, sk, d1, d2;
+                kappa3(c, A, B, C, kap, sk, d1, d2);
+                if (k + i < b.cap_t3) {
+                    b.t3_l1[k + i] = l1;
+                    b.t3_l2[k + i] = l2;
+                    b.t3_ac[k + i] = make_uint2(ia, ic);
+                    b.t3_ks[k + i] = make_float2(kap, sk);
+                }
+            }
+            continue;
+        }
+        const uint32_t q0 = min(b.ls_off[ib], b.cap_ls), q1 = min(b.ls_off[ib + 1], b.cap_ls);
         if (q0 == q1) {
             if (!kFill) b.t3_cnt[l1] = 0;
             continue;
@@ -608,6 +666,7 @@ __global__ __launch_bounds__(256) void k_t3(const Batch b, Totals *t, const Cons
             kappa3(c, A, B, C, kap, sk, d1, d2);
             if (!(fabsf(kap) <= c.kmaxf + c.ns * sk)) continue;
             if (!rz3(c, A, B, C, d1, d2)) continue;
+            if (!kFill && k < kKeepT3) b.t3_keep[(size_t)l1 * kKeepT3 + k] = l2;
             if (kFill && k < b.cap_t3) {
                 b.t3_l1[k] = l1;
                 b.t3_l2[k] = l2;
@@ -915,8 +974,23 @@ __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Con
     const uint32_t cap = kKind == 0 ? b.cap_ptc3 : b.cap_ptc5;
     const uint32_t per_row = 3u * c.nkb + 1u;
     uint64_t cand = 0;
+    uint32_t *keep = kKind == 0 ? b.ptc3_keep : b.ptc5_keep;
     GRID_STRIDE(unit, n) {
         uint32_t k = kFill ? off[unit] : 0u;
+        if (kFill) {
+            // the count pass kept the first kKeepPt objects of this unit
+            const uint32_t cnt = off[unit + 1] - k;
+            if (cnt <= kKeepPt) {
+                const uint32_t p = unit / c.n_surf;
+                for (uint32_t i = 0; i < cnt; i++) {
+                    if (k + i < cap) {
+                        out_p[k + i] = p;
+                        out_o[k + i] = keep[(size_t)unit * kKeepPt + i];
+                    }
+                }
+                continue;
+            }
+        }
         const uint4 r = b.road[unit];
         if (r.z & 0x80000000u) {
             const uint32_t p = unit / c.n_surf, sfi = unit - p * c.n_surf;
@@ -941,6 +1015,7 @@ __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Con
                         const float2 ks = bks[i];
                         if (!kFill) cand++;
                         if (!(fabs(kp - (double)ks.x) <= c.n_sigma * (skp + (double)ks.y))) continue;
+                        if (!kFill && k < kKeepPt) keep[(size_t)unit * kKeepPt + k] = bk_items[i];
                         if (kFill && k < cap) {
                             out_p[k] = p;
                             out_o[k] = bk_items[i];

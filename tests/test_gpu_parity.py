@@ -215,3 +215,20 @@ def test_regrow_after_overflow(geo):
         r_ref = c.run_event(big)
     for k in STAGES:
         assert np.array_equal(r_big[k], r_ref[k]), k
+
+
+def test_full_batch_sampled_parity(ctx, geo):
+    """The benchmark's launch: 64 PU200-like events in one batch.  Sampled
+    events match the oracle; every event matches its own per-event run."""
+    g = geo["pu200"]
+    evs = [s.gen_event(g, s.config_pu(200), s.event_seed(2, i)) for i in range(64)]
+    with lst.Context(max_batch=64) as c:
+        c.load_geometry(g)
+        batch = c.run_batch(evs)
+    for i in (0, 63):
+        check_canonical(batch[i], evs[i])
+        check_parity(g, evs[i], batch[i])
+    for i in range(0, 64, 9):
+        r1 = ctx.run_event(evs[i])
+        for k in STAGES:
+            assert np.array_equal(r1[k], batch[i][k]), (i, k)
