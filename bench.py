@@ -40,14 +40,17 @@ def log(*a):
 # 80 B, candidate 24 B) times the units of this batch.  Candidates are what
 # each stage examines; S_B is the number of outer-MD gathers one pass over the
 # connection map needs (per edge leaving a module that holds MDs, the MDs of
-# its destination), E_used the number of such edges.
+# its destination), E_used the number of such edges.  The seed lookup walks
+# bucket entries of 12 B (curvature, its resolution, anchor azimuth) and
+# writes (seed, object) pairs of 8 B; the full seed cuts read each seed
+# (80 B) once and, per pair, the pair, the object's anchors (2 x 20 B plus
+# curvature 8 B) and write a 4 B verdict.
 def step_bytes(c: dict, n_hits: int, n_pls: int, n_units: int, s_b: int, e_used: int) -> dict:
     nmd, nls, nt3, nt5 = c["md"], c["ls"], c["t3"], c["t5"]
     ls = 20.0 * nmd + 20.0 * s_b + 6.0 * e_used + 4.0 * nmd
     t3 = 8.0 * nls + 8.0 * nmd + 24.0 * c["cand_t3"]
     t5 = 8.0 * nt3 + 8.0 * nmd + 24.0 * c["cand_t5"]
-    pt = 80.0 * n_pls * 2 + 24.0 * (c["cand_pt3"] + c["cand_pt5"])
-    return {
+    out = {
         "hit_hist": 17.0 * n_hits + 8.0 * n_hits,
         "hit_scatter": 25.0 * n_hits + 16.0 * n_hits,
         "hit_gather": 16.0 * n_hits + 24.0 * n_hits,
@@ -59,9 +62,13 @@ def step_bytes(c: dict, n_hits: int, n_pls: int, n_units: int, s_b: int, e_used:
         "t3_fill": t3 + 8.0 * nt3 + 16.0 * nt3,
         "t5_count": t5 + 4.0 * nt3,
         "t5_fill": t5 + 16.0 * nt5,
-        "ptc_count": pt,
-        "ptc_fill": pt + 8.0 * (c["pt3"] + c["pt5"]),
     }
+    for k in ("3", "5"):
+        walk = 80.0 * n_pls + 12.0 * c["cand_pt" + k]
+        out[f"pt{k}c_count"] = walk + 4.0 * c["eval_pt" + k]
+        out[f"pt{k}c_fill"] = 12.0 * c["eval_pt" + k]
+        out[f"pt{k}_eval"] = 80.0 * n_pls + (8.0 + 48.0 + 4.0) * c["eval_pt" + k]
+    return out
 
 
 def outer_gathers(events, results, begin, dst):

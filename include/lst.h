@@ -190,9 +190,10 @@ lst_status lst_kernel_times(lst_ctx *ctx, const char **names, double *total_ms,
                             uint32_t *launches, uint32_t *n);
 lst_status lst_batch_download(lst_ctx *ctx, lst_event_out **outs);
 /* Object totals of the last execute over the whole batch: md, ls, t3, t5,
- * pt3, pt5, tc, and candidate counts of the md, ls, t3, t5, pt3 and pt5
- * stages (13 values). */
-lst_status lst_batch_counts(lst_ctx *ctx, uint64_t counts[13]);
+ * pt3, pt5, tc; candidates examined by the md, ls, t3, t5, pt3 and pt5
+ * stages (for pt3 / pt5: bucket entries walked by the seed lookup); and the
+ * pt3 / pt5 candidates that reach the full seed cuts (15 values). */
+lst_status lst_batch_counts(lst_ctx *ctx, uint64_t counts[15]);
 
 void lst_free_output(lst_event_out *out);
 

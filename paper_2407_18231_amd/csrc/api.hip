@@ -124,14 +124,15 @@ void carve_work(Carver &cv, Batch &b, uint32_t n_mod, uint32_t n_surf, uint32_t 
     b.bk3_id = cv.take<uint32_t>(b.cap_t3);
     b.bk3_rank = cv.take<uint32_t>(b.cap_t3);
     b.bk3_items = cv.take<uint32_t>(b.cap_t3);
-    b.bk3_ks = cv.take<float2>(b.cap_t3);
+    b.bk3_ks = cv.take<float4>(b.cap_t3);
     b.bk5_cnt = cv.take<uint32_t>(bk + 1);
     b.bk5_off = cv.take<uint32_t>(bk + 1);
     b.bk5_id = cv.take<uint32_t>(b.cap_t5);
     b.bk5_rank = cv.take<uint32_t>(b.cap_t5);
     b.bk5_items = cv.take<uint32_t>(b.cap_t5);
-    b.bk5_ks = cv.take<float2>(b.cap_t5);
+    b.bk5_ks = cv.take<float4>(b.cap_t5);
     b.road = cv.take<uint4>(pt_units);
+    b.road_phi = cv.take<float2>(pt_units);
     b.ptc3_cnt = cv.take<uint32_t>(pt_units + 1);
     b.ptc3_off = cv.take<uint32_t>(pt_units + 1);
     b.ptc3_p = cv.take<uint32_t>(b.cap_ptc3);
@@ -640,8 +641,8 @@ uint64_t predict_footprint(uint64_t hits, uint64_t pls, const lst::Consts &k)
     lst::Caps c = lst::plan_caps(1, hits, pls);
     uint64_t b = 0;
     b += 73ull * c.hits + 80ull * c.pls + 24ull * k.n_mod;
-    b += (40ull + 4ull * lst::kKeepLs) * c.md + (16ull + 4ull * lst::kKeepT3) * c.ls + 52ull * c.t3 + 36ull * c.t5;
-    b += 8ull * (c.pt3 + c.pt5) + (32ull + 8ull * lst::kKeepPt) * c.pls * k.n_surf + 3ull * c.pls + 16ull * (c.pt3 + c.t5 + c.pls);
+    b += (40ull + 4ull * lst::kKeepLs) * c.md + (16ull + 4ull * lst::kKeepT3) * c.ls + 60ull * c.t3 + 44ull * c.t5;
+    b += 8ull * (c.pt3 + c.pt5) + (40ull + 8ull * lst::kKeepPt) * c.pls * k.n_surf + 3ull * c.pls + 16ull * (c.pt3 + c.t5 + c.pls);
     b += 16ull * (c.ptc3 + c.ptc5);
     b += 2ull * 8ull * k.n_surf * k.nphi * (3 * k.nkb + 1);
     return b;
@@ -1043,7 +1044,7 @@ lst_status lst_batch_download(lst_ctx *ctx, lst_event_out **outs)
     return download(ctx, *ctx->plain, outs);
 }
 
-lst_status lst_batch_counts(lst_ctx *ctx, uint64_t counts[13])
+lst_status lst_batch_counts(lst_ctx *ctx, uint64_t counts[15])
 {
     if (!ctx || !counts) return LST_ERR_INVALID_ARG;
     if (!ctx->plain || !ctx->plain->h_tot) return set_err(ctx, LST_ERR_INVALID_ARG, "no staged batch");
@@ -1056,8 +1057,9 @@ lst_status lst_batch_counts(lst_ctx *ctx, uint64_t counts[13])
     st = finish_run(ctx, s, true);
     if (st != LST_OK) return st;
     const lst::Totals &t = *s.h_tot;
-    const uint64_t v[13] = {t.n_md, t.n_ls, t.n_t3, t.n_t5, t.n_pt3, t.n_pt5, t.n_tc + t.n_pt5,
-                            t.cand[0], t.cand[1], t.cand[2], t.cand[3], t.cand[4], t.cand[5]};
+    const uint64_t v[15] = {t.n_md, t.n_ls, t.n_t3, t.n_t5, t.n_pt3, t.n_pt5, t.n_tc + t.n_pt5,
+                            t.cand[0], t.cand[1], t.cand[2], t.cand[3], t.cand[4], t.cand[5],
+                            t.n_ptc3, t.n_ptc5};
     std::memcpy(counts, v, sizeof v);
     return LST_OK;
 }

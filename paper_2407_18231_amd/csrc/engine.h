@@ -90,11 +90,12 @@ struct Batch {
     // objects with a wide curvature resolution
     uint32_t *bk3_cnt, *bk3_off, *bk3_id, *bk3_rank, *bk3_items;
     uint32_t *bk5_cnt, *bk5_off, *bk5_id, *bk5_rank, *bk5_items;
-    float2 *bk3_ks, *bk5_ks;            // curvature and resolution of each bucketed object
+    float4 *bk3_ks, *bk5_ks;            // (curvature, resolution, inner-anchor azimuth, 0) of each bucketed object
     // a7: road of each (seed, surface) unit: x = first azimuth bin | bin count
     // << 16; y, z = curvature bin ranges of the resolution classes (k0 | k1 << 8
     // per class, class 2 in z), valid << 31 in z
     uint4 *road;
+    float2 *road_phi;                   // azimuth window of the road: (start in [0, 2 pi), width)
     // seed-object candidates per (seed, surface) unit, their keep flags,
     // and the pT3 / pT5 lists (seed, object)
     uint32_t *ptc3_cnt, *ptc3_off, *ptc3_p, *ptc3_o, *pt3_keep, *pt3_koff;

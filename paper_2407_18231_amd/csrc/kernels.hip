@@ -795,12 +795,15 @@ __global__ void k_bucket_scatter(const Batch b, const Totals *t)
     const uint32_t *id = kKind == 0 ? b.bk3_id : b.bk5_id;
     const uint32_t *rank = kKind == 0 ? b.bk3_rank : b.bk5_rank;
     uint32_t *items = kKind == 0 ? b.bk3_items : b.bk5_items;
-    float2 *bks = kKind == 0 ? b.bk3_ks : b.bk5_ks;
+    float4 *bks = kKind == 0 ? b.bk3_ks : b.bk5_ks;
     const float2 *ks = kKind == 0 ? b.t3_ks : b.t5_ks;
     GRID_STRIDE(i, n) {
         const uint32_t pos = off[id[i]] + rank[i];
+        const uint32_t a = kKind == 0 ? b.t3_ac[i].x : b.t3_ac[b.t5_u[i]].x;
+        const float4 pa = b.md_pos[a];
+        const float2 k = ks[i];
         items[pos] = i;
-        bks[pos] = ks[i];
+        bks[pos] = make_float4(k.x, k.y, atan2f(pa.y, pa.x), 0.0f);
     }
 }
 
@@ -867,7 +870,7 @@ __device__ inline bool p_cut(const Consts &c, const Seed &s, float kobj, float s
 // linked to seed s; returns false when the helix band misses the surface.
 // Conservative bounds of the seed cuts over the surface's anchor radii.
 __device__ inline bool seed_road(const Consts &c, const Seed &s, const Surface &sf,
-                                 int &b0, int &b1)
+                                 int &b0, int &b1, double &plo, double &pwidth)
 {
     const double ns = c.n_sigma;
     const double ak = fabs(s.kp);
@@ -914,8 +917,13 @@ __device__ inline bool seed_road(const Consts &c, const Seed &s, const Surface &
     if (!(hi - lo < 2.0 * kPiD) || !(lo > -3.0 * kPiD) || !(hi < 4.0 * kPiD)) {
         b0 = 0;
         b1 = (int)c.nphi - 1;
+        plo = 0.0;
+        pwidth = 4.0 * kPiD;     // every azimuth
         return true;
     }
+    plo = fmod(lo, 2.0 * kPiD);
+    if (plo < 0.0) plo += 2.0 * kPiD;
+    pwidth = hi - lo;
     // lo, hi lie within [-3 pi, 4 pi] here
     const double scale = (double)c.nphi / (2.0 * kPiD);
     b0 = (int)floor((lo + kPiD) * scale);
@@ -934,10 +942,13 @@ __global__ __launch_bounds__(256) void k_road(const Batch b, const Totals *t, co
         const uint32_t p = unit / c.n_surf, sfi = unit - p * c.n_surf;
         const Surface sf = g.surf[sfi];
         uint4 r = make_uint4(0u, 0u, 0u, 0u);
+        float2 rp = make_float2(0.0f, 0.0f);
         int b0 = 0, b1 = -1;
+        double plo = 0.0, pwidth = 0.0;
         if (sf.kind <= 1u) {
             const Seed s = load_seed(b, c, p);
-            if (seed_road(c, s, sf, b0, b1)) {
+            if (seed_road(c, s, sf, b0, b1, plo, pwidth)) {
+                rp = make_float2((float)plo, (float)pwidth);
                 // objects of resolution class i: curvature within the seed's
                 // window widened by the class's largest resolution
                 uint32_t kr[3];
@@ -953,6 +964,7 @@ __global__ __launch_bounds__(256) void k_road(const Batch b, const Totals *t, co
             }
         }
         b.road[unit] = r;
+        b.road_phi[unit] = rp;
     }
 }
 
@@ -966,7 +978,7 @@ __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Con
     const uint32_t n_ev = t->n_ev;
     const uint32_t *bk_off = kKind == 0 ? b.bk3_off : b.bk5_off;
     const uint32_t *bk_items = kKind == 0 ? b.bk3_items : b.bk5_items;
-    const float2 *bks = kKind == 0 ? b.bk3_ks : b.bk5_ks;
+    const float4 *bks = kKind == 0 ? b.bk3_ks : b.bk5_ks;
     uint32_t *cnt = kKind == 0 ? b.ptc3_cnt : b.ptc5_cnt;
     const uint32_t *off = kKind == 0 ? b.ptc3_off : b.ptc5_off;
     uint32_t *out_p = kKind == 0 ? b.ptc3_p : b.ptc5_p;
@@ -1002,6 +1014,10 @@ __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Con
             const uint32_t row0 = (e * c.n_surf + sfi) * c.nphi;
             const uint32_t first = r.x & 0xFFFFu, nbins = r.x >> 16;
             const uint32_t kr[3] = {r.y & 0xFFFFu, r.y >> 16, r.z & 0xFFFFu};
+            // the road's azimuth window (padded): a cheap, conservative test of
+            // the inner anchor before the exact seed cuts
+            const float2 rp = b.road_phi[unit];
+            const float two_pi = 2.0f * kPiF;
             for (uint32_t j = 0; j < nbins; j++) {
                 uint32_t bin = first + j;
                 if (bin >= c.nphi) bin -= c.nphi;
@@ -1012,8 +1028,11 @@ __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Con
                     const uint32_t hi = part < 3 ? rb + part * c.nkb + (kr[part] >> 8) + 1u : rb + per_row;
                     const uint32_t i0 = bk_off[lo], i1 = bk_off[hi];
                     for (uint32_t i = i0; i < i1; i++) {
-                        const float2 ks = bks[i];
+                        const float4 ks = bks[i];
                         if (!kFill) cand++;
+                        float dphi = ks.z - rp.x;
+                        dphi -= two_pi * floorf(dphi / two_pi);
+                        if (!(dphi <= rp.y)) continue;
                         if (!(fabs(kp - (double)ks.x) <= c.n_sigma * (skp + (double)ks.y))) continue;
                         if (!kFill && k < kKeepPt) keep[(size_t)unit * kKeepPt + k] = bk_items[i];
                         if (kFill && k < cap) {
@@ -1265,14 +1284,14 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     // a7: pT3 / pT5: candidates, seed cuts, compaction, per-seed order
     const uint64_t cap_pu = (uint64_t)b.cap_pls * c.n_surf;
     L.launch("road", k_road, grid_for(cap_pu), blk, b, (const Totals *)t, g, c);
-    L.launch("ptc_count", k_ptc<0, false>, grid_for(cap_pu), blk, b, t, c, stats);
-    L.launch("ptc_count", k_ptc<1, false>, grid_for(cap_pu), blk, b, t, c, stats);
+    L.launch("pt3c_count", k_ptc<0, false>, grid_for(cap_pu), blk, b, t, c, stats);
+    L.launch("pt5c_count", k_ptc<1, false>, grid_for(cap_pu), blk, b, t, c, stats);
     L.scan(b.ptc3_cnt, b.ptc3_off, &t->n_pt_units, (uint32_t)cap_pu, &t->n_ptc3, "scan_pt");
     L.scan(b.ptc5_cnt, b.ptc5_off, &t->n_pt_units, (uint32_t)cap_pu, &t->n_ptc5, "scan_pt");
-    L.launch("ptc_fill", k_ptc<0, true>, grid_for(cap_pu), blk, b, t, c, 0);
-    L.launch("ptc_fill", k_ptc<1, true>, grid_for(cap_pu), blk, b, t, c, 0);
-    L.launch("pt_eval", k_pt_eval<0>, grid_for(b.cap_ptc3), blk, b, (const Totals *)t, c);
-    L.launch("pt_eval", k_pt_eval<1>, grid_for(b.cap_ptc5), blk, b, (const Totals *)t, c);
+    L.launch("pt3c_fill", k_ptc<0, true>, grid_for(cap_pu), blk, b, t, c, 0);
+    L.launch("pt5c_fill", k_ptc<1, true>, grid_for(cap_pu), blk, b, t, c, 0);
+    L.launch("pt3_eval", k_pt_eval<0>, grid_for(b.cap_ptc3), blk, b, (const Totals *)t, c);
+    L.launch("pt5_eval", k_pt_eval<1>, grid_for(b.cap_ptc5), blk, b, (const Totals *)t, c);
     L.scan(b.pt3_keep, b.pt3_koff, &t->n_ptc3, b.cap_ptc3, &t->n_pt3, "scan_pt");
     L.scan(b.pt5_keep, b.pt5_koff, &t->n_ptc5, b.cap_ptc5, &t->n_pt5, "scan_pt");
     L.launch("pt_compact", k_pt_compact<0>, grid_for(b.cap_ptc3), blk, b, (const Totals *)t);

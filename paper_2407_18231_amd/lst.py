@@ -320,10 +320,10 @@ class Context:
         return res
 
     def batch_counts(self) -> dict:
-        v = (C.c_uint64 * 13)()
+        v = (C.c_uint64 * 15)()
         self._check(self.L.lst_batch_counts(self.h, v))
         keys = ["md", "ls", "t3", "t5", "pt3", "pt5", "tc", "cand_md", "cand_ls", "cand_t3",
-                "cand_t5", "cand_pt3", "cand_pt5"]
+                "cand_t5", "cand_pt3", "cand_pt5", "eval_pt3", "eval_pt5"]
         return {k: int(x) for k, x in zip(keys, v)}
 
 
