@@ -123,13 +123,11 @@ void carve_work(Carver &cv, Batch &b, uint32_t n_mod, uint32_t n_surf, uint32_t 
     b.bk3_off = cv.take<uint32_t>(bk + 1);
     b.bk3_id = cv.take<uint32_t>(b.cap_t3);
     b.bk3_rank = cv.take<uint32_t>(b.cap_t3);
-    b.bk3_items = cv.take<uint32_t>(b.cap_t3);
     b.bk3_ks = cv.take<float4>(b.cap_t3);
     b.bk5_cnt = cv.take<uint32_t>(bk + 1);
     b.bk5_off = cv.take<uint32_t>(bk + 1);
     b.bk5_id = cv.take<uint32_t>(b.cap_t5);
     b.bk5_rank = cv.take<uint32_t>(b.cap_t5);
-    b.bk5_items = cv.take<uint32_t>(b.cap_t5);
     b.bk5_ks = cv.take<float4>(b.cap_t5);
     b.road = cv.take<uint4>(pt_units);
     b.road_phi = cv.take<float2>(pt_units);

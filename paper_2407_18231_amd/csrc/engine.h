@@ -88,9 +88,9 @@ struct Batch {
     // a6: seed lookup buckets of T3s / T5s by (event, surface, azimuth bin,
     // resolution class, curvature bin); the last bucket of a row holds the
     // objects with a wide curvature resolution
-    uint32_t *bk3_cnt, *bk3_off, *bk3_id, *bk3_rank, *bk3_items;
-    uint32_t *bk5_cnt, *bk5_off, *bk5_id, *bk5_rank, *bk5_items;
-    float4 *bk3_ks, *bk5_ks;            // (curvature, resolution, inner-anchor azimuth, 0) of each bucketed object
+    uint32_t *bk3_cnt, *bk3_off, *bk3_id, *bk3_rank;
+    uint32_t *bk5_cnt, *bk5_off, *bk5_id, *bk5_rank;
+    float4 *bk3_ks, *bk5_ks;            // (curvature, resolution, inner-anchor azimuth, object index bits)
     // a7: road of each (seed, surface) unit: x = first azimuth bin | bin count
     // << 16; y, z = curvature bin ranges of the resolution classes (k0 | k1 << 8
     // per class, class 2 in z), valid << 31 in z

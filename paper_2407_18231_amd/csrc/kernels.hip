@@ -794,7 +794,6 @@ __global__ void k_bucket_scatter(const Batch b, const Totals *t)
     const uint32_t *off = kKind == 0 ? b.bk3_off : b.bk5_off;
     const uint32_t *id = kKind == 0 ? b.bk3_id : b.bk5_id;
     const uint32_t *rank = kKind == 0 ? b.bk3_rank : b.bk5_rank;
-    uint32_t *items = kKind == 0 ? b.bk3_items : b.bk5_items;
     float4 *bks = kKind == 0 ? b.bk3_ks : b.bk5_ks;
     const float2 *ks = kKind == 0 ? b.t3_ks : b.t5_ks;
     GRID_STRIDE(i, n) {
@@ -802,8 +801,7 @@ __global__ void k_bucket_scatter(const Batch b, const Totals *t)
         const uint32_t a = kKind == 0 ? b.t3_ac[i].x : b.t3_ac[b.t5_u[i]].x;
         const float4 pa = b.md_pos[a];
         const float2 k = ks[i];
-        items[pos] = i;
-        bks[pos] = make_float4(k.x, k.y, atan2f(pa.y, pa.x), 0.0f);
+        bks[pos] = make_float4(k.x, k.y, atan2f(pa.y, pa.x), __uint_as_float(i));
     }
 }
 
@@ -811,6 +809,7 @@ __global__ void k_bucket_scatter(const Batch b, const Totals *t)
 
 struct Seed {
     double kp, skp, phi0, cot, z0, s11, s22, s44;
+    double cphi, sphi;       // cos and sin of phi0
 };
 
 __device__ inline Seed load_seed(const Batch &b, const Consts &c, uint32_t p)
@@ -826,40 +825,46 @@ __device__ inline Seed load_seed(const Batch &b, const Consts &c, uint32_t p)
     s.s11 = sqrt((double)cov[5]);
     s.s22 = sqrt((double)cov[9]);
     s.s44 = sqrt((double)cov[14]);
+    sincos(s.phi0, &s.sphi, &s.cphi);
     return s;
 }
 
 // binary64 seed-object compatibility: curvature, then azimuth and z (barrel)
-// or r (disk) of the helix at the object's inner and outer anchors
+// or r (disk) of the helix at the object's inner and outer anchors.  The
+// helix direction at radius r is phi0 - asin(u), u = r kappa / 2; its unit
+// vector follows from cos/sin of phi0 and u, and the azimuth test
+// |dphi| <= W (W in [0, pi)) is taken as cos(dphi) >= cos(W), i.e. on the
+// dot product of that unit vector with the anchor.
 __device__ inline bool p_cut(const Consts &c, const Seed &s, float kobj, float skobj,
                              const Anchor &in, const Anchor &out)
 {
     const double ns = c.n_sigma;
     if (!(fabs(s.kp - (double)kobj) <= ns * (s.skp + (double)skobj))) return false;
+#pragma unroll 1
     for (int i = 0; i < 2; i++) {
-        const Anchor &a = i == 0 ? in : out;
-        double x = a.x, y = a.y, z = a.z;
-        double r = sqrt(x * x + y * y);
-        double u = r * s.kp / 2.0;
+        const Anchor a = i == 0 ? in : out;
+        const double x = a.x, y = a.y, z = a.z;
+        const double r = sqrt(x * x + y * y);
+        const double u = r * s.kp / 2.0;
         if (!(fabs(u) < 1.0)) return false;
-        double dphi = atan2(y, x) - (s.phi0 - asin(u));
-        dphi = fmod(dphi + kPiD, 2.0 * kPiD);
-        if (dphi < 0.0) dphi += 2.0 * kPiD;
-        dphi -= kPiD;
-        double sr = a.disk ? c.sig_c : 0.0;
-        double W = ns * (s.s11 + (r * s.skp + sr * fabs(s.kp)) / (2.0 * sqrt(1.0 - u * u)) + c.sig_rphi / r);
-        if (!(fabs(dphi) <= W)) return false;
+        const double cb = sqrt(1.0 - u * u);
+        const double dx = s.cphi * cb + s.sphi * u, dy = s.sphi * cb - s.cphi * u;
+        const double dot = dx * x + dy * y;
+        const double sr = a.disk ? c.sig_c : 0.0;
+        const double W = ns * (s.s11 + (r * s.skp + sr * fabs(s.kp)) / (2.0 * cb) + c.sig_rphi / r);
+        if (!(W >= 0.0)) return false;
+        if (W < kPiD && !(dot >= r * cos(W))) return false;
         if (!a.disk) {
-            double sa = (u == 0.0) ? r : r * asin(u) / u;
-            double zp = s.z0 + s.cot * sa;
+            const double sa = (u == 0.0) ? r : r * asin(u) / u;
+            const double zp = s.z0 + s.cot * sa;
             if (!(fabs(z - zp) <= ns * (s.s44 + sa * s.s22 + c.sig_c))) return false;
         } else {
             if (s.cot == 0.0) return false;
-            double sa = (z - s.z0) / s.cot;
+            const double sa = (z - s.z0) / s.cot;
             if (!(sa > 0.0)) return false;
-            double w = fabs(s.kp) * sa / 2.0;
+            const double w = fabs(s.kp) * sa / 2.0;
             if (!(w < kPiD / 2)) return false;
-            double rp = (w == 0.0) ? sa : sa * sin(w) / w;
+            const double rp = (w == 0.0) ? sa : sa * sin(w) / w;
             if (!(fabs(r - rp) <= ns * ((s.s44 + sa * s.s22) / fabs(s.cot) + c.sig_c))) return false;
         }
     }
@@ -969,15 +974,17 @@ __global__ __launch_bounds__(256) void k_road(const Batch b, const Totals *t, co
 }
 
 // Candidates: one thread per (seed, surface) walks the buckets of its road
-// and keeps the objects that pass the (exact, binary64) curvature test; the
-// other seed cuts run in k_pt_eval, one thread per candidate.
+// and keeps the objects inside the road's azimuth window (padded,
+// conservative) that pass the exact binary64 curvature test; the other seed
+// cuts run in k_pt_eval, one thread per candidate.  The offsets of the four
+// ranges of a bin are loaded together and entries two at a time, so that a
+// bin costs few dependent round trips to memory.
 template <int kKind, bool kFill>
 __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Consts c, int stats)
 {
     const uint32_t n = min(t->n_pls, b.cap_pls) * c.n_surf;
     const uint32_t n_ev = t->n_ev;
     const uint32_t *bk_off = kKind == 0 ? b.bk3_off : b.bk5_off;
-    const uint32_t *bk_items = kKind == 0 ? b.bk3_items : b.bk5_items;
     const float4 *bks = kKind == 0 ? b.bk3_ks : b.bk5_ks;
     uint32_t *cnt = kKind == 0 ? b.ptc3_cnt : b.ptc5_cnt;
     const uint32_t *off = kKind == 0 ? b.ptc3_off : b.ptc5_off;
@@ -985,16 +992,17 @@ __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Con
     uint32_t *out_o = kKind == 0 ? b.ptc3_o : b.ptc5_o;
     const uint32_t cap = kKind == 0 ? b.cap_ptc3 : b.cap_ptc5;
     const uint32_t per_row = 3u * c.nkb + 1u;
+    const float two_pi = 2.0f * kPiF;
     uint64_t cand = 0;
     uint32_t *keep = kKind == 0 ? b.ptc3_keep : b.ptc5_keep;
     GRID_STRIDE(unit, n) {
         uint32_t k = kFill ? off[unit] : 0u;
+        const uint32_t p = unit / c.n_surf;
         if (kFill) {
             // the count pass kept the first kKeepPt objects of this unit
-            const uint32_t cnt = off[unit + 1] - k;
-            if (cnt <= kKeepPt) {
-                const uint32_t p = unit / c.n_surf;
-                for (uint32_t i = 0; i < cnt; i++) {
+            const uint32_t nk = off[unit + 1] - k;
+            if (nk <= kKeepPt) {
+                for (uint32_t i = 0; i < nk; i++) {
                     if (k + i < cap) {
                         out_p[k + i] = p;
                         out_o[k + i] = keep[(size_t)unit * kKeepPt + i];
@@ -1005,7 +1013,7 @@ __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Con
         }
         const uint4 r = b.road[unit];
         if (r.z & 0x80000000u) {
-            const uint32_t p = unit / c.n_surf, sfi = unit - p * c.n_surf;
+            const uint32_t sfi = unit - p * c.n_surf;
             const float *par = b.in_par + 5 * (size_t)p;
             const float *cov = b.in_cov + 15 * (size_t)p;
             const double kp = (double)par[0] * c.kB;
@@ -1013,35 +1021,44 @@ __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Con
             const uint32_t e = find_event(b.ev_pls_off, n_ev, p);
             const uint32_t row0 = (e * c.n_surf + sfi) * c.nphi;
             const uint32_t first = r.x & 0xFFFFu, nbins = r.x >> 16;
-            const uint32_t kr[3] = {r.y & 0xFFFFu, r.y >> 16, r.z & 0xFFFFu};
-            // the road's azimuth window (padded): a cheap, conservative test of
-            // the inner anchor before the exact seed cuts
+            const uint32_t kr0 = r.y & 0xFFFFu, kr1 = r.y >> 16, kr2 = r.z & 0xFFFFu;
             const float2 rp = b.road_phi[unit];
-            const float two_pi = 2.0f * kPiF;
+            auto visit = [&](const float4 q) {
+                if (!kFill) cand++;
+                float dphi = q.z - rp.x;
+                dphi -= two_pi * floorf(dphi / two_pi);
+                if (!(dphi <= rp.y)) return;
+                if (!(fabs(kp - (double)q.x) <= c.n_sigma * (skp + (double)q.y))) return;
+                const uint32_t o = __float_as_uint(q.w);
+                if (!kFill && k < kKeepPt) keep[(size_t)unit * kKeepPt + k] = o;
+                if (kFill && k < cap) {
+                    out_p[k] = p;
+                    out_o[k] = o;
+                }
+                k++;
+            };
+            auto walk = [&](uint32_t i, const uint32_t end) {
+                for (; i + 1u < end; i += 2u) {
+                    const float4 q0 = bks[i], q1 = bks[i + 1u];
+                    visit(q0);
+                    visit(q1);
+                }
+                if (i < end) visit(bks[i]);
+            };
             for (uint32_t j = 0; j < nbins; j++) {
                 uint32_t bin = first + j;
                 if (bin >= c.nphi) bin -= c.nphi;
                 const uint32_t rb = (row0 + bin) * per_row;
-                for (int part = 0; part < 4; part++) {
-                    // parts 0-2: the curvature range of each resolution class; 3: wide objects
-                    const uint32_t lo = part < 3 ? rb + part * c.nkb + (kr[part] & 0xFFu) : rb + 3u * c.nkb;
-                    const uint32_t hi = part < 3 ? rb + part * c.nkb + (kr[part] >> 8) + 1u : rb + per_row;
-                    const uint32_t i0 = bk_off[lo], i1 = bk_off[hi];
-                    for (uint32_t i = i0; i < i1; i++) {
-                        const float4 ks = bks[i];
-                        if (!kFill) cand++;
-                        float dphi = ks.z - rp.x;
-                        dphi -= two_pi * floorf(dphi / two_pi);
-                        if (!(dphi <= rp.y)) continue;
-                        if (!(fabs(kp - (double)ks.x) <= c.n_sigma * (skp + (double)ks.y))) continue;
-                        if (!kFill && k < kKeepPt) keep[(size_t)unit * kKeepPt + k] = bk_items[i];
-                        if (kFill && k < cap) {
-                            out_p[k] = p;
-                            out_o[k] = bk_items[i];
-                        }
-                        k++;
-                    }
-                }
+                // parts 0-2: the curvature range of each resolution class; 3: wide objects
+                const uint32_t a0 = bk_off[rb + (kr0 & 0xFFu)], e0 = bk_off[rb + (kr0 >> 8) + 1u];
+                const uint32_t a1 = bk_off[rb + c.nkb + (kr1 & 0xFFu)], e1 = bk_off[rb + c.nkb + (kr1 >> 8) + 1u];
+                const uint32_t a2 = bk_off[rb + 2u * c.nkb + (kr2 & 0xFFu)];
+                const uint32_t e2 = bk_off[rb + 2u * c.nkb + (kr2 >> 8) + 1u];
+                const uint32_t a3 = bk_off[rb + 3u * c.nkb], e3 = bk_off[rb + per_row];
+                walk(a0, e0);
+                walk(a1, e1);
+                walk(a2, e2);
+                walk(a3, e3);
             }
         }
         if (!kFill) cnt[unit] = k;
