@@ -42,9 +42,9 @@ def log(*a):
 # connection map needs (per edge leaving a module that holds MDs, the MDs of
 # its destination), E_used the number of such edges.  The seed lookup walks
 # bucket entries of 12 B (curvature, its resolution, anchor azimuth) and
-# writes (seed, object) pairs of 8 B; the full seed cuts read each seed
+# appends (seed, object) pairs of 8 B; the full seed cuts read each seed
 # (80 B) once and, per pair, the pair, the object's anchors (2 x 20 B plus
-# curvature 8 B) and write a 4 B verdict.
+# curvature 8 B) and write a 4 B rank.
 def step_bytes(c: dict, n_hits: int, n_pls: int, n_units: int, s_b: int, e_used: int) -> dict:
     nmd, nls, nt3, nt5 = c["md"], c["ls"], c["t3"], c["t5"]
     ls = 20.0 * nmd + 20.0 * s_b + 6.0 * e_used + 4.0 * nmd
@@ -64,9 +64,7 @@ def step_bytes(c: dict, n_hits: int, n_pls: int, n_units: int, s_b: int, e_used:
         "t5_fill": t5 + 16.0 * nt5,
     }
     for k in ("3", "5"):
-        walk = 80.0 * n_pls + 12.0 * c["cand_pt" + k]
-        out[f"pt{k}c_count"] = walk + 4.0 * c["eval_pt" + k]
-        out[f"pt{k}c_fill"] = 12.0 * c["eval_pt" + k]
+        out[f"pt{k}c_walk"] = 80.0 * n_pls + 12.0 * c["cand_pt" + k] + 8.0 * c["eval_pt" + k]
         out[f"pt{k}_eval"] = 80.0 * n_pls + (8.0 + 48.0 + 4.0) * c["eval_pt" + k]
     return out
 

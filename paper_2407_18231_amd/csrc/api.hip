@@ -131,20 +131,24 @@ void carve_work(Carver &cv, Batch &b, uint32_t n_mod, uint32_t n_surf, uint32_t 
     b.bk5_ks = cv.take<float4>(b.cap_t5);
     b.road = cv.take<uint4>(pt_units);
     b.road_phi = cv.take<float2>(pt_units);
-    b.ptc3_cnt = cv.take<uint32_t>(pt_units + 1);
-    b.ptc3_off = cv.take<uint32_t>(pt_units + 1);
     b.ptc3_p = cv.take<uint32_t>(b.cap_ptc3);
     b.ptc3_o = cv.take<uint32_t>(b.cap_ptc3);
-    b.pt3_keep = cv.take<uint32_t>((size_t)b.cap_ptc3 + 1);
-    b.pt3_koff = cv.take<uint32_t>((size_t)b.cap_ptc3 + 1);
-    b.ptc5_cnt = cv.take<uint32_t>(pt_units + 1);
-    b.ptc5_off = cv.take<uint32_t>(pt_units + 1);
+    b.ptc3_rank = cv.take<uint32_t>(b.cap_ptc3);
     b.ptc5_p = cv.take<uint32_t>(b.cap_ptc5);
     b.ptc5_o = cv.take<uint32_t>(b.cap_ptc5);
-    b.pt5_keep = cv.take<uint32_t>((size_t)b.cap_ptc5 + 1);
-    b.pt5_koff = cv.take<uint32_t>((size_t)b.cap_ptc5 + 1);
-    b.ptc3_keep = cv.take<uint32_t>(pt_units * kKeepPt);
-    b.ptc5_keep = cv.take<uint32_t>(pt_units * kKeepPt);
+    b.ptc5_rank = cv.take<uint32_t>(b.cap_ptc5);
+    b.ptc3_sub = cv.take<uint32_t>((size_t)kSubLists * kSubStride);
+    b.ptc5_sub = cv.take<uint32_t>((size_t)kSubLists * kSubStride);
+    b.ptc3_soff = cv.take<uint32_t>(kSubLists + 1);
+    b.ptc5_soff = cv.take<uint32_t>(kSubLists + 1);
+    b.pt3_cnt = cv.take<uint32_t>((size_t)b.cap_pls + 1);
+    b.pt3_off = cv.take<uint32_t>((size_t)b.cap_pls + 1);
+    b.pt5_cnt = cv.take<uint32_t>((size_t)b.cap_pls + 1);
+    b.pt5_off = cv.take<uint32_t>((size_t)b.cap_pls + 1);
+    b.pt3_tp = cv.take<uint32_t>(b.cap_pt3);
+    b.pt3_to = cv.take<uint32_t>(b.cap_pt3);
+    b.pt5_tp = cv.take<uint32_t>(b.cap_pt5);
+    b.pt5_to = cv.take<uint32_t>(b.cap_pt5);
     b.pt3_p = cv.take<uint32_t>(b.cap_pt3);
     b.pt3_o = cv.take<uint32_t>(b.cap_pt3);
     b.pt5_p = cv.take<uint32_t>(b.cap_pt5);
@@ -640,8 +644,8 @@ uint64_t predict_footprint(uint64_t hits, uint64_t pls, const lst::Consts &k)
     uint64_t b = 0;
     b += 73ull * c.hits + 80ull * c.pls + 24ull * k.n_mod;
     b += (40ull + 4ull * lst::kKeepLs) * c.md + (16ull + 4ull * lst::kKeepT3) * c.ls + 60ull * c.t3 + 44ull * c.t5;
-    b += 8ull * (c.pt3 + c.pt5) + (40ull + 8ull * lst::kKeepPt) * c.pls * k.n_surf + 3ull * c.pls + 16ull * (c.pt3 + c.t5 + c.pls);
-    b += 16ull * (c.ptc3 + c.ptc5);
+    b += 16ull * (c.pt3 + c.pt5) + 24ull * c.pls * k.n_surf + 19ull * c.pls + 16ull * (c.pt3 + c.t5 + c.pls);
+    b += 12ull * (c.ptc3 + c.ptc5);
     b += 2ull * 8ull * k.n_surf * k.nphi * (3 * k.nkb + 1);
     return b;
 }

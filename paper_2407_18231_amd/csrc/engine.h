@@ -22,7 +22,12 @@ constexpr unsigned kMaxGrid = 2048;
 constexpr int kEvTabCols = 12;
 // survivors a count pass records per unit, so that the fill pass copies them
 // instead of walking the candidates again (units with more walk again)
-constexpr uint32_t kKeepLs = 8, kKeepT3 = 2, kKeepPt = 8;
+constexpr uint32_t kKeepLs = 8, kKeepT3 = 2;
+constexpr uint32_t kPairBuf = 16;   // seed lookup: candidate pairs a thread buffers in LDS
+// The candidate-pair list is split into kSubLists equal parts, each with its
+// own append counter (kSubStride words apart), so that appends from
+// different blocks do not contend on one address.
+constexpr uint32_t kSubLists = 256, kSubStride = 16;
 
 // Device copy of the geometry (read-only).
 struct DevGeom {
@@ -42,7 +47,7 @@ struct Totals {
     uint32_t n_bins, n_md_units, n_bk, n_sorted, n_rows, n_pt_units;
     uint32_t n_md, n_ls, n_t3, n_t5, n_pt3, n_pt5;
     uint32_t n_bk3, n_bk5, n_tcu, n_tc;
-    uint32_t n_ptc3, n_ptc5;      // seed-object candidates after the curvature test
+    uint32_t n_ptc3, n_ptc5;      // seed-object candidate pairs (or, after a sub-list overflow, the capacity needed)
     uint32_t err;
     unsigned long long cand[6];  // candidates examined: md, ls, t3, t5, pt3, pt5
 };
@@ -96,11 +101,16 @@ struct Batch {
     // per class, class 2 in z), valid << 31 in z
     uint4 *road;
     float2 *road_phi;                   // azimuth window of the road: (start in [0, 2 pi), width)
-    // seed-object candidates per (seed, surface) unit, their keep flags,
-    // and the pT3 / pT5 lists (seed, object)
-    uint32_t *ptc3_cnt, *ptc3_off, *ptc3_p, *ptc3_o, *pt3_keep, *pt3_koff;
-    uint32_t *ptc5_cnt, *ptc5_off, *ptc5_p, *ptc5_o, *pt5_keep, *pt5_koff;
-    uint32_t *ptc3_keep, *ptc5_keep;    // kKeepPt objects per (seed, surface)
+    // seed-object candidate pairs (unordered) and, per pair, its rank among
+    // the accepted pairs of its seed (kInvalid: rejected); accepted pairs
+    // per seed and their offsets; the pT3 / pT5 lists (seed, object) before
+    // (tp, to) and after (p, o) the per-seed order by object
+    uint32_t *ptc3_p, *ptc3_o, *ptc3_rank;
+    uint32_t *ptc5_p, *ptc5_o, *ptc5_rank;
+    uint32_t *ptc3_sub, *ptc5_sub;      // append counters of the sub-lists
+    uint32_t *ptc3_soff, *ptc5_soff;    // dense offsets of the sub-lists (kSubLists + 1)
+    uint32_t *pt3_cnt, *pt3_off, *pt5_cnt, *pt5_off;
+    uint32_t *pt3_tp, *pt3_to, *pt5_tp, *pt5_to;
     uint32_t *pt3_p, *pt3_o;
     uint32_t *pt5_p, *pt5_o;
     // a8: track candidates over [pT3 | T5 | pLS]

@@ -156,6 +156,11 @@ __global__ void k_zero_u8(uint8_t *__restrict__ p, const uint32_t *n_ptr, uint32
     GRID_STRIDE(i, n) p[i] = 0u;
 }
 
+__global__ void k_zero_fixed(uint32_t *__restrict__ p, uint32_t n)
+{
+    GRID_STRIDE(i, n) p[i] = 0u;
+}
+
 // derive the per-batch unit counts; clear error flags and statistics
 __global__ void k_setup(Totals *t, uint32_t n_mod, uint32_t n_surf, uint32_t nphi, uint32_t nkb)
 {
@@ -164,7 +169,6 @@ __global__ void k_setup(Totals *t, uint32_t n_mod, uint32_t n_surf, uint32_t nph
         t->n_md_units = t->n_ev * n_mod;
         t->n_rows = t->n_ev * n_surf * nphi;
         t->n_bk = t->n_rows * (3u * nkb + 1u);
-        t->n_pt_units = t->n_pls * n_surf;
         t->err = 0;
         for (int i = 0; i < 6; i++) t->cand[i] = 0ull;
     }
@@ -973,45 +977,57 @@ __global__ __launch_bounds__(256) void k_road(const Batch b, const Totals *t, co
     }
 }
 
+// wave64 inclusive prefix sum
+__device__ inline uint32_t wave_incl_scan(uint32_t v, uint32_t lane)
+{
+    for (uint32_t d = 1; d < 64u; d <<= 1) {
+        const uint32_t u = __shfl_up(v, d, 64);
+        if (lane >= d) v += u;
+    }
+    return v;
+}
+
 // Candidates: one thread per (seed, surface) walks the buckets of its road
 // and keeps the objects inside the road's azimuth window (padded,
-// conservative) that pass the exact binary64 curvature test; the other seed
-// cuts run in k_pt_eval, one thread per candidate.  The offsets of the four
-// ranges of a bin are loaded together and entries two at a time, so that a
-// bin costs few dependent round trips to memory.
-template <int kKind, bool kFill>
-__global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Consts c, int stats)
+// conservative) that pass the exact binary64 curvature test.  The offsets of
+// the four ranges of a bin are loaded together and entries two at a time, so
+// that a bin costs few dependent round trips to memory.  Pairs collect in a
+// per-thread LDS buffer and are appended to the block's sub-list of the
+// (unordered) pair list with one reservation per wave; a thread whose buffer
+// fills flushes it alone.  The other seed cuts run in k_pt_eval, one thread
+// per pair.
+template <int kKind>
+__global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Consts c, uint32_t nsub, int stats)
 {
+    __shared__ uint32_t buf[kPairBuf * 256];
     const uint32_t n = min(t->n_pls, b.cap_pls) * c.n_surf;
     const uint32_t n_ev = t->n_ev;
+    const uint32_t lane = threadIdx.x & 63u;
     const uint32_t *bk_off = kKind == 0 ? b.bk3_off : b.bk5_off;
     const float4 *bks = kKind == 0 ? b.bk3_ks : b.bk5_ks;
-    uint32_t *cnt = kKind == 0 ? b.ptc3_cnt : b.ptc5_cnt;
-    const uint32_t *off = kKind == 0 ? b.ptc3_off : b.ptc5_off;
-    uint32_t *out_p = kKind == 0 ? b.ptc3_p : b.ptc5_p;
-    uint32_t *out_o = kKind == 0 ? b.ptc3_o : b.ptc5_o;
-    const uint32_t cap = kKind == 0 ? b.cap_ptc3 : b.cap_ptc5;
+    const uint32_t sub = blockIdx.x % nsub;
+    const uint32_t cap = (kKind == 0 ? b.cap_ptc3 : b.cap_ptc5) / nsub;
+    uint32_t *n_pairs = (kKind == 0 ? b.ptc3_sub : b.ptc5_sub) + sub * kSubStride;
+    uint32_t *out_p = (kKind == 0 ? b.ptc3_p : b.ptc5_p) + (size_t)sub * cap;
+    uint32_t *out_o = (kKind == 0 ? b.ptc3_o : b.ptc5_o) + (size_t)sub * cap;
     const uint32_t per_row = 3u * c.nkb + 1u;
     const float two_pi = 2.0f * kPiF;
     uint64_t cand = 0;
-    uint32_t *keep = kKind == 0 ? b.ptc3_keep : b.ptc5_keep;
-    GRID_STRIDE(unit, n) {
-        uint32_t k = kFill ? off[unit] : 0u;
+    // every lane of a wave runs the same number of iterations (the wave
+    // reservation below needs them all)
+    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        const uint32_t unit = base + threadIdx.x;
         const uint32_t p = unit / c.n_surf;
-        if (kFill) {
-            // the count pass kept the first kKeepPt objects of this unit
-            const uint32_t nk = off[unit + 1] - k;
-            if (nk <= kKeepPt) {
-                for (uint32_t i = 0; i < nk; i++) {
-                    if (k + i < cap) {
-                        out_p[k + i] = p;
-                        out_o[k + i] = keep[(size_t)unit * kKeepPt + i];
-                    }
+        uint32_t k = 0;                  // pairs in this thread's buffer
+        auto store = [&](uint32_t at) {
+            for (uint32_t j = 0; j < k; j++) {
+                if (at + j < cap) {
+                    out_p[at + j] = p;
+                    out_o[at + j] = buf[j * 256u + threadIdx.x];
                 }
-                continue;
             }
-        }
-        const uint4 r = b.road[unit];
+        };
+        const uint4 r = unit < n ? b.road[unit] : make_uint4(0u, 0u, 0u, 0u);
         if (r.z & 0x80000000u) {
             const uint32_t sfi = unit - p * c.n_surf;
             const float *par = b.in_par + 5 * (size_t)p;
@@ -1024,17 +1040,16 @@ __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Con
             const uint32_t kr0 = r.y & 0xFFFFu, kr1 = r.y >> 16, kr2 = r.z & 0xFFFFu;
             const float2 rp = b.road_phi[unit];
             auto visit = [&](const float4 q) {
-                if (!kFill) cand++;
+                cand++;
                 float dphi = q.z - rp.x;
                 dphi -= two_pi * floorf(dphi / two_pi);
                 if (!(dphi <= rp.y)) return;
                 if (!(fabs(kp - (double)q.x) <= c.n_sigma * (skp + (double)q.y))) return;
-                const uint32_t o = __float_as_uint(q.w);
-                if (!kFill && k < kKeepPt) keep[(size_t)unit * kKeepPt + k] = o;
-                if (kFill && k < cap) {
-                    out_p[k] = p;
-                    out_o[k] = o;
+                if (k == kPairBuf) {
+                    store(atomicAdd(n_pairs, k));
+                    k = 0;
                 }
+                buf[k * 256u + threadIdx.x] = __float_as_uint(q.w);
                 k++;
             };
             auto walk = [&](uint32_t i, const uint32_t end) {
@@ -1061,23 +1076,77 @@ __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Con
                 walk(a3, e3);
             }
         }
-        if (!kFill) cnt[unit] = k;
+        // one reservation per wave for what the lanes still buffer
+        const uint32_t incl = wave_incl_scan(k, lane);
+        const uint32_t tot = __shfl(incl, 63);
+        uint32_t at = 0;
+        if (tot != 0u && lane == 63u) at = atomicAdd(n_pairs, tot);
+        at = __shfl(at, 63);
+        store(at + incl - k);
     }
-    if (!kFill && stats) atomicAdd(&t->cand[4 + kKind], (unsigned long long)cand);
+    if (stats) atomicAdd(&t->cand[4 + kKind], (unsigned long long)cand);
 }
 
-// full seed cuts, one thread per candidate
+// Sizes of the nsub sub-lists in use to dense offsets (one block of
+// kSubLists threads; offsets past nsub hold the total).  A sub-list that
+// overflowed reports, as the pair count, the capacity that holds it (the
+// host then grows the list and runs the batch again).
 template <int kKind>
-__global__ __launch_bounds__(256) void k_pt_eval(const Batch b, const Totals *t, const Consts c)
+__global__ __launch_bounds__(kSubLists) void k_pair_offsets(const Batch b, Totals *t, uint32_t nsub)
 {
-    const uint32_t n = kKind == 0 ? min(t->n_ptc3, b.cap_ptc3) : min(t->n_ptc5, b.cap_ptc5);
+    static_assert(kSubLists == (uint32_t)kScanBlock, "one sub-list per thread");
+    __shared__ uint32_t s_max;
+    const uint32_t *sub = kKind == 0 ? b.ptc3_sub : b.ptc5_sub;
+    uint32_t *soff = kKind == 0 ? b.ptc3_soff : b.ptc5_soff;
+    const uint32_t cap = (kKind == 0 ? b.cap_ptc3 : b.cap_ptc5) / nsub;
+    if (threadIdx.x == 0) s_max = 0;
+    __syncthreads();
+    const uint32_t v = threadIdx.x < nsub ? sub[threadIdx.x * kSubStride] : 0u;
+    if (v > cap) atomicMax(&s_max, v);
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan(min(v, cap), tot);
+    soff[threadIdx.x] = ex;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        soff[kSubLists] = tot;
+        const uint32_t need = s_max > cap ? (uint32_t)min(0xFFFFFFF0ull, (unsigned long long)s_max * nsub) : tot;
+        if (kKind == 0) t->n_ptc3 = need;
+        else t->n_ptc5 = need;
+    }
+}
+
+// dense pair index j (< total) to its slot: the sub-list s with
+// soff[s] <= j < soff[s + 1]
+__device__ inline uint32_t pair_slot(const uint32_t *s_off, uint32_t j, uint32_t subcap)
+{
+    uint32_t lo = 0, hi = kSubLists;
+    while (hi - lo > 1u) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (s_off[mid] <= j) lo = mid;
+        else hi = mid;
+    }
+    return lo * subcap + (j - s_off[lo]);
+}
+
+// full seed cuts, one thread per pair; an accepted pair draws its rank
+// among the accepted pairs of its seed
+template <int kKind>
+__global__ __launch_bounds__(256) void k_pt_eval(const Batch b, const Consts c, uint32_t nsub)
+{
+    __shared__ uint32_t s_off[kSubLists + 1];
+    const uint32_t *soff = kKind == 0 ? b.ptc3_soff : b.ptc5_soff;
+    for (uint32_t i = threadIdx.x; i <= kSubLists; i += blockDim.x) s_off[i] = soff[i];
+    __syncthreads();
+    const uint32_t n = s_off[kSubLists];
+    const uint32_t subcap = (kKind == 0 ? b.cap_ptc3 : b.cap_ptc5) / nsub;
     const uint32_t *cp = kKind == 0 ? b.ptc3_p : b.ptc5_p;
     const uint32_t *co = kKind == 0 ? b.ptc3_o : b.ptc5_o;
-    uint32_t *keep = kKind == 0 ? b.pt3_keep : b.pt5_keep;
-    GRID_STRIDE(i, n) {
+    uint32_t *rank = kKind == 0 ? b.ptc3_rank : b.ptc5_rank;
+    uint32_t *pcnt = kKind == 0 ? b.pt3_cnt : b.pt5_cnt;
+    GRID_STRIDE(j, n) {
+        const uint32_t i = pair_slot(s_off, j, subcap);
         const uint32_t p = cp[i], o = co[i];
         uint32_t ia, io;
-        float ko, sko;
         float2 ks;
         if (kKind == 0) {
             const uint2 ac = b.t3_ac[o];
@@ -1089,66 +1158,70 @@ __global__ __launch_bounds__(256) void k_pt_eval(const Batch b, const Totals *t,
             io = b.t3_ac[b.t5_w[o]].y;
             ks = b.t5_ks[o];
         }
-        ko = ks.x;
-        sko = ks.y;
         const Seed s = load_seed(b, c, p);
-        keep[i] = p_cut(c, s, ko, sko, load_anchor(b, ia), load_anchor(b, io)) ? 1u : 0u;
+        const bool pass = p_cut(c, s, ks.x, ks.y, load_anchor(b, ia), load_anchor(b, io));
+        rank[i] = pass ? atomicAdd(&pcnt[p], 1u) : kInvalid;
     }
 }
 
+// accepted pairs to their seed's slots (in rank order)
 template <int kKind>
-__global__ void k_pt_compact(const Batch b, const Totals *t)
+__global__ __launch_bounds__(256) void k_pt_place(const Batch b, uint32_t nsub)
 {
-    const uint32_t n = kKind == 0 ? min(t->n_ptc3, b.cap_ptc3) : min(t->n_ptc5, b.cap_ptc5);
+    __shared__ uint32_t s_off[kSubLists + 1];
+    const uint32_t *soff = kKind == 0 ? b.ptc3_soff : b.ptc5_soff;
+    for (uint32_t i = threadIdx.x; i <= kSubLists; i += blockDim.x) s_off[i] = soff[i];
+    __syncthreads();
+    const uint32_t n = s_off[kSubLists];
+    const uint32_t subcap = (kKind == 0 ? b.cap_ptc3 : b.cap_ptc5) / nsub;
     const uint32_t *cp = kKind == 0 ? b.ptc3_p : b.ptc5_p;
     const uint32_t *co = kKind == 0 ? b.ptc3_o : b.ptc5_o;
-    const uint32_t *keep = kKind == 0 ? b.pt3_keep : b.pt5_keep;
-    const uint32_t *koff = kKind == 0 ? b.pt3_koff : b.pt5_koff;
-    uint32_t *out_p = kKind == 0 ? b.pt3_p : b.pt5_p;
-    uint32_t *out_o = kKind == 0 ? b.pt3_o : b.pt5_o;
+    const uint32_t *rank = kKind == 0 ? b.ptc3_rank : b.ptc5_rank;
+    const uint32_t *poff = kKind == 0 ? b.pt3_off : b.pt5_off;
+    uint32_t *tp = kKind == 0 ? b.pt3_tp : b.pt5_tp;
+    uint32_t *to = kKind == 0 ? b.pt3_to : b.pt5_to;
     const uint32_t cap = kKind == 0 ? b.cap_pt3 : b.cap_pt5;
-    GRID_STRIDE(i, n) {
-        if (!keep[i]) continue;
-        const uint32_t k = koff[i];
+    GRID_STRIDE(j, n) {
+        const uint32_t i = pair_slot(s_off, j, subcap);
+        const uint32_t r = rank[i];
+        if (r == kInvalid) continue;
+        const uint32_t p = cp[i];
+        const uint32_t k = poff[p] + r;
         if (k < cap) {
-            out_p[k] = cp[i];
-            out_o[k] = co[i];
+            tp[k] = p;
+            to[k] = co[i];
         }
     }
 }
 
 // first pT index of seed p (seeds p <= n_pls)
 template <int kKind>
-__device__ inline uint32_t pt_first(const Batch &b, const Consts &c, uint32_t p)
+__device__ inline uint32_t pt_first(const Batch &b, uint32_t p)
 {
-    const uint32_t *off = kKind == 0 ? b.ptc3_off : b.ptc5_off;
-    const uint32_t *koff = kKind == 0 ? b.pt3_koff : b.pt5_koff;
-    const uint32_t capc = kKind == 0 ? b.cap_ptc3 : b.cap_ptc5;
-    const uint32_t cap = kKind == 0 ? b.cap_pt3 : b.cap_pt5;
-    return min(koff[min(off[p * c.n_surf], capc)], cap);
+    return kKind == 0 ? min(b.pt3_off[p], b.cap_pt3) : min(b.pt5_off[p], b.cap_pt5);
 }
 
-__device__ inline void sort_range(uint32_t *v, uint32_t k0, uint32_t k1)
+// canonical order within each seed: every element counts the elements of
+// its seed with a smaller object index (ties, which a seed's pairs do not
+// have, by position) and moves to that rank
+template <int kKind>
+__global__ void k_pt_order(const Batch b, const Totals *t)
 {
-    for (uint32_t i = k0 + 1; i < k1; i++) {
-        const uint32_t x = v[i];
-        uint32_t j = i;
-        while (j > k0 && v[j - 1] > x) {
-            v[j] = v[j - 1];
-            j--;
+    const uint32_t n = kKind == 0 ? min(t->n_pt3, b.cap_pt3) : min(t->n_pt5, b.cap_pt5);
+    const uint32_t *tp = kKind == 0 ? b.pt3_tp : b.pt5_tp;
+    const uint32_t *to = kKind == 0 ? b.pt3_to : b.pt5_to;
+    uint32_t *out_p = kKind == 0 ? b.pt3_p : b.pt5_p;
+    uint32_t *out_o = kKind == 0 ? b.pt3_o : b.pt5_o;
+    GRID_STRIDE(j, n) {
+        const uint32_t p = tp[j], o = to[j];
+        const uint32_t a = pt_first<kKind>(b, p), e = min(pt_first<kKind>(b, p + 1), n);
+        uint32_t r = 0;
+        for (uint32_t i = a; i < e; i++) {
+            const uint32_t w = to[i];
+            r += (w < o || (w == o && i < j)) ? 1u : 0u;
         }
-        v[j] = x;
-    }
-}
-
-// canonical order within each seed (pT3 and pT5 lists): by object index
-__global__ void k_pt_sort(const Batch b, const Totals *t, const Consts c)
-{
-    const uint32_t n = min(t->n_pls, b.cap_pls);
-    GRID_STRIDE(q, 2 * n) {
-        const uint32_t p = q >> 1;
-        if (q & 1u) sort_range(b.pt5_o, pt_first<1>(b, c, p), pt_first<1>(b, c, p + 1));
-        else sort_range(b.pt3_o, pt_first<0>(b, c, p), pt_first<0>(b, c, p + 1));
+        out_p[a + r] = p;
+        out_o[a + r] = o;
     }
 }
 
@@ -1213,8 +1286,8 @@ __global__ void k_event_table(const Batch b, const Totals *t, const Consts c)
         uint32_t ls = min(b.ls_off[md], b.cap_ls);
         uint32_t t3 = min(b.t3_off[ls], b.cap_t3);
         uint32_t t5 = min(b.t5_off[t3], b.cap_t5);
-        uint32_t p3 = pt_first<0>(b, c, pls);
-        uint32_t p5 = pt_first<1>(b, c, pls);
+        uint32_t p3 = pt_first<0>(b, pls);
+        uint32_t p5 = pt_first<1>(b, pls);
         row[0] = hit;
         row[1] = pls;
         row[2] = md;
@@ -1298,22 +1371,27 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     L.scan(b.bk5_cnt, b.bk5_off, &t->n_bk, cap_bk, &t->n_bk5, "scan_bucket");
     L.launch("bucket_scatter", k_bucket_scatter<0>, grid_for(b.cap_t3), blk, b, (const Totals *)t);
     L.launch("bucket_scatter", k_bucket_scatter<1>, grid_for(b.cap_t5), blk, b, (const Totals *)t);
-    // a7: pT3 / pT5: candidates, seed cuts, compaction, per-seed order
+    // a7: pT3 / pT5: roads, candidate pairs, seed cuts, per-seed placement and order
     const uint64_t cap_pu = (uint64_t)b.cap_pls * c.n_surf;
     L.launch("road", k_road, grid_for(cap_pu), blk, b, (const Totals *)t, g, c);
-    L.launch("pt3c_count", k_ptc<0, false>, grid_for(cap_pu), blk, b, t, c, stats);
-    L.launch("pt5c_count", k_ptc<1, false>, grid_for(cap_pu), blk, b, t, c, stats);
-    L.scan(b.ptc3_cnt, b.ptc3_off, &t->n_pt_units, (uint32_t)cap_pu, &t->n_ptc3, "scan_pt");
-    L.scan(b.ptc5_cnt, b.ptc5_off, &t->n_pt_units, (uint32_t)cap_pu, &t->n_ptc5, "scan_pt");
-    L.launch("pt3c_fill", k_ptc<0, true>, grid_for(cap_pu), blk, b, t, c, 0);
-    L.launch("pt5c_fill", k_ptc<1, true>, grid_for(cap_pu), blk, b, t, c, 0);
-    L.launch("pt3_eval", k_pt_eval<0>, grid_for(b.cap_ptc3), blk, b, (const Totals *)t, c);
-    L.launch("pt5_eval", k_pt_eval<1>, grid_for(b.cap_ptc5), blk, b, (const Totals *)t, c);
-    L.scan(b.pt3_keep, b.pt3_koff, &t->n_ptc3, b.cap_ptc3, &t->n_pt3, "scan_pt");
-    L.scan(b.pt5_keep, b.pt5_koff, &t->n_ptc5, b.cap_ptc5, &t->n_pt5, "scan_pt");
-    L.launch("pt_compact", k_pt_compact<0>, grid_for(b.cap_ptc3), blk, b, (const Totals *)t);
-    L.launch("pt_compact", k_pt_compact<1>, grid_for(b.cap_ptc5), blk, b, (const Totals *)t);
-    L.launch("pt_sort", k_pt_sort, grid_for(2ull * b.cap_pls), blk, b, (const Totals *)t, c);
+    L.launch("zero", k_zero_fixed, dim3(kSubLists * kSubStride / 256), blk, b.ptc3_sub, kSubLists * kSubStride);
+    L.launch("zero", k_zero_fixed, dim3(kSubLists * kSubStride / 256), blk, b.ptc5_sub, kSubLists * kSubStride);
+    const dim3 gwalk = grid_for(cap_pu);
+    const uint32_t nsub = std::min<uint32_t>(kSubLists, gwalk.x);
+    L.launch("pt3c_walk", k_ptc<0>, gwalk, blk, b, t, c, nsub, stats);
+    L.launch("pt5c_walk", k_ptc<1>, gwalk, blk, b, t, c, nsub, stats);
+    L.launch("pair_offsets", k_pair_offsets<0>, dim3(1), dim3(kSubLists), b, t, nsub);
+    L.launch("pair_offsets", k_pair_offsets<1>, dim3(1), dim3(kSubLists), b, t, nsub);
+    L.launch("zero", k_zero_u32, grid_for((uint64_t)b.cap_pls + 1), blk, b.pt3_cnt, &t->n_pls, b.cap_pls, 1u);
+    L.launch("zero", k_zero_u32, grid_for((uint64_t)b.cap_pls + 1), blk, b.pt5_cnt, &t->n_pls, b.cap_pls, 1u);
+    L.launch("pt3_eval", k_pt_eval<0>, grid_for(b.cap_ptc3), blk, b, c, nsub);
+    L.launch("pt5_eval", k_pt_eval<1>, grid_for(b.cap_ptc5), blk, b, c, nsub);
+    L.scan(b.pt3_cnt, b.pt3_off, &t->n_pls, b.cap_pls, &t->n_pt3, "scan_pt");
+    L.scan(b.pt5_cnt, b.pt5_off, &t->n_pls, b.cap_pls, &t->n_pt5, "scan_pt");
+    L.launch("pt_place", k_pt_place<0>, grid_for(b.cap_ptc3), blk, b, nsub);
+    L.launch("pt_place", k_pt_place<1>, grid_for(b.cap_ptc5), blk, b, nsub);
+    L.launch("pt_order", k_pt_order<0>, grid_for(b.cap_pt3), blk, b, (const Totals *)t);
+    L.launch("pt_order", k_pt_order<1>, grid_for(b.cap_pt5), blk, b, (const Totals *)t);
     // a8: track candidates
     L.launch("zero8", k_zero_u8, grid_for(b.cap_pls), blk, b.pls_used5, &t->n_pls, b.cap_pls);
     L.launch("zero8", k_zero_u8, grid_for(b.cap_pls), blk, b.pls_used3, &t->n_pls, b.cap_pls);
