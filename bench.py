@@ -58,6 +58,8 @@ def step_bytes(c: dict, n_hits: int, n_pls: int, n_units: int, s_b: int, e_used:
         "md_fill": 16.0 * n_hits + 12.0 * n_units + 28.0 * nmd,
         "ls_count": ls,
         "ls_fill": ls + 8.0 * nls,
+        "ls_walk": ls,
+        "ls_place": 8.0 * nls,
         "t3_count": t3 + 4.0 * nls,
         "t3_fill": t3 + 8.0 * nt3 + 16.0 * nt3,
         "t5_count": t5 + 4.0 * nt3,

@@ -107,6 +107,11 @@ void carve_work(Carver &cv, Batch &b, uint32_t n_mod, uint32_t n_surf, uint32_t 
     b.ls_a = cv.take<uint32_t>(b.cap_ls);
     b.ls_b = cv.take<uint32_t>(b.cap_ls);
     b.ls_keep = cv.take<uint32_t>((size_t)b.cap_md * kKeepLs);
+    b.lss_a = cv.take<uint32_t>(b.cap_ls);
+    b.lss_b = cv.take<uint32_t>(b.cap_ls);
+    b.lss_j = cv.take<uint32_t>(b.cap_ls);
+    b.lss_sub = cv.take<uint32_t>((size_t)kSubLists * kSubStride);
+    b.lss_soff = cv.take<uint32_t>(kSubLists + 1);
     b.t3_cnt = cv.take<uint32_t>((size_t)b.cap_ls + 1);
     b.t3_off = cv.take<uint32_t>((size_t)b.cap_ls + 1);
     b.t3_l1 = cv.take<uint32_t>(b.cap_t3);
@@ -473,7 +478,7 @@ int overflowed(Slot &s)
     };
     bool g = false;
     g |= grow(t.n_md, b.cap_md);
-    g |= grow(t.n_ls, b.cap_ls);
+    g |= grow(std::max(t.n_ls, t.n_lss), b.cap_ls);
     g |= grow(t.n_t3, b.cap_t3);
     g |= grow(t.n_t5, b.cap_t5);
     g |= grow(t.n_pt3, b.cap_pt3);
@@ -643,7 +648,7 @@ uint64_t predict_footprint(uint64_t hits, uint64_t pls, const lst::Consts &k)
     lst::Caps c = lst::plan_caps(1, hits, pls);
     uint64_t b = 0;
     b += 73ull * c.hits + 80ull * c.pls + 24ull * k.n_mod;
-    b += (40ull + 4ull * lst::kKeepLs) * c.md + (16ull + 4ull * lst::kKeepT3) * c.ls + 60ull * c.t3 + 44ull * c.t5;
+    b += (40ull + 4ull * lst::kKeepLs) * c.md + (28ull + 4ull * lst::kKeepT3) * c.ls + 60ull * c.t3 + 44ull * c.t5;
     b += 16ull * (c.pt3 + c.pt5) + 24ull * c.pls * k.n_surf + 19ull * c.pls + 16ull * (c.pt3 + c.t5 + c.pls);
     b += 12ull * (c.ptc3 + c.ptc5);
     b += 2ull * 8ull * k.n_surf * k.nphi * (3 * k.nkb + 1);

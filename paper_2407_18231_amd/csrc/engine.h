@@ -24,6 +24,7 @@ constexpr int kEvTabCols = 12;
 // instead of walking the candidates again (units with more walk again)
 constexpr uint32_t kKeepLs = 8, kKeepT3 = 2;
 constexpr uint32_t kPairBuf = 16;   // seed lookup: candidate pairs a thread buffers in LDS
+constexpr uint32_t kSegBuf = 16;    // segments: outer MDs a thread buffers in LDS
 // The candidate-pair list is split into kSubLists equal parts, each with its
 // own append counter (kSubStride words apart), so that appends from
 // different blocks do not contend on one address.
@@ -48,6 +49,7 @@ struct Totals {
     uint32_t n_md, n_ls, n_t3, n_t5, n_pt3, n_pt5;
     uint32_t n_bk3, n_bk5, n_tcu, n_tc;
     uint32_t n_ptc3, n_ptc5;      // seed-object candidate pairs (or, after a sub-list overflow, the capacity needed)
+    uint32_t n_lss;               // segments in the unordered segment sub-lists (likewise)
     uint32_t err;
     unsigned long long cand[6];  // candidates examined: md, ls, t3, t5, pt3, pt5
 };
@@ -79,7 +81,10 @@ struct Batch {
     // a3: line segments
     uint32_t *ls_cnt, *ls_off;          // per inner MD
     uint32_t *ls_a, *ls_b;
-    uint32_t *ls_keep;                  // kKeepLs outer MDs per inner MD
+    uint32_t *ls_keep;                  // kKeepLs outer MDs per inner MD (small batches)
+    // large batches: segments in the block sub-lists of an unordered list,
+    // (inner MD, outer MD, place in the inner MD's list), before placement
+    uint32_t *lss_a, *lss_b, *lss_j, *lss_sub, *lss_soff;
     // a4: T3
     uint32_t *t3_cnt, *t3_off;          // per inner LS
     uint32_t *t3_l1, *t3_l2;

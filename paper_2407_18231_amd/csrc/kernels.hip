@@ -144,6 +144,19 @@ __device__ inline uint32_t find_event(const uint32_t *__restrict__ off, uint32_t
     return lo;
 }
 
+// dense pair index j (< total) to its slot: the sub-list s with
+// soff[s] <= j < soff[s + 1]
+__device__ inline uint32_t pair_slot(const uint32_t *s_off, uint32_t j, uint32_t subcap)
+{
+    uint32_t lo = 0, hi = kSubLists;
+    while (hi - lo > 1u) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (s_off[mid] <= j) lo = mid;
+        else hi = mid;
+    }
+    return lo * subcap + (j - s_off[lo]);
+}
+
 __global__ void k_zero_u32(uint32_t *__restrict__ p, const uint32_t *n_ptr, uint32_t cap, uint32_t extra)
 {
     const uint32_t n = min(*n_ptr, cap) + extra;
@@ -420,46 +433,87 @@ __device__ inline void ls_walk(const Batch &b, const DevGeom &g, const Consts &c
     }
 }
 
-template <bool kFill>
+// Large batches: one thread per inner MD, one pass.  Survivors collect in a
+// per-thread LDS buffer and go, with their place in the MD's list, to the
+// block's sub-list of an unordered segment list (one reservation per wave; a
+// thread whose buffer fills flushes it alone); k_ls_place moves them to their
+// canonical slots once the per-MD counts are scanned.  The walk meets the
+// outer MDs in increasing order (edges are sorted by destination module), so
+// the place in the list is the canonical one.
 __global__ __launch_bounds__(256) void k_ls(const Batch b, Totals *t, const DevGeom g, const Consts c,
-                                            int stats)
+                                            uint32_t nsub, int stats)
 {
+    __shared__ uint32_t buf[kSegBuf * 256];
     const uint32_t n = min(t->n_md, b.cap_md);
     const uint32_t n_mod = c.n_mod;
     const bool bend = (c.flags & LST_FLAG_BEND) != 0u;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t sub = blockIdx.x % nsub;
+    const uint32_t cap = b.cap_ls / nsub;
+    uint32_t *n_seg = b.lss_sub + sub * kSubStride;
+    uint32_t *sa = b.lss_a + (size_t)sub * cap;
+    uint32_t *sb = b.lss_b + (size_t)sub * cap;
+    uint32_t *sj = b.lss_j + (size_t)sub * cap;
     uint64_t cand = 0;
-    GRID_STRIDE(a, n) {
-        uint32_t k = kFill ? b.ls_off[a] : 0u;
-        if (kFill) {
-            // the count pass kept the first kKeepLs outer MDs
-            const uint32_t cnt = b.ls_off[a + 1] - k;
-            if (cnt <= kKeepLs) {
-                for (uint32_t i = 0; i < cnt; i++) {
-                    if (k + i < b.cap_ls) {
-                        b.ls_a[k + i] = a;
-                        b.ls_b[k + i] = b.ls_keep[(size_t)a * kKeepLs + i];
-                    }
+    // every lane of a wave runs the same number of iterations (the wave
+    // reservation below needs them all)
+    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        const uint32_t a = base + threadIdx.x;
+        uint32_t kb = 0, k = 0;          // buffered, found so far
+        auto store = [&](uint32_t at) {
+            for (uint32_t j = 0; j < kb; j++) {
+                if (at + j < cap) {
+                    sa[at + j] = a;
+                    sb[at + j] = buf[j * 256u + threadIdx.x];
+                    sj[at + j] = k - kb + j;
                 }
-                continue;
             }
+        };
+        if (a < n) {
+            const uint32_t u = b.md_u[a] & kUnitMask;
+            const uint32_t m = u % n_mod;
+            const float4 pa = b.md_pos[a];
+            const float ba = b.md_beta[a];
+            ls_walk(b, g, c, bend, m, u - m, pa, ba, [&](uint32_t q, bool pass) {
+                cand++;
+                if (!pass) return;
+                if (kb == kSegBuf) {
+                    store(atomicAdd(n_seg, kb));
+                    kb = 0;
+                }
+                buf[kb * 256u + threadIdx.x] = q;
+                kb++;
+                k++;
+            });
+            b.ls_cnt[a] = k;
         }
-        const uint32_t u = b.md_u[a] & kUnitMask;
-        const uint32_t m = u % n_mod;
-        const float4 pa = b.md_pos[a];
-        const float ba = b.md_beta[a];
-        ls_walk(b, g, c, bend, m, u - m, pa, ba, [&](uint32_t q, bool pass) {
-            if (!kFill) cand++;
-            if (!pass) return;
-            if (!kFill && k < kKeepLs) b.ls_keep[(size_t)a * kKeepLs + k] = q;
-            if (kFill && k < b.cap_ls) {
-                b.ls_a[k] = a;
-                b.ls_b[k] = q;
-            }
-            k++;
-        });
-        if (!kFill) b.ls_cnt[a] = k;
+        const uint32_t incl = wave_incl_scan(kb);
+        const uint32_t tot = __shfl(incl, 63);
+        uint32_t at = 0;
+        if (tot != 0u && lane == 63u) at = atomicAdd(n_seg, tot);
+        at = __shfl(at, 63);
+        store(at + incl - kb);
     }
-    if (!kFill && stats) atomicAdd(&t->cand[1], (unsigned long long)cand);
+    if (stats) atomicAdd(&t->cand[1], (unsigned long long)cand);
+}
+
+// segments from the sub-lists to their canonical slots
+__global__ __launch_bounds__(256) void k_ls_place(const Batch b, uint32_t nsub)
+{
+    __shared__ uint32_t s_off[kSubLists + 1];
+    for (uint32_t i = threadIdx.x; i <= kSubLists; i += blockDim.x) s_off[i] = b.lss_soff[i];
+    __syncthreads();
+    const uint32_t n = s_off[kSubLists];
+    const uint32_t subcap = b.cap_ls / nsub;
+    GRID_STRIDE(j, n) {
+        const uint32_t i = pair_slot(s_off, j, subcap);
+        const uint32_t a = b.lss_a[i];
+        const uint32_t k = b.ls_off[a] + b.lss_j[i];
+        if (k < b.cap_ls) {
+            b.ls_a[k] = a;
+            b.ls_b[k] = b.lss_b[i];
+        }
+    }
 }
 
 // Latency variant for small batches (a few events): a wave takes two
@@ -977,16 +1031,6 @@ __global__ __launch_bounds__(256) void k_road(const Batch b, const Totals *t, co
     }
 }
 
-// wave64 inclusive prefix sum
-__device__ inline uint32_t wave_incl_scan(uint32_t v, uint32_t lane)
-{
-    for (uint32_t d = 1; d < 64u; d <<= 1) {
-        const uint32_t u = __shfl_up(v, d, 64);
-        if (lane >= d) v += u;
-    }
-    return v;
-}
-
 // Candidates: one thread per (seed, surface) walks the buckets of its road
 // and keeps the objects inside the road's azimuth window (padded,
 // conservative) that pass the exact binary64 curvature test.  The offsets of
@@ -1077,7 +1121,7 @@ __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Con
             }
         }
         // one reservation per wave for what the lanes still buffer
-        const uint32_t incl = wave_incl_scan(k, lane);
+        const uint32_t incl = wave_incl_scan(k);
         const uint32_t tot = __shfl(incl, 63);
         uint32_t at = 0;
         if (tot != 0u && lane == 63u) at = atomicAdd(n_pairs, tot);
@@ -1088,17 +1132,16 @@ __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Con
 }
 
 // Sizes of the nsub sub-lists in use to dense offsets (one block of
-// kSubLists threads; offsets past nsub hold the total).  A sub-list that
-// overflowed reports, as the pair count, the capacity that holds it (the
+// kSubLists threads; offsets past nsub hold the total).  need receives the
+// total or, when a sub-list overflowed, the list capacity that holds it (the
 // host then grows the list and runs the batch again).
-template <int kKind>
-__global__ __launch_bounds__(kSubLists) void k_pair_offsets(const Batch b, Totals *t, uint32_t nsub)
+__global__ __launch_bounds__(kSubLists) void k_sub_offsets(const uint32_t *__restrict__ sub,
+                                                           uint32_t *__restrict__ soff, uint32_t cap_total,
+                                                           uint32_t nsub, uint32_t *need)
 {
     static_assert(kSubLists == (uint32_t)kScanBlock, "one sub-list per thread");
     __shared__ uint32_t s_max;
-    const uint32_t *sub = kKind == 0 ? b.ptc3_sub : b.ptc5_sub;
-    uint32_t *soff = kKind == 0 ? b.ptc3_soff : b.ptc5_soff;
-    const uint32_t cap = (kKind == 0 ? b.cap_ptc3 : b.cap_ptc5) / nsub;
+    const uint32_t cap = cap_total / nsub;
     if (threadIdx.x == 0) s_max = 0;
     __syncthreads();
     const uint32_t v = threadIdx.x < nsub ? sub[threadIdx.x * kSubStride] : 0u;
@@ -1109,24 +1152,10 @@ __global__ __launch_bounds__(kSubLists) void k_pair_offsets(const Batch b, Total
     __syncthreads();
     if (threadIdx.x == 0) {
         soff[kSubLists] = tot;
-        const uint32_t need = s_max > cap ? (uint32_t)min(0xFFFFFFF0ull, (unsigned long long)s_max * nsub) : tot;
-        if (kKind == 0) t->n_ptc3 = need;
-        else t->n_ptc5 = need;
+        *need = s_max > cap ? (uint32_t)min(0xFFFFFFF0ull, (unsigned long long)s_max * nsub) : tot;
     }
 }
 
-// dense pair index j (< total) to its slot: the sub-list s with
-// soff[s] <= j < soff[s + 1]
-__device__ inline uint32_t pair_slot(const uint32_t *s_off, uint32_t j, uint32_t subcap)
-{
-    uint32_t lo = 0, hi = kSubLists;
-    while (hi - lo > 1u) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (s_off[mid] <= j) lo = mid;
-        else hi = mid;
-    }
-    return lo * subcap + (j - s_off[lo]);
-}
 
 // full seed cuts, one thread per pair; an accepted pair draws its rank
 // among the accepted pairs of its seed
@@ -1348,9 +1377,14 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
         L.scan(b.ls_cnt, b.ls_off, &t->n_md, b.cap_md, &t->n_ls, "scan_ls");
         L.launch("ls_fill", k_ls_wave<true>, grid_for(32ull * b.cap_md), blk, b, t, g, c, 0);
     } else {
-        L.launch("ls_count", k_ls<false>, grid_for(b.cap_md), blk, b, t, g, c, stats);
+        const dim3 gls = grid_for(b.cap_md);
+        const uint32_t nsub_ls = std::min<uint32_t>(kSubLists, gls.x);
+        L.launch("zero", k_zero_fixed, dim3(kSubLists * kSubStride / 256), blk, b.lss_sub, kSubLists * kSubStride);
+        L.launch("ls_walk", k_ls, gls, blk, b, t, g, c, nsub_ls, stats);
+        L.launch("sub_offsets", k_sub_offsets, dim3(1), dim3(kSubLists), b.lss_sub, b.lss_soff, b.cap_ls, nsub_ls,
+                 &t->n_lss);
         L.scan(b.ls_cnt, b.ls_off, &t->n_md, b.cap_md, &t->n_ls, "scan_ls");
-        L.launch("ls_fill", k_ls<true>, grid_for(b.cap_md), blk, b, t, g, c, 0);
+        L.launch("ls_place", k_ls_place, grid_for(b.cap_ls), blk, b, nsub_ls);
     }
     // a4: T3
     L.launch("t3_count", k_t3<false>, grid_for(b.cap_ls), blk, b, t, c, stats);
@@ -1380,8 +1414,10 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     const uint32_t nsub = std::min<uint32_t>(kSubLists, gwalk.x);
     L.launch("pt3c_walk", k_ptc<0>, gwalk, blk, b, t, c, nsub, stats);
     L.launch("pt5c_walk", k_ptc<1>, gwalk, blk, b, t, c, nsub, stats);
-    L.launch("pair_offsets", k_pair_offsets<0>, dim3(1), dim3(kSubLists), b, t, nsub);
-    L.launch("pair_offsets", k_pair_offsets<1>, dim3(1), dim3(kSubLists), b, t, nsub);
+    L.launch("sub_offsets", k_sub_offsets, dim3(1), dim3(kSubLists), b.ptc3_sub, b.ptc3_soff, b.cap_ptc3, nsub,
+             &t->n_ptc3);
+    L.launch("sub_offsets", k_sub_offsets, dim3(1), dim3(kSubLists), b.ptc5_sub, b.ptc5_soff, b.cap_ptc5, nsub,
+             &t->n_ptc5);
     L.launch("zero", k_zero_u32, grid_for((uint64_t)b.cap_pls + 1), blk, b.pt3_cnt, &t->n_pls, b.cap_pls, 1u);
     L.launch("zero", k_zero_u32, grid_for((uint64_t)b.cap_pls + 1), blk, b.pt5_cnt, &t->n_pls, b.cap_pls, 1u);
     L.launch("pt3_eval", k_pt_eval<0>, grid_for(b.cap_ptc3), blk, b, c, nsub);
