@@ -62,6 +62,8 @@ def step_bytes(c: dict, n_hits: int, n_pls: int, n_units: int, s_b: int, e_used:
         "ls_place": 8.0 * nls,
         "t3_count": t3 + 4.0 * nls,
         "t3_fill": t3 + 8.0 * nt3 + 16.0 * nt3,
+        "t3_walk": t3 + 4.0 * nls,
+        "t3_place": 24.0 * nt3,
         "t5_count": t5 + 4.0 * nt3,
         "t5_fill": t5 + 16.0 * nt5,
     }

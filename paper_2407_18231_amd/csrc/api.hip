@@ -116,7 +116,13 @@ void carve_work(Carver &cv, Batch &b, uint32_t n_mod, uint32_t n_surf, uint32_t 
     b.t3_off = cv.take<uint32_t>((size_t)b.cap_ls + 1);
     b.t3_l1 = cv.take<uint32_t>(b.cap_t3);
     b.t3_l2 = cv.take<uint32_t>(b.cap_t3);
-    b.t3_keep = cv.take<uint32_t>((size_t)b.cap_ls * kKeepT3);
+    b.t3s_l1 = cv.take<uint32_t>(b.cap_t3);
+    b.t3s_l2 = cv.take<uint32_t>(b.cap_t3);
+    b.t3s_j = cv.take<uint32_t>(b.cap_t3);
+    b.t3s_ac = cv.take<uint2>(b.cap_t3);
+    b.t3s_ks = cv.take<float2>(b.cap_t3);
+    b.t3s_sub = cv.take<uint32_t>((size_t)kSubLists * kSubStride);
+    b.t3s_soff = cv.take<uint32_t>(kSubLists + 1);
     b.t3_ac = cv.take<uint2>(b.cap_t3);
     b.t3_ks = cv.take<float2>(b.cap_t3);
     b.t5_cnt = cv.take<uint32_t>((size_t)b.cap_t3 + 1);
@@ -479,7 +485,7 @@ int overflowed(Slot &s)
     bool g = false;
     g |= grow(t.n_md, b.cap_md);
     g |= grow(std::max(t.n_ls, t.n_lss), b.cap_ls);
-    g |= grow(t.n_t3, b.cap_t3);
+    g |= grow(std::max(t.n_t3, t.n_t3s), b.cap_t3);
     g |= grow(t.n_t5, b.cap_t5);
     g |= grow(t.n_pt3, b.cap_pt3);
     g |= grow(t.n_pt5, b.cap_pt5);
@@ -648,7 +654,7 @@ uint64_t predict_footprint(uint64_t hits, uint64_t pls, const lst::Consts &k)
     lst::Caps c = lst::plan_caps(1, hits, pls);
     uint64_t b = 0;
     b += 73ull * c.hits + 80ull * c.pls + 24ull * k.n_mod;
-    b += (40ull + 4ull * lst::kKeepLs) * c.md + (28ull + 4ull * lst::kKeepT3) * c.ls + 60ull * c.t3 + 44ull * c.t5;
+    b += (40ull + 4ull * lst::kKeepLs) * c.md + 28ull * c.ls + 88ull * c.t3 + 44ull * c.t5;
     b += 16ull * (c.pt3 + c.pt5) + 24ull * c.pls * k.n_surf + 19ull * c.pls + 16ull * (c.pt3 + c.t5 + c.pls);
     b += 12ull * (c.ptc3 + c.ptc5);
     b += 2ull * 8ull * k.n_surf * k.nphi * (3 * k.nkb + 1);

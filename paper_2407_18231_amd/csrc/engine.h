@@ -22,9 +22,10 @@ constexpr unsigned kMaxGrid = 2048;
 constexpr int kEvTabCols = 12;
 // survivors a count pass records per unit, so that the fill pass copies them
 // instead of walking the candidates again (units with more walk again)
-constexpr uint32_t kKeepLs = 8, kKeepT3 = 2;
+constexpr uint32_t kKeepLs = 8;
 constexpr uint32_t kPairBuf = 16;   // seed lookup: candidate pairs a thread buffers in LDS
 constexpr uint32_t kSegBuf = 16;    // segments: outer MDs a thread buffers in LDS
+constexpr uint32_t kT3Buf = 4;      // T3: (outer LS, outer anchor, curvature) a thread buffers in LDS
 // The candidate-pair list is split into kSubLists equal parts, each with its
 // own append counter (kSubStride words apart), so that appends from
 // different blocks do not contend on one address.
@@ -50,6 +51,7 @@ struct Totals {
     uint32_t n_bk3, n_bk5, n_tcu, n_tc;
     uint32_t n_ptc3, n_ptc5;      // seed-object candidate pairs (or, after a sub-list overflow, the capacity needed)
     uint32_t n_lss;               // segments in the unordered segment sub-lists (likewise)
+    uint32_t n_t3s;               // T3s in the unordered T3 sub-lists (likewise)
     uint32_t err;
     unsigned long long cand[6];  // candidates examined: md, ls, t3, t5, pt3, pt5
 };
@@ -88,7 +90,11 @@ struct Batch {
     // a4: T3
     uint32_t *t3_cnt, *t3_off;          // per inner LS
     uint32_t *t3_l1, *t3_l2;
-    uint32_t *t3_keep;                  // kKeepT3 outer LSs per inner LS
+    // T3s in the block sub-lists of an unordered list before placement:
+    // (inner LS, outer LS, place in the inner LS's list, anchors, curvature)
+    uint32_t *t3s_l1, *t3s_l2, *t3s_j, *t3s_sub, *t3s_soff;
+    uint2 *t3s_ac;
+    float2 *t3s_ks;
     uint2 *t3_ac;                       // inner and outer MD
     float2 *t3_ks;                      // curvature and its resolution
     // a5: T5

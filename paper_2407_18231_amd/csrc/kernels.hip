@@ -454,6 +454,7 @@ __global__ __launch_bounds__(256) void k_ls(const Batch b, Totals *t, const DevG
     uint32_t *sa = b.lss_a + (size_t)sub * cap;
     uint32_t *sb = b.lss_b + (size_t)sub * cap;
     uint32_t *sj = b.lss_j + (size_t)sub * cap;
+    const unsigned long long below = (1ull << lane) - 1ull;
     uint64_t cand = 0;
     // every lane of a wave runs the same number of iterations (the wave
     // reservation below needs them all)
@@ -487,12 +488,26 @@ __global__ __launch_bounds__(256) void k_ls(const Batch b, Totals *t, const DevG
             });
             b.ls_cnt[a] = k;
         }
-        const uint32_t incl = wave_incl_scan(kb);
-        const uint32_t tot = __shfl(incl, 63);
+        // one reservation per wave; the buffers go out column by column
+        // (entry j of every lane that has one), so that stores coalesce
+        const uint32_t tot = __shfl(wave_incl_scan(kb), 63);
         uint32_t at = 0;
         if (tot != 0u && lane == 63u) at = atomicAdd(n_seg, tot);
         at = __shfl(at, 63);
-        store(at + incl - kb);
+        for (uint32_t j = 0; j < kSegBuf; j++) {
+            const bool has = j < kb;
+            const unsigned long long m = __ballot(has);
+            if (m == 0ull) break;
+            if (has) {
+                const uint32_t slot = at + (uint32_t)__popcll(m & below);
+                if (slot < cap) {
+                    sa[slot] = a;
+                    sb[slot] = buf[j * 256u + threadIdx.x];
+                    sj[slot] = k - kb + j;
+                }
+            }
+            at += (uint32_t)__popcll(m);
+        }
     }
     if (stats) atomicAdd(&t->cand[1], (unsigned long long)cand);
 }
@@ -682,60 +697,108 @@ __device__ inline bool rz3(const Consts &c, const Anchor &A, const Anchor &B, co
     return fabsf(E) <= c.ns * res + bias;
 }
 
-template <bool kFill>
-__global__ __launch_bounds__(256) void k_t3(const Batch b, Totals *t, const Consts c, int stats)
+// T3: one thread per inner LS l1 tests the LSs that start at l1's outer
+// MD, four at a time (their outer MDs and anchors load together).
+// Survivors collect in a per-thread LDS buffer and go, with their place in
+// l1's list, to the block's sub-list of an unordered T3 list (one
+// reservation per wave, stores column by column; a thread whose buffer
+// fills flushes it alone); k_t3_place moves them to their canonical slots
+// once the per-LS counts are scanned.  Outer LSs are met in index order, so
+// the place in the list is the canonical one.
+__global__ __launch_bounds__(256) void k_t3(const Batch b, Totals *t, const Consts c, uint32_t nsub, int stats)
 {
+    __shared__ uint4 buf[kT3Buf * 256];
     const uint32_t n = min(t->n_ls, b.cap_ls);
+    const uint32_t lane = threadIdx.x & 63u;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const uint32_t sub = blockIdx.x % nsub;
+    const uint32_t cap = b.cap_t3 / nsub;
+    uint32_t *n_t3 = b.t3s_sub + sub * kSubStride;
+    const size_t sb0 = (size_t)sub * cap;
     uint64_t cand = 0;
-    GRID_STRIDE(l1, n) {
-        uint32_t k = kFill ? b.t3_off[l1] : 0u;
-        const uint32_t cnt = kFill ? b.t3_off[l1 + 1] - k : 0u;
-        if (kFill && cnt == 0) continue;
-        const uint32_t ia = b.ls_a[l1], ib = b.ls_b[l1];
-        if (kFill && cnt <= kKeepT3) {
-            // the count pass kept the outer LSs of this T3 list
-            const Anchor A = load_anchor(b, ia), B = load_anchor(b, ib);
-            for (uint32_t i = 0; i < cnt; i++) {
-                const uint32_t l2 = b.t3_keep[(size_t)l1 * kKeepT3 + i];
-                const uint32_t ic = b.ls_b[l2];
-                const Anchor C = load_anchor(b, ic);
-                float kap, sk, d1, d2;
-                kappa3(c, A, B, C, kap, sk, d1, d2);
-                if (k + i < b.cap_t3) {
-                    b.t3_l1[k + i] = l1;
-                    b.t3_l2[k + i] = l2;
-                    b.t3_ac[k + i] = make_uint2(ia, ic);
-                    b.t3_ks[k + i] = make_float2(kap, sk);
+    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        const uint32_t l1 = base + threadIdx.x;
+        uint32_t kb = 0, k = 0, ia = 0;  // buffered, found so far, inner anchor
+        auto put = [&](uint32_t slot, uint32_t j) {
+            const uint4 v = buf[j * 256u + threadIdx.x];
+            if (slot < cap) {
+                b.t3s_l1[sb0 + slot] = l1;
+                b.t3s_l2[sb0 + slot] = v.x;
+                b.t3s_j[sb0 + slot] = k - kb + j;
+                b.t3s_ac[sb0 + slot] = make_uint2(ia, v.y);
+                b.t3s_ks[sb0 + slot] = make_float2(__uint_as_float(v.z), __uint_as_float(v.w));
+            }
+        };
+        if (l1 < n) {
+            ia = b.ls_a[l1];
+            const uint32_t ib = b.ls_b[l1];
+            const uint32_t q0 = min(b.ls_off[ib], b.cap_ls), q1 = min(b.ls_off[ib + 1], b.cap_ls);
+            if (q0 < q1) {
+                const Anchor A = load_anchor(b, ia), B = load_anchor(b, ib);
+                for (uint32_t l2 = q0; l2 < q1; l2 += 4u) {
+                    uint32_t ic[4];
+                    Anchor C[4];
+#pragma unroll
+                    for (int j = 0; j < 4; j++) ic[j] = l2 + j < q1 ? b.ls_b[l2 + j] : ib;
+#pragma unroll
+                    for (int j = 0; j < 4; j++) C[j] = load_anchor(b, ic[j]);
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        if (l2 + j >= q1) break;
+                        float kap, sk, d1, d2;
+                        cand++;
+                        kappa3(c, A, B, C[j], kap, sk, d1, d2);
+                        if (!(fabsf(kap) <= c.kmaxf + c.ns * sk)) continue;
+                        if (!rz3(c, A, B, C[j], d1, d2)) continue;
+                        if (kb == kT3Buf) {
+                            const uint32_t at = atomicAdd(n_t3, kb);
+                            for (uint32_t q = 0; q < kb; q++) put(at + q, q);
+                            kb = 0;
+                        }
+                        buf[kb * 256u + threadIdx.x] = make_uint4(l2 + j, ic[j], __float_as_uint(kap),
+                                                                 __float_as_uint(sk));
+                        kb++;
+                        k++;
+                    }
                 }
             }
-            continue;
+            b.t3_cnt[l1] = k;
         }
-        const uint32_t q0 = min(b.ls_off[ib], b.cap_ls), q1 = min(b.ls_off[ib + 1], b.cap_ls);
-        if (q0 == q1) {
-            if (!kFill) b.t3_cnt[l1] = 0;
-            continue;
+        // one reservation per wave; the buffers go out column by column
+        const uint32_t tot = __shfl(wave_incl_scan(kb), 63);
+        uint32_t at = 0;
+        if (tot != 0u && lane == 63u) at = atomicAdd(n_t3, tot);
+        at = __shfl(at, 63);
+        for (uint32_t j = 0; j < kT3Buf; j++) {
+            const bool has = j < kb;
+            const unsigned long long m = __ballot(has);
+            if (m == 0ull) break;
+            if (has) put(at + (uint32_t)__popcll(m & below), j);
+            at += (uint32_t)__popcll(m);
         }
-        const Anchor A = load_anchor(b, ia), B = load_anchor(b, ib);
-        for (uint32_t l2 = q0; l2 < q1; l2++) {
-            const uint32_t ic = b.ls_b[l2];
-            const Anchor C = load_anchor(b, ic);
-            float kap, sk, d1, d2;
-            if (!kFill) cand++;
-            kappa3(c, A, B, C, kap, sk, d1, d2);
-            if (!(fabsf(kap) <= c.kmaxf + c.ns * sk)) continue;
-            if (!rz3(c, A, B, C, d1, d2)) continue;
-            if (!kFill && k < kKeepT3) b.t3_keep[(size_t)l1 * kKeepT3 + k] = l2;
-            if (kFill && k < b.cap_t3) {
-                b.t3_l1[k] = l1;
-                b.t3_l2[k] = l2;
-                b.t3_ac[k] = make_uint2(ia, ic);
-                b.t3_ks[k] = make_float2(kap, sk);
-            }
-            k++;
-        }
-        if (!kFill) b.t3_cnt[l1] = k;
     }
-    if (!kFill && stats) atomicAdd(&t->cand[2], (unsigned long long)cand);
+    if (stats) atomicAdd(&t->cand[2], (unsigned long long)cand);
+}
+
+// T3s from the sub-lists to their canonical slots
+__global__ __launch_bounds__(256) void k_t3_place(const Batch b, uint32_t nsub)
+{
+    __shared__ uint32_t s_off[kSubLists + 1];
+    for (uint32_t i = threadIdx.x; i <= kSubLists; i += blockDim.x) s_off[i] = b.t3s_soff[i];
+    __syncthreads();
+    const uint32_t n = s_off[kSubLists];
+    const uint32_t subcap = b.cap_t3 / nsub;
+    GRID_STRIDE(j, n) {
+        const uint32_t i = pair_slot(s_off, j, subcap);
+        const uint32_t l1 = b.t3s_l1[i];
+        const uint32_t k = b.t3_off[l1] + b.t3s_j[i];
+        if (k < b.cap_t3) {
+            b.t3_l1[k] = l1;
+            b.t3_l2[k] = b.t3s_l2[i];
+            b.t3_ac[k] = b.t3s_ac[i];
+            b.t3_ks[k] = b.t3s_ks[i];
+        }
+    }
 }
 
 // ------------------------------------------------------------ a5: T5 ----
@@ -1056,6 +1119,7 @@ __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Con
     uint32_t *out_o = (kKind == 0 ? b.ptc3_o : b.ptc5_o) + (size_t)sub * cap;
     const uint32_t per_row = 3u * c.nkb + 1u;
     const float two_pi = 2.0f * kPiF;
+    const unsigned long long below = (1ull << lane) - 1ull;
     uint64_t cand = 0;
     // every lane of a wave runs the same number of iterations (the wave
     // reservation below needs them all)
@@ -1120,13 +1184,25 @@ __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Con
                 walk(a3, e3);
             }
         }
-        // one reservation per wave for what the lanes still buffer
-        const uint32_t incl = wave_incl_scan(k);
-        const uint32_t tot = __shfl(incl, 63);
+        // one reservation per wave; the buffers go out column by column
+        // (entry j of every lane that has one), so that stores coalesce
+        const uint32_t tot = __shfl(wave_incl_scan(k), 63);
         uint32_t at = 0;
         if (tot != 0u && lane == 63u) at = atomicAdd(n_pairs, tot);
         at = __shfl(at, 63);
-        store(at + incl - k);
+        for (uint32_t j = 0; j < kPairBuf; j++) {
+            const bool has = j < k;
+            const unsigned long long m = __ballot(has);
+            if (m == 0ull) break;
+            if (has) {
+                const uint32_t slot = at + (uint32_t)__popcll(m & below);
+                if (slot < cap) {
+                    out_p[slot] = p;
+                    out_o[slot] = buf[j * 256u + threadIdx.x];
+                }
+            }
+            at += (uint32_t)__popcll(m);
+        }
     }
     if (stats) atomicAdd(&t->cand[4 + kKind], (unsigned long long)cand);
 }
@@ -1387,9 +1463,14 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
         L.launch("ls_place", k_ls_place, grid_for(b.cap_ls), blk, b, nsub_ls);
     }
     // a4: T3
-    L.launch("t3_count", k_t3<false>, grid_for(b.cap_ls), blk, b, t, c, stats);
+    const dim3 gt3 = grid_for(b.cap_ls);
+    const uint32_t nsub_t3 = std::min<uint32_t>(kSubLists, gt3.x);
+    L.launch("zero", k_zero_fixed, dim3(kSubLists * kSubStride / 256), blk, b.t3s_sub, kSubLists * kSubStride);
+    L.launch("t3_walk", k_t3, gt3, blk, b, t, c, nsub_t3, stats);
+    L.launch("sub_offsets", k_sub_offsets, dim3(1), dim3(kSubLists), b.t3s_sub, b.t3s_soff, b.cap_t3, nsub_t3,
+             &t->n_t3s);
     L.scan(b.t3_cnt, b.t3_off, &t->n_ls, b.cap_ls, &t->n_t3, "scan_t3");
-    L.launch("t3_fill", k_t3<true>, grid_for(b.cap_ls), blk, b, t, c, 0);
+    L.launch("t3_place", k_t3_place, grid_for(b.cap_t3), blk, b, nsub_t3);
     // a5: T5
     L.launch("t5_count", k_t5<false>, grid_for(b.cap_t3), blk, b, t, c, stats);
     L.scan(b.t5_cnt, b.t5_off, &t->n_t3, b.cap_t3, &t->n_t5, "scan_t5");
