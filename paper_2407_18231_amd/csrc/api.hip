@@ -851,7 +851,7 @@ lst_status lst_load_geometry(lst_ctx *ctx, const lst_module_desc *m, uint32_t n)
     size_t off_eb = lst::align_up(off_mdc + 16 * nm);
     size_t off_edge = lst::align_up(off_eb + 4 * (nm + 1));
     size_t off_cls = lst::align_up(off_edge + 8 * std::max<size_t>(ne, 1));
-    size_t off_sf = lst::align_up(off_cls + sizeof(lst::LsClass) * nc);
+    size_t off_sf = lst::align_up(off_cls + sizeof(lst::LsK) * nc);
     size_t total = lst::align_up(off_sf + sizeof(lst::Surface) * std::max<size_t>(ns, 1));
     std::vector<char> host(total, 0);
     std::memcpy(&host[off_kind], geom.kind.data(), 4 * nm);
@@ -862,7 +862,19 @@ lst_status lst_load_geometry(lst_ctx *ctx, const lst_module_desc *m, uint32_t n)
         uint32_t v[2] = {geom.edge_dst[i], geom.edge_cls[i]};
         std::memcpy(&host[off_edge + 8 * i], v, 8);
     }
-    if (!geom.classes.empty()) std::memcpy(&host[off_cls], geom.classes.data(), sizeof(lst::LsClass) * geom.classes.size());
+    for (size_t i = 0; i < geom.classes.size(); i++) {
+        const lst::LsClass &k = geom.classes[i];
+        float v[8] = {k.S, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (k.type == 0u) {
+            v[1] = k.rho_lo; v[2] = k.rho_hi; v[3] = k.lam_lo; v[4] = k.lam_hi; v[5] = k.tau;
+        } else if (k.type == 1u) {
+            v[1] = k.lo_fac; v[2] = k.hi_fac;
+        } else {
+            v[1] = k.cf; v[2] = k.zs; v[3] = k.zbpl; v[4] = k.zbml;
+        }
+        std::memcpy(&v[7], &k.type, 4);
+        std::memcpy(&host[off_cls + sizeof(lst::LsK) * i], v, sizeof v);
+    }
     if (ns) std::memcpy(&host[off_sf], geom.surfaces.data(), sizeof(lst::Surface) * ns);
     void *dmem = nullptr;
     if (hipMalloc(&dmem, total) != hipSuccess) return set_err(ctx, LST_ERR_OOM, "geometry allocation failed");
@@ -880,7 +892,7 @@ lst_status lst_load_geometry(lst_ctx *ctx, const lst_module_desc *m, uint32_t n)
     ctx->dg.mdc = (const float4 *)(d + off_mdc);
     ctx->dg.edge_begin = (const uint32_t *)(d + off_eb);
     ctx->dg.edge = (const uint2 *)(d + off_edge);
-    ctx->dg.cls = (const lst::LsClass *)(d + off_cls);
+    ctx->dg.cls = (const lst::LsK *)(d + off_cls);
     ctx->dg.surf = (const lst::Surface *)(d + off_sf);
     ctx->geom = std::move(geom);
     ctx->has_geom = true;

@@ -32,13 +32,22 @@ constexpr uint32_t kT3Buf = 4;      // T3: (outer LS, outer anchor, curvature) a
 constexpr uint32_t kSubLists = 256, kSubStride = 16;
 
 // Device copy of the geometry (read-only).
+// Device copy of a line-segment class (LsClass), 32 bytes:
+//   a = (S, p0, p1, p2), b = (p3, p4, 0, type bits) with
+//   barrel -> barrel: p0..p4 = rho_lo, rho_hi, lam_lo, lam_hi, tau;
+//   endcap -> endcap: p0, p1 = lo_fac, hi_fac;
+//   barrel -> endcap: p0..p3 = cf, zs, zbpl, zbml.
+struct LsK {
+    float4 a, b;
+};
+
 struct DevGeom {
     const uint32_t *mod_kind;   // n_mod
     const uint32_t *mod_surf;   // n_mod
     const float4 *mdc;          // n_mod: (S, G, K, D)
     const uint32_t *edge_begin; // n_mod + 1
     const uint2 *edge;          // (destination module, class)
-    const LsClass *cls;
+    const LsK *cls;
     const Surface *surf;        // n_surf
 };
 

@@ -340,18 +340,19 @@ __global__ void k_md_units(const Batch b, const Totals *t)
 
 // ------------------------------------------------------ a3: line segments ---
 
-__device__ inline bool ls_cut(const LsClass &k, const Consts &c, bool bend,
+__device__ inline bool ls_cut(const LsK &k, const Consts &c, bool bend,
                               float xa, float ya, float za, float ra, float beta_a,
                               float xb, float yb, float zb, float rb)
 {
+    const uint32_t type = __float_as_uint(k.b.w);
     float dx = xb - xa, dy = yb - ya;
     float cr = xa * dy - ya * dx;
     float d = xa * xb + ya * yb;
     float rr = ra * rb;
     if (!(d > 0.0f)) return false;
-    if (!(fabsf(cr) <= k.S * rr)) return false;
-    if (k.type == 0u) {
-        const float rho[2] = {k.rho_lo, k.rho_hi};
+    if (!(fabsf(cr) <= k.a.x * rr)) return false;
+    if (type == 0u) {
+        const float rho[2] = {k.a.y, k.a.z};
         const float vv[2] = {-c.L, c.L};
         const float zp[2] = {za - c.ec, za + c.ec};
         float lo = rho[0] * (zp[0] - vv[0]) + vv[0];
@@ -371,26 +372,26 @@ __device__ inline bool ls_cut(const LsClass &k, const Consts &c, bool bend,
         if (!(fabsf(zb - mid) <= half)) return false;
         if (bend) {
             float sab = cr / rr;
-            float p1 = k.lam_lo * beta_a, p2 = k.lam_hi * beta_a;
-            float blo = fminf(p1, p2) - k.tau, bhi = fmaxf(p1, p2) + k.tau;
+            float p1 = k.a.w * beta_a, p2 = k.b.x * beta_a;
+            float blo = fminf(p1, p2) - k.b.y, bhi = fmaxf(p1, p2) + k.b.y;
             float bmid = 0.5f * (blo + bhi), bhalf = 0.5f * (bhi - blo);
             if (!(fabsf(sab - bmid) <= bhalf)) return false;
         }
         return true;
     }
-    if (k.type == 1u) {
-        float lo = k.lo_fac * (ra - c.ec) - c.ec;
-        float hi = k.hi_fac * (ra + c.ec) + c.ec;
+    if (type == 1u) {
+        float lo = k.a.y * (ra - c.ec) - c.ec;
+        float hi = k.a.z * (ra + c.ec) + c.ec;
         float mid = 0.5f * (lo + hi), half = 0.5f * (hi - lo);
         return fabsf(rb - mid) <= half;
     }
-    float zap = k.zs * za;
+    float zap = k.a.z * za;
     float dhi = (zap + c.ec) + c.L;
     if (!(dhi > 0.0f)) return false;
-    float lo = (k.cf * (k.zbpl / dhi)) * ra - c.ec;
+    float lo = (k.a.y * (k.a.w / dhi)) * ra - c.ec;
     float dlo = (zap - c.ec) - c.L;
     if (dlo > 0.0f) {
-        float hi = (k.zbml / dlo) * ra + c.ec;
+        float hi = (k.b.x / dlo) * ra + c.ec;
         float mid = 0.5f * (lo + hi), half = 0.5f * (hi - lo);
         return fabsf(rb - mid) <= half;
     }
@@ -398,8 +399,11 @@ __device__ inline bool ls_cut(const LsClass &k, const Consts &c, bool bend,
 }
 
 // One thread per inner MD a: every MD of every module a's module connects to.
-// Edges are read in groups of 8 so that their MD ranges load together.
+// Edges are read in groups of 8 so that their MD ranges load together; the
+// candidates of a group then run kLsVec at a time (their positions and
+// classes load together), in (edge, outer MD) order.
 constexpr int kEdgeGroup = 8;
+constexpr int kLsVec = 2;
 
 template <typename Visit>
 __device__ inline void ls_walk(const Batch &b, const DevGeom &g, const Consts &c, bool bend, uint32_t m,
@@ -408,26 +412,50 @@ __device__ inline void ls_walk(const Batch &b, const DevGeom &g, const Consts &c
     const float xa = pa.x, ya = pa.y, za = pa.z, ra = fabsf(pa.w);
     const uint32_t e0 = g.edge_begin[m], e1 = g.edge_begin[m + 1];
     for (uint32_t eb = e0; eb < e1; eb += kEdgeGroup) {
-        uint32_t bq[kEdgeGroup], eq[kEdgeGroup], cl[kEdgeGroup];
+        uint32_t bq[kEdgeGroup], cum[kEdgeGroup + 1], cl[kEdgeGroup];
+        cum[0] = 0;
 #pragma unroll
         for (int j = 0; j < kEdgeGroup; j++) {
             bq[j] = 0;
-            eq[j] = 0;
             cl[j] = 0;
+            uint32_t eq = 0;
             if (eb + j < e1) {
                 const uint2 ed = g.edge[eb + j];
                 bq[j] = min(b.md_off[base + ed.x], b.cap_md);
-                eq[j] = min(b.md_off[base + ed.x + 1], b.cap_md);
+                eq = max(min(b.md_off[base + ed.x + 1], b.cap_md), bq[j]);
                 cl[j] = ed.y;
             }
+            cum[j + 1] = cum[j] + (eq - bq[j]);
         }
+        const uint32_t T = cum[kEdgeGroup];
+        for (uint32_t t0 = 0; t0 < T; t0 += kLsVec) {
+            uint32_t qq[kLsVec], kk[kLsVec];
 #pragma unroll
-        for (int j = 0; j < kEdgeGroup; j++) {
-            if (bq[j] >= eq[j]) continue;
-            const LsClass kc = g.cls[cl[j]];
-            for (uint32_t q = bq[j]; q < eq[j]; q++) {
-                const float4 pq = b.md_pos[q];
-                visit(q, ls_cut(kc, c, bend, xa, ya, za, ra, ba, pq.x, pq.y, pq.z, fabsf(pq.w)));
+            for (int u = 0; u < kLsVec; u++) {
+                // candidate t0 + u: the last edge j with cum[j] <= t0 + u
+                const uint32_t tt = t0 + u;
+                uint32_t q = bq[0] + tt, k = cl[0];
+#pragma unroll
+                for (int j = 1; j < kEdgeGroup; j++) {
+                    if (tt >= cum[j]) {
+                        q = bq[j] + (tt - cum[j]);
+                        k = cl[j];
+                    }
+                }
+                qq[u] = tt < T ? q : qq[0];
+                kk[u] = tt < T ? k : kk[0];
+            }
+            float4 pq[kLsVec];
+            LsK kc[kLsVec];
+#pragma unroll
+            for (int u = 0; u < kLsVec; u++) {
+                pq[u] = b.md_pos[qq[u]];
+                kc[u] = g.cls[kk[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < kLsVec; u++) {
+                if (t0 + u < T)
+                    visit(qq[u], ls_cut(kc[u], c, bend, xa, ya, za, ra, ba, pq[u].x, pq[u].y, pq[u].z, fabsf(pq[u].w)));
             }
         }
     }
@@ -585,7 +613,7 @@ __global__ __launch_bounds__(256) void k_ls_wave(const Batch b, Totals *t, const
         for (uint32_t eb = e0; eb < e1; eb += kLsLanes) {
             const uint32_t e = eb + w;
             uint32_t bb = 0, be = 0;
-            LsClass kc;
+            LsK kc;
             if (e < e1) {
                 const uint2 ed = g.edge[e];
                 bb = min(b.md_off[base + ed.x], b.cap_md);
