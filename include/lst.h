@@ -188,6 +188,11 @@ lst_status lst_batch_execute(lst_ctx *ctx, uint32_t repeats, int32_t use_graph, 
                              double *ms);
 lst_status lst_kernel_times(lst_ctx *ctx, const char **names, double *total_ms,
                             uint32_t *launches, uint32_t *n);
+/* Restrict the timing of later lst_batch_execute calls to the launches named
+ * name (as reported by lst_kernel_times); NULL or "" times every launch.
+ * With a restriction the repeats run back to back (no host wait between
+ * them).  Errors: INVALID_ARG. */
+lst_status lst_time_only(lst_ctx *ctx, const char *name);
 lst_status lst_batch_download(lst_ctx *ctx, lst_event_out **outs);
 /* Object totals of the last execute over the whole batch: md, ls, t3, t5,
  * pt3, pt5, tc; candidates examined by the md, ls, t3, t5, pt3 and pt5

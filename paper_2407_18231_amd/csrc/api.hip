@@ -164,6 +164,7 @@ void carve_work(Carver &cv, Batch &b, uint32_t n_mod, uint32_t n_surf, uint32_t 
     b.pt3_o = cv.take<uint32_t>(b.cap_pt3);
     b.pt5_p = cv.take<uint32_t>(b.cap_pt5);
     b.pt5_o = cv.take<uint32_t>(b.cap_pt5);
+    b.pls_ev = cv.take<uint32_t>(b.cap_pls);
     b.pls_used5 = cv.take<uint8_t>(b.cap_pls);
     b.pls_used3 = cv.take<uint8_t>(b.cap_pls);
     b.t5_used = cv.take<uint8_t>(b.cap_t5);
@@ -224,6 +225,7 @@ struct lst_ctx {
     void *geom_mem = nullptr;
     std::unique_ptr<lst::Slot> plain;   // per-event / batched / device-resident path
     std::map<std::string, std::pair<double, uint32_t>> ktimes;
+    std::string time_only;          // launch name that timing is restricted to (empty: all)
     std::mutex run_mu;                  // serialises the plain path
     // served path
     std::vector<std::unique_ptr<lst::Slot>> slots;
@@ -998,6 +1000,19 @@ lst_status lst_batch_execute(lst_ctx *ctx, uint32_t repeats, int32_t use_graph, 
     HIP_TRY(hipSetDevice(ctx->device));
     Slot &s = *ctx->plain;
     if (timing) ctx->ktimes.clear();
+    s.L.only = ctx->time_only.empty() ? nullptr : ctx->time_only.c_str();
+    auto drain = [&]() {
+        for (auto &rec : s.L.recs) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, rec.second.first, rec.second.second) == hipSuccess) {
+                auto &kt = ctx->ktimes[rec.first];
+                kt.first += t;
+                kt.second += 1;
+            }
+        }
+        s.L.recs.clear();
+        s.L.used = 0;
+    };
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
@@ -1005,23 +1020,16 @@ lst_status lst_batch_execute(lst_ctx *ctx, uint32_t repeats, int32_t use_graph, 
     for (uint32_t r = 0; r < repeats; r++) {
         st = enqueue(ctx, s, use_graph != 0, timing != 0, false);
         if (st != LST_OK) break;
-        if (timing) {
-            // drain the event records of this repeat so the pool stays small
+        if (timing && !s.L.only) {
+            // every launch timed: drain each repeat so the event pool stays small
             HIP_TRY(hipStreamSynchronize(s.stream));
-            for (auto &rec : s.L.recs) {
-                float t = 0.f;
-                if (hipEventElapsedTime(&t, rec.second.first, rec.second.second) == hipSuccess) {
-                    auto &kt = ctx->ktimes[rec.first];
-                    kt.first += t;
-                    kt.second += 1;
-                }
-            }
-            s.L.recs.clear();
-            s.L.used = 0;
+            drain();
         }
     }
     HIP_TRY(hipEventRecord(e1, s.stream));
     HIP_TRY(hipEventSynchronize(e1));
+    if (timing) drain();
+    s.L.only = nullptr;
     float t = 0.f;
     HIP_TRY(hipEventElapsedTime(&t, e0, e1));
     (void)hipEventDestroy(e0);
@@ -1034,6 +1042,14 @@ lst_status lst_batch_execute(lst_ctx *ctx, uint32_t repeats, int32_t use_graph, 
     s.L.timing = was_timing;
     if (st != LST_OK) return st;
     if (overflowed(s)) return set_err(ctx, LST_ERR_OOM, "object list overflow during execute");
+    return LST_OK;
+}
+
+lst_status lst_time_only(lst_ctx *ctx, const char *name)
+{
+    if (!ctx) return LST_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> g(ctx->run_mu);
+    ctx->time_only = name ? name : "";
     return LST_OK;
 }
 

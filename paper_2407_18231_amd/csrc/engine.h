@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <string>
 #include <utility>
+#include <cstring>
 #include <vector>
 
 #include "lst_internal.h"
@@ -135,6 +136,7 @@ struct Batch {
     uint32_t *pt5_p, *pt5_o;
     // a8: track candidates over [pT3 | T5 | pLS]
     uint8_t *pls_used5, *pls_used3, *t5_used;
+    uint32_t *pls_ev;                   // event of each seed
     uint32_t *tc_cnt, *tc_off, *tc_type, *tc_idx;
     uint32_t *ev_tab;                   // (cap_ev + 1) x kEvTabCols
 };
@@ -145,6 +147,7 @@ struct Launcher {
     hipStream_t stream = nullptr;
     uint32_t *part = nullptr;           // scan partials, kScanGrid entries
     bool timing = false;
+    const char *only = nullptr;         // with timing: time only the launches of this name (nullptr: all)
     std::vector<hipEvent_t> pool;
     size_t used = 0;
     std::vector<std::pair<const char *, std::pair<hipEvent_t, hipEvent_t>>> recs;
@@ -164,7 +167,8 @@ struct Launcher {
     void launch(const char *name, void (*kernel)(KArgs...), dim3 grid, dim3 block, Args... args)
     {
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (timing) {
+        const bool timed = timing && (only == nullptr || std::strcmp(only, name) == 0);
+        if (timed) {
             e0 = next_event();
             e1 = next_event();
             if (e0) (void)hipEventRecord(e0, stream);
@@ -172,7 +176,7 @@ struct Launcher {
         kernel<<<grid, block, 0, stream>>>(args...);
         hipError_t le = hipGetLastError();
         if (le != hipSuccess && err == hipSuccess) err = le;
-        if (timing && e1) {
+        if (timed && e1) {
             (void)hipEventRecord(e1, stream);
             recs.push_back({name, {e0, e1}});
         }

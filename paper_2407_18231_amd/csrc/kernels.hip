@@ -211,10 +211,13 @@ __global__ void k_hit_hist(const Batch b, Totals *t, uint32_t n_mod)
     }
 }
 
+// seeds: finite parameters; the event of each seed
 __global__ void k_pls_check(const Batch b, Totals *t)
 {
     const uint32_t n = min(t->n_pls, b.cap_pls);
+    const uint32_t n_ev = t->n_ev;
     GRID_STRIDE(p, n) {
+        b.pls_ev[p] = find_event(b.ev_pls_off, n_ev, p);
         bool ok = true;
         for (int k = 0; k < 5; k++) ok = ok && isfinite(b.in_par[5 * p + k]);
         for (int k = 0; k < 15; k++) ok = ok && isfinite(b.in_cov[15 * p + k]);
@@ -1136,7 +1139,6 @@ __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Con
 {
     __shared__ uint32_t buf[kPairBuf * 256];
     const uint32_t n = min(t->n_pls, b.cap_pls) * c.n_surf;
-    const uint32_t n_ev = t->n_ev;
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t *bk_off = kKind == 0 ? b.bk3_off : b.bk5_off;
     const float4 *bks = kKind == 0 ? b.bk3_ks : b.bk5_ks;
@@ -1170,7 +1172,7 @@ __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Con
             const float *cov = b.in_cov + 15 * (size_t)p;
             const double kp = (double)par[0] * c.kB;
             const double skp = c.kB * sqrt((double)cov[0]);
-            const uint32_t e = find_event(b.ev_pls_off, n_ev, p);
+            const uint32_t e = b.pls_ev[p];
             const uint32_t row0 = (e * c.n_surf + sfi) * c.nphi;
             const uint32_t first = r.x & 0xFFFFu, nbins = r.x >> 16;
             const uint32_t kr0 = r.y & 0xFFFFu, kr1 = r.y >> 16, kr2 = r.z & 0xFFFFu;

@@ -95,6 +95,7 @@ def load(path: str = LIB_PATH):
         "lst_kernel_times": (C.c_int32, [C.c_void_p, _P(C.c_char_p), _P(C.c_double), _P(C.c_uint32), _P(C.c_uint32)]),
         "lst_batch_download": (C.c_int32, [C.c_void_p, _P(_P(lst_event_out))]),
         "lst_batch_counts": (C.c_int32, [C.c_void_p, _P(C.c_uint64)]),
+        "lst_time_only": (C.c_int32, [C.c_void_p, C.c_char_p]),
         "lst_free_output": (None, [_P(lst_event_out)]),
         "lst_destroy": (None, [C.c_void_p]),
         "lst_status_str": (C.c_char_p, [C.c_int32]),
@@ -318,6 +319,11 @@ class Context:
             res.append(_out_to_dict(o.contents))
             self.L.lst_free_output(o)
         return res
+
+    def time_only(self, name: str | None):
+        """Restrict batch_execute(timing=True) to the launches of this name
+        (None: every launch)."""
+        self._check(self.L.lst_time_only(self.h, name.encode() if name else None))
 
     def batch_counts(self) -> dict:
         v = (C.c_uint64 * 15)()
