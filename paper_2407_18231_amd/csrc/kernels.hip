@@ -211,6 +211,10 @@ __global__ void k_hit_hist(const Batch b, Totals *t, uint32_t n_mod)
     }
 }
 
+// four consecutive hits per thread in the scatter: their loads, then their
+// offset gathers, are in flight together
+constexpr uint32_t kHitsPerThread = 4;
+
 // seeds: finite parameters; the event of each seed
 __global__ void k_pls_check(const Batch b, Totals *t)
 {
@@ -225,24 +229,71 @@ __global__ void k_pls_check(const Batch b, Totals *t)
     }
 }
 
-// each hit's record to its bin (coalesced reads, one 16-byte write per hit)
+// each hit's record to its bin (coalesced reads, one 16-byte write per hit;
+// four hits per thread)
 __global__ void k_hit_scatter(const Batch b, const Totals *t)
 {
     const uint32_t n = min(t->n_hits, b.cap_hits);
-    GRID_STRIDE(h, n) {
-        uint32_t bin = b.hbin[h];
-        if (bin == kInvalid) continue;
-        b.hrec[b.bin_off[bin] + b.hrank[h]] = make_float4(b.in_x[h], b.in_y[h], b.in_z[h], __uint_as_float(h));
+    const uint32_t nq = (n + kHitsPerThread - 1) / kHitsPerThread;
+    GRID_STRIDE(qd, nq) {
+        const uint32_t h0 = qd * kHitsPerThread;
+        uint32_t bin[kHitsPerThread], rank[kHitsPerThread], dst[kHitsPerThread];
+        float4 v[kHitsPerThread];
+#pragma unroll
+        for (uint32_t k = 0; k < kHitsPerThread; k++) {
+            const uint32_t h = min(h0 + k, n - 1u);
+            bin[k] = h0 + k < n ? b.hbin[h] : kInvalid;
+            rank[k] = b.hrank[h];
+            v[k] = make_float4(b.in_x[h], b.in_y[h], b.in_z[h], __uint_as_float(h));
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < kHitsPerThread; k++) dst[k] = bin[k] != kInvalid ? b.bin_off[bin[k]] + rank[k] : 0u;
+#pragma unroll
+        for (uint32_t k = 0; k < kHitsPerThread; k++)
+            if (bin[k] != kInvalid) b.hrec[dst[k]] = v[k];
     }
 }
 
 // per (event, module, sensor) bin: restore input order (the scatter used
-// atomic slots) and write the sorted SoA with r = sqrt(x^2 + y^2)
+// atomic slots) and write the sorted SoA with r = sqrt(x^2 + y^2).  Bins of
+// up to four hits sort in registers.
 __global__ void k_hit_gather(const Batch b, const Totals *t, uint32_t n_mod)
 {
     const uint32_t nb = t->n_bins;
     GRID_STRIDE(bin, nb) {
         const uint32_t beg = b.bin_off[bin], end = b.bin_off[bin + 1];
+        if (beg == end) continue;
+        const uint32_t e = bin / (2u * n_mod);
+        const uint32_t h0 = b.ev_hit_off[e];
+        auto put = [&](uint32_t i, const float4 v) {
+            b.hpos[i] = make_float4(v.x, v.y, v.z, sqrtf(v.x * v.x + v.y * v.y));
+            b.hin[i] = __float_as_uint(v.w) - h0;
+            b.hbin_s[i] = bin;
+        };
+        if (end - beg <= 4u) {
+            float4 v[4];
+#pragma unroll
+            for (uint32_t k = 0; k < 4; k++)
+                v[k] = beg + k < end ? b.hrec[beg + k] : make_float4(0.f, 0.f, 0.f, __uint_as_float(0xFFFFFFFFu));
+            // sorting network on the input index (padding, with the largest
+            // key, sorts last and is not written)
+            auto cswap = [&](int i, int j) {
+                if (__float_as_uint(v[i].w) > __float_as_uint(v[j].w)) {
+                    const float4 tmp = v[i];
+                    v[i] = v[j];
+                    v[j] = tmp;
+                }
+            };
+            cswap(0, 1);
+            cswap(2, 3);
+            cswap(0, 2);
+            cswap(1, 3);
+            cswap(1, 2);
+#pragma unroll
+            for (uint32_t k = 0; k < 4; k++)
+                if (beg + k < end) put(beg + k, v[k]);
+            continue;
+        }
         for (uint32_t i = beg + 1; i < end; i++) {
             const float4 v = b.hrec[i];
             const uint32_t key = __float_as_uint(v.w);
@@ -253,14 +304,7 @@ __global__ void k_hit_gather(const Batch b, const Totals *t, uint32_t n_mod)
             }
             b.hrec[j] = v;
         }
-        const uint32_t e = bin / (2u * n_mod);
-        const uint32_t h0 = b.ev_hit_off[e];
-        for (uint32_t i = beg; i < end; i++) {
-            const float4 v = b.hrec[i];
-            b.hpos[i] = make_float4(v.x, v.y, v.z, sqrtf(v.x * v.x + v.y * v.y));
-            b.hin[i] = __float_as_uint(v.w) - h0;
-            b.hbin_s[i] = bin;
-        }
+        for (uint32_t i = beg; i < end; i++) put(i, b.hrec[i]);
     }
 }
 
