@@ -153,8 +153,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-events", type=int, default=8)
-    ap.add_argument("--cpu-budget", type=float, default=25.0)
+    ap.add_argument("--cpu-events", type=int, default=32)
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--quick", action="store_true", help="only the batched path (profiling runs)")
     ap.add_argument("--chain-only", type=int, default=0, metavar="N",
                     help="counter runs: upload one batch, run the chain N times, print nothing else")
