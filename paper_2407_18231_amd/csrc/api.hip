@@ -110,7 +110,7 @@ void carve_work(Carver &cv, Batch &b, uint32_t n_mod, uint32_t n_surf, uint32_t 
     b.lss_a = cv.take<uint32_t>(b.cap_ls);
     b.lss_b = cv.take<uint32_t>(b.cap_ls);
     b.lss_j = cv.take<uint32_t>(b.cap_ls);
-    b.lss_sub = cv.take<uint32_t>((size_t)kSubLists * kSubStride);
+    b.lss_sub = cv.take<uint32_t>(kSubLists);
     b.lss_soff = cv.take<uint32_t>(kSubLists + 1);
     b.t3_cnt = cv.take<uint32_t>((size_t)b.cap_ls + 1);
     b.t3_off = cv.take<uint32_t>((size_t)b.cap_ls + 1);
@@ -121,7 +121,7 @@ void carve_work(Carver &cv, Batch &b, uint32_t n_mod, uint32_t n_surf, uint32_t 
     b.t3s_j = cv.take<uint32_t>(b.cap_t3);
     b.t3s_ac = cv.take<uint2>(b.cap_t3);
     b.t3s_ks = cv.take<float2>(b.cap_t3);
-    b.t3s_sub = cv.take<uint32_t>((size_t)kSubLists * kSubStride);
+    b.t3s_sub = cv.take<uint32_t>(kSubLists);
     b.t3s_soff = cv.take<uint32_t>(kSubLists + 1);
     b.t3_ac = cv.take<uint2>(b.cap_t3);
     b.t3_ks = cv.take<float2>(b.cap_t3);
@@ -148,8 +148,8 @@ void carve_work(Carver &cv, Batch &b, uint32_t n_mod, uint32_t n_surf, uint32_t 
     b.ptc5_p = cv.take<uint32_t>(b.cap_ptc5);
     b.ptc5_o = cv.take<uint32_t>(b.cap_ptc5);
     b.ptc5_rank = cv.take<uint32_t>(b.cap_ptc5);
-    b.ptc3_sub = cv.take<uint32_t>((size_t)kSubLists * kSubStride);
-    b.ptc5_sub = cv.take<uint32_t>((size_t)kSubLists * kSubStride);
+    b.ptc3_sub = cv.take<uint32_t>(kSubLists);
+    b.ptc5_sub = cv.take<uint32_t>(kSubLists);
     b.ptc3_soff = cv.take<uint32_t>(kSubLists + 1);
     b.ptc5_soff = cv.take<uint32_t>(kSubLists + 1);
     b.pt3_cnt = cv.take<uint32_t>((size_t)b.cap_pls + 1);

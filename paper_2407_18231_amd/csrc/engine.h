@@ -27,10 +27,11 @@ constexpr uint32_t kKeepLs = 8;
 constexpr uint32_t kPairBuf = 16;   // seed lookup: candidate pairs a thread buffers in LDS
 constexpr uint32_t kSegBuf = 16;    // segments: outer MDs a thread buffers in LDS
 constexpr uint32_t kT3Buf = 4;      // T3: (outer LS, outer anchor, curvature) a thread buffers in LDS
-// The candidate-pair list is split into kSubLists equal parts, each with its
-// own append counter (kSubStride words apart), so that appends from
-// different blocks do not contend on one address.
-constexpr uint32_t kSubLists = 256, kSubStride = 16;
+// Lists that a walk appends to in no particular order (segments, T3s,
+// seed-object pairs) are split into one equal region per block of the walk
+// (at most kSubLists): a block counts its appends in LDS and publishes the
+// count when it ends, so appends never wait on a global atomic.
+constexpr uint32_t kSubLists = kMaxGrid;
 
 // Device copy of the geometry (read-only).
 // Device copy of a line-segment class (LsClass), 32 bytes:
@@ -128,8 +129,8 @@ struct Batch {
     // (tp, to) and after (p, o) the per-seed order by object
     uint32_t *ptc3_p, *ptc3_o, *ptc3_rank;
     uint32_t *ptc5_p, *ptc5_o, *ptc5_rank;
-    uint32_t *ptc3_sub, *ptc5_sub;      // append counters of the sub-lists
-    uint32_t *ptc3_soff, *ptc5_soff;    // dense offsets of the sub-lists (kSubLists + 1)
+    uint32_t *ptc3_sub, *ptc5_sub;      // appends per block region
+    uint32_t *ptc3_soff, *ptc5_soff;    // dense offsets of the regions (kSubLists + 1)
     uint32_t *pt3_cnt, *pt3_off, *pt5_cnt, *pt5_off;
     uint32_t *pt3_tp, *pt3_to, *pt5_tp, *pt5_to;
     uint32_t *pt3_p, *pt3_o;

@@ -144,11 +144,11 @@ __device__ inline uint32_t find_event(const uint32_t *__restrict__ off, uint32_t
     return lo;
 }
 
-// dense pair index j (< total) to its slot: the sub-list s with
-// soff[s] <= j < soff[s + 1]
-__device__ inline uint32_t pair_slot(const uint32_t *s_off, uint32_t j, uint32_t subcap)
+// dense index j (< total) of a list split into block regions to its slot:
+// the region s with soff[s] <= j < soff[s + 1], s < nsub
+__device__ inline uint32_t pair_slot(const uint32_t *s_off, uint32_t j, uint32_t subcap, uint32_t nsub)
 {
-    uint32_t lo = 0, hi = kSubLists;
+    uint32_t lo = 0, hi = nsub;
     while (hi - lo > 1u) {
         const uint32_t mid = (lo + hi) >> 1;
         if (s_off[mid] <= j) lo = mid;
@@ -166,11 +166,6 @@ __global__ void k_zero_u32(uint32_t *__restrict__ p, const uint32_t *n_ptr, uint
 __global__ void k_zero_u8(uint8_t *__restrict__ p, const uint32_t *n_ptr, uint32_t cap)
 {
     const uint32_t n = min(*n_ptr, cap);
-    GRID_STRIDE(i, n) p[i] = 0u;
-}
-
-__global__ void k_zero_fixed(uint32_t *__restrict__ p, uint32_t n)
-{
     GRID_STRIDE(i, n) p[i] = 0u;
 }
 
@@ -445,145 +440,150 @@ __device__ inline bool ls_cut(const LsK &k, const Consts &c, bool bend,
     return lo <= rb;
 }
 
-// One thread per inner MD a: every MD of every module a's module connects to.
-// Edges are read in groups of 8 so that their MD ranges load together; the
-// candidates of a group then run kLsVec at a time (their positions and
-// classes load together), in (edge, outer MD) order.
+// Large batches: one thread per inner MD a, one pass over every MD of every
+// module that a's module connects to.  Edges are read in groups of 8 so that
+// their MD ranges load together; the candidates of a group then run kLsVec
+// at a time (their positions and 32-byte classes load together), in (edge,
+// outer MD) order.  The walk is wave-uniform (a wave steps while any lane
+// has candidates left), so that survivors, buffered per thread in LDS, can
+// leave whenever a buffer may fill: the wave reserves space in its block's
+// sub-list of an unordered segment list with one atomic and stores column by
+// column (entry j of every lane), so the stores coalesce.  Each segment
+// carries its place in a's list; k_ls_place moves it to its canonical slot
+// once the per-MD counts are scanned (edges are sorted by destination
+// module, so walk order is canonical order).
 constexpr int kEdgeGroup = 8;
 constexpr int kLsVec = 2;
 
-template <typename Visit>
-__device__ inline void ls_walk(const Batch &b, const DevGeom &g, const Consts &c, bool bend, uint32_t m,
-                               uint32_t base, const float4 &pa, float ba, Visit visit)
-{
-    const float xa = pa.x, ya = pa.y, za = pa.z, ra = fabsf(pa.w);
-    const uint32_t e0 = g.edge_begin[m], e1 = g.edge_begin[m + 1];
-    for (uint32_t eb = e0; eb < e1; eb += kEdgeGroup) {
-        uint32_t bq[kEdgeGroup], cum[kEdgeGroup + 1], cl[kEdgeGroup];
-        cum[0] = 0;
-#pragma unroll
-        for (int j = 0; j < kEdgeGroup; j++) {
-            bq[j] = 0;
-            cl[j] = 0;
-            uint32_t eq = 0;
-            if (eb + j < e1) {
-                const uint2 ed = g.edge[eb + j];
-                bq[j] = min(b.md_off[base + ed.x], b.cap_md);
-                eq = max(min(b.md_off[base + ed.x + 1], b.cap_md), bq[j]);
-                cl[j] = ed.y;
-            }
-            cum[j + 1] = cum[j] + (eq - bq[j]);
-        }
-        const uint32_t T = cum[kEdgeGroup];
-        for (uint32_t t0 = 0; t0 < T; t0 += kLsVec) {
-            uint32_t qq[kLsVec], kk[kLsVec];
-#pragma unroll
-            for (int u = 0; u < kLsVec; u++) {
-                // candidate t0 + u: the last edge j with cum[j] <= t0 + u
-                const uint32_t tt = t0 + u;
-                uint32_t q = bq[0] + tt, k = cl[0];
-#pragma unroll
-                for (int j = 1; j < kEdgeGroup; j++) {
-                    if (tt >= cum[j]) {
-                        q = bq[j] + (tt - cum[j]);
-                        k = cl[j];
-                    }
-                }
-                qq[u] = tt < T ? q : qq[0];
-                kk[u] = tt < T ? k : kk[0];
-            }
-            float4 pq[kLsVec];
-            LsK kc[kLsVec];
-#pragma unroll
-            for (int u = 0; u < kLsVec; u++) {
-                pq[u] = b.md_pos[qq[u]];
-                kc[u] = g.cls[kk[u]];
-            }
-#pragma unroll
-            for (int u = 0; u < kLsVec; u++) {
-                if (t0 + u < T)
-                    visit(qq[u], ls_cut(kc[u], c, bend, xa, ya, za, ra, ba, pq[u].x, pq[u].y, pq[u].z, fabsf(pq[u].w)));
-            }
-        }
-    }
-}
-
-// Large batches: one thread per inner MD, one pass.  Survivors collect in a
-// per-thread LDS buffer and go, with their place in the MD's list, to the
-// block's sub-list of an unordered segment list (one reservation per wave; a
-// thread whose buffer fills flushes it alone); k_ls_place moves them to their
-// canonical slots once the per-MD counts are scanned.  The walk meets the
-// outer MDs in increasing order (edges are sorted by destination module), so
-// the place in the list is the canonical one.
 __global__ __launch_bounds__(256) void k_ls(const Batch b, Totals *t, const DevGeom g, const Consts c,
                                             uint32_t nsub, int stats)
 {
+    static_assert(kSegBuf >= 2 * kLsVec, "buffer holds at least two steps");
     __shared__ uint32_t buf[kSegBuf * 256];
     const uint32_t n = min(t->n_md, b.cap_md);
     const uint32_t n_mod = c.n_mod;
     const bool bend = (c.flags & LST_FLAG_BEND) != 0u;
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t sub = blockIdx.x % nsub;
+    __shared__ uint32_t s_n;             // appends to this block's region
     const uint32_t cap = b.cap_ls / nsub;
-    uint32_t *n_seg = b.lss_sub + sub * kSubStride;
-    uint32_t *sa = b.lss_a + (size_t)sub * cap;
-    uint32_t *sb = b.lss_b + (size_t)sub * cap;
-    uint32_t *sj = b.lss_j + (size_t)sub * cap;
+    uint32_t *n_seg = &s_n;
+    uint32_t *sa = b.lss_a + (size_t)blockIdx.x * cap;
+    uint32_t *sb = b.lss_b + (size_t)blockIdx.x * cap;
+    uint32_t *sj = b.lss_j + (size_t)blockIdx.x * cap;
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
     const unsigned long long below = (1ull << lane) - 1ull;
     uint64_t cand = 0;
-    // every lane of a wave runs the same number of iterations (the wave
-    // reservation below needs them all)
+    // every lane of a wave runs the same number of iterations and steps
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
         const uint32_t a = base + threadIdx.x;
         uint32_t kb = 0, k = 0;          // buffered, found so far
-        auto store = [&](uint32_t at) {
-            for (uint32_t j = 0; j < kb; j++) {
-                if (at + j < cap) {
-                    sa[at + j] = a;
-                    sb[at + j] = buf[j * 256u + threadIdx.x];
-                    sj[at + j] = k - kb + j;
+        auto flush = [&]() {
+            const uint32_t tot = __shfl(wave_incl_scan(kb), 63);
+            uint32_t at = 0;
+            if (tot != 0u && lane == 63u) at = atomicAdd(n_seg, tot);
+            at = __shfl(at, 63);
+            for (uint32_t j = 0; j < kSegBuf; j++) {
+                const bool has = j < kb;
+                const unsigned long long mk = __ballot(has);
+                if (mk == 0ull) break;
+                if (has) {
+                    const uint32_t slot = at + (uint32_t)__popcll(mk & below);
+                    if (slot < cap) {
+                        sa[slot] = a;
+                        sb[slot] = buf[j * 256u + threadIdx.x];
+                        sj[slot] = k - kb + j;
+                    }
                 }
+                at += (uint32_t)__popcll(mk);
             }
+            kb = 0;
         };
+        uint32_t e_cur = 0, e_end = 0, ubase = 0;
+        float xa = 0.f, ya = 0.f, za = 0.f, ra = 0.f, ba = 0.f;
         if (a < n) {
             const uint32_t u = b.md_u[a] & kUnitMask;
             const uint32_t m = u % n_mod;
+            ubase = u - m;
+            e_cur = g.edge_begin[m];
+            e_end = g.edge_begin[m + 1];
             const float4 pa = b.md_pos[a];
-            const float ba = b.md_beta[a];
-            ls_walk(b, g, c, bend, m, u - m, pa, ba, [&](uint32_t q, bool pass) {
-                cand++;
-                if (!pass) return;
-                if (kb == kSegBuf) {
-                    store(atomicAdd(n_seg, kb));
-                    kb = 0;
-                }
-                buf[kb * 256u + threadIdx.x] = q;
-                kb++;
-                k++;
-            });
-            b.ls_cnt[a] = k;
+            xa = pa.x;
+            ya = pa.y;
+            za = pa.z;
+            ra = fabsf(pa.w);
+            ba = b.md_beta[a];
         }
-        // one reservation per wave; the buffers go out column by column
-        // (entry j of every lane that has one), so that stores coalesce
-        const uint32_t tot = __shfl(wave_incl_scan(kb), 63);
-        uint32_t at = 0;
-        if (tot != 0u && lane == 63u) at = atomicAdd(n_seg, tot);
-        at = __shfl(at, 63);
-        for (uint32_t j = 0; j < kSegBuf; j++) {
-            const bool has = j < kb;
-            const unsigned long long m = __ballot(has);
-            if (m == 0ull) break;
-            if (has) {
-                const uint32_t slot = at + (uint32_t)__popcll(m & below);
-                if (slot < cap) {
-                    sa[slot] = a;
-                    sb[slot] = buf[j * 256u + threadIdx.x];
-                    sj[slot] = k - kb + j;
+        uint32_t bq[kEdgeGroup], cum[kEdgeGroup + 1], cl[kEdgeGroup];
+        uint32_t T = 0, t0 = 0;
+        while (true) {
+            if (t0 >= T && e_cur < e_end) {
+                // next group of edges and their MD ranges
+                cum[0] = 0;
+#pragma unroll
+                for (int j = 0; j < kEdgeGroup; j++) {
+                    bq[j] = 0;
+                    cl[j] = 0;
+                    uint32_t eq = 0;
+                    if (e_cur + j < e_end) {
+                        const uint2 ed = g.edge[e_cur + j];
+                        bq[j] = min(b.md_off[ubase + ed.x], b.cap_md);
+                        eq = max(min(b.md_off[ubase + ed.x + 1], b.cap_md), bq[j]);
+                        cl[j] = ed.y;
+                    }
+                    cum[j + 1] = cum[j] + (eq - bq[j]);
                 }
+                T = cum[kEdgeGroup];
+                t0 = 0;
+                e_cur += kEdgeGroup;
             }
-            at += (uint32_t)__popcll(m);
+            const bool has = t0 < T;
+            if (__ballot(has || e_cur < e_end) == 0ull) break;
+            if (has) {
+                uint32_t qq[kLsVec], kk[kLsVec];
+#pragma unroll
+                for (int v = 0; v < kLsVec; v++) {
+                    // candidate t0 + v: the last edge j with cum[j] <= t0 + v
+                    const uint32_t tt = t0 + v;
+                    uint32_t q = bq[0] + tt, kx = cl[0];
+#pragma unroll
+                    for (int j = 1; j < kEdgeGroup; j++) {
+                        if (tt >= cum[j]) {
+                            q = bq[j] + (tt - cum[j]);
+                            kx = cl[j];
+                        }
+                    }
+                    qq[v] = tt < T ? q : qq[0];
+                    kk[v] = tt < T ? kx : kk[0];
+                }
+                float4 pq[kLsVec];
+                LsK kc[kLsVec];
+#pragma unroll
+                for (int v = 0; v < kLsVec; v++) {
+                    pq[v] = b.md_pos[qq[v]];
+                    kc[v] = g.cls[kk[v]];
+                }
+#pragma unroll
+                for (int v = 0; v < kLsVec; v++) {
+                    if (t0 + v < T) {
+                        cand++;
+                        if (ls_cut(kc[v], c, bend, xa, ya, za, ra, ba, pq[v].x, pq[v].y, pq[v].z, fabsf(pq[v].w))) {
+                            buf[kb * 256u + threadIdx.x] = qq[v];
+                            kb++;
+                            k++;
+                        }
+                    }
+                }
+                t0 += kLsVec;
+            }
+            // a buffer that could overflow on the next step goes out now
+            if (__ballot(kb + kLsVec > kSegBuf) != 0ull) flush();
         }
+        if (a < n) b.ls_cnt[a] = k;
+        flush();
     }
+    __syncthreads();
+    if (threadIdx.x == 0) b.lss_sub[blockIdx.x] = s_n;
     if (stats) atomicAdd(&t->cand[1], (unsigned long long)cand);
 }
 
@@ -591,12 +591,12 @@ __global__ __launch_bounds__(256) void k_ls(const Batch b, Totals *t, const DevG
 __global__ __launch_bounds__(256) void k_ls_place(const Batch b, uint32_t nsub)
 {
     __shared__ uint32_t s_off[kSubLists + 1];
-    for (uint32_t i = threadIdx.x; i <= kSubLists; i += blockDim.x) s_off[i] = b.lss_soff[i];
+    for (uint32_t i = threadIdx.x; i <= nsub; i += blockDim.x) s_off[i] = b.lss_soff[i];
     __syncthreads();
-    const uint32_t n = s_off[kSubLists];
+    const uint32_t n = s_off[nsub];
     const uint32_t subcap = b.cap_ls / nsub;
     GRID_STRIDE(j, n) {
-        const uint32_t i = pair_slot(s_off, j, subcap);
+        const uint32_t i = pair_slot(s_off, j, subcap, nsub);
         const uint32_t a = b.lss_a[i];
         const uint32_t k = b.ls_off[a] + b.lss_j[i];
         if (k < b.cap_ls) {
@@ -786,10 +786,12 @@ __global__ __launch_bounds__(256) void k_t3(const Batch b, Totals *t, const Cons
     const uint32_t n = min(t->n_ls, b.cap_ls);
     const uint32_t lane = threadIdx.x & 63u;
     const unsigned long long below = (1ull << lane) - 1ull;
-    const uint32_t sub = blockIdx.x % nsub;
+    __shared__ uint32_t s_n;             // appends to this block's region
     const uint32_t cap = b.cap_t3 / nsub;
-    uint32_t *n_t3 = b.t3s_sub + sub * kSubStride;
-    const size_t sb0 = (size_t)sub * cap;
+    uint32_t *n_t3 = &s_n;
+    const size_t sb0 = (size_t)blockIdx.x * cap;
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
     uint64_t cand = 0;
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
         const uint32_t l1 = base + threadIdx.x;
@@ -852,6 +854,8 @@ __global__ __launch_bounds__(256) void k_t3(const Batch b, Totals *t, const Cons
             at += (uint32_t)__popcll(m);
         }
     }
+    __syncthreads();
+    if (threadIdx.x == 0) b.t3s_sub[blockIdx.x] = s_n;
     if (stats) atomicAdd(&t->cand[2], (unsigned long long)cand);
 }
 
@@ -859,12 +863,12 @@ __global__ __launch_bounds__(256) void k_t3(const Batch b, Totals *t, const Cons
 __global__ __launch_bounds__(256) void k_t3_place(const Batch b, uint32_t nsub)
 {
     __shared__ uint32_t s_off[kSubLists + 1];
-    for (uint32_t i = threadIdx.x; i <= kSubLists; i += blockDim.x) s_off[i] = b.t3s_soff[i];
+    for (uint32_t i = threadIdx.x; i <= nsub; i += blockDim.x) s_off[i] = b.t3s_soff[i];
     __syncthreads();
-    const uint32_t n = s_off[kSubLists];
+    const uint32_t n = s_off[nsub];
     const uint32_t subcap = b.cap_t3 / nsub;
     GRID_STRIDE(j, n) {
-        const uint32_t i = pair_slot(s_off, j, subcap);
+        const uint32_t i = pair_slot(s_off, j, subcap, nsub);
         const uint32_t l1 = b.t3s_l1[i];
         const uint32_t k = b.t3_off[l1] + b.t3s_j[i];
         if (k < b.cap_t3) {
@@ -1186,11 +1190,13 @@ __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Con
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t *bk_off = kKind == 0 ? b.bk3_off : b.bk5_off;
     const float4 *bks = kKind == 0 ? b.bk3_ks : b.bk5_ks;
-    const uint32_t sub = blockIdx.x % nsub;
+    __shared__ uint32_t s_n;             // appends to this block's region
     const uint32_t cap = (kKind == 0 ? b.cap_ptc3 : b.cap_ptc5) / nsub;
-    uint32_t *n_pairs = (kKind == 0 ? b.ptc3_sub : b.ptc5_sub) + sub * kSubStride;
-    uint32_t *out_p = (kKind == 0 ? b.ptc3_p : b.ptc5_p) + (size_t)sub * cap;
-    uint32_t *out_o = (kKind == 0 ? b.ptc3_o : b.ptc5_o) + (size_t)sub * cap;
+    uint32_t *n_pairs = &s_n;
+    uint32_t *out_p = (kKind == 0 ? b.ptc3_p : b.ptc5_p) + (size_t)blockIdx.x * cap;
+    uint32_t *out_o = (kKind == 0 ? b.ptc3_o : b.ptc5_o) + (size_t)blockIdx.x * cap;
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
     const uint32_t per_row = 3u * c.nkb + 1u;
     const float two_pi = 2.0f * kPiF;
     const unsigned long long below = (1ull << lane) - 1ull;
@@ -1278,34 +1284,44 @@ __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Con
             at += (uint32_t)__popcll(m);
         }
     }
+    __syncthreads();
+    if (threadIdx.x == 0) (kKind == 0 ? b.ptc3_sub : b.ptc5_sub)[blockIdx.x] = s_n;
     if (stats) atomicAdd(&t->cand[4 + kKind], (unsigned long long)cand);
 }
 
-// Sizes of the nsub sub-lists in use to dense offsets (one block of
-// kSubLists threads; offsets past nsub hold the total).  need receives the
-// total or, when a sub-list overflowed, the list capacity that holds it (the
-// host then grows the list and runs the batch again).
-__global__ __launch_bounds__(kSubLists) void k_sub_offsets(const uint32_t *__restrict__ sub,
-                                                           uint32_t *__restrict__ soff, uint32_t cap_total,
-                                                           uint32_t nsub, uint32_t *need)
+// Region sizes (nsub <= kSubLists, one block of 256 threads, each summing a
+// run of consecutive regions) to dense offsets soff[0..nsub].  need receives
+// the total or, when a region overflowed, the list capacity that holds it
+// (the host then grows the list and runs the batch again).
+__global__ __launch_bounds__(256) void k_sub_offsets(const uint32_t *__restrict__ sub,
+                                                     uint32_t *__restrict__ soff, uint32_t cap_total,
+                                                     uint32_t nsub, uint32_t *need)
 {
-    static_assert(kSubLists == (uint32_t)kScanBlock, "one sub-list per thread");
     __shared__ uint32_t s_max;
     const uint32_t cap = cap_total / nsub;
+    const uint32_t per = (nsub + 255u) / 256u;
+    const uint32_t i0 = min(threadIdx.x * per, nsub), i1 = min(i0 + per, nsub);
     if (threadIdx.x == 0) s_max = 0;
     __syncthreads();
-    const uint32_t v = threadIdx.x < nsub ? sub[threadIdx.x * kSubStride] : 0u;
-    if (v > cap) atomicMax(&s_max, v);
+    uint32_t sum = 0, vmax = 0;
+    for (uint32_t i = i0; i < i1; i++) {
+        const uint32_t v = sub[i];
+        vmax = max(vmax, v);
+        sum += min(v, cap);
+    }
+    if (vmax > cap) atomicMax(&s_max, vmax);
     uint32_t tot;
-    const uint32_t ex = block_excl_scan(min(v, cap), tot);
-    soff[threadIdx.x] = ex;
+    uint32_t ex = block_excl_scan(sum, tot);
+    for (uint32_t i = i0; i < i1; i++) {
+        soff[i] = ex;
+        ex += min(sub[i], cap);
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        soff[kSubLists] = tot;
+        soff[nsub] = tot;
         *need = s_max > cap ? (uint32_t)min(0xFFFFFFF0ull, (unsigned long long)s_max * nsub) : tot;
     }
 }
-
 
 // full seed cuts, one thread per pair; an accepted pair draws its rank
 // among the accepted pairs of its seed
@@ -1314,16 +1330,16 @@ __global__ __launch_bounds__(256) void k_pt_eval(const Batch b, const Consts c, 
 {
     __shared__ uint32_t s_off[kSubLists + 1];
     const uint32_t *soff = kKind == 0 ? b.ptc3_soff : b.ptc5_soff;
-    for (uint32_t i = threadIdx.x; i <= kSubLists; i += blockDim.x) s_off[i] = soff[i];
+    for (uint32_t i = threadIdx.x; i <= nsub; i += blockDim.x) s_off[i] = soff[i];
     __syncthreads();
-    const uint32_t n = s_off[kSubLists];
+    const uint32_t n = s_off[nsub];
     const uint32_t subcap = (kKind == 0 ? b.cap_ptc3 : b.cap_ptc5) / nsub;
     const uint32_t *cp = kKind == 0 ? b.ptc3_p : b.ptc5_p;
     const uint32_t *co = kKind == 0 ? b.ptc3_o : b.ptc5_o;
     uint32_t *rank = kKind == 0 ? b.ptc3_rank : b.ptc5_rank;
     uint32_t *pcnt = kKind == 0 ? b.pt3_cnt : b.pt5_cnt;
     GRID_STRIDE(j, n) {
-        const uint32_t i = pair_slot(s_off, j, subcap);
+        const uint32_t i = pair_slot(s_off, j, subcap, nsub);
         const uint32_t p = cp[i], o = co[i];
         uint32_t ia, io;
         float2 ks;
@@ -1349,9 +1365,9 @@ __global__ __launch_bounds__(256) void k_pt_place(const Batch b, uint32_t nsub)
 {
     __shared__ uint32_t s_off[kSubLists + 1];
     const uint32_t *soff = kKind == 0 ? b.ptc3_soff : b.ptc5_soff;
-    for (uint32_t i = threadIdx.x; i <= kSubLists; i += blockDim.x) s_off[i] = soff[i];
+    for (uint32_t i = threadIdx.x; i <= nsub; i += blockDim.x) s_off[i] = soff[i];
     __syncthreads();
-    const uint32_t n = s_off[kSubLists];
+    const uint32_t n = s_off[nsub];
     const uint32_t subcap = (kKind == 0 ? b.cap_ptc3 : b.cap_ptc5) / nsub;
     const uint32_t *cp = kKind == 0 ? b.ptc3_p : b.ptc5_p;
     const uint32_t *co = kKind == 0 ? b.ptc3_o : b.ptc5_o;
@@ -1361,7 +1377,7 @@ __global__ __launch_bounds__(256) void k_pt_place(const Batch b, uint32_t nsub)
     uint32_t *to = kKind == 0 ? b.pt3_to : b.pt5_to;
     const uint32_t cap = kKind == 0 ? b.cap_pt3 : b.cap_pt5;
     GRID_STRIDE(j, n) {
-        const uint32_t i = pair_slot(s_off, j, subcap);
+        const uint32_t i = pair_slot(s_off, j, subcap, nsub);
         const uint32_t r = rank[i];
         if (r == kInvalid) continue;
         const uint32_t p = cp[i];
@@ -1528,20 +1544,18 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
         L.launch("ls_fill", k_ls_wave<true>, grid_for(32ull * b.cap_md), blk, b, t, g, c, 0);
     } else {
         const dim3 gls = grid_for(b.cap_md);
-        const uint32_t nsub_ls = std::min<uint32_t>(kSubLists, gls.x);
-        L.launch("zero", k_zero_fixed, dim3(kSubLists * kSubStride / 256), blk, b.lss_sub, kSubLists * kSubStride);
+        const uint32_t nsub_ls = gls.x;
         L.launch("ls_walk", k_ls, gls, blk, b, t, g, c, nsub_ls, stats);
-        L.launch("sub_offsets", k_sub_offsets, dim3(1), dim3(kSubLists), b.lss_sub, b.lss_soff, b.cap_ls, nsub_ls,
+        L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.lss_sub, b.lss_soff, b.cap_ls, nsub_ls,
                  &t->n_lss);
         L.scan(b.ls_cnt, b.ls_off, &t->n_md, b.cap_md, &t->n_ls, "scan_ls");
         L.launch("ls_place", k_ls_place, grid_for(b.cap_ls), blk, b, nsub_ls);
     }
     // a4: T3
     const dim3 gt3 = grid_for(b.cap_ls);
-    const uint32_t nsub_t3 = std::min<uint32_t>(kSubLists, gt3.x);
-    L.launch("zero", k_zero_fixed, dim3(kSubLists * kSubStride / 256), blk, b.t3s_sub, kSubLists * kSubStride);
+    const uint32_t nsub_t3 = gt3.x;
     L.launch("t3_walk", k_t3, gt3, blk, b, t, c, nsub_t3, stats);
-    L.launch("sub_offsets", k_sub_offsets, dim3(1), dim3(kSubLists), b.t3s_sub, b.t3s_soff, b.cap_t3, nsub_t3,
+    L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.t3s_sub, b.t3s_soff, b.cap_t3, nsub_t3,
              &t->n_t3s);
     L.scan(b.t3_cnt, b.t3_off, &t->n_ls, b.cap_ls, &t->n_t3, "scan_t3");
     L.launch("t3_place", k_t3_place, grid_for(b.cap_t3), blk, b, nsub_t3);
@@ -1563,15 +1577,13 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     // a7: pT3 / pT5: roads, candidate pairs, seed cuts, per-seed placement and order
     const uint64_t cap_pu = (uint64_t)b.cap_pls * c.n_surf;
     L.launch("road", k_road, grid_for(cap_pu), blk, b, (const Totals *)t, g, c);
-    L.launch("zero", k_zero_fixed, dim3(kSubLists * kSubStride / 256), blk, b.ptc3_sub, kSubLists * kSubStride);
-    L.launch("zero", k_zero_fixed, dim3(kSubLists * kSubStride / 256), blk, b.ptc5_sub, kSubLists * kSubStride);
     const dim3 gwalk = grid_for(cap_pu);
-    const uint32_t nsub = std::min<uint32_t>(kSubLists, gwalk.x);
+    const uint32_t nsub = gwalk.x;
     L.launch("pt3c_walk", k_ptc<0>, gwalk, blk, b, t, c, nsub, stats);
     L.launch("pt5c_walk", k_ptc<1>, gwalk, blk, b, t, c, nsub, stats);
-    L.launch("sub_offsets", k_sub_offsets, dim3(1), dim3(kSubLists), b.ptc3_sub, b.ptc3_soff, b.cap_ptc3, nsub,
+    L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.ptc3_sub, b.ptc3_soff, b.cap_ptc3, nsub,
              &t->n_ptc3);
-    L.launch("sub_offsets", k_sub_offsets, dim3(1), dim3(kSubLists), b.ptc5_sub, b.ptc5_soff, b.cap_ptc5, nsub,
+    L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.ptc5_sub, b.ptc5_soff, b.cap_ptc5, nsub,
              &t->n_ptc5);
     L.launch("zero", k_zero_u32, grid_for((uint64_t)b.cap_pls + 1), blk, b.pt3_cnt, &t->n_pls, b.cap_pls, 1u);
     L.launch("zero", k_zero_u32, grid_for((uint64_t)b.cap_pls + 1), blk, b.pt5_cnt, &t->n_pls, b.cap_pls, 1u);
