@@ -1173,11 +1173,14 @@ __global__ __launch_bounds__(256) void k_road(const Batch b, const Totals *t, co
     }
 }
 
+constexpr uint32_t kPtVec = 4;   // bucket entries a seed-lookup thread loads at a time
+
 // Candidates: one thread per (seed, surface) walks the buckets of its road
 // and keeps the objects inside the road's azimuth window (padded,
 // conservative) that pass the exact binary64 curvature test.  The offsets of
-// the four ranges of a bin are loaded together and entries two at a time, so
-// that a bin costs few dependent round trips to memory.  Pairs collect in a
+// the four ranges of a bin are loaded together, and the ranges are walked as
+// one sequence, kPtVec entries at a time, so that a bin costs few dependent
+// round trips to memory.  Pairs collect in a
 // per-thread LDS buffer and are appended to the block's sub-list of the
 // (unordered) pair list with one reservation per wave; a thread whose buffer
 // fills flushes it alone.  The other seed cuts run in k_pt_eval, one thread
@@ -1240,14 +1243,6 @@ __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Con
                 buf[k * 256u + threadIdx.x] = __float_as_uint(q.w);
                 k++;
             };
-            auto walk = [&](uint32_t i, const uint32_t end) {
-                for (; i + 1u < end; i += 2u) {
-                    const float4 q0 = bks[i], q1 = bks[i + 1u];
-                    visit(q0);
-                    visit(q1);
-                }
-                if (i < end) visit(bks[i]);
-            };
             for (uint32_t j = 0; j < nbins; j++) {
                 uint32_t bin = first + j;
                 if (bin >= c.nphi) bin -= c.nphi;
@@ -1258,10 +1253,24 @@ __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Con
                 const uint32_t a2 = bk_off[rb + 2u * c.nkb + (kr2 & 0xFFu)];
                 const uint32_t e2 = bk_off[rb + 2u * c.nkb + (kr2 >> 8) + 1u];
                 const uint32_t a3 = bk_off[rb + 3u * c.nkb], e3 = bk_off[rb + per_row];
-                walk(a0, e0);
-                walk(a1, e1);
-                walk(a2, e2);
-                walk(a3, e3);
+                // the four ranges as one sequence, kPtVec entries loaded at a time
+                const uint32_t c1 = e0 > a0 ? e0 - a0 : 0u;
+                const uint32_t c2 = c1 + (e1 > a1 ? e1 - a1 : 0u);
+                const uint32_t c3 = c2 + (e2 > a2 ? e2 - a2 : 0u);
+                const uint32_t T = c3 + (e3 > a3 ? e3 - a3 : 0u);
+                for (uint32_t t0 = 0; t0 < T; t0 += kPtVec) {
+                    float4 q[kPtVec];
+#pragma unroll
+                    for (uint32_t v = 0; v < kPtVec; v++) {
+                        const uint32_t tt = min(t0 + v, T - 1u);
+                        const uint32_t i = tt < c1 ? a0 + tt : tt < c2 ? a1 + (tt - c1) : tt < c3 ? a2 + (tt - c2)
+                                                                                               : a3 + (tt - c3);
+                        q[v] = bks[i];
+                    }
+#pragma unroll
+                    for (uint32_t v = 0; v < kPtVec; v++)
+                        if (t0 + v < T) visit(q[v]);
+                }
             }
         }
         // one reservation per wave; the buffers go out column by column
