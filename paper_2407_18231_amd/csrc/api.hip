@@ -896,6 +896,14 @@ lst_status lst_load_geometry(lst_ctx *ctx, const lst_module_desc *m, uint32_t n)
     ctx->dg.edge = (const uint2 *)(d + off_edge);
     ctx->dg.cls = (const lst::LsK *)(d + off_cls);
     ctx->dg.surf = (const lst::Surface *)(d + off_sf);
+    // the hit histogram runs per event in LDS, in slices of the event's
+    // (module, sensor) bins that fit one block's LDS
+    int lds_max = 0;
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device) != hipSuccess ||
+        lds_max < 65536)
+        lds_max = 65536;   // every CDNA workgroup has at least 64 KiB of LDS
+    ctx->dg.hist_slice =
+        (uint32_t)std::min<int64_t>((int64_t)lds_max / 4 / 256 * 256, 2 * (int64_t)geom.n_mod);
     ctx->geom = std::move(geom);
     ctx->has_geom = true;
     // arenas depend on the module count

@@ -51,6 +51,7 @@ struct DevGeom {
     const uint2 *edge;          // (destination module, class)
     const LsK *cls;
     const Surface *surf;        // n_surf
+    uint32_t hist_slice;        // hit histogram in LDS: (module, sensor) bins per slice
 };
 
 // Counters of one batch in device memory.  n_ev / n_hits / n_pls are written
@@ -167,6 +168,13 @@ struct Launcher {
     template <typename... KArgs, typename... Args>
     void launch(const char *name, void (*kernel)(KArgs...), dim3 grid, dim3 block, Args... args)
     {
+        launch_lds(name, kernel, grid, block, 0u, args...);
+    }
+
+    // with dynamic LDS of lds bytes per block
+    template <typename... KArgs, typename... Args>
+    void launch_lds(const char *name, void (*kernel)(KArgs...), dim3 grid, dim3 block, uint32_t lds, Args... args)
+    {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         const bool timed = timing && (only == nullptr || std::strcmp(only, name) == 0);
         if (timed) {
@@ -174,7 +182,7 @@ struct Launcher {
             e1 = next_event();
             if (e0) (void)hipEventRecord(e0, stream);
         }
-        kernel<<<grid, block, 0, stream>>>(args...);
+        kernel<<<grid, block, lds, stream>>>(args...);
         hipError_t le = hipGetLastError();
         if (le != hipSuccess && err == hipSuccess) err = le;
         if (timed && e1) {

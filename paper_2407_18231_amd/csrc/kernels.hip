@@ -184,25 +184,46 @@ __global__ void k_setup(Totals *t, uint32_t n_mod, uint32_t n_surf, uint32_t nph
 
 // ------------------------------------------------------ a1: hit ingest ---
 
-__global__ void k_hit_hist(const Batch b, Totals *t, uint32_t n_mod)
+// Hit histogram per event in LDS: a block takes one event and a slice of
+// its (module, sensor) bins, counts the event's hits that fall in the slice
+// with LDS atomics (the returned value is the hit's slot in its bin) and
+// writes the slice's counts out, so no global atomic is needed.  Bad hits
+// are reported by the slice-0 block only.
+constexpr uint32_t kHistBlock = 1024;
+
+__global__ __launch_bounds__(kHistBlock) void k_hit_hist(const Batch b, Totals *t, uint32_t n_mod, uint32_t slice)
 {
+    extern __shared__ uint32_t s_cnt[];
     const uint32_t n_ev = t->n_ev, n = min(t->n_hits, b.cap_hits);
-    GRID_STRIDE(h, n) {
-        uint32_t e = find_event(b.ev_hit_off, n_ev, h);
-        uint32_t m = b.in_mod[h];
-        uint32_t s = b.in_sen[h];
-        float x = b.in_x[h], y = b.in_y[h], z = b.in_z[h];
-        uint32_t bad = 0;
-        if (m >= n_mod || s > 1u) bad |= kErrBadModule;
-        if (!isfinite(x) || !isfinite(y) || !isfinite(z)) bad |= kErrNonFinite;
-        if (bad) {
-            atomicOr(&t->err, bad);
-            b.hbin[h] = kInvalid;
-            continue;
+    const uint32_t bins_ev = 2u * n_mod;
+    const uint32_t n_sl = (bins_ev + slice - 1u) / slice;
+    for (uint32_t w = blockIdx.x; w < n_ev * n_sl; w += gridDim.x) {
+        const uint32_t e = w / n_sl, sl = w - e * n_sl;
+        const uint32_t b0 = sl * slice, nb = min(slice, bins_ev - b0);
+        for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) s_cnt[i] = 0u;
+        __syncthreads();
+        const uint32_t h1 = min(b.ev_hit_off[e + 1], n);
+        for (uint32_t h = b.ev_hit_off[e] + threadIdx.x; h < h1; h += blockDim.x) {
+            const uint32_t m = b.in_mod[h], sn = b.in_sen[h];
+            const float x = b.in_x[h], y = b.in_y[h], z = b.in_z[h];
+            uint32_t bad = 0;
+            if (m >= n_mod || sn > 1u) bad |= kErrBadModule;
+            if (!isfinite(x) || !isfinite(y) || !isfinite(z)) bad |= kErrNonFinite;
+            if (bad) {
+                if (sl == 0u) {
+                    atomicOr(&t->err, bad);
+                    b.hbin[h] = kInvalid;
+                }
+                continue;
+            }
+            const uint32_t local = 2u * m + sn;
+            if (local < b0 || local >= b0 + nb) continue;
+            b.hbin[h] = e * bins_ev + local;
+            b.hrank[h] = atomicAdd(&s_cnt[local - b0], 1u);
         }
-        uint32_t bin = e * 2u * n_mod + 2u * m + s;
-        b.hbin[h] = bin;
-        b.hrank[h] = atomicAdd(&b.bin_cnt[bin], 1u);
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) b.bin_cnt[e * bins_ev + b0 + i] = s_cnt[i];
+        __syncthreads();
     }
 }
 
@@ -773,13 +794,15 @@ __device__ inline bool rz3(const Consts &c, const Anchor &A, const Anchor &B, co
 }
 
 // T3: one thread per inner LS l1 tests the LSs that start at l1's outer
-// MD, four at a time (their outer MDs and anchors load together).
+// MD, kT3Vec at a time (their outer MDs and anchors load together).
 // Survivors collect in a per-thread LDS buffer and go, with their place in
 // l1's list, to the block's sub-list of an unordered T3 list (one
 // reservation per wave, stores column by column; a thread whose buffer
 // fills flushes it alone); k_t3_place moves them to their canonical slots
 // once the per-LS counts are scanned.  Outer LSs are met in index order, so
 // the place in the list is the canonical one.
+constexpr uint32_t kT3Vec = 4;   // outer LSs a T3 thread loads at a time
+
 __global__ __launch_bounds__(256) void k_t3(const Batch b, Totals *t, const Consts c, uint32_t nsub, int stats)
 {
     __shared__ uint4 buf[kT3Buf * 256];
@@ -812,15 +835,15 @@ __global__ __launch_bounds__(256) void k_t3(const Batch b, Totals *t, const Cons
             const uint32_t q0 = min(b.ls_off[ib], b.cap_ls), q1 = min(b.ls_off[ib + 1], b.cap_ls);
             if (q0 < q1) {
                 const Anchor A = load_anchor(b, ia), B = load_anchor(b, ib);
-                for (uint32_t l2 = q0; l2 < q1; l2 += 4u) {
-                    uint32_t ic[4];
-                    Anchor C[4];
+                for (uint32_t l2 = q0; l2 < q1; l2 += kT3Vec) {
+                    uint32_t ic[kT3Vec];
+                    Anchor C[kT3Vec];
 #pragma unroll
-                    for (int j = 0; j < 4; j++) ic[j] = l2 + j < q1 ? b.ls_b[l2 + j] : ib;
+                    for (uint32_t j = 0; j < kT3Vec; j++) ic[j] = l2 + j < q1 ? b.ls_b[l2 + j] : ib;
 #pragma unroll
-                    for (int j = 0; j < 4; j++) C[j] = load_anchor(b, ic[j]);
+                    for (uint32_t j = 0; j < kT3Vec; j++) C[j] = load_anchor(b, ic[j]);
 #pragma unroll
-                    for (int j = 0; j < 4; j++) {
+                    for (uint32_t j = 0; j < kT3Vec; j++) {
                         if (l2 + j >= q1) break;
                         float kap, sk, d1, d2;
                         cand++;
@@ -1531,9 +1554,9 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     const uint32_t n_mod = c.n_mod;
     // a1: hit ingest & sort by (event, module, sensor)
     launch_setup(L, t, c);
-    L.launch("zero", k_zero_u32, grid_for((uint64_t)b.cap_ev * 2 * n_mod + 1), blk, b.bin_cnt, &t->n_bins,
-             b.cap_ev * 2u * n_mod, 1u);
-    L.launch("hit_hist", k_hit_hist, grid_for(b.cap_hits), blk, b, t, n_mod);
+    const uint32_t n_sl = (2u * n_mod + g.hist_slice - 1u) / g.hist_slice;
+    const dim3 gh((unsigned)std::min<uint64_t>((uint64_t)b.cap_ev * n_sl, kMaxGrid));
+    L.launch_lds("hit_hist", k_hit_hist, gh, dim3(kHistBlock), g.hist_slice * 4u, b, t, n_mod, g.hist_slice);
     L.launch("pls_check", k_pls_check, grid_for(b.cap_pls), blk, b, t);
     L.scan(b.bin_cnt, b.bin_off, &t->n_bins, b.cap_ev * 2u * n_mod, &t->n_sorted, "scan_hits");
     L.launch("hit_scatter", k_hit_scatter, grid_for(b.cap_hits), blk, b, (const Totals *)t);
