@@ -739,12 +739,37 @@ __global__ __launch_bounds__(256) void k_ls_wave(const Batch b, Totals *t, const
     if (!kFill && stats) atomicAdd(&t->cand[1], (unsigned long long)cand);
 }
 
+// For every LS: the range of LSs that start at its outer MD (the T3
+// candidates of an LS) and its outer MD's anchor, stored beside the LS so
+// that the T3 walk reads them with its own record instead of through two
+// more dependent gathers.
+__global__ void k_ls_aux(const Batch b, const Totals *t)
+{
+    const uint32_t n = min(t->n_ls, b.cap_ls);
+    GRID_STRIDE(l, n) {
+        const uint32_t q = b.ls_b[l];
+        b.ls_nx[l] = make_uint2(min(b.ls_off[q], b.cap_ls), min(b.ls_off[q + 1], b.cap_ls));
+        b.ls_pb[l] = b.md_pos[q];
+    }
+}
+
 // ------------------------------------------------------------ a4: T3 ----
 
 struct Anchor {
     float x, y, z, r;
     bool disk;
 };
+
+__device__ inline Anchor anchor_of(const float4 p)
+{
+    Anchor A;
+    A.x = p.x;
+    A.y = p.y;
+    A.z = p.z;
+    A.r = fabsf(p.w);
+    A.disk = p.w < 0.0f;
+    return A;
+}
 
 __device__ inline Anchor load_anchor(const Batch &b, uint32_t i)
 {
@@ -794,7 +819,7 @@ __device__ inline bool rz3(const Consts &c, const Anchor &A, const Anchor &B, co
 }
 
 // T3: one thread per inner LS l1 tests the LSs that start at l1's outer
-// MD, kT3Vec at a time (their outer MDs and anchors load together).
+// MD (range and anchors stored per LS by k_ls_aux), kT3Vec at a time.
 // Survivors collect in a per-thread LDS buffer and go, with their place in
 // l1's list, to the block's sub-list of an unordered T3 list (one
 // reservation per wave, stores column by column; a thread whose buffer
@@ -831,17 +856,19 @@ __global__ __launch_bounds__(256) void k_t3(const Batch b, Totals *t, const Cons
         };
         if (l1 < n) {
             ia = b.ls_a[l1];
-            const uint32_t ib = b.ls_b[l1];
-            const uint32_t q0 = min(b.ls_off[ib], b.cap_ls), q1 = min(b.ls_off[ib + 1], b.cap_ls);
+            const uint2 nx = b.ls_nx[l1];
+            const uint32_t q0 = nx.x, q1 = nx.y;
             if (q0 < q1) {
-                const Anchor A = load_anchor(b, ia), B = load_anchor(b, ib);
+                const Anchor A = load_anchor(b, ia), B = anchor_of(b.ls_pb[l1]);
                 for (uint32_t l2 = q0; l2 < q1; l2 += kT3Vec) {
                     uint32_t ic[kT3Vec];
                     Anchor C[kT3Vec];
 #pragma unroll
-                    for (uint32_t j = 0; j < kT3Vec; j++) ic[j] = l2 + j < q1 ? b.ls_b[l2 + j] : ib;
-#pragma unroll
-                    for (uint32_t j = 0; j < kT3Vec; j++) C[j] = load_anchor(b, ic[j]);
+                    for (uint32_t j = 0; j < kT3Vec; j++) {
+                        const uint32_t l = min(l2 + j, q1 - 1u);
+                        ic[j] = b.ls_b[l];
+                        C[j] = anchor_of(b.ls_pb[l]);
+                    }
 #pragma unroll
                     for (uint32_t j = 0; j < kT3Vec; j++) {
                         if (l2 + j >= q1) break;
@@ -1583,6 +1610,7 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
         L.scan(b.ls_cnt, b.ls_off, &t->n_md, b.cap_md, &t->n_ls, "scan_ls");
         L.launch("ls_place", k_ls_place, grid_for(b.cap_ls), blk, b, nsub_ls);
     }
+    L.launch("ls_aux", k_ls_aux, grid_for(b.cap_ls), blk, b, (const Totals *)t);
     // a4: T3
     const dim3 gt3 = grid_for(b.cap_ls);
     const uint32_t nsub_t3 = gt3.x;
