@@ -814,8 +814,21 @@ __device__ inline bool rz3(const Consts &c, const Anchor &A, const Anchor &B, co
     float stA = A.disk ? c.sc : c.srp, stB = B.disk ? c.sc : c.srp, stC = C.disk ? c.sc : c.srp;
     float res = (((szA * d2 + szB * (d1 + d2)) + szC * d1) + fabsf(B.z - A.z) * (stB + stC)) +
                 fabsf(C.z - B.z) * (stA + stB);
+    // the bias term is finite and not negative when d1 + d2 > 0, and adding
+    // it cannot lower the rounded bound: a candidate inside the bound without
+    // it passes, and the division is only needed for the others
+    if (d1 + d2 > 0.0f && fabsf(E) <= c.ns * res) return true;
     float bias = ((c.Kb * (fabsf(C.z - A.z) / (d1 + d2))) * (d1 * d2)) * fabsf(d1 * d1 - d2 * d2);
     return fabsf(E) <= c.ns * res + bias;
+}
+
+// the two chord lengths of the circle through A, B, C (as kappa3 computes them)
+__device__ inline void sides3(const Anchor &A, const Anchor &B, const Anchor &C, float &d1, float &d2)
+{
+    float dx1 = B.x - A.x, dy1 = B.y - A.y;
+    float dx2 = C.x - B.x, dy2 = C.y - B.y;
+    d1 = sqrtf(dx1 * dx1 + dy1 * dy1);
+    d2 = sqrtf(dx2 * dx2 + dy2 * dy2);
 }
 
 // T3: one thread per inner LS l1 tests the LSs that start at l1's outer
@@ -874,9 +887,12 @@ __global__ __launch_bounds__(256) void k_t3(const Batch b, Totals *t, const Cons
                         if (l2 + j >= q1) break;
                         float kap, sk, d1, d2;
                         cand++;
+                        // the rz cut first (it needs two of the three chords and
+                        // rejects most candidates), then the curvature cut
+                        sides3(A, B, C[j], d1, d2);
+                        if (!rz3(c, A, B, C[j], d1, d2)) continue;
                         kappa3(c, A, B, C[j], kap, sk, d1, d2);
                         if (!(fabsf(kap) <= c.kmaxf + c.ns * sk)) continue;
-                        if (!rz3(c, A, B, C[j], d1, d2)) continue;
                         if (kb == kT3Buf) {
                             const uint32_t at = atomicAdd(n_t3, kb);
                             for (uint32_t q = 0; q < kb; q++) put(at + q, q);
