@@ -87,15 +87,29 @@ def outer_gathers(events, results, begin, dst):
     return s_b, e_used
 
 
+def kernels_digest() -> str:
+    """sha256 of the kernel sources, to tie counter results to the code they
+    were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "engine.h"):
+        with open(os.path.join(ROOT, "paper_2407_18231_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def traffic_of(kernel: str):
     """HBM bytes per launch measured with rocprofv3 counters (FETCH_SIZE,
     WRITE_SIZE, each scaled by what the counter reads for a plain copy of
-    known size), stored beside the profile summaries; null when absent."""
+    known size), stored beside the profile summaries; null when absent or
+    when the kernels have changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
+        return None
+    if t.get("kernels_sha256") != kernels_digest():
         return None
     v = t.get("kernels", {}).get(kernel)
     return None if v is None else v.get("bytes_per_launch")
