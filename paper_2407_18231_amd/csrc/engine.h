@@ -18,7 +18,7 @@ constexpr uint32_t kDiskBit = 0x80000000u;   // md_u: anchor on an endcap module
 constexpr uint32_t kUnitMask = 0x7FFFFFFFu;  // md_u: (event, module) unit
 constexpr uint32_t kErrBadModule = 1u;
 constexpr uint32_t kErrNonFinite = 2u;
-constexpr int kScanGrid = 256;
+constexpr int kScanGrid = 2048;   // blocks (and partial sums) of the device-wide scan
 constexpr unsigned kMaxGrid = 2048;
 constexpr int kEvTabCols = 12;
 // survivors a count pass records per unit, so that the fill pass copies them

@@ -64,20 +64,28 @@ __device__ inline uint32_t scan_chunk(uint32_t n)
     return (per + kScanTile - 1) / kScanTile * kScanTile;
 }
 
+// Three-phase scan: every block sums a chunk (whole tiles of kScanTile
+// values, four per thread as one 16-byte load), one block scans the
+// kScanGrid partial sums, every block scans its chunk again with its carry.
 __global__ __launch_bounds__(kScanBlock) void k_scan_up(const uint32_t *__restrict__ in,
                                                         const uint32_t *n_ptr, uint32_t cap,
                                                         uint32_t *__restrict__ part)
 {
     const uint32_t n = min(*n_ptr, cap);
     const uint32_t chunk = scan_chunk(n);
-    const uint32_t start = blockIdx.x * chunk;
+    const uint32_t start = min(blockIdx.x * chunk, n);
     const uint32_t end = min(start + chunk, n);
     uint32_t s = 0;
     for (uint32_t base = start; base < end; base += kScanTile) {
-        uint32_t i = base + 4 * threadIdx.x;
+        const uint32_t i = base + 4 * threadIdx.x;
+        if (i + 3 < end) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(in + i);
+            s += (v.x + v.y) + (v.z + v.w);
+        } else {
 #pragma unroll
-        for (int k = 0; k < 4; k++)
-            if (i + k < end) s += in[i + k];
+            for (int k = 0; k < 4; k++)
+                if (i + k < end) s += in[i + k];
+        }
     }
     uint32_t tot;
     block_excl_scan(s, tot);
@@ -89,12 +97,22 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_mid(uint32_t *__restrict__ 
                                                          uint32_t *__restrict__ out,
                                                          uint32_t *total_out)
 {
-    static_assert(kScanGrid == kScanBlock, "one partial per thread");
+    constexpr uint32_t kPer = kScanGrid / kScanBlock;
+    static_assert(kScanGrid % kScanBlock == 0, "whole partials per thread");
     const uint32_t n = min(*n_ptr, cap);
-    uint32_t v = part[threadIdx.x];
+    uint32_t v[kPer], s = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; k++) {
+        v[k] = part[threadIdx.x * kPer + k];
+        s += v[k];
+    }
     uint32_t tot;
-    uint32_t ex = block_excl_scan(v, tot);
-    part[threadIdx.x] = ex;
+    uint32_t ex = block_excl_scan(s, tot);
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; k++) {
+        part[threadIdx.x * kPer + k] = ex;
+        ex += v[k];
+    }
     if (threadIdx.x == 0) {
         out[n] = tot;
         *total_out = tot;
@@ -108,21 +126,38 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_down(const uint32_t *__rest
 {
     const uint32_t n = min(*n_ptr, cap);
     const uint32_t chunk = scan_chunk(n);
-    const uint32_t start = blockIdx.x * chunk;
+    const uint32_t start = min(blockIdx.x * chunk, n);
     const uint32_t end = min(start + chunk, n);
     uint32_t carry = part[blockIdx.x];
     for (uint32_t base = start; base < end; base += kScanTile) {
-        uint32_t i = base + 4 * threadIdx.x;
+        const uint32_t i = base + 4 * threadIdx.x;
+        const bool full = i + 3 < end;
         uint32_t v[4];
+        if (full) {
+            const uint4 q = *reinterpret_cast<const uint4 *>(in + i);
+            v[0] = q.x;
+            v[1] = q.y;
+            v[2] = q.z;
+            v[3] = q.w;
+        } else {
 #pragma unroll
-        for (int k = 0; k < 4; k++) v[k] = (i + k < end) ? in[i + k] : 0u;
-        uint32_t s = v[0] + v[1] + v[2] + v[3];
+            for (int k = 0; k < 4; k++) v[k] = (i + k < end) ? in[i + k] : 0u;
+        }
+        const uint32_t s = (v[0] + v[1]) + (v[2] + v[3]);
         uint32_t tot;
         uint32_t ex = block_excl_scan(s, tot) + carry;
+        uint32_t o[4];
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            if (i + k < end) out[i + k] = ex;
+            o[k] = ex;
             ex += v[k];
+        }
+        if (full) {
+            *reinterpret_cast<uint4 *>(out + i) = make_uint4(o[0], o[1], o[2], o[3]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; k++)
+                if (i + k < end) out[i + k] = o[k];
         }
         carry += tot;
     }
