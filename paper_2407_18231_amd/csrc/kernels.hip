@@ -866,94 +866,104 @@ __device__ inline void sides3(const Anchor &A, const Anchor &B, const Anchor &C,
     d2 = sqrtf(dx2 * dx2 + dy2 * dy2);
 }
 
-// T3: one thread per inner LS l1 tests the LSs that start at l1's outer
-// MD (range and anchors stored per LS by k_ls_aux), kT3Vec at a time.
-// Survivors collect in a per-thread LDS buffer and go, with their place in
-// l1's list, to the block's sub-list of an unordered T3 list (one
-// reservation per wave, stores column by column; a thread whose buffer
-// fills flushes it alone); k_t3_place moves them to their canonical slots
-// once the per-LS counts are scanned.  Outer LSs are met in index order, so
-// the place in the list is the canonical one.
-constexpr uint32_t kT3Vec = 4;   // outer LSs a T3 thread loads at a time
+// lanes s0 .. e0 - 1 of a wave (0 <= s0 <= e0 <= 64)
+__device__ inline unsigned long long lane_range(uint32_t s0, uint32_t e0)
+{
+    const unsigned long long hi = e0 >= 64u ? ~0ull : (1ull << e0) - 1ull;
+    return hi & ~((1ull << s0) - 1ull);
+}
 
+// T3: the 64 inner LSs of a wave (one per lane) pool their candidates --
+// the LSs that start at each one's outer MD, range and anchors stored per LS
+// by k_ls_aux -- and the lanes take the pooled candidates 64 at a time, so
+// the cut arithmetic runs on full waves however the candidates are spread.
+// A candidate finds its owner lane by a binary search over the lanes'
+// first-candidate offsets and takes the owner's anchors by lane shuffles.
+// Survivors go to the block's region of an unordered T3 list with their
+// place in the owner's list (the owner's earlier survivors plus those before
+// it in the same 64), so k_t3_place can put them in canonical order.
 __global__ __launch_bounds__(256) void k_t3(const Batch b, Totals *t, const Consts c, uint32_t nsub, int stats)
 {
-    __shared__ uint4 buf[kT3Buf * 256];
+    __shared__ uint32_t s_n;             // appends to this block's region
     const uint32_t n = min(t->n_ls, b.cap_ls);
     const uint32_t lane = threadIdx.x & 63u;
     const unsigned long long below = (1ull << lane) - 1ull;
-    __shared__ uint32_t s_n;             // appends to this block's region
     const uint32_t cap = b.cap_t3 / nsub;
-    uint32_t *n_t3 = &s_n;
     const size_t sb0 = (size_t)blockIdx.x * cap;
     if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
     uint64_t cand = 0;
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
         const uint32_t l1 = base + threadIdx.x;
-        uint32_t kb = 0, k = 0, ia = 0;  // buffered, found so far, inner anchor
-        auto put = [&](uint32_t slot, uint32_t j) {
-            const uint4 v = buf[j * 256u + threadIdx.x];
-            if (slot < cap) {
-                b.t3s_l1[sb0 + slot] = l1;
-                b.t3s_l2[sb0 + slot] = v.x;
-                b.t3s_j[sb0 + slot] = k - kb + j;
-                b.t3s_ac[sb0 + slot] = make_uint2(ia, v.y);
-                b.t3s_ks[sb0 + slot] = make_float2(__uint_as_float(v.z), __uint_as_float(v.w));
-            }
-        };
+        uint32_t ia = 0, q0 = 0, cnt = 0;
+        float4 pa = make_float4(0.f, 0.f, 0.f, 0.f), pb = pa;
         if (l1 < n) {
             ia = b.ls_a[l1];
             const uint2 nx = b.ls_nx[l1];
-            const uint32_t q0 = nx.x, q1 = nx.y;
-            if (q0 < q1) {
-                const Anchor A = load_anchor(b, ia), B = anchor_of(b.ls_pb[l1]);
-                for (uint32_t l2 = q0; l2 < q1; l2 += kT3Vec) {
-                    uint32_t ic[kT3Vec];
-                    Anchor C[kT3Vec];
+            q0 = nx.x;
+            cnt = nx.y > nx.x ? nx.y - nx.x : 0u;
+            if (cnt) {
+                pb = b.ls_pb[l1];
+                pa = b.md_pos[ia];
+            }
+        }
+        const uint32_t incl = wave_incl_scan(cnt);
+        const uint32_t off = incl - cnt;                 // this lane's first pooled candidate
+        const uint32_t total = __shfl(incl, 63);
+        uint32_t run = 0;                                // survivors of this lane's LS so far
+        for (uint32_t cb = 0; cb < total; cb += 64u) {
+            const uint32_t ci = cb + lane;
+            // owner: the last lane o with off_o <= ci (it has ci - off_o < cnt_o)
+            uint32_t o = 0;
 #pragma unroll
-                    for (uint32_t j = 0; j < kT3Vec; j++) {
-                        const uint32_t l = min(l2 + j, q1 - 1u);
-                        ic[j] = b.ls_b[l];
-                        C[j] = anchor_of(b.ls_pb[l]);
-                    }
-#pragma unroll
-                    for (uint32_t j = 0; j < kT3Vec; j++) {
-                        if (l2 + j >= q1) break;
-                        float kap, sk, d1, d2;
-                        cand++;
-                        // the rz cut first (it needs two of the three chords and
-                        // rejects most candidates), then the curvature cut
-                        sides3(A, B, C[j], d1, d2);
-                        if (!rz3(c, A, B, C[j], d1, d2)) continue;
-                        kappa3(c, A, B, C[j], kap, sk, d1, d2);
-                        if (!(fabsf(kap) <= c.kmaxf + c.ns * sk)) continue;
-                        if (kb == kT3Buf) {
-                            const uint32_t at = atomicAdd(n_t3, kb);
-                            for (uint32_t q = 0; q < kb; q++) put(at + q, q);
-                            kb = 0;
-                        }
-                        buf[kb * 256u + threadIdx.x] = make_uint4(l2 + j, ic[j], __float_as_uint(kap),
-                                                                 __float_as_uint(sk));
-                        kb++;
-                        k++;
-                    }
+            for (uint32_t step = 32; step; step >>= 1)
+                if (__shfl(off, o + step) <= ci) o += step;
+            const uint32_t o_q0 = __shfl(q0, o), o_off = __shfl(off, o), o_ia = __shfl(ia, o);
+            const uint32_t o_l1 = __shfl(l1, o), o_run = __shfl(run, o);
+            const float4 oa = make_float4(__shfl(pa.x, o), __shfl(pa.y, o), __shfl(pa.z, o), __shfl(pa.w, o));
+            const float4 ob = make_float4(__shfl(pb.x, o), __shfl(pb.y, o), __shfl(pb.z, o), __shfl(pb.w, o));
+            bool pass = false;
+            uint32_t l2 = 0, ic = 0;
+            float kap = 0.f, sk = 0.f;
+            if (ci < total) {
+                l2 = o_q0 + (ci - o_off);
+                ic = b.ls_b[l2];
+                const Anchor A = anchor_of(oa), B = anchor_of(ob), C = anchor_of(b.ls_pb[l2]);
+                float d1, d2;
+                cand++;
+                // the rz cut first (it needs two of the three chords and rejects
+                // most candidates), then the curvature cut
+                sides3(A, B, C, d1, d2);
+                if (rz3(c, A, B, C, d1, d2)) {
+                    kappa3(c, A, B, C, kap, sk, d1, d2);
+                    pass = fabsf(kap) <= c.kmaxf + c.ns * sk;
                 }
             }
-            b.t3_cnt[l1] = k;
+            const unsigned long long m = __ballot(pass);
+            const uint32_t np = (uint32_t)__popcll(m);
+            uint32_t at = 0;
+            if (np != 0u && lane == 0u) at = atomicAdd(&s_n, np);
+            at = __shfl(at, 0);
+            if (pass) {
+                const uint32_t slot = at + (uint32_t)__popcll(m & below);
+                const uint32_t s0 = o_off > cb ? o_off - cb : 0u;
+                const uint32_t jj = o_run + (uint32_t)__popcll(m & below & ~((1ull << s0) - 1ull));
+                if (slot < cap) {
+                    b.t3s_l1[sb0 + slot] = o_l1;
+                    b.t3s_l2[sb0 + slot] = l2;
+                    b.t3s_j[sb0 + slot] = jj;
+                    b.t3s_ac[sb0 + slot] = make_uint2(o_ia, ic);
+                    b.t3s_ks[sb0 + slot] = make_float2(kap, sk);
+                }
+            }
+            // each lane counts the survivors among its own candidates in this 64
+            if (cnt != 0u && off < cb + 64u && off + cnt > cb) {
+                const uint32_t s0 = off > cb ? off - cb : 0u;
+                const uint32_t e0 = min(off + cnt - cb, 64u);
+                run += (uint32_t)__popcll(m & lane_range(s0, e0));
+            }
         }
-        // one reservation per wave; the buffers go out column by column
-        const uint32_t tot = __shfl(wave_incl_scan(kb), 63);
-        uint32_t at = 0;
-        if (tot != 0u && lane == 63u) at = atomicAdd(n_t3, tot);
-        at = __shfl(at, 63);
-        for (uint32_t j = 0; j < kT3Buf; j++) {
-            const bool has = j < kb;
-            const unsigned long long m = __ballot(has);
-            if (m == 0ull) break;
-            if (has) put(at + (uint32_t)__popcll(m & below), j);
-            at += (uint32_t)__popcll(m);
-        }
+        if (l1 < n) b.t3_cnt[l1] = run;
     }
     __syncthreads();
     if (threadIdx.x == 0) b.t3s_sub[blockIdx.x] = s_n;
