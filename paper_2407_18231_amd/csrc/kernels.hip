@@ -192,6 +192,21 @@ __device__ inline uint32_t pair_slot(const uint32_t *s_off, uint32_t j, uint32_t
     return lo * subcap + (j - s_off[lo]);
 }
 
+// lanes s0 .. e0 - 1 of a wave (0 <= s0 <= e0 <= 64)
+__device__ inline unsigned long long lane_range(uint32_t s0, uint32_t e0)
+{
+    const unsigned long long hi = e0 >= 64u ? ~0ull : (1ull << e0) - 1ull;
+    return hi & ~((1ull << s0) - 1ull);
+}
+
+// orders a wave's LDS accesses (all lanes of one wave; no block barrier)
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __global__ void k_zero_u32(uint32_t *__restrict__ p, const uint32_t *n_ptr, uint32_t cap, uint32_t extra)
 {
     const uint32_t n = min(*n_ptr, cap) + extra;
@@ -496,73 +511,49 @@ __device__ inline bool ls_cut(const LsK &k, const Consts &c, bool bend,
     return lo <= rb;
 }
 
-// Large batches: one thread per inner MD a, one pass over every MD of every
-// module that a's module connects to.  Edges are read in groups of 8 so that
-// their MD ranges load together; the candidates of a group then run kLsVec
-// at a time (their positions and 32-byte classes load together), in (edge,
-// outer MD) order.  The walk is wave-uniform (a wave steps while any lane
-// has candidates left), so that survivors, buffered per thread in LDS, can
-// leave whenever a buffer may fill: the wave reserves space in its block's
-// sub-list of an unordered segment list with one atomic and stores column by
-// column (entry j of every lane), so the stores coalesce.  Each segment
-// carries its place in a's list; k_ls_place moves it to its canonical slot
-// once the per-MD counts are scanned (edges are sorted by destination
-// module, so walk order is canonical order).
+// Large batches: the 64 inner MDs of a wave (one per lane) step through
+// their modules' edges in groups of 8 together.  For each group a lane loads
+// its edges' MD ranges and stores them in LDS; the wave pools the
+// candidates (every MD of every edge of the group, lane by lane in (edge,
+// outer MD) order) and the lanes take them 64 at a time, so the cut
+// arithmetic runs on full waves however the degrees and MD counts are
+// spread.  A candidate finds its owner lane by a binary search over the
+// lanes' first-candidate offsets, its edge in the owner's group in LDS and
+// the owner's anchor by lane shuffles.  Survivors go to the block's region of
+// an unordered segment list with their place in the owner's list (its
+// earlier survivors plus those before it in the same 64); edges are sorted by
+// destination module, so that place is the canonical one.
 constexpr int kEdgeGroup = 8;
-constexpr int kLsVec = 2;
 
 __global__ __launch_bounds__(256) void k_ls(const Batch b, Totals *t, const DevGeom g, const Consts c,
                                             uint32_t nsub, int stats)
 {
-    static_assert(kSegBuf >= 2 * kLsVec, "buffer holds at least two steps");
-    __shared__ uint32_t buf[kSegBuf * 256];
+    constexpr uint32_t kF = 3 * kEdgeGroup;          // per lane: bq[8], cum[1..8], class[8]
+    __shared__ uint32_t s_grp[4][kF][64];
+    __shared__ uint32_t s_n;                          // appends to this block's region
     const uint32_t n = min(t->n_md, b.cap_md);
     const uint32_t n_mod = c.n_mod;
     const bool bend = (c.flags & LST_FLAG_BEND) != 0u;
-    const uint32_t lane = threadIdx.x & 63u;
-    __shared__ uint32_t s_n;             // appends to this block's region
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    const unsigned long long below = (1ull << lane) - 1ull;
     const uint32_t cap = b.cap_ls / nsub;
-    uint32_t *n_seg = &s_n;
     uint32_t *sa = b.lss_a + (size_t)blockIdx.x * cap;
     uint32_t *sb = b.lss_b + (size_t)blockIdx.x * cap;
     uint32_t *sj = b.lss_j + (size_t)blockIdx.x * cap;
     if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
-    const unsigned long long below = (1ull << lane) - 1ull;
     uint64_t cand = 0;
     // every lane of a wave runs the same number of iterations and steps
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
         const uint32_t a = base + threadIdx.x;
-        uint32_t kb = 0, k = 0;          // buffered, found so far
-        auto flush = [&]() {
-            const uint32_t tot = __shfl(wave_incl_scan(kb), 63);
-            uint32_t at = 0;
-            if (tot != 0u && lane == 63u) at = atomicAdd(n_seg, tot);
-            at = __shfl(at, 63);
-            for (uint32_t j = 0; j < kSegBuf; j++) {
-                const bool has = j < kb;
-                const unsigned long long mk = __ballot(has);
-                if (mk == 0ull) break;
-                if (has) {
-                    const uint32_t slot = at + (uint32_t)__popcll(mk & below);
-                    if (slot < cap) {
-                        sa[slot] = a;
-                        sb[slot] = buf[j * 256u + threadIdx.x];
-                        sj[slot] = k - kb + j;
-                    }
-                }
-                at += (uint32_t)__popcll(mk);
-            }
-            kb = 0;
-        };
-        uint32_t e_cur = 0, e_end = 0, ubase = 0;
+        uint32_t e0 = 0, e1 = 0, ubase = 0;
         float xa = 0.f, ya = 0.f, za = 0.f, ra = 0.f, ba = 0.f;
         if (a < n) {
             const uint32_t u = b.md_u[a] & kUnitMask;
             const uint32_t m = u % n_mod;
             ubase = u - m;
-            e_cur = g.edge_begin[m];
-            e_end = g.edge_begin[m + 1];
+            e0 = g.edge_begin[m];
+            e1 = g.edge_begin[m + 1];
             const float4 pa = b.md_pos[a];
             xa = pa.x;
             ya = pa.y;
@@ -570,73 +561,81 @@ __global__ __launch_bounds__(256) void k_ls(const Batch b, Totals *t, const DevG
             ra = fabsf(pa.w);
             ba = b.md_beta[a];
         }
-        uint32_t bq[kEdgeGroup], cum[kEdgeGroup + 1], cl[kEdgeGroup];
-        uint32_t T = 0, t0 = 0;
-        while (true) {
-            if (t0 >= T && e_cur < e_end) {
-                // next group of edges and their MD ranges
-                cum[0] = 0;
+        uint32_t run = 0;                             // segments of this lane's MD so far
+        for (uint32_t eb = e0;; eb += kEdgeGroup) {
+            if (__ballot(eb < e1) == 0ull) break;
+            // this lane's group: MD ranges of up to 8 edges, to LDS
+            uint32_t T = 0;
 #pragma unroll
-                for (int j = 0; j < kEdgeGroup; j++) {
-                    bq[j] = 0;
-                    cl[j] = 0;
-                    uint32_t eq = 0;
-                    if (e_cur + j < e_end) {
-                        const uint2 ed = g.edge[e_cur + j];
-                        bq[j] = min(b.md_off[ubase + ed.x], b.cap_md);
-                        eq = max(min(b.md_off[ubase + ed.x + 1], b.cap_md), bq[j]);
-                        cl[j] = ed.y;
-                    }
-                    cum[j + 1] = cum[j] + (eq - bq[j]);
+            for (int j = 0; j < kEdgeGroup; j++) {
+                uint32_t bq = 0, eq = 0, cl = 0;
+                if (eb + j < e1) {
+                    const uint2 ed = g.edge[eb + j];
+                    bq = min(b.md_off[ubase + ed.x], b.cap_md);
+                    eq = max(min(b.md_off[ubase + ed.x + 1], b.cap_md), bq);
+                    cl = ed.y;
                 }
-                T = cum[kEdgeGroup];
-                t0 = 0;
-                e_cur += kEdgeGroup;
+                T += eq - bq;
+                s_grp[wv][j][lane] = bq;
+                s_grp[wv][kEdgeGroup + j][lane] = T;  // cum[j + 1]
+                s_grp[wv][2 * kEdgeGroup + j][lane] = cl;
             }
-            const bool has = t0 < T;
-            if (__ballot(has || e_cur < e_end) == 0ull) break;
-            if (has) {
-                uint32_t qq[kLsVec], kk[kLsVec];
+            wave_lds_sync();
+            const uint32_t incl = wave_incl_scan(T);
+            const uint32_t off = incl - T;
+            const uint32_t total = __shfl(incl, 63);
+            for (uint32_t cb = 0; cb < total; cb += 64u) {
+                const uint32_t ci = cb + lane;
+                uint32_t o = 0;
 #pragma unroll
-                for (int v = 0; v < kLsVec; v++) {
-                    // candidate t0 + v: the last edge j with cum[j] <= t0 + v
-                    const uint32_t tt = t0 + v;
-                    uint32_t q = bq[0] + tt, kx = cl[0];
+                for (uint32_t step = 32; step; step >>= 1)
+                    if (__shfl(off, o + step) <= ci) o += step;
+                const uint32_t o_off = __shfl(off, o), o_run = __shfl(run, o);
+                const float oxa = __shfl(xa, o), oya = __shfl(ya, o), oza = __shfl(za, o), ora = __shfl(ra, o);
+                const float oba = __shfl(ba, o);
+                bool pass = false;
+                uint32_t q = 0;
+                if (ci < total) {
+                    // edge j of the owner's group: the last with cum[j] <= tt
+                    const uint32_t tt = ci - o_off;
+                    uint32_t j = 0, cj = 0;
 #pragma unroll
-                    for (int j = 1; j < kEdgeGroup; j++) {
-                        if (tt >= cum[j]) {
-                            q = bq[j] + (tt - cum[j]);
-                            kx = cl[j];
+                    for (int k = 0; k < kEdgeGroup - 1; k++) {
+                        const uint32_t cum = s_grp[wv][kEdgeGroup + k][o];
+                        if (cum <= tt) {
+                            j = k + 1;
+                            cj = cum;
                         }
                     }
-                    qq[v] = tt < T ? q : qq[0];
-                    kk[v] = tt < T ? kx : kk[0];
+                    q = s_grp[wv][j][o] + (tt - cj);
+                    const LsK kc = g.cls[s_grp[wv][2 * kEdgeGroup + j][o]];
+                    const float4 pq = b.md_pos[q];
+                    cand++;
+                    pass = ls_cut(kc, c, bend, oxa, oya, oza, ora, oba, pq.x, pq.y, pq.z, fabsf(pq.w));
                 }
-                float4 pq[kLsVec];
-                LsK kc[kLsVec];
-#pragma unroll
-                for (int v = 0; v < kLsVec; v++) {
-                    pq[v] = b.md_pos[qq[v]];
-                    kc[v] = g.cls[kk[v]];
-                }
-#pragma unroll
-                for (int v = 0; v < kLsVec; v++) {
-                    if (t0 + v < T) {
-                        cand++;
-                        if (ls_cut(kc[v], c, bend, xa, ya, za, ra, ba, pq[v].x, pq[v].y, pq[v].z, fabsf(pq[v].w))) {
-                            buf[kb * 256u + threadIdx.x] = qq[v];
-                            kb++;
-                            k++;
-                        }
+                const unsigned long long mk = __ballot(pass);
+                const uint32_t np = (uint32_t)__popcll(mk);
+                uint32_t at = 0;
+                if (np != 0u && lane == 0u) at = atomicAdd(&s_n, np);
+                at = __shfl(at, 0);
+                if (pass) {
+                    const uint32_t slot = at + (uint32_t)__popcll(mk & below);
+                    const uint32_t s0 = o_off > cb ? o_off - cb : 0u;
+                    if (slot < cap) {
+                        sa[slot] = base + wv * 64u + o;
+                        sb[slot] = q;
+                        sj[slot] = o_run + (uint32_t)__popcll(mk & below & ~((1ull << s0) - 1ull));
                     }
                 }
-                t0 += kLsVec;
+                if (T != 0u && off < cb + 64u && off + T > cb) {
+                    const uint32_t s0 = off > cb ? off - cb : 0u;
+                    const uint32_t e0c = min(off + T - cb, 64u);
+                    run += (uint32_t)__popcll(mk & lane_range(s0, e0c));
+                }
             }
-            // a buffer that could overflow on the next step goes out now
-            if (__ballot(kb + kLsVec > kSegBuf) != 0ull) flush();
+            wave_lds_sync();
         }
-        if (a < n) b.ls_cnt[a] = k;
-        flush();
+        if (a < n) b.ls_cnt[a] = run;
     }
     __syncthreads();
     if (threadIdx.x == 0) b.lss_sub[blockIdx.x] = s_n;
@@ -864,13 +863,6 @@ __device__ inline void sides3(const Anchor &A, const Anchor &B, const Anchor &C,
     float dx2 = C.x - B.x, dy2 = C.y - B.y;
     d1 = sqrtf(dx1 * dx1 + dy1 * dy1);
     d2 = sqrtf(dx2 * dx2 + dy2 * dy2);
-}
-
-// lanes s0 .. e0 - 1 of a wave (0 <= s0 <= e0 <= 64)
-__device__ inline unsigned long long lane_range(uint32_t s0, uint32_t e0)
-{
-    const unsigned long long hi = e0 >= 64u ? ~0ull : (1ull << e0) - 1ull;
-    return hi & ~((1ull << s0) - 1ull);
 }
 
 // T3: the 64 inner LSs of a wave (one per lane) pool their candidates --
