@@ -24,7 +24,6 @@ constexpr int kEvTabCols = 12;
 // survivors a count pass records per unit, so that the fill pass copies them
 // instead of walking the candidates again (units with more walk again)
 constexpr uint32_t kKeepLs = 8;
-constexpr uint32_t kPairBuf = 16;   // seed lookup: candidate pairs a thread buffers in LDS
 // Lists that a walk appends to in no particular order (segments, T3s,
 // seed-object pairs) are split into one equal region per block of the walk
 // (at most kSubLists): a block counts its appends in LDS and publishes the

@@ -1276,124 +1276,129 @@ __global__ __launch_bounds__(256) void k_road(const Batch b, const Totals *t, co
     }
 }
 
-constexpr uint32_t kPtVec = 4;   // bucket entries a seed-lookup thread loads at a time
-
-// Candidates: one thread per (seed, surface) walks the buckets of its road
-// and keeps the objects inside the road's azimuth window (padded,
-// conservative) that pass the exact binary64 curvature test.  The offsets of
-// the four ranges of a bin are loaded together, and the ranges are walked as
-// one sequence, kPtVec entries at a time, so that a bin costs few dependent
-// round trips to memory.  Pairs collect in a
-// per-thread LDS buffer and are appended to the block's sub-list of the
-// (unordered) pair list with one reservation per wave; a thread whose buffer
-// fills flushes it alone.  The other seed cuts run in k_pt_eval, one thread
-// per pair.
+// Candidates: the 64 (seed, surface) units of a wave (one per lane) step
+// through the azimuth bins of their roads together.  For each bin a lane
+// loads the offsets of the bin's four ranges (the curvature range of each
+// resolution class, and the wide objects) and stores them in LDS; the wave
+// pools the entries of all lanes' ranges and the lanes take them 64 at a
+// time, so loads and tests run on full waves however the bucket sizes are
+// spread.  An entry finds its owner lane by a binary search over the lanes'
+// first-entry offsets, its range in the owner's LDS slot, and the owner's
+// azimuth window and curvature by lane shuffles.  Entries inside the road's
+// azimuth window (padded, conservative) that pass the exact binary64
+// curvature test are appended as (seed, object) pairs to the block's region
+// of an unordered pair list; the other seed cuts run in k_pt_eval, one
+// thread per pair.
 template <int kKind>
 __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Consts c, uint32_t nsub, int stats)
 {
-    __shared__ uint32_t buf[kPairBuf * 256];
+    __shared__ uint32_t s_rng[4][7][64];             // per lane: a0..a3, then cumulative sizes c1..c3
+    __shared__ uint32_t s_n;                          // appends to this block's region
     const uint32_t n = min(t->n_pls, b.cap_pls) * c.n_surf;
-    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    const unsigned long long below = (1ull << lane) - 1ull;
     const uint32_t *bk_off = kKind == 0 ? b.bk3_off : b.bk5_off;
     const float4 *bks = kKind == 0 ? b.bk3_ks : b.bk5_ks;
-    __shared__ uint32_t s_n;             // appends to this block's region
     const uint32_t cap = (kKind == 0 ? b.cap_ptc3 : b.cap_ptc5) / nsub;
-    uint32_t *n_pairs = &s_n;
     uint32_t *out_p = (kKind == 0 ? b.ptc3_p : b.ptc5_p) + (size_t)blockIdx.x * cap;
     uint32_t *out_o = (kKind == 0 ? b.ptc3_o : b.ptc5_o) + (size_t)blockIdx.x * cap;
     if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
     const uint32_t per_row = 3u * c.nkb + 1u;
     const float two_pi = 2.0f * kPiF;
-    const unsigned long long below = (1ull << lane) - 1ull;
     uint64_t cand = 0;
-    // every lane of a wave runs the same number of iterations (the wave
-    // reservation below needs them all)
+    // every lane of a wave runs the same number of iterations and steps
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
         const uint32_t unit = base + threadIdx.x;
         const uint32_t p = unit / c.n_surf;
-        uint32_t k = 0;                  // pairs in this thread's buffer
-        auto store = [&](uint32_t at) {
-            for (uint32_t j = 0; j < k; j++) {
-                if (at + j < cap) {
-                    out_p[at + j] = p;
-                    out_o[at + j] = buf[j * 256u + threadIdx.x];
-                }
-            }
-        };
         const uint4 r = unit < n ? b.road[unit] : make_uint4(0u, 0u, 0u, 0u);
-        if (r.z & 0x80000000u) {
+        const bool road = (r.z & 0x80000000u) != 0u;
+        uint32_t row0 = 0, first = 0, nbins = 0;
+        double kp = 0.0, skp = 0.0;
+        float2 rp = make_float2(0.f, 0.f);
+        if (road) {
             const uint32_t sfi = unit - p * c.n_surf;
-            const float *par = b.in_par + 5 * (size_t)p;
-            const float *cov = b.in_cov + 15 * (size_t)p;
-            const double kp = (double)par[0] * c.kB;
-            const double skp = c.kB * sqrt((double)cov[0]);
-            const uint32_t e = b.pls_ev[p];
-            const uint32_t row0 = (e * c.n_surf + sfi) * c.nphi;
-            const uint32_t first = r.x & 0xFFFFu, nbins = r.x >> 16;
-            const uint32_t kr0 = r.y & 0xFFFFu, kr1 = r.y >> 16, kr2 = r.z & 0xFFFFu;
-            const float2 rp = b.road_phi[unit];
-            auto visit = [&](const float4 q) {
-                cand++;
-                float dphi = q.z - rp.x;
-                dphi -= two_pi * floorf(dphi / two_pi);
-                if (!(dphi <= rp.y)) return;
-                if (!(fabs(kp - (double)q.x) <= c.n_sigma * (skp + (double)q.y))) return;
-                if (k == kPairBuf) {
-                    store(atomicAdd(n_pairs, k));
-                    k = 0;
-                }
-                buf[k * 256u + threadIdx.x] = __float_as_uint(q.w);
-                k++;
-            };
-            for (uint32_t j = 0; j < nbins; j++) {
-                uint32_t bin = first + j;
-                if (bin >= c.nphi) bin -= c.nphi;
-                const uint32_t rb = (row0 + bin) * per_row;
-                // parts 0-2: the curvature range of each resolution class; 3: wide objects
-                const uint32_t a0 = bk_off[rb + (kr0 & 0xFFu)], e0 = bk_off[rb + (kr0 >> 8) + 1u];
-                const uint32_t a1 = bk_off[rb + c.nkb + (kr1 & 0xFFu)], e1 = bk_off[rb + c.nkb + (kr1 >> 8) + 1u];
-                const uint32_t a2 = bk_off[rb + 2u * c.nkb + (kr2 & 0xFFu)];
-                const uint32_t e2 = bk_off[rb + 2u * c.nkb + (kr2 >> 8) + 1u];
-                const uint32_t a3 = bk_off[rb + 3u * c.nkb], e3 = bk_off[rb + per_row];
-                // the four ranges as one sequence, kPtVec entries loaded at a time
-                const uint32_t c1 = e0 > a0 ? e0 - a0 : 0u;
-                const uint32_t c2 = c1 + (e1 > a1 ? e1 - a1 : 0u);
-                const uint32_t c3 = c2 + (e2 > a2 ? e2 - a2 : 0u);
-                const uint32_t T = c3 + (e3 > a3 ? e3 - a3 : 0u);
-                for (uint32_t t0 = 0; t0 < T; t0 += kPtVec) {
-                    float4 q[kPtVec];
-#pragma unroll
-                    for (uint32_t v = 0; v < kPtVec; v++) {
-                        const uint32_t tt = min(t0 + v, T - 1u);
-                        const uint32_t i = tt < c1 ? a0 + tt : tt < c2 ? a1 + (tt - c1) : tt < c3 ? a2 + (tt - c2)
-                                                                                               : a3 + (tt - c3);
-                        q[v] = bks[i];
-                    }
-#pragma unroll
-                    for (uint32_t v = 0; v < kPtVec; v++)
-                        if (t0 + v < T) visit(q[v]);
-                }
-            }
+            kp = (double)b.in_par[5 * (size_t)p] * c.kB;
+            skp = c.kB * sqrt((double)b.in_cov[15 * (size_t)p]);
+            row0 = (b.pls_ev[p] * c.n_surf + sfi) * c.nphi;
+            first = r.x & 0xFFFFu;
+            nbins = r.x >> 16;
+            rp = b.road_phi[unit];
         }
-        // one reservation per wave; the buffers go out column by column
-        // (entry j of every lane that has one), so that stores coalesce
-        const uint32_t tot = __shfl(wave_incl_scan(k), 63);
-        uint32_t at = 0;
-        if (tot != 0u && lane == 63u) at = atomicAdd(n_pairs, tot);
-        at = __shfl(at, 63);
-        for (uint32_t j = 0; j < kPairBuf; j++) {
-            const bool has = j < k;
-            const unsigned long long m = __ballot(has);
-            if (m == 0ull) break;
-            if (has) {
-                const uint32_t slot = at + (uint32_t)__popcll(m & below);
-                if (slot < cap) {
-                    out_p[slot] = p;
-                    out_o[slot] = buf[j * 256u + threadIdx.x];
+        const uint32_t kr0 = r.y & 0xFFFFu, kr1 = r.y >> 16, kr2 = r.z & 0xFFFFu;
+        for (uint32_t j = 0;; j++) {
+            if (__ballot(j < nbins) == 0ull) break;
+            uint32_t T = 0;
+            {
+                uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0, c1 = 0, c2 = 0, c3 = 0;
+                if (j < nbins) {
+                    uint32_t bin = first + j;
+                    if (bin >= c.nphi) bin -= c.nphi;
+                    const uint32_t rb = (row0 + bin) * per_row;
+                    a0 = bk_off[rb + (kr0 & 0xFFu)];
+                    const uint32_t e0 = bk_off[rb + (kr0 >> 8) + 1u];
+                    a1 = bk_off[rb + c.nkb + (kr1 & 0xFFu)];
+                    const uint32_t e1 = bk_off[rb + c.nkb + (kr1 >> 8) + 1u];
+                    a2 = bk_off[rb + 2u * c.nkb + (kr2 & 0xFFu)];
+                    const uint32_t e2 = bk_off[rb + 2u * c.nkb + (kr2 >> 8) + 1u];
+                    a3 = bk_off[rb + 3u * c.nkb];
+                    const uint32_t e3 = bk_off[rb + per_row];
+                    c1 = e0 > a0 ? e0 - a0 : 0u;
+                    c2 = c1 + (e1 > a1 ? e1 - a1 : 0u);
+                    c3 = c2 + (e2 > a2 ? e2 - a2 : 0u);
+                    T = c3 + (e3 > a3 ? e3 - a3 : 0u);
+                }
+                s_rng[wv][0][lane] = a0;
+                s_rng[wv][1][lane] = a1;
+                s_rng[wv][2][lane] = a2;
+                s_rng[wv][3][lane] = a3;
+                s_rng[wv][4][lane] = c1;
+                s_rng[wv][5][lane] = c2;
+                s_rng[wv][6][lane] = c3;
+            }
+            wave_lds_sync();
+            const uint32_t incl = wave_incl_scan(T);
+            const uint32_t off = incl - T;
+            const uint32_t total = __shfl(incl, 63);
+            for (uint32_t cb = 0; cb < total; cb += 64u) {
+                const uint32_t ci = cb + lane;
+                uint32_t o = 0;
+#pragma unroll
+                for (uint32_t step = 32; step; step >>= 1)
+                    if (__shfl(off, o + step) <= ci) o += step;
+                const uint32_t o_off = __shfl(off, o), o_p = __shfl(p, o);
+                const double o_kp = __shfl(kp, o), o_skp = __shfl(skp, o);
+                const float o_plo = __shfl(rp.x, o), o_pw = __shfl(rp.y, o);
+                bool pass = false;
+                uint32_t obj = 0;
+                if (ci < total) {
+                    const uint32_t tt = ci - o_off;
+                    const uint32_t c1 = s_rng[wv][4][o], c2 = s_rng[wv][5][o], c3 = s_rng[wv][6][o];
+                    const uint32_t i = tt < c1 ? s_rng[wv][0][o] + tt
+                                     : tt < c2 ? s_rng[wv][1][o] + (tt - c1)
+                                     : tt < c3 ? s_rng[wv][2][o] + (tt - c2)
+                                               : s_rng[wv][3][o] + (tt - c3);
+                    const float4 q = bks[i];
+                    cand++;
+                    float dphi = q.z - o_plo;
+                    dphi -= two_pi * floorf(dphi / two_pi);
+                    pass = dphi <= o_pw && fabs(o_kp - (double)q.x) <= c.n_sigma * (o_skp + (double)q.y);
+                    obj = __float_as_uint(q.w);
+                }
+                const unsigned long long mk = __ballot(pass);
+                const uint32_t np = (uint32_t)__popcll(mk);
+                uint32_t at = 0;
+                if (np != 0u && lane == 0u) at = atomicAdd(&s_n, np);
+                at = __shfl(at, 0);
+                if (pass) {
+                    const uint32_t slot = at + (uint32_t)__popcll(mk & below);
+                    if (slot < cap) {
+                        out_p[slot] = o_p;
+                        out_o[slot] = obj;
+                    }
                 }
             }
-            at += (uint32_t)__popcll(m);
+            wave_lds_sync();
         }
     }
     __syncthreads();
