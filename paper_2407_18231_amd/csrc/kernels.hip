@@ -1010,8 +1010,9 @@ __global__ __launch_bounds__(256) void k_t5(const Batch b, Totals *t, const Cons
             const float k2 = ks2.x, sk2 = ks2.y;
             float k3, sk3, d1, d2;
             if (!kFill) cand++;
-            kappa3(c, A, C, E, k3, sk3, d1, d2);
+            // the pairwise test of the two stored curvatures needs no new arithmetic
             if (!(fabsf(k1 - k2) <= c.ns * (sk1 + sk2))) continue;
+            kappa3(c, A, C, E, k3, sk3, d1, d2);
             if (!(fabsf(k1 - k3) <= c.ns * (sk1 + sk3))) continue;
             if (!(fabsf(k2 - k3) <= c.ns * (sk2 + sk3))) continue;
             if (!rz3(c, A, C, E, d1, d2)) continue;
