@@ -58,9 +58,10 @@ __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t &total)
     return off + inc - v;
 }
 
-__device__ inline uint32_t scan_chunk(uint32_t n)
+// values per block: whole tiles, nb blocks covering n
+__device__ inline uint32_t scan_chunk(uint32_t n, uint32_t nb)
 {
-    uint32_t per = (n + kScanGrid - 1) / kScanGrid;
+    uint32_t per = (n + nb - 1) / nb;
     return (per + kScanTile - 1) / kScanTile * kScanTile;
 }
 
@@ -72,7 +73,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_up(const uint32_t *__restri
                                                         uint32_t *__restrict__ part)
 {
     const uint32_t n = min(*n_ptr, cap);
-    const uint32_t chunk = scan_chunk(n);
+    const uint32_t chunk = scan_chunk(n, gridDim.x);
     const uint32_t start = min(blockIdx.x * chunk, n);
     const uint32_t end = min(start + chunk, n);
     uint32_t s = 0;
@@ -92,7 +93,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_up(const uint32_t *__restri
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_mid(uint32_t *__restrict__ part,
+__global__ __launch_bounds__(kScanBlock) void k_scan_mid(uint32_t *__restrict__ part, uint32_t nb,
                                                          const uint32_t *n_ptr, uint32_t cap,
                                                          uint32_t *__restrict__ out,
                                                          uint32_t *total_out)
@@ -103,14 +104,16 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_mid(uint32_t *__restrict__ 
     uint32_t v[kPer], s = 0;
 #pragma unroll
     for (uint32_t k = 0; k < kPer; k++) {
-        v[k] = part[threadIdx.x * kPer + k];
+        const uint32_t i = threadIdx.x * kPer + k;
+        v[k] = i < nb ? part[i] : 0u;
         s += v[k];
     }
     uint32_t tot;
     uint32_t ex = block_excl_scan(s, tot);
 #pragma unroll
     for (uint32_t k = 0; k < kPer; k++) {
-        part[threadIdx.x * kPer + k] = ex;
+        const uint32_t i = threadIdx.x * kPer + k;
+        if (i < nb) part[i] = ex;
         ex += v[k];
     }
     if (threadIdx.x == 0) {
@@ -125,7 +128,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_down(const uint32_t *__rest
                                                           uint32_t *__restrict__ out)
 {
     const uint32_t n = min(*n_ptr, cap);
-    const uint32_t chunk = scan_chunk(n);
+    const uint32_t chunk = scan_chunk(n, gridDim.x);
     const uint32_t start = min(blockIdx.x * chunk, n);
     const uint32_t end = min(start + chunk, n);
     uint32_t carry = part[blockIdx.x];
@@ -1621,9 +1624,12 @@ __global__ void k_event_table(const Batch b, const Totals *t, const Consts c)
 void Launcher::scan(const uint32_t *in, uint32_t *out, const uint32_t *n_ptr, uint32_t cap,
                     uint32_t *total, const char *name)
 {
-    launch(name, k_scan_up, dim3(kScanGrid), dim3(kScanBlock), in, n_ptr, cap, part);
-    launch(name, k_scan_mid, dim3(1), dim3(kScanBlock), part, n_ptr, cap, out, total);
-    launch(name, k_scan_down, dim3(kScanGrid), dim3(kScanBlock), in, n_ptr, cap, (const uint32_t *)part, out);
+    // blocks for the capacity (the count itself is known on the device only)
+    const uint32_t nb = (uint32_t)std::max<uint64_t>(
+        1u, std::min<uint64_t>(kScanGrid, ((uint64_t)cap + kScanTile - 1) / kScanTile));
+    launch(name, k_scan_up, dim3(nb), dim3(kScanBlock), in, n_ptr, cap, part);
+    launch(name, k_scan_mid, dim3(1), dim3(kScanBlock), part, nb, n_ptr, cap, out, total);
+    launch(name, k_scan_down, dim3(nb), dim3(kScanBlock), in, n_ptr, cap, (const uint32_t *)part, out);
 }
 
 static inline dim3 grid_for(uint64_t units)
