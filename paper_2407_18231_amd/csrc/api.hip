@@ -187,7 +187,8 @@ struct Slot {
     size_t in_bytes = 0, work_bytes = 0;
     Batch b{};
     Totals *d_tot = nullptr, *h_tot = nullptr;
-    uint32_t *d_part = nullptr;
+    uint32_t *d_part = nullptr;          // scan partials of the stream and of the side stream
+    hipStream_t side = nullptr;
     char *h_stage = nullptr;
     size_t stage_bytes = 0;
     char *h_out = nullptr;              // pinned landing buffer of the results
@@ -291,7 +292,10 @@ void destroy_slot(Slot &s)
     if (s.h_tot) (void)hipHostFree(s.h_tot);
     if (s.d_part) (void)hipFree(s.d_part);
     for (hipEvent_t e : s.L.pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : s.L.ev_fork) if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : s.L.ev_join) if (e) (void)hipEventDestroy(e);
     if (s.done) (void)hipEventDestroy(s.done);
+    if (s.side) (void)hipStreamDestroy(s.side);
     if (s.stream) (void)hipStreamDestroy(s.stream);
 }
 
@@ -302,10 +306,18 @@ lst_status make_slot(lst_ctx *ctx, std::unique_ptr<Slot> &out)
     HIP_TRY(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
     HIP_TRY(hipMalloc(&s->d_tot, sizeof(lst::Totals)));
     HIP_TRY(hipHostMalloc((void **)&s->h_tot, sizeof(lst::Totals), hipHostMallocDefault));
-    HIP_TRY(hipMalloc(&s->d_part, sizeof(uint32_t) * lst::kScanGrid));
+    HIP_TRY(hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking));
+    HIP_TRY(hipMalloc(&s->d_part, 2 * sizeof(uint32_t) * lst::kScanGrid));
     HIP_TRY(hipEventCreateWithFlags(&s->done, hipEventDisableTiming));
+    for (int k = 0; k < 2; k++) {
+        HIP_TRY(hipEventCreateWithFlags(&s->L.ev_fork[k], hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&s->L.ev_join[k], hipEventDisableTiming));
+    }
     s->L.stream = s->stream;
+    s->L.side = s->side;
+    s->L.cur = s->stream;
     s->L.part = s->d_part;
+    s->L.part_side = s->d_part + lst::kScanGrid;
     out = std::move(s);
     return LST_OK;
 }

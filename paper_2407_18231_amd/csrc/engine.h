@@ -145,8 +145,12 @@ struct Batch {
 // Launches kernels on one stream; optionally brackets each launch with HIP
 // events to time it.
 struct Launcher {
-    hipStream_t stream = nullptr;
-    uint32_t *part = nullptr;           // scan partials, kScanGrid entries
+    hipStream_t stream = nullptr;       // the slot's stream
+    hipStream_t side = nullptr;         // second stream for branches of the chain that run alongside
+    hipStream_t cur = nullptr;          // stream the next launches go to
+    uint32_t *part = nullptr;           // scan partials of each stream, kScanGrid entries
+    uint32_t *part_side = nullptr;
+    hipEvent_t ev_fork[2] = {nullptr, nullptr}, ev_join[2] = {nullptr, nullptr};
     bool timing = false;
     const char *only = nullptr;         // with timing: time only the launches of this name (nullptr: all)
     std::vector<hipEvent_t> pool;
@@ -164,6 +168,30 @@ struct Launcher {
         return pool[used++];
     }
 
+    // the side stream starts after what the slot's stream has queued so far
+    void fork(int k)
+    {
+        if (!side) return;
+        hipError_t e = hipEventRecord(ev_fork[k], stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(side, ev_fork[k], 0);
+        if (e != hipSuccess && err == hipSuccess) err = e;
+    }
+    // a point on the side stream (after what it has queued so far) ...
+    void mark(int k)
+    {
+        if (!side) return;
+        hipError_t e = hipEventRecord(ev_join[k], side);
+        if (e != hipSuccess && err == hipSuccess) err = e;
+    }
+    // ... that the slot's stream waits for from here on
+    void wait(int k)
+    {
+        if (!side) return;
+        hipError_t e = hipStreamWaitEvent(stream, ev_join[k], 0);
+        if (e != hipSuccess && err == hipSuccess) err = e;
+    }
+    void on_side(bool s) { cur = (s && side) ? side : stream; }
+
     template <typename... KArgs, typename... Args>
     void launch(const char *name, void (*kernel)(KArgs...), dim3 grid, dim3 block, Args... args)
     {
@@ -175,17 +203,18 @@ struct Launcher {
     void launch_lds(const char *name, void (*kernel)(KArgs...), dim3 grid, dim3 block, uint32_t lds, Args... args)
     {
         hipEvent_t e0 = nullptr, e1 = nullptr;
+        const hipStream_t st = cur ? cur : stream;
         const bool timed = timing && (only == nullptr || std::strcmp(only, name) == 0);
         if (timed) {
             e0 = next_event();
             e1 = next_event();
-            if (e0) (void)hipEventRecord(e0, stream);
+            if (e0) (void)hipEventRecord(e0, st);
         }
-        kernel<<<grid, block, lds, stream>>>(args...);
+        kernel<<<grid, block, lds, st>>>(args...);
         hipError_t le = hipGetLastError();
         if (le != hipSuccess && err == hipSuccess) err = le;
         if (timed && e1) {
-            (void)hipEventRecord(e1, stream);
+            (void)hipEventRecord(e1, st);
             recs.push_back({name, {e0, e1}});
         }
     }

@@ -1627,9 +1627,10 @@ void Launcher::scan(const uint32_t *in, uint32_t *out, const uint32_t *n_ptr, ui
     // blocks for the capacity (the count itself is known on the device only)
     const uint32_t nb = (uint32_t)std::max<uint64_t>(
         1u, std::min<uint64_t>(kScanGrid, ((uint64_t)cap + kScanTile - 1) / kScanTile));
-    launch(name, k_scan_up, dim3(nb), dim3(kScanBlock), in, n_ptr, cap, part);
-    launch(name, k_scan_mid, dim3(1), dim3(kScanBlock), part, nb, n_ptr, cap, out, total);
-    launch(name, k_scan_down, dim3(nb), dim3(kScanBlock), in, n_ptr, cap, (const uint32_t *)part, out);
+    uint32_t *pt = (side && cur == side) ? part_side : part;
+    launch(name, k_scan_up, dim3(nb), dim3(kScanBlock), in, n_ptr, cap, pt);
+    launch(name, k_scan_mid, dim3(1), dim3(kScanBlock), pt, nb, n_ptr, cap, out, total);
+    launch(name, k_scan_down, dim3(nb), dim3(kScanBlock), in, n_ptr, cap, (const uint32_t *)pt, out);
 }
 
 static inline dim3 grid_for(uint64_t units)
@@ -1644,12 +1645,26 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
 {
     const dim3 blk(256);
     const uint32_t n_mod = c.n_mod;
-    // a1: hit ingest & sort by (event, module, sensor)
+    const uint32_t cap_rows = b.cap_ev * c.n_surf * c.nphi;
+    const uint32_t cap_bk = cap_rows * (3 * c.nkb + 1);
+    const uint64_t cap_pu = (uint64_t)b.cap_pls * c.n_surf;
+    const dim3 gwalk = grid_for(cap_pu);
+    const uint32_t nsub = gwalk.x;
+    // Two streams: the seed checks and roads, then (after T3) T5, its
+    // buckets and pT5, run on the side stream alongside the main chain; the
+    // track-candidate selection waits for both.
+    L.on_side(false);
     launch_setup(L, t, c);
+    L.fork(0);
+    L.on_side(true);
+    L.launch("pls_check", k_pls_check, grid_for(b.cap_pls), blk, b, t);
+    L.launch("road", k_road, grid_for(cap_pu), blk, b, (const Totals *)t, g, c);
+    L.mark(0);                           // the main stream waits for this only before its seed walk
+    L.on_side(false);
+    // a1: hit ingest & sort by (event, module, sensor)
     const uint32_t n_sl = (2u * n_mod + g.hist_slice - 1u) / g.hist_slice;
     const dim3 gh((unsigned)std::min<uint64_t>((uint64_t)b.cap_ev * n_sl, kMaxGrid));
     L.launch_lds("hit_hist", k_hit_hist, gh, dim3(kHistBlock), g.hist_slice * 4u, b, t, n_mod, g.hist_slice);
-    L.launch("pls_check", k_pls_check, grid_for(b.cap_pls), blk, b, t);
     L.scan(b.bin_cnt, b.bin_off, &t->n_bins, b.cap_ev * 2u * n_mod, &t->n_sorted, "scan_hits");
     L.launch("hit_scatter", k_hit_scatter, grid_for(b.cap_hits), blk, b, (const Totals *)t);
     L.launch("hit_gather", k_hit_gather, grid_for((uint64_t)b.cap_ev * 2 * n_mod), blk, b, (const Totals *)t,
@@ -1661,7 +1676,7 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     L.launch("md_fill", k_md<true>, gmd, blk, b, t, g, c, 0);
     L.launch("md_units", k_md_units, grid_for((uint64_t)b.cap_ev * n_mod + 1), blk, b, (const Totals *)t);
     // a3: line segments over the connection map
-    // small batches: 32 lanes per MD for latency; large ones: a thread per MD
+    // small batches: 32 lanes per MD for latency; large ones: pooled walk
     if (b.cap_md <= kLsWaveMaxMd) {
         L.launch("ls_count", k_ls_wave<false>, grid_for(32ull * b.cap_md), blk, b, t, g, c, stats);
         L.scan(b.ls_cnt, b.ls_off, &t->n_md, b.cap_md, &t->n_ls, "scan_ls");
@@ -1684,46 +1699,48 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
              &t->n_t3s);
     L.scan(b.t3_cnt, b.t3_off, &t->n_ls, b.cap_ls, &t->n_t3, "scan_t3");
     L.launch("t3_place", k_t3_place, grid_for(b.cap_t3), blk, b, nsub_t3);
-    // a5: T5
+
+    // side: a5 T5, its seed-lookup buckets (a6) and pT5 (a7)
+    L.fork(1);
+    L.on_side(true);
     L.launch("t5_count", k_t5<false>, grid_for(b.cap_t3), blk, b, t, c, stats);
     L.scan(b.t5_cnt, b.t5_off, &t->n_t3, b.cap_t3, &t->n_t5, "scan_t5");
     L.launch("t5_fill", k_t5<true>, grid_for(b.cap_t3), blk, b, t, c, 0);
-    // a6: seed lookup buckets
-    const uint32_t cap_rows = b.cap_ev * c.n_surf * c.nphi;
-    const uint32_t cap_bk = cap_rows * (3 * c.nkb + 1);
-    L.launch("zero", k_zero_u32, grid_for((uint64_t)cap_bk + 1), blk, b.bk3_cnt, &t->n_bk, cap_bk, 1u);
     L.launch("zero", k_zero_u32, grid_for((uint64_t)cap_bk + 1), blk, b.bk5_cnt, &t->n_bk, cap_bk, 1u);
-    L.launch("bucket_hist", k_bucket_hist<0>, grid_for(b.cap_t3), blk, b, t, g, c);
     L.launch("bucket_hist", k_bucket_hist<1>, grid_for(b.cap_t5), blk, b, t, g, c);
-    L.scan(b.bk3_cnt, b.bk3_off, &t->n_bk, cap_bk, &t->n_bk3, "scan_bucket");
     L.scan(b.bk5_cnt, b.bk5_off, &t->n_bk, cap_bk, &t->n_bk5, "scan_bucket");
-    L.launch("bucket_scatter", k_bucket_scatter<0>, grid_for(b.cap_t3), blk, b, (const Totals *)t);
     L.launch("bucket_scatter", k_bucket_scatter<1>, grid_for(b.cap_t5), blk, b, (const Totals *)t);
-    // a7: pT3 / pT5: roads, candidate pairs, seed cuts, per-seed placement and order
-    const uint64_t cap_pu = (uint64_t)b.cap_pls * c.n_surf;
-    L.launch("road", k_road, grid_for(cap_pu), blk, b, (const Totals *)t, g, c);
-    const dim3 gwalk = grid_for(cap_pu);
-    const uint32_t nsub = gwalk.x;
-    L.launch("pt3c_walk", k_ptc<0>, gwalk, blk, b, t, c, nsub, stats);
     L.launch("pt5c_walk", k_ptc<1>, gwalk, blk, b, t, c, nsub, stats);
-    L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.ptc3_sub, b.ptc3_soff, b.cap_ptc3, nsub,
-             &t->n_ptc3);
     L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.ptc5_sub, b.ptc5_soff, b.cap_ptc5, nsub,
              &t->n_ptc5);
-    L.launch("zero", k_zero_u32, grid_for((uint64_t)b.cap_pls + 1), blk, b.pt3_cnt, &t->n_pls, b.cap_pls, 1u);
     L.launch("zero", k_zero_u32, grid_for((uint64_t)b.cap_pls + 1), blk, b.pt5_cnt, &t->n_pls, b.cap_pls, 1u);
-    L.launch("pt3_eval", k_pt_eval<0>, grid_for(b.cap_ptc3), blk, b, c, nsub);
     L.launch("pt5_eval", k_pt_eval<1>, grid_for(b.cap_ptc5), blk, b, c, nsub);
-    L.scan(b.pt3_cnt, b.pt3_off, &t->n_pls, b.cap_pls, &t->n_pt3, "scan_pt");
     L.scan(b.pt5_cnt, b.pt5_off, &t->n_pls, b.cap_pls, &t->n_pt5, "scan_pt");
-    L.launch("pt_place", k_pt_place<0>, grid_for(b.cap_ptc3), blk, b, nsub);
     L.launch("pt_place", k_pt_place<1>, grid_for(b.cap_ptc5), blk, b, nsub);
-    L.launch("pt_order", k_pt_order<0>, grid_for(b.cap_pt3), blk, b, (const Totals *)t);
     L.launch("pt_order", k_pt_order<1>, grid_for(b.cap_pt5), blk, b, (const Totals *)t);
-    // a8: track candidates
+    L.launch("zero8", k_zero_u8, grid_for(b.cap_t5), blk, b.t5_used, &t->n_t5, b.cap_t5);
+
+    // main: the T3 seed-lookup buckets (a6) and pT3 (a7)
+    L.on_side(false);
+    L.launch("zero", k_zero_u32, grid_for((uint64_t)cap_bk + 1), blk, b.bk3_cnt, &t->n_bk, cap_bk, 1u);
+    L.launch("bucket_hist", k_bucket_hist<0>, grid_for(b.cap_t3), blk, b, t, g, c);
+    L.scan(b.bk3_cnt, b.bk3_off, &t->n_bk, cap_bk, &t->n_bk3, "scan_bucket");
+    L.launch("bucket_scatter", k_bucket_scatter<0>, grid_for(b.cap_t3), blk, b, (const Totals *)t);
+    L.wait(0);
+    L.launch("pt3c_walk", k_ptc<0>, gwalk, blk, b, t, c, nsub, stats);
+    L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.ptc3_sub, b.ptc3_soff, b.cap_ptc3, nsub,
+             &t->n_ptc3);
+    L.launch("zero", k_zero_u32, grid_for((uint64_t)b.cap_pls + 1), blk, b.pt3_cnt, &t->n_pls, b.cap_pls, 1u);
+    L.launch("pt3_eval", k_pt_eval<0>, grid_for(b.cap_ptc3), blk, b, c, nsub);
+    L.scan(b.pt3_cnt, b.pt3_off, &t->n_pls, b.cap_pls, &t->n_pt3, "scan_pt");
+    L.launch("pt_place", k_pt_place<0>, grid_for(b.cap_ptc3), blk, b, nsub);
+    L.launch("pt_order", k_pt_order<0>, grid_for(b.cap_pt3), blk, b, (const Totals *)t);
     L.launch("zero8", k_zero_u8, grid_for(b.cap_pls), blk, b.pls_used5, &t->n_pls, b.cap_pls);
     L.launch("zero8", k_zero_u8, grid_for(b.cap_pls), blk, b.pls_used3, &t->n_pls, b.cap_pls);
-    L.launch("zero8", k_zero_u8, grid_for(b.cap_t5), blk, b.t5_used, &t->n_t5, b.cap_t5);
+
+    // a8: track candidates, once both branches are done
+    L.mark(1);
+    L.wait(1);
     L.launch("tc_mark", k_tc_mark, grid_for(std::max(b.cap_pt3, b.cap_pt5)), blk, b, (const Totals *)t);
     L.launch("tc_keep", k_tc_keep, grid_for((uint64_t)b.cap_pt3 + b.cap_t5 + b.cap_pls), blk, b, t);
     L.scan(b.tc_cnt, b.tc_off, &t->n_tcu, b.cap_pt3 + b.cap_t5 + b.cap_pls, &t->n_tc, "scan_tc");
