@@ -1659,7 +1659,14 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     L.on_side(true);
     L.launch("pls_check", k_pls_check, grid_for(b.cap_pls), blk, b, t);
     L.launch("road", k_road, grid_for(cap_pu), blk, b, (const Totals *)t, g, c);
-    L.mark(0);                           // the main stream waits for this only before its seed walk
+    // counters of later stages that need clearing
+    L.launch("zero", k_zero_u32, grid_for((uint64_t)cap_bk + 1), blk, b.bk3_cnt, &t->n_bk, cap_bk, 1u);
+    L.launch("zero", k_zero_u32, grid_for((uint64_t)cap_bk + 1), blk, b.bk5_cnt, &t->n_bk, cap_bk, 1u);
+    L.launch("zero", k_zero_u32, grid_for((uint64_t)b.cap_pls + 1), blk, b.pt3_cnt, &t->n_pls, b.cap_pls, 1u);
+    L.launch("zero", k_zero_u32, grid_for((uint64_t)b.cap_pls + 1), blk, b.pt5_cnt, &t->n_pls, b.cap_pls, 1u);
+    L.launch("zero8", k_zero_u8, grid_for(b.cap_pls), blk, b.pls_used5, &t->n_pls, b.cap_pls);
+    L.launch("zero8", k_zero_u8, grid_for(b.cap_pls), blk, b.pls_used3, &t->n_pls, b.cap_pls);
+    L.mark(0);                           // the main stream waits for this only before its seed-lookup stage
     L.on_side(false);
     // a1: hit ingest & sort by (event, module, sensor)
     const uint32_t n_sl = (2u * n_mod + g.hist_slice - 1u) / g.hist_slice;
@@ -1706,14 +1713,12 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     L.launch("t5_count", k_t5<false>, grid_for(b.cap_t3), blk, b, t, c, stats);
     L.scan(b.t5_cnt, b.t5_off, &t->n_t3, b.cap_t3, &t->n_t5, "scan_t5");
     L.launch("t5_fill", k_t5<true>, grid_for(b.cap_t3), blk, b, t, c, 0);
-    L.launch("zero", k_zero_u32, grid_for((uint64_t)cap_bk + 1), blk, b.bk5_cnt, &t->n_bk, cap_bk, 1u);
     L.launch("bucket_hist", k_bucket_hist<1>, grid_for(b.cap_t5), blk, b, t, g, c);
     L.scan(b.bk5_cnt, b.bk5_off, &t->n_bk, cap_bk, &t->n_bk5, "scan_bucket");
     L.launch("bucket_scatter", k_bucket_scatter<1>, grid_for(b.cap_t5), blk, b, (const Totals *)t);
     L.launch("pt5c_walk", k_ptc<1>, gwalk, blk, b, t, c, nsub, stats);
     L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.ptc5_sub, b.ptc5_soff, b.cap_ptc5, nsub,
              &t->n_ptc5);
-    L.launch("zero", k_zero_u32, grid_for((uint64_t)b.cap_pls + 1), blk, b.pt5_cnt, &t->n_pls, b.cap_pls, 1u);
     L.launch("pt5_eval", k_pt_eval<1>, grid_for(b.cap_ptc5), blk, b, c, nsub);
     L.scan(b.pt5_cnt, b.pt5_off, &t->n_pls, b.cap_pls, &t->n_pt5, "scan_pt");
     L.launch("pt_place", k_pt_place<1>, grid_for(b.cap_ptc5), blk, b, nsub);
@@ -1722,21 +1727,17 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
 
     // main: the T3 seed-lookup buckets (a6) and pT3 (a7)
     L.on_side(false);
-    L.launch("zero", k_zero_u32, grid_for((uint64_t)cap_bk + 1), blk, b.bk3_cnt, &t->n_bk, cap_bk, 1u);
+    L.wait(0);
     L.launch("bucket_hist", k_bucket_hist<0>, grid_for(b.cap_t3), blk, b, t, g, c);
     L.scan(b.bk3_cnt, b.bk3_off, &t->n_bk, cap_bk, &t->n_bk3, "scan_bucket");
     L.launch("bucket_scatter", k_bucket_scatter<0>, grid_for(b.cap_t3), blk, b, (const Totals *)t);
-    L.wait(0);
     L.launch("pt3c_walk", k_ptc<0>, gwalk, blk, b, t, c, nsub, stats);
     L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.ptc3_sub, b.ptc3_soff, b.cap_ptc3, nsub,
              &t->n_ptc3);
-    L.launch("zero", k_zero_u32, grid_for((uint64_t)b.cap_pls + 1), blk, b.pt3_cnt, &t->n_pls, b.cap_pls, 1u);
     L.launch("pt3_eval", k_pt_eval<0>, grid_for(b.cap_ptc3), blk, b, c, nsub);
     L.scan(b.pt3_cnt, b.pt3_off, &t->n_pls, b.cap_pls, &t->n_pt3, "scan_pt");
     L.launch("pt_place", k_pt_place<0>, grid_for(b.cap_ptc3), blk, b, nsub);
     L.launch("pt_order", k_pt_order<0>, grid_for(b.cap_pt3), blk, b, (const Totals *)t);
-    L.launch("zero8", k_zero_u8, grid_for(b.cap_pls), blk, b.pls_used5, &t->n_pls, b.cap_pls);
-    L.launch("zero8", k_zero_u8, grid_for(b.cap_pls), blk, b.pls_used3, &t->n_pls, b.cap_pls);
 
     // a8: track candidates, once both branches are done
     L.mark(1);
