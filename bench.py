@@ -67,6 +67,8 @@ def step_bytes(c: dict, n_hits: int, n_pls: int, n_units: int, s_b: int, e_used:
         "t3_place": 24.0 * nt3,
         "t5_count": t5 + 4.0 * nt3,
         "t5_fill": t5 + 16.0 * nt5,
+        "t5_walk": t5 + 4.0 * nt3,
+        "t5_place": 16.0 * nt5,
     }
     for k in ("3", "5"):
         out[f"pt{k}c_walk"] = 80.0 * n_pls + 12.0 * c["cand_pt" + k] + 8.0 * c["eval_pt" + k]

@@ -132,6 +132,12 @@ void carve_work(Carver &cv, Batch &b, uint32_t n_mod, uint32_t n_surf, uint32_t 
     b.t5_u = cv.take<uint32_t>(b.cap_t5);
     b.t5_w = cv.take<uint32_t>(b.cap_t5);
     b.t5_ks = cv.take<float2>(b.cap_t5);
+    b.t5s_u = cv.take<uint32_t>(b.cap_t5);
+    b.t5s_w = cv.take<uint32_t>(b.cap_t5);
+    b.t5s_j = cv.take<uint32_t>(b.cap_t5);
+    b.t5s_ks = cv.take<float2>(b.cap_t5);
+    b.t5s_sub = cv.take<uint32_t>(kSubLists);
+    b.t5s_soff = cv.take<uint32_t>(kSubLists + 1);
     b.bk3_cnt = cv.take<uint32_t>(bk + 1);
     b.bk3_off = cv.take<uint32_t>(bk + 1);
     b.bk3_id = cv.take<uint32_t>(b.cap_t3);
@@ -361,7 +367,15 @@ lst_status ensure_work(lst_ctx *ctx, Slot &s)
     lst::carve_work(cw, b, c.n_mod, c.n_surf, c.nphi, c.nkb);
     s.work_bytes = cw.off;
     hipError_t e = hipMalloc(&s.work_arena, s.work_bytes);
-    if (e != hipSuccess) { s.work_arena = nullptr; return set_err(ctx, LST_ERR_OOM, "work arena allocation failed"); }
+    if (e != hipSuccess) {
+        s.work_arena = nullptr;
+        return set_err(ctx, LST_ERR_OOM,
+                       "work arena allocation failed (" + std::to_string(s.work_bytes >> 20) + " MiB; capacities md " +
+                           std::to_string(b.cap_md) + " ls " + std::to_string(b.cap_ls) + " t3 " +
+                           std::to_string(b.cap_t3) + " t5 " + std::to_string(b.cap_t5) + " pt3 " +
+                           std::to_string(b.cap_pt3) + " pt5 " + std::to_string(b.cap_pt5) + " pairs " +
+                           std::to_string(b.cap_ptc3) + "/" + std::to_string(b.cap_ptc5) + ")");
+    }
     lst::Carver cw2{(char *)s.work_arena};
     lst::carve_work(cw2, b, c.n_mod, c.n_surf, c.nphi, c.nkb);
     s.graph_valid = false;
@@ -502,7 +516,7 @@ int overflowed(Slot &s)
     g |= grow(t.n_md, b.cap_md);
     g |= grow(std::max(t.n_ls, t.n_lss), b.cap_ls);
     g |= grow(std::max(t.n_t3, t.n_t3s), b.cap_t3);
-    g |= grow(t.n_t5, b.cap_t5);
+    g |= grow(std::max(t.n_t5, t.n_t5s), b.cap_t5);
     g |= grow(t.n_pt3, b.cap_pt3);
     g |= grow(t.n_pt5, b.cap_pt5);
     g |= grow(t.n_ptc3, b.cap_ptc3);
@@ -670,7 +684,7 @@ uint64_t predict_footprint(uint64_t hits, uint64_t pls, const lst::Consts &k)
     lst::Caps c = lst::plan_caps(1, hits, pls);
     uint64_t b = 0;
     b += 73ull * c.hits + 80ull * c.pls + 24ull * k.n_mod;
-    b += (40ull + 4ull * lst::kKeepLs) * c.md + 52ull * c.ls + 88ull * c.t3 + 44ull * c.t5;
+    b += (40ull + 4ull * lst::kKeepLs) * c.md + 52ull * c.ls + 88ull * c.t3 + 64ull * c.t5;
     b += 16ull * (c.pt3 + c.pt5) + 24ull * c.pls * k.n_surf + 19ull * c.pls + 16ull * (c.pt3 + c.t5 + c.pls);
     b += 12ull * (c.ptc3 + c.ptc5);
     b += 2ull * 8ull * k.n_surf * k.nphi * (3 * k.nkb + 1);

@@ -61,6 +61,7 @@ struct Totals {
     uint32_t n_ptc3, n_ptc5;      // seed-object candidate pairs (or, after a sub-list overflow, the capacity needed)
     uint32_t n_lss;               // segments in the unordered segment sub-lists (likewise)
     uint32_t n_t3s;               // T3s in the unordered T3 sub-lists (likewise)
+    uint32_t n_t5s;               // T5s in the unordered T5 regions (likewise)
     uint32_t err;
     unsigned long long cand[6];  // candidates examined: md, ls, t3, t5, pt3, pt5
 };
@@ -112,6 +113,10 @@ struct Batch {
     uint32_t *t5_cnt, *t5_off;          // per inner T3
     uint32_t *t5_u, *t5_w;
     float2 *t5_ks;                      // curvature through (A, C, E) and its resolution
+    // T5s in the block regions of an unordered list before placement:
+    // (inner T3, outer T3, place in the inner T3's list, curvature)
+    uint32_t *t5s_u, *t5s_w, *t5s_j, *t5s_sub, *t5s_soff;
+    float2 *t5s_ks;
     // a6: seed lookup buckets of T3s / T5s by (event, surface, azimuth bin,
     // resolution class, curvature bin); the last bucket of a row holds the
     // objects with a wide curvature resolution

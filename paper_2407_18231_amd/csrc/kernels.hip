@@ -231,6 +231,13 @@ __global__ void k_setup(Totals *t, uint32_t n_mod, uint32_t n_surf, uint32_t nph
         t->n_rows = t->n_ev * n_surf * nphi;
         t->n_bk = t->n_rows * (3u * nkb + 1u);
         t->err = 0;
+        // region needs: written by the stages that append to regions (the
+        // small-batch segment stage does not)
+        t->n_lss = 0;
+        t->n_t3s = 0;
+        t->n_t5s = 0;
+        t->n_ptc3 = 0;
+        t->n_ptc5 = 0;
         for (int i = 0; i < 6; i++) t->cand[i] = 0ull;
     }
 }
@@ -988,47 +995,118 @@ __global__ __launch_bounds__(256) void k_t3_place(const Batch b, uint32_t nsub)
 
 // ------------------------------------------------------------ a5: T5 ----
 
-template <bool kFill>
-__global__ __launch_bounds__(256) void k_t5(const Batch b, Totals *t, const Consts c, int stats)
+// T5: the 64 inner T3s of a wave (one per lane) pool their candidates --
+// the T3s whose inner MD is each one's outer MD (through the LS and T3
+// offsets) -- and the lanes take the pooled candidates 64 at a time, as in
+// the T3 walk.  The stored-curvature test runs first (it needs no new
+// arithmetic).  Survivors go to the block's region of an unordered T5 list
+// with their place in the owner's list; k_t5_place puts them in order.
+__global__ __launch_bounds__(256) void k_t5(const Batch b, Totals *t, const Consts c, uint32_t nsub, int stats)
 {
+    __shared__ uint32_t s_n;             // appends to this block's region
     const uint32_t n = min(t->n_t3, b.cap_t3);
+    const uint32_t lane = threadIdx.x & 63u;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const uint32_t cap = b.cap_t5 / nsub;
+    const size_t sb0 = (size_t)blockIdx.x * cap;
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
     uint64_t cand = 0;
-    GRID_STRIDE(u, n) {
-        const uint2 ac = b.t3_ac[u];
-        const uint32_t ia = ac.x, ic = ac.y;
-        // T3s whose inner MD is ic: those built from segments starting at ic
-        const uint32_t w0 = min(b.t3_off[min(b.ls_off[ic], b.cap_ls)], b.cap_t3);
-        const uint32_t w1 = min(b.t3_off[min(b.ls_off[ic + 1], b.cap_ls)], b.cap_t3);
-        uint32_t k = kFill ? b.t5_off[u] : 0u;
-        if (w0 == w1) {
-            if (!kFill) b.t5_cnt[u] = 0;
-            continue;
-        }
-        const Anchor A = load_anchor(b, ia), C = load_anchor(b, ic);
-        const float2 ks1 = b.t3_ks[u];
-        const float k1 = ks1.x, sk1 = ks1.y;
-        for (uint32_t w = w0; w < w1; w++) {
-            const Anchor E = load_anchor(b, b.t3_ac[w].y);
-            const float2 ks2 = b.t3_ks[w];
-            const float k2 = ks2.x, sk2 = ks2.y;
-            float k3, sk3, d1, d2;
-            if (!kFill) cand++;
-            // the pairwise test of the two stored curvatures needs no new arithmetic
-            if (!(fabsf(k1 - k2) <= c.ns * (sk1 + sk2))) continue;
-            kappa3(c, A, C, E, k3, sk3, d1, d2);
-            if (!(fabsf(k1 - k3) <= c.ns * (sk1 + sk3))) continue;
-            if (!(fabsf(k2 - k3) <= c.ns * (sk2 + sk3))) continue;
-            if (!rz3(c, A, C, E, d1, d2)) continue;
-            if (kFill && k < b.cap_t5) {
-                b.t5_u[k] = u;
-                b.t5_w[k] = w;
-                b.t5_ks[k] = make_float2(k3, sk3);
+    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        const uint32_t u = base + threadIdx.x;
+        uint32_t w0 = 0, cnt = 0;
+        float4 pa = make_float4(0.f, 0.f, 0.f, 0.f), pc = pa;
+        float2 ks1 = make_float2(0.f, 0.f);
+        if (u < n) {
+            const uint2 ac = b.t3_ac[u];
+            // T3s whose inner MD is ac.y: those built from segments starting at ac.y
+            w0 = min(b.t3_off[min(b.ls_off[ac.y], b.cap_ls)], b.cap_t3);
+            const uint32_t w1 = min(b.t3_off[min(b.ls_off[ac.y + 1], b.cap_ls)], b.cap_t3);
+            cnt = w1 > w0 ? w1 - w0 : 0u;
+            if (cnt) {
+                pa = b.md_pos[ac.x];
+                pc = b.md_pos[ac.y];
+                ks1 = b.t3_ks[u];
             }
-            k++;
         }
-        if (!kFill) b.t5_cnt[u] = k;
+        const uint32_t incl = wave_incl_scan(cnt);
+        const uint32_t off = incl - cnt;
+        const uint32_t total = __shfl(incl, 63);
+        uint32_t run = 0;
+        for (uint32_t cb = 0; cb < total; cb += 64u) {
+            const uint32_t ci = cb + lane;
+            uint32_t o = 0;
+#pragma unroll
+            for (uint32_t step = 32; step; step >>= 1)
+                if (__shfl(off, o + step) <= ci) o += step;
+            const uint32_t o_w0 = __shfl(w0, o), o_off = __shfl(off, o), o_run = __shfl(run, o);
+            const uint32_t o_u = __shfl(u, o);
+            const float4 oa = make_float4(__shfl(pa.x, o), __shfl(pa.y, o), __shfl(pa.z, o), __shfl(pa.w, o));
+            const float4 oc = make_float4(__shfl(pc.x, o), __shfl(pc.y, o), __shfl(pc.z, o), __shfl(pc.w, o));
+            const float k1 = __shfl(ks1.x, o), sk1 = __shfl(ks1.y, o);
+            bool pass = false;
+            uint32_t w = 0;
+            float k3 = 0.f, sk3 = 0.f;
+            if (ci < total) {
+                w = o_w0 + (ci - o_off);
+                const float2 ks2 = b.t3_ks[w];
+                const float k2 = ks2.x, sk2 = ks2.y;
+                cand++;
+                // the pairwise test of the two stored curvatures needs no new arithmetic
+                if (fabsf(k1 - k2) <= c.ns * (sk1 + sk2)) {
+                    const Anchor A = anchor_of(oa), C = anchor_of(oc), E = load_anchor(b, b.t3_ac[w].y);
+                    float d1, d2;
+                    kappa3(c, A, C, E, k3, sk3, d1, d2);
+                    pass = fabsf(k1 - k3) <= c.ns * (sk1 + sk3) && fabsf(k2 - k3) <= c.ns * (sk2 + sk3) &&
+                           rz3(c, A, C, E, d1, d2);
+                }
+            }
+            const unsigned long long mk = __ballot(pass);
+            const uint32_t np = (uint32_t)__popcll(mk);
+            uint32_t at = 0;
+            if (np != 0u && lane == 0u) at = atomicAdd(&s_n, np);
+            at = __shfl(at, 0);
+            if (pass) {
+                const uint32_t slot = at + (uint32_t)__popcll(mk & below);
+                const uint32_t s0 = o_off > cb ? o_off - cb : 0u;
+                if (slot < cap) {
+                    b.t5s_u[sb0 + slot] = o_u;
+                    b.t5s_w[sb0 + slot] = w;
+                    b.t5s_j[sb0 + slot] = o_run + (uint32_t)__popcll(mk & below & ~((1ull << s0) - 1ull));
+                    b.t5s_ks[sb0 + slot] = make_float2(k3, sk3);
+                }
+            }
+            if (cnt != 0u && off < cb + 64u && off + cnt > cb) {
+                const uint32_t s0 = off > cb ? off - cb : 0u;
+                const uint32_t e0 = min(off + cnt - cb, 64u);
+                run += (uint32_t)__popcll(mk & lane_range(s0, e0));
+            }
+        }
+        if (u < n) b.t5_cnt[u] = run;
     }
-    if (!kFill && stats) atomicAdd(&t->cand[3], (unsigned long long)cand);
+    __syncthreads();
+    if (threadIdx.x == 0) b.t5s_sub[blockIdx.x] = s_n;
+    if (stats) atomicAdd(&t->cand[3], (unsigned long long)cand);
+}
+
+// T5s from the block regions to their canonical slots
+__global__ __launch_bounds__(256) void k_t5_place(const Batch b, uint32_t nsub)
+{
+    __shared__ uint32_t s_off[kSubLists + 1];
+    for (uint32_t i = threadIdx.x; i <= nsub; i += blockDim.x) s_off[i] = b.t5s_soff[i];
+    __syncthreads();
+    const uint32_t n = s_off[nsub];
+    const uint32_t subcap = b.cap_t5 / nsub;
+    GRID_STRIDE(j, n) {
+        const uint32_t i = pair_slot(s_off, j, subcap, nsub);
+        const uint32_t u = b.t5s_u[i];
+        const uint32_t k = b.t5_off[u] + b.t5s_j[i];
+        if (k < b.cap_t5) {
+            b.t5_u[k] = u;
+            b.t5_w[k] = b.t5s_w[i];
+            b.t5_ks[k] = b.t5s_ks[i];
+        }
+    }
 }
 
 // --------------------------------------------- a6: seed lookup buckets ----
@@ -1710,9 +1788,13 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     // side: a5 T5, its seed-lookup buckets (a6) and pT5 (a7)
     L.fork(1);
     L.on_side(true);
-    L.launch("t5_count", k_t5<false>, grid_for(b.cap_t3), blk, b, t, c, stats);
+    const dim3 gt5 = grid_for(b.cap_t3);
+    const uint32_t nsub_t5 = gt5.x;
+    L.launch("t5_walk", k_t5, gt5, blk, b, t, c, nsub_t5, stats);
+    L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.t5s_sub, b.t5s_soff, b.cap_t5, nsub_t5,
+             &t->n_t5s);
     L.scan(b.t5_cnt, b.t5_off, &t->n_t3, b.cap_t3, &t->n_t5, "scan_t5");
-    L.launch("t5_fill", k_t5<true>, grid_for(b.cap_t3), blk, b, t, c, 0);
+    L.launch("t5_place", k_t5_place, grid_for(b.cap_t5), blk, b, nsub_t5);
     L.launch("bucket_hist", k_bucket_hist<1>, grid_for(b.cap_t5), blk, b, t, g, c);
     L.scan(b.bk5_cnt, b.bk5_off, &t->n_bk, cap_bk, &t->n_bk5, "scan_bucket");
     L.launch("bucket_scatter", k_bucket_scatter<1>, grid_for(b.cap_t5), blk, b, (const Totals *)t);
