@@ -56,6 +56,8 @@ def step_bytes(c: dict, n_hits: int, n_pls: int, n_units: int, s_b: int, e_used:
         "hit_gather": 16.0 * n_hits + 24.0 * n_hits,
         "md_count": 16.0 * n_hits + 12.0 * n_units + 4.0 * n_hits,
         "md_fill": 16.0 * n_hits + 12.0 * n_units + 28.0 * nmd,
+        "md_walk": 16.0 * n_hits + 12.0 * n_units + 4.0 * n_hits,
+        "md_place": 28.0 * nmd,
         "ls_count": ls,
         "ls_fill": ls + 8.0 * nls,
         "ls_walk": ls,

@@ -96,6 +96,9 @@ void carve_work(Carver &cv, Batch &b, uint32_t n_mod, uint32_t n_surf, uint32_t 
     b.hbin_s = cv.take<uint32_t>(b.cap_hits);
     b.md_cnt = cv.take<uint32_t>((size_t)b.cap_hits + 1);
     b.md_hoff = cv.take<uint32_t>((size_t)b.cap_hits + 1);
+    b.mds = cv.take<uint4>(b.cap_md);
+    b.mds_sub = cv.take<uint32_t>(kSubLists);
+    b.mds_soff = cv.take<uint32_t>(kSubLists + 1);
     b.md_off = cv.take<uint32_t>(units + 1);
     b.md_pos = cv.take<float4>(b.cap_md);
     b.md_beta = cv.take<float>(b.cap_md);
@@ -513,7 +516,7 @@ int overflowed(Slot &s)
         return true;
     };
     bool g = false;
-    g |= grow(t.n_md, b.cap_md);
+    g |= grow(std::max(t.n_md, t.n_mds), b.cap_md);
     g |= grow(std::max(t.n_ls, t.n_lss), b.cap_ls);
     g |= grow(std::max(t.n_t3, t.n_t3s), b.cap_t3);
     g |= grow(std::max(t.n_t5, t.n_t5s), b.cap_t5);
@@ -684,7 +687,7 @@ uint64_t predict_footprint(uint64_t hits, uint64_t pls, const lst::Consts &k)
     lst::Caps c = lst::plan_caps(1, hits, pls);
     uint64_t b = 0;
     b += 73ull * c.hits + 80ull * c.pls + 24ull * k.n_mod;
-    b += (40ull + 4ull * lst::kKeepLs) * c.md + 52ull * c.ls + 88ull * c.t3 + 64ull * c.t5;
+    b += (56ull + 4ull * lst::kKeepLs) * c.md + 52ull * c.ls + 88ull * c.t3 + 64ull * c.t5;
     b += 16ull * (c.pt3 + c.pt5) + 24ull * c.pls * k.n_surf + 19ull * c.pls + 16ull * (c.pt3 + c.t5 + c.pls);
     b += 12ull * (c.ptc3 + c.ptc5);
     b += 2ull * 8ull * k.n_surf * k.nphi * (3 * k.nkb + 1);

@@ -59,6 +59,7 @@ struct Totals {
     uint32_t n_md, n_ls, n_t3, n_t5, n_pt3, n_pt5;
     uint32_t n_bk3, n_bk5, n_tcu, n_tc;
     uint32_t n_ptc3, n_ptc5;      // seed-object candidate pairs (or, after a sub-list overflow, the capacity needed)
+    uint32_t n_mds;               // MDs in the unordered MD regions (likewise)
     uint32_t n_lss;               // segments in the unordered segment sub-lists (likewise)
     uint32_t n_t3s;               // T3s in the unordered T3 sub-lists (likewise)
     uint32_t n_t5s;               // T5s in the unordered T5 regions (likewise)
@@ -86,6 +87,10 @@ struct Batch {
     uint32_t *hbin_s;                   // bin of each sorted hit
     // a2: mini-doublets (anchor = hit on the lower sensor)
     uint32_t *md_cnt, *md_hoff;         // per sorted hit (MDs of a lower-sensor hit)
+    // MDs in the block regions of an unordered list before placement:
+    // (lower hit's sorted position, place in its list, upper hit's sorted position, beta)
+    uint4 *mds;
+    uint32_t *mds_sub, *mds_soff;
     uint32_t *md_off;                   // per (event, module) unit
     float4 *md_pos;                     // anchor (x, y, z, r)
     float *md_beta;

@@ -233,6 +233,7 @@ __global__ void k_setup(Totals *t, uint32_t n_mod, uint32_t n_surf, uint32_t nph
         t->err = 0;
         // region needs: written by the stages that append to regions (the
         // small-batch segment stage does not)
+        t->n_mds = 0;
         t->n_lss = 0;
         t->n_t3s = 0;
         t->n_t5s = 0;
@@ -386,10 +387,6 @@ __global__ void k_hit_gather(const Batch b, const Totals *t, uint32_t n_mod)
 
 // ------------------------------------------------------ a2: mini-doublets ---
 
-struct MdOut {
-    float beta;
-};
-
 __device__ inline bool md_cut(const float4 mc, bool barrel, float L,
                               float xi, float yi, float zi, float ri,
                               float xj, float yj, float zj, float rj, float &beta)
@@ -409,11 +406,96 @@ __device__ inline bool md_cut(const float4 mc, bool barrel, float L,
     return true;
 }
 
-// one thread per sorted hit: a hit on a lower sensor pairs with every hit on
-// the upper sensor of its module (hits of upper sensors count zero)
-template <bool kFill>
+// MD: the 64 sorted hits of a wave (one per lane; lower-sensor hits own the
+// upper-sensor hits of their module as candidates) pool their candidates and
+// the lanes take them 64 at a time.  Survivors go to the block's region of
+// an unordered MD list as (lower hit, place in its list, upper hit, beta);
+// k_md_place writes the MD records in canonical order once the per-hit
+// counts are scanned.
 __global__ __launch_bounds__(256) void k_md(const Batch b, Totals *t, const DevGeom g, const Consts c,
-                                            int stats)
+                                            uint32_t nsub, int stats)
+{
+    __shared__ uint32_t s_n;             // appends to this block's region
+    const uint32_t n = t->n_sorted;
+    const uint32_t n_mod = c.n_mod;
+    const uint32_t lane = threadIdx.x & 63u;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const uint32_t cap = b.cap_md / nsub;
+    uint4 *out = b.mds + (size_t)blockIdx.x * cap;
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    uint64_t cand = 0;
+    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        const uint32_t i = base + threadIdx.x;
+        uint32_t up0 = 0, cnt = 0, m = 0;
+        float4 hi = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (i < n) {
+            const uint32_t bin = b.hbin_s[i];
+            if (!(bin & 1u)) {
+                up0 = b.bin_off[bin + 1];
+                const uint32_t up1 = b.bin_off[bin + 2];
+                cnt = up1 > up0 ? up1 - up0 : 0u;
+                if (cnt) {
+                    m = (bin >> 1) % n_mod;
+                    hi = b.hpos[i];
+                }
+            }
+        }
+        const uint32_t incl = wave_incl_scan(cnt);
+        const uint32_t off = incl - cnt;
+        const uint32_t total = __shfl(incl, 63);
+        uint32_t run = 0;
+        for (uint32_t cb = 0; cb < total; cb += 64u) {
+            const uint32_t ci = cb + lane;
+            uint32_t o = 0;
+#pragma unroll
+            for (uint32_t step = 32; step; step >>= 1)
+                if (__shfl(off, o + step) <= ci) o += step;
+            const uint32_t o_up0 = __shfl(up0, o), o_off = __shfl(off, o), o_run = __shfl(run, o);
+            const uint32_t o_i = __shfl(i, o), o_m = __shfl(m, o);
+            const float hx = __shfl(hi.x, o), hy = __shfl(hi.y, o), hz = __shfl(hi.z, o), hw = __shfl(hi.w, o);
+            bool pass = false;
+            uint32_t j = 0;
+            float beta = 0.f;
+            if (ci < total) {
+                j = o_up0 + (ci - o_off);
+                const float4 mc = g.mdc[o_m];
+                const bool barrel = g.mod_kind[o_m] == LST_BARREL;
+                const float4 hj = b.hpos[j];
+                cand++;
+                pass = md_cut(mc, barrel, c.L, hx, hy, hz, hw, hj.x, hj.y, hj.z, hj.w, beta);
+            }
+            const unsigned long long mk = __ballot(pass);
+            const uint32_t np = (uint32_t)__popcll(mk);
+            uint32_t at = 0;
+            if (np != 0u && lane == 0u) at = atomicAdd(&s_n, np);
+            at = __shfl(at, 0);
+            if (pass) {
+                const uint32_t slot = at + (uint32_t)__popcll(mk & below);
+                const uint32_t s0 = o_off > cb ? o_off - cb : 0u;
+                if (slot < cap)
+                    out[slot] = make_uint4(o_i, o_run + (uint32_t)__popcll(mk & below & ~((1ull << s0) - 1ull)), j,
+                                           __float_as_uint(beta));
+            }
+            if (cnt != 0u && off < cb + 64u && off + cnt > cb) {
+                const uint32_t s0 = off > cb ? off - cb : 0u;
+                const uint32_t e0 = min(off + cnt - cb, 64u);
+                run += (uint32_t)__popcll(mk & lane_range(s0, e0));
+            }
+        }
+        if (i < n) b.md_cnt[i] = run;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) b.mds_sub[blockIdx.x] = s_n;
+    if (stats) atomicAdd(&t->cand[0], (unsigned long long)cand);
+}
+
+// Latency variant for small batches: one thread per sorted hit, a count
+// pass and (after the scan) a fill pass that writes the MDs in place; two
+// launches fewer than the pooled walk and its placement.
+template <bool kFill>
+__global__ __launch_bounds__(256) void k_md_direct(const Batch b, Totals *t, const DevGeom g, const Consts c,
+                                                   int stats)
 {
     const uint32_t n = t->n_sorted;
     const uint32_t n_mod = c.n_mod;
@@ -423,24 +505,22 @@ __global__ __launch_bounds__(256) void k_md(const Batch b, Totals *t, const DevG
         uint32_t k = kFill ? b.md_hoff[i] : 0u;
         if (!(bin & 1u)) {
             const uint32_t up0 = b.bin_off[bin + 1], up1 = b.bin_off[bin + 2];
-            if (up0 != up1) {
+            if (up0 < up1) {
                 const uint32_t u = bin >> 1;
                 const uint32_t m = u % n_mod;
                 const float4 mc = g.mdc[m];
                 const bool barrel = g.mod_kind[m] == LST_BARREL;
-                const uint32_t disk_bit = barrel ? 0u : kDiskBit;
                 const float4 hi = b.hpos[i];
                 for (uint32_t j = up0; j < up1; j++) {
                     float beta;
-                    if (!kFill) cand++;
                     const float4 hj = b.hpos[j];
+                    if (!kFill) cand++;
                     if (!md_cut(mc, barrel, c.L, hi.x, hi.y, hi.z, hi.w, hj.x, hj.y, hj.z, hj.w, beta))
                         continue;
                     if (kFill && k < b.cap_md) {
-                        // the sign of r marks an anchor on a disk (r > 0)
                         b.md_pos[k] = make_float4(hi.x, hi.y, hi.z, barrel ? hi.w : -hi.w);
                         b.md_beta[k] = beta;
-                        b.md_u[k] = u | disk_bit;
+                        b.md_u[k] = u | (barrel ? 0u : kDiskBit);
                         b.md_hlo[k] = b.hin[i];
                         b.md_hup[k] = b.hin[j];
                     }
@@ -451,6 +531,31 @@ __global__ __launch_bounds__(256) void k_md(const Batch b, Totals *t, const DevG
         if (!kFill) b.md_cnt[i] = k;
     }
     if (!kFill && stats) atomicAdd(&t->cand[0], (unsigned long long)cand);
+}
+
+// MDs from the block regions to their canonical slots, with the anchor
+// (the lower hit; the sign of r marks a disk), beta, unit and input hits
+__global__ __launch_bounds__(256) void k_md_place(const Batch b, const DevGeom g, const Consts c, uint32_t nsub)
+{
+    __shared__ uint32_t s_off[kSubLists + 1];
+    for (uint32_t i = threadIdx.x; i <= nsub; i += blockDim.x) s_off[i] = b.mds_soff[i];
+    __syncthreads();
+    const uint32_t n = s_off[nsub];
+    const uint32_t subcap = b.cap_md / nsub;
+    GRID_STRIDE(jj, n) {
+        const uint4 r = b.mds[pair_slot(s_off, jj, subcap, nsub)];
+        const uint32_t k = b.md_hoff[r.x] + r.y;
+        if (k < b.cap_md) {
+            const uint32_t u = b.hbin_s[r.x] >> 1;
+            const bool barrel = g.mod_kind[u % c.n_mod] == LST_BARREL;
+            const float4 hi = b.hpos[r.x];
+            b.md_pos[k] = make_float4(hi.x, hi.y, hi.z, barrel ? hi.w : -hi.w);
+            b.md_beta[k] = __uint_as_float(r.w);
+            b.md_u[k] = u | (barrel ? 0u : kDiskBit);
+            b.md_hlo[k] = b.hin[r.x];
+            b.md_hup[k] = b.hin[r.z];
+        }
+    }
 }
 
 // MD range of every (event, module) unit: the MDs of its lower-sensor hits
@@ -1755,10 +1860,19 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     L.launch("hit_gather", k_hit_gather, grid_for((uint64_t)b.cap_ev * 2 * n_mod), blk, b, (const Totals *)t,
              n_mod);
     // a2: mini-doublets
+    // small batches: count and fill in place for latency; large ones: pooled walk
     const dim3 gmd = grid_for(b.cap_hits);
-    L.launch("md_count", k_md<false>, gmd, blk, b, t, g, c, stats);
-    L.scan(b.md_cnt, b.md_hoff, &t->n_sorted, b.cap_hits, &t->n_md, "scan_md");
-    L.launch("md_fill", k_md<true>, gmd, blk, b, t, g, c, 0);
+    if (b.cap_md <= kLsWaveMaxMd) {
+        L.launch("md_count", k_md_direct<false>, gmd, blk, b, t, g, c, stats);
+        L.scan(b.md_cnt, b.md_hoff, &t->n_sorted, b.cap_hits, &t->n_md, "scan_md");
+        L.launch("md_fill", k_md_direct<true>, gmd, blk, b, t, g, c, 0);
+    } else {
+        const uint32_t nsub_md = gmd.x;
+        L.launch("md_walk", k_md, gmd, blk, b, t, g, c, nsub_md, stats);
+        L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.mds_sub, b.mds_soff, b.cap_md, nsub_md, &t->n_mds);
+        L.scan(b.md_cnt, b.md_hoff, &t->n_sorted, b.cap_hits, &t->n_md, "scan_md");
+        L.launch("md_place", k_md_place, grid_for(b.cap_md), blk, b, g, c, nsub_md);
+    }
     L.launch("md_units", k_md_units, grid_for((uint64_t)b.cap_ev * n_mod + 1), blk, b, (const Totals *)t);
     // a3: line segments over the connection map
     // small batches: 32 lanes per MD for latency; large ones: pooled walk
