@@ -177,6 +177,7 @@ def main():
     ap.add_argument("--quick", action="store_true", help="only the batched path (profiling runs)")
     ap.add_argument("--chain-only", type=int, default=0, metavar="N",
                     help="counter runs: upload one batch, run the chain N times, print nothing else")
+    ap.add_argument("--graph", action="store_true", help="with --chain-only: replay the captured graph")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="counter calibration: one device-to-device copy of MB megabytes (torch)")
     args = ap.parse_args()
@@ -206,7 +207,7 @@ def main():
     # ---- batched path: B events per launch --------------------------------
     ctx.batch_upload(events)
     if args.chain_only:
-        ctx.batch_execute(args.chain_only, graph=False, timing=False)
+        ctx.batch_execute(args.chain_only, graph=args.graph, timing=False)
         log(f"chain run {args.chain_only} times on {B} events")
         ctx.close()
         return
