@@ -627,7 +627,7 @@ __device__ inline bool ls_cut(const LsK &k, const Consts &c, bool bend,
 }
 
 // Large batches: the 64 inner MDs of a wave (one per lane) step through
-// their modules' edges in groups of 8 together.  For each group a lane loads
+// their modules' edges in groups of 6 together.  For each group a lane loads
 // its edges' MD ranges and stores them in LDS; the wave pools the
 // candidates (every MD of every edge of the group, lane by lane in (edge,
 // outer MD) order) and the lanes take them 64 at a time, so the cut
@@ -637,13 +637,15 @@ __device__ inline bool ls_cut(const LsK &k, const Consts &c, bool bend,
 // the owner's anchor by lane shuffles.  Survivors go to the block's region of
 // an unordered segment list with their place in the owner's list (its
 // earlier survivors plus those before it in the same 64); edges are sorted by
-// destination module, so that place is the canonical one.
-constexpr int kEdgeGroup = 8;
+// destination module, so that place is the canonical one.  Groups of 6 keep
+// the block's LDS under 20 KB and the kernel at 64 VGPRs, so 8 blocks of 4
+// waves fit a CU and the whole launch is resident at once.
+constexpr int kEdgeGroup = 6;
 
-__global__ __launch_bounds__(256) void k_ls(const Batch b, Totals *t, const DevGeom g, const Consts c,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_ls(const Batch b, Totals *t, const DevGeom g, const Consts c,
                                             uint32_t nsub, int stats)
 {
-    constexpr uint32_t kF = 3 * kEdgeGroup;          // per lane: bq[8], cum[1..8], class[8]
+    constexpr uint32_t kF = 3 * kEdgeGroup;          // per lane and edge of the group: first outer MD, running count, class
     __shared__ uint32_t s_grp[4][kF][64];
     __shared__ uint32_t s_n;                          // appends to this block's region
     const uint32_t n = min(t->n_md, b.cap_md);
@@ -679,7 +681,7 @@ __global__ __launch_bounds__(256) void k_ls(const Batch b, Totals *t, const DevG
         uint32_t run = 0;                             // segments of this lane's MD so far
         for (uint32_t eb = e0;; eb += kEdgeGroup) {
             if (__ballot(eb < e1) == 0ull) break;
-            // this lane's group: MD ranges of up to 8 edges, to LDS
+            // this lane's group: MD ranges of up to kEdgeGroup edges, to LDS
             uint32_t T = 0;
 #pragma unroll
             for (int j = 0; j < kEdgeGroup; j++) {
@@ -989,7 +991,7 @@ __device__ inline void sides3(const Anchor &A, const Anchor &B, const Anchor &C,
 // Survivors go to the block's region of an unordered T3 list with their
 // place in the owner's list (the owner's earlier survivors plus those before
 // it in the same 64), so k_t3_place can put them in canonical order.
-__global__ __launch_bounds__(256) void k_t3(const Batch b, Totals *t, const Consts c, uint32_t nsub, int stats)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_t3(const Batch b, Totals *t, const Consts c, uint32_t nsub, int stats)
 {
     __shared__ uint32_t s_n;             // appends to this block's region
     const uint32_t n = min(t->n_ls, b.cap_ls);
