@@ -637,12 +637,13 @@ __device__ inline bool ls_cut(const LsK &k, const Consts &c, bool bend,
 // the owner's anchor by lane shuffles.  Survivors go to the block's region of
 // an unordered segment list with their place in the owner's list (its
 // earlier survivors plus those before it in the same 64); edges are sorted by
-// destination module, so that place is the canonical one.  Groups of 6 keep
-// the block's LDS under 20 KB and the kernel at 64 VGPRs, so 8 blocks of 4
-// waves fit a CU and the whole launch is resident at once.
+// destination module, so that place is the canonical one.  The rounds are
+// bound by the latency of the outer MD and class loads, which depend on LDS
+// reads and lane shuffles; a step takes two rounds, both rounds' loads issued
+// before either cut.
 constexpr int kEdgeGroup = 6;
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_ls(const Batch b, Totals *t, const DevGeom g, const Consts c,
+__global__ __launch_bounds__(256) void k_ls(const Batch b, Totals *t, const DevGeom g, const Consts c,
                                             uint32_t nsub, int stats)
 {
     constexpr uint32_t kF = 3 * kEdgeGroup;          // per lane and edge of the group: first outer MD, running count, class
@@ -701,53 +702,73 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
             const uint32_t incl = wave_incl_scan(T);
             const uint32_t off = incl - T;
             const uint32_t total = __shfl(incl, 63);
-            for (uint32_t cb = 0; cb < total; cb += 64u) {
-                const uint32_t ci = cb + lane;
-                uint32_t o = 0;
+            // two pooled rounds per step: the indices and loads of both are
+            // issued before either cut, so that twice the loads are in flight
+            for (uint32_t cb = 0; cb < total; cb += 128u) {
+                uint32_t o[2], q[2];
+                float4 pq[2];
+                LsK kc[2];
 #pragma unroll
-                for (uint32_t step = 32; step; step >>= 1)
-                    if (__shfl(off, o + step) <= ci) o += step;
-                const uint32_t o_off = __shfl(off, o), o_run = __shfl(run, o);
-                const float oxa = __shfl(xa, o), oya = __shfl(ya, o), oza = __shfl(za, o), ora = __shfl(ra, o);
-                const float oba = __shfl(ba, o);
-                bool pass = false;
-                uint32_t q = 0;
-                if (ci < total) {
+                for (int r = 0; r < 2; r++) {
+                    const uint32_t ci = cb + 64u * r + lane;
+                    uint32_t ow = 0;
+#pragma unroll
+                    for (uint32_t step = 32; step; step >>= 1)
+                        if (__shfl(off, ow + step) <= ci) ow += step;
                     // edge j of the owner's group: the last with cum[j] <= tt
-                    const uint32_t tt = ci - o_off;
+                    // (lanes past the total read valid LDS and load entry 0)
+                    const uint32_t tt = ci - __shfl(off, ow);
                     uint32_t j = 0, cj = 0;
 #pragma unroll
                     for (int k = 0; k < kEdgeGroup - 1; k++) {
-                        const uint32_t cum = s_grp[wv][kEdgeGroup + k][o];
+                        const uint32_t cum = s_grp[wv][kEdgeGroup + k][ow];
                         if (cum <= tt) {
                             j = k + 1;
                             cj = cum;
                         }
                     }
-                    q = s_grp[wv][j][o] + (tt - cj);
-                    const LsK kc = g.cls[s_grp[wv][2 * kEdgeGroup + j][o]];
-                    const float4 pq = b.md_pos[q];
-                    cand++;
-                    pass = ls_cut(kc, c, bend, oxa, oya, oza, ora, oba, pq.x, pq.y, pq.z, fabsf(pq.w));
+                    q[r] = ci < total ? s_grp[wv][j][ow] + (tt - cj) : 0u;
+                    kc[r] = g.cls[s_grp[wv][2 * kEdgeGroup + j][ow]];
+                    pq[r] = b.md_pos[q[r]];
+                    o[r] = ow;
                 }
-                const unsigned long long mk = __ballot(pass);
-                const uint32_t np = (uint32_t)__popcll(mk);
-                uint32_t at = 0;
-                if (np != 0u && lane == 0u) at = atomicAdd(&s_n, np);
-                at = __shfl(at, 0);
-                if (pass) {
-                    const uint32_t slot = at + (uint32_t)__popcll(mk & below);
-                    const uint32_t s0 = o_off > cb ? o_off - cb : 0u;
-                    if (slot < cap) {
-                        sa[slot] = base + wv * 64u + o;
-                        sb[slot] = q;
-                        sj[slot] = o_run + (uint32_t)__popcll(mk & below & ~((1ull << s0) - 1ull));
+                bool pass[2];
+#pragma unroll
+                for (int r = 0; r < 2; r++) {
+                    const uint32_t ci = cb + 64u * r + lane;
+                    const float oxa = __shfl(xa, o[r]), oya = __shfl(ya, o[r]), oza = __shfl(za, o[r]);
+                    const float ora = __shfl(ra, o[r]), oba = __shfl(ba, o[r]);
+                    pass[r] = false;
+                    if (ci < total) {
+                        cand++;
+                        pass[r] = ls_cut(kc[r], c, bend, oxa, oya, oza, ora, oba, pq[r].x, pq[r].y, pq[r].z,
+                                         fabsf(pq[r].w));
                     }
                 }
-                if (T != 0u && off < cb + 64u && off + T > cb) {
-                    const uint32_t s0 = off > cb ? off - cb : 0u;
-                    const uint32_t e0c = min(off + T - cb, 64u);
-                    run += (uint32_t)__popcll(mk & lane_range(s0, e0c));
+#pragma unroll
+                for (int r = 0; r < 2; r++) {
+                    const uint32_t c0 = cb + 64u * r;
+                    if (c0 >= total) break;                   // the same on every lane
+                    const uint32_t o_off = __shfl(off, o[r]), o_run = __shfl(run, o[r]);
+                    const unsigned long long mk = __ballot(pass[r]);
+                    const uint32_t np = (uint32_t)__popcll(mk);
+                    uint32_t at = 0;
+                    if (np != 0u && lane == 0u) at = atomicAdd(&s_n, np);
+                    at = __shfl(at, 0);
+                    if (pass[r]) {
+                        const uint32_t slot = at + (uint32_t)__popcll(mk & below);
+                        const uint32_t s0 = o_off > c0 ? o_off - c0 : 0u;
+                        if (slot < cap) {
+                            sa[slot] = base + wv * 64u + o[r];
+                            sb[slot] = q[r];
+                            sj[slot] = o_run + (uint32_t)__popcll(mk & below & ~((1ull << s0) - 1ull));
+                        }
+                    }
+                    if (T != 0u && off < c0 + 64u && off + T > c0) {
+                        const uint32_t s0 = off > c0 ? off - c0 : 0u;
+                        const uint32_t e0c = min(off + T - c0, 64u);
+                        run += (uint32_t)__popcll(mk & lane_range(s0, e0c));
+                    }
                 }
             }
             wave_lds_sync();
