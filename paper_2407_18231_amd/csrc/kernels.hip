@@ -65,9 +65,10 @@ __device__ inline uint32_t scan_chunk(uint32_t n, uint32_t nb)
     return (per + kScanTile - 1) / kScanTile * kScanTile;
 }
 
-// Three-phase scan: every block sums a chunk (whole tiles of kScanTile
-// values, four per thread as one 16-byte load), one block scans the
-// kScanGrid partial sums, every block scans its chunk again with its carry.
+// Two-kernel scan: every block sums a chunk (whole tiles of kScanTile
+// values, four per thread as one 16-byte load); then every block sums the
+// partial sums of the blocks before it (at most kScanGrid, from L2) for its
+// carry and scans its chunk again, and the last block writes the total.
 __global__ __launch_bounds__(kScanBlock) void k_scan_up(const uint32_t *__restrict__ in,
                                                         const uint32_t *n_ptr, uint32_t cap,
                                                         uint32_t *__restrict__ part)
@@ -93,45 +94,20 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_up(const uint32_t *__restri
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_mid(uint32_t *__restrict__ part, uint32_t nb,
-                                                         const uint32_t *n_ptr, uint32_t cap,
-                                                         uint32_t *__restrict__ out,
-                                                         uint32_t *total_out)
-{
-    constexpr uint32_t kPer = kScanGrid / kScanBlock;
-    static_assert(kScanGrid % kScanBlock == 0, "whole partials per thread");
-    const uint32_t n = min(*n_ptr, cap);
-    uint32_t v[kPer], s = 0;
-#pragma unroll
-    for (uint32_t k = 0; k < kPer; k++) {
-        const uint32_t i = threadIdx.x * kPer + k;
-        v[k] = i < nb ? part[i] : 0u;
-        s += v[k];
-    }
-    uint32_t tot;
-    uint32_t ex = block_excl_scan(s, tot);
-#pragma unroll
-    for (uint32_t k = 0; k < kPer; k++) {
-        const uint32_t i = threadIdx.x * kPer + k;
-        if (i < nb) part[i] = ex;
-        ex += v[k];
-    }
-    if (threadIdx.x == 0) {
-        out[n] = tot;
-        *total_out = tot;
-    }
-}
-
 __global__ __launch_bounds__(kScanBlock) void k_scan_down(const uint32_t *__restrict__ in,
                                                           const uint32_t *n_ptr, uint32_t cap,
                                                           const uint32_t *__restrict__ part,
-                                                          uint32_t *__restrict__ out)
+                                                          uint32_t *__restrict__ out,
+                                                          uint32_t *total_out)
 {
     const uint32_t n = min(*n_ptr, cap);
     const uint32_t chunk = scan_chunk(n, gridDim.x);
     const uint32_t start = min(blockIdx.x * chunk, n);
     const uint32_t end = min(start + chunk, n);
-    uint32_t carry = part[blockIdx.x];
+    uint32_t before = 0;
+    for (uint32_t i = threadIdx.x; i < blockIdx.x; i += kScanBlock) before += part[i];
+    uint32_t carry;
+    block_excl_scan(before, carry);
     for (uint32_t base = start; base < end; base += kScanTile) {
         const uint32_t i = base + 4 * threadIdx.x;
         const bool full = i + 3 < end;
@@ -163,6 +139,10 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_down(const uint32_t *__rest
                 if (i + k < end) out[i + k] = o[k];
         }
         carry += tot;
+    }
+    if (blockIdx.x == gridDim.x - 1u && threadIdx.x == 0) {
+        out[n] = carry;
+        *total_out = carry;
     }
 }
 
@@ -1835,8 +1815,7 @@ void Launcher::scan(const uint32_t *in, uint32_t *out, const uint32_t *n_ptr, ui
         1u, std::min<uint64_t>(kScanGrid, ((uint64_t)cap + kScanTile - 1) / kScanTile));
     uint32_t *pt = (side && cur == side) ? part_side : part;
     launch(name, k_scan_up, dim3(nb), dim3(kScanBlock), in, n_ptr, cap, pt);
-    launch(name, k_scan_mid, dim3(1), dim3(kScanBlock), pt, nb, n_ptr, cap, out, total);
-    launch(name, k_scan_down, dim3(nb), dim3(kScanBlock), in, n_ptr, cap, (const uint32_t *)pt, out);
+    launch(name, k_scan_down, dim3(nb), dim3(kScanBlock), in, n_ptr, cap, (const uint32_t *)pt, out, total);
 }
 
 static inline dim3 grid_for(uint64_t units)
