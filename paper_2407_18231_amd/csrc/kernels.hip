@@ -912,6 +912,46 @@ struct Anchor {
     bool disk;
 };
 
+constexpr float kPiF = 3.14159265358979f;
+
+__device__ inline uint32_t phi_bin(float x, float y, uint32_t nphi)
+{
+    float ph = atan2f(y, x);
+    int bi = (int)((ph + kPiF) * ((float)nphi / (2.0f * kPiF)));
+    bi = bi < 0 ? 0 : (bi >= (int)nphi ? (int)nphi - 1 : bi);
+    return (uint32_t)bi;
+}
+
+__device__ inline uint32_t kappa_bin(float k, const Consts &c)
+{
+    float t = (k + c.kspan) * ((float)c.nkb / (2.0f * c.kspan));
+    if (!(t > 0.0f)) return 0u;
+    if (t >= (float)c.nkb) return c.nkb - 1u;
+    return (uint32_t)t;
+}
+
+// Seed-lookup bucket of a T3 or T5, taken where the object is placed in its
+// canonical slot: the row (event, surface of the inner anchor's module,
+// azimuth bin of the inner anchor), then within the row the resolution class
+// and curvature bin (wide objects, or a NaN resolution, in the row's last
+// bucket).
+__device__ inline uint32_t bucket_row(const Batch &b, const DevGeom &g, const Consts &c, uint32_t a, float x,
+                                      float y)
+{
+    const uint32_t u = b.md_u[a] & kUnitMask;
+    const uint32_t e = u / c.n_mod, m = u - e * c.n_mod;
+    return ((e * c.n_surf + g.mod_surf[m]) * c.nphi + phi_bin(x, y, c.nphi)) * (3u * c.nkb + 1u);
+}
+
+__device__ inline uint32_t bucket_in_row(float k, float sk, const Consts &c)
+{
+    uint32_t kb = 3u * c.nkb;
+    if (sk <= c.sk_cls[0]) kb = kappa_bin(k, c);
+    else if (sk <= c.sk_cls[1]) kb = c.nkb + kappa_bin(k, c);
+    else if (sk <= c.sk_cls[2]) kb = 2u * c.nkb + kappa_bin(k, c);
+    return kb;
+}
+
 __device__ inline Anchor anchor_of(const float4 p)
 {
     Anchor A;
@@ -1081,7 +1121,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
 }
 
 // T3s from the sub-lists to their canonical slots
-__global__ __launch_bounds__(256) void k_t3_place(const Batch b, uint32_t nsub)
+__global__ __launch_bounds__(256) void k_t3_place(const Batch b, const DevGeom g, const Consts c, uint32_t nsub)
 {
     __shared__ uint32_t s_off[kSubLists + 1];
     for (uint32_t i = threadIdx.x; i <= nsub; i += blockDim.x) s_off[i] = b.t3s_soff[i];
@@ -1097,6 +1137,13 @@ __global__ __launch_bounds__(256) void k_t3_place(const Batch b, uint32_t nsub)
             b.t3_l2[k] = b.t3s_l2[i];
             b.t3_ac[k] = b.t3s_ac[i];
             b.t3_ks[k] = b.t3s_ks[i];
+            // the object's slot in its seed-lookup bucket
+            const uint2 ac = b.t3s_ac[i];
+            const float2 ks = b.t3s_ks[i];
+            const float4 pa = b.md_pos[ac.x];
+            const uint32_t bk = bucket_row(b, g, c, ac.x, pa.x, pa.y) + bucket_in_row(ks.x, ks.y, c);
+            b.bk3_id[k] = bk;
+            b.bk3_rank[k] = atomicAdd(&b.bk3_cnt[bk], 1u);
         }
     }
 }
@@ -1198,7 +1245,7 @@ __global__ __launch_bounds__(256) void k_t5(const Batch b, Totals *t, const Cons
 }
 
 // T5s from the block regions to their canonical slots
-__global__ __launch_bounds__(256) void k_t5_place(const Batch b, uint32_t nsub)
+__global__ __launch_bounds__(256) void k_t5_place(const Batch b, const DevGeom g, const Consts c, uint32_t nsub)
 {
     __shared__ uint32_t s_off[kSubLists + 1];
     for (uint32_t i = threadIdx.x; i <= nsub; i += blockDim.x) s_off[i] = b.t5s_soff[i];
@@ -1213,6 +1260,13 @@ __global__ __launch_bounds__(256) void k_t5_place(const Batch b, uint32_t nsub)
             b.t5_u[k] = u;
             b.t5_w[k] = b.t5s_w[i];
             b.t5_ks[k] = b.t5s_ks[i];
+            // the object's slot in its seed-lookup bucket
+            const uint32_t a = b.t3_ac[u].x;
+            const float2 ks = b.t5s_ks[i];
+            const float4 pa = b.md_pos[a];
+            const uint32_t bk = bucket_row(b, g, c, a, pa.x, pa.y) + bucket_in_row(ks.x, ks.y, c);
+            b.bk5_id[k] = bk;
+            b.bk5_rank[k] = atomicAdd(&b.bk5_cnt[bk], 1u);
         }
     }
 }
@@ -1225,24 +1279,7 @@ __global__ __launch_bounds__(256) void k_t5_place(const Batch b, uint32_t nsub)
 // helix band crosses, restricted to the curvature bins its curvature cut can
 // accept (bounded with the row's largest object resolution).
 
-constexpr float kPiF = 3.14159265358979f;
 constexpr double kPiD = 3.14159265358979323846;
-
-__device__ inline uint32_t phi_bin(float x, float y, uint32_t nphi)
-{
-    float ph = atan2f(y, x);
-    int bi = (int)((ph + kPiF) * ((float)nphi / (2.0f * kPiF)));
-    bi = bi < 0 ? 0 : (bi >= (int)nphi ? (int)nphi - 1 : bi);
-    return (uint32_t)bi;
-}
-
-__device__ inline uint32_t kappa_bin(float k, const Consts &c)
-{
-    float t = (k + c.kspan) * ((float)c.nkb / (2.0f * c.kspan));
-    if (!(t > 0.0f)) return 0u;
-    if (t >= (float)c.nkb) return c.nkb - 1u;
-    return (uint32_t)t;
-}
 
 __device__ inline int kappa_bin_d(double k, const Consts &c)
 {
@@ -1253,33 +1290,6 @@ __device__ inline int kappa_bin_d(double k, const Consts &c)
 }
 
 // kind 0: T3 objects, 1: T5 objects
-template <int kKind>
-__global__ void k_bucket_hist(const Batch b, Totals *t, const DevGeom g, const Consts c)
-{
-    const uint32_t n = kKind == 0 ? min(t->n_t3, b.cap_t3) : min(t->n_t5, b.cap_t5);
-    uint32_t *cnt = kKind == 0 ? b.bk3_cnt : b.bk5_cnt;
-    uint32_t *id = kKind == 0 ? b.bk3_id : b.bk5_id;
-    uint32_t *rank = kKind == 0 ? b.bk3_rank : b.bk5_rank;
-    GRID_STRIDE(i, n) {
-        const uint32_t a = kKind == 0 ? b.t3_ac[i].x : b.t3_ac[b.t5_u[i]].x;
-        const float2 ks = kKind == 0 ? b.t3_ks[i] : b.t5_ks[i];
-        const float k = ks.x, sk = ks.y;
-        const uint32_t u = b.md_u[a] & kUnitMask;
-        const uint32_t e = u / c.n_mod, m = u - e * c.n_mod;
-        const float4 pa = b.md_pos[a];
-        const uint32_t row = (e * c.n_surf + g.mod_surf[m]) * c.nphi + phi_bin(pa.x, pa.y, c.nphi);
-        // objects by resolution class and curvature bin; wide ones (or a NaN
-        // resolution) in the last bucket of the row
-        uint32_t kb = 3u * c.nkb;
-        if (sk <= c.sk_cls[0]) kb = kappa_bin(k, c);
-        else if (sk <= c.sk_cls[1]) kb = c.nkb + kappa_bin(k, c);
-        else if (sk <= c.sk_cls[2]) kb = 2u * c.nkb + kappa_bin(k, c);
-        const uint32_t bk = row * (3u * c.nkb + 1u) + kb;
-        id[i] = bk;
-        rank[i] = atomicAdd(&cnt[bk], 1u);
-    }
-}
-
 template <int kKind>
 __global__ void k_bucket_scatter(const Batch b, const Totals *t)
 {
@@ -1899,7 +1909,8 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.t3s_sub, b.t3s_soff, b.cap_t3, nsub_t3,
              &t->n_t3s);
     L.scan(b.t3_cnt, b.t3_off, &t->n_ls, b.cap_ls, &t->n_t3, "scan_t3");
-    L.launch("t3_place", k_t3_place, grid_for(b.cap_t3), blk, b, nsub_t3);
+    L.wait(0);                           // the placement counts into the cleared T3 buckets
+    L.launch("t3_place", k_t3_place, grid_for(b.cap_t3), blk, b, g, c, nsub_t3);
 
     // side: a5 T5, its seed-lookup buckets (a6) and pT5 (a7)
     L.fork(1);
@@ -1910,8 +1921,7 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.t5s_sub, b.t5s_soff, b.cap_t5, nsub_t5,
              &t->n_t5s);
     L.scan(b.t5_cnt, b.t5_off, &t->n_t3, b.cap_t3, &t->n_t5, "scan_t5");
-    L.launch("t5_place", k_t5_place, grid_for(b.cap_t5), blk, b, nsub_t5);
-    L.launch("bucket_hist", k_bucket_hist<1>, grid_for(b.cap_t5), blk, b, t, g, c);
+    L.launch("t5_place", k_t5_place, grid_for(b.cap_t5), blk, b, g, c, nsub_t5);
     L.scan(b.bk5_cnt, b.bk5_off, &t->n_bk, cap_bk, &t->n_bk5, "scan_bucket");
     L.launch("bucket_scatter", k_bucket_scatter<1>, grid_for(b.cap_t5), blk, b, (const Totals *)t);
     L.launch("pt5c_walk", k_ptc<1>, gwalk, blk, b, t, c, nsub, stats);
@@ -1925,8 +1935,6 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
 
     // main: the T3 seed-lookup buckets (a6) and pT3 (a7)
     L.on_side(false);
-    L.wait(0);
-    L.launch("bucket_hist", k_bucket_hist<0>, grid_for(b.cap_t3), blk, b, t, g, c);
     L.scan(b.bk3_cnt, b.bk3_off, &t->n_bk, cap_bk, &t->n_bk3, "scan_bucket");
     L.launch("bucket_scatter", k_bucket_scatter<0>, grid_for(b.cap_t3), blk, b, (const Totals *)t);
     L.launch("pt3c_walk", k_ptc<0>, gwalk, blk, b, t, c, nsub, stats);
