@@ -885,7 +885,8 @@ lst_status lst_load_geometry(lst_ctx *ctx, const lst_module_desc *m, uint32_t n)
     size_t off_edge = lst::align_up(off_eb + 4 * (nm + 1));
     size_t off_cls = lst::align_up(off_edge + 8 * std::max<size_t>(ne, 1));
     size_t off_sf = lst::align_up(off_cls + sizeof(lst::LsK) * nc);
-    size_t total = lst::align_up(off_sf + sizeof(lst::Surface) * std::max<size_t>(ns, 1));
+    size_t off_phi = lst::align_up(off_sf + sizeof(lst::Surface) * std::max<size_t>(ns, 1));
+    size_t total = lst::align_up(off_phi + 8 * nm);
     std::vector<char> host(total, 0);
     std::memcpy(&host[off_kind], geom.kind.data(), 4 * nm);
     std::memcpy(&host[off_surf], geom.surf.data(), 4 * nm);
@@ -897,7 +898,11 @@ lst_status lst_load_geometry(lst_ctx *ctx, const lst_module_desc *m, uint32_t n)
     }
     for (size_t i = 0; i < geom.classes.size(); i++) {
         const lst::LsClass &k = geom.classes[i];
-        float v[8] = {k.S, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        // v[6]: the largest azimuth difference of the anchors, asin(S), plus
+        // the map's margin and room for the binary32 arithmetic of the
+        // per-segment reach test
+        float v[8] = {k.S, 0.f, 0.f, 0.f, 0.f, 0.f,
+                      (float)(std::asin(std::min(1.0, (double)k.S)) + 2e-5), 0.f};
         if (k.type == 0u) {
             v[1] = k.rho_lo; v[2] = k.rho_hi; v[3] = k.lam_lo; v[4] = k.lam_hi; v[5] = k.tau;
         } else if (k.type == 1u) {
@@ -909,6 +914,7 @@ lst_status lst_load_geometry(lst_ctx *ctx, const lst_module_desc *m, uint32_t n)
         std::memcpy(&host[off_cls + sizeof(lst::LsK) * i], v, sizeof v);
     }
     if (ns) std::memcpy(&host[off_sf], geom.surfaces.data(), sizeof(lst::Surface) * ns);
+    std::memcpy(&host[off_phi], geom.mod_phi.data(), 8 * nm);
     void *dmem = nullptr;
     if (hipMalloc(&dmem, total) != hipSuccess) return set_err(ctx, LST_ERR_OOM, "geometry allocation failed");
     hipError_t e = hipMemcpy(dmem, host.data(), total, hipMemcpyHostToDevice);
@@ -927,6 +933,7 @@ lst_status lst_load_geometry(lst_ctx *ctx, const lst_module_desc *m, uint32_t n)
     ctx->dg.edge = (const uint2 *)(d + off_edge);
     ctx->dg.cls = (const lst::LsK *)(d + off_cls);
     ctx->dg.surf = (const lst::Surface *)(d + off_sf);
+    ctx->dg.mod_phi = (const float2 *)(d + off_phi);
     // the hit histogram runs per event in LDS, in slices of the event's
     // (module, sensor) bins that fit one block's LDS
     int lds_max = 0;

@@ -32,7 +32,8 @@ constexpr uint32_t kSubLists = kMaxGrid;
 
 // Device copy of the geometry (read-only).
 // Device copy of a line-segment class (LsClass), 32 bytes:
-//   a = (S, p0, p1, p2), b = (p3, p4, 0, type bits) with
+//   a = (S, p0, p1, p2), b = (p3, p4, reach, type bits) with reach the
+//   largest azimuth difference of the anchors (asin S, plus margin) and
 //   barrel -> barrel: p0..p4 = rho_lo, rho_hi, lam_lo, lam_hi, tau;
 //   endcap -> endcap: p0, p1 = lo_fac, hi_fac;
 //   barrel -> endcap: p0..p3 = cf, zs, zbpl, zbml.
@@ -48,6 +49,7 @@ struct DevGeom {
     const uint2 *edge;          // (destination module, class)
     const LsK *cls;
     const Surface *surf;        // n_surf
+    const float2 *mod_phi;      // n_mod: azimuth centre and half-width (with margin)
     uint32_t hist_slice;        // hit histogram in LDS: (module, sensor) bins per slice
 };
 

@@ -353,6 +353,19 @@ lst_status build_geometry(const lst_params &p, const lst_module_desc *m, uint32_
         }
     }
 
+    // azimuth extent of every module with the margin the map uses for an
+    // outer module: a segment's outer anchor lies within it
+    g.mod_phi.resize(2 * (size_t)n);
+    for (uint32_t B = 0; B < n; B++) {
+        const lst_module_desc &b = m[B];
+        const double rb_min = b.kind == LST_BARREL ? b.s_lo : b.c_min;
+        const double mphiB = kEdgeSigmas * p.sig_rphi / rb_min + 1e-6;
+        double c = 0.5 * (b.phi_min + b.phi_max);
+        if (c > kPi) c -= kTwoPi;
+        g.mod_phi[2 * (size_t)B] = (float)c;
+        g.mod_phi[2 * (size_t)B + 1] = (float)(0.5 * (b.phi_max - b.phi_min) + mphiB);
+    }
+
     // ---- surfaces for the seed lookup --------------------------------------
     g.surfaces.assign(n_surf, Surface{});
     std::vector<bool> seen(n_surf, false);

@@ -26,6 +26,8 @@ namespace lst {
 
 constexpr int kScanBlock = 256;
 constexpr int kScanTile = 4 * kScanBlock;
+constexpr float kPiF = 3.14159265358979f;
+constexpr double kPiD = 3.14159265358979323846;
 
 __device__ inline uint32_t wave_incl_scan(uint32_t v)
 {
@@ -548,6 +550,19 @@ __global__ void k_md_units(const Batch b, const Totals *t)
 
 // ------------------------------------------------------ a3: line segments ---
 
+// Whether an outer module can hold a segment's outer anchor for an inner
+// anchor at azimuth pha: the arc distance from pha to the module's azimuth
+// extent (centre, half-width with margin) is within the class's reach.  The
+// azimuth cut needs |sin(dphi)| <= S with cos(dphi) > 0, i.e. |dphi| <= asin S,
+// so a module out of reach holds no partner and its MDs are not visited; the
+// reach carries margins beyond the rounding of this test.
+__device__ inline bool in_reach(float pha, const float2 mp, float reach)
+{
+    float d = fabsf(pha - mp.x);
+    if (d > kPiF) d = 2.0f * kPiF - d;
+    return d <= mp.y + reach;
+}
+
 __device__ inline bool ls_cut(const LsK &k, const Consts &c, bool bend,
                               float xa, float ya, float za, float ra, float beta_a,
                               float xb, float yb, float zb, float rb)
@@ -645,7 +660,7 @@ __global__ __launch_bounds__(256) void k_ls(const Batch b, Totals *t, const DevG
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
         const uint32_t a = base + threadIdx.x;
         uint32_t e0 = 0, e1 = 0, ubase = 0;
-        float xa = 0.f, ya = 0.f, za = 0.f, ra = 0.f, ba = 0.f;
+        float xa = 0.f, ya = 0.f, za = 0.f, ra = 0.f, ba = 0.f, pha = 0.f;
         if (a < n) {
             const uint32_t u = b.md_u[a] & kUnitMask;
             const uint32_t m = u % n_mod;
@@ -658,6 +673,7 @@ __global__ __launch_bounds__(256) void k_ls(const Batch b, Totals *t, const DevG
             za = pa.z;
             ra = fabsf(pa.w);
             ba = b.md_beta[a];
+            pha = atan2f(ya, xa);
         }
         uint32_t run = 0;                             // segments of this lane's MD so far
         for (uint32_t eb = e0;; eb += kEdgeGroup) {
@@ -669,9 +685,11 @@ __global__ __launch_bounds__(256) void k_ls(const Batch b, Totals *t, const DevG
                 uint32_t bq = 0, eq = 0, cl = 0;
                 if (eb + j < e1) {
                     const uint2 ed = g.edge[eb + j];
-                    bq = min(b.md_off[ubase + ed.x], b.cap_md);
-                    eq = max(min(b.md_off[ubase + ed.x + 1], b.cap_md), bq);
                     cl = ed.y;
+                    if (in_reach(pha, g.mod_phi[ed.x], g.cls[cl].b.z)) {
+                        bq = min(b.md_off[ubase + ed.x], b.cap_md);
+                        eq = max(min(b.md_off[ubase + ed.x + 1], b.cap_md), bq);
+                    }
                 }
                 T += eq - bq;
                 s_grp[wv][j][lane] = bq;
@@ -818,6 +836,7 @@ __global__ __launch_bounds__(256) void k_ls_wave(const Batch b, Totals *t, const
         const uint32_t base = u - m;
         const float4 pa = b.md_pos[a];
         const float xa = pa.x, ya = pa.y, za = pa.z, ra = fabsf(pa.w), ba = b.md_beta[a];
+        const float pha = atan2f(ya, xa);
         const uint32_t e0 = g.edge_begin[m], e1 = g.edge_begin[m + 1];
         uint32_t carry = kFill ? b.ls_off[a] : 0u;
         if (kFill) {
@@ -838,7 +857,10 @@ __global__ __launch_bounds__(256) void k_ls_wave(const Batch b, Totals *t, const
                 const uint2 ed = g.edge[e];
                 bb = min(b.md_off[base + ed.x], b.cap_md);
                 be = min(b.md_off[base + ed.x + 1], b.cap_md);
-                if (bb < be) kc = g.cls[ed.y];
+                if (bb < be) {
+                    kc = g.cls[ed.y];
+                    if (!in_reach(pha, g.mod_phi[ed.x], kc.b.z)) be = bb;   // out of azimuth reach
+                }
             }
             // pass mask of this lane's candidates (up to 32; beyond, re-test)
             uint32_t cnt = 0, mask = 0;
@@ -912,7 +934,6 @@ struct Anchor {
     bool disk;
 };
 
-constexpr float kPiF = 3.14159265358979f;
 
 __device__ inline uint32_t phi_bin(float x, float y, uint32_t nphi)
 {
@@ -1279,7 +1300,6 @@ __global__ __launch_bounds__(256) void k_t5_place(const Batch b, const DevGeom g
 // helix band crosses, restricted to the curvature bins its curvature cut can
 // accept (bounded with the row's largest object resolution).
 
-constexpr double kPiD = 3.14159265358979323846;
 
 __device__ inline int kappa_bin_d(double k, const Consts &c)
 {

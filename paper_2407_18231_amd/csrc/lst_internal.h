@@ -64,6 +64,9 @@ struct Geometry {
     std::vector<uint32_t> edge_dst;   // per edge: destination module
     std::vector<uint32_t> edge_cls;   // per edge: class id
     std::vector<LsClass> classes;
+    // per module: azimuth centre in (-pi, pi] and half-width, widened by the
+    // connection map's hit-position margin (radians)
+    std::vector<float> mod_phi;
     std::vector<Surface> surfaces;
     Consts c{};
 };
