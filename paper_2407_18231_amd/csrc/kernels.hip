@@ -517,7 +517,8 @@ __global__ __launch_bounds__(256) void k_md_direct(const Batch b, Totals *t, con
 
 // MDs from the block regions to their canonical slots, with the anchor
 // (the lower hit; the sign of r marks a disk), beta, unit and input hits
-__global__ __launch_bounds__(256) void k_md_place(const Batch b, const DevGeom g, const Consts c, uint32_t nsub)
+__global__ __launch_bounds__(256) void k_md_place(const Batch b, const Totals *t, const DevGeom g, const Consts c,
+                                                  uint32_t nsub)
 {
     __shared__ uint32_t s_off[kSubLists + 1];
     for (uint32_t i = threadIdx.x; i <= nsub; i += blockDim.x) s_off[i] = b.mds_soff[i];
@@ -538,6 +539,9 @@ __global__ __launch_bounds__(256) void k_md_place(const Batch b, const DevGeom g
             b.md_hup[k] = b.hin[r.z];
         }
     }
+    // the per-module MD offsets (as k_md_units writes them)
+    const uint32_t nu = t->n_md_units;
+    GRID_STRIDE(u, nu + 1) b.md_off[u] = b.md_hoff[b.bin_off[2u * u]];
 }
 
 // MD range of every (event, module) unit: the MDs of its lower-sensor hits
@@ -1754,20 +1758,17 @@ __global__ void k_pt_order(const Batch b, const Totals *t)
         }
         out_p[a + r] = p;
         out_o[a + r] = o;
+        // the track-candidate flags: seeds and T5s used by a pT5, seeds used by a pT3
+        if (kKind == 1) {
+            b.pls_used5[p] = 1u;
+            b.t5_used[o] = 1u;
+        } else {
+            b.pls_used3[p] = 1u;
+        }
     }
 }
 
 // ------------------------------------------------ a8: track candidates ----
-
-__global__ void k_tc_mark(const Batch b, const Totals *t)
-{
-    const uint32_t n5 = min(t->n_pt5, b.cap_pt5), n3 = min(t->n_pt3, b.cap_pt3);
-    GRID_STRIDE(i, n5) {
-        b.pls_used5[b.pt5_p[i]] = 1u;
-        b.t5_used[b.pt5_o[i]] = 1u;
-    }
-    GRID_STRIDE(i, n3) b.pls_used3[b.pt3_p[i]] = 1u;
-}
 
 // keep flags over [pT3 | T5 | pLS]: pT3 whose seed has no pT5, T5 in no pT5,
 // seeds in neither (every pT5 is a track candidate)
@@ -1898,14 +1899,15 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
         L.launch("md_count", k_md_direct<false>, gmd, blk, b, t, g, c, stats);
         L.scan(b.md_cnt, b.md_hoff, &t->n_sorted, b.cap_hits, &t->n_md, "scan_md");
         L.launch("md_fill", k_md_direct<true>, gmd, blk, b, t, g, c, 0);
+        L.launch("md_units", k_md_units, grid_for((uint64_t)b.cap_ev * n_mod + 1), blk, b, (const Totals *)t);
     } else {
         const uint32_t nsub_md = gmd.x;
         L.launch("md_walk", k_md, gmd, blk, b, t, g, c, nsub_md, stats);
         L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.mds_sub, b.mds_soff, b.cap_md, nsub_md, &t->n_mds);
         L.scan(b.md_cnt, b.md_hoff, &t->n_sorted, b.cap_hits, &t->n_md, "scan_md");
-        L.launch("md_place", k_md_place, grid_for(b.cap_md), blk, b, g, c, nsub_md);
+        L.launch("md_place", k_md_place, grid_for(std::max<uint64_t>(b.cap_md, (uint64_t)b.cap_ev * n_mod + 1)), blk,
+                 b, (const Totals *)t, g, c, nsub_md);
     }
-    L.launch("md_units", k_md_units, grid_for((uint64_t)b.cap_ev * n_mod + 1), blk, b, (const Totals *)t);
     // a3: line segments over the connection map
     // small batches: 32 lanes per MD for latency; large ones: pooled walk
     if (b.cap_md <= kLsWaveMaxMd) {
@@ -1950,8 +1952,8 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     L.launch("pt5_eval", k_pt_eval<1>, grid_for(b.cap_ptc5), blk, b, c, nsub);
     L.scan(b.pt5_cnt, b.pt5_off, &t->n_pls, b.cap_pls, &t->n_pt5, "scan_pt");
     L.launch("pt_place", k_pt_place<1>, grid_for(b.cap_ptc5), blk, b, nsub);
-    L.launch("pt_order", k_pt_order<1>, grid_for(b.cap_pt5), blk, b, (const Totals *)t);
     L.launch("zero8", k_zero_u8, grid_for(b.cap_t5), blk, b.t5_used, &t->n_t5, b.cap_t5);
+    L.launch("pt_order", k_pt_order<1>, grid_for(b.cap_pt5), blk, b, (const Totals *)t);
 
     // main: the T3 seed-lookup buckets (a6) and pT3 (a7)
     L.on_side(false);
@@ -1968,7 +1970,6 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     // a8: track candidates, once both branches are done
     L.mark(1);
     L.wait(1);
-    L.launch("tc_mark", k_tc_mark, grid_for(std::max(b.cap_pt3, b.cap_pt5)), blk, b, (const Totals *)t);
     L.launch("tc_keep", k_tc_keep, grid_for((uint64_t)b.cap_pt3 + b.cap_t5 + b.cap_pls), blk, b, t);
     L.scan(b.tc_cnt, b.tc_off, &t->n_tcu, b.cap_pt3 + b.cap_t5 + b.cap_pls, &t->n_tc, "scan_tc");
     L.launch("tc_write", k_tc_write, grid_for((uint64_t)b.cap_pt3 + b.cap_t5 + b.cap_pls), blk, b,
