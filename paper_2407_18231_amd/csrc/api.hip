@@ -176,6 +176,7 @@ void carve_work(Carver &cv, Batch &b, uint32_t n_mod, uint32_t n_surf, uint32_t 
     b.pt5_p = cv.take<uint32_t>(b.cap_pt5);
     b.pt5_o = cv.take<uint32_t>(b.cap_pt5);
     b.pls_ev = cv.take<uint32_t>(b.cap_pls);
+    b.pls_seed = cv.take<double>(10ull * b.cap_pls);
     b.pls_used5 = cv.take<uint8_t>(b.cap_pls);
     b.pls_used3 = cv.take<uint8_t>(b.cap_pls);
     b.t5_used = cv.take<uint8_t>(b.cap_t5);
@@ -686,7 +687,7 @@ uint64_t predict_footprint(uint64_t hits, uint64_t pls, const lst::Consts &k)
     // capacity + the per-event bins of the sort and of the seed lookup
     lst::Caps c = lst::plan_caps(1, hits, pls);
     uint64_t b = 0;
-    b += 73ull * c.hits + 80ull * c.pls + 24ull * k.n_mod;
+    b += 73ull * c.hits + 160ull * c.pls + 24ull * k.n_mod;
     b += (56ull + 4ull * lst::kKeepLs) * c.md + 52ull * c.ls + 88ull * c.t3 + 64ull * c.t5;
     b += 16ull * (c.pt3 + c.pt5) + 24ull * c.pls * k.n_surf + 19ull * c.pls + 16ull * (c.pt3 + c.t5 + c.pls);
     b += 12ull * (c.ptc3 + c.ptc5);

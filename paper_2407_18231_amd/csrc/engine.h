@@ -150,6 +150,7 @@ struct Batch {
     // a8: track candidates over [pT3 | T5 | pLS]
     uint8_t *pls_used5, *pls_used3, *t5_used;
     uint32_t *pls_ev;                   // event of each seed
+    double *pls_seed;                   // derived binary64 quantities of each seed (10 words)
     uint32_t *tc_cnt, *tc_off, *tc_type, *tc_idx;
     uint32_t *ev_tab;                   // (cap_ev + 1) x kEvTabCols
 };

@@ -274,20 +274,6 @@ __global__ __launch_bounds__(kHistBlock) void k_hit_hist(const Batch b, Totals *
 // offset gathers, are in flight together
 constexpr uint32_t kHitsPerThread = 4;
 
-// seeds: finite parameters; the event of each seed
-__global__ void k_pls_check(const Batch b, Totals *t)
-{
-    const uint32_t n = min(t->n_pls, b.cap_pls);
-    const uint32_t n_ev = t->n_ev;
-    GRID_STRIDE(p, n) {
-        b.pls_ev[p] = find_event(b.ev_pls_off, n_ev, p);
-        bool ok = true;
-        for (int k = 0; k < 5; k++) ok = ok && isfinite(b.in_par[5 * p + k]);
-        for (int k = 0; k < 15; k++) ok = ok && isfinite(b.in_cov[15 * p + k]);
-        if (!ok) atomicOr(&t->err, kErrNonFinite);
-    }
-}
-
 // each hit's record to its bin (coalesced reads, one 16-byte write per hit;
 // four hits per thread)
 __global__ void k_hit_scatter(const Batch b, const Totals *t)
@@ -1356,6 +1342,47 @@ __device__ inline Seed load_seed(const Batch &b, const Consts &c, uint32_t p)
     return s;
 }
 
+// seeds: the event of each, the finite check of its parameters, and its
+// derived binary64 quantities (load_seed), stored once for the roads and the
+// seed cuts of every pair
+__global__ void k_pls_prep(const Batch b, Totals *t, const Consts c)
+{
+    const uint32_t n = min(t->n_pls, b.cap_pls);
+    const uint32_t n_ev = t->n_ev;
+    GRID_STRIDE(p, n) {
+        b.pls_ev[p] = find_event(b.ev_pls_off, n_ev, p);
+        bool ok = true;
+        for (int k = 0; k < 5; k++) ok = ok && isfinite(b.in_par[5 * p + k]);
+        for (int k = 0; k < 15; k++) ok = ok && isfinite(b.in_cov[15 * p + k]);
+        if (!ok) atomicOr(&t->err, kErrNonFinite);
+        const Seed s = load_seed(b, c, p);
+        double2 *r = reinterpret_cast<double2 *>(b.pls_seed) + 5 * (size_t)p;
+        r[0] = make_double2(s.kp, s.skp);
+        r[1] = make_double2(s.phi0, s.cot);
+        r[2] = make_double2(s.z0, s.s11);
+        r[3] = make_double2(s.s22, s.s44);
+        r[4] = make_double2(s.cphi, s.sphi);
+    }
+}
+
+__device__ inline Seed seed_of(const Batch &b, uint32_t p)
+{
+    const double2 *r = reinterpret_cast<const double2 *>(b.pls_seed) + 5 * (size_t)p;
+    const double2 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3], r4 = r[4];
+    Seed s;
+    s.kp = r0.x;
+    s.skp = r0.y;
+    s.phi0 = r1.x;
+    s.cot = r1.y;
+    s.z0 = r2.x;
+    s.s11 = r2.y;
+    s.s22 = r3.x;
+    s.s44 = r3.y;
+    s.cphi = r4.x;
+    s.sphi = r4.y;
+    return s;
+}
+
 // binary64 seed-object compatibility: curvature, then azimuth and z (barrel)
 // or r (disk) of the helix at the object's inner and outer anchors.  The
 // helix direction at radius r is phi0 - asin(u), u = r kappa / 2; its unit
@@ -1478,7 +1505,7 @@ __global__ __launch_bounds__(256) void k_road(const Batch b, const Totals *t, co
         int b0 = 0, b1 = -1;
         double plo = 0.0, pwidth = 0.0;
         if (sf.kind <= 1u) {
-            const Seed s = load_seed(b, c, p);
+            const Seed s = seed_of(b, p);
             if (seed_road(c, s, sf, b0, b1, plo, pwidth)) {
                 rp = make_float2((float)plo, (float)pwidth);
                 // objects of resolution class i: curvature within the seed's
@@ -1694,7 +1721,7 @@ __global__ __launch_bounds__(256) void k_pt_eval(const Batch b, const Consts c, 
             io = b.t3_ac[b.t5_w[o]].y;
             ks = b.t5_ks[o];
         }
-        const Seed s = load_seed(b, c, p);
+        const Seed s = seed_of(b, p);
         const bool pass = p_cut(c, s, ks.x, ks.y, load_anchor(b, ia), load_anchor(b, io));
         rank[i] = pass ? atomicAdd(&pcnt[p], 1u) : kInvalid;
     }
@@ -1873,7 +1900,7 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     launch_setup(L, t, c);
     L.fork(0);
     L.on_side(true);
-    L.launch("pls_check", k_pls_check, grid_for(b.cap_pls), blk, b, t);
+    L.launch("pls_prep", k_pls_prep, grid_for(b.cap_pls), blk, b, t, c);
     L.launch("road", k_road, grid_for(cap_pu), blk, b, (const Totals *)t, g, c);
     // counters of later stages that need clearing
     L.launch("zero", k_zero_u32, grid_for((uint64_t)cap_bk + 1), blk, b.bk3_cnt, &t->n_bk, cap_bk, 1u);
