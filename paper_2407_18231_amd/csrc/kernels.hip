@@ -177,6 +177,32 @@ __device__ inline uint32_t pair_slot(const uint32_t *s_off, uint32_t j, uint32_t
     return lo * subcap + (j - s_off[lo]);
 }
 
+// One increment of cnt[key] per active lane with one atomic per distinct
+// key of the wave: the lanes sharing a key are ranked by lane order behind
+// the first of them, whose single add covers them all (every lane of the
+// wave calls it).  Returns the lane's slot among the key's increments.
+__device__ inline uint32_t wave_grouped_inc(uint32_t *cnt, uint32_t key, bool active)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    unsigned long long todo = __ballot(active);
+    uint32_t leader = lane, rank = 0, count = 0;
+    while (todo != 0ull) {
+        const uint32_t l = (uint32_t)__ffsll(todo) - 1u;
+        const uint32_t lk = __shfl(key, l);
+        const unsigned long long peers = __ballot(active && key == lk) & todo;
+        if ((peers >> lane) & 1ull) {
+            leader = l;
+            rank = (uint32_t)__popcll(peers & below);
+        }
+        if (lane == l) count = (uint32_t)__popcll(peers);
+        todo &= ~peers;
+    }
+    uint32_t base = 0;
+    if (active && leader == lane) base = atomicAdd(&cnt[key], count);
+    return __shfl(base, leader) + rank;
+}
+
 // lanes s0 .. e0 - 1 of a wave (0 <= s0 <= e0 <= 64)
 __device__ inline unsigned long long lane_range(uint32_t s0, uint32_t e0)
 {
@@ -1139,22 +1165,32 @@ __global__ __launch_bounds__(256) void k_t3_place(const Batch b, const DevGeom g
     __syncthreads();
     const uint32_t n = s_off[nsub];
     const uint32_t subcap = b.cap_t3 / nsub;
-    GRID_STRIDE(j, n) {
-        const uint32_t i = pair_slot(s_off, j, subcap, nsub);
-        const uint32_t l1 = b.t3s_l1[i];
-        const uint32_t k = b.t3_off[l1] + b.t3s_j[i];
-        if (k < b.cap_t3) {
-            b.t3_l1[k] = l1;
-            b.t3_l2[k] = b.t3s_l2[i];
-            b.t3_ac[k] = b.t3s_ac[i];
-            b.t3_ks[k] = b.t3s_ks[i];
-            // the object's slot in its seed-lookup bucket
-            const uint2 ac = b.t3s_ac[i];
-            const float2 ks = b.t3s_ks[i];
-            const float4 pa = b.md_pos[ac.x];
-            const uint32_t bk = bucket_row(b, g, c, ac.x, pa.x, pa.y) + bucket_in_row(ks.x, ks.y, c);
+    // whole waves per step (the bucket slots are drawn per wave)
+    for (uint32_t jb = blockIdx.x * blockDim.x; jb < n; jb += gridDim.x * blockDim.x) {
+        const uint32_t j = jb + threadIdx.x;
+        bool in = false;
+        uint32_t k = 0, bk = 0;
+        if (j < n) {
+            const uint32_t i = pair_slot(s_off, j, subcap, nsub);
+            const uint32_t l1 = b.t3s_l1[i];
+            k = b.t3_off[l1] + b.t3s_j[i];
+            if (k < b.cap_t3) {
+                in = true;
+                const uint2 ac = b.t3s_ac[i];
+                const float2 ks = b.t3s_ks[i];
+                b.t3_l1[k] = l1;
+                b.t3_l2[k] = b.t3s_l2[i];
+                b.t3_ac[k] = ac;
+                b.t3_ks[k] = ks;
+                // the object's seed-lookup bucket
+                const float4 pa = b.md_pos[ac.x];
+                bk = bucket_row(b, g, c, ac.x, pa.x, pa.y) + bucket_in_row(ks.x, ks.y, c);
+            }
+        }
+        const uint32_t slot = wave_grouped_inc(b.bk3_cnt, bk, in);
+        if (in) {
             b.bk3_id[k] = bk;
-            b.bk3_rank[k] = atomicAdd(&b.bk3_cnt[bk], 1u);
+            b.bk3_rank[k] = slot;
         }
     }
 }
@@ -1263,21 +1299,31 @@ __global__ __launch_bounds__(256) void k_t5_place(const Batch b, const DevGeom g
     __syncthreads();
     const uint32_t n = s_off[nsub];
     const uint32_t subcap = b.cap_t5 / nsub;
-    GRID_STRIDE(j, n) {
-        const uint32_t i = pair_slot(s_off, j, subcap, nsub);
-        const uint32_t u = b.t5s_u[i];
-        const uint32_t k = b.t5_off[u] + b.t5s_j[i];
-        if (k < b.cap_t5) {
-            b.t5_u[k] = u;
-            b.t5_w[k] = b.t5s_w[i];
-            b.t5_ks[k] = b.t5s_ks[i];
-            // the object's slot in its seed-lookup bucket
-            const uint32_t a = b.t3_ac[u].x;
-            const float2 ks = b.t5s_ks[i];
-            const float4 pa = b.md_pos[a];
-            const uint32_t bk = bucket_row(b, g, c, a, pa.x, pa.y) + bucket_in_row(ks.x, ks.y, c);
+    // whole waves per step (the bucket slots are drawn per wave)
+    for (uint32_t jb = blockIdx.x * blockDim.x; jb < n; jb += gridDim.x * blockDim.x) {
+        const uint32_t j = jb + threadIdx.x;
+        bool in = false;
+        uint32_t k = 0, bk = 0;
+        if (j < n) {
+            const uint32_t i = pair_slot(s_off, j, subcap, nsub);
+            const uint32_t u = b.t5s_u[i];
+            k = b.t5_off[u] + b.t5s_j[i];
+            if (k < b.cap_t5) {
+                in = true;
+                const float2 ks = b.t5s_ks[i];
+                b.t5_u[k] = u;
+                b.t5_w[k] = b.t5s_w[i];
+                b.t5_ks[k] = ks;
+                // the object's seed-lookup bucket
+                const uint32_t a = b.t3_ac[u].x;
+                const float4 pa = b.md_pos[a];
+                bk = bucket_row(b, g, c, a, pa.x, pa.y) + bucket_in_row(ks.x, ks.y, c);
+            }
+        }
+        const uint32_t slot = wave_grouped_inc(b.bk5_cnt, bk, in);
+        if (in) {
             b.bk5_id[k] = bk;
-            b.bk5_rank[k] = atomicAdd(&b.bk5_cnt[bk], 1u);
+            b.bk5_rank[k] = slot;
         }
     }
 }
