@@ -246,3 +246,24 @@ def test_binary32_stages_bit_exact(ctx, geo):
         for k in ("md", "ls", "t3", "t5"):
             acc = {q for q, st in od[k].items() if st & oracle.ST_ACC}
             assert set(got[k]) == acc, (i, k, len(set(got[k]) ^ acc))
+
+
+def test_graph_replay_matches_eager(geo):
+    """The captured two-stream chain replayed from a hipGraph (the bench's
+    graph figure) gives the eager run's lists, replay after replay, with
+    eager runs in between; 16 events take the pooled large-batch kernels."""
+    g = geo["pu200"]
+    evs = [s.gen_event(g, s.config_pu(200), s.event_seed(2, i)) for i in range(16)]
+    with lst.Context(max_batch=16) as c:
+        c.load_geometry(g)
+        c.batch_upload(evs)
+        c.batch_execute(1, graph=False)
+        eager = c.batch_download(len(evs))
+        for rounds in (1, 3, 2):
+            c.batch_execute(rounds, graph=True)
+            got = c.batch_download(len(evs))
+            for a, b in zip(eager, got):
+                for k in STAGES:
+                    assert np.array_equal(a[k], b[k]), (rounds, k)
+            c.batch_execute(1, graph=False)
+    assert sum(len(r["ls"]) for r in eager) > 16 * 50_000
