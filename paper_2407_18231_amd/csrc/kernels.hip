@@ -1012,17 +1012,23 @@ __device__ inline Anchor load_anchor(const Batch &b, uint32_t i)
     return A;
 }
 
+// the transverse chord between two anchors
+__device__ inline float chord(const Anchor &A, const Anchor &B)
+{
+    float dx = B.x - A.x, dy = B.y - A.y;
+    return sqrtf(dx * dx + dy * dy);
+}
+
 // curvature of the circle through three transverse points (positive for a
-// clockwise turn) and its resolution; also returns the chords A-B and B-C
+// clockwise turn) and its resolution, given the chords d1 = A-B and d2 = B-C
+// (the walks take the chord their owner fixes once per owner)
 __device__ inline void kappa3(const Consts &c, const Anchor &A, const Anchor &B, const Anchor &C,
-                              float &kap, float &sk, float &d1, float &d2)
+                              float d1, float d2, float &kap, float &sk)
 {
     float dx1 = B.x - A.x, dy1 = B.y - A.y;
     float dx2 = C.x - B.x, dy2 = C.y - B.y;
     float dx3 = C.x - A.x, dy3 = C.y - A.y;
     float cr = dx1 * dy2 - dy1 * dx2;
-    d1 = sqrtf(dx1 * dx1 + dy1 * dy1);
-    d2 = sqrtf(dx2 * dx2 + dy2 * dy2);
     float d3 = sqrtf(dx3 * dx3 + dy3 * dy3);
     kap = (-2.0f * cr) / ((d1 * d2) * d3);
     float hC = fminf(1.0f, C.r * c.khalf);
@@ -1051,15 +1057,6 @@ __device__ inline bool rz3(const Consts &c, const Anchor &A, const Anchor &B, co
     return fabsf(E) <= c.ns * res + bias;
 }
 
-// the two chord lengths of the circle through A, B, C (as kappa3 computes them)
-__device__ inline void sides3(const Anchor &A, const Anchor &B, const Anchor &C, float &d1, float &d2)
-{
-    float dx1 = B.x - A.x, dy1 = B.y - A.y;
-    float dx2 = C.x - B.x, dy2 = C.y - B.y;
-    d1 = sqrtf(dx1 * dx1 + dy1 * dy1);
-    d2 = sqrtf(dx2 * dx2 + dy2 * dy2);
-}
-
 // T3: the 64 inner LSs of a wave (one per lane) pool their candidates --
 // the LSs that start at each one's outer MD, range and anchors stored per LS
 // by k_ls_aux -- and the lanes take the pooled candidates 64 at a time, so
@@ -1084,6 +1081,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
         const uint32_t l1 = base + threadIdx.x;
         uint32_t ia = 0, q0 = 0, cnt = 0;
         float4 pa = make_float4(0.f, 0.f, 0.f, 0.f), pb = pa;
+        float dab = 0.f;                                 // the chord A-B, fixed by the owner
         if (l1 < n) {
             ia = b.ls_a[l1];
             const uint2 nx = b.ls_nx[l1];
@@ -1092,6 +1090,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
             if (cnt) {
                 pb = b.ls_pb[l1];
                 pa = b.md_pos[ia];
+                dab = chord(anchor_of(pa), anchor_of(pb));
             }
         }
         const uint32_t incl = wave_incl_scan(cnt);
@@ -1109,6 +1108,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
             const uint32_t o_l1 = __shfl(l1, o), o_run = __shfl(run, o);
             const float4 oa = make_float4(__shfl(pa.x, o), __shfl(pa.y, o), __shfl(pa.z, o), __shfl(pa.w, o));
             const float4 ob = make_float4(__shfl(pb.x, o), __shfl(pb.y, o), __shfl(pb.z, o), __shfl(pb.w, o));
+            const float d1 = __shfl(dab, o);
             bool pass = false;
             uint32_t l2 = 0, ic = 0;
             float kap = 0.f, sk = 0.f;
@@ -1116,13 +1116,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
                 l2 = o_q0 + (ci - o_off);
                 ic = b.ls_b[l2];
                 const Anchor A = anchor_of(oa), B = anchor_of(ob), C = anchor_of(b.ls_pb[l2]);
-                float d1, d2;
                 cand++;
-                // the rz cut first (it needs two of the three chords and rejects
+                // the rz cut first (it needs the chords A-B and B-C and rejects
                 // most candidates), then the curvature cut
-                sides3(A, B, C, d1, d2);
+                const float d2 = chord(B, C);
                 if (rz3(c, A, B, C, d1, d2)) {
-                    kappa3(c, A, B, C, kap, sk, d1, d2);
+                    kappa3(c, A, B, C, d1, d2, kap, sk);
                     pass = fabsf(kap) <= c.kmaxf + c.ns * sk;
                 }
             }
@@ -1257,8 +1256,8 @@ __global__ __launch_bounds__(256) void k_t5(const Batch b, Totals *t, const Cons
                 // the pairwise test of the two stored curvatures needs no new arithmetic
                 if (fabsf(k1 - k2) <= c.ns * (sk1 + sk2)) {
                     const Anchor A = anchor_of(oa), C = anchor_of(oc), E = load_anchor(b, b.t3_ac[w].y);
-                    float d1, d2;
-                    kappa3(c, A, C, E, k3, sk3, d1, d2);
+                    const float d1 = chord(A, C), d2 = chord(C, E);
+                    kappa3(c, A, C, E, d1, d2, k3, sk3);
                     pass = fabsf(k1 - k3) <= c.ns * (sk1 + sk3) && fabsf(k2 - k3) <= c.ns * (sk2 + sk3) &&
                            rz3(c, A, C, E, d1, d2);
                 }
