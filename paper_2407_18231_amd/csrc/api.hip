@@ -855,6 +855,9 @@ lst_status lst_create(const lst_params *p, lst_ctx **out)
     if (prm.max_batch == 0 || prm.max_batch > 4096 || prm.n_slots == 0 || prm.n_slots > 8 ||
         prm.queue_depth == 0)
         return LST_ERR_INVALID_ARG;
+    if ((prm.n_phi_bins != 0 && (prm.n_phi_bins < 4 || prm.n_phi_bins > 4096)) ||
+        (prm.n_kappa_bins != 0 && (prm.n_kappa_bins < 2 || prm.n_kappa_bins > 128)))
+        return LST_ERR_INVALID_ARG;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || prm.device < 0 || prm.device >= ndev) return LST_ERR_DEVICE;
     if (hipSetDevice(prm.device) != hipSuccess) return LST_ERR_DEVICE;

@@ -37,7 +37,7 @@ class lst_params(C.Structure):
                 ("L", C.c_double), ("sig_rphi", C.c_double), ("sig_c", C.c_double),
                 ("n_sigma", C.c_double), ("flags", C.c_uint32), ("max_batch", C.c_uint32),
                 ("n_slots", C.c_uint32), ("queue_depth", C.c_uint32),
-                ("mem_budget", C.c_uint64)]
+                ("mem_budget", C.c_uint64), ("n_phi_bins", C.c_uint32), ("n_kappa_bins", C.c_uint32)]
 
 
 MODULE_DTYPE = np.dtype([("kind", "<u4"), ("layer", "<u4"), ("side", "<i4"), ("pad", "<u4"),

@@ -80,3 +80,22 @@ def test_connection_map_holds_every_oracle_segment(lib, kind):
                   for t in set(range(nb + 2 * nd)) if _is_next(nb, nd, int(sid[a]), t)) if kind == "tiny" else None
     if n_pairs:
         assert dst.size < 0.5 * n_pairs
+
+
+def test_bucket_granularity_params(lib, tmp_path):
+    """The seed-lookup bucket counts default to 0 (the library's 64 x 16) and
+    out-of-range values are refused before any device is touched; the
+    tuner's cache round-trips per architecture and workload."""
+    p = lst.default_params()
+    assert p.n_phi_bins == 0 and p.n_kappa_bins == 0
+    for bad in (dict(n_phi_bins=3), dict(n_phi_bins=5000), dict(n_kappa_bins=1), dict(n_kappa_bins=200)):
+        with pytest.raises(lst.LstError) as e:
+            lst.Context(**bad)
+        assert e.value.name == "INVALID_ARG", bad
+    from paper_2407_18231_amd import tune
+    path = str(tmp_path / "cache.json")
+    assert tune.load_choice("gfx950", "batch64-pu200", path) is None
+    tune.store_choice("gfx950", "batch64-pu200", {"n_phi_bins": 64, "n_kappa_bins": 16}, path)
+    tune.store_choice("gfx950", "batch8-pu100", {"n_phi_bins": 32, "n_kappa_bins": 12}, path)
+    assert tune.load_choice("gfx950", "batch64-pu200", path) == {"n_phi_bins": 64, "n_kappa_bins": 16}
+    assert tune.load_choice("gfx942", "batch64-pu200", path) is None

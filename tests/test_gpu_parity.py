@@ -267,3 +267,17 @@ def test_graph_replay_matches_eager(geo):
                     assert np.array_equal(a[k], b[k]), (rounds, k)
             c.batch_execute(1, graph=False)
     assert sum(len(r["ls"]) for r in eager) > 16 * 50_000
+
+
+@pytest.mark.parametrize("bins", [(32, 12), (128, 24)])
+def test_bucket_granularity_does_not_change_lists(ctx, geo, bins):
+    """The seed-lookup bucket granularity (what the tuner picks) changes only
+    the speed: the lists equal those of the default setting."""
+    g = geo["pu200"]
+    ev = s.gen_event(g, s.config_pu(200), s.event_seed(2, 7))
+    ref = ctx.run_event(ev)
+    with lst.Context(n_phi_bins=bins[0], n_kappa_bins=bins[1]) as c:
+        c.load_geometry(g)
+        got = c.run_event(ev)
+    for k in STAGES:
+        assert np.array_equal(ref[k], got[k]), (bins, k)
