@@ -62,7 +62,6 @@ def step_bytes(c: dict, n_hits: int, n_pls: int, n_units: int, s_b: int, e_used:
         "ls_fill": ls + 8.0 * nls,
         "ls_walk": ls,
         "ls_place": 8.0 * nls,
-        "ls_aux": 52.0 * nls,
         "t3_count": t3 + 4.0 * nls,
         "t3_fill": t3 + 8.0 * nt3 + 16.0 * nt3,
         "t3_walk": t3 + 4.0 * nls,

@@ -109,8 +109,6 @@ void carve_work(Carver &cv, Batch &b, uint32_t n_mod, uint32_t n_surf, uint32_t 
     b.ls_off = cv.take<uint32_t>((size_t)b.cap_md + 1);
     b.ls_a = cv.take<uint32_t>(b.cap_ls);
     b.ls_b = cv.take<uint32_t>(b.cap_ls);
-    b.ls_nx = cv.take<uint2>(b.cap_ls);
-    b.ls_pb = cv.take<float4>(b.cap_ls);
     b.ls_keep = cv.take<uint32_t>((size_t)b.cap_md * kKeepLs);
     b.lss_a = cv.take<uint32_t>(b.cap_ls);
     b.lss_b = cv.take<uint32_t>(b.cap_ls);
@@ -688,7 +686,7 @@ uint64_t predict_footprint(uint64_t hits, uint64_t pls, const lst::Consts &k)
     lst::Caps c = lst::plan_caps(1, hits, pls);
     uint64_t b = 0;
     b += 73ull * c.hits + 160ull * c.pls + 24ull * k.n_mod;
-    b += (56ull + 4ull * lst::kKeepLs) * c.md + 52ull * c.ls + 88ull * c.t3 + 64ull * c.t5;
+    b += (56ull + 4ull * lst::kKeepLs) * c.md + 28ull * c.ls + 88ull * c.t3 + 64ull * c.t5;
     b += 16ull * (c.pt3 + c.pt5) + 24ull * c.pls * k.n_surf + 19ull * c.pls + 16ull * (c.pt3 + c.t5 + c.pls);
     b += 12ull * (c.ptc3 + c.ptc5);
     b += 2ull * 8ull * k.n_surf * k.nphi * (3 * k.nkb + 1);

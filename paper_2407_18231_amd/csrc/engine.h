@@ -100,8 +100,6 @@ struct Batch {
     // a3: line segments
     uint32_t *ls_cnt, *ls_off;          // per inner MD
     uint32_t *ls_a, *ls_b;
-    uint2 *ls_nx;                       // per LS: the range of LSs that start at its outer MD
-    float4 *ls_pb;                      // per LS: its outer MD's anchor
     uint32_t *ls_keep;                  // kKeepLs outer MDs per inner MD (small batches)
     // large batches: segments in the block sub-lists of an unordered list,
     // (inner MD, outer MD, place in the inner MD's list), before placement

@@ -929,20 +929,6 @@ __global__ __launch_bounds__(256) void k_ls_wave(const Batch b, Totals *t, const
     if (!kFill && stats) atomicAdd(&t->cand[1], (unsigned long long)cand);
 }
 
-// For every LS: the range of LSs that start at its outer MD (the T3
-// candidates of an LS) and its outer MD's anchor, stored beside the LS so
-// that the T3 walk reads them with its own record instead of through two
-// more dependent gathers.
-__global__ void k_ls_aux(const Batch b, const Totals *t)
-{
-    const uint32_t n = min(t->n_ls, b.cap_ls);
-    GRID_STRIDE(l, n) {
-        const uint32_t q = b.ls_b[l];
-        b.ls_nx[l] = make_uint2(min(b.ls_off[q], b.cap_ls), min(b.ls_off[q + 1], b.cap_ls));
-        b.ls_pb[l] = b.md_pos[q];
-    }
-}
-
 // ------------------------------------------------------------ a4: T3 ----
 
 struct Anchor {
@@ -1058,8 +1044,9 @@ __device__ inline bool rz3(const Consts &c, const Anchor &A, const Anchor &B, co
 }
 
 // T3: the 64 inner LSs of a wave (one per lane) pool their candidates --
-// the LSs that start at each one's outer MD, range and anchors stored per LS
-// by k_ls_aux -- and the lanes take the pooled candidates 64 at a time, so
+// the LSs that start at each one's outer MD (their range from the LS
+// offsets, their outer anchors through their outer MDs) -- and the lanes
+// take the pooled candidates 64 at a time, so
 // the cut arithmetic runs on full waves however the candidates are spread.
 // A candidate finds its owner lane by a binary search over the lanes'
 // first-candidate offsets and takes the owner's anchors by lane shuffles.
@@ -1084,11 +1071,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
         float dab = 0.f;                                 // the chord A-B, fixed by the owner
         if (l1 < n) {
             ia = b.ls_a[l1];
-            const uint2 nx = b.ls_nx[l1];
-            q0 = nx.x;
-            cnt = nx.y > nx.x ? nx.y - nx.x : 0u;
+            const uint32_t q = b.ls_b[l1];
+            // the segments that start at the outer MD
+            q0 = min(b.ls_off[q], b.cap_ls);
+            const uint32_t q1 = min(b.ls_off[q + 1], b.cap_ls);
+            cnt = q1 > q0 ? q1 - q0 : 0u;
             if (cnt) {
-                pb = b.ls_pb[l1];
+                pb = b.md_pos[q];
                 pa = b.md_pos[ia];
                 dab = chord(anchor_of(pa), anchor_of(pb));
             }
@@ -1115,7 +1104,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
             if (ci < total) {
                 l2 = o_q0 + (ci - o_off);
                 ic = b.ls_b[l2];
-                const Anchor A = anchor_of(oa), B = anchor_of(ob), C = anchor_of(b.ls_pb[l2]);
+                const Anchor A = anchor_of(oa), B = anchor_of(ob), C = anchor_of(b.md_pos[ic]);
                 cand++;
                 // the rz cut first (it needs the chords A-B and B-C and rejects
                 // most candidates), then the curvature cut
@@ -1995,7 +1984,6 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
         L.scan(b.ls_cnt, b.ls_off, &t->n_md, b.cap_md, &t->n_ls, "scan_ls");
         L.launch("ls_place", k_ls_place, grid_for(b.cap_ls), blk, b, nsub_ls);
     }
-    L.launch("ls_aux", k_ls_aux, grid_for(b.cap_ls), blk, b, (const Totals *)t);
     // a4: T3
     const dim3 gt3 = grid_for(b.cap_ls);
     const uint32_t nsub_t3 = gt3.x;
