@@ -1563,8 +1563,9 @@ __global__ __launch_bounds__(256) void k_road(const Batch b, const Totals *t, co
 
 // Candidates: the 64 (seed, surface) units of a wave (one per lane) step
 // through the azimuth bins of their roads together.  For each bin a lane
-// loads the offsets of the bin's four ranges (the curvature range of each
-// resolution class, and the wide objects) and stores them in LDS; the wave
+// loads the offsets of the four ranges of each of its next two bins (the
+// curvature range of each resolution class, and the wide objects; all
+// sixteen loads in flight together) and stores them in LDS; the wave
 // pools the entries of all lanes' ranges and the lanes take them 64 at a
 // time, so loads and tests run on full waves however the bucket sizes are
 // spread.  An entry finds its owner lane by a binary search over the lanes'
@@ -1577,7 +1578,9 @@ __global__ __launch_bounds__(256) void k_road(const Batch b, const Totals *t, co
 template <int kKind>
 __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Consts c, uint32_t nsub, int stats)
 {
-    __shared__ uint32_t s_rng[4][7][64];             // per lane: a0..a3, then cumulative sizes c1..c3
+    // per lane: the starts of the eight ranges of its two bins, then the
+    // cumulative sizes c1..c7
+    __shared__ uint32_t s_rng[4][15][64];
     __shared__ uint32_t s_n;                          // appends to this block's region
     const uint32_t n = min(t->n_pls, b.cap_pls) * c.n_surf;
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
@@ -1611,35 +1614,40 @@ __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Con
             rp = b.road_phi[unit];
         }
         const uint32_t kr0 = r.y & 0xFFFFu, kr1 = r.y >> 16, kr2 = r.z & 0xFFFFu;
-        for (uint32_t j = 0;; j++) {
+        for (uint32_t j = 0;; j += 2u) {
             if (__ballot(j < nbins) == 0ull) break;
+            // this lane's next two bins: the offsets of their eight ranges,
+            // all loads in flight together
             uint32_t T = 0;
             {
-                uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0, c1 = 0, c2 = 0, c3 = 0;
-                if (j < nbins) {
-                    uint32_t bin = first + j;
-                    if (bin >= c.nphi) bin -= c.nphi;
-                    const uint32_t rb = (row0 + bin) * per_row;
-                    a0 = bk_off[rb + (kr0 & 0xFFu)];
-                    const uint32_t e0 = bk_off[rb + (kr0 >> 8) + 1u];
-                    a1 = bk_off[rb + c.nkb + (kr1 & 0xFFu)];
-                    const uint32_t e1 = bk_off[rb + c.nkb + (kr1 >> 8) + 1u];
-                    a2 = bk_off[rb + 2u * c.nkb + (kr2 & 0xFFu)];
-                    const uint32_t e2 = bk_off[rb + 2u * c.nkb + (kr2 >> 8) + 1u];
-                    a3 = bk_off[rb + 3u * c.nkb];
-                    const uint32_t e3 = bk_off[rb + per_row];
-                    c1 = e0 > a0 ? e0 - a0 : 0u;
-                    c2 = c1 + (e1 > a1 ? e1 - a1 : 0u);
-                    c3 = c2 + (e2 > a2 ? e2 - a2 : 0u);
-                    T = c3 + (e3 > a3 ? e3 - a3 : 0u);
+                uint32_t lo[8], hi[8];
+#pragma unroll
+                for (uint32_t h = 0; h < 2u; h++) {
+#pragma unroll
+                    for (int k = 0; k < 4; k++) {
+                        lo[4 * h + k] = 0u;
+                        hi[4 * h + k] = 0u;
+                    }
+                    if (j + h < nbins) {
+                        uint32_t bin = first + j + h;
+                        if (bin >= c.nphi) bin -= c.nphi;
+                        const uint32_t rb = (row0 + bin) * per_row;
+                        lo[4 * h] = bk_off[rb + (kr0 & 0xFFu)];
+                        hi[4 * h] = bk_off[rb + (kr0 >> 8) + 1u];
+                        lo[4 * h + 1] = bk_off[rb + c.nkb + (kr1 & 0xFFu)];
+                        hi[4 * h + 1] = bk_off[rb + c.nkb + (kr1 >> 8) + 1u];
+                        lo[4 * h + 2] = bk_off[rb + 2u * c.nkb + (kr2 & 0xFFu)];
+                        hi[4 * h + 2] = bk_off[rb + 2u * c.nkb + (kr2 >> 8) + 1u];
+                        lo[4 * h + 3] = bk_off[rb + 3u * c.nkb];
+                        hi[4 * h + 3] = bk_off[rb + per_row];
+                    }
                 }
-                s_rng[wv][0][lane] = a0;
-                s_rng[wv][1][lane] = a1;
-                s_rng[wv][2][lane] = a2;
-                s_rng[wv][3][lane] = a3;
-                s_rng[wv][4][lane] = c1;
-                s_rng[wv][5][lane] = c2;
-                s_rng[wv][6][lane] = c3;
+#pragma unroll
+                for (int k = 0; k < 8; k++) {
+                    s_rng[wv][k][lane] = lo[k];
+                    T += hi[k] > lo[k] ? hi[k] - lo[k] : 0u;
+                    if (k < 7) s_rng[wv][8 + k][lane] = T;
+                }
             }
             wave_lds_sync();
             const uint32_t incl = wave_incl_scan(T);
@@ -1657,12 +1665,18 @@ __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Con
                 bool pass = false;
                 uint32_t obj = 0;
                 if (ci < total) {
+                    // range k of the owner's two bins: the last with cum[k] <= tt
                     const uint32_t tt = ci - o_off;
-                    const uint32_t c1 = s_rng[wv][4][o], c2 = s_rng[wv][5][o], c3 = s_rng[wv][6][o];
-                    const uint32_t i = tt < c1 ? s_rng[wv][0][o] + tt
-                                     : tt < c2 ? s_rng[wv][1][o] + (tt - c1)
-                                     : tt < c3 ? s_rng[wv][2][o] + (tt - c2)
-                                               : s_rng[wv][3][o] + (tt - c3);
+                    uint32_t k = 0, ck = 0;
+#pragma unroll
+                    for (int q = 0; q < 7; q++) {
+                        const uint32_t cum = s_rng[wv][8 + q][o];
+                        if (cum <= tt) {
+                            k = q + 1;
+                            ck = cum;
+                        }
+                    }
+                    const uint32_t i = s_rng[wv][k][o] + (tt - ck);
                     const float4 q = bks[i];
                     cand++;
                     float dphi = q.z - o_plo;
