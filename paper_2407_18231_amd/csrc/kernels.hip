@@ -1562,7 +1562,7 @@ __global__ __launch_bounds__(256) void k_road(const Batch b, const Totals *t, co
 }
 
 // Candidates: the 64 (seed, surface) units of a wave (one per lane) step
-// through the azimuth bins of their roads together.  For each bin a lane
+// through the azimuth bins of their roads together, two bins a step: a lane
 // loads the offsets of the four ranges of each of its next two bins (the
 // curvature range of each resolution class, and the wide objects; all
 // sixteen loads in flight together) and stores them in LDS; the wave
