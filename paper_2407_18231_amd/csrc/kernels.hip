@@ -177,6 +177,19 @@ __device__ inline uint32_t pair_slot(const uint32_t *s_off, uint32_t j, uint32_t
     return lo * subcap + (j - s_off[lo]);
 }
 
+// The entries of a list split into block regions (nsub regions of subcap
+// slots; soff[r + 1] - soff[r] entries filled in region r, from
+// k_sub_offsets): a block per region, its threads over the region's slots,
+// so no entry searches for its region.  For lists whose regions are even
+// (the seed-pair lists: every walk block took several tiles); the others
+// keep the dense grid-stride order with pair_slot, which balances uneven
+// regions.
+#define REGION_ENTRIES(i, soff, subcap, nsub)                                              \
+    for (uint32_t rg_ = blockIdx.x; rg_ < (nsub); rg_ += gridDim.x)                        \
+        for (uint32_t q_ = threadIdx.x, cnt_ = (soff)[rg_ + 1] - (soff)[rg_]; q_ < cnt_;   \
+             q_ += blockDim.x)                                                             \
+            for (uint32_t i = rg_ * (subcap) + q_, once_ = 1; once_; once_ = 0)
+
 // One increment of cnt[key] per active lane with one atomic per distinct
 // key of the wave: the lanes sharing a key are ranked by lane order behind
 // the first of them, whose single add covers them all (every lane of the
@@ -1744,18 +1757,13 @@ __global__ __launch_bounds__(256) void k_sub_offsets(const uint32_t *__restrict_
 template <int kKind>
 __global__ __launch_bounds__(256) void k_pt_eval(const Batch b, const Consts c, uint32_t nsub)
 {
-    __shared__ uint32_t s_off[kSubLists + 1];
     const uint32_t *soff = kKind == 0 ? b.ptc3_soff : b.ptc5_soff;
-    for (uint32_t i = threadIdx.x; i <= nsub; i += blockDim.x) s_off[i] = soff[i];
-    __syncthreads();
-    const uint32_t n = s_off[nsub];
     const uint32_t subcap = (kKind == 0 ? b.cap_ptc3 : b.cap_ptc5) / nsub;
     const uint32_t *cp = kKind == 0 ? b.ptc3_p : b.ptc5_p;
     const uint32_t *co = kKind == 0 ? b.ptc3_o : b.ptc5_o;
     uint32_t *rank = kKind == 0 ? b.ptc3_rank : b.ptc5_rank;
     uint32_t *pcnt = kKind == 0 ? b.pt3_cnt : b.pt5_cnt;
-    GRID_STRIDE(j, n) {
-        const uint32_t i = pair_slot(s_off, j, subcap, nsub);
+    REGION_ENTRIES(i, soff, subcap, nsub) {
         const uint32_t p = cp[i], o = co[i];
         uint32_t ia, io;
         float2 ks;
@@ -1779,11 +1787,7 @@ __global__ __launch_bounds__(256) void k_pt_eval(const Batch b, const Consts c, 
 template <int kKind>
 __global__ __launch_bounds__(256) void k_pt_place(const Batch b, uint32_t nsub)
 {
-    __shared__ uint32_t s_off[kSubLists + 1];
     const uint32_t *soff = kKind == 0 ? b.ptc3_soff : b.ptc5_soff;
-    for (uint32_t i = threadIdx.x; i <= nsub; i += blockDim.x) s_off[i] = soff[i];
-    __syncthreads();
-    const uint32_t n = s_off[nsub];
     const uint32_t subcap = (kKind == 0 ? b.cap_ptc3 : b.cap_ptc5) / nsub;
     const uint32_t *cp = kKind == 0 ? b.ptc3_p : b.ptc5_p;
     const uint32_t *co = kKind == 0 ? b.ptc3_o : b.ptc5_o;
@@ -1792,8 +1796,7 @@ __global__ __launch_bounds__(256) void k_pt_place(const Batch b, uint32_t nsub)
     uint32_t *tp = kKind == 0 ? b.pt3_tp : b.pt5_tp;
     uint32_t *to = kKind == 0 ? b.pt3_to : b.pt5_to;
     const uint32_t cap = kKind == 0 ? b.cap_pt3 : b.cap_pt5;
-    GRID_STRIDE(j, n) {
-        const uint32_t i = pair_slot(s_off, j, subcap, nsub);
+    REGION_ENTRIES(i, soff, subcap, nsub) {
         const uint32_t r = rank[i];
         if (r == kInvalid) continue;
         const uint32_t p = cp[i];
@@ -2023,9 +2026,9 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     L.launch("pt5c_walk", k_ptc<1>, gwalk, blk, b, t, c, nsub, stats);
     L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.ptc5_sub, b.ptc5_soff, b.cap_ptc5, nsub,
              &t->n_ptc5);
-    L.launch("pt5_eval", k_pt_eval<1>, grid_for(b.cap_ptc5), blk, b, c, nsub);
+    L.launch("pt5_eval", k_pt_eval<1>, dim3(nsub), blk, b, c, nsub);
     L.scan(b.pt5_cnt, b.pt5_off, &t->n_pls, b.cap_pls, &t->n_pt5, "scan_pt");
-    L.launch("pt_place", k_pt_place<1>, grid_for(b.cap_ptc5), blk, b, nsub);
+    L.launch("pt_place", k_pt_place<1>, dim3(nsub), blk, b, nsub);
     L.launch("zero8", k_zero_u8, grid_for(b.cap_t5), blk, b.t5_used, &t->n_t5, b.cap_t5);
     L.launch("pt_order", k_pt_order<1>, grid_for(b.cap_pt5), blk, b, (const Totals *)t);
 
@@ -2036,9 +2039,9 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     L.launch("pt3c_walk", k_ptc<0>, gwalk, blk, b, t, c, nsub, stats);
     L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.ptc3_sub, b.ptc3_soff, b.cap_ptc3, nsub,
              &t->n_ptc3);
-    L.launch("pt3_eval", k_pt_eval<0>, grid_for(b.cap_ptc3), blk, b, c, nsub);
+    L.launch("pt3_eval", k_pt_eval<0>, dim3(nsub), blk, b, c, nsub);
     L.scan(b.pt3_cnt, b.pt3_off, &t->n_pls, b.cap_pls, &t->n_pt3, "scan_pt");
-    L.launch("pt_place", k_pt_place<0>, grid_for(b.cap_ptc3), blk, b, nsub);
+    L.launch("pt_place", k_pt_place<0>, dim3(nsub), blk, b, nsub);
     L.launch("pt_order", k_pt_order<0>, grid_for(b.cap_pt3), blk, b, (const Totals *)t);
 
     // a8: track candidates, once both branches are done
