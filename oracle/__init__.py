@@ -107,6 +107,11 @@ def lib():
         L.or_kappa3.argtypes = [C.POINTER(_Geom), C.POINTER(_Params), C.POINTER(C.c_float)]
         L.or_kappa3.restype = C.c_float
         L.or_derived.argtypes = [C.POINTER(_Geom), C.POINTER(_Params), C.POINTER(C.c_float)]
+        L.or_kappa3_res.argtypes = [C.POINTER(_Geom), C.POINTER(_Params), C.POINTER(C.c_float),
+                                    C.POINTER(C.c_int), C.c_float, C.POINTER(C.c_float)]
+        L.or_pls_anchor.argtypes = [C.POINTER(_Params), C.POINTER(C.c_float), C.POINTER(C.c_float),
+                                    C.c_float, C.c_float, C.c_float, C.c_int, C.POINTER(C.c_double)]
+        L.or_pls_anchor.restype = C.c_int
         _lib = L
     return _lib
 
@@ -151,6 +156,30 @@ def kappa3(geom, xy, params: Params | None = None) -> float:
     g = _GeomHolder(geom); p = (params or Params()).c()
     a = np.ascontiguousarray(xy, dtype=np.float32)
     return float(lib().or_kappa3(C.byref(g.c), C.byref(p), _ptr(a, C.c_float)))
+
+
+def kappa3_res(geom, xy, disk=(0, 0, 0), r_c: float = 0.0, params: Params | None = None):
+    """(curvature, resolution) of three anchors (xy: 6 floats); disk[i] = 1
+    for an anchor on a disk, r_c the radius of the third anchor."""
+    g = _GeomHolder(geom); p = (params or Params()).c()
+    a = np.ascontiguousarray(xy, dtype=np.float32)
+    dk = (C.c_int * 3)(*[int(v) for v in disk])
+    out = np.zeros(2, np.float32)
+    lib().or_kappa3_res(C.byref(g.c), C.byref(p), _ptr(a, C.c_float), dk, float(r_c), _ptr(out, C.c_float))
+    return float(out[0]), float(out[1])
+
+
+def pls_anchor(par, cov, x, y, z, disk=False, params: Params | None = None):
+    """One pixel-seed anchor test: (code, azimuth difference, its window,
+    coarse deviation, its window); code 0 = evaluated, 1 = helix does not
+    reach the radius, 2 = no disk prediction."""
+    p = (params or Params()).c()
+    pa = np.ascontiguousarray(par, dtype=np.float32)
+    cv = np.ascontiguousarray(cov, dtype=np.float32)
+    out = np.zeros(4, np.float64)
+    code = lib().or_pls_anchor(C.byref(p), _ptr(pa, C.c_float), _ptr(cv, C.c_float),
+                               float(x), float(y), float(z), int(bool(disk)), _ptr(out, C.c_double))
+    return (int(code),) + tuple(float(v) for v in out)
 
 
 def derived(geom, params: Params | None = None) -> np.ndarray:
@@ -229,6 +258,28 @@ def keyed(res: dict) -> dict:
         for k, s in zip(ks[name], st):
             d[k] = d.get(k, 0) | int(s)
         out[name] = d
+    return out
+
+
+def flag_breakdown(res: dict) -> dict:
+    """Per stage: (objects kept, flagged, flagged by the object's own cut
+    margin).  An object is flagged by its own margin when it is flagged and
+    none of its constituents (MDs of a segment, segments of a T3, T3s of a
+    T5, the T3 / T5 of a pT3 / pT5) is; the rest inherit the flag."""
+    fl = {k: (res[k + "_st"] & ST_FLAG) > 0 for k in _OBJ}
+    inherited = {
+        "md": np.zeros(len(fl["md"]), bool),
+        "ls": fl["md"][res["ls"][:, 0]] | fl["md"][res["ls"][:, 1]] if len(res["ls"]) else np.zeros(0, bool),
+        "t3": fl["ls"][res["t3"][:, 0]] | fl["ls"][res["t3"][:, 1]] if len(res["t3"]) else np.zeros(0, bool),
+        "t5": fl["t3"][res["t5"][:, 0]] | fl["t3"][res["t5"][:, 1]] if len(res["t5"]) else np.zeros(0, bool),
+        "pt3": fl["t3"][res["pt3"][:, 1]] if len(res["pt3"]) else np.zeros(0, bool),
+        "pt5": fl["t5"][res["pt5"][:, 1]] if len(res["pt5"]) else np.zeros(0, bool),
+    }
+    out = {}
+    for k in _OBJ:
+        f = fl[k]
+        own = f & ~inherited[k] if k in inherited else np.zeros(len(f), bool)
+        out[k] = (len(f), int(f.sum()), int(own.sum()))
     return out
 
 

@@ -437,6 +437,51 @@ static verdict t5_cut(const derived *d, const anchor *A, const anchor *C, const 
     return s;
 }
 
+/* One anchor of a pixel seed (binary64): the azimuth difference between the
+   anchor and the seed's helix at the anchor's radius, its window, and the
+   deviation along the coarse coordinate (z at a barrel anchor, r at a disk
+   anchor) with its window.  Returns 0 when both tests can be evaluated, 1
+   when the helix does not reach the anchor's radius (|r kappa / 2| >= 1), 2
+   when the disk prediction is undefined (cot(theta) = 0, plane behind the
+   seed, or a turning angle of pi or more). */
+static int p_anchor(const or_params *pp, double kp, double skp, const float *par, const float *cov,
+                    const anchor *a, double out[4])
+{
+    double ns = pp->n_sigma;
+    double phi0 = par[1], cot = par[2], z0 = par[4];
+    double s11 = sqrt((double)cov[5]), s22 = sqrt((double)cov[9]), s44 = sqrt((double)cov[14]);
+    double x = a->x, y = a->y, z = a->z;
+    double r = sqrt(x * x + y * y);
+    double u = r * kp / 2.0;
+    if (!(fabs(u) < 1.0)) return 1;
+    /* azimuth of the helix at radius r: phi0 minus half the turning angle */
+    double dphi = atan2(y, x) - (phi0 - asin(u));
+    dphi = fmod(dphi + OR_PI, 2.0 * OR_PI);
+    if (dphi < 0.0) dphi += 2.0 * OR_PI;
+    dphi -= OR_PI;
+    double sr = a->disk ? pp->sig_c : 0.0;
+    out[0] = dphi;
+    out[1] = ns * (s11 + (r * skp + sr * fabs(kp)) / (2.0 * sqrt(1.0 - u * u)) + pp->sig_rphi / r);
+    if (!a->disk) {
+        /* z after the transverse arc length s(r) */
+        double sa = (u == 0.0) ? r : r * asin(u) / u;
+        double zp = z0 + cot * sa;
+        out[2] = z - zp;
+        out[3] = ns * (s44 + sa * s22 + pp->sig_c);
+        return 0;
+    }
+    /* radius where the helix crosses the anchor's plane */
+    if (cot == 0.0) return 2;
+    double sa = (z - z0) / cot;
+    if (!(sa > 0.0)) return 2;
+    double w = fabs(kp) * sa / 2.0;
+    if (!(w < OR_PI / 2)) return 2;
+    double rp = (w == 0.0) ? sa : sa * sin(w) / w;
+    out[2] = r - rp;
+    out[3] = ns * ((s44 + sa * s22) / fabs(cot) + pp->sig_c);
+    return 0;
+}
+
 /* pixel seed p against an object with curvature kobj (+/- skobj) and inner /
    outer anchors; binary64 throughout */
 static verdict p_cut(const or_params *pp, const float *par, const float *cov,
@@ -449,34 +494,14 @@ static verdict p_cut(const or_params *pp, const float *par, const float *cov,
     chkd(&s, fabs(kp - (double)kobj), ns * (skp + (double)skobj));
     if (s.hard) return s;
     const anchor *an[2] = {in, out};
-    double phi0 = par[1], cot = par[2], z0 = par[4];
-    double s11 = sqrt((double)cov[5]), s22 = sqrt((double)cov[9]), s44 = sqrt((double)cov[14]);
     for (int i = 0; i < 2; i++) {
-        double x = an[i]->x, y = an[i]->y, z = an[i]->z;
-        double r = sqrt(x * x + y * y);
-        double u = r * kp / 2.0;
-        if (!(fabs(u) < 1.0)) { s.hard = 1; return s; }
-        double dphi = atan2(y, x) - (phi0 - asin(u));
-        dphi = fmod(dphi + OR_PI, 2.0 * OR_PI);
-        if (dphi < 0.0) dphi += 2.0 * OR_PI;
-        dphi -= OR_PI;
-        double sr = an[i]->disk ? pp->sig_c : 0.0;
-        double W = ns * (s11 + (r * skp + sr * fabs(kp)) / (2.0 * sqrt(1.0 - u * u)) + pp->sig_rphi / r);
-        chkd(&s, fabs(dphi), W);
+        double v[4];
+        int code = p_anchor(pp, kp, skp, par, cov, an[i], v);
+        if (code == 1) { s.hard = 1; return s; }
+        chkd(&s, fabs(v[0]), v[1]);
         if (s.hard) return s;
-        if (!an[i]->disk) {
-            double sa = (u == 0.0) ? r : r * asin(u) / u;
-            double zp = z0 + cot * sa;
-            chkd(&s, fabs(z - zp), ns * (s44 + sa * s22 + pp->sig_c));
-        } else {
-            if (cot == 0.0) { s.hard = 1; return s; }
-            double sa = (z - z0) / cot;
-            if (!(sa > 0.0)) { s.hard = 1; return s; }
-            double w = fabs(kp) * sa / 2.0;
-            if (!(w < OR_PI / 2)) { s.hard = 1; return s; }
-            double rp = (w == 0.0) ? sa : sa * sin(w) / w;
-            chkd(&s, fabs(r - rp), ns * ((s44 + sa * s22) / fabs(cot) + pp->sig_c));
-        }
+        if (code == 2) { s.hard = 1; return s; }
+        chkd(&s, fabs(v[2]), v[3]);
         if (s.hard) return s;
     }
     return s;
@@ -736,4 +761,28 @@ void or_derived(const or_geom *g, const or_params *p, float out[8])
     derived d; derive(g, p, &d);
     out[0] = d.L; out[1] = d.ec; out[2] = d.kmaxf; out[3] = d.khalf;
     out[4] = d.ns; out[5] = d.srp; out[6] = d.sc; out[7] = d.Kb;
+}
+
+/* curvature and resolution of three anchors; disk[i] = 1 for an anchor on a
+   disk, rC the radius of the third anchor */
+void or_kappa3_res(const or_geom *g, const or_params *p, const float xy[6], const int disk[3], float rC,
+                   float out[2])
+{
+    derived d; derive(g, p, &d);
+    float k, sk, d1, d2;
+    kappa3(&d, xy[0], xy[1], disk[0], xy[2], xy[3], disk[1], xy[4], xy[5], rC, disk[2], &k, &sk, &d1, &d2);
+    out[0] = k; out[1] = sk;
+}
+
+/* one pixel-seed anchor test (see p_anchor): out = (azimuth difference, its
+   window, coarse deviation, its window); returns p_anchor's code */
+int or_pls_anchor(const or_params *p, const float par[5], const float cov[15],
+                  float x, float y, float z, int disk, double out[4])
+{
+    double kB = 0.299792458e-2 * p->B;
+    double kp = (double)par[0] * kB;
+    double skp = kB * sqrt((double)cov[0]);
+    anchor a = {x, y, z, sqrtf(x * x + y * y), disk};
+    out[0] = out[1] = out[2] = out[3] = 0.0;
+    return p_anchor(p, kp, skp, par, cov, &a, out);
 }

@@ -13,7 +13,12 @@
   set of combinations computed here with numpy;
 * invariants of the chain and of the track-candidate partition;
 * pixel-seed linking: exact seeds link to their own track's T3/T5 and stop
-  linking when charge or direction is changed.
+  linking when charge or direction is changed;
+* the flagged fraction: candidates within 1e-5 relative of a cut boundary,
+  per stage, over sixteen PU200-like events.
+
+The window constants are pinned one by one against helix geometry in
+test_oracle_windows.py.
 """
 import math
 import os
@@ -62,19 +67,6 @@ def test_window_constants_closed_form():
     close("kappa_max", oracle.derived(g, p0)[2])
     # resolution terms widen the windows
     assert oracle.module_const(g, L0)[0] > oracle.module_const(g, L0, p0)[0]
-
-
-def test_bend_ratio_monotone_in_curvature():
-    """The bend-consistency window uses lambda(kappa) only at kappa = 0 and
-    kappa_max; it is valid because lambda is monotone in between."""
-    kmax = 0.299792458e-2 * 3.8 / 0.8
-    for Ra, Rb in zip(s.BARREL_RADII[:-1], s.BARREL_RADII[1:]):
-        a, b, ah = Ra - 0.13, Rb - 0.13, Ra + 0.13
-        ks = np.linspace(1e-9, kmax, 400)
-        A = lambda r: np.arcsin(r * ks / 2)
-        lam = np.sin(A(b) - A(a)) / np.sin(A(ah) - A(a))
-        assert np.all(np.diff(lam) > 0)
-        assert abs(lam[0] - (b - a) / 0.26) < 1e-4 * lam[0]
 
 
 def _eff(g, ev, mask, params=None):
@@ -319,9 +311,31 @@ def test_pixel_seed_linking():
 
 
 def test_flagged_fraction_small(pu200_result):
-    """Borderline candidates (within 1e-5 relative of a cut boundary) are rare."""
+    """One PU200-like event: candidates flagged by their own cut margin
+    (within 1e-5 relative of a boundary) stay below 3e-4 of each stage's
+    objects (a single event fluctuates around the 16-event figure below)."""
     g, ev, r = pu200_result
-    for k in ("md", "ls", "t3", "t5", "pt3", "pt5"):
-        st = r[k + "_st"]
-        nflag = int((st & oracle.ST_FLAG).sum())
-        assert nflag <= max(2, 1e-3 * len(st)), (k, nflag, len(st))
+    for k, (n, nflag, own) in oracle.flag_breakdown(r).items():
+        assert own <= max(3, 3e-4 * n), (k, own, n)
+        assert nflag <= max(5, 6e-4 * n), (k, nflag, n)
+
+
+def test_flagged_fraction_bar_16_events():
+    """Sixteen PU200-like events (the benchmark's seeds): per stage, the
+    candidates flagged by their own cut margin are at most 1e-4 of the
+    stage's objects; with the objects that only inherit a flag from a
+    constituent (segments of a flagged MD, T3s of a flagged segment ...),
+    at most 2.5e-4.  Measured: MD 2.3e-5, LS 9.8e-5 (1.8e-4 with inherited
+    flags), T3 1.9e-5 (1.7e-4), none in T5, pT3, pT5 and TC."""
+    g = s.make_geometry("pu200")
+    tot = {}
+    for i in range(16):
+        ev = s.gen_event(g, s.config_pu(200), 2000 + i)
+        for k, v in oracle.flag_breakdown(oracle.run(g, ev)).items():
+            a = tot.setdefault(k, [0, 0, 0])
+            for j in range(3):
+                a[j] += v[j]
+    for k, (n, nflag, own) in tot.items():
+        assert n > 1000, k
+        assert own <= 1e-4 * n, (k, own, n)
+        assert nflag <= 2.5e-4 * n, (k, nflag, n)
