@@ -49,6 +49,7 @@ typedef int32_t lst_status;
 #define LST_ERR_TOO_LARGE -8
 #define LST_ERR_QUEUE_FULL -9
 #define LST_ERR_UNKNOWN_TICKET -10
+#define LST_ERR_HIT_OUTSIDE -11   /* a hit breaks the input contract of lst_event_in */
 
 typedef struct lst_ctx lst_ctx;
 
@@ -75,9 +76,31 @@ typedef struct {
      * paper_2407_18231_amd.tune picks them by measurement. */
     uint32_t n_phi_bins;
     uint32_t n_kappa_bins;
+    /* hipStream_t the per-event and batched paths (lst_run_event,
+     * lst_run_batch, lst_batch_*) enqueue their work on; NULL: a stream of the
+     * library's own.  Borrowed: it must outlive the context and is never
+     * destroyed by the library; the calls still return only once their work
+     * on it is complete.  The served path always uses its own streams. */
+    void *stream;
 } lst_params;
 
 #define LST_FLAG_BEND 1u     /* line segments: MD bend consistent with the segment's (barrel pairs) */
+/* lst_run_event / lst_run_batch fill lst_event_out.stage_ns: the chain then
+ * runs on one stream with a HIP event pair around every launch (slower; for
+ * diagnosis).  Without it stage_ns is all zero. */
+#define LST_FLAG_STAGE_TIMES 2u
+
+/* Stages of the chain (Sec. 1: hits -> MD -> LS -> T3 -> T5; pLS linked into
+ * pT3 / pT5; track candidates), the index of each in stage_ns */
+#define LST_STAGE_INGEST 0       /* validation and sort of the hits by (module, sensor) */
+#define LST_STAGE_MD 1
+#define LST_STAGE_LS 2
+#define LST_STAGE_T3 3
+#define LST_STAGE_T5 4
+#define LST_STAGE_SEED_LOOKUP 5  /* seed quantities, roads, object buckets, seed-object candidate walk */
+#define LST_STAGE_PT 6           /* seed cuts of the candidate pairs, pT3 / pT5 lists */
+#define LST_STAGE_TC 7
+#define LST_N_STAGES 8
 
 /* One double-sensor module.  Modules must be listed with consecutive ids
  * 0..n-1 in this array.  Barrel modules are cylinder patches, endcap modules
@@ -96,9 +119,23 @@ typedef struct {
 #define LST_BARREL 0u
 #define LST_ENDCAP 1u
 
-/* Input of one event.  Host pointers unless flags & LST_DEVICE_PTRS (device
- * pointers, e.g. from torch tensors on the context's device).  Borrowed for
- * the duration of the call (lst_submit copies them before returning). */
+/* Input of one event: the hits of the outer tracker and the inner-tracker
+ * seeds (Sec. 1: outer-tracker hits are the input, and the objects built from
+ * them are linked to inner-tracker tracks).  Host pointers unless flags &
+ * LST_DEVICE_PTRS (device pointers, e.g. from torch tensors on the context's
+ * device).  Borrowed for the duration of the call (lst_submit copies them
+ * before returning).
+ *
+ * Input contract, checked for every hit at ingest (LST_ERR_HIT_OUTSIDE
+ * otherwise; BAD_MODULE for a module id >= n or sensor > 1, NONFINITE for a
+ * NaN or infinite coordinate or seed value): the hit lies on its sensor --
+ * radius (barrel) or plane z (endcap) within 0.008 cm of that sensor's
+ * s_lo / s_hi -- and inside its module's extent widened by 5.5 resolutions:
+ * z (barrel) or r (endcap) within [c_min - 5.5 sig_c, c_max + 5.5 sig_c],
+ * azimuth within [phi_min - w, phi_max + w] with w = 5.5 sig_rphi over the
+ * module's inner radius.  The connection map and the seed roads cover hits up
+ * to 6 resolutions out, so every hit that passes the check is searched as
+ * widely as a search without the map would. */
 typedef struct {
     uint32_t n_hits;
     uint32_t n_pls;
@@ -119,8 +156,9 @@ typedef struct {
 #define LST_TC_T5 2u
 #define LST_TC_PLS 3u
 
-/* Result of one event, owned by the library (free with lst_free_output).
- * Pairs are stored flat: element 2*i and 2*i+1. */
+/* Result of one event, owned by the library (free with lst_free_output):
+ * the objects of every stage and the track candidates (Sec. 1, list of
+ * propagated objects).  Pairs are stored flat: element 2*i and 2*i+1. */
 typedef struct {
     uint32_t n_md, n_ls, n_t3, n_t5, n_pt3, n_pt5, n_tc;
     uint32_t status;         /* lst_status of this event (served path) */
@@ -134,6 +172,17 @@ typedef struct {
     float *t3_kappa;         /* signed transverse curvature of each T3 [1/cm] */
     double latency_us;       /* served path: completion minus submission */
     uint64_t ticket;
+    /* times the chain was re-run with larger object lists because one
+     * overflowed (regrow and re-run; 0 when the first run fit) */
+    uint32_t n_flag_regrow;
+    uint32_t n_stage;        /* LST_N_STAGES */
+    /* with LST_FLAG_STAGE_TIMES: device nanoseconds per stage (LST_STAGE_*)
+     * of the launch that produced this event -- for a batch, of the whole
+     * batch; their sum does not exceed the call's duration */
+    uint64_t stage_ns[LST_N_STAGES];
+    uint32_t batch_events;   /* events in the launch that produced this output */
+    uint32_t pad;
+    uint64_t footprint;      /* served path: predicted device bytes the event was admitted with */
 } lst_event_out;
 
 void lst_default_params(lst_params *p);
@@ -162,22 +211,37 @@ lst_status lst_build_connection_map(const lst_params *p, const lst_module_desc *
                                     uint32_t **begin, uint32_t **dst, uint32_t *n_edges);
 void lst_free_map(uint32_t *begin, uint32_t *dst);
 
-/* Run one event synchronously (the plain per-event path).  *out is allocated
- * by the library.  Errors: NO_GEOMETRY, BAD_MODULE (module id out of range or
- * sensor > 1), NONFINITE (NaN/inf coordinate or seed parameter), OOM,
- * TOO_LARGE (event above the device memory budget), DEVICE. */
+/* Run one event synchronously (the plain per-event path): hits and seeds in,
+ * the object lists of every stage and the track candidates out (Sec. 1: the
+ * candidates either combine a seed with outer-tracker objects or use the
+ * outer tracker alone).  *out is allocated by the library.
+ * Errors: NO_GEOMETRY, BAD_MODULE (module id out of range or sensor > 1),
+ * NONFINITE (NaN/inf coordinate or seed parameter), HIT_OUTSIDE (a hit
+ * breaks the input contract), OOM, TOO_LARGE (event above the device memory
+ * budget), DEVICE. */
 lst_status lst_run_event(lst_ctx *ctx, const lst_event_in *ev, lst_event_out **out);
 
 /* Run n events in one launch of the chain (the batched path); outs[i] receives
- * event i.  Same errors as lst_run_event; INVALID_ARG if n > max_batch. */
+ * event i.  Every object of a stage depends only on objects of its own event
+ * (Sec. 1: objects of one kind are built independently, so they can be
+ * created concurrently), so a batch is one flat index space and each output
+ * equals the event's lst_run_event output.  Same errors as lst_run_event
+ * (an input error in any event fails the call); INVALID_ARG if
+ * n > max_batch. */
 lst_status lst_run_batch(lst_ctx *ctx, const lst_event_in *evs, uint32_t n, lst_event_out **outs);
 
 /* Served path.  lst_submit copies the event and returns a ticket at once;
  * a scheduler admits waiting events into free device slots by their predicted
  * device-memory footprint, forms micro-batches and runs them on parallel
- * streams.  lst_poll returns LST_OK and hands over the output once (the ticket
+ * streams (the paper's throughput runs keep two streams of events on one GPU,
+ * Sec. 3).  lst_poll returns LST_OK and hands over the output once (the ticket
  * is then consumed) or LST_PENDING; timeout_us = 0 does not wait, -1 waits.
- * Errors: QUEUE_FULL, TOO_LARGE, UNKNOWN_TICKET, DEVICE, input errors. */
+ * An input error fails only its own ticket (lst_poll returns the error);
+ * the other events of its micro-batch are unaffected.
+ * Errors: lst_submit: QUEUE_FULL (queue_depth events waiting or in flight),
+ * TOO_LARGE (predicted footprint above mem_budget), INVALID_ARG (device
+ * pointers); lst_poll: UNKNOWN_TICKET, DEVICE, the input errors of
+ * lst_run_event. */
 lst_status lst_submit(lst_ctx *ctx, const lst_event_in *ev, uint64_t *ticket);
 lst_status lst_poll(lst_ctx *ctx, uint64_t ticket, int64_t timeout_us, lst_event_out **out);
 

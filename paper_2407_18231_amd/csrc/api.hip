@@ -183,6 +183,7 @@ void carve_work(Carver &cv, Batch &b, uint32_t n_mod, uint32_t n_surf, uint32_t 
     b.tc_type = cv.take<uint32_t>(tcu);
     b.tc_idx = cv.take<uint32_t>(tcu);
     b.ev_tab = cv.take<uint32_t>(((size_t)b.cap_ev + 1) * kEvTabCols);
+    b.ev_err = cv.take<uint32_t>((size_t)b.cap_ev + 1);
 }
 
 }  // namespace
@@ -209,6 +210,9 @@ struct Slot {
     uint32_t n_ev = 0;
     std::vector<uint32_t> hit_off, pls_off;
     hipEvent_t done = nullptr;
+    bool own_stream = true;          // false: the caller's stream (lst_params.stream), not destroyed here
+    uint32_t n_regrow = 0;           // re-runs of the last batch after an overflow
+    uint64_t stage_ns[LST_N_STAGES] = {};   // stage times of the last batch (stage timing only)
     std::vector<uint64_t> tickets;   // served path
     std::vector<std::chrono::steady_clock::time_point> t_submit;
 };
@@ -304,14 +308,19 @@ void destroy_slot(Slot &s)
     for (hipEvent_t e : s.L.ev_join) if (e) (void)hipEventDestroy(e);
     if (s.done) (void)hipEventDestroy(s.done);
     if (s.side) (void)hipStreamDestroy(s.side);
-    if (s.stream) (void)hipStreamDestroy(s.stream);
+    if (s.stream && s.own_stream) (void)hipStreamDestroy(s.stream);
 }
 
-lst_status make_slot(lst_ctx *ctx, std::unique_ptr<Slot> &out)
+lst_status make_slot(lst_ctx *ctx, std::unique_ptr<Slot> &out, hipStream_t caller = nullptr)
 {
     auto s = std::make_unique<Slot>();
     s->device = ctx->device;
-    HIP_TRY(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+    if (caller) {
+        s->stream = caller;
+        s->own_stream = false;
+    } else {
+        HIP_TRY(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+    }
     HIP_TRY(hipMalloc(&s->d_tot, sizeof(lst::Totals)));
     HIP_TRY(hipHostMalloc((void **)&s->h_tot, sizeof(lst::Totals), hipHostMallocDefault));
     HIP_TRY(hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking));
@@ -342,6 +351,9 @@ lst_status ensure_inputs(lst_ctx *ctx, Slot &s, uint32_t n_ev, uint64_t hits, ui
     c.md = std::max(c.md, b.cap_md); c.ls = std::max(c.ls, b.cap_ls); c.t3 = std::max(c.t3, b.cap_t3);
     c.t5 = std::max(c.t5, b.cap_t5); c.pt3 = std::max(c.pt3, b.cap_pt3); c.pt5 = std::max(c.pt5, b.cap_pt5);
     c.ptc3 = std::max(c.ptc3, b.cap_ptc3); c.ptc5 = std::max(c.ptc5, b.cap_ptc5);
+    // (seed, surface) units are 32-bit indices on the device
+    if ((uint64_t)std::max<uint32_t>(c.pls, 1) * ctx->geom.c.n_surf > 0xFFFFFFF0ull)
+        return set_err(ctx, LST_ERR_TOO_LARGE, "too many seeds for 32-bit (seed, surface) indexing");
     free_slot_arenas(s);
     b.cap_ev = c.ev; b.cap_hits = std::max<uint32_t>(c.hits, 1); b.cap_pls = std::max<uint32_t>(c.pls, 1);
     b.cap_md = c.md; b.cap_ls = c.ls; b.cap_t3 = c.t3; b.cap_t5 = c.t5; b.cap_pt3 = c.pt3; b.cap_pt5 = c.pt5;
@@ -526,38 +538,65 @@ int overflowed(Slot &s)
     return g ? 1 : 0;
 }
 
-lst_status finish_run(lst_ctx *ctx, Slot &s, bool stats)
+// Elapsed times of the timed launches since the last drain: per launch name
+// into the context's kernel table, per stage into the slot's stage times.
+void drain_records(lst_ctx *ctx, Slot &s)
 {
-    HIP_TRY(hipMemcpyAsync(s.h_tot, s.d_tot, sizeof(lst::Totals), hipMemcpyDeviceToHost, s.stream));
-    HIP_TRY(hipStreamSynchronize(s.stream));
-    (void)stats;
-    if (s.L.timing) {
-        for (auto &r : s.L.recs) {
-            float ms = 0.f;
-            if (hipEventElapsedTime(&ms, r.second.first, r.second.second) == hipSuccess) {
-                auto &kt = ctx->ktimes[r.first];
-                kt.first += ms;
-                kt.second += 1;
-            }
+    for (auto &r : s.L.recs) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.e0, r.e1) == hipSuccess) {
+            auto &kt = ctx->ktimes[r.name];
+            kt.first += ms;
+            kt.second += 1;
+            if (r.stage >= 0 && r.stage < LST_N_STAGES) s.stage_ns[r.stage] += (uint64_t)(ms * 1e6 + 0.5);
         }
-        s.L.recs.clear();
-        s.L.used = 0;
     }
-    if (s.h_tot->err & lst::kErrBadModule) return set_err(ctx, LST_ERR_BAD_MODULE, "hit with module id out of range or sensor > 1");
-    if (s.h_tot->err & lst::kErrNonFinite) return set_err(ctx, LST_ERR_NONFINITE, "non-finite hit coordinate or seed parameter");
+    s.L.recs.clear();
+    s.L.used = 0;
+}
+
+lst_status input_error(lst_ctx *ctx, uint32_t bits)
+{
+    if (bits & lst::kErrBadModule) return set_err(ctx, LST_ERR_BAD_MODULE, "hit with module id out of range or sensor > 1");
+    if (bits & lst::kErrNonFinite) return set_err(ctx, LST_ERR_NONFINITE, "non-finite hit coordinate or seed parameter");
+    if (bits & lst::kErrOutside)
+        return set_err(ctx, LST_ERR_HIT_OUTSIDE, "hit off its sensor or outside its module's extent (input contract)");
     return LST_OK;
 }
 
-// Run the staged batch to completion, growing arenas on overflow.
-lst_status run_staged(lst_ctx *ctx, Slot &s, bool use_graph, bool timing, bool stats)
+// After the chain: fetch the counters (and the stage times of a timed run).
+// batch_errors: an input error of any event fails the batch; otherwise input
+// errors are left to the per-event status (served path).
+lst_status finish_run(lst_ctx *ctx, Slot &s, bool batch_errors)
 {
+    HIP_TRY(hipMemcpyAsync(s.h_tot, s.d_tot, sizeof(lst::Totals), hipMemcpyDeviceToHost, s.stream));
+    HIP_TRY(hipStreamSynchronize(s.stream));
+    if (s.L.timing) drain_records(ctx, s);
+    if (batch_errors) return input_error(ctx, s.h_tot->err);
+    return LST_OK;
+}
+
+// Run the staged batch to completion, growing arenas on overflow.  With
+// stage_times the chain runs eagerly on the slot's stream alone, every launch
+// timed.
+lst_status run_staged(lst_ctx *ctx, Slot &s, bool use_graph, bool stage_times, bool batch_errors)
+{
+    s.n_regrow = 0;
+    hipStream_t side = s.L.side;
     for (int attempt = 0; attempt < 12; attempt++) {
-        lst_status st = enqueue(ctx, s, use_graph, timing, stats);
-        if (st != LST_OK) return st;
-        st = finish_run(ctx, s, stats);
+        std::memset(s.stage_ns, 0, sizeof s.stage_ns);
+        if (stage_times) {
+            s.L.side = nullptr;
+            s.L.only = nullptr;
+        }
+        lst_status st = enqueue(ctx, s, use_graph && !stage_times, stage_times, false);
+        if (st == LST_OK) st = finish_run(ctx, s, batch_errors);
+        s.L.side = side;
+        s.L.timing = false;
         if (st != LST_OK) return st;
         if (!overflowed(s)) return LST_OK;
         // grow the work arena; staged inputs stay valid
+        s.n_regrow++;
         if (s.gexec) { (void)hipGraphExecDestroy(s.gexec); s.gexec = nullptr; }
         if (s.graph) { (void)hipGraphDestroy(s.graph); s.graph = nullptr; }
         s.graph_valid = false;
@@ -568,7 +607,6 @@ lst_status run_staged(lst_ctx *ctx, Slot &s, bool use_graph, bool timing, bool s
     return set_err(ctx, LST_ERR_OOM, "object lists kept overflowing");
 }
 
-// Copy the results of the staged batch to host memory, one output per event.
 // Copy the results of the staged batch to host memory, one output per event:
 // one pinned landing buffer per slot, then per-event assembly (on several
 // host threads for larger batches).
@@ -606,6 +644,19 @@ lst_status download(lst_ctx *ctx, Slot &s, lst_event_out **outs)
     std::vector<int> failed(n, 0);
     auto build = [&](uint32_t e) {
         const uint32_t *r0 = &tab[(size_t)e * lst::kEvTabCols], *r1 = r0 + lst::kEvTabCols;
+        if (r0[11]) {
+            // an input error of this event: its status only, no lists
+            lst_event_out *o = (lst_event_out *)std::calloc(1, sizeof(lst_event_out));
+            if (!o) { failed[e] = 1; return; }
+            o->status = (uint32_t)(r0[11] & lst::kErrBadModule ? LST_ERR_BAD_MODULE
+                                   : r0[11] & lst::kErrNonFinite ? LST_ERR_NONFINITE
+                                                                 : LST_ERR_HIT_OUTSIDE);
+            o->n_flag_regrow = s.n_regrow;
+            o->n_stage = LST_N_STAGES;
+            o->batch_events = n;
+            outs[e] = o;
+            return;
+        }
         const uint32_t pls0 = r0[1], md0 = r0[2], ls0 = r0[3], t30 = r0[4], t50 = r0[5], p30 = r0[6], p50 = r0[7];
         const uint32_t cmd = r1[2] - md0, cls = r1[3] - ls0, ct3 = r1[4] - t30, ct5 = r1[5] - t50;
         const uint32_t cp3 = r1[6] - p30, cp5 = r1[7] - p50;
@@ -642,6 +693,10 @@ lst_status download(lst_ctx *ctx, Slot &s, lst_event_out **outs)
         for (uint32_t i = r0[9]; i < r1[9]; i++) { o->tc[2 * k] = tty[i]; o->tc[2 * k + 1] = tix[i] - t50; k++; }
         for (uint32_t i = r0[10]; i < r1[10]; i++) { o->tc[2 * k] = tty[i]; o->tc[2 * k + 1] = tix[i] - pls0; k++; }
         o->status = LST_OK;
+        o->n_flag_regrow = s.n_regrow;
+        o->n_stage = LST_N_STAGES;
+        std::memcpy(o->stage_ns, s.stage_ns, sizeof o->stage_ns);
+        o->batch_events = n;
         outs[e] = o;
     };
     const uint32_t n_threads = std::min<uint32_t>(n >= 4 ? 8u : 1u, n);
@@ -669,7 +724,7 @@ lst_status check_ctx(lst_ctx *ctx, bool need_geom)
 lst_status ensure_plain(lst_ctx *ctx)
 {
     if (ctx->plain) return LST_OK;
-    return make_slot(ctx, ctx->plain);
+    return make_slot(ctx, ctx->plain, (hipStream_t)ctx->p.stream);
 }
 
 }  // namespace
@@ -716,6 +771,7 @@ void worker_main(lst_ctx *ctx)
             if (hipEventQuery(s.done) == hipErrorNotReady) continue;
             lk.unlock();
             lst_status st = finish_run(ctx, s, false);
+            s.n_regrow = 0;
             std::vector<lst_event_out *> outs(s.n_ev, nullptr);
             if (st == LST_OK && overflowed(s)) {
                 if (s.work_arena) { (void)hipFree(s.work_arena); s.work_arena = nullptr; }
@@ -723,7 +779,10 @@ void worker_main(lst_ctx *ctx)
                 if (s.graph) { (void)hipGraphDestroy(s.graph); s.graph = nullptr; }
                 s.graph_valid = false;
                 st = ensure_work(ctx, s);
-                if (st == LST_OK) st = run_staged(ctx, s, true, false, false);
+                if (st == LST_OK) {
+                    st = run_staged(ctx, s, true, false, false);
+                    s.n_regrow++;
+                }
             }
             if (st == LST_OK) st = download(ctx, s, outs.data());
             auto now = std::chrono::steady_clock::now();
@@ -736,6 +795,7 @@ void worker_main(lst_ctx *ctx)
                 }
                 if (o) {
                     o->ticket = s.tickets[e];
+                    o->footprint = e < held[i].size() ? held[i][e]->footprint : 0;
                     o->latency_us = std::chrono::duration<double, std::micro>(now - s.t_submit[e]).count();
                 }
                 ctx->finished[s.tickets[e]] = o;
@@ -759,8 +819,10 @@ void worker_main(lst_ctx *ctx)
             uint64_t mem = 0;
             const uint64_t budget = ctx->p.mem_budget ? ctx->p.mem_budget : (32ull << 30);
             while (!ctx->waiting.empty() && take.size() < ctx->p.max_batch) {
+                // every admitted event fits the budget with what is in flight
+                // (an event alone always fits: submit refuses larger ones)
                 uint64_t f = ctx->waiting.front()->footprint;
-                if (!take.empty() && ctx->mem_in_use + mem + f > budget) break;
+                if (ctx->mem_in_use + mem + f > budget) break;
                 mem += f;
                 take.push_back(std::move(ctx->waiting.front()));
                 ctx->waiting.pop_front();
@@ -877,6 +939,32 @@ lst_status lst_load_geometry(lst_ctx *ctx, const lst_module_desc *m, uint32_t n)
     std::string err;
     st = lst::build_geometry(ctx->p, m, n, geom, err);
     if (st != LST_OK) return set_err(ctx, st, err);
+    // every bin, unit and bucket index of a batch of max_batch events is a
+    // 32-bit number on the device
+    {
+        const lst::Consts &k = geom.c;
+        const uint64_t bins = (uint64_t)ctx->p.max_batch * 2u * k.n_mod + 1u;
+        const uint64_t bk = (uint64_t)ctx->p.max_batch * k.n_surf * k.nphi * (3u * k.nkb + 1u) + 1u;
+        if (bins > 0xFFFFFFF0ull || bk > 0xFFFFFFF0ull)
+            return set_err(ctx, LST_ERR_INVALID_ARG,
+                           "max_batch x modules or x seed-lookup buckets exceeds 32-bit indexing");
+    }
+    // the served slots and the staged batch of the plain path hold arenas
+    // sized for the old geometry: refuse while served events are in flight,
+    // otherwise wait for the streams and drop the staged batch
+    std::lock_guard<std::mutex> q(ctx->q_mu);
+    if (ctx->in_system > 0)
+        return set_err(ctx, LST_ERR_INVALID_ARG, "served events in flight: poll them before reloading the geometry");
+    if (ctx->plain) {
+        HIP_TRY(hipStreamSynchronize(ctx->plain->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->plain->side));
+        ctx->plain->n_ev = 0;
+    }
+    for (auto &sl : ctx->slots) {
+        HIP_TRY(hipStreamSynchronize(sl->stream));
+        HIP_TRY(hipStreamSynchronize(sl->side));
+        sl->n_ev = 0;
+    }
     // device copy: one allocation
     const size_t nm = geom.n_mod, ne = geom.edge_dst.size(), nc = std::max<size_t>(geom.classes.size(), 1);
     const size_t ns = geom.surfaces.size();
@@ -888,7 +976,8 @@ lst_status lst_load_geometry(lst_ctx *ctx, const lst_module_desc *m, uint32_t n)
     size_t off_cls = lst::align_up(off_edge + 8 * std::max<size_t>(ne, 1));
     size_t off_sf = lst::align_up(off_cls + sizeof(lst::LsK) * nc);
     size_t off_phi = lst::align_up(off_sf + sizeof(lst::Surface) * std::max<size_t>(ns, 1));
-    size_t total = lst::align_up(off_phi + 8 * nm);
+    size_t off_ext = lst::align_up(off_phi + 8 * nm);
+    size_t total = lst::align_up(off_ext + 32 * nm);
     std::vector<char> host(total, 0);
     std::memcpy(&host[off_kind], geom.kind.data(), 4 * nm);
     std::memcpy(&host[off_surf], geom.surf.data(), 4 * nm);
@@ -917,6 +1006,7 @@ lst_status lst_load_geometry(lst_ctx *ctx, const lst_module_desc *m, uint32_t n)
     }
     if (ns) std::memcpy(&host[off_sf], geom.surfaces.data(), sizeof(lst::Surface) * ns);
     std::memcpy(&host[off_phi], geom.mod_phi.data(), 8 * nm);
+    std::memcpy(&host[off_ext], geom.mod_ext.data(), 32 * nm);
     void *dmem = nullptr;
     if (hipMalloc(&dmem, total) != hipSuccess) return set_err(ctx, LST_ERR_OOM, "geometry allocation failed");
     hipError_t e = hipMemcpy(dmem, host.data(), total, hipMemcpyHostToDevice);
@@ -936,6 +1026,7 @@ lst_status lst_load_geometry(lst_ctx *ctx, const lst_module_desc *m, uint32_t n)
     ctx->dg.cls = (const lst::LsK *)(d + off_cls);
     ctx->dg.surf = (const lst::Surface *)(d + off_sf);
     ctx->dg.mod_phi = (const float2 *)(d + off_phi);
+    ctx->dg.mod_ext = (const float4 *)(d + off_ext);
     // the hit histogram runs per event in LDS, in slices of the event's
     // (module, sensor) bins that fit one block's LDS
     int lds_max = 0;
@@ -1005,7 +1096,7 @@ lst_status lst_run_batch(lst_ctx *ctx, const lst_event_in *evs, uint32_t n, lst_
     Slot &s = *ctx->plain;
     st = stage_inputs(ctx, s, evs, n);
     if (st != LST_OK) return st;
-    st = run_staged(ctx, s, true, false, false);
+    st = run_staged(ctx, s, true, (ctx->p.flags & LST_FLAG_STAGE_TIMES) != 0, true);
     if (st != LST_OK) return st;
     for (uint32_t i = 0; i < n; i++) outs[i] = nullptr;
     st = download(ctx, s, outs);
@@ -1036,7 +1127,7 @@ lst_status lst_batch_upload(lst_ctx *ctx, const lst_event_in *evs, uint32_t n)
     if (st != LST_OK) return st;
     HIP_TRY(hipStreamSynchronize(s.stream));
     // size the work arena with one untimed run
-    return run_staged(ctx, s, false, false, false);
+    return run_staged(ctx, s, false, false, true);
 }
 
 lst_status lst_batch_execute(lst_ctx *ctx, uint32_t repeats, int32_t use_graph, int32_t timing, double *ms)
@@ -1049,18 +1140,7 @@ lst_status lst_batch_execute(lst_ctx *ctx, uint32_t repeats, int32_t use_graph, 
     Slot &s = *ctx->plain;
     if (timing) ctx->ktimes.clear();
     s.L.only = ctx->time_only.empty() ? nullptr : ctx->time_only.c_str();
-    auto drain = [&]() {
-        for (auto &rec : s.L.recs) {
-            float t = 0.f;
-            if (hipEventElapsedTime(&t, rec.second.first, rec.second.second) == hipSuccess) {
-                auto &kt = ctx->ktimes[rec.first];
-                kt.first += t;
-                kt.second += 1;
-            }
-        }
-        s.L.recs.clear();
-        s.L.used = 0;
-    };
+    auto drain = [&]() { drain_records(ctx, s); };
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
@@ -1084,10 +1164,8 @@ lst_status lst_batch_execute(lst_ctx *ctx, uint32_t repeats, int32_t use_graph, 
     (void)hipEventDestroy(e1);
     if (ms) *ms = t;
     if (st != LST_OK) return st;
-    bool was_timing = s.L.timing;
     s.L.timing = false;
-    st = finish_run(ctx, s, false);
-    s.L.timing = was_timing;
+    st = finish_run(ctx, s, true);
     if (st != LST_OK) return st;
     if (overflowed(s)) return set_err(ctx, LST_ERR_OOM, "object list overflow during execute");
     return LST_OK;
@@ -1136,7 +1214,7 @@ lst_status lst_batch_download(lst_ctx *ctx, lst_event_out **outs)
 lst_status lst_batch_counts(lst_ctx *ctx, uint64_t counts[15])
 {
     if (!ctx || !counts) return LST_ERR_INVALID_ARG;
-    if (!ctx->plain || !ctx->plain->h_tot) return set_err(ctx, LST_ERR_INVALID_ARG, "no staged batch");
+    if (!ctx->plain || !ctx->plain->n_ev) return set_err(ctx, LST_ERR_INVALID_ARG, "no staged batch");
     std::lock_guard<std::mutex> g(ctx->run_mu);
     Slot &s = *ctx->plain;
     // re-run once with candidate statistics
@@ -1161,9 +1239,6 @@ lst_status lst_submit(lst_ctx *ctx, const lst_event_in *ev, uint64_t *ticket)
     st = check_event(ctx, *ev);
     if (st != LST_OK) return st;
     if (ev->flags & LST_DEVICE_PTRS) return set_err(ctx, LST_ERR_INVALID_ARG, "served events take host pointers");
-    const uint64_t budget = ctx->p.mem_budget ? ctx->p.mem_budget : (32ull << 30);
-    uint64_t f = predict_footprint(ev->n_hits, ev->n_pls, ctx->geom.c);
-    if (f > budget) return set_err(ctx, LST_ERR_TOO_LARGE, "event above the device memory budget");
     auto se = std::make_unique<ServedEvent>();
     se->x.assign(ev->x, ev->x + ev->n_hits);
     se->y.assign(ev->y, ev->y + ev->n_hits);
@@ -1172,9 +1247,12 @@ lst_status lst_submit(lst_ctx *ctx, const lst_event_in *ev, uint64_t *ticket)
     se->sen.assign(ev->sensor, ev->sensor + ev->n_hits);
     se->par.assign(ev->pls_par, ev->pls_par + 5ull * ev->n_pls);
     se->cov.assign(ev->pls_cov, ev->pls_cov + 15ull * ev->n_pls);
-    se->footprint = f;
     se->t_submit = std::chrono::steady_clock::now();
     std::lock_guard<std::mutex> g(ctx->q_mu);
+    const uint64_t budget = ctx->p.mem_budget ? ctx->p.mem_budget : (32ull << 30);
+    const uint64_t f = predict_footprint(ev->n_hits, ev->n_pls, ctx->geom.c);
+    if (f > budget) return set_err(ctx, LST_ERR_TOO_LARGE, "event above the device memory budget");
+    se->footprint = f;
     if (ctx->in_system >= ctx->p.queue_depth) return set_err(ctx, LST_ERR_QUEUE_FULL, "queue full");
     if (!ctx->worker_started) {
         ctx->slots.clear();
@@ -1252,6 +1330,7 @@ const char *lst_status_str(lst_status s)
     case LST_ERR_TOO_LARGE: return "event too large";
     case LST_ERR_QUEUE_FULL: return "queue full";
     case LST_ERR_UNKNOWN_TICKET: return "unknown ticket";
+    case LST_ERR_HIT_OUTSIDE: return "hit outside its module or off its sensor";
     default: return "unknown status";
     }
 }

@@ -18,6 +18,7 @@ constexpr uint32_t kDiskBit = 0x80000000u;   // md_u: anchor on an endcap module
 constexpr uint32_t kUnitMask = 0x7FFFFFFFu;  // md_u: (event, module) unit
 constexpr uint32_t kErrBadModule = 1u;
 constexpr uint32_t kErrNonFinite = 2u;
+constexpr uint32_t kErrOutside = 4u;   // hit outside its module's extent or off its sensor
 constexpr int kScanGrid = 2048;   // blocks (and partial sums) of the device-wide scan
 constexpr unsigned kMaxGrid = 2048;
 constexpr int kEvTabCols = 12;
@@ -50,6 +51,7 @@ struct DevGeom {
     const LsK *cls;
     const Surface *surf;        // n_surf
     const float2 *mod_phi;      // n_mod: azimuth centre and half-width (with margin)
+    const float4 *mod_ext;      // 2 per module: accepted extent of a hit, sensor positions
     uint32_t hist_slice;        // hit histogram in LDS: (module, sensor) bins per slice
 };
 
@@ -151,6 +153,7 @@ struct Batch {
     double *pls_seed;                   // derived binary64 quantities of each seed (10 words)
     uint32_t *tc_cnt, *tc_off, *tc_type, *tc_idx;
     uint32_t *ev_tab;                   // (cap_ev + 1) x kEvTabCols
+    uint32_t *ev_err;                   // input error bits of each event (kErr*)
 };
 
 // Launches kernels on one stream; optionally brackets each launch with HIP
@@ -166,7 +169,13 @@ struct Launcher {
     const char *only = nullptr;         // with timing: time only the launches of this name (nullptr: all)
     std::vector<hipEvent_t> pool;
     size_t used = 0;
-    std::vector<std::pair<const char *, std::pair<hipEvent_t, hipEvent_t>>> recs;
+    int stage = 0;                      // stage of the chain the next launches belong to (LST_STAGE_*)
+    struct Rec {
+        const char *name;
+        int stage;
+        hipEvent_t e0, e1;
+    };
+    std::vector<Rec> recs;
     hipError_t err = hipSuccess;
 
     hipEvent_t next_event()
@@ -226,7 +235,7 @@ struct Launcher {
         if (le != hipSuccess && err == hipSuccess) err = le;
         if (timed && e1) {
             (void)hipEventRecord(e1, st);
-            recs.push_back({name, {e0, e1}});
+            recs.push_back({name, stage, e0, e1});
         }
     }
 
@@ -234,7 +243,7 @@ struct Launcher {
               const char *name);
 };
 
-void launch_setup(Launcher &L, Totals *t, const Consts &c);
+void launch_setup(Launcher &L, const Batch &b, Totals *t, const Consts &c);
 void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, const Consts &c, int stats);
 
 }  // namespace lst

@@ -24,9 +24,16 @@ namespace {
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kTwoPi = 2.0 * kPi;
 
-// Hits are assumed within this many resolutions of their module's extent
-// (the synthetic inputs truncate their smearing at 5).
+// The connection map and the seed-lookup surfaces cover hits up to this many
+// resolutions outside their module's extent (sigma_rphi over the module's
+// inner radius in azimuth, sigma_c along z in the barrel and r on a disk).
 constexpr double kEdgeSigmas = 6.0;
+// Input contract checked at ingest: a hit lies within this many resolutions
+// of its module's extent, and on its sensor (barrel radius, disk plane z)
+// within kSurfTol.  The half resolution between the two margins absorbs the
+// binary32 rounding of the ingest check.
+constexpr double kHitSigmas = 5.5;
+constexpr double kSurfTol = 0.008;   // cm; the map and the roads allow 0.01
 
 double half_turn(double r, double k)
 {
@@ -316,7 +323,7 @@ lst_status build_geometry(const lst_params &p, const lst_module_desc *m, uint32_
                 } else {
                     double za0 = a.c_min - mz, za1 = a.c_max + mz;
                     double zap0 = k.zs > 0 ? za0 : -za1, zap1 = k.zs > 0 ? za1 : -za0;
-                    double ra0 = a.s_lo, ra1 = a.s_lo + 0.01;
+                    double ra0 = a.s_lo - 0.01, ra1 = a.s_lo + 0.01;
                     if (!(zap1 + ec + L > 0)) {
                         ok = false;
                     } else {
@@ -364,6 +371,26 @@ lst_status build_geometry(const lst_params &p, const lst_module_desc *m, uint32_
         if (c > kPi) c -= kTwoPi;
         g.mod_phi[2 * (size_t)B] = (float)c;
         g.mod_phi[2 * (size_t)B + 1] = (float)(0.5 * (b.phi_max - b.phi_min) + mphiB);
+    }
+
+    // extent of every module as the ingest check reads it: azimuth centre in
+    // (-pi, pi] and half-width, coarse-coordinate range, each widened by
+    // kHitSigmas resolutions; the two sensor positions and their tolerance
+    g.mod_ext.resize(8 * (size_t)n);
+    for (uint32_t i = 0; i < n; i++) {
+        const lst_module_desc &d = m[i];
+        const double r_min = d.kind == LST_BARREL ? d.s_lo : d.c_min;
+        double c = 0.5 * (d.phi_min + d.phi_max);
+        if (c > kPi) c -= kTwoPi;
+        float *e = &g.mod_ext[8 * (size_t)i];
+        e[0] = (float)c;
+        e[1] = (float)(0.5 * (d.phi_max - d.phi_min) + kHitSigmas * p.sig_rphi / r_min);
+        e[2] = (float)(d.c_min - kHitSigmas * p.sig_c);
+        e[3] = (float)(d.c_max + kHitSigmas * p.sig_c);
+        e[4] = (float)d.s_lo;
+        e[5] = (float)d.s_hi;
+        e[6] = (float)kSurfTol;
+        e[7] = d.kind == LST_BARREL ? 0.0f : 1.0f;
     }
 
     // ---- surfaces for the seed lookup --------------------------------------

@@ -244,8 +244,10 @@ __global__ void k_zero_u8(uint8_t *__restrict__ p, const uint32_t *n_ptr, uint32
 }
 
 // derive the per-batch unit counts; clear error flags and statistics
-__global__ void k_setup(Totals *t, uint32_t n_mod, uint32_t n_surf, uint32_t nphi, uint32_t nkb)
+__global__ void k_setup(Totals *t, uint32_t *__restrict__ ev_err, uint32_t cap_ev, uint32_t n_mod, uint32_t n_surf,
+                        uint32_t nphi, uint32_t nkb)
 {
+    for (uint32_t e = threadIdx.x; e < min(t->n_ev, cap_ev); e += blockDim.x) ev_err[e] = 0u;
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         t->n_bins = t->n_ev * 2u * n_mod;
         t->n_md_units = t->n_ev * n_mod;
@@ -270,10 +272,28 @@ __global__ void k_setup(Totals *t, uint32_t n_mod, uint32_t n_surf, uint32_t nph
 // its (module, sensor) bins, counts the event's hits that fall in the slice
 // with LDS atomics (the returned value is the hit's slot in its bin) and
 // writes the slice's counts out, so no global atomic is needed.  Bad hits
-// are reported by the slice-0 block only.
+// are reported by the slice-0 block only, for the batch and for their event.
 constexpr uint32_t kHistBlock = 1024;
 
-__global__ __launch_bounds__(kHistBlock) void k_hit_hist(const Batch b, Totals *t, uint32_t n_mod, uint32_t slice)
+// Input contract of a hit: on its sensor (barrel radius or disk plane z
+// within the stated tolerance) and inside its module's extent widened by the
+// stated resolutions (coarse coordinate, azimuth); ext holds both per module.
+__device__ inline bool hit_inside(const float4 *__restrict__ ext, uint32_t m, uint32_t sn, float x, float y, float z)
+{
+    const float4 a = ext[2 * m], sp = ext[2 * m + 1];
+    const float r = sqrtf(x * x + y * y);
+    const bool barrel = sp.w == 0.0f;
+    const float across = barrel ? r : z;
+    const float coarse = barrel ? z : r;
+    if (!(fabsf(across - (sn ? sp.y : sp.x)) <= sp.z)) return false;
+    if (!(coarse >= a.z && coarse <= a.w)) return false;
+    float d = fabsf(atan2f(y, x) - a.x);
+    if (d > kPiF) d = 2.0f * kPiF - d;
+    return d <= a.y;
+}
+
+__global__ __launch_bounds__(kHistBlock) void k_hit_hist(const Batch b, Totals *t, const float4 *__restrict__ ext,
+                                                         uint32_t n_mod, uint32_t slice)
 {
     extern __shared__ uint32_t s_cnt[];
     const uint32_t n_ev = t->n_ev, n = min(t->n_hits, b.cap_hits);
@@ -291,9 +311,11 @@ __global__ __launch_bounds__(kHistBlock) void k_hit_hist(const Batch b, Totals *
             uint32_t bad = 0;
             if (m >= n_mod || sn > 1u) bad |= kErrBadModule;
             if (!isfinite(x) || !isfinite(y) || !isfinite(z)) bad |= kErrNonFinite;
+            if (!bad && !hit_inside(ext, m, sn, x, y, z)) bad |= kErrOutside;
             if (bad) {
                 if (sl == 0u) {
                     atomicOr(&t->err, bad);
+                    atomicOr(&b.ev_err[e], bad);
                     b.hbin[h] = kInvalid;
                 }
                 continue;
@@ -1397,11 +1419,15 @@ __global__ void k_pls_prep(const Batch b, Totals *t, const Consts c)
     const uint32_t n = min(t->n_pls, b.cap_pls);
     const uint32_t n_ev = t->n_ev;
     GRID_STRIDE(p, n) {
-        b.pls_ev[p] = find_event(b.ev_pls_off, n_ev, p);
+        const uint32_t e = find_event(b.ev_pls_off, n_ev, p);
+        b.pls_ev[p] = e;
         bool ok = true;
         for (int k = 0; k < 5; k++) ok = ok && isfinite(b.in_par[5 * p + k]);
         for (int k = 0; k < 15; k++) ok = ok && isfinite(b.in_cov[15 * p + k]);
-        if (!ok) atomicOr(&t->err, kErrNonFinite);
+        if (!ok) {
+            atomicOr(&t->err, kErrNonFinite);
+            atomicOr(&b.ev_err[e], kErrNonFinite);
+        }
         const Seed s = load_seed(b, c, p);
         double2 *r = reinterpret_cast<double2 *>(b.pls_seed) + 5 * (size_t)p;
         r[0] = make_double2(s.kp, s.skp);
@@ -1910,7 +1936,7 @@ __global__ void k_event_table(const Batch b, const Totals *t, const Consts c)
         row[8] = b.tc_off[min(p3, n3)];
         row[9] = b.tc_off[n3 + min(t5, n5)];
         row[10] = b.tc_off[n3 + n5 + pls];
-        row[11] = 0;
+        row[11] = e < n_ev ? b.ev_err[e] : 0u;   // input errors of the event
     }
 }
 
@@ -1948,9 +1974,11 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     // buckets and pT5, run on the side stream alongside the main chain; the
     // track-candidate selection waits for both.
     L.on_side(false);
-    launch_setup(L, t, c);
+    L.stage = LST_STAGE_INGEST;
+    launch_setup(L, b, t, c);
     L.fork(0);
     L.on_side(true);
+    L.stage = LST_STAGE_SEED_LOOKUP;
     L.launch("pls_prep", k_pls_prep, grid_for(b.cap_pls), blk, b, t, c);
     L.launch("road", k_road, grid_for(cap_pu), blk, b, (const Totals *)t, g, c);
     // counters of later stages that need clearing
@@ -1963,14 +1991,17 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     L.mark(0);                           // the main stream waits for this only before its seed-lookup stage
     L.on_side(false);
     // a1: hit ingest & sort by (event, module, sensor)
+    L.stage = LST_STAGE_INGEST;
     const uint32_t n_sl = (2u * n_mod + g.hist_slice - 1u) / g.hist_slice;
     const dim3 gh((unsigned)std::min<uint64_t>((uint64_t)b.cap_ev * n_sl, kMaxGrid));
-    L.launch_lds("hit_hist", k_hit_hist, gh, dim3(kHistBlock), g.hist_slice * 4u, b, t, n_mod, g.hist_slice);
+    L.launch_lds("hit_hist", k_hit_hist, gh, dim3(kHistBlock), g.hist_slice * 4u, b, t, g.mod_ext, n_mod,
+                 g.hist_slice);
     L.scan(b.bin_cnt, b.bin_off, &t->n_bins, b.cap_ev * 2u * n_mod, &t->n_sorted, "scan_hits");
     L.launch("hit_scatter", k_hit_scatter, grid_for(b.cap_hits), blk, b, (const Totals *)t);
     L.launch("hit_gather", k_hit_gather, grid_for((uint64_t)b.cap_ev * 2 * n_mod), blk, b, (const Totals *)t,
              n_mod);
     // a2: mini-doublets
+    L.stage = LST_STAGE_MD;
     // small batches: count and fill in place for latency; large ones: pooled walk
     const dim3 gmd = grid_for(b.cap_hits);
     if (b.cap_md <= kLsWaveMaxMd) {
@@ -1987,6 +2018,7 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
                  b, (const Totals *)t, g, c, nsub_md);
     }
     // a3: line segments over the connection map
+    L.stage = LST_STAGE_LS;
     // small batches: 32 lanes per MD for latency; large ones: pooled walk
     if (b.cap_md <= kLsWaveMaxMd) {
         L.launch("ls_count", k_ls_wave<false>, grid_for(32ull * b.cap_md), blk, b, t, g, c, stats);
@@ -2002,6 +2034,7 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
         L.launch("ls_place", k_ls_place, grid_for(b.cap_ls), blk, b, nsub_ls);
     }
     // a4: T3
+    L.stage = LST_STAGE_T3;
     const dim3 gt3 = grid_for(b.cap_ls);
     const uint32_t nsub_t3 = gt3.x;
     L.launch("t3_walk", k_t3, gt3, blk, b, t, c, nsub_t3, stats);
@@ -2014,6 +2047,7 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     // side: a5 T5, its seed-lookup buckets (a6) and pT5 (a7)
     L.fork(1);
     L.on_side(true);
+    L.stage = LST_STAGE_T5;
     const dim3 gt5 = grid_for(b.cap_t3);
     const uint32_t nsub_t5 = gt5.x;
     L.launch("t5_walk", k_t5, gt5, blk, b, t, c, nsub_t5, stats);
@@ -2021,9 +2055,11 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
              &t->n_t5s);
     L.scan(b.t5_cnt, b.t5_off, &t->n_t3, b.cap_t3, &t->n_t5, "scan_t5");
     L.launch("t5_place", k_t5_place, grid_for(b.cap_t5), blk, b, g, c, nsub_t5);
+    L.stage = LST_STAGE_SEED_LOOKUP;
     L.scan(b.bk5_cnt, b.bk5_off, &t->n_bk, cap_bk, &t->n_bk5, "scan_bucket");
     L.launch("bucket_scatter", k_bucket_scatter<1>, grid_for(b.cap_t5), blk, b, (const Totals *)t);
     L.launch("pt5c_walk", k_ptc<1>, gwalk, blk, b, t, c, nsub, stats);
+    L.stage = LST_STAGE_PT;
     L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.ptc5_sub, b.ptc5_soff, b.cap_ptc5, nsub,
              &t->n_ptc5);
     L.launch("pt5_eval", k_pt_eval<1>, dim3(nsub), blk, b, c, nsub);
@@ -2034,9 +2070,11 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
 
     // main: the T3 seed-lookup buckets (a6) and pT3 (a7)
     L.on_side(false);
+    L.stage = LST_STAGE_SEED_LOOKUP;
     L.scan(b.bk3_cnt, b.bk3_off, &t->n_bk, cap_bk, &t->n_bk3, "scan_bucket");
     L.launch("bucket_scatter", k_bucket_scatter<0>, grid_for(b.cap_t3), blk, b, (const Totals *)t);
     L.launch("pt3c_walk", k_ptc<0>, gwalk, blk, b, t, c, nsub, stats);
+    L.stage = LST_STAGE_PT;
     L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.ptc3_sub, b.ptc3_soff, b.cap_ptc3, nsub,
              &t->n_ptc3);
     L.launch("pt3_eval", k_pt_eval<0>, dim3(nsub), blk, b, c, nsub);
@@ -2047,6 +2085,7 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     // a8: track candidates, once both branches are done
     L.mark(1);
     L.wait(1);
+    L.stage = LST_STAGE_TC;
     L.launch("tc_keep", k_tc_keep, grid_for((uint64_t)b.cap_pt3 + b.cap_t5 + b.cap_pls), blk, b, t);
     L.scan(b.tc_cnt, b.tc_off, &t->n_tcu, b.cap_pt3 + b.cap_t5 + b.cap_pls, &t->n_tc, "scan_tc");
     L.launch("tc_write", k_tc_write, grid_for((uint64_t)b.cap_pt3 + b.cap_t5 + b.cap_pls), blk, b,
@@ -2054,9 +2093,9 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     L.launch("event_table", k_event_table, grid_for(b.cap_ev + 1), blk, b, (const Totals *)t, c);
 }
 
-void launch_setup(Launcher &L, Totals *t, const Consts &c)
+void launch_setup(Launcher &L, const Batch &b, Totals *t, const Consts &c)
 {
-    L.launch("setup", k_setup, dim3(1), dim3(64), t, c.n_mod, c.n_surf, c.nphi, c.nkb);
+    L.launch("setup", k_setup, dim3(1), dim3(256), t, b.ev_err, b.cap_ev, c.n_mod, c.n_surf, c.nphi, c.nkb);
 }
 
 }  // namespace lst

@@ -67,6 +67,10 @@ struct Geometry {
     // per module: azimuth centre in (-pi, pi] and half-width, widened by the
     // connection map's hit-position margin (radians)
     std::vector<float> mod_phi;
+    // per module, 8 floats: the extent the ingest check accepts (azimuth
+    // centre, half-width, coarse lo, coarse hi) and the sensor positions
+    // (s_lo, s_hi, tolerance, 0)
+    std::vector<float> mod_ext;
     std::vector<Surface> surfaces;
     Consts c{};
 };

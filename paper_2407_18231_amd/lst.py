@@ -19,8 +19,10 @@ LST_OK = 0
 LST_PENDING = 1
 STATUS = {0: "OK", 1: "PENDING", -1: "INVALID_ARG", -2: "DEVICE", -3: "NO_GEOMETRY",
           -4: "BAD_GEOMETRY", -5: "BAD_MODULE", -6: "NONFINITE", -7: "OOM",
-          -8: "TOO_LARGE", -9: "QUEUE_FULL", -10: "UNKNOWN_TICKET"}
+          -8: "TOO_LARGE", -9: "QUEUE_FULL", -10: "UNKNOWN_TICKET", -11: "HIT_OUTSIDE"}
 LST_FLAG_BEND = 1
+LST_FLAG_STAGE_TIMES = 2
+STAGES = ("ingest", "md", "ls", "t3", "t5", "seed_lookup", "pt", "tc")
 LST_DEVICE_PTRS = 1
 TC_PT5, TC_PT3, TC_T5, TC_PLS = 0, 1, 2, 3
 
@@ -37,7 +39,8 @@ class lst_params(C.Structure):
                 ("L", C.c_double), ("sig_rphi", C.c_double), ("sig_c", C.c_double),
                 ("n_sigma", C.c_double), ("flags", C.c_uint32), ("max_batch", C.c_uint32),
                 ("n_slots", C.c_uint32), ("queue_depth", C.c_uint32),
-                ("mem_budget", C.c_uint64), ("n_phi_bins", C.c_uint32), ("n_kappa_bins", C.c_uint32)]
+                ("mem_budget", C.c_uint64), ("n_phi_bins", C.c_uint32), ("n_kappa_bins", C.c_uint32),
+                ("stream", C.c_void_p)]
 
 
 MODULE_DTYPE = np.dtype([("kind", "<u4"), ("layer", "<u4"), ("side", "<i4"), ("pad", "<u4"),
@@ -61,7 +64,10 @@ class lst_event_out(C.Structure):
                 ("t3", C.POINTER(C.c_uint32)), ("t5", C.POINTER(C.c_uint32)),
                 ("pt3", C.POINTER(C.c_uint32)), ("pt5", C.POINTER(C.c_uint32)),
                 ("tc", C.POINTER(C.c_uint32)), ("t3_kappa", C.POINTER(C.c_float)),
-                ("latency_us", C.c_double), ("ticket", C.c_uint64)]
+                ("latency_us", C.c_double), ("ticket", C.c_uint64),
+                ("n_flag_regrow", C.c_uint32), ("n_stage", C.c_uint32),
+                ("stage_ns", C.c_uint64 * len(STAGES)), ("batch_events", C.c_uint32),
+                ("pad", C.c_uint32), ("footprint", C.c_uint64)]
 
 
 _P = C.POINTER
@@ -130,7 +136,12 @@ def default_params(**kw) -> lst_params:
     load().lst_default_params(C.byref(p))
     for k, v in kw.items():
         if k == "bend":
-            p.flags = LST_FLAG_BEND if v else 0
+            p.flags = (p.flags & ~LST_FLAG_BEND) | (LST_FLAG_BEND if v else 0)
+        elif k == "stage_times":
+            p.flags = (p.flags & ~LST_FLAG_STAGE_TIMES) | (LST_FLAG_STAGE_TIMES if v else 0)
+        elif k == "stream":
+            # a torch.cuda.Stream, or a raw hipStream_t handle
+            p.stream = C.c_void_p(int(getattr(v, "cuda_stream", v)) if v is not None else None)
         else:
             setattr(p, k, v)
     return p
@@ -199,6 +210,10 @@ def _out_to_dict(o: lst_event_out) -> dict:
                      if o.n_t3 else np.zeros(0, np.float32))
     d["latency_us"] = o.latency_us
     d["ticket"] = o.ticket
+    d["n_flag_regrow"] = o.n_flag_regrow
+    d["batch_events"] = o.batch_events
+    d["footprint"] = o.footprint
+    d["stage_ns"] = {name: int(o.stage_ns[i]) for i, name in enumerate(STAGES)}
     return d
 
 

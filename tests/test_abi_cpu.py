@@ -99,3 +99,65 @@ def test_bucket_granularity_params(lib, tmp_path):
     tune.store_choice("gfx950", "batch8-pu100", {"n_phi_bins": 32, "n_kappa_bins": 12}, path)
     assert tune.load_choice("gfx950", "batch64-pu200", path) == {"n_phi_bins": 64, "n_kappa_bins": 16}
     assert tune.load_choice("gfx942", "batch64-pu200", path) is None
+
+
+def _c_layout(struct: str, fields: list) -> dict:
+    """sizeof and offsetof of a struct of include/lst.h, as gcc lays it out."""
+    import subprocess
+    import tempfile
+    body = "\n".join(f'printf("{f} %zu\\n", offsetof({struct}, {f}));' for f in fields)
+    src = ('#include <stddef.h>\n#include <stdio.h>\n#include "lst.h"\n'
+           f'int main(void) {{ printf("sizeof %zu\\n", sizeof({struct})); {body} return 0; }}\n')
+    with tempfile.TemporaryDirectory() as d:
+        c, exe = os.path.join(d, "t.c"), os.path.join(d, "t")
+        open(c, "w").write(src)
+        subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        out = subprocess.check_output([exe]).decode().split()
+    return {k: int(v) for k, v in zip(out[::2], out[1::2])}
+
+
+@pytest.mark.parametrize("cls,struct", [(lst.lst_params, "lst_params"), (lst.lst_event_in, "lst_event_in"),
+                                        (lst.lst_event_out, "lst_event_out")])
+def test_struct_layout_matches_header(lib, cls, struct):
+    """The binding's ctypes structs have the header's size and field offsets
+    (stage_ns and n_flag_regrow of the output, the caller stream of the
+    parameters included)."""
+    import ctypes
+    names = [f[0] for f in cls._fields_]
+    lay = _c_layout(struct, names)
+    assert lay["sizeof"] == ctypes.sizeof(cls)
+    for n in names:
+        assert lay[n] == getattr(cls, n).offset, n
+    if struct == "lst_event_out":
+        assert lst.lst_event_out.stage_ns.size == 8 * len(lst.STAGES)
+
+
+def test_module_desc_layout(lib):
+    lay = _c_layout("lst_module_desc", list(lst.MODULE_DTYPE.names))
+    assert lay["sizeof"] == lst.MODULE_DTYPE.itemsize
+    for n in lst.MODULE_DTYPE.names:
+        assert lay[n] == lst.MODULE_DTYPE.fields[n][1], n
+
+
+def test_connection_map_covers_the_input_contract(lib):
+    """Hits at the edge of the input contract (5.4 resolutions outside their
+    module's extent, across azimuth and z / r edges): every segment the
+    brute-force oracle builds from them lies on a map edge."""
+    import contract
+    g = s.make_geometry("pu200")
+    ev = s.gen_event(g, s.config_pu(200, smear=False), 4242)
+    gs = contract.shrunk(g, 5.4)
+    out = contract.outside_extent(gs, ev)
+    assert out.max() > 5.3 and (out > 4.0).sum() > 1000
+    begin, dst = lst.build_connection_map(gs)
+    src = np.repeat(np.arange(g.n_mod), np.diff(begin))
+    edges = set(zip(src.tolist(), dst.tolist()))
+    r = oracle.run(gs, ev)
+    md_mod = ev["module"][r["md"][:, 0]]
+    a_out = out[r["md"][:, 0]]
+    pairs = {(int(md_mod[a]), int(md_mod[b])) for a, b in r["ls"]}
+    # segments whose anchors lie outside their modules are many
+    edge_ls = sum(1 for a, b in r["ls"] if a_out[a] > 3.0 or a_out[b] > 3.0)
+    assert edge_ls > 500
+    missing = pairs - edges
+    assert not missing, list(missing)[:5]

@@ -1,0 +1,243 @@
+"""GPU tests of the boundary, through the C ABI: the hits' input contract, input
+errors confined to their own event in the served mix, stage times, a caller's
+stream, geometry reload, served admission (queue depth, memory budget) and
+determinism of the per-event and batched paths."""
+import time
+
+import numpy as np
+import pytest
+
+import contract
+from paper_2407_18231_amd import lst, synth as s
+from parity import STAGES, check_canonical, check_parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def g():
+    return s.make_geometry("pu200")
+
+
+@pytest.fixture(scope="module")
+def ctx(g):
+    c = lst.Context()
+    c.load_geometry(g)
+    yield c
+    c.close()
+
+
+def same(a, b):
+    for k in STAGES:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_contract_edge_parity(g):
+    """Hits up to 5.4 resolutions outside their module's extent (across
+    azimuth and z / r edges) are searched as widely as by the brute-force
+    oracle: the lists match it."""
+    ev = s.gen_event(g, s.config_pu(200, smear=False), 4242)
+    gs = contract.shrunk(g, 5.4)
+    assert (contract.outside_extent(gs, ev) > 4.0).sum() > 1000
+    with lst.Context() as c:
+        c.load_geometry(gs)
+        res = c.run_event(ev)
+    check_canonical(res, ev)
+    check_parity(gs, ev, res)
+
+
+def test_outside_contract_rejected(g, ctx):
+    """Hits 10 resolutions outside their module, or off their sensor, break
+    the input contract: HIT_OUTSIDE, and the context keeps working."""
+    ev = s.gen_event(g, s.config_pu(50, smear=False), 4243)
+    with lst.Context() as c:
+        c.load_geometry(contract.shrunk(g, 10.0))
+        with pytest.raises(lst.LstError) as e:
+            c.run_event(ev)
+        assert e.value.name == "HIT_OUTSIDE"
+    barrel = np.nonzero(g.kind[ev["module"]] == s.BARREL)[0]
+    disk = np.nonzero(g.kind[ev["module"]] != s.BARREL)[0]
+    for idx, radial in ((barrel[3], True), (disk[5], False)):
+        bad = dict(ev, x=ev["x"].copy(), y=ev["y"].copy(), z=ev["z"].copy())
+        if radial:                    # 0.02 cm off the barrel sensor's radius
+            f = 1.0 + 0.02 / float(np.hypot(ev["x"][idx], ev["y"][idx]))
+            bad["x"][idx] *= f
+            bad["y"][idx] *= f
+        else:                         # 0.02 cm off the disk sensor's plane
+            bad["z"][idx] += np.float32(0.02 * np.sign(ev["z"][idx]))
+        with pytest.raises(lst.LstError) as e:
+            ctx.run_event(bad)
+        assert e.value.name == "HIT_OUTSIDE"
+    check_parity(g, ev, ctx.run_event(ev))
+
+
+def test_served_bad_event_fails_only_its_ticket(g):
+    """An event with a bad module id, a NaN or a hit outside its module is
+    co-batched with good events: only its own ticket fails, with the matching
+    error; the good events equal their results alone."""
+    good = s.batch_events(6, g, pu_lo=140, pu_hi=200, seed_base=4)
+    b1 = dict(good[0], module=good[0]["module"].copy())
+    b1["module"][11] = g.n_mod + 3
+    b2 = dict(good[1], x=good[1]["x"].copy())
+    b2["x"][5] = np.nan
+    b3 = dict(good[2], z=good[2]["z"].copy())
+    b3["z"][np.nonzero(g.kind[good[2]["module"]] == s.BARREL)[0][0]] = 1e4
+    b4 = dict(good[3], pls_par=good[3]["pls_par"].copy())
+    b4["pls_par"][2, 0] = np.inf
+    # (event, index of its good twin or None, expected error or None)
+    mix = [(good[0], 0, None), (b1, None, "BAD_MODULE"), (good[1], 1, None), (b2, None, "NONFINITE"),
+           (good[2], 2, None), (b3, None, "HIT_OUTSIDE"), (good[3], 3, None), (b4, None, "NONFINITE"),
+           (good[4], 4, None), (good[5], 5, None)]
+    with lst.Context(max_batch=8, n_slots=2) as c:
+        c.load_geometry(g)
+        alone = [c.run_event(ev) for ev in good]
+        tickets = [c.submit(ev) for ev, _, _ in mix]
+        for t, (ev, k, err) in zip(tickets, mix):
+            if err is None:
+                same(alone[k], c.poll(t, -1))
+            else:
+                with pytest.raises(lst.LstError) as e:
+                    c.poll(t, -1)
+                assert e.value.name == err
+
+
+def test_stage_times(g, ctx):
+    """With stage timing every stage of the per-event path reports a positive
+    device time, their sum fits inside the call, and the lists are those of
+    the untimed run."""
+    ev = s.gen_event(g, s.config_pu(200), s.event_seed(2, 1))
+    ref = ctx.run_event(ev)
+    assert all(v == 0 for v in ref["stage_ns"].values())
+    with lst.Context(stage_times=True) as c:
+        c.load_geometry(g)
+        c.run_event(ev)
+        t0 = time.perf_counter()
+        res = c.run_event(ev)
+        wall_ns = (time.perf_counter() - t0) * 1e9
+    same(ref, res)
+    st = res["stage_ns"]
+    print(st, wall_ns, flush=True)
+    assert all(v > 0 for v in st.values()), st
+    assert sum(st.values()) <= wall_ns
+    assert res["n_flag_regrow"] == 0 and res["batch_events"] == 1
+
+
+def test_regrow_count_reported(g):
+    small = s.gen_event(g, s.config_pu(20), 1)
+    big = s.gen_event(g, s.config_pu(300, noise_frac=0.4), 2)
+    with lst.Context() as c:
+        c.load_geometry(g)
+        assert c.run_event(small)["n_flag_regrow"] == 0
+        r = c.run_event(big)
+        assert r["n_flag_regrow"] >= 1
+        assert c.run_event(big)["n_flag_regrow"] == 0
+
+
+def test_caller_stream(g, ctx):
+    """The per-event, batched and device-resident paths run on a stream the
+    caller owns (here torch's) and give the same lists."""
+    torch = pytest.importorskip("torch")
+    evs = [s.gen_event(g, s.config_pu(150), s.event_seed(2, 20 + i)) for i in range(3)]
+    ref = [ctx.run_event(ev) for ev in evs]
+    st = torch.cuda.Stream()
+    with lst.Context(stream=st) as c:
+        c.load_geometry(g)
+        for ev, r in zip(evs, ref):
+            same(r, c.run_event(ev))
+        for r, b in zip(ref, c.run_batch(evs)):
+            same(r, b)
+        c.batch_upload(evs)
+        c.batch_execute(2, graph=True)
+        for r, b in zip(ref, c.batch_download(len(evs))):
+            same(r, b)
+    st.synchronize()
+
+
+def test_geometry_reload_drops_staged_batch(g):
+    """Reloading the geometry releases the arenas of the staged batch: the
+    device-resident calls then report that no batch is staged instead of
+    touching freed memory; a new upload works."""
+    evs = [s.gen_event(g, s.config_pu(100), s.event_seed(2, 30 + i)) for i in range(2)]
+    with lst.Context() as c:
+        c.load_geometry(g)
+        c.batch_upload(evs)
+        c.batch_execute(1, graph=True)
+        first = c.batch_download(2)
+        c.load_geometry(g)
+        for call in (lambda: c.batch_execute(1, graph=True), lambda: c.batch_download(2), c.batch_counts):
+            with pytest.raises(lst.LstError) as e:
+                call()
+            assert e.value.name == "INVALID_ARG"
+        c.batch_upload(evs)
+        c.batch_execute(1, graph=True)
+        for a, b in zip(first, c.batch_download(2)):
+            same(a, b)
+
+
+def test_served_queue_full_and_too_large(g):
+    """Submissions beyond queue_depth are refused with QUEUE_FULL and the
+    accepted ones complete correctly; an event above the memory budget is
+    refused with TOO_LARGE at submission."""
+    ev = s.gen_event(g, s.config_pu(300, noise_frac=0.4), s.event_seed(5, 1))
+    with lst.Context(queue_depth=2, max_batch=1, n_slots=1) as c:
+        c.load_geometry(g)
+        ref = c.run_event(ev)
+        tickets, full = [], 0
+        for _ in range(40):
+            try:
+                tickets.append(c.submit(ev))
+            except lst.LstError as e:
+                assert e.value.name == "QUEUE_FULL"
+                full += 1
+        assert full > 0 and len(tickets) >= 2
+        for t in tickets:
+            same(ref, c.poll(t, -1))
+    with lst.Context(mem_budget=1 << 20) as c:
+        c.load_geometry(g)
+        with pytest.raises(lst.LstError) as e:
+            c.submit(ev)
+        assert e.value.name == "TOO_LARGE"
+
+
+def test_served_admission_under_budget(g):
+    """With a device-memory budget for two events at most two are admitted at
+    once (one micro-batch holds at most two); results equal the events' runs
+    alone."""
+    evs = s.batch_events(8, g, pu_lo=140, pu_hi=200, seed_base=4)
+    with lst.Context(max_batch=8, n_slots=2) as c:
+        c.load_geometry(g)
+        alone = [c.run_event(ev) for ev in evs]
+        fp = [c.poll(c.submit(ev), -1)["footprint"] for ev in evs]
+    assert min(fp) > 0
+    budget = int(min(fp) + max(fp) + 0.5 * min(fp))   # two events fit, three never do
+    assert budget < 3 * min(fp)
+    with lst.Context(max_batch=8, n_slots=2, mem_budget=budget) as c:
+        c.load_geometry(g)
+        tickets = [c.submit(ev) for ev in evs]
+        outs = [c.poll(t, -1) for t in tickets]
+    for a, o in zip(alone, outs):
+        same(a, o)
+        assert o["batch_events"] <= 2
+    assert max(o["batch_events"] for o in outs) <= 2
+
+
+def test_deterministic_x10(g, ctx):
+    """Ten runs of the per-event path (small-batch kernels) and ten of a
+    64-event batch (pooled kernels, eager and graph) give identical lists."""
+    ev = s.gen_event(g, s.config_pu(200), s.event_seed(2, 3))
+    a = ctx.run_event(ev)
+    for _ in range(9):
+        b = ctx.run_event(ev)
+        same(a, b)
+        assert np.array_equal(a["t3_kappa"].view(np.uint32), b["t3_kappa"].view(np.uint32))
+    evs = [s.gen_event(g, s.config_pu(200), s.event_seed(2, i)) for i in range(64)]
+    with lst.Context(max_batch=64) as c:
+        c.load_geometry(g)
+        c.batch_upload(evs)
+        c.batch_execute(1, graph=False)
+        ref = c.batch_download(64)
+        for i in range(9):
+            c.batch_execute(1, graph=bool(i % 2))
+            got = c.batch_download(64)
+            for r, q in zip(ref, got):
+                same(r, q)

@@ -14,10 +14,9 @@ import pytest
 
 import oracle
 from paper_2407_18231_amd import lst, synth as s
+from parity import STAGES, check_canonical, check_parity
 
 pytestmark = pytest.mark.gpu
-
-STAGES = ("md", "ls", "t3", "t5", "pt3", "pt5", "tc")
 
 
 @pytest.fixture(scope="module")
@@ -39,32 +38,6 @@ def ctx_tiny(geo):
     c.load_geometry(geo["tiny"])
     yield c
     c.close()
-
-
-def check_parity(geom, ev, res, flag_budget=5e-3):
-    kd = oracle.keyed(oracle.run(geom, ev))
-    got = lst.result_keys(res)
-    for k in STAGES:
-        assert len(set(got[k])) == len(got[k]), f"duplicates in {k}"
-    rep = oracle.compare(kd, got)
-    for k in STAGES:
-        r = rep[k]
-        print(k, {q: r[q] for q in ("got", "total", "flagged", "missing", "extra")}, flush=True)
-        assert r["missing"] == 0 and r["extra"] == 0, (k, r)
-        assert r["flagged"] <= max(3, flag_budget * r["total"]), (k, r)
-    return rep
-
-
-def check_canonical(res, ev):
-    md = res["md"].astype(np.int64)
-    if len(md) > 1:
-        key = np.lexsort((md[:, 1], md[:, 0], ev["module"][md[:, 0]]))
-        assert np.array_equal(key, np.arange(len(md))), "md order"
-    for k in ("ls", "t3", "t5", "pt3", "pt5"):
-        a = res[k].astype(np.int64)
-        if len(a) > 1:
-            key = a[:, 0] * (1 << 32) + a[:, 1]
-            assert np.all(np.diff(key) > 0), k
 
 
 def test_parity_tiny(ctx_tiny, geo):
@@ -281,3 +254,38 @@ def test_bucket_granularity_does_not_change_lists(ctx, geo, bins):
         got = c.run_event(ev)
     for k in STAGES:
         assert np.array_equal(ref[k], got[k]), (bins, k)
+
+
+def test_parity_special_seeds(ctx, geo):
+    """Seeds whose helix cannot reach the outer tracker (|r kappa / 2| >= 1
+    from r = 17.5 cm on), with cot(theta) = 0 (no disk prediction) and with
+    q/pT = 0 (a straight line), among ordinary ones."""
+    g = geo["pu200"]
+    ev = s.gen_event(g, s.config_pu(100), s.event_seed(2, 40))
+    par, cov = ev["pls_par"].copy(), ev["pls_cov"].copy()
+    hi_pt = np.argsort(np.abs(par[:, 0]))[:8]          # straightest seeds
+    par[hi_pt[:4], 0] = 0.0
+    par[hi_pt[4:], 2] = 0.0
+    par[:6, 0] = np.where(par[:6, 0] < 0, -12.0, 12.0)    # pT ~ 0.08 GeV
+    cov[:6, 0] = (0.015 * 12.0) ** 2
+    ev2 = dict(ev, pls_par=par, pls_cov=cov)
+    res = ctx.run_event(ev2)
+    check_canonical(res, ev2)
+    check_parity(g, ev2, res)
+    linked = set(res["pt3"][:, 0].tolist()) | set(res["pt5"][:, 0].tolist())
+    assert not linked & set(range(6))
+    assert len(res["pt3"]) > 1000
+
+
+def test_parity_disk_only(ctx, geo):
+    """An event with hits on the disks only: endcap MDs, disk-to-disk
+    segments and the T3 / T5 / seed links built from them."""
+    g = geo["pu200"]
+    ev = s.gen_event(g, s.config_pu(200), s.event_seed(2, 41))
+    keep = g.kind[ev["module"]] != s.BARREL
+    ev2 = {k: ev[k][keep] for k in ("x", "y", "z", "module", "sensor")}
+    ev2.update(pls_par=ev["pls_par"], pls_cov=ev["pls_cov"])
+    res = ctx.run_event(ev2)
+    check_canonical(res, ev2)
+    check_parity(g, ev2, res)
+    assert len(res["t3"]) > 100 and len(res["ls"]) > 1000
