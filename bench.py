@@ -198,6 +198,12 @@ def main():
     log(f"generated {B} events in {time.perf_counter() - t0:.1f} s")
     n_hits = int(sum(e["x"].size for e in events))
     n_pls = int(sum(e["pls_par"].shape[0] for e in events))
+    if not args.quick and not args.chain_only:
+        # the served workloads, generated on the host's cores before the GPU is touched
+        t0 = time.perf_counter()
+        pool4 = served_events(5000)
+        pool5 = served_events(256, 300.0, 300.0, 5, 0.4, 0.05)
+        log(f"served pools: {len(pool4)} + {len(pool5)} events in {time.perf_counter() - t0:.1f} s")
 
     ctx = lst.Context(max_batch=max(B, 64))
     ctx.load_geometry(g)
@@ -315,9 +321,10 @@ def main():
         ctx.batch_execute(args.steps, graph=True)
         result["mixed_pu50_250_batch64_events_per_s"] = round(64 / ((time.perf_counter() - t1) / args.steps), 2)
         log("mixed batch:", result["mixed_pu50_250_batch64_events_per_s"])
-        # ---- served path: Poisson arrivals -------------------------------------
-        result["served"] = served(ctx, g, synth)
-        log("served:", result["served"])
+        # ---- served path: Poisson arrivals, then saturation ---------------------
+        result["served"] = served(g, pool4)
+        result["served_pu300_stress"] = served_stress(g, pool5)
+        log("served stress:", result["served_pu300_stress"])
     ctx.close()
 
     if not args.no_cpu:
@@ -340,49 +347,123 @@ def copy_probe(mb: int):
     log(f"copied {mb} MiB")
 
 
-def served(ctx, g, synth, rates=(500.0, 2000.0, 8000.0), seconds=1.0):
+_INPUT_KEYS = ("x", "y", "z", "module", "sensor", "pls_par", "pls_cov")
+
+
+def _served_event(args):
+    """One event of the served workload: PU ~ U[pu_lo, pu_hi] drawn for it."""
+    from paper_2407_18231_amd import synth
+    i, pu_lo, pu_hi, cfg_index, noise, fakes = args
+    g = synth.make_geometry("pu200")
+    rng = np.random.default_rng(synth.event_seed(cfg_index, i) + 700_000)
+    pu = float(rng.uniform(pu_lo, pu_hi))
+    ev = synth.gen_event(g, synth.config_pu(pu, noise_frac=noise, fake_frac=fakes), synth.event_seed(cfg_index, i))
+    return {k: ev[k] for k in _INPUT_KEYS}
+
+
+def served_events(n, pu_lo=140.0, pu_hi=200.0, cfg_index=4, noise=0.2, fakes=0.02):
+    """n distinct events, generated on the host's cores."""
+    import multiprocessing as mp
+    procs = max(1, min(16, len(os.sched_getaffinity(0))))
+    args = [(i, pu_lo, pu_hi, cfg_index, noise, fakes) for i in range(n)]
+    with mp.get_context("fork").Pool(procs) as pool:
+        return pool.map(_served_event, args, chunksize=8)
+
+
+def served_run(ctx, pool, rate_hz, n, seed, submitters=4):
+    """Poisson arrivals at rate_hz (rate_hz = 0: back to back), each arrival a
+    random event of the pool; several submitting threads follow the arrival
+    schedule and one thread polls.  Latency = completion - submission,
+    measured by the library; events/s = n / (last completion - first
+    arrival)."""
+    import threading
     from paper_2407_18231_amd import lst
-    """Events with PU ~ U[140, 200] arriving as a Poisson stream (seed 99) at
-    each rate; latency = completion - submission, measured by the library.
-    A warm-up pass first sizes the device slots."""
-    rng = np.random.default_rng(99)
-    pool = []
-    for i in range(48):
-        pu = float(rng.uniform(140, 200))
-        pool.append(synth.gen_event(g, synth.config_pu(pu), synth.event_seed(4, i)))
-    for t in [ctx.submit(ev) for ev in pool]:
-        ctx.poll(t, -1)
-    out = []
-    for rate_hz in rates:
-        n = int(rate_hz * seconds)
-        gaps = rng.exponential(1.0 / rate_hz, n)
-        tickets = []
-        t_start = time.perf_counter()
-        t_next = t_start
-        lat = []
-        done = 0
-        for i in range(n):
-            t_next += gaps[i]
-            while time.perf_counter() < t_next:
-                pass
+    rng = np.random.default_rng(seed)
+    t_arr = np.cumsum(rng.exponential(1.0 / rate_hz, n)) if rate_hz > 0 else np.zeros(n)
+    pick = rng.integers(0, len(pool), n)
+    ins = [lst.EventIn(ev) for ev in pool]
+    tickets = [None] * n
+    posted = [threading.Event() for _ in range(n)]
+    rejected = [0]
+    lat = np.zeros(n)
+    batch = np.zeros(n, np.int64)
+    t0 = time.perf_counter() + 0.05
+
+    def submit(k):
+        for i in range(k, n, submitters):
+            while True:
+                d = t0 + t_arr[i] - time.perf_counter()
+                if d <= 0:
+                    break
+                if d > 3e-4:
+                    time.sleep(d - 2e-4)
             while True:
                 try:
-                    tickets.append(ctx.submit(pool[i % len(pool)]))
+                    tickets[i] = ctx.submit_in(ins[pick[i]])
                     break
                 except lst.LstError as e:
                     if e.name != "QUEUE_FULL":
                         raise
-                    # back-pressure: wait for the oldest event in flight
-                    lat.append(ctx.poll(tickets[done], -1)["latency_us"])
-                    done += 1
-        for t in tickets[done:]:
-            lat.append(ctx.poll(t, -1)["latency_us"])
-        t_end = time.perf_counter()
-        lat = np.array(lat)
-        out.append(dict(rate_hz=rate_hz, events=n, events_per_s=round(n / (t_end - t_start), 1),
-                        latency_us_p50=round(float(np.percentile(lat, 50)), 1),
-                        latency_us_p99=round(float(np.percentile(lat, 99)), 1)))
+                    rejected[0] += 1
+                    time.sleep(50e-6)
+            posted[i].set()
+
+    def drain():
+        for i in range(n):
+            posted[i].wait()
+            o = ctx.poll(tickets[i], -1, fetch=False)
+            lat[i] = o["latency_us"]
+            batch[i] = o["batch_events"]
+
+    th = [threading.Thread(target=submit, args=(k,)) for k in range(submitters)]
+    dr = threading.Thread(target=drain)
+    sw = sys.getswitchinterval()
+    sys.setswitchinterval(1e-4)        # hand the interpreter between the threads often
+    for t in th:
+        t.start()
+    dr.start()
+    for t in th:
+        t.join()
+    dr.join()
+    wall = time.perf_counter() - t0
+    sys.setswitchinterval(sw)
+    return dict(rate_hz=rate_hz if rate_hz > 0 else "back-to-back", events=n,
+                events_per_s=round(n / wall, 1),
+                latency_us_p50=round(float(np.percentile(lat, 50)), 1),
+                latency_us_p99=round(float(np.percentile(lat, 99)), 1),
+                mean_batch=round(float(batch.mean()), 2), queue_full_retries=rejected[0])
+
+
+def served(g, pool, n_poisson=5000):
+    """Served path (continuous batching, two device slots, 64 events per
+    micro-batch at most): n_poisson Poisson arrivals at 500 Hz, then offered
+    rates up to back-to-back submission to find saturation; events have
+    PU ~ U[140, 200] drawn per event (distinct events of the pool, seeds
+    4000+i, each arrival a random one of them)."""
+    from paper_2407_18231_amd import lst
+    out = []
+    with lst.Context(max_batch=64, n_slots=2) as c:
+        c.load_geometry(g)
+        served_run(c, pool[:256], 0, 512, 98)            # warm-up: sizes the slots
+        out.append(served_run(c, pool, 500.0, n_poisson, 99))
+        log("served:", out[-1])
+        for rate in (4000.0, 16000.0, 0.0):
+            out.append(served_run(c, pool, rate, 8000, 100 + int(rate)))
+            log("served:", out[-1])
     return out
+
+
+def served_stress(g, pool, n=2048):
+    """PU300 stress events (6000 tracks, 40% noise, 3000 seeds with 5% fakes)
+    through the serving loop, 32 events per micro-batch at most, submitted
+    back to back."""
+    from paper_2407_18231_amd import lst
+    with lst.Context(max_batch=32, n_slots=2) as c:
+        c.load_geometry(g)
+        served_run(c, pool[:64], 0, 128, 97)
+        r = served_run(c, pool, 0, n, 101)
+    r["workload"] = "PU300 stress, 32 per micro-batch"
+    return r
 
 
 if __name__ == "__main__":

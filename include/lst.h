@@ -89,6 +89,16 @@ typedef struct {
  * runs on one stream with a HIP event pair around every launch (slower; for
  * diagnosis).  Without it stage_ns is all zero. */
 #define LST_FLAG_STAGE_TIMES 2u
+/* Duplicate cleaning of the track candidates: lst_event_out.tcc lists the
+ * candidates that survive it.  The paper names the candidate types (Sec. 1)
+ * and measures duplicate rates (Sec. 3) but does not describe the removal;
+ * this library's rule: a candidate with outer-tracker MDs (pT5 and T5: 5,
+ * pT3: 3) is removed when another one that ranks higher shares more than
+ * half of the smaller of the two MD sets.  Rank: type (pT5, pT3, T5), then
+ * the smaller curvature disagreement (seed against object for pT5 / pT3,
+ * inner against outer T3 for a T5, relative to the summed resolutions),
+ * then the smaller index in its own list.  Seed-only candidates are kept. */
+#define LST_FLAG_TC_CLEAN 4u
 
 /* Stages of the chain (Sec. 1: hits -> MD -> LS -> T3 -> T5; pLS linked into
  * pT3 / pT5; track candidates), the index of each in stage_ns */
@@ -181,8 +191,9 @@ typedef struct {
      * batch; their sum does not exceed the call's duration */
     uint64_t stage_ns[LST_N_STAGES];
     uint32_t batch_events;   /* events in the launch that produced this output */
-    uint32_t pad;
+    uint32_t n_tcc;          /* with LST_FLAG_TC_CLEAN: candidates kept by the duplicate cleaning */
     uint64_t footprint;      /* served path: predicted device bytes the event was admitted with */
+    uint32_t *tcc;           /* (type, index) as in tc, the kept subset in tc order; NULL without the flag */
 } lst_event_out;
 
 void lst_default_params(lst_params *p);

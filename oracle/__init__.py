@@ -72,7 +72,9 @@ class _Result(C.Structure):
         ("n_pt5", C.c_uint32), ("pt5", C.POINTER(C.c_uint32)), ("pt5_st", C.POINTER(C.c_uint8)),
         ("n_tc", C.c_uint32), ("tc", C.POINTER(C.c_uint32)), ("tc_st", C.POINTER(C.c_uint8)),
         ("md_cand", C.c_uint32), ("ls_cand", C.c_uint32), ("t3_cand", C.c_uint32),
-        ("t5_cand", C.c_uint32), ("pt3_cand", C.c_uint32), ("pt5_cand", C.c_uint32)]
+        ("t5_cand", C.c_uint32), ("pt3_cand", C.c_uint32), ("pt5_cand", C.c_uint32),
+        ("t5_k", C.POINTER(C.c_float)), ("t5_sk", C.POINTER(C.c_float)),
+        ("tc_keep", C.POINTER(C.c_uint8))]
 
 
 @dataclass
@@ -222,6 +224,12 @@ def run(geom, ev: dict, params: Params | None = None) -> dict:
         n = r.n_t3
         out["t3_k"] = np.ctypeslib.as_array(r.t3_k, shape=(n,)).copy() if n else np.zeros(0, np.float32)
         out["t3_sk"] = np.ctypeslib.as_array(r.t3_sk, shape=(n,)).copy() if n else np.zeros(0, np.float32)
+        n = r.n_t5
+        out["t5_k"] = np.ctypeslib.as_array(r.t5_k, shape=(n,)).copy() if n else np.zeros(0, np.float32)
+        out["t5_sk"] = np.ctypeslib.as_array(r.t5_sk, shape=(n,)).copy() if n else np.zeros(0, np.float32)
+        n = r.n_tc
+        out["tc_keep"] = (np.ctypeslib.as_array(r.tc_keep, shape=(n,)).copy().astype(bool) if n
+                          else np.zeros(0, bool))
         out["cand"] = {k: getattr(r, k + "_cand") for k in ("md", "ls", "t3", "t5", "pt3", "pt5")}
     finally:
         lib().or_free(C.byref(r))

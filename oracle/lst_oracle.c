@@ -17,6 +17,7 @@
  *        of the second)                                          (Sec. 1, T5)
  *   pT3, pT5 : every (pixel seed, T3 / T5) pair                  (Sec. 1)
  *   TC : pT5s, pT3s, T5s and pixel seeds not used elsewhere      (Sec. 1 list)
+ *   TC duplicate cleaning: every pair of candidates               (reading)
  *
  * The paper gives no cut values (it defers them to its references); the cut
  * catalogue implemented here is this project's own, derived from prompt-helix
@@ -84,6 +85,8 @@ typedef struct {
     uint32_t n_pt5; uint32_t *pt5; uint8_t *pt5_st; /* pls, t5 */
     uint32_t n_tc;  uint32_t *tc;  uint8_t *tc_st;  /* type, index */
     uint32_t md_cand, ls_cand, t3_cand, t5_cand, pt3_cand, pt5_cand;
+    float *t5_k, *t5_sk;    /* curvature through the outer anchors A, C, E of each T5 and its resolution */
+    uint8_t *tc_keep;       /* per track candidate: 1 = kept by the duplicate cleaning */
 } or_result;
 
 #define ST_ACC 1u
@@ -699,11 +702,75 @@ int or_run(const or_geom *g, const or_params *p, const or_event *ev, or_result *
         ol_push(&tc, 3, i, (uint8_t)(ST_ACC | (u ? ST_FLAG : 0)), 0, 0);
     }
 
+    /* ---- duplicate cleaning of the track candidates ----
+       Reading (the paper lists the candidate types but not how duplicates
+       are removed): a candidate with outer-tracker MDs (pT5: the 5 of its
+       T5, pT3: the 3 of its T3, T5: its 5) is removed when another such
+       candidate shares more than half of the smaller of the two MD sets and
+       ranks higher.  Rank: type (pT5, then pT3, then T5), then the smaller
+       curvature disagreement -- |kappa_seed - kappa_obj| / (sigma_seed +
+       sigma_obj) for pT5 / pT3, |kappa_ABC - kappa_CDE| / (sigma_ABC +
+       sigma_CDE) of the two T3s for a T5, in binary64 -- then the smaller
+       index in its own list.  Seed-only candidates carry no outer-tracker
+       hit and are all kept.  Every pair is compared (no ordering of the
+       removals): a candidate is kept unless a higher-ranked duplicate exists. */
+    size_t ntc = tc.n;
+    uint8_t *keep = (uint8_t *)malloc(ntc ? ntc : 1);
+    uint32_t *tmd = (uint32_t *)calloc(5 * (ntc ? ntc : 1), sizeof(uint32_t));
+    uint32_t *tnm = (uint32_t *)calloc(ntc ? ntc : 1, sizeof(uint32_t));
+    double *tq = (double *)calloc(ntc ? ntc : 1, sizeof(double));
+    double kB = 0.299792458e-2 * p->B;
+    for (size_t i = 0; i < ntc; i++) {
+        uint32_t typ = tc.v[2 * i], idx = tc.v[2 * i + 1];
+        keep[i] = 1;
+        if (typ == 3 || !(tc.st[i] & ST_ACC)) continue;
+        uint32_t u, w = 0, ps = 0;
+        if (typ == 0) { ps = pt5.v[2 * idx]; u = t5.v[2 * pt5.v[2 * idx + 1]]; w = t5.v[2 * pt5.v[2 * idx + 1] + 1]; }
+        else if (typ == 1) { ps = pt3.v[2 * idx]; u = pt3.v[2 * idx + 1]; }
+        else { u = t5.v[2 * idx]; w = t5.v[2 * idx + 1]; }
+        uint32_t *m = tmd + 5 * i;
+        m[0] = t3m.v[2 * u];
+        m[1] = ls.v[2 * t3.v[2 * u] + 1];
+        m[2] = t3m.v[2 * u + 1];
+        tnm[i] = 3;
+        if (typ != 1) {
+            m[3] = ls.v[2 * t3.v[2 * w] + 1];
+            m[4] = t3m.v[2 * w + 1];
+            tnm[i] = 5;
+        }
+        if (typ == 2) {
+            tq[i] = fabs((double)t3.f0[u] - (double)t3.f0[w]) / ((double)t3.f1[u] + (double)t3.f1[w]);
+        } else {
+            double kp = (double)ev->pls_par[5 * (size_t)ps] * kB;
+            double skp = kB * sqrt((double)ev->pls_cov[15 * (size_t)ps]);
+            uint32_t o = typ == 0 ? pt5.v[2 * idx + 1] : u;
+            double ko = typ == 0 ? (double)t5.f0[o] : (double)t3.f0[o];
+            double so = typ == 0 ? (double)t5.f1[o] : (double)t3.f1[o];
+            tq[i] = fabs(kp - ko) / (skp + so);
+        }
+    }
+    for (size_t i = 0; i < ntc; i++) {
+        if (!tnm[i]) continue;
+        for (size_t j = 0; j < ntc && keep[i]; j++) {
+            if (j == i || !tnm[j]) continue;
+            uint32_t ti = tc.v[2 * i], tj = tc.v[2 * j];
+            int better = tj < ti || (tj == ti && (tq[j] < tq[i] || (tq[j] == tq[i] && tc.v[2 * j + 1] < tc.v[2 * i + 1])));
+            if (!better) continue;
+            uint32_t shared = 0;
+            for (uint32_t x = 0; x < tnm[i]; x++)
+                for (uint32_t y = 0; y < tnm[j]; y++)
+                    if (tmd[5 * i + x] == tmd[5 * j + y]) shared++;
+            uint32_t small = tnm[i] < tnm[j] ? tnm[i] : tnm[j];
+            if (2 * shared > small) keep[i] = 0;
+        }
+    }
+    free(tmd); free(tnm); free(tq);
+
     out->n_md = nmd; out->md = md.v; out->md_st = md.st;
     out->n_ls = nls; out->ls = ls.v; out->ls_st = ls.st;
     out->n_t3 = nt3; out->t3 = t3.v; out->t3_st = t3.st; out->t3_k = t3.f0; out->t3_sk = t3.f1;
-    out->n_t5 = nt5; out->t5 = t5.v; out->t5_st = t5.st;
-    free(t5.f0); free(t5.f1);
+    out->n_t5 = nt5; out->t5 = t5.v; out->t5_st = t5.st; out->t5_k = t5.f0; out->t5_sk = t5.f1;
+    out->tc_keep = keep;
     out->n_pt3 = (uint32_t)pt3.n; out->pt3 = pt3.v; out->pt3_st = pt3.st;
     out->n_pt5 = (uint32_t)pt5.n; out->pt5 = pt5.v; out->pt5_st = pt5.st;
     out->n_tc = (uint32_t)tc.n; out->tc = tc.v; out->tc_st = tc.st;
@@ -725,6 +792,7 @@ void or_free(or_result *r)
     free(r->t3); free(r->t3_st); free(r->t3_k); free(r->t3_sk);
     free(r->t5); free(r->t5_st); free(r->pt3); free(r->pt3_st);
     free(r->pt5); free(r->pt5_st); free(r->tc); free(r->tc_st);
+    free(r->t5_k); free(r->t5_sk); free(r->tc_keep);
     memset(r, 0, sizeof *r);
 }
 

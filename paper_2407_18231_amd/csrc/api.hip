@@ -182,6 +182,15 @@ void carve_work(Carver &cv, Batch &b, uint32_t n_mod, uint32_t n_surf, uint32_t 
     b.tc_off = cv.take<uint32_t>(tcu + 1);
     b.tc_type = cv.take<uint32_t>(tcu);
     b.tc_idx = cv.take<uint32_t>(tcu);
+    const size_t tcc = (size_t)b.cap_pt5 + tcu;
+    b.tcc_md = cv.take<uint32_t>(5 * tcc);
+    b.tcc_nm = cv.take<uint32_t>(tcc);
+    b.tcc_rank = cv.take<uint32_t>(5 * tcc);
+    b.md_tcc_cnt = cv.take<uint32_t>((size_t)b.cap_md + 1);
+    b.md_tcc_off = cv.take<uint32_t>((size_t)b.cap_md + 1);
+    b.md_tcc = cv.take<uint32_t>(5 * tcc);
+    b.tcc_q = cv.take<double>(tcc);
+    b.tcc_keep = cv.take<uint8_t>(tcc);
     b.ev_tab = cv.take<uint32_t>(((size_t)b.cap_ev + 1) * kEvTabCols);
     b.ev_err = cv.take<uint32_t>((size_t)b.cap_ev + 1);
 }
@@ -211,6 +220,12 @@ struct Slot {
     std::vector<uint32_t> hit_off, pls_off;
     hipEvent_t done = nullptr;
     bool own_stream = true;          // false: the caller's stream (lst_params.stream), not destroyed here
+    // served path: the events' host blocks as copied to the device, and the
+    // offset of each block (device and pinned host copies)
+    char *raw = nullptr;
+    size_t raw_cap = 0;
+    unsigned long long *d_rawoff = nullptr, *h_rawoff = nullptr;
+    uint32_t rawoff_cap = 0;
     uint32_t n_regrow = 0;           // re-runs of the last batch after an overflow
     uint64_t stage_ns[LST_N_STAGES] = {};   // stage times of the last batch (stage timing only)
     std::vector<uint64_t> tickets;   // served path
@@ -219,11 +234,56 @@ struct Slot {
 
 }  // namespace lst
 
+// Pinned host blocks that hold submitted events until their micro-batch is
+// copied to the device; freed blocks are kept per size class and reused.
+struct PinnedPool {
+    std::mutex mu;
+    std::map<size_t, std::vector<char *>> free_blocks;
+    std::vector<char *> all;
+    static size_t size_class(size_t bytes)
+    {
+        size_t c = 64 << 10;
+        while (c < bytes) c += c / 2;   // classes 64 KiB x 1.5^k
+        return c;
+    }
+    char *get(size_t bytes, size_t &cls)
+    {
+        cls = size_class(bytes);
+        {
+            std::lock_guard<std::mutex> g(mu);
+            auto it = free_blocks.find(cls);
+            if (it != free_blocks.end() && !it->second.empty()) {
+                char *p = it->second.back();
+                it->second.pop_back();
+                return p;
+            }
+        }
+        char *p = nullptr;
+        if (hipHostMalloc((void **)&p, cls, hipHostMallocDefault) != hipSuccess) return nullptr;
+        std::lock_guard<std::mutex> g(mu);
+        all.push_back(p);
+        return p;
+    }
+    void put(char *p, size_t cls)
+    {
+        if (!p) return;
+        std::lock_guard<std::mutex> g(mu);
+        free_blocks[cls].push_back(p);
+    }
+    void release()
+    {
+        for (char *p : all) (void)hipHostFree(p);
+        all.clear();
+        free_blocks.clear();
+    }
+};
+
 struct ServedEvent {
     uint64_t ticket;
-    std::vector<float> x, y, z, par, cov;
-    std::vector<uint32_t> mod;
-    std::vector<uint8_t> sen;
+    uint32_t n_hits = 0, n_pls = 0;
+    char *blk = nullptr;        // pinned block (served_block_layout)
+    size_t blk_cls = 0;
+    size_t blk_bytes = 0;
     uint64_t footprint;
     std::chrono::steady_clock::time_point t_submit;
 };
@@ -245,8 +305,16 @@ struct lst_ctx {
     // served path
     std::vector<std::unique_ptr<lst::Slot>> slots;
     std::mutex q_mu;
-    std::condition_variable q_cv, done_cv;
+    // q_cv: the admission thread (new events, a slot freed); slot_cv: the
+    // completion threads (a slot launched); done_cv: pollers (outputs ready)
+    std::condition_variable q_cv, slot_cv, done_cv;
     std::deque<std::unique_ptr<ServedEvent>> waiting;
+    PinnedPool pinned;
+    std::vector<int> slot_state;        // 0 free, 1 being staged, 2 launched
+    std::vector<uint64_t> slot_mem;
+    std::vector<std::vector<std::unique_ptr<ServedEvent>>> held;
+    std::vector<std::thread> completers;
+    bool stop_completers = false;
     std::unordered_map<uint64_t, lst_event_out *> finished;
     std::unordered_map<uint64_t, int> state;   // 1 waiting / running, 2 finished
     uint64_t next_ticket = 1;
@@ -300,6 +368,9 @@ void free_slot_arenas(Slot &s)
 void destroy_slot(Slot &s)
 {
     free_slot_arenas(s);
+    if (s.raw) (void)hipFree(s.raw);
+    if (s.d_rawoff) (void)hipFree(s.d_rawoff);
+    if (s.h_rawoff) (void)hipHostFree(s.h_rawoff);
     if (s.d_tot) (void)hipFree(s.d_tot);
     if (s.h_tot) (void)hipHostFree(s.h_tot);
     if (s.d_part) (void)hipFree(s.d_part);
@@ -325,7 +396,7 @@ lst_status make_slot(lst_ctx *ctx, std::unique_ptr<Slot> &out, hipStream_t calle
     HIP_TRY(hipHostMalloc((void **)&s->h_tot, sizeof(lst::Totals), hipHostMallocDefault));
     HIP_TRY(hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking));
     HIP_TRY(hipMalloc(&s->d_part, 2 * sizeof(uint32_t) * lst::kScanGrid));
-    HIP_TRY(hipEventCreateWithFlags(&s->done, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&s->done, hipEventDisableTiming | hipEventBlockingSync));
     for (int k = 0; k < 2; k++) {
         HIP_TRY(hipEventCreateWithFlags(&s->L.ev_fork[k], hipEventDisableTiming));
         HIP_TRY(hipEventCreateWithFlags(&s->L.ev_join[k], hipEventDisableTiming));
@@ -345,8 +416,11 @@ lst_status ensure_inputs(lst_ctx *ctx, Slot &s, uint32_t n_ev, uint64_t hits, ui
 {
     Batch &b = s.b;
     if (s.in_arena && n_ev <= b.cap_ev && hits <= b.cap_hits && pls <= b.cap_pls) return LST_OK;
-    lst::Caps c = lst::plan_caps(std::max(n_ev, b.cap_ev), std::max<uint64_t>(hits, b.cap_hits),
-                                 std::max<uint64_t>(pls, b.cap_pls));
+    // a quarter of headroom: events of similar size that follow reuse the
+    // arenas (and the captured graph) instead of reallocating them one after
+    // another
+    lst::Caps c = lst::plan_caps(std::max(n_ev, b.cap_ev), std::max<uint64_t>(hits + hits / 4 + 1024, b.cap_hits),
+                                 std::max<uint64_t>(pls + pls / 4 + 64, b.cap_pls));
     // keep work capacities at least as large as before
     c.md = std::max(c.md, b.cap_md); c.ls = std::max(c.ls, b.cap_ls); c.t3 = std::max(c.t3, b.cap_t3);
     c.t5 = std::max(c.t5, b.cap_t5); c.pt3 = std::max(c.pt3, b.cap_pt3); c.pt5 = std::max(c.pt5, b.cap_pt5);
@@ -624,7 +698,9 @@ lst_status download(lst_ctx *ctx, Slot &s, lst_event_out **outs)
                     {b.t5_u, nt5 * 4ull, 0}, {b.t5_w, nt5 * 4ull, 0},
                     {b.pt3_p, np3 * 4ull, 0}, {b.pt3_o, np3 * 4ull, 0},
                     {b.pt5_p, np5 * 4ull, 0}, {b.pt5_o, np5 * 4ull, 0},
-                    {b.tc_type, ntc * 4ull, 0}, {b.tc_idx, ntc * 4ull, 0}};
+                    {b.tc_type, ntc * 4ull, 0}, {b.tc_idx, ntc * 4ull, 0},
+                    {b.tcc_keep, (ctx->geom.c.flags & LST_FLAG_TC_CLEAN) ? (size_t)np5 + ntc : 0ull, 0}};
+    const bool clean = (ctx->geom.c.flags & LST_FLAG_TC_CLEAN) != 0u;
     size_t total = 0;
     for (Part &p : parts) { p.at = total; total += lst::align_up(p.bytes); }
     if (total > s.out_bytes) {
@@ -641,6 +717,7 @@ lst_status download(lst_ctx *ctx, Slot &s, lst_event_out **outs)
     const uint32_t *u2 = arr(6), *w1 = arr(8), *w2 = arr(9), *p3 = arr(10), *o3 = arr(11), *p5 = arr(12);
     const uint32_t *o5 = arr(13), *tty = arr(14), *tix = arr(15);
     const float2 *k3 = (const float2 *)(s.h_out + parts[7].at);
+    const uint8_t *kp = (const uint8_t *)(s.h_out + parts[16].at);   // cleaning: pT5 flags, then the kept entries
     std::vector<int> failed(n, 0);
     auto build = [&](uint32_t e) {
         const uint32_t *r0 = &tab[(size_t)e * lst::kEvTabCols], *r1 = r0 + lst::kEvTabCols;
@@ -662,7 +739,7 @@ lst_status download(lst_ctx *ctx, Slot &s, lst_event_out **outs)
         const uint32_t cp3 = r1[6] - p30, cp5 = r1[7] - p50;
         const uint32_t ctc3 = r1[8] - r0[8], ctc5 = r1[9] - r0[9], ctcp = r1[10] - r0[10];
         const uint32_t ctc = cp5 + ctc3 + ctc5 + ctcp;
-        size_t words = 2ull * (cmd + cls + ct3 + ct5 + cp3 + cp5 + ctc) + ct3;
+        size_t words = 2ull * (cmd + cls + ct3 + ct5 + cp3 + cp5 + ctc) + ct3 + (clean ? 2ull * ctc : 0ull);
         size_t bytes = sizeof(lst_event_out) + 4 * words + 64;
         char *mem = (char *)std::malloc(bytes);
         if (!mem) { failed[e] = 1; return; }
@@ -678,6 +755,7 @@ lst_status download(lst_ctx *ctx, Slot &s, lst_event_out **outs)
         o->pt5 = w; w += 2 * cp5;
         o->tc = w; w += 2 * ctc;
         o->t3_kappa = (float *)w;
+        w += ct3;
         for (uint32_t i = 0; i < cmd; i++) { o->md[2 * i] = hlo[md0 + i]; o->md[2 * i + 1] = hup[md0 + i]; }
         for (uint32_t i = 0; i < cls; i++) { o->ls[2 * i] = la[ls0 + i] - md0; o->ls[2 * i + 1] = lb[ls0 + i] - md0; }
         for (uint32_t i = 0; i < ct3; i++) {
@@ -692,6 +770,21 @@ lst_status download(lst_ctx *ctx, Slot &s, lst_event_out **outs)
         for (uint32_t i = r0[8]; i < r1[8]; i++) { o->tc[2 * k] = tty[i]; o->tc[2 * k + 1] = tix[i] - p30; k++; }
         for (uint32_t i = r0[9]; i < r1[9]; i++) { o->tc[2 * k] = tty[i]; o->tc[2 * k + 1] = tix[i] - t50; k++; }
         for (uint32_t i = r0[10]; i < r1[10]; i++) { o->tc[2 * k] = tty[i]; o->tc[2 * k + 1] = tix[i] - pls0; k++; }
+        if (clean) {
+            o->tcc = w;
+            uint32_t q = 0;
+            auto put = [&](uint32_t type, uint32_t idx, uint8_t keep) {
+                if (!keep) return;
+                o->tcc[2 * q] = type;
+                o->tcc[2 * q + 1] = idx;
+                q++;
+            };
+            for (uint32_t i = 0; i < cp5; i++) put(LST_TC_PT5, i, kp[p50 + i]);
+            for (uint32_t i = r0[8]; i < r1[8]; i++) put(tty[i], tix[i] - p30, kp[np5 + i]);
+            for (uint32_t i = r0[9]; i < r1[9]; i++) put(tty[i], tix[i] - t50, kp[np5 + i]);
+            for (uint32_t i = r0[10]; i < r1[10]; i++) put(tty[i], tix[i] - pls0, kp[np5 + i]);
+            o->n_tcc = q;
+        }
         o->status = LST_OK;
         o->n_flag_regrow = s.n_regrow;
         o->n_stage = LST_N_STAGES;
@@ -748,135 +841,215 @@ uint64_t predict_footprint(uint64_t hits, uint64_t pls, const lst::Consts &k)
     return b;
 }
 
-void worker_main(lst_ctx *ctx);
+void admit_main(lst_ctx *ctx);
+void complete_main(lst_ctx *ctx, uint32_t i);
 
 }  // namespace
 
 namespace {
 
-void worker_main(lst_ctx *ctx)
+// Copy a micro-batch of served events to slot s and launch the chain: one
+// host-to-device copy per event block (pinned at submission), the unpack
+// kernel, then the captured chain.
+lst_status stage_served(lst_ctx *ctx, Slot &s, const std::vector<std::unique_ptr<ServedEvent>> &evs)
+{
+    const uint32_t n = (uint32_t)evs.size();
+    uint64_t hits = 0, pls = 0, raw = 0;
+    for (const auto &e : evs) {
+        hits += e->n_hits;
+        pls += e->n_pls;
+        raw += e->blk_bytes;
+    }
+    if (hits > 0x7FFFFFFFull || pls > 0x7FFFFFFFull) return set_err(ctx, LST_ERR_TOO_LARGE, "batch too large");
+    lst_status st = ensure_inputs(ctx, s, n, hits, pls);
+    if (st == LST_OK) st = ensure_work(ctx, s);
+    if (st != LST_OK) return st;
+    if (raw > s.raw_cap) {
+        if (s.raw) (void)hipFree(s.raw);
+        s.raw = nullptr;
+        s.raw_cap = 0;
+        const size_t want = raw + raw / 4 + (1 << 20);
+        if (hipMalloc(&s.raw, want) != hipSuccess) { s.raw = nullptr; return set_err(ctx, LST_ERR_OOM, "served input allocation failed"); }
+        s.raw_cap = want;
+    }
+    if (n + 1 > s.rawoff_cap) {
+        if (s.d_rawoff) (void)hipFree(s.d_rawoff);
+        if (s.h_rawoff) (void)hipHostFree(s.h_rawoff);
+        s.d_rawoff = s.h_rawoff = nullptr;
+        s.rawoff_cap = 0;
+        const uint32_t cap = std::max<uint32_t>(ctx->p.max_batch, n) + 1;
+        HIP_TRY(hipMalloc((void **)&s.d_rawoff, 8ull * cap));
+        HIP_TRY(hipHostMalloc((void **)&s.h_rawoff, 8ull * cap, hipHostMallocDefault));
+        s.rawoff_cap = cap;
+    }
+    Batch &b = s.b;
+    s.n_ev = n;
+    s.hit_off.assign(n + 1, 0);
+    s.pls_off.assign(n + 1, 0);
+    uint64_t at = 0;
+    for (uint32_t i = 0; i < n; i++) {
+        s.hit_off[i + 1] = s.hit_off[i] + evs[i]->n_hits;
+        s.pls_off[i + 1] = s.pls_off[i] + evs[i]->n_pls;
+        s.h_rawoff[i] = at;
+        if (evs[i]->blk_bytes)
+            HIP_TRY(hipMemcpyAsync(s.raw + at, evs[i]->blk, evs[i]->blk_bytes, hipMemcpyHostToDevice, s.stream));
+        at += evs[i]->blk_bytes;
+    }
+    s.h_rawoff[n] = at;
+    HIP_TRY(hipMemcpyAsync(s.d_rawoff, s.h_rawoff, 8ull * (n + 1), hipMemcpyHostToDevice, s.stream));
+    char *hs = s.h_stage;
+    const size_t hoff_at = (char *)b.ev_hit_off - (char *)s.in_arena;
+    const size_t poff_at = (char *)b.ev_pls_off - (char *)s.in_arena;
+    std::memcpy(hs + hoff_at, s.hit_off.data(), (n + 1) * 4);
+    std::memcpy(hs + poff_at, s.pls_off.data(), (n + 1) * 4);
+    HIP_TRY(hipMemcpyAsync(b.ev_hit_off, hs + hoff_at, (n + 1) * 4, hipMemcpyHostToDevice, s.stream));
+    HIP_TRY(hipMemcpyAsync(b.ev_pls_off, hs + poff_at, (n + 1) * 4, hipMemcpyHostToDevice, s.stream));
+    s.h_tot->n_ev = n;
+    s.h_tot->n_hits = (uint32_t)hits;
+    s.h_tot->n_pls = (uint32_t)pls;
+    HIP_TRY(hipMemcpyAsync(s.d_tot, s.h_tot, 3 * sizeof(uint32_t), hipMemcpyHostToDevice, s.stream));
+    s.L.on_side(false);
+    s.L.timing = false;
+    s.L.err = hipSuccess;
+    lst::launch_unpack(s.L, b, s.d_tot, s.raw, s.d_rawoff);
+    if (s.L.err != hipSuccess) {
+        fail(ctx, std::string("kernel launch: ") + hipGetErrorString(s.L.err));
+        return LST_ERR_DEVICE;
+    }
+    st = enqueue(ctx, s, true, false, false);
+    if (st != LST_OK) return st;
+    HIP_TRY(hipEventRecord(s.done, s.stream));
+    return LST_OK;
+}
+
+// Admission: whenever events wait and a slot is free, take the events at the
+// front of the queue that fit the memory budget beside what is in flight (up
+// to max_batch) into that slot and launch them; completion runs on the
+// slot's own thread, so staging one slot overlaps the device work and the
+// result assembly of the others.
+void admit_main(lst_ctx *ctx)
 {
     (void)hipSetDevice(ctx->device);
     const uint32_t n_slots = (uint32_t)ctx->slots.size();
-    std::vector<bool> busy(n_slots, false);
-    std::vector<uint64_t> slot_mem(n_slots, 0);
-    std::vector<std::vector<std::unique_ptr<ServedEvent>>> held(n_slots);
+    const uint64_t budget = ctx->p.mem_budget ? ctx->p.mem_budget : (32ull << 30);
     std::unique_lock<std::mutex> lk(ctx->q_mu);
     while (true) {
-        // 1) complete finished slots
-        bool progressed = false;
-        for (uint32_t i = 0; i < n_slots; i++) {
-            if (!busy[i]) continue;
-            Slot &s = *ctx->slots[i];
-            if (hipEventQuery(s.done) == hipErrorNotReady) continue;
-            lk.unlock();
-            lst_status st = finish_run(ctx, s, false);
-            s.n_regrow = 0;
-            std::vector<lst_event_out *> outs(s.n_ev, nullptr);
-            if (st == LST_OK && overflowed(s)) {
-                if (s.work_arena) { (void)hipFree(s.work_arena); s.work_arena = nullptr; }
-                if (s.gexec) { (void)hipGraphExecDestroy(s.gexec); s.gexec = nullptr; }
-                if (s.graph) { (void)hipGraphDestroy(s.graph); s.graph = nullptr; }
-                s.graph_valid = false;
-                st = ensure_work(ctx, s);
-                if (st == LST_OK) {
-                    st = run_staged(ctx, s, true, false, false);
-                    s.n_regrow++;
-                }
+        int slot = -1;
+        auto ready = [&] {
+            slot = -1;
+            if (ctx->waiting.empty()) return ctx->stop;
+            if (ctx->mem_in_use + ctx->waiting.front()->footprint > budget) return false;
+            for (uint32_t i = 0; i < n_slots; i++)
+                if (ctx->slot_state[i] == 0) { slot = (int)i; return true; }
+            return false;
+        };
+        ctx->q_cv.wait(lk, ready);
+        if (slot < 0) break;     // stopping with nothing left to admit
+        std::vector<std::unique_ptr<ServedEvent>> take;
+        uint64_t mem = 0;
+        while (!ctx->waiting.empty() && take.size() < ctx->p.max_batch) {
+            // every admitted event fits the budget with what is in flight
+            // (an event alone always fits: submit refuses larger ones)
+            const uint64_t f = ctx->waiting.front()->footprint;
+            if (ctx->mem_in_use + mem + f > budget) break;
+            mem += f;
+            take.push_back(std::move(ctx->waiting.front()));
+            ctx->waiting.pop_front();
+        }
+        ctx->mem_in_use += mem;
+        ctx->slot_state[slot] = 1;
+        lk.unlock();
+        Slot &s = *ctx->slots[slot];
+        s.tickets.resize(take.size());
+        s.t_submit.resize(take.size());
+        for (size_t k = 0; k < take.size(); k++) {
+            s.tickets[k] = take[k]->ticket;
+            s.t_submit[k] = take[k]->t_submit;
+        }
+        const lst_status st = stage_served(ctx, s, take);
+        lk.lock();
+        if (st != LST_OK) {
+            for (auto &se : take) {
+                ctx->pinned.put(se->blk, se->blk_cls);
+                lst_event_out *o = (lst_event_out *)std::calloc(1, sizeof(lst_event_out));
+                if (o) { o->status = (uint32_t)st; o->ticket = se->ticket; }
+                ctx->finished[se->ticket] = o;
+                ctx->state[se->ticket] = 2;
             }
-            if (st == LST_OK) st = download(ctx, s, outs.data());
-            auto now = std::chrono::steady_clock::now();
-            lk.lock();
-            for (uint32_t e = 0; e < s.n_ev; e++) {
-                lst_event_out *o = outs[e];
-                if (!o) {
-                    o = (lst_event_out *)std::calloc(1, sizeof(lst_event_out));
-                    if (o) o->status = (uint32_t)(st == LST_OK ? LST_ERR_DEVICE : st);
-                }
-                if (o) {
-                    o->ticket = s.tickets[e];
-                    o->footprint = e < held[i].size() ? held[i][e]->footprint : 0;
-                    o->latency_us = std::chrono::duration<double, std::micro>(now - s.t_submit[e]).count();
-                }
-                ctx->finished[s.tickets[e]] = o;
-                ctx->state[s.tickets[e]] = 2;
-            }
-            ctx->in_system -= s.n_ev;
-            ctx->mem_in_use -= slot_mem[i];
-            slot_mem[i] = 0;
-            held[i].clear();
-            busy[i] = false;
-            progressed = true;
+            ctx->in_system -= take.size();
+            ctx->mem_in_use -= mem;
+            ctx->slot_state[slot] = 0;
             ctx->done_cv.notify_all();
+            continue;
         }
-        if (ctx->stop && ctx->waiting.empty() &&
-            std::none_of(busy.begin(), busy.end(), [](bool b) { return b; }))
-            break;
-        // 2) admit waiting events into free slots (continuous batching)
-        for (uint32_t i = 0; i < n_slots && !ctx->waiting.empty(); i++) {
-            if (busy[i]) continue;
-            std::vector<std::unique_ptr<ServedEvent>> take;
-            uint64_t mem = 0;
-            const uint64_t budget = ctx->p.mem_budget ? ctx->p.mem_budget : (32ull << 30);
-            while (!ctx->waiting.empty() && take.size() < ctx->p.max_batch) {
-                // every admitted event fits the budget with what is in flight
-                // (an event alone always fits: submit refuses larger ones)
-                uint64_t f = ctx->waiting.front()->footprint;
-                if (ctx->mem_in_use + mem + f > budget) break;
-                mem += f;
-                take.push_back(std::move(ctx->waiting.front()));
-                ctx->waiting.pop_front();
-            }
-            if (take.empty()) break;
-            ctx->mem_in_use += mem;
-            lk.unlock();
-            Slot &s = *ctx->slots[i];
-            std::vector<lst_event_in> evs(take.size());
-            s.tickets.resize(take.size());
-            s.t_submit.resize(take.size());
-            for (size_t k = 0; k < take.size(); k++) {
-                const ServedEvent &se = *take[k];
-                lst_event_in &ev = evs[k];
-                std::memset(&ev, 0, sizeof ev);
-                ev.n_hits = (uint32_t)se.x.size();
-                ev.n_pls = (uint32_t)(se.par.size() / 5);
-                ev.x = se.x.data(); ev.y = se.y.data(); ev.z = se.z.data();
-                ev.module = se.mod.data(); ev.sensor = se.sen.data();
-                ev.pls_par = se.par.data(); ev.pls_cov = se.cov.data();
-                s.tickets[k] = se.ticket;
-                s.t_submit[k] = se.t_submit;
-            }
-            lst_status st = stage_inputs(ctx, s, evs.data(), (uint32_t)evs.size());
-            if (st == LST_OK) st = enqueue(ctx, s, true, false, false);
-            if (st == LST_OK && hipEventRecord(s.done, s.stream) != hipSuccess) st = LST_ERR_DEVICE;
-            lk.lock();
-            if (st != LST_OK) {
-                for (auto &se : take) {
-                    lst_event_out *o = (lst_event_out *)std::calloc(1, sizeof(lst_event_out));
-                    if (o) { o->status = (uint32_t)st; o->ticket = se->ticket; }
-                    ctx->finished[se->ticket] = o;
-                    ctx->state[se->ticket] = 2;
-                }
-                ctx->in_system -= take.size();
-                ctx->mem_in_use -= mem;
-                ctx->done_cv.notify_all();
-                continue;
-            }
-            slot_mem[i] = mem;
-            held[i] = std::move(take);
-            busy[i] = true;
-            progressed = true;
+        ctx->slot_mem[slot] = mem;
+        ctx->held[slot] = std::move(take);
+        ctx->slot_state[slot] = 2;
+        ctx->slot_cv.notify_all();
+    }
+}
+
+// Completion of slot i: wait for its launch (a blocking-sync event, no
+// polling), re-run with larger lists if one overflowed, copy the results
+// back and hand each event its output.
+void complete_main(lst_ctx *ctx, uint32_t i)
+{
+    (void)hipSetDevice(ctx->device);
+    Slot &s = *ctx->slots[i];
+    std::unique_lock<std::mutex> lk(ctx->q_mu);
+    while (true) {
+        ctx->slot_cv.wait(lk, [&] { return ctx->stop_completers || ctx->slot_state[i] == 2; });
+        if (ctx->slot_state[i] != 2) break;
+        lk.unlock();
+        lst_status st = LST_OK;
+        const hipError_t he = hipEventSynchronize(s.done);
+        if (he != hipSuccess) {
+            fail(ctx, std::string("served batch: ") + hipGetErrorString(he));
+            st = LST_ERR_DEVICE;
         }
-        if (!progressed) {
-            bool any_busy = std::any_of(busy.begin(), busy.end(), [](bool b) { return b; });
-            if (any_busy) {
-                lk.unlock();
-                std::this_thread::sleep_for(std::chrono::microseconds(20));
-                lk.lock();
-            } else {
-                ctx->q_cv.wait(lk, [&] { return ctx->stop || !ctx->waiting.empty(); });
+        if (st == LST_OK) st = finish_run(ctx, s, false);
+        s.n_regrow = 0;
+        std::vector<lst_event_out *> outs(s.n_ev, nullptr);
+        if (st == LST_OK && overflowed(s)) {
+            if (s.work_arena) { (void)hipFree(s.work_arena); s.work_arena = nullptr; }
+            if (s.gexec) { (void)hipGraphExecDestroy(s.gexec); s.gexec = nullptr; }
+            if (s.graph) { (void)hipGraphDestroy(s.graph); s.graph = nullptr; }
+            s.graph_valid = false;
+            st = ensure_work(ctx, s);
+            if (st == LST_OK) {
+                st = run_staged(ctx, s, true, false, false);
+                s.n_regrow++;
             }
         }
+        if (st == LST_OK) st = download(ctx, s, outs.data());
+        const auto now = std::chrono::steady_clock::now();
+        auto &held = ctx->held[i];
+        for (auto &se : held) {
+            ctx->pinned.put(se->blk, se->blk_cls);
+            se->blk = nullptr;
+        }
+        lk.lock();
+        for (uint32_t e = 0; e < s.n_ev; e++) {
+            lst_event_out *o = outs[e];
+            if (!o) {
+                o = (lst_event_out *)std::calloc(1, sizeof(lst_event_out));
+                if (o) o->status = (uint32_t)(st == LST_OK ? LST_ERR_DEVICE : st);
+            }
+            if (o) {
+                o->ticket = s.tickets[e];
+                o->footprint = e < held.size() ? held[e]->footprint : 0;
+                o->latency_us = std::chrono::duration<double, std::micro>(now - s.t_submit[e]).count();
+            }
+            ctx->finished[s.tickets[e]] = o;
+            ctx->state[s.tickets[e]] = 2;
+        }
+        ctx->in_system -= s.n_ev;
+        ctx->mem_in_use -= ctx->slot_mem[i];
+        ctx->slot_mem[i] = 0;
+        held.clear();
+        ctx->slot_state[i] = 0;
+        ctx->q_cv.notify_all();
+        ctx->done_cv.notify_all();
     }
 }
 
@@ -1239,30 +1412,45 @@ lst_status lst_submit(lst_ctx *ctx, const lst_event_in *ev, uint64_t *ticket)
     st = check_event(ctx, *ev);
     if (st != LST_OK) return st;
     if (ev->flags & LST_DEVICE_PTRS) return set_err(ctx, LST_ERR_INVALID_ARG, "served events take host pointers");
+    if (ev->n_hits >= (1u << 28) || ev->n_pls >= (1u << 26))
+        return set_err(ctx, LST_ERR_TOO_LARGE, "event above the served path's size limits");
+    // the event is copied once, into a pinned block that the device reads
     auto se = std::make_unique<ServedEvent>();
-    se->x.assign(ev->x, ev->x + ev->n_hits);
-    se->y.assign(ev->y, ev->y + ev->n_hits);
-    se->z.assign(ev->z, ev->z + ev->n_hits);
-    se->mod.assign(ev->module, ev->module + ev->n_hits);
-    se->sen.assign(ev->sensor, ev->sensor + ev->n_hits);
-    se->par.assign(ev->pls_par, ev->pls_par + 5ull * ev->n_pls);
-    se->cov.assign(ev->pls_cov, ev->pls_cov + 15ull * ev->n_pls);
+    se->n_hits = ev->n_hits;
+    se->n_pls = ev->n_pls;
+    const lst::BlockLayout lay = lst::served_block_layout(ev->n_hits, ev->n_pls);
+    se->blk_bytes = lay.bytes;
+    if (lay.bytes) {
+        se->blk = ctx->pinned.get(lay.bytes, se->blk_cls);
+        if (!se->blk) return set_err(ctx, LST_ERR_OOM, "pinned host allocation failed");
+        const void *src[7] = {ev->x, ev->y, ev->z, ev->module, ev->sensor, ev->pls_par, ev->pls_cov};
+        const size_t sz[7] = {4ull * ev->n_hits, 4ull * ev->n_hits, 4ull * ev->n_hits, 4ull * ev->n_hits,
+                              ev->n_hits, 20ull * ev->n_pls, 60ull * ev->n_pls};
+        for (int i = 0; i < 7; i++)
+            if (sz[i]) std::memcpy(se->blk + lay.off[i], src[i], sz[i]);
+    }
     se->t_submit = std::chrono::steady_clock::now();
     std::lock_guard<std::mutex> g(ctx->q_mu);
+    auto give_back = [&] { ctx->pinned.put(se->blk, se->blk_cls); se->blk = nullptr; };
     const uint64_t budget = ctx->p.mem_budget ? ctx->p.mem_budget : (32ull << 30);
     const uint64_t f = predict_footprint(ev->n_hits, ev->n_pls, ctx->geom.c);
-    if (f > budget) return set_err(ctx, LST_ERR_TOO_LARGE, "event above the device memory budget");
+    if (f > budget) { give_back(); return set_err(ctx, LST_ERR_TOO_LARGE, "event above the device memory budget"); }
     se->footprint = f;
-    if (ctx->in_system >= ctx->p.queue_depth) return set_err(ctx, LST_ERR_QUEUE_FULL, "queue full");
+    if (ctx->in_system >= ctx->p.queue_depth) { give_back(); return set_err(ctx, LST_ERR_QUEUE_FULL, "queue full"); }
     if (!ctx->worker_started) {
         ctx->slots.clear();
         for (uint32_t i = 0; i < ctx->p.n_slots; i++) {
-            std::unique_ptr<Slot> s;
-            st = make_slot(ctx, s);
-            if (st != LST_OK) return st;
-            ctx->slots.push_back(std::move(s));
+            std::unique_ptr<Slot> sl;
+            st = make_slot(ctx, sl);
+            if (st != LST_OK) { give_back(); return st; }
+            ctx->slots.push_back(std::move(sl));
         }
-        ctx->worker = std::thread(worker_main, ctx);
+        ctx->slot_state.assign(ctx->p.n_slots, 0);
+        ctx->slot_mem.assign(ctx->p.n_slots, 0);
+        ctx->held.clear();
+        ctx->held.resize(ctx->p.n_slots);
+        ctx->worker = std::thread(admit_main, ctx);
+        for (uint32_t i = 0; i < ctx->p.n_slots; i++) ctx->completers.emplace_back(complete_main, ctx, i);
         ctx->worker_started = true;
     }
     se->ticket = ctx->next_ticket++;
@@ -1306,12 +1494,26 @@ void lst_destroy(lst_ctx *ctx)
         ctx->stop = true;
         ctx->q_cv.notify_all();
     }
+    // the admission thread ends once nothing waits; the completion threads
+    // once every slot has been handed back
     if (ctx->worker.joinable()) ctx->worker.join();
+    {
+        std::unique_lock<std::mutex> lk(ctx->q_mu);
+        ctx->done_cv.wait(lk, [&] {
+            return std::all_of(ctx->slot_state.begin(), ctx->slot_state.end(), [](int v) { return v == 0; });
+        });
+        ctx->stop_completers = true;
+        ctx->slot_cv.notify_all();
+    }
+    for (auto &th : ctx->completers)
+        if (th.joinable()) th.join();
+    for (auto &kv : ctx->waiting) ctx->pinned.put(kv->blk, kv->blk_cls);
     for (auto &kv : ctx->finished) std::free(kv.second);
     (void)hipSetDevice(ctx->device);
     for (auto &s : ctx->slots) destroy_slot(*s);
     if (ctx->plain) destroy_slot(*ctx->plain);
     if (ctx->geom_mem) (void)hipFree(ctx->geom_mem);
+    ctx->pinned.release();
     delete ctx;
 }
 

@@ -67,6 +67,7 @@ struct Totals {
     uint32_t n_lss;               // segments in the unordered segment sub-lists (likewise)
     uint32_t n_t3s;               // T3s in the unordered T3 sub-lists (likewise)
     uint32_t n_t5s;               // T5s in the unordered T5 regions (likewise)
+    uint32_t n_tccm;              // (MD, candidate) entries of the track-candidate cleaning
     uint32_t err;
     unsigned long long cand[6];  // candidates examined: md, ls, t3, t5, pt3, pt5
 };
@@ -152,6 +153,13 @@ struct Batch {
     uint32_t *pls_ev;                   // event of each seed
     double *pls_seed;                   // derived binary64 quantities of each seed (10 words)
     uint32_t *tc_cnt, *tc_off, *tc_type, *tc_idx;
+    // duplicate cleaning of the track candidates (pT5 list, then the kept
+    // [pT3 | T5 | pLS] entries): MD set (5 per candidate, 3 or 5 used),
+    // rank quality, each candidate's slot in the list of every one of its
+    // MDs, the candidates of each MD (offsets by MD), keep flags
+    uint32_t *tcc_md, *tcc_nm, *tcc_rank, *md_tcc_cnt, *md_tcc_off, *md_tcc;
+    double *tcc_q;
+    uint8_t *tcc_keep;
     uint32_t *ev_tab;                   // (cap_ev + 1) x kEvTabCols
     uint32_t *ev_err;                   // input error bits of each event (kErr*)
 };
@@ -244,6 +252,29 @@ struct Launcher {
 };
 
 void launch_setup(Launcher &L, const Batch &b, Totals *t, const Consts &c);
+
+// Bytes of one served event's host block and the offsets of its parts
+// (x, y, z, module, sensor, seed parameters, seed covariance), every part
+// aligned to 16 bytes; k_unpack reads the same layout.
+struct BlockLayout {
+    size_t off[7];
+    size_t bytes;
+};
+inline BlockLayout served_block_layout(uint32_t n_hits, uint32_t n_pls)
+{
+    auto pad = [](size_t v) { return (v + 15) & ~(size_t)15; };
+    BlockLayout l;
+    const size_t sz[7] = {4ull * n_hits, 4ull * n_hits, 4ull * n_hits, 4ull * n_hits, n_hits, 20ull * n_pls,
+                          60ull * n_pls};
+    size_t at = 0;
+    for (int i = 0; i < 7; i++) {
+        l.off[i] = at;
+        at += pad(sz[i]);
+    }
+    l.bytes = at;
+    return l;
+}
+void launch_unpack(Launcher &L, const Batch &b, const Totals *t, const char *raw, const unsigned long long *raw_off);
 void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, const Consts &c, int stats);
 
 }  // namespace lst

@@ -231,6 +231,36 @@ __device__ inline void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// inclusive prefix maximum across a wave (values >= 0) with row shifts and
+// row broadcasts, no LDS round trip
+__device__ inline uint32_t wave_incl_max(uint32_t v)
+{
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));
+    return v;
+}
+
+// Owner lane of the pooled candidate cb + lane, for steps of 64 pooled
+// candidates: each lane whose first candidate falls in [cb, cb + 64) marks
+// that slot in its wave's 64-entry LDS row; a prefix maximum in registers
+// spreads the marks over the following candidates; carry keeps the owner of
+// the last candidate of the step before (0 before the first step).
+__device__ inline uint32_t pooled_owner(uint32_t *mark, uint32_t lane, uint32_t n_own, uint32_t off, uint32_t cb,
+                                        uint32_t &carry)
+{
+    mark[lane] = 0u;
+    wave_lds_sync();
+    if (n_own != 0u && off >= cb && off < cb + 64u) mark[off - cb] = lane + 1u;
+    wave_lds_sync();
+    const uint32_t m = wave_incl_max(max(mark[lane], carry));
+    carry = (uint32_t)__builtin_amdgcn_readlane((int)m, 63);
+    return m - 1u;
+}
+
 __global__ void k_zero_u32(uint32_t *__restrict__ p, const uint32_t *n_ptr, uint32_t cap, uint32_t extra)
 {
     const uint32_t n = min(*n_ptr, cap) + extra;
@@ -275,13 +305,13 @@ __global__ void k_setup(Totals *t, uint32_t *__restrict__ ev_err, uint32_t cap_e
 // are reported by the slice-0 block only, for the batch and for their event.
 constexpr uint32_t kHistBlock = 1024;
 
-// Input contract of a hit: on its sensor (barrel radius or disk plane z
-// within the stated tolerance) and inside its module's extent widened by the
-// stated resolutions (coarse coordinate, azimuth); ext holds both per module.
-__device__ inline bool hit_inside(const float4 *__restrict__ ext, uint32_t m, uint32_t sn, float x, float y, float z)
+// Input contract of a hit (x, y, z, r = sqrt(x^2 + y^2)) on sensor sn: on
+// that sensor (barrel radius or disk plane z within the stated tolerance) and
+// inside its module's extent widened by the stated resolutions (coarse
+// coordinate, azimuth).  a: the module's accepted extent (azimuth centre,
+// half-width, coarse lo, hi); sp: its sensor positions, tolerance, kind.
+__device__ inline bool hit_inside(const float4 a, const float4 sp, uint32_t sn, float x, float y, float z, float r)
 {
-    const float4 a = ext[2 * m], sp = ext[2 * m + 1];
-    const float r = sqrtf(x * x + y * y);
     const bool barrel = sp.w == 0.0f;
     const float across = barrel ? r : z;
     const float coarse = barrel ? z : r;
@@ -292,8 +322,7 @@ __device__ inline bool hit_inside(const float4 *__restrict__ ext, uint32_t m, ui
     return d <= a.y;
 }
 
-__global__ __launch_bounds__(kHistBlock) void k_hit_hist(const Batch b, Totals *t, const float4 *__restrict__ ext,
-                                                         uint32_t n_mod, uint32_t slice)
+__global__ __launch_bounds__(kHistBlock) void k_hit_hist(const Batch b, Totals *t, uint32_t n_mod, uint32_t slice)
 {
     extern __shared__ uint32_t s_cnt[];
     const uint32_t n_ev = t->n_ev, n = min(t->n_hits, b.cap_hits);
@@ -311,7 +340,6 @@ __global__ __launch_bounds__(kHistBlock) void k_hit_hist(const Batch b, Totals *
             uint32_t bad = 0;
             if (m >= n_mod || sn > 1u) bad |= kErrBadModule;
             if (!isfinite(x) || !isfinite(y) || !isfinite(z)) bad |= kErrNonFinite;
-            if (!bad && !hit_inside(ext, m, sn, x, y, z)) bad |= kErrOutside;
             if (bad) {
                 if (sl == 0u) {
                     atomicOr(&t->err, bad);
@@ -362,8 +390,10 @@ __global__ void k_hit_scatter(const Batch b, const Totals *t)
 
 // per (event, module, sensor) bin: restore input order (the scatter used
 // atomic slots) and write the sorted SoA with r = sqrt(x^2 + y^2).  Bins of
-// up to four hits sort in registers.
-__global__ void k_hit_gather(const Batch b, const Totals *t, uint32_t n_mod)
+// up to four hits sort in registers.  Each hit is checked against the input
+// contract here, where its module's extent is loaded once per bin; a hit
+// outside fails its event (its lists are not used).
+__global__ void k_hit_gather(const Batch b, Totals *t, const float4 *__restrict__ ext, uint32_t n_mod)
 {
     const uint32_t nb = t->n_bins;
     GRID_STRIDE(bin, nb) {
@@ -371,8 +401,13 @@ __global__ void k_hit_gather(const Batch b, const Totals *t, uint32_t n_mod)
         if (beg == end) continue;
         const uint32_t e = bin / (2u * n_mod);
         const uint32_t h0 = b.ev_hit_off[e];
+        const uint32_t local = bin - e * 2u * n_mod, m = local >> 1, sn = local & 1u;
+        const float4 ea = ext[2 * m], es = ext[2 * m + 1];
+        bool outside = false;
         auto put = [&](uint32_t i, const float4 v) {
-            b.hpos[i] = make_float4(v.x, v.y, v.z, sqrtf(v.x * v.x + v.y * v.y));
+            const float r = sqrtf(v.x * v.x + v.y * v.y);
+            outside = outside || !hit_inside(ea, es, sn, v.x, v.y, v.z, r);
+            b.hpos[i] = make_float4(v.x, v.y, v.z, r);
             b.hin[i] = __float_as_uint(v.w) - h0;
             b.hbin_s[i] = bin;
         };
@@ -398,6 +433,10 @@ __global__ void k_hit_gather(const Batch b, const Totals *t, uint32_t n_mod)
 #pragma unroll
             for (uint32_t k = 0; k < 4; k++)
                 if (beg + k < end) put(beg + k, v[k]);
+            if (outside) {
+                atomicOr(&t->err, kErrOutside);
+                atomicOr(&b.ev_err[e], kErrOutside);
+            }
             continue;
         }
         for (uint32_t i = beg + 1; i < end; i++) {
@@ -411,6 +450,10 @@ __global__ void k_hit_gather(const Batch b, const Totals *t, uint32_t n_mod)
             b.hrec[j] = v;
         }
         for (uint32_t i = beg; i < end; i++) put(i, b.hrec[i]);
+        if (outside) {
+            atomicOr(&t->err, kErrOutside);
+            atomicOr(&b.ev_err[e], kErrOutside);
+        }
     }
 }
 
@@ -444,10 +487,11 @@ __device__ inline bool md_cut(const float4 mc, bool barrel, float L,
 __global__ __launch_bounds__(256) void k_md(const Batch b, Totals *t, const DevGeom g, const Consts c,
                                             uint32_t nsub, int stats)
 {
+    __shared__ uint32_t s_mark[4][64];   // pooled-candidate owner marks, one row per wave
     __shared__ uint32_t s_n;             // appends to this block's region
     const uint32_t n = t->n_sorted;
     const uint32_t n_mod = c.n_mod;
-    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     const unsigned long long below = (1ull << lane) - 1ull;
     const uint32_t cap = b.cap_md / nsub;
     uint4 *out = b.mds + (size_t)blockIdx.x * cap;
@@ -474,12 +518,10 @@ __global__ __launch_bounds__(256) void k_md(const Batch b, Totals *t, const DevG
         const uint32_t off = incl - cnt;
         const uint32_t total = __shfl(incl, 63);
         uint32_t run = 0;
+        uint32_t carry = 0;
         for (uint32_t cb = 0; cb < total; cb += 64u) {
             const uint32_t ci = cb + lane;
-            uint32_t o = 0;
-#pragma unroll
-            for (uint32_t step = 32; step; step >>= 1)
-                if (__shfl(off, o + step) <= ci) o += step;
+            const uint32_t o = pooled_owner(s_mark[wv], lane, cnt, off, cb, carry);
             const uint32_t o_up0 = __shfl(up0, o), o_off = __shfl(off, o), o_run = __shfl(run, o);
             const uint32_t o_i = __shfl(i, o), o_m = __shfl(m, o);
             const float hx = __shfl(hi.x, o), hy = __shfl(hi.y, o), hz = __shfl(hi.z, o), hw = __shfl(hi.w, o);
@@ -678,15 +720,18 @@ __device__ inline bool ls_cut(const LsK &k, const Consts &c, bool bend,
 // candidates (every MD of every edge of the group, lane by lane in (edge,
 // outer MD) order) and the lanes take them 64 at a time, so the cut
 // arithmetic runs on full waves however the degrees and MD counts are
-// spread.  A candidate finds its owner lane by a binary search over the
-// lanes' first-candidate offsets, its edge in the owner's group in LDS and
+// spread.  The group's loads go out together (edge records, then every
+// edge's destination extent, class reach and MD range), two round trips per
+// group.  A candidate finds its owner lane from a mark each owner leaves in
+// LDS at its first candidate of the step, spread to the following
+// candidates by a prefix maximum in registers (row shifts and broadcasts, no
+// chain of lane shuffles); its edge in the owner's group comes from LDS and
 // the owner's anchor by lane shuffles.  Survivors go to the block's region of
 // an unordered segment list with their place in the owner's list (its
 // earlier survivors plus those before it in the same 64); edges are sorted by
 // destination module, so that place is the canonical one.  The rounds are
-// bound by the latency of the outer MD and class loads, which depend on LDS
-// reads and lane shuffles; a step takes two rounds, both rounds' loads issued
-// before either cut.
+// bound by the latency of the outer MD and class loads; a step takes two
+// rounds, both rounds' loads issued before either cut.
 constexpr int kEdgeGroup = 6;
 
 __global__ __launch_bounds__(256) void k_ls(const Batch b, Totals *t, const DevGeom g, const Consts c,
@@ -694,6 +739,7 @@ __global__ __launch_bounds__(256) void k_ls(const Batch b, Totals *t, const DevG
 {
     constexpr uint32_t kF = 3 * kEdgeGroup;          // per lane and edge of the group: first outer MD, running count, class
     __shared__ uint32_t s_grp[4][kF][64];
+    __shared__ uint32_t s_mark[4][128];               // owner lane + 1 at each owner's first candidate of a step
     __shared__ uint32_t s_n;                          // appends to this block's region
     const uint32_t n = min(t->n_md, b.cap_md);
     const uint32_t n_mod = c.n_mod;
@@ -729,23 +775,36 @@ __global__ __launch_bounds__(256) void k_ls(const Batch b, Totals *t, const DevG
         uint32_t run = 0;                             // segments of this lane's MD so far
         for (uint32_t eb = e0;; eb += kEdgeGroup) {
             if (__ballot(eb < e1) == 0ull) break;
-            // this lane's group: MD ranges of up to kEdgeGroup edges, to LDS
+            // this lane's group: MD ranges of up to kEdgeGroup edges, to LDS.
+            // The loads of all the group's edges go out together (edges past
+            // the lane's last load a valid edge and are dropped after), then
+            // the destination's azimuth extent, the class's reach and the MD
+            // range of every edge together: two round trips per group.
+            uint2 ed[kEdgeGroup];
+#pragma unroll
+            for (int j = 0; j < kEdgeGroup; j++) ed[j] = g.edge[min(eb + j, e1 > e0 ? e1 - 1u : 0u)];
+            float2 mp[kEdgeGroup];
+            float rch[kEdgeGroup];
+            uint32_t lo[kEdgeGroup], hi[kEdgeGroup];
+#pragma unroll
+            for (int j = 0; j < kEdgeGroup; j++) {
+                mp[j] = g.mod_phi[ed[j].x];
+                rch[j] = g.cls[ed[j].y].b.z;
+                lo[j] = b.md_off[ubase + ed[j].x];
+                hi[j] = b.md_off[ubase + ed[j].x + 1];
+            }
             uint32_t T = 0;
 #pragma unroll
             for (int j = 0; j < kEdgeGroup; j++) {
-                uint32_t bq = 0, eq = 0, cl = 0;
-                if (eb + j < e1) {
-                    const uint2 ed = g.edge[eb + j];
-                    cl = ed.y;
-                    if (in_reach(pha, g.mod_phi[ed.x], g.cls[cl].b.z)) {
-                        bq = min(b.md_off[ubase + ed.x], b.cap_md);
-                        eq = max(min(b.md_off[ubase + ed.x + 1], b.cap_md), bq);
-                    }
+                uint32_t bq = 0, eq = 0;
+                if (eb + j < e1 && in_reach(pha, mp[j], rch[j])) {
+                    bq = min(lo[j], b.cap_md);
+                    eq = max(min(hi[j], b.cap_md), bq);
                 }
                 T += eq - bq;
                 s_grp[wv][j][lane] = bq;
                 s_grp[wv][kEdgeGroup + j][lane] = T;  // cum[j + 1]
-                s_grp[wv][2 * kEdgeGroup + j][lane] = cl;
+                s_grp[wv][2 * kEdgeGroup + j][lane] = ed[j].y;
             }
             wave_lds_sync();
             const uint32_t incl = wave_incl_scan(T);
@@ -753,17 +812,25 @@ __global__ __launch_bounds__(256) void k_ls(const Batch b, Totals *t, const DevG
             const uint32_t total = __shfl(incl, 63);
             // two pooled rounds per step: the indices and loads of both are
             // issued before either cut, so that twice the loads are in flight
+            uint32_t carry = 0;                       // owner + 1 of the last candidate so far
             for (uint32_t cb = 0; cb < total; cb += 128u) {
                 uint32_t o[2], q[2];
                 float4 pq[2];
                 LsK kc[2];
+                // owners by a prefix maximum over marks at their first
+                // candidates, instead of a search over the lanes' offsets
+                s_mark[wv][lane] = 0u;
+                s_mark[wv][64u + lane] = 0u;
+                wave_lds_sync();
+                if (T != 0u && off >= cb && off < cb + 128u) s_mark[wv][off - cb] = lane + 1u;
+                wave_lds_sync();
+                uint32_t mk2[2] = {s_mark[wv][lane], s_mark[wv][64u + lane]};
 #pragma unroll
                 for (int r = 0; r < 2; r++) {
                     const uint32_t ci = cb + 64u * r + lane;
-                    uint32_t ow = 0;
-#pragma unroll
-                    for (uint32_t step = 32; step; step >>= 1)
-                        if (__shfl(off, ow + step) <= ci) ow += step;
+                    const uint32_t m = wave_incl_max(max(mk2[r], carry));
+                    carry = (uint32_t)__builtin_amdgcn_readlane((int)m, 63);
+                    const uint32_t ow = m - 1u;
                     // edge j of the owner's group: the last with cum[j] <= tt
                     // (lanes past the total read valid LDS and load entry 0)
                     const uint32_t tt = ci - __shfl(off, ow);
@@ -1090,9 +1157,10 @@ __device__ inline bool rz3(const Consts &c, const Anchor &A, const Anchor &B, co
 // it in the same 64), so k_t3_place can put them in canonical order.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_t3(const Batch b, Totals *t, const Consts c, uint32_t nsub, int stats)
 {
+    __shared__ uint32_t s_mark[4][64];   // pooled-candidate owner marks, one row per wave
     __shared__ uint32_t s_n;             // appends to this block's region
     const uint32_t n = min(t->n_ls, b.cap_ls);
-    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     const unsigned long long below = (1ull << lane) - 1ull;
     const uint32_t cap = b.cap_t3 / nsub;
     const size_t sb0 = (size_t)blockIdx.x * cap;
@@ -1121,13 +1189,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
         const uint32_t off = incl - cnt;                 // this lane's first pooled candidate
         const uint32_t total = __shfl(incl, 63);
         uint32_t run = 0;                                // survivors of this lane's LS so far
+        uint32_t carry = 0;
         for (uint32_t cb = 0; cb < total; cb += 64u) {
             const uint32_t ci = cb + lane;
             // owner: the last lane o with off_o <= ci (it has ci - off_o < cnt_o)
-            uint32_t o = 0;
-#pragma unroll
-            for (uint32_t step = 32; step; step >>= 1)
-                if (__shfl(off, o + step) <= ci) o += step;
+            const uint32_t o = pooled_owner(s_mark[wv], lane, cnt, off, cb, carry);
             const uint32_t o_q0 = __shfl(q0, o), o_off = __shfl(off, o), o_ia = __shfl(ia, o);
             const uint32_t o_l1 = __shfl(l1, o), o_run = __shfl(run, o);
             const float4 oa = make_float4(__shfl(pa.x, o), __shfl(pa.y, o), __shfl(pa.z, o), __shfl(pa.w, o));
@@ -1226,11 +1292,12 @@ __global__ __launch_bounds__(256) void k_t3_place(const Batch b, const DevGeom g
 // the T3 walk.  The stored-curvature test runs first (it needs no new
 // arithmetic).  Survivors go to the block's region of an unordered T5 list
 // with their place in the owner's list; k_t5_place puts them in order.
-__global__ __launch_bounds__(256) void k_t5(const Batch b, Totals *t, const Consts c, uint32_t nsub, int stats)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_t5(const Batch b, Totals *t, const Consts c, uint32_t nsub, int stats)
 {
+    __shared__ uint32_t s_mark[4][64];   // pooled-candidate owner marks, one row per wave
     __shared__ uint32_t s_n;             // appends to this block's region
     const uint32_t n = min(t->n_t3, b.cap_t3);
-    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     const unsigned long long below = (1ull << lane) - 1ull;
     const uint32_t cap = b.cap_t5 / nsub;
     const size_t sb0 = (size_t)blockIdx.x * cap;
@@ -1258,12 +1325,10 @@ __global__ __launch_bounds__(256) void k_t5(const Batch b, Totals *t, const Cons
         const uint32_t off = incl - cnt;
         const uint32_t total = __shfl(incl, 63);
         uint32_t run = 0;
+        uint32_t carry = 0;
         for (uint32_t cb = 0; cb < total; cb += 64u) {
             const uint32_t ci = cb + lane;
-            uint32_t o = 0;
-#pragma unroll
-            for (uint32_t step = 32; step; step >>= 1)
-                if (__shfl(off, o + step) <= ci) o += step;
+            const uint32_t o = pooled_owner(s_mark[wv], lane, cnt, off, cb, carry);
             const uint32_t o_w0 = __shfl(w0, o), o_off = __shfl(off, o), o_run = __shfl(run, o);
             const uint32_t o_u = __shfl(u, o);
             const float4 oa = make_float4(__shfl(pa.x, o), __shfl(pa.y, o), __shfl(pa.z, o), __shfl(pa.w, o));
@@ -1620,6 +1685,7 @@ __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Con
     // per lane: the starts of the eight ranges of its two bins, then the
     // cumulative sizes c1..c7
     __shared__ uint32_t s_rng[4][15][64];
+    __shared__ uint32_t s_mark[4][64];                // pooled-candidate owner marks, one row per wave
     __shared__ uint32_t s_n;                          // appends to this block's region
     const uint32_t n = min(t->n_pls, b.cap_pls) * c.n_surf;
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
@@ -1692,12 +1758,10 @@ __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Con
             const uint32_t incl = wave_incl_scan(T);
             const uint32_t off = incl - T;
             const uint32_t total = __shfl(incl, 63);
+            uint32_t carry = 0;
             for (uint32_t cb = 0; cb < total; cb += 64u) {
                 const uint32_t ci = cb + lane;
-                uint32_t o = 0;
-#pragma unroll
-                for (uint32_t step = 32; step; step >>= 1)
-                    if (__shfl(off, o + step) <= ci) o += step;
+                const uint32_t o = pooled_owner(s_mark[wv], lane, T, off, cb, carry);
                 const uint32_t o_off = __shfl(off, o), o_p = __shfl(p, o);
                 const double o_kp = __shfl(kp, o), o_skp = __shfl(skp, o);
                 const float o_plo = __shfl(rp.x, o), o_pw = __shfl(rp.y, o);
@@ -1910,6 +1974,124 @@ __global__ void k_tc_write(const Batch b, const Totals *t)
     }
 }
 
+// ------------------------------------------- track-candidate cleaning ---
+//
+// Candidates with outer-tracker MDs are compared pairwise through the MDs
+// they share: candidate i (i < n_pT5: pT5 i; otherwise the kept entry
+// i - n_pT5 of [pT3 | T5 | pLS]) is removed when another candidate that
+// ranks higher shares more than half of the smaller of the two MD sets.
+// Rank: type (pT5, pT3, T5), then the curvature disagreement q (binary64:
+// seed against object for pT5 / pT3, inner against outer T3 for a T5), then
+// the index in the candidate's own list.  Seed-only candidates are kept.
+
+__device__ inline uint32_t tcc_type(const Batch &b, uint32_t n5, uint32_t i)
+{
+    return i < n5 ? LST_TC_PT5 : b.tc_type[i - n5];
+}
+
+__device__ inline uint32_t tcc_index(const Batch &b, uint32_t n5, uint32_t i)
+{
+    return i < n5 ? i : b.tc_idx[i - n5];
+}
+
+// MD set and rank quality of every candidate; each MD counts its candidates
+// (the returned slot is the candidate's place in that MD's list)
+__global__ void k_tcc_prep(const Batch b, const Totals *t)
+{
+    const uint32_t n5 = min(t->n_pt5, b.cap_pt5);
+    const uint32_t n = n5 + min(t->n_tc, b.cap_tc);
+    GRID_STRIDE(i, n) {
+        const uint32_t typ = tcc_type(b, n5, i), idx = tcc_index(b, n5, i);
+        uint32_t nm = 0;
+        uint32_t m[5] = {0u, 0u, 0u, 0u, 0u};
+        double q = 0.0;
+        if (typ != LST_TC_PLS) {
+            uint32_t u, w = 0u, obj = 0u, seed = 0u;
+            if (typ == LST_TC_PT5) {
+                seed = b.pt5_p[idx];
+                obj = b.pt5_o[idx];
+                u = b.t5_u[obj];
+                w = b.t5_w[obj];
+            } else if (typ == LST_TC_PT3) {
+                seed = b.pt3_p[idx];
+                u = b.pt3_o[idx];
+            } else {
+                u = b.t5_u[idx];
+                w = b.t5_w[idx];
+            }
+            m[0] = b.t3_ac[u].x;
+            m[1] = b.ls_b[b.t3_l1[u]];
+            m[2] = b.t3_ac[u].y;
+            nm = 3u;
+            if (typ != LST_TC_PT3) {
+                m[3] = b.ls_b[b.t3_l1[w]];
+                m[4] = b.t3_ac[w].y;
+                nm = 5u;
+            }
+            if (typ == LST_TC_T5) {
+                const float2 ki = b.t3_ks[u], ko = b.t3_ks[w];
+                q = fabs((double)ki.x - (double)ko.x) / ((double)ki.y + (double)ko.y);
+            } else {
+                const double2 sk = reinterpret_cast<const double2 *>(b.pls_seed)[5 * (size_t)seed];
+                const float2 ko = typ == LST_TC_PT5 ? b.t5_ks[obj] : b.t3_ks[u];
+                q = fabs(sk.x - (double)ko.x) / (sk.y + (double)ko.y);
+            }
+        }
+        b.tcc_nm[i] = nm;
+        b.tcc_q[i] = q;
+        for (uint32_t k = 0; k < 5u; k++) {
+            b.tcc_md[5 * (size_t)i + k] = m[k];
+            if (k < nm) b.tcc_rank[5 * (size_t)i + k] = atomicAdd(&b.md_tcc_cnt[m[k]], 1u);
+        }
+    }
+}
+
+__global__ void k_tcc_fill(const Batch b, const Totals *t)
+{
+    const uint32_t n5 = min(t->n_pt5, b.cap_pt5);
+    const uint32_t n = n5 + min(t->n_tc, b.cap_tc);
+    GRID_STRIDE(i, n) {
+        const uint32_t nm = b.tcc_nm[i];
+        for (uint32_t k = 0; k < nm; k++)
+            b.md_tcc[b.md_tcc_off[b.tcc_md[5 * (size_t)i + k]] + b.tcc_rank[5 * (size_t)i + k]] = i;
+    }
+}
+
+__global__ void k_tcc_decide(const Batch b, const Totals *t)
+{
+    const uint32_t n5 = min(t->n_pt5, b.cap_pt5);
+    const uint32_t n = n5 + min(t->n_tc, b.cap_tc);
+    GRID_STRIDE(i, n) {
+        const uint32_t nm = b.tcc_nm[i];
+        bool keep = true;
+        if (nm) {
+            uint32_t m[5];
+            for (uint32_t k = 0; k < 5u; k++) m[k] = b.tcc_md[5 * (size_t)i + k];
+            const uint32_t ti = tcc_type(b, n5, i), xi = tcc_index(b, n5, i);
+            const double qi = b.tcc_q[i];
+            for (uint32_t k = 0; k < nm && keep; k++) {
+                const uint32_t e = b.md_tcc_off[m[k] + 1];
+                for (uint32_t s = b.md_tcc_off[m[k]]; s < e && keep; s++) {
+                    const uint32_t j = b.md_tcc[s];
+                    if (j == i) continue;
+                    const uint32_t tj = tcc_type(b, n5, j);
+                    const double qj = b.tcc_q[j];
+                    const bool better = tj < ti || (tj == ti && (qj < qi || (qj == qi && tcc_index(b, n5, j) < xi)));
+                    if (!better) continue;
+                    const uint32_t nj = b.tcc_nm[j];
+                    uint32_t shared = 0;
+                    for (uint32_t y = 0; y < nj; y++) {
+                        const uint32_t mj = b.tcc_md[5 * (size_t)j + y];
+                        for (uint32_t x = 0; x < nm; x++) shared += mj == m[x] ? 1u : 0u;
+                    }
+                    if (2u * shared > min(nm, nj)) keep = false;
+                }
+            }
+        }
+        b.tcc_keep[i] = keep ? 1u : 0u;
+    }
+}
+
 // per-event first index of every list (row n_ev holds the totals)
 __global__ void k_event_table(const Batch b, const Totals *t, const Consts c)
 {
@@ -1994,12 +2176,10 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     L.stage = LST_STAGE_INGEST;
     const uint32_t n_sl = (2u * n_mod + g.hist_slice - 1u) / g.hist_slice;
     const dim3 gh((unsigned)std::min<uint64_t>((uint64_t)b.cap_ev * n_sl, kMaxGrid));
-    L.launch_lds("hit_hist", k_hit_hist, gh, dim3(kHistBlock), g.hist_slice * 4u, b, t, g.mod_ext, n_mod,
-                 g.hist_slice);
+    L.launch_lds("hit_hist", k_hit_hist, gh, dim3(kHistBlock), g.hist_slice * 4u, b, t, n_mod, g.hist_slice);
     L.scan(b.bin_cnt, b.bin_off, &t->n_bins, b.cap_ev * 2u * n_mod, &t->n_sorted, "scan_hits");
     L.launch("hit_scatter", k_hit_scatter, grid_for(b.cap_hits), blk, b, (const Totals *)t);
-    L.launch("hit_gather", k_hit_gather, grid_for((uint64_t)b.cap_ev * 2 * n_mod), blk, b, (const Totals *)t,
-             n_mod);
+    L.launch("hit_gather", k_hit_gather, grid_for((uint64_t)b.cap_ev * 2 * n_mod), blk, b, t, g.mod_ext, n_mod);
     // a2: mini-doublets
     L.stage = LST_STAGE_MD;
     // small batches: count and fill in place for latency; large ones: pooled walk
@@ -2090,7 +2270,54 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     L.scan(b.tc_cnt, b.tc_off, &t->n_tcu, b.cap_pt3 + b.cap_t5 + b.cap_pls, &t->n_tc, "scan_tc");
     L.launch("tc_write", k_tc_write, grid_for((uint64_t)b.cap_pt3 + b.cap_t5 + b.cap_pls), blk, b,
              (const Totals *)t);
+    if (c.flags & LST_FLAG_TC_CLEAN) {
+        const uint64_t cap_tcc = (uint64_t)b.cap_pt5 + b.cap_tc;
+        L.launch("zero", k_zero_u32, grid_for((uint64_t)b.cap_md + 1), blk, b.md_tcc_cnt, &t->n_md, b.cap_md, 1u);
+        L.launch("tcc_prep", k_tcc_prep, grid_for(cap_tcc), blk, b, (const Totals *)t);
+        L.scan(b.md_tcc_cnt, b.md_tcc_off, &t->n_md, b.cap_md, &t->n_tccm, "scan_tcc");
+        L.launch("tcc_fill", k_tcc_fill, grid_for(cap_tcc), blk, b, (const Totals *)t);
+        L.launch("tcc_decide", k_tcc_decide, grid_for(cap_tcc), blk, b, (const Totals *)t);
+    }
     L.launch("event_table", k_event_table, grid_for(b.cap_ev + 1), blk, b, (const Totals *)t, c);
+}
+
+// Served events arrive as one block per event in host order
+// [x | y | z | module | sensor | seed parameters | seed covariance], each
+// part starting at a multiple of 16 bytes (served_block_bytes); the blocks
+// are copied to the device as they are and unpacked here into the batch's
+// arrays.
+__device__ inline uint32_t pad16(uint32_t v) { return (v + 15u) & ~15u; }
+
+__global__ void k_unpack(const Batch b, const Totals *t, const char *__restrict__ raw,
+                         const unsigned long long *__restrict__ raw_off)
+{
+    const uint32_t n_ev = t->n_ev, nh = min(t->n_hits, b.cap_hits), np = min(t->n_pls, b.cap_pls);
+    GRID_STRIDE(h, nh) {
+        const uint32_t e = find_event(b.ev_hit_off, n_ev, h);
+        const uint32_t i = h - b.ev_hit_off[e], n = b.ev_hit_off[e + 1] - b.ev_hit_off[e];
+        const char *blk = raw + raw_off[e];
+        const uint32_t s4 = pad16(4u * n);
+        b.in_x[h] = reinterpret_cast<const float *>(blk)[i];
+        b.in_y[h] = reinterpret_cast<const float *>(blk + s4)[i];
+        b.in_z[h] = reinterpret_cast<const float *>(blk + 2u * s4)[i];
+        b.in_mod[h] = reinterpret_cast<const uint32_t *>(blk + 3u * s4)[i];
+        b.in_sen[h] = reinterpret_cast<const uint8_t *>(blk + 4u * s4)[i];
+    }
+    GRID_STRIDE(p, np) {
+        const uint32_t e = find_event(b.ev_pls_off, n_ev, p);
+        const uint32_t j = p - b.ev_pls_off[e], m = b.ev_pls_off[e + 1] - b.ev_pls_off[e];
+        const uint32_t n = b.ev_hit_off[e + 1] - b.ev_hit_off[e];
+        const char *par = raw + raw_off[e] + 4u * pad16(4u * n) + pad16(n);
+        const float *pp = reinterpret_cast<const float *>(par) + 5u * j;
+        const float *pc = reinterpret_cast<const float *>(par + pad16(20u * m)) + 15u * j;
+        for (uint32_t w = 0; w < 5u; w++) b.in_par[5u * (size_t)p + w] = pp[w];
+        for (uint32_t w = 0; w < 15u; w++) b.in_cov[15u * (size_t)p + w] = pc[w];
+    }
+}
+
+void launch_unpack(Launcher &L, const Batch &b, const Totals *t, const char *raw, const unsigned long long *raw_off)
+{
+    L.launch("unpack", k_unpack, grid_for(b.cap_hits), dim3(256), b, t, raw, raw_off);
 }
 
 void launch_setup(Launcher &L, const Batch &b, Totals *t, const Consts &c)

@@ -22,6 +22,7 @@ STATUS = {0: "OK", 1: "PENDING", -1: "INVALID_ARG", -2: "DEVICE", -3: "NO_GEOMET
           -8: "TOO_LARGE", -9: "QUEUE_FULL", -10: "UNKNOWN_TICKET", -11: "HIT_OUTSIDE"}
 LST_FLAG_BEND = 1
 LST_FLAG_STAGE_TIMES = 2
+LST_FLAG_TC_CLEAN = 4
 STAGES = ("ingest", "md", "ls", "t3", "t5", "seed_lookup", "pt", "tc")
 LST_DEVICE_PTRS = 1
 TC_PT5, TC_PT3, TC_T5, TC_PLS = 0, 1, 2, 3
@@ -67,7 +68,7 @@ class lst_event_out(C.Structure):
                 ("latency_us", C.c_double), ("ticket", C.c_uint64),
                 ("n_flag_regrow", C.c_uint32), ("n_stage", C.c_uint32),
                 ("stage_ns", C.c_uint64 * len(STAGES)), ("batch_events", C.c_uint32),
-                ("pad", C.c_uint32), ("footprint", C.c_uint64)]
+                ("n_tcc", C.c_uint32), ("footprint", C.c_uint64), ("tcc", C.POINTER(C.c_uint32))]
 
 
 _P = C.POINTER
@@ -139,6 +140,8 @@ def default_params(**kw) -> lst_params:
             p.flags = (p.flags & ~LST_FLAG_BEND) | (LST_FLAG_BEND if v else 0)
         elif k == "stage_times":
             p.flags = (p.flags & ~LST_FLAG_STAGE_TIMES) | (LST_FLAG_STAGE_TIMES if v else 0)
+        elif k == "tc_clean":
+            p.flags = (p.flags & ~LST_FLAG_TC_CLEAN) | (LST_FLAG_TC_CLEAN if v else 0)
         elif k == "stream":
             # a torch.cuda.Stream, or a raw hipStream_t handle
             p.stream = C.c_void_p(int(getattr(v, "cuda_stream", v)) if v is not None else None)
@@ -212,6 +215,7 @@ def _out_to_dict(o: lst_event_out) -> dict:
     d["ticket"] = o.ticket
     d["n_flag_regrow"] = o.n_flag_regrow
     d["batch_events"] = o.batch_events
+    d["tcc"] = pairs(o.tcc, o.n_tcc) if o.tcc else None
     d["footprint"] = o.footprint
     d["stage_ns"] = {name: int(o.stage_ns[i]) for i, name in enumerate(STAGES)}
     return d
@@ -294,15 +298,27 @@ class Context:
         self._check(self.L.lst_submit(self.h, C.byref(e.c), C.byref(t)))
         return t.value
 
-    def poll(self, ticket: int, timeout_us: int = -1):
-        """Returns the output dict, or None while pending."""
+    def submit_in(self, e: EventIn) -> int:
+        """lst_submit of an event already marshalled (EventIn)."""
+        t = C.c_uint64()
+        self._check(self.L.lst_submit(self.h, C.byref(e.c), C.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int, timeout_us: int = -1, fetch: bool = True):
+        """Returns the output dict, or None while pending.  fetch=False returns
+        only the diagnostics (latency, ticket, batch size, footprint) and
+        drops the lists."""
         o = _P(lst_event_out)()
         st = self.L.lst_poll(self.h, ticket, timeout_us, C.byref(o))
         if st == LST_PENDING:
             return None
         try:
             self._check(st)
-            return _out_to_dict(o.contents)
+            if fetch:
+                return _out_to_dict(o.contents)
+            c = o.contents
+            return dict(latency_us=c.latency_us, ticket=c.ticket, batch_events=c.batch_events,
+                        footprint=c.footprint)
         finally:
             if o:
                 self.L.lst_free_output(o)
@@ -379,4 +395,7 @@ def result_keys(res: dict) -> dict:
     pt5 = [(int(p),) + t5[v] for p, v in res["pt5"]]
     src = {0: pt5, 1: pt3, 2: t5}
     tc = [(int(t),) + (src[int(t)][i] if int(t) in src else (int(i),)) for t, i in res["tc"]]
-    return dict(md=md, ls=ls, t3=t3, t5=t5, pt3=pt3, pt5=pt5, tc=tc)
+    out = dict(md=md, ls=ls, t3=t3, t5=t5, pt3=pt3, pt5=pt5, tc=tc)
+    if res.get("tcc") is not None:
+        out["tcc"] = [(int(t),) + (src[int(t)][i] if int(t) in src else (int(i),)) for t, i in res["tcc"]]
+    return out

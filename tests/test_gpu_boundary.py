@@ -187,7 +187,7 @@ def test_served_queue_full_and_too_large(g):
             try:
                 tickets.append(c.submit(ev))
             except lst.LstError as e:
-                assert e.value.name == "QUEUE_FULL"
+                assert e.name == "QUEUE_FULL"
                 full += 1
         assert full > 0 and len(tickets) >= 2
         for t in tickets:

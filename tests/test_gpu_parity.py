@@ -289,3 +289,55 @@ def test_parity_disk_only(ctx, geo):
     check_canonical(res, ev2)
     check_parity(g, ev2, res)
     assert len(res["t3"]) > 100 and len(res["ls"]) > 1000
+
+
+def _md_pairs(key):
+    """MDs (hit pairs) of a candidate key: (type, [seed,] hits...)."""
+    hits = key[2:] if key[0] in (0, 1) else key[1:] if key[0] == 2 else ()
+    return {(hits[i], hits[i + 1]) for i in range(0, len(hits), 2)}
+
+
+def _oracle_cleaned(geom, ev):
+    """The oracle's accepted candidates and the subset its duplicate cleaning
+    keeps, as keys, and the candidates whose cleaning may depend on a
+    borderline one: the flagged candidates and every candidate sharing an MD
+    with one of them (a device that kept or dropped the flagged candidate
+    may rank its neighbours differently)."""
+    ores = oracle.run(geom, ev)
+    ks = oracle.object_keys(ores["md"], ores["ls"], ores["t3"], ores["t5"], ores["pt3"], ores["pt5"],
+                            ores["tc"])["tc"]
+    st = ores["tc_st"]
+    acc = [k for k, q in zip(ks, st) if q & oracle.ST_ACC]
+    kept = [k for k, q, f in zip(ks, st, ores["tc_keep"]) if (q & oracle.ST_ACC) and f]
+    flagged = [k for k, q in zip(ks, st) if q & oracle.ST_FLAG]
+    fl_mds = set().union(*[_md_pairs(k) for k in flagged]) if flagged else set()
+    affected = {k for k in ks if k in set(flagged) or _md_pairs(k) & fl_mds}
+    return acc, kept, set(flagged), affected
+
+
+def test_tc_cleaning_parity(geo):
+    """Duplicate cleaning of the track candidates: the kept subset equals the
+    oracle's, for single events and inside a batch; it removes most
+    candidates and never a seed-only one."""
+    g = geo["pu200"]
+    evs = [s.gen_event(g, s.config_pu(200), s.event_seed(2, i)) for i in (0, 1)]
+    evs.append(s.gen_event(g, s.config_pu(300, noise_frac=0.4, fake_frac=0.05), s.event_seed(5, 2)))
+    with lst.Context(tc_clean=True, max_batch=8) as c:
+        c.load_geometry(g)
+        singles = [c.run_event(ev) for ev in evs]
+        batch = c.run_batch(evs)
+    for ev, r, rb in zip(evs, singles, batch):
+        acc, kept, flagged, affected = _oracle_cleaned(g, ev)
+        got = lst.result_keys(r)
+        print("candidates", len(acc), "kept", len(kept), "flagged", len(flagged), "affected", len(affected), flush=True)
+        assert len(affected) <= 0.01 * len(acc)
+        assert set(got["tc"]) - flagged == set(acc) - flagged
+        assert len(got["tcc"]) == len(set(got["tcc"]))
+        assert set(got["tcc"]) - affected == set(kept) - affected
+        assert np.array_equal(r["tcc"], rb["tcc"])
+        assert len(kept) < 0.5 * len(acc)
+        n_pls = int((r["tc"][:, 0] == lst.TC_PLS).sum())
+        assert int((r["tcc"][:, 0] == lst.TC_PLS).sum()) == n_pls
+    with lst.Context() as c:
+        c.load_geometry(g)
+        assert c.run_event(evs[0])["tcc"] is None
