@@ -281,6 +281,38 @@ lst_status lst_batch_download(lst_ctx *ctx, lst_event_out **outs);
  * pt3 / pt5 candidates that reach the full seed cuts (15 values). */
 lst_status lst_batch_counts(lst_ctx *ctx, uint64_t counts[15]);
 
+/* Output of lst_run_event_noalloc: the lists of lst_event_out (same pairs,
+ * same canonical order) written into device buffers the caller owns, each
+ * holding 2 x cap_* uint32 (t3_kappa: cap_t3 floats, or NULL).  The library
+ * sets the n_* fields. */
+typedef struct {
+    uint32_t *md, *ls, *t3, *t5, *pt3, *pt5, *tc;
+    float *t3_kappa;
+    uint32_t cap_md, cap_ls, cap_t3, cap_t5, cap_pt3, cap_pt5, cap_tc;
+    uint32_t n_md, n_ls, n_t3, n_t5, n_pt3, n_pt5, n_tc;
+} lst_event_dev_out;
+
+#define LST_NOALLOC_MAX_HITS 131072u
+#define LST_NOALLOC_MAX_PLS 8192u
+#define LST_NOALLOC_WORKSPACE_BYTES (128ull << 20)
+
+/* lst_run_event for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, hosts that forbid allocation): the
+ * call makes no device or pinned-host allocation.  Every intermediate buffer
+ * lives in a fixed workspace of LST_NOALLOC_WORKSPACE_BYTES that the library
+ * holds on each GPU it runs on (a static device array, kept until the process
+ * ends); inputs must be device pointers (LST_DEVICE_PTRS) of at most
+ * LST_NOALLOC_MAX_HITS hits and LST_NOALLOC_MAX_PLS seeds, and the outputs go
+ * to the caller's device buffers in *out.  The work runs on `stream`
+ * (hipStream_t; NULL: the null stream) and is complete when the call returns.
+ * Calls on one GPU share its workspace, which keeps the last call's contents:
+ * the library serialises them within a process (concurrent callers wait).
+ * Errors: as lst_run_event; INVALID_ARG (host pointers, a null output buffer
+ * that the event needs); TOO_LARGE (inputs above the limits, object lists that
+ * do not fit the workspace, or an output buffer below the event's count -- the
+ * n_* fields then give the sizes needed; nothing is written). */
+lst_status lst_run_event_noalloc(lst_ctx *ctx, const lst_event_in *ev, lst_event_dev_out *out, void *stream);
+
 void lst_free_output(lst_event_out *out);
 
 /* Drains in-flight served events, then frees everything. */

@@ -234,6 +234,21 @@ struct Slot {
 
 }  // namespace lst
 
+// Workspace of lst_run_event_noalloc: every device buffer that call needs
+// beyond its inputs and outputs (counters, scan partials, sorted hits, the
+// object lists of every stage) is carved from this array, so the call makes
+// no device allocation.  Each GPU the library runs on holds its own copy
+// until the process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns on that device (noalloc_ws).
+namespace {
+constexpr size_t kScratchBytes = LST_NOALLOC_WORKSPACE_BYTES;
+constexpr int kMaxDevices = 64;
+std::mutex g_ws_mu;                          // guards g_ws
+void *g_ws[kMaxDevices] = {};                // address of scratch on each device
+std::mutex g_ws_run_mu[kMaxDevices];         // serialises the calls on one device
+}  // namespace
+static __device__ __align__(256) char scratch[kScratchBytes];
+
 // Pinned host blocks that hold submitted events until their micro-batch is
 // copied to the device; freed blocks are kept per size class and reused.
 struct PinnedPool {
@@ -291,6 +306,7 @@ struct ServedEvent {
 struct lst_ctx {
     lst_params p{};
     int device = 0;
+    void *ws = nullptr;                 // this device's copy of scratch (lst_run_event_noalloc)
     std::atomic<bool> failed{false};
     mutable std::mutex err_mu;
     std::string last_error;
@@ -1098,6 +1114,19 @@ lst_status lst_create(const lst_params *p, lst_ctx **out)
     if (!ctx) return LST_ERR_OOM;
     ctx->p = prm;
     ctx->device = prm.device;
+    // the device address of the no-allocation workspace, once per device
+    // (with the device current); a failure leaves only that entry point
+    // unusable
+    if (prm.device < kMaxDevices) {
+        std::lock_guard<std::mutex> g(g_ws_mu);
+        if (!g_ws[prm.device]) {
+            void *ptr = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e == hipSuccess && ptr) g_ws[prm.device] = ptr;
+            else (void)hipGetLastError();
+        }
+        ctx->ws = g_ws[prm.device];
+    }
     *out = ctx;
     return LST_OK;
 }
@@ -1481,6 +1510,109 @@ lst_status lst_poll(lst_ctx *ctx, uint64_t ticket, int64_t timeout_us, lst_event
     *out = o;
     if (!o) return LST_ERR_OOM;
     if (o->status != (uint32_t)LST_OK) return (lst_status)(int32_t)o->status;
+    return LST_OK;
+}
+
+lst_status lst_run_event_noalloc(lst_ctx *ctx, const lst_event_in *ev, lst_event_dev_out *out, void *stream)
+{
+    lst_status st = check_ctx(ctx, true);
+    if (st != LST_OK) return st;
+    if (!ev || !out) return set_err(ctx, LST_ERR_INVALID_ARG, "null event or output");
+    if (!(ev->flags & LST_DEVICE_PTRS)) return set_err(ctx, LST_ERR_INVALID_ARG, "inputs must be device pointers");
+    st = check_event(ctx, *ev);
+    if (st != LST_OK) return st;
+    if (!ctx->ws) return set_err(ctx, LST_ERR_DEVICE, "no-allocation workspace unavailable on this device");
+    if (ev->n_hits > LST_NOALLOC_MAX_HITS || ev->n_pls > LST_NOALLOC_MAX_PLS)
+        return set_err(ctx, LST_ERR_TOO_LARGE, "event above the no-allocation workspace's limits");
+    std::lock_guard<std::mutex> run(g_ws_run_mu[ctx->device]);
+    HIP_TRY(hipSetDevice(ctx->device));
+    const hipStream_t sm = (hipStream_t)stream;
+    const lst::Consts &k = ctx->geom.c;
+    // fixed part of the workspace: counters, scan partials, event offsets
+    char *ws = (char *)ctx->ws;
+    lst::Totals *d_tot = (lst::Totals *)ws;
+    uint32_t *part = (uint32_t *)(ws + lst::align_up(sizeof(lst::Totals)));
+    uint32_t *offs = part + lst::kScanGrid;
+    const size_t fixed = lst::align_up(sizeof(lst::Totals)) + lst::align_up(4ull * lst::kScanGrid + 16);
+    Batch b{};
+    b.cap_ev = 1;
+    b.cap_hits = std::max<uint32_t>(ev->n_hits, 1);
+    b.cap_pls = std::max<uint32_t>(ev->n_pls, 1);
+    b.in_x = const_cast<float *>(ev->x);
+    b.in_y = const_cast<float *>(ev->y);
+    b.in_z = const_cast<float *>(ev->z);
+    b.in_mod = const_cast<uint32_t *>(ev->module);
+    b.in_sen = const_cast<uint8_t *>(ev->sensor);
+    b.in_par = const_cast<float *>(ev->pls_par);
+    b.in_cov = const_cast<float *>(ev->pls_cov);
+    b.ev_hit_off = offs;
+    b.ev_pls_off = offs + 2;
+    lst::Caps c = lst::plan_caps(1, ev->n_hits, ev->n_pls);
+    b.cap_md = c.md; b.cap_ls = c.ls; b.cap_t3 = c.t3; b.cap_t5 = c.t5;
+    b.cap_pt3 = c.pt3; b.cap_pt5 = c.pt5; b.cap_ptc3 = c.ptc3; b.cap_ptc5 = c.ptc5;
+    lst::Launcher L;
+    L.stream = sm;
+    L.side = nullptr;
+    L.cur = sm;
+    L.part = part;
+    lst::Totals tot{};
+    for (int attempt = 0;; attempt++) {
+        b.cap_tc = b.cap_pt3 + b.cap_t5 + b.cap_pls;
+        lst::Carver cw{nullptr};
+        lst::carve_work(cw, b, k.n_mod, k.n_surf, k.nphi, k.nkb);
+        if (fixed + cw.off > kScratchBytes || attempt >= 6)
+            return set_err(ctx, LST_ERR_TOO_LARGE,
+                           "object lists of this event do not fit the no-allocation workspace (" +
+                               std::to_string((fixed + cw.off) >> 20) + " MiB needed)");
+        lst::Carver cw2{ws + fixed};
+        lst::carve_work(cw2, b, k.n_mod, k.n_surf, k.nphi, k.nkb);
+        lst::launch_event_init(L, b, d_tot, ev->n_hits, ev->n_pls);
+        lst::enqueue_chain(L, b, d_tot, ctx->dg, k, 0);
+        if (L.err != hipSuccess) {
+            fail(ctx, std::string("kernel launch: ") + hipGetErrorString(L.err));
+            return LST_ERR_DEVICE;
+        }
+        HIP_TRY(hipMemcpyAsync(&tot, d_tot, sizeof tot, hipMemcpyDeviceToHost, sm));
+        HIP_TRY(hipStreamSynchronize(sm));
+        st = input_error(ctx, tot.err);
+        if (st != LST_OK) return st;
+        // a list that overflowed: larger capacities inside the same workspace
+        auto grow = [](uint32_t need, uint32_t &cap) {
+            if (need <= cap) return false;
+            cap = lst::clamp32((uint64_t)need + need / 4 + 1024);
+            return true;
+        };
+        bool g = false;
+        g |= grow(std::max(tot.n_md, tot.n_mds), b.cap_md);
+        g |= grow(std::max(tot.n_ls, tot.n_lss), b.cap_ls);
+        g |= grow(std::max(tot.n_t3, tot.n_t3s), b.cap_t3);
+        g |= grow(std::max(tot.n_t5, tot.n_t5s), b.cap_t5);
+        g |= grow(tot.n_pt3, b.cap_pt3);
+        g |= grow(tot.n_pt5, b.cap_pt5);
+        g |= grow(tot.n_ptc3, b.cap_ptc3);
+        g |= grow(tot.n_ptc5, b.cap_ptc5);
+        if (!g) break;
+    }
+    out->n_md = tot.n_md; out->n_ls = tot.n_ls; out->n_t3 = tot.n_t3; out->n_t5 = tot.n_t5;
+    out->n_pt3 = tot.n_pt3; out->n_pt5 = tot.n_pt5; out->n_tc = tot.n_pt5 + tot.n_tc;
+    if (out->n_md > out->cap_md || out->n_ls > out->cap_ls || out->n_t3 > out->cap_t3 ||
+        out->n_t5 > out->cap_t5 || out->n_pt3 > out->cap_pt3 || out->n_pt5 > out->cap_pt5 ||
+        out->n_tc > out->cap_tc)
+        return set_err(ctx, LST_ERR_TOO_LARGE, "output buffers too small (the counts give the sizes needed)");
+    const uint64_t items = (uint64_t)out->n_md + out->n_ls + out->n_t3 + out->n_t5 + out->n_pt3 + out->n_pt5 +
+                           out->n_tc;
+    if ((out->n_md && !out->md) || (out->n_ls && !out->ls) || (out->n_t3 && !out->t3) || (out->n_t5 && !out->t5) ||
+        (out->n_pt3 && !out->pt3) || (out->n_pt5 && !out->pt5) || (out->n_tc && !out->tc))
+        return set_err(ctx, LST_ERR_INVALID_ARG, "null output buffer");
+    if (items) {
+        const lst::EventOut o{out->md, out->ls, out->t3, out->t5, out->pt3, out->pt5, out->tc, out->t3_kappa};
+        lst::launch_event_out(L, b, d_tot, o, items);
+        if (L.err != hipSuccess) {
+            fail(ctx, std::string("kernel launch: ") + hipGetErrorString(L.err));
+            return LST_ERR_DEVICE;
+        }
+        HIP_TRY(hipStreamSynchronize(sm));
+    }
     return LST_OK;
 }
 

@@ -253,6 +253,16 @@ struct Launcher {
 
 void launch_setup(Launcher &L, const Batch &b, Totals *t, const Consts &c);
 
+// Object lists of a one-event batch written as the pairs of lst_event_out,
+// into buffers the caller owns (device memory).
+struct EventOut {
+    uint32_t *md, *ls, *t3, *t5, *pt3, *pt5, *tc;
+    float *t3_kappa;         // may be null
+};
+// One event staged by kernel arguments alone: n_ev = 1 and the event's hit
+// and seed offsets written on the device (no host copy).
+void launch_event_init(Launcher &L, const Batch &b, Totals *t, uint32_t n_hits, uint32_t n_pls);
+
 // Bytes of one served event's host block and the offsets of its parts
 // (x, y, z, module, sensor, seed parameters, seed covariance), every part
 // aligned to 16 bytes; k_unpack reads the same layout.
@@ -275,6 +285,7 @@ inline BlockLayout served_block_layout(uint32_t n_hits, uint32_t n_pls)
     return l;
 }
 void launch_unpack(Launcher &L, const Batch &b, const Totals *t, const char *raw, const unsigned long long *raw_off);
+void launch_event_out(Launcher &L, const Batch &b, const Totals *t, const EventOut &o, uint64_t n_items);
 void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, const Consts &c, int stats);
 
 }  // namespace lst

@@ -2281,6 +2281,49 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     L.launch("event_table", k_event_table, grid_for(b.cap_ev + 1), blk, b, (const Totals *)t, c);
 }
 
+__global__ void k_event_init(Totals *t, uint32_t *__restrict__ hit_off, uint32_t *__restrict__ pls_off,
+                             uint32_t n_hits, uint32_t n_pls)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        t->n_ev = 1u;
+        t->n_hits = n_hits;
+        t->n_pls = n_pls;
+        hit_off[0] = 0u;
+        hit_off[1] = n_hits;
+        pls_off[0] = 0u;
+        pls_off[1] = n_pls;
+    }
+}
+
+// The lists of a one-event batch as flat pairs: MD (lower, upper input hit),
+// LS (inner, outer MD), T3 (inner, outer LS), T5 (inner, outer T3), pT3 /
+// pT5 (seed, object), TC (type, index): every pT5, then the kept pT3s, T5s
+// and seeds in the order of the keep flags.
+__global__ void k_event_out(const Batch b, const Totals *t, const EventOut o)
+{
+    const uint32_t nmd = t->n_md, nls = t->n_ls, nt3 = t->n_t3, nt5 = t->n_t5;
+    const uint32_t np3 = t->n_pt3, np5 = t->n_pt5, ntc = t->n_tc;
+    const uint64_t n = (uint64_t)nmd + nls + nt3 + nt5 + np3 + np5 + np5 + ntc;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t k = i;
+        uint32_t *dst;
+        uint32_t a, c;
+        if (k < nmd) { dst = o.md; a = b.md_hlo[k]; c = b.md_hup[k]; }
+        else if ((k -= nmd) < nls) { dst = o.ls; a = b.ls_a[k]; c = b.ls_b[k]; }
+        else if ((k -= nls) < nt3) {
+            dst = o.t3; a = b.t3_l1[k]; c = b.t3_l2[k];
+            if (o.t3_kappa) o.t3_kappa[k] = b.t3_ks[k].x;
+        }
+        else if ((k -= nt3) < nt5) { dst = o.t5; a = b.t5_u[k]; c = b.t5_w[k]; }
+        else if ((k -= nt5) < np3) { dst = o.pt3; a = b.pt3_p[k]; c = b.pt3_o[k]; }
+        else if ((k -= np3) < np5) { dst = o.pt5; a = b.pt5_p[k]; c = b.pt5_o[k]; }
+        else if ((k -= np5) < np5) { dst = o.tc; a = LST_TC_PT5; c = (uint32_t)k; }
+        else { k -= np5; dst = o.tc + 2u * np5; a = b.tc_type[k]; c = b.tc_idx[k]; }
+        dst[2 * k] = a;
+        dst[2 * k + 1] = c;
+    }
+}
+
 // Served events arrive as one block per event in host order
 // [x | y | z | module | sensor | seed parameters | seed covariance], each
 // part starting at a multiple of 16 bytes (served_block_bytes); the blocks
@@ -2318,6 +2361,16 @@ __global__ void k_unpack(const Batch b, const Totals *t, const char *__restrict_
 void launch_unpack(Launcher &L, const Batch &b, const Totals *t, const char *raw, const unsigned long long *raw_off)
 {
     L.launch("unpack", k_unpack, grid_for(b.cap_hits), dim3(256), b, t, raw, raw_off);
+}
+
+void launch_event_init(Launcher &L, const Batch &b, Totals *t, uint32_t n_hits, uint32_t n_pls)
+{
+    L.launch("event_init", k_event_init, dim3(1), dim3(64), t, b.ev_hit_off, b.ev_pls_off, n_hits, n_pls);
+}
+
+void launch_event_out(Launcher &L, const Batch &b, const Totals *t, const EventOut &o, uint64_t n_items)
+{
+    L.launch("event_out", k_event_out, grid_for(n_items), dim3(256), b, t, o);
 }
 
 void launch_setup(Launcher &L, const Batch &b, Totals *t, const Consts &c)

@@ -26,6 +26,7 @@ LST_FLAG_TC_CLEAN = 4
 STAGES = ("ingest", "md", "ls", "t3", "t5", "seed_lookup", "pt", "tc")
 LST_DEVICE_PTRS = 1
 TC_PT5, TC_PT3, TC_T5, TC_PLS = 0, 1, 2, 3
+NOALLOC_MAX_HITS, NOALLOC_MAX_PLS = 131072, 8192
 
 
 class LstError(RuntimeError):
@@ -71,6 +72,14 @@ class lst_event_out(C.Structure):
                 ("n_tcc", C.c_uint32), ("footprint", C.c_uint64), ("tcc", C.POINTER(C.c_uint32))]
 
 
+_LISTS = ("md", "ls", "t3", "t5", "pt3", "pt5", "tc")
+
+
+class lst_event_dev_out(C.Structure):
+    _fields_ = ([(k, C.c_void_p) for k in _LISTS] + [("t3_kappa", C.c_void_p)]
+                + [("cap_" + k, C.c_uint32) for k in _LISTS] + [("n_" + k, C.c_uint32) for k in _LISTS])
+
+
 _P = C.POINTER
 _lib = None
 
@@ -103,6 +112,7 @@ def load(path: str = LIB_PATH):
         "lst_batch_download": (C.c_int32, [C.c_void_p, _P(_P(lst_event_out))]),
         "lst_batch_counts": (C.c_int32, [C.c_void_p, _P(C.c_uint64)]),
         "lst_time_only": (C.c_int32, [C.c_void_p, C.c_char_p]),
+        "lst_run_event_noalloc": (C.c_int32, [C.c_void_p, _P(lst_event_in), _P(lst_event_dev_out), C.c_void_p]),
         "lst_free_output": (None, [_P(lst_event_out)]),
         "lst_destroy": (None, [C.c_void_p]),
         "lst_status_str": (C.c_char_p, [C.c_int32]),
@@ -322,6 +332,27 @@ class Context:
         finally:
             if o:
                 self.L.lst_free_output(o)
+
+    def run_event_noalloc(self, ev: dict, bufs: dict, t3_kappa=None, stream=None) -> dict:
+        """lst_run_event_noalloc: ev holds torch tensors on the device; bufs
+        maps each list name (md, ls, t3, t5, pt3, pt5, tc) to a caller-owned
+        (capacity, 2) 32-bit integer device tensor.  Returns the counts; the
+        pairs are in the first count rows of each buffer."""
+        e = EventIn(ev)
+        o = lst_event_dev_out()
+        for k in _LISTS:
+            t = bufs[k]
+            setattr(o, k, C.c_void_p(t.data_ptr()) if t.numel() else None)
+            setattr(o, "cap_" + k, int(t.shape[0]))
+        o.t3_kappa = C.c_void_p(t3_kappa.data_ptr()) if t3_kappa is not None else None
+        sp = C.c_void_p(int(getattr(stream, "cuda_stream", stream))) if stream is not None else None
+        st = self.L.lst_run_event_noalloc(self.h, C.byref(e.c), C.byref(o), sp)
+        counts = {k: int(getattr(o, "n_" + k)) for k in _LISTS}
+        if st < 0:
+            err = LstError(st, self.L.lst_last_error(self.h).decode())
+            err.counts = counts
+            raise err
+        return counts
 
     # -- device-resident path ----------------------------------------------
     def batch_upload(self, evs: list):

@@ -117,7 +117,8 @@ def _c_layout(struct: str, fields: list) -> dict:
 
 
 @pytest.mark.parametrize("cls,struct", [(lst.lst_params, "lst_params"), (lst.lst_event_in, "lst_event_in"),
-                                        (lst.lst_event_out, "lst_event_out")])
+                                        (lst.lst_event_out, "lst_event_out"),
+                                        (lst.lst_event_dev_out, "lst_event_dev_out")])
 def test_struct_layout_matches_header(lib, cls, struct):
     """The binding's ctypes structs have the header's size and field offsets
     (stage_ns and n_flag_regrow of the output, the caller stream of the
