@@ -296,20 +296,34 @@ def main():
         kt1 = ctx1.kernel_times()
         per_event_kernels = {k: round(v[0] / 10, 4) for k, v in sorted(kt1.items(), key=lambda kv: -kv[1][0])[:12]}
         log("per-event kernel ms:", per_event_kernels)
-        # end to end: host inputs in, host outputs back (lst_run_event)
-        e2e = []
-        for i in range(min(B, 32)):
+        # end to end: host inputs in, host outputs back (lst_run_event), over
+        # 200 events with PU ~ U[140, 200]: the library call alone, and with
+        # the binding's conversion of the lists to numpy
+        e2e_evs = pool4[:200]
+        for ev in e2e_evs[:3]:
+            ctx1.run_event(ev)
+        ins = [lst.EventIn(ev) for ev in e2e_evs]
+        e2e, e2e_py = [], []
+        for e in ins:
             t1 = time.perf_counter()
-            ctx1.run_event(events[i])
+            ctx1.run_event_in(e, fetch=False)
             e2e.append(time.perf_counter() - t1)
+        for e in ins:
+            t1 = time.perf_counter()
+            ctx1.run_event_in(e, fetch=True)
+            e2e_py.append(time.perf_counter() - t1)
         ctx1.close()
-        e2e_us = np.array(e2e[2:]) * 1e6
+        e2e_us = np.array(e2e) * 1e6
+        e2e_py_us = np.array(e2e_py) * 1e6
         result["per_event"] = dict(events_per_s=round(per_event_rate, 2),
                                    latency_us_p50=round(float(np.percentile(lat_us, 50)), 1),
                                    latency_us_p99=round(float(np.percentile(lat_us, 99)), 1),
                                    e2e_events_per_s=round(1e6 / e2e_us.mean(), 2),
                                    e2e_latency_us_p50=round(float(np.percentile(e2e_us, 50)), 1),
-                                   e2e_latency_us_p99=round(float(np.percentile(e2e_us, 99)), 1))
+                                   e2e_latency_us_p99=round(float(np.percentile(e2e_us, 99)), 1),
+                                   e2e_events="200, PU ~ U[140, 200]",
+                                   e2e_python_latency_us_p50=round(float(np.percentile(e2e_py_us, 50)), 1),
+                                   e2e_python_latency_us_p99=round(float(np.percentile(e2e_py_us, 99)), 1))
         result["per_event_kernel_ms"] = per_event_kernels
         result["batched_over_per_event"] = round(value / per_event_rate, 2)
         log("per-event:", result["per_event"])
@@ -321,6 +335,9 @@ def main():
         ctx.batch_execute(args.steps, graph=True)
         result["mixed_pu50_250_batch64_events_per_s"] = round(64 / ((time.perf_counter() - t1) / args.steps), 2)
         log("mixed batch:", result["mixed_pu50_250_batch64_events_per_s"])
+        # ---- cost of a stage boundary: launches vs a persistent kernel ---------
+        result["stage_boundary_probe"] = sync_probe()
+        log("stage boundary probe:", result["stage_boundary_probe"])
         # ---- served path: Poisson arrivals, then saturation ---------------------
         result["served"] = served(g, pool4)
         result["served_pu300_stress"] = served_stress(g, pool5)
@@ -333,6 +350,21 @@ def main():
         result["cpu_baseline_all_cores"] = cpu_baseline_all_cores(args.cpu_budget)
         log("cpu baseline, all cores:", result["cpu_baseline_all_cores"])
     print(json.dumps(result), flush=True)
+
+
+def sync_probe(iters: int = 200):
+    """Microseconds per stage boundary for the chain's grid shape, crossed by
+    launches (graph replay, eager) or by grid barriers in one persistent
+    cooperative kernel (paper_2407_18231_amd/csrc/sync_probe.hip), run as a
+    separate process."""
+    import subprocess
+    exe = os.path.join(ROOT, "paper_2407_18231_amd", "sync_probe")
+    if not os.path.exists(exe):
+        return None
+    out = subprocess.run([exe, str(iters)], capture_output=True, text=True, timeout=120)
+    if out.returncode != 0:
+        return {"error": out.stderr.strip()[-200:]}
+    return json.loads(out.stdout.strip().splitlines()[-1])
 
 
 def copy_probe(mb: int):
@@ -450,6 +482,14 @@ def served(g, pool, n_poisson=5000):
         for rate in (4000.0, 16000.0, 0.0):
             out.append(served_run(c, pool, rate, 8000, 100 + int(rate)))
             log("served:", out[-1])
+    # saturation with four device slots instead of two
+    with lst.Context(max_batch=64, n_slots=4) as c:
+        c.load_geometry(g)
+        served_run(c, pool[:256], 0, 512, 98)
+        r = served_run(c, pool, 0.0, 8000, 100)
+        r["slots"] = 4
+        out.append(r)
+        log("served:", out[-1])
     return out
 
 

@@ -71,11 +71,16 @@ typedef struct {
     uint32_t queue_depth;    /* served path: most events waiting or in flight (default 1024) */
     uint64_t mem_budget;     /* device bytes the served path may hold (0 = 32 GiB) */
     /* Seed-lookup bucket granularity: azimuth bins per (event, surface) row
-     * (0 = 64, else 4..4096) and curvature bins per resolution class (0 = 16,
+     * (0 = 64, else 4..4096) and curvature bins per resolution class (0 = 12,
      * else 2..128).  The object lists do not depend on them, only the speed;
      * paper_2407_18231_amd.tune picks them by measurement. */
     uint32_t n_phi_bins;
     uint32_t n_kappa_bins;
+    /* Segment walk: edges of a module taken per group (0 = 6, else 4, 6 or 8)
+     * and the minimum number of waves per SIMD its registers allow (0 = the
+     * compiler's choice, else 6 or 8).  Speed only; picked by the tuner. */
+    uint32_t ls_group;
+    uint32_t ls_waves;
     /* hipStream_t the per-event and batched paths (lst_run_event,
      * lst_run_batch, lst_batch_*) enqueue their work on; NULL: a stream of the
      * library's own.  Borrowed: it must outlive the context and is never

@@ -12,6 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblst.so")
+PROBE = os.path.join(HERE, "sync_probe")
 SOURCES = ["geometry.cpp", "kernels.hip", "api.hip"]
 
 FLAGS = [
@@ -67,6 +68,13 @@ def build(verbose: bool = False) -> str:
         print(" ".join(link), flush=True)
     subprocess.check_call(link)
     os.replace(tmp, LIB)
+    # the stage-boundary probe (a program of its own; bench.py runs it)
+    probe = [hipcc, "--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+             "-packed-fp32-ops", os.path.join(CSRC, "sync_probe.hip"), "-o", PROBE + ".tmp"]
+    if verbose:
+        print(" ".join(probe), flush=True)
+    subprocess.check_call(probe)
+    os.replace(PROBE + ".tmp", PROBE)
     return LIB
 
 

@@ -1107,6 +1107,9 @@ lst_status lst_create(const lst_params *p, lst_ctx **out)
     if ((prm.n_phi_bins != 0 && (prm.n_phi_bins < 4 || prm.n_phi_bins > 4096)) ||
         (prm.n_kappa_bins != 0 && (prm.n_kappa_bins < 2 || prm.n_kappa_bins > 128)))
         return LST_ERR_INVALID_ARG;
+    if ((prm.ls_group != 0 && prm.ls_group != 4 && prm.ls_group != 6 && prm.ls_group != 8) ||
+        (prm.ls_waves != 0 && prm.ls_waves != 6 && prm.ls_waves != 8))
+        return LST_ERR_INVALID_ARG;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || prm.device < 0 || prm.device >= ndev) return LST_ERR_DEVICE;
     if (hipSetDevice(prm.device) != hipSuccess) return LST_ERR_DEVICE;

@@ -52,6 +52,8 @@ struct Consts {
     uint32_t nkb;            // curvature bins of the seed-lookup buckets (per resolution class)
     float kspan;             // curvature bins cover [-kspan, kspan]
     float sk_cls[3];         // resolution classes: sigma_kappa <= sk_cls[i]; larger ones go to the wide bin
+    uint32_t ls_group;       // segment walk: edges per group (4, 6, 8)
+    uint32_t ls_waves;       // segment walk: minimum waves per SIMD (0: the compiler's choice, 6, 8)
 };
 
 struct Geometry {

@@ -42,7 +42,7 @@ class lst_params(C.Structure):
                 ("n_sigma", C.c_double), ("flags", C.c_uint32), ("max_batch", C.c_uint32),
                 ("n_slots", C.c_uint32), ("queue_depth", C.c_uint32),
                 ("mem_budget", C.c_uint64), ("n_phi_bins", C.c_uint32), ("n_kappa_bins", C.c_uint32),
-                ("stream", C.c_void_p)]
+                ("ls_group", C.c_uint32), ("ls_waves", C.c_uint32), ("stream", C.c_void_p)]
 
 
 MODULE_DTYPE = np.dtype([("kind", "<u4"), ("layer", "<u4"), ("side", "<i4"), ("pad", "<u4"),
@@ -237,6 +237,10 @@ class Context:
     def __init__(self, params: lst_params | None = None, **kw):
         L = load()
         self.L = L
+        if params is None and not any(k in kw for k in ("n_phi_bins", "n_kappa_bins", "ls_group", "ls_waves")):
+            # the autotuner's cached choice for this GPU and batch size, if any
+            from . import tune
+            kw = {**(tune.cached_choice(kw.get("max_batch", 64)) or {}), **kw}
         p = params or default_params(**kw)
         h = C.c_void_p()
         self._check(L.lst_create(C.byref(p), C.byref(h)), ctx=False)
@@ -288,6 +292,16 @@ class Context:
         self._check(self.L.lst_run_event(self.h, C.byref(e.c), C.byref(o)))
         try:
             return _out_to_dict(o.contents)
+        finally:
+            self.L.lst_free_output(o)
+
+    def run_event_in(self, e: EventIn, fetch: bool = True):
+        """lst_run_event of an event already marshalled (EventIn); fetch=False
+        drops the lists (timing of the library call alone)."""
+        o = _P(lst_event_out)()
+        self._check(self.L.lst_run_event(self.h, C.byref(e.c), C.byref(o)))
+        try:
+            return _out_to_dict(o.contents) if fetch else None
         finally:
             self.L.lst_free_output(o)
 

@@ -83,12 +83,13 @@ def test_connection_map_holds_every_oracle_segment(lib, kind):
 
 
 def test_bucket_granularity_params(lib, tmp_path):
-    """The seed-lookup bucket counts default to 0 (the library's 64 x 16) and
+    """The seed-lookup bucket counts default to 0 (the library's 64 x 12) and
     out-of-range values are refused before any device is touched; the
     tuner's cache round-trips per architecture and workload."""
     p = lst.default_params()
     assert p.n_phi_bins == 0 and p.n_kappa_bins == 0
-    for bad in (dict(n_phi_bins=3), dict(n_phi_bins=5000), dict(n_kappa_bins=1), dict(n_kappa_bins=200)):
+    for bad in (dict(n_phi_bins=3), dict(n_phi_bins=5000), dict(n_kappa_bins=1), dict(n_kappa_bins=200),
+                dict(ls_group=5), dict(ls_waves=7)):
         with pytest.raises(lst.LstError) as e:
             lst.Context(**bad)
         assert e.value.name == "INVALID_ARG", bad
@@ -99,6 +100,12 @@ def test_bucket_granularity_params(lib, tmp_path):
     tune.store_choice("gfx950", "batch8-pu100", {"n_phi_bins": 32, "n_kappa_bins": 12}, path)
     assert tune.load_choice("gfx950", "batch64-pu200", path) == {"n_phi_bins": 64, "n_kappa_bins": 16}
     assert tune.load_choice("gfx942", "batch64-pu200", path) is None
+    per_arch = {"batch64-pu200": {"n_phi_bins": 64, "n_kappa_bins": 16, "ls_group": 4, "ls_waves": 8,
+                                  "ms_per_batch": {}},
+                "batch8-pu100": {"n_phi_bins": 32, "n_kappa_bins": 12}}
+    assert tune.choice_for(per_arch, 64) == {"n_phi_bins": 64, "n_kappa_bins": 16, "ls_group": 4, "ls_waves": 8}
+    assert tune.choice_for(per_arch, 8) == {"n_phi_bins": 32, "n_kappa_bins": 12}
+    assert tune.choice_for(per_arch, 16) is None
 
 
 def _c_layout(struct: str, fields: list) -> dict:

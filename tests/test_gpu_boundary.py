@@ -241,3 +241,21 @@ def test_deterministic_x10(g, ctx):
             got = c.batch_download(64)
             for r, q in zip(ref, got):
                 same(r, q)
+
+
+def test_served_pu300_stress_batches_of_32(g):
+    """The stress workload inside the serving loop: PU300 events (40% noise,
+    5% fake seeds) admitted 32 per micro-batch; every output equals the
+    event's run alone and sampled ones match the oracle."""
+    evs = [s.gen_event(g, s.config_pu(300, noise_frac=0.4, fake_frac=0.05), s.event_seed(5, 10 + i))
+           for i in range(32)]
+    with lst.Context(max_batch=32, n_slots=2) as c:
+        c.load_geometry(g)
+        alone = [c.run_event(ev) for ev in evs]
+        tickets = [c.submit(ev) for ev in evs]
+        outs = [c.poll(t, -1) for t in tickets]
+    assert max(o["batch_events"] for o in outs) > 1
+    for a, o in zip(alone, outs):
+        same(a, o)
+    for i in (0, 31):
+        check_parity(g, evs[i], outs[i])

@@ -256,6 +256,24 @@ def test_bucket_granularity_does_not_change_lists(ctx, geo, bins):
         assert np.array_equal(ref[k], got[k]), (bins, k)
 
 
+@pytest.mark.parametrize("variant", [(4, 0), (8, 8), (6, 6)])
+def test_segment_walk_variants_do_not_change_lists(geo, variant):
+    """The segment walk's edge-group size and occupancy (the tuner's other
+    choices) change only the speed, on the pooled large-batch walk."""
+    g = geo["pu200"]
+    evs = [s.gen_event(g, s.config_pu(200), s.event_seed(2, 60 + i)) for i in range(12)]
+    out = []
+    for group, waves in ((6, 0), variant):
+        with lst.Context(max_batch=12, ls_group=group, ls_waves=waves) as c:
+            c.load_geometry(g)
+            c.batch_upload(evs)
+            c.batch_execute(1, graph=True)
+            out.append(c.batch_download(len(evs)))
+    for a, b in zip(*out):
+        for k in STAGES:
+            assert np.array_equal(a[k], b[k]), (variant, k)
+
+
 def test_parity_special_seeds(ctx, geo):
     """Seeds whose helix cannot reach the outer tracker (|r kappa / 2| >= 1
     from r = 17.5 cm on), with cot(theta) = 0 (no disk prediction) and with
