@@ -71,7 +71,7 @@ typedef struct {
     uint32_t queue_depth;    /* served path: most events waiting or in flight (default 1024) */
     uint64_t mem_budget;     /* device bytes the served path may hold (0 = 32 GiB) */
     /* Seed-lookup bucket granularity: azimuth bins per (event, surface) row
-     * (0 = 64, else 4..4096) and curvature bins per resolution class (0 = 12,
+     * (0 = 64, else 4..4096) and curvature bins per resolution class (0 = 16,
      * else 2..128).  The object lists do not depend on them, only the speed;
      * paper_2407_18231_amd.tune picks them by measurement. */
     uint32_t n_phi_bins;

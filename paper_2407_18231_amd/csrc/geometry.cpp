@@ -179,7 +179,7 @@ lst_status build_geometry(const lst_params &p, const lst_module_desc *m, uint32_
     c.n_surf = n_surf;
     c.flags = p.flags;
     c.nphi = p.n_phi_bins ? p.n_phi_bins : 64;
-    c.nkb = p.n_kappa_bins ? p.n_kappa_bins : 12;
+    c.nkb = p.n_kappa_bins ? p.n_kappa_bins : 16;
     c.ls_group = p.ls_group ? p.ls_group : 6;
     c.ls_waves = p.ls_waves;
     c.kspan = (float)(1.25 * kmax);

@@ -390,8 +390,10 @@ __global__ void k_hit_scatter(const Batch b, const Totals *t)
 
 // per (event, module, sensor) bin: restore input order (the scatter used
 // atomic slots) and write the sorted SoA with r = sqrt(x^2 + y^2).  Bins of
-// up to four hits sort in registers.
-__global__ void k_hit_gather(const Batch b, const Totals *t, uint32_t n_mod)
+// up to four hits sort in registers.  Each hit is checked against the input
+// contract here, where its module's extent is loaded once per bin; a hit
+// outside fails its event (its lists are not used).
+__global__ void k_hit_gather(const Batch b, Totals *t, const float4 *__restrict__ ext, uint32_t n_mod)
 {
     const uint32_t nb = t->n_bins;
     GRID_STRIDE(bin, nb) {
@@ -399,8 +401,13 @@ __global__ void k_hit_gather(const Batch b, const Totals *t, uint32_t n_mod)
         if (beg == end) continue;
         const uint32_t e = bin / (2u * n_mod);
         const uint32_t h0 = b.ev_hit_off[e];
+        const uint32_t local = bin - e * 2u * n_mod, m = local >> 1, sn = local & 1u;
+        const float4 ea = ext[2 * m], es = ext[2 * m + 1];
+        bool outside = false;
         auto put = [&](uint32_t i, const float4 v) {
-            b.hpos[i] = make_float4(v.x, v.y, v.z, sqrtf(v.x * v.x + v.y * v.y));
+            const float r = sqrtf(v.x * v.x + v.y * v.y);
+            outside = outside || !hit_inside(ea, es, sn, v.x, v.y, v.z, r);
+            b.hpos[i] = make_float4(v.x, v.y, v.z, r);
             b.hin[i] = __float_as_uint(v.w) - h0;
             b.hbin_s[i] = bin;
         };
@@ -426,6 +433,10 @@ __global__ void k_hit_gather(const Batch b, const Totals *t, uint32_t n_mod)
 #pragma unroll
             for (uint32_t k = 0; k < 4; k++)
                 if (beg + k < end) put(beg + k, v[k]);
+            if (outside) {
+                atomicOr(&t->err, kErrOutside);
+                atomicOr(&b.ev_err[e], kErrOutside);
+            }
             continue;
         }
         for (uint32_t i = beg + 1; i < end; i++) {
@@ -439,22 +450,9 @@ __global__ void k_hit_gather(const Batch b, const Totals *t, uint32_t n_mod)
             b.hrec[j] = v;
         }
         for (uint32_t i = beg; i < end; i++) put(i, b.hrec[i]);
-    }
-}
-
-// The input contract of every hit with a valid module and finite
-// coordinates (the histogram reports the others), off the main chain: a
-// hit outside fails its event (its lists are not used).
-__global__ void k_hit_check(const Batch b, Totals *t, const float4 *__restrict__ ext, uint32_t n_mod)
-{
-    const uint32_t n = min(t->n_hits, b.cap_hits), n_ev = t->n_ev;
-    GRID_STRIDE(h, n) {
-        const uint32_t m = b.in_mod[h], sn = b.in_sen[h];
-        const float x = b.in_x[h], y = b.in_y[h], z = b.in_z[h];
-        if (m >= n_mod || sn > 1u || !isfinite(x) || !isfinite(y) || !isfinite(z)) continue;
-        if (!hit_inside(ext[2 * m], ext[2 * m + 1], sn, x, y, z, sqrtf(x * x + y * y))) {
+        if (outside) {
             atomicOr(&t->err, kErrOutside);
-            atomicOr(&b.ev_err[find_event(b.ev_hit_off, n_ev, h)], kErrOutside);
+            atomicOr(&b.ev_err[e], kErrOutside);
         }
     }
 }
@@ -2183,8 +2181,6 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     launch_setup(L, b, t, c);
     L.fork(0);
     L.on_side(true);
-    L.stage = LST_STAGE_INGEST;
-    L.launch("hit_check", k_hit_check, grid_for(b.cap_hits), blk, b, t, g.mod_ext, n_mod);
     L.stage = LST_STAGE_SEED_LOOKUP;
     L.launch("pls_prep", k_pls_prep, grid_for(b.cap_pls), blk, b, t, c);
     L.launch("road", k_road, grid_for(cap_pu), blk, b, (const Totals *)t, g, c);
@@ -2204,8 +2200,7 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     L.launch_lds("hit_hist", k_hit_hist, gh, dim3(kHistBlock), g.hist_slice * 4u, b, t, n_mod, g.hist_slice);
     L.scan(b.bin_cnt, b.bin_off, &t->n_bins, b.cap_ev * 2u * n_mod, &t->n_sorted, "scan_hits");
     L.launch("hit_scatter", k_hit_scatter, grid_for(b.cap_hits), blk, b, (const Totals *)t);
-    L.launch("hit_gather", k_hit_gather, grid_for((uint64_t)b.cap_ev * 2 * n_mod), blk, b, (const Totals *)t,
-             n_mod);
+    L.launch("hit_gather", k_hit_gather, grid_for((uint64_t)b.cap_ev * 2 * n_mod), blk, b, t, g.mod_ext, n_mod);
     // a2: mini-doublets
     L.stage = LST_STAGE_MD;
     // small batches: count and fill in place for latency; large ones: pooled walk

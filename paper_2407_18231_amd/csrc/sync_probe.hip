@@ -37,8 +37,9 @@ __global__ __launch_bounds__(256) void k_persistent(unsigned *p, unsigned n, uns
 // The same with a barrier of our own: every block adds one to a counter
 // and waits (with a sleep between polls) until the counter reaches the
 // number of blocks times the stages passed.  The wait is bounded: after
-// kMaxPolls polls a block records a timeout and goes on, so every wave ends.
-constexpr unsigned kMaxPolls = 1u << 22;
+// kMaxPolls polls a block records a timeout, and once one is recorded no
+// block waits any more, so every wave ends.
+constexpr unsigned kMaxPolls = 1u << 18;
 
 __global__ __launch_bounds__(256) void k_persistent_own(unsigned *p, unsigned n, unsigned iters, unsigned *bar,
                                                         unsigned *timed_out)
@@ -54,10 +55,8 @@ __global__ __launch_bounds__(256) void k_persistent_own(unsigned *p, unsigned n,
             unsigned polls = 0;
             while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
                 __builtin_amdgcn_s_sleep(1);
-                if (++polls == kMaxPolls) {
-                    atomicOr(timed_out, 1u);
-                    break;
-                }
+                if (++polls == kMaxPolls) atomicOr(timed_out, 1u);
+                if (__hip_atomic_load(timed_out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
             }
         }
         __syncthreads();
@@ -80,7 +79,10 @@ int main(int argc, char **argv)
     CHECK(hipSetDevice(dev));
     CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     CHECK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    int per_cu_own = 0;
     CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent, 256, 0));
+    CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_own, k_persistent_own, 256, 0));
+    if (per_cu_own < per_cu) per_cu = per_cu_own;     // every block of both kernels co-resident
     if (!coop || per_cu < 1) {
         std::printf("{\"cooperative_launch\": false}\n");
         return 0;
