@@ -179,9 +179,20 @@ def main():
     ap.add_argument("--graph", action="store_true", help="with --chain-only: replay the captured graph")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="counter calibration: one device-to-device copy of MB megabytes (torch)")
+    ap.add_argument("--served-only", type=int, default=0, metavar="N",
+                    help="trace runs: N events (PU ~ U[140, 200]) submitted back to back to the served path")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.served_only:
+        from paper_2407_18231_amd import lst, synth
+        pool = served_events(min(args.served_only, 512))
+        g = synth.make_geometry("pu200")
+        with lst.Context(max_batch=64, n_slots=2) as c:
+            c.load_geometry(g)
+            r = served_run(c, pool, 0.0, args.served_only, 100)
+        log("served:", r)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: the events of a batch shard across GPUs with no "

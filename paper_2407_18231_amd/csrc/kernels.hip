@@ -29,16 +29,23 @@ constexpr int kScanTile = 4 * kScanBlock;
 constexpr float kPiF = 3.14159265358979f;
 constexpr double kPiD = 3.14159265358979323846;
 
+// inclusive prefix sum across a wave: row shifts by 1, 2, 4, 8 within each
+// row of 16 lanes, then the last lane of rows 0 / 2 broadcast into rows 1 / 3
+// and the last lane of row 1 into rows 2 and 3 (register-to-register, no
+// LDS round trip; lanes a shift cannot reach add 0)
 __device__ inline uint32_t wave_incl_scan(uint32_t v)
 {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t t = __shfl_up(v, d, 64);
-        if (lane >= d) v += t;
-    }
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);
     return v;
 }
+
+// the value of lane 63 in every lane (a scalar read, no LDS)
+__device__ inline uint32_t wave_last(uint32_t v) { return (uint32_t)__builtin_amdgcn_readlane((int)v, 63); }
 
 // exclusive scan of one value per thread across a 256-thread block
 __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t &total)
@@ -516,7 +523,7 @@ __global__ __launch_bounds__(256) void k_md(const Batch b, Totals *t, const DevG
         }
         const uint32_t incl = wave_incl_scan(cnt);
         const uint32_t off = incl - cnt;
-        const uint32_t total = __shfl(incl, 63);
+        const uint32_t total = wave_last(incl);
         uint32_t run = 0;
         uint32_t carry = 0;
         for (uint32_t cb = 0; cb < total; cb += 64u) {
@@ -811,7 +818,7 @@ __global__ __launch_bounds__(256, kMinWaves) void k_ls(const Batch b, Totals *t,
             wave_lds_sync();
             const uint32_t incl = wave_incl_scan(T);
             const uint32_t off = incl - T;
-            const uint32_t total = __shfl(incl, 63);
+            const uint32_t total = wave_last(incl);
             // two pooled rounds per step: the indices and loads of both are
             // issued before either cut, so that twice the loads are in flight
             uint32_t carry = 0;                       // owner + 1 of the last candidate so far
@@ -926,14 +933,17 @@ __global__ __launch_bounds__(256) void k_ls_place(const Batch b, uint32_t nsub)
 constexpr uint32_t kLsLanes = 32;
 constexpr uint32_t kLsWaveMaxMd = 1u << 17;   // MD capacity up to which the latency variant runs
 
+// inclusive prefix sum within each half (32 lanes) of a wave: the row
+// shifts of wave_incl_scan, then only the broadcast of rows 0 / 2 into
+// rows 1 / 3
 __device__ inline uint32_t half_incl_scan(uint32_t v)
 {
-    const uint32_t w = threadIdx.x & (kLsLanes - 1);
-#pragma unroll
-    for (uint32_t d = 1; d < kLsLanes; d <<= 1) {
-        uint32_t t = __shfl_up(v, d, kLsLanes);
-        if (w >= d) v += t;
-    }
+    static_assert(kLsLanes == 32, "half-wave scan");
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);
     return v;
 }
 
@@ -1189,7 +1199,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
         }
         const uint32_t incl = wave_incl_scan(cnt);
         const uint32_t off = incl - cnt;                 // this lane's first pooled candidate
-        const uint32_t total = __shfl(incl, 63);
+        const uint32_t total = wave_last(incl);
         uint32_t run = 0;                                // survivors of this lane's LS so far
         uint32_t carry = 0;
         for (uint32_t cb = 0; cb < total; cb += 64u) {
@@ -1325,7 +1335,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
         }
         const uint32_t incl = wave_incl_scan(cnt);
         const uint32_t off = incl - cnt;
-        const uint32_t total = __shfl(incl, 63);
+        const uint32_t total = wave_last(incl);
         uint32_t run = 0;
         uint32_t carry = 0;
         for (uint32_t cb = 0; cb < total; cb += 64u) {
@@ -1759,7 +1769,7 @@ __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Con
             wave_lds_sync();
             const uint32_t incl = wave_incl_scan(T);
             const uint32_t off = incl - T;
-            const uint32_t total = __shfl(incl, 63);
+            const uint32_t total = wave_last(incl);
             uint32_t carry = 0;
             for (uint32_t cb = 0; cb < total; cb += 64u) {
                 const uint32_t ci = cb + lane;
