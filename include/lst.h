@@ -76,7 +76,8 @@ typedef struct {
      * paper_2407_18231_amd.tune picks them by measurement. */
     uint32_t n_phi_bins;
     uint32_t n_kappa_bins;
-    /* Segment walk: edges of a module taken per group (0 = 6, else 4, 6 or 8)
+    /* Segment walk: runs of a module's edges (edges to consecutive modules of
+     * one class) taken per group (0 = 6, else 4, 6 or 8)
      * and the minimum number of waves per SIMD its registers allow (0 = the
      * compiler's choice, else 6 or 8).  Speed only; picked by the tuner. */
     uint32_t ls_group;
@@ -173,7 +174,11 @@ typedef struct {
 
 /* Result of one event, owned by the library (free with lst_free_output):
  * the objects of every stage and the track candidates (Sec. 1, list of
- * propagated objects).  Pairs are stored flat: element 2*i and 2*i+1. */
+ * propagated objects).  Pairs are stored flat: element 2*i and 2*i+1.
+ * The lists of all events of one batch (or served micro-batch) lie in one
+ * pinned host buffer, copied from the device in one transfer; it is released
+ * when the last output pointing into it is freed, which may be after
+ * lst_destroy.  Holding one output keeps its batch's buffer. */
 typedef struct {
     uint32_t n_md, n_ls, n_t3, n_t5, n_pt3, n_pt5, n_tc;
     uint32_t status;         /* lst_status of this event (served path) */
@@ -318,6 +323,8 @@ typedef struct {
  * n_* fields then give the sizes needed; nothing is written). */
 lst_status lst_run_event_noalloc(lst_ctx *ctx, const lst_event_in *ev, lst_event_dev_out *out, void *stream);
 
+/* Frees an output of lst_run_event, lst_run_batch, lst_batch_download or
+ * lst_poll (NULL: nothing); thread-safe, also after lst_destroy. */
 void lst_free_output(lst_event_out *out);
 
 /* Drains in-flight served events, then frees everything. */

@@ -209,8 +209,8 @@ struct Slot {
     hipStream_t side = nullptr;
     char *h_stage = nullptr;
     size_t stage_bytes = 0;
-    char *h_out = nullptr;              // pinned landing buffer of the results
-    size_t out_bytes = 0;
+    uint32_t *img = nullptr;            // device output image of the batch (in the work arena)
+    size_t img_words = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     bool graph_valid = false;
@@ -261,19 +261,24 @@ struct PinnedPool {
         while (c < bytes) c += c / 2;   // classes 64 KiB x 1.5^k
         return c;
     }
-    char *get(size_t bytes, size_t &cls)
+    // the smallest free block of this size class or up to four classes
+    // larger, else a new block of the class of bytes + headroom
+    char *get(size_t bytes, size_t &cls, size_t headroom = 0)
     {
         cls = size_class(bytes);
         {
             std::lock_guard<std::mutex> g(mu);
-            auto it = free_blocks.find(cls);
-            if (it != free_blocks.end() && !it->second.empty()) {
+            const size_t limit = 5 * cls + 1;
+            for (auto it = free_blocks.lower_bound(cls); it != free_blocks.end() && it->first <= limit; ++it) {
+                if (it->second.empty()) continue;
                 char *p = it->second.back();
                 it->second.pop_back();
+                cls = it->first;
                 return p;
             }
         }
         char *p = nullptr;
+        cls = size_class(bytes + headroom);
         if (hipHostMalloc((void **)&p, cls, hipHostMallocDefault) != hipSuccess) return nullptr;
         std::lock_guard<std::mutex> g(mu);
         all.push_back(p);
@@ -291,7 +296,38 @@ struct PinnedPool {
         all.clear();
         free_blocks.clear();
     }
+    ~PinnedPool() { release(); }
 };
+
+// The outputs of one batch: a pinned buffer that holds every event's lists
+// (the output image, copied from the device in one transfer) and the number
+// of outputs that point into it; the last lst_free_output gives it back to
+// the pool, which each buffer keeps alive (outputs may outlive the context).
+struct OutBatch {
+    std::shared_ptr<PinnedPool> pool;
+    char *buf = nullptr;
+    size_t cls = 0;
+    std::atomic<uint32_t> refs{0};
+    void unref()
+    {
+        if (refs.fetch_sub(1, std::memory_order_acq_rel) == 1) {
+            pool->put(buf, cls);
+            delete this;
+        }
+    }
+};
+
+// What an lst_event_out pointer handed to the caller points to.
+struct OutBox {
+    lst_event_out pub;       // first member: the caller's pointer is its address
+    OutBatch *batch;         // buffer the lists point into (null: no lists)
+};
+
+lst_event_out *new_out()
+{
+    OutBox *b = (OutBox *)std::calloc(1, sizeof(OutBox));
+    return b ? &b->pub : nullptr;
+}
 
 struct ServedEvent {
     uint64_t ticket;
@@ -326,6 +362,7 @@ struct lst_ctx {
     std::condition_variable q_cv, slot_cv, done_cv;
     std::deque<std::unique_ptr<ServedEvent>> waiting;
     PinnedPool pinned;
+    std::shared_ptr<PinnedPool> out_pool = std::make_shared<PinnedPool>();   // output batches
     std::vector<int> slot_state;        // 0 free, 1 being staged, 2 launched
     std::vector<uint64_t> slot_mem;
     std::vector<std::vector<std::unique_ptr<ServedEvent>>> held;
@@ -377,8 +414,8 @@ void free_slot_arenas(Slot &s)
     if (s.in_arena) { (void)hipFree(s.in_arena); s.in_arena = nullptr; }
     if (s.work_arena) { (void)hipFree(s.work_arena); s.work_arena = nullptr; }
     if (s.h_stage) { (void)hipHostFree(s.h_stage); s.h_stage = nullptr; }
-    if (s.h_out) { (void)hipHostFree(s.h_out); s.h_out = nullptr; }
-    s.in_bytes = s.work_bytes = s.stage_bytes = s.out_bytes = 0;
+    s.img = nullptr;   // part of the work arena
+    s.in_bytes = s.work_bytes = s.stage_bytes = s.img_words = 0;
 }
 
 void destroy_slot(Slot &s)
@@ -469,7 +506,15 @@ lst_status ensure_work(lst_ctx *ctx, Slot &s)
     const lst::Consts &c = ctx->geom.c;
     lst::Carver cw{nullptr};
     lst::carve_work(cw, b, c.n_mod, c.n_surf, c.nphi, c.nkb);
-    s.work_bytes = cw.off;
+    // the output image of the batch follows the lists, sized for their
+    // capacities (download never allocates)
+    const bool clean = (c.flags & LST_FLAG_TC_CLEAN) != 0u;
+    const uint64_t img_words = (uint64_t)(b.cap_ev + 1) * lst::kEvTabCols + b.cap_ev +
+                               2ull * ((uint64_t)b.cap_md + b.cap_ls + b.cap_t3 + b.cap_t5 + b.cap_pt3 +
+                                       2ull * b.cap_pt5 + b.cap_tc) +
+                               b.cap_t3 + (clean ? 2ull * ((uint64_t)b.cap_pt5 + b.cap_tc) : 0ull);
+    const size_t img_at = lst::align_up(cw.off);
+    s.work_bytes = img_at + 4 * img_words;
     hipError_t e = hipMalloc(&s.work_arena, s.work_bytes);
     if (e != hipSuccess) {
         s.work_arena = nullptr;
@@ -482,6 +527,8 @@ lst_status ensure_work(lst_ctx *ctx, Slot &s)
     }
     lst::Carver cw2{(char *)s.work_arena};
     lst::carve_work(cw2, b, c.n_mod, c.n_surf, c.nphi, c.nkb);
+    s.img = (uint32_t *)((char *)s.work_arena + img_at);
+    s.img_words = img_words;
     s.graph_valid = false;
     return LST_OK;
 }
@@ -691,6 +738,7 @@ lst_status run_staged(lst_ctx *ctx, Slot &s, bool use_graph, bool stage_times, b
         if (s.graph) { (void)hipGraphDestroy(s.graph); s.graph = nullptr; }
         s.graph_valid = false;
         if (s.work_arena) { (void)hipFree(s.work_arena); s.work_arena = nullptr; }
+        s.img = nullptr;
         st = ensure_work(ctx, s);
         if (st != LST_OK) return st;
     }
@@ -698,70 +746,80 @@ lst_status run_staged(lst_ctx *ctx, Slot &s, bool use_graph, bool stage_times, b
 }
 
 // Copy the results of the staged batch to host memory, one output per event:
-// one pinned landing buffer per slot, then per-event assembly (on several
-// host threads for larger batches).
+// the device writes the batch's output image (every event's lists with
+// event-local indices, in the layout of lst_event_out), one transfer brings it
+// into a pinned buffer, and each event's output points into that buffer.
 lst_status download(lst_ctx *ctx, Slot &s, lst_event_out **outs)
 {
     const uint32_t n = s.n_ev;
+    for (uint32_t e = 0; e < n; e++) outs[e] = nullptr;
     const lst::Totals &t = *s.h_tot;
-    const Batch &b = s.b;
-    const uint32_t nmd = t.n_md, nls = t.n_ls, nt3 = t.n_t3, nt5 = t.n_t5, np3 = t.n_pt3, np5 = t.n_pt5, ntc = t.n_tc;
-    struct Part { const void *src; size_t bytes; size_t at; };
-    Part parts[] = {{b.ev_tab, (size_t)(n + 1) * lst::kEvTabCols * 4, 0},
-                    {b.md_hlo, nmd * 4ull, 0}, {b.md_hup, nmd * 4ull, 0},
-                    {b.ls_a, nls * 4ull, 0}, {b.ls_b, nls * 4ull, 0},
-                    {b.t3_l1, nt3 * 4ull, 0}, {b.t3_l2, nt3 * 4ull, 0}, {b.t3_ks, nt3 * 8ull, 0},
-                    {b.t5_u, nt5 * 4ull, 0}, {b.t5_w, nt5 * 4ull, 0},
-                    {b.pt3_p, np3 * 4ull, 0}, {b.pt3_o, np3 * 4ull, 0},
-                    {b.pt5_p, np5 * 4ull, 0}, {b.pt5_o, np5 * 4ull, 0},
-                    {b.tc_type, ntc * 4ull, 0}, {b.tc_idx, ntc * 4ull, 0},
-                    {b.tcc_keep, (ctx->geom.c.flags & LST_FLAG_TC_CLEAN) ? (size_t)np5 + ntc : 0ull, 0}};
     const bool clean = (ctx->geom.c.flags & LST_FLAG_TC_CLEAN) != 0u;
-    size_t total = 0;
-    for (Part &p : parts) { p.at = total; total += lst::align_up(p.bytes); }
-    if (total > s.out_bytes) {
-        if (s.h_out) { (void)hipHostFree(s.h_out); s.h_out = nullptr; s.out_bytes = 0; }
-        size_t want = total + total / 4;
-        HIP_TRY(hipHostMalloc((void **)&s.h_out, want, hipHostMallocDefault));
-        s.out_bytes = want;
+    const uint64_t n_tab = (uint64_t)(n + 1) * lst::kEvTabCols;
+    const uint64_t head = n_tab + n;
+    const uint64_t pairs = (uint64_t)t.n_md + t.n_ls + t.n_t3 + t.n_t5 + t.n_pt3 + 2ull * t.n_pt5 + t.n_tc;
+    const uint64_t words = head + 2 * pairs + t.n_t3 + (clean ? 2ull * ((uint64_t)t.n_pt5 + t.n_tc) : 0ull);
+    if (!s.img || words > s.img_words) {
+        fail(ctx, "output image larger than the list capacities");
+        return LST_ERR_DEVICE;
     }
-    for (const Part &p : parts)
-        if (p.bytes) HIP_TRY(hipMemcpyAsync(s.h_out + p.at, p.src, p.bytes, hipMemcpyDeviceToHost, s.stream));
-    HIP_TRY(hipStreamSynchronize(s.stream));
-    auto arr = [&](int i) { return (const uint32_t *)(s.h_out + parts[i].at); };
-    const uint32_t *tab = arr(0), *hlo = arr(1), *hup = arr(2), *la = arr(3), *lb = arr(4), *u1 = arr(5);
-    const uint32_t *u2 = arr(6), *w1 = arr(8), *w2 = arr(9), *p3 = arr(10), *o3 = arr(11), *p5 = arr(12);
-    const uint32_t *o5 = arr(13), *tty = arr(14), *tix = arr(15);
-    const float2 *k3 = (const float2 *)(s.h_out + parts[7].at);
-    const uint8_t *kp = (const uint8_t *)(s.h_out + parts[16].at);   // cleaning: pT5 flags, then the kept entries
-    std::vector<int> failed(n, 0);
-    auto build = [&](uint32_t e) {
+    OutBatch *ob = new (std::nothrow) OutBatch;
+    if (!ob) return set_err(ctx, LST_ERR_OOM, "host allocation of outputs failed");
+    ob->pool = ctx->out_pool;
+    // a new block gets room for batches half as large again (sizes vary
+    // from batch to batch; larger free blocks serve smaller ones)
+    ob->buf = ob->pool->get(4 * words, ob->cls, 4 * words / 2);
+    if (!ob->buf) {
+        delete ob;
+        return set_err(ctx, LST_ERR_OOM, "pinned allocation of outputs failed");
+    }
+    ob->refs = 1;   // held while the outputs are made
+    s.L.on_side(false);
+    s.L.timing = false;
+    s.L.err = hipSuccess;
+    const uint64_t items = n_tab + pairs + t.n_t3;   // one per pair, curvature and table word
+    lst::launch_pack(s.L, s.b, s.d_tot, s.img, n, head, words, clean, items);
+    hipError_t he = s.L.err;
+    if (he == hipSuccess) he = hipMemcpyAsync(ob->buf, s.img, 4 * words, hipMemcpyDeviceToHost, s.stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(s.stream);
+    if (he != hipSuccess) {
+        ob->unref();
+        fail(ctx, std::string("output copy: ") + hipGetErrorString(he));
+        return LST_ERR_DEVICE;
+    }
+    uint32_t *img = (uint32_t *)ob->buf;
+    const uint32_t *tab = img;
+    // the image's size from the copied table must be the one the totals gave
+    auto before = [&](const uint32_t *r) {
+        const uint64_t p = (uint64_t)r[2] + r[3] + r[4] + r[5] + r[6] + 2ull * r[7] + r[8] + r[9] + r[10];
+        return 2 * p + r[4] + (clean ? 2ull * ((uint64_t)r[7] + r[8] + r[9] + r[10]) : 0ull);
+    };
+    if (head + before(tab + n_tab - lst::kEvTabCols) - before(tab) != words) {
+        ob->unref();
+        fail(ctx, "output image size differs from the list totals");
+        return LST_ERR_DEVICE;
+    }
+    uint32_t *lists = img + head;
+    bool failed = false;
+    for (uint32_t e = 0; e < n; e++) {
         const uint32_t *r0 = &tab[(size_t)e * lst::kEvTabCols], *r1 = r0 + lst::kEvTabCols;
+        lst_event_out *o = new_out();
+        if (!o) { failed = true; break; }
+        outs[e] = o;
+        o->n_flag_regrow = s.n_regrow;
+        o->n_stage = LST_N_STAGES;
+        o->batch_events = n;
         if (r0[11]) {
             // an input error of this event: its status only, no lists
-            lst_event_out *o = (lst_event_out *)std::calloc(1, sizeof(lst_event_out));
-            if (!o) { failed[e] = 1; return; }
             o->status = (uint32_t)(r0[11] & lst::kErrBadModule ? LST_ERR_BAD_MODULE
                                    : r0[11] & lst::kErrNonFinite ? LST_ERR_NONFINITE
                                                                  : LST_ERR_HIT_OUTSIDE);
-            o->n_flag_regrow = s.n_regrow;
-            o->n_stage = LST_N_STAGES;
-            o->batch_events = n;
-            outs[e] = o;
-            return;
+            continue;
         }
-        const uint32_t pls0 = r0[1], md0 = r0[2], ls0 = r0[3], t30 = r0[4], t50 = r0[5], p30 = r0[6], p50 = r0[7];
-        const uint32_t cmd = r1[2] - md0, cls = r1[3] - ls0, ct3 = r1[4] - t30, ct5 = r1[5] - t50;
-        const uint32_t cp3 = r1[6] - p30, cp5 = r1[7] - p50;
-        const uint32_t ctc3 = r1[8] - r0[8], ctc5 = r1[9] - r0[9], ctcp = r1[10] - r0[10];
-        const uint32_t ctc = cp5 + ctc3 + ctc5 + ctcp;
-        size_t words = 2ull * (cmd + cls + ct3 + ct5 + cp3 + cp5 + ctc) + ct3 + (clean ? 2ull * ctc : 0ull);
-        size_t bytes = sizeof(lst_event_out) + 4 * words + 64;
-        char *mem = (char *)std::malloc(bytes);
-        if (!mem) { failed[e] = 1; return; }
-        lst_event_out *o = (lst_event_out *)mem;
-        std::memset(o, 0, sizeof *o);
-        uint32_t *w = (uint32_t *)(mem + sizeof(lst_event_out));
+        const uint32_t cmd = r1[2] - r0[2], cls = r1[3] - r0[3], ct3 = r1[4] - r0[4], ct5 = r1[5] - r0[5];
+        const uint32_t cp3 = r1[6] - r0[6], cp5 = r1[7] - r0[7];
+        const uint32_t ctc = cp5 + (r1[8] - r0[8]) + (r1[9] - r0[9]) + (r1[10] - r0[10]);
+        uint32_t *w = lists + (before(r0) - before(tab));
         o->n_md = cmd; o->n_ls = cls; o->n_t3 = ct3; o->n_t5 = ct5; o->n_pt3 = cp3; o->n_pt5 = cp5; o->n_tc = ctc;
         o->md = w; w += 2 * cmd;
         o->ls = w; w += 2 * cls;
@@ -772,53 +830,21 @@ lst_status download(lst_ctx *ctx, Slot &s, lst_event_out **outs)
         o->tc = w; w += 2 * ctc;
         o->t3_kappa = (float *)w;
         w += ct3;
-        for (uint32_t i = 0; i < cmd; i++) { o->md[2 * i] = hlo[md0 + i]; o->md[2 * i + 1] = hup[md0 + i]; }
-        for (uint32_t i = 0; i < cls; i++) { o->ls[2 * i] = la[ls0 + i] - md0; o->ls[2 * i + 1] = lb[ls0 + i] - md0; }
-        for (uint32_t i = 0; i < ct3; i++) {
-            o->t3[2 * i] = u1[t30 + i] - ls0; o->t3[2 * i + 1] = u2[t30 + i] - ls0;
-            o->t3_kappa[i] = k3[t30 + i].x;
-        }
-        for (uint32_t i = 0; i < ct5; i++) { o->t5[2 * i] = w1[t50 + i] - t30; o->t5[2 * i + 1] = w2[t50 + i] - t30; }
-        for (uint32_t i = 0; i < cp3; i++) { o->pt3[2 * i] = p3[p30 + i] - pls0; o->pt3[2 * i + 1] = o3[p30 + i] - t30; }
-        for (uint32_t i = 0; i < cp5; i++) { o->pt5[2 * i] = p5[p50 + i] - pls0; o->pt5[2 * i + 1] = o5[p50 + i] - t50; }
-        uint32_t k = 0;
-        for (uint32_t i = 0; i < cp5; i++) { o->tc[2 * k] = LST_TC_PT5; o->tc[2 * k + 1] = i; k++; }
-        for (uint32_t i = r0[8]; i < r1[8]; i++) { o->tc[2 * k] = tty[i]; o->tc[2 * k + 1] = tix[i] - p30; k++; }
-        for (uint32_t i = r0[9]; i < r1[9]; i++) { o->tc[2 * k] = tty[i]; o->tc[2 * k + 1] = tix[i] - t50; k++; }
-        for (uint32_t i = r0[10]; i < r1[10]; i++) { o->tc[2 * k] = tty[i]; o->tc[2 * k + 1] = tix[i] - pls0; k++; }
         if (clean) {
             o->tcc = w;
-            uint32_t q = 0;
-            auto put = [&](uint32_t type, uint32_t idx, uint8_t keep) {
-                if (!keep) return;
-                o->tcc[2 * q] = type;
-                o->tcc[2 * q + 1] = idx;
-                q++;
-            };
-            for (uint32_t i = 0; i < cp5; i++) put(LST_TC_PT5, i, kp[p50 + i]);
-            for (uint32_t i = r0[8]; i < r1[8]; i++) put(tty[i], tix[i] - p30, kp[np5 + i]);
-            for (uint32_t i = r0[9]; i < r1[9]; i++) put(tty[i], tix[i] - t50, kp[np5 + i]);
-            for (uint32_t i = r0[10]; i < r1[10]; i++) put(tty[i], tix[i] - pls0, kp[np5 + i]);
-            o->n_tcc = q;
+            o->n_tcc = img[n_tab + e];
+            if (o->n_tcc > ctc) { failed = true; break; }
         }
         o->status = LST_OK;
-        o->n_flag_regrow = s.n_regrow;
-        o->n_stage = LST_N_STAGES;
         std::memcpy(o->stage_ns, s.stage_ns, sizeof o->stage_ns);
-        o->batch_events = n;
-        outs[e] = o;
-    };
-    const uint32_t n_threads = std::min<uint32_t>(n >= 4 ? 8u : 1u, n);
-    if (n_threads <= 1) {
-        for (uint32_t e = 0; e < n; e++) build(e);
-    } else {
-        std::vector<std::thread> pool;
-        for (uint32_t w = 0; w < n_threads; w++)
-            pool.emplace_back([&, w] { for (uint32_t e = w; e < n; e += n_threads) build(e); });
-        for (auto &th : pool) th.join();
+        ob->refs.fetch_add(1, std::memory_order_relaxed);
+        ((OutBox *)o)->batch = ob;
     }
-    for (uint32_t e = 0; e < n; e++)
-        if (failed[e]) return set_err(ctx, LST_ERR_OOM, "host allocation of outputs failed");
+    ob->unref();
+    if (failed) {
+        for (uint32_t e = 0; e < n; e++) { lst_free_output(outs[e]); outs[e] = nullptr; }
+        return set_err(ctx, LST_ERR_OOM, "host allocation of outputs failed");
+    }
     return LST_OK;
 }
 
@@ -987,7 +1013,7 @@ void admit_main(lst_ctx *ctx)
         if (st != LST_OK) {
             for (auto &se : take) {
                 ctx->pinned.put(se->blk, se->blk_cls);
-                lst_event_out *o = (lst_event_out *)std::calloc(1, sizeof(lst_event_out));
+                lst_event_out *o = new_out();
                 if (o) { o->status = (uint32_t)st; o->ticket = se->ticket; }
                 ctx->finished[se->ticket] = o;
                 ctx->state[se->ticket] = 2;
@@ -1028,6 +1054,7 @@ void complete_main(lst_ctx *ctx, uint32_t i)
         std::vector<lst_event_out *> outs(s.n_ev, nullptr);
         if (st == LST_OK && overflowed(s)) {
             if (s.work_arena) { (void)hipFree(s.work_arena); s.work_arena = nullptr; }
+            s.img = nullptr;
             if (s.gexec) { (void)hipGraphExecDestroy(s.gexec); s.gexec = nullptr; }
             if (s.graph) { (void)hipGraphDestroy(s.graph); s.graph = nullptr; }
             s.graph_valid = false;
@@ -1048,7 +1075,7 @@ void complete_main(lst_ctx *ctx, uint32_t i)
         for (uint32_t e = 0; e < s.n_ev; e++) {
             lst_event_out *o = outs[e];
             if (!o) {
-                o = (lst_event_out *)std::calloc(1, sizeof(lst_event_out));
+                o = new_out();
                 if (o) o->status = (uint32_t)(st == LST_OK ? LST_ERR_DEVICE : st);
             }
             if (o) {
@@ -1182,7 +1209,11 @@ lst_status lst_load_geometry(lst_ctx *ctx, const lst_module_desc *m, uint32_t n)
     size_t off_sf = lst::align_up(off_cls + sizeof(lst::LsK) * nc);
     size_t off_phi = lst::align_up(off_sf + sizeof(lst::Surface) * std::max<size_t>(ns, 1));
     size_t off_ext = lst::align_up(off_phi + 8 * nm);
-    size_t total = lst::align_up(off_ext + 32 * nm);
+    const size_t nr = geom.run_win.size();
+    size_t off_rb = lst::align_up(off_ext + 32 * nm);
+    size_t off_run = lst::align_up(off_rb + 4 * (nm + 1));
+    size_t off_rw = lst::align_up(off_run + 16 * std::max<size_t>(nr, 1));
+    size_t total = lst::align_up(off_rw + 4 * std::max<size_t>(nr, 1));
     std::vector<char> host(total, 0);
     std::memcpy(&host[off_kind], geom.kind.data(), 4 * nm);
     std::memcpy(&host[off_surf], geom.surf.data(), 4 * nm);
@@ -1197,8 +1228,7 @@ lst_status lst_load_geometry(lst_ctx *ctx, const lst_module_desc *m, uint32_t n)
         // v[6]: the largest azimuth difference of the anchors, asin(S), plus
         // the map's margin and room for the binary32 arithmetic of the
         // per-segment reach test
-        float v[8] = {k.S, 0.f, 0.f, 0.f, 0.f, 0.f,
-                      (float)(std::asin(std::min(1.0, (double)k.S)) + 2e-5), 0.f};
+        float v[8] = {k.S, 0.f, 0.f, 0.f, 0.f, 0.f, lst::ls_reach(k), 0.f};
         if (k.type == 0u) {
             v[1] = k.rho_lo; v[2] = k.rho_hi; v[3] = k.lam_lo; v[4] = k.lam_hi; v[5] = k.tau;
         } else if (k.type == 1u) {
@@ -1212,6 +1242,11 @@ lst_status lst_load_geometry(lst_ctx *ctx, const lst_module_desc *m, uint32_t n)
     if (ns) std::memcpy(&host[off_sf], geom.surfaces.data(), sizeof(lst::Surface) * ns);
     std::memcpy(&host[off_phi], geom.mod_phi.data(), 8 * nm);
     std::memcpy(&host[off_ext], geom.mod_ext.data(), 32 * nm);
+    std::memcpy(&host[off_rb], geom.run_begin.data(), 4 * (nm + 1));
+    if (nr) {
+        std::memcpy(&host[off_run], geom.run_rec.data(), 16 * nr);
+        std::memcpy(&host[off_rw], geom.run_win.data(), 4 * nr);
+    }
     void *dmem = nullptr;
     if (hipMalloc(&dmem, total) != hipSuccess) return set_err(ctx, LST_ERR_OOM, "geometry allocation failed");
     hipError_t e = hipMemcpy(dmem, host.data(), total, hipMemcpyHostToDevice);
@@ -1232,6 +1267,9 @@ lst_status lst_load_geometry(lst_ctx *ctx, const lst_module_desc *m, uint32_t n)
     ctx->dg.surf = (const lst::Surface *)(d + off_sf);
     ctx->dg.mod_phi = (const float2 *)(d + off_phi);
     ctx->dg.mod_ext = (const float4 *)(d + off_ext);
+    ctx->dg.run_begin = (const uint32_t *)(d + off_rb);
+    ctx->dg.run = (const uint4 *)(d + off_run);
+    ctx->dg.run_win = (const float *)(d + off_rw);
     // the hit histogram runs per event in LDS, in slices of the event's
     // (module, sensor) bins that fit one block's LDS
     int lds_max = 0;
@@ -1306,7 +1344,7 @@ lst_status lst_run_batch(lst_ctx *ctx, const lst_event_in *evs, uint32_t n, lst_
     for (uint32_t i = 0; i < n; i++) outs[i] = nullptr;
     st = download(ctx, s, outs);
     if (st != LST_OK) {
-        for (uint32_t i = 0; i < n; i++) { std::free(outs[i]); outs[i] = nullptr; }
+        for (uint32_t i = 0; i < n; i++) { lst_free_output(outs[i]); outs[i] = nullptr; }
     }
     return st;
 }
@@ -1619,7 +1657,13 @@ lst_status lst_run_event_noalloc(lst_ctx *ctx, const lst_event_in *ev, lst_event
     return LST_OK;
 }
 
-void lst_free_output(lst_event_out *out) { std::free(out); }
+void lst_free_output(lst_event_out *out)
+{
+    if (!out) return;
+    OutBox *b = (OutBox *)out;
+    if (b->batch) b->batch->unref();
+    std::free(b);
+}
 
 void lst_destroy(lst_ctx *ctx)
 {
@@ -1643,7 +1687,7 @@ void lst_destroy(lst_ctx *ctx)
     for (auto &th : ctx->completers)
         if (th.joinable()) th.join();
     for (auto &kv : ctx->waiting) ctx->pinned.put(kv->blk, kv->blk_cls);
-    for (auto &kv : ctx->finished) std::free(kv.second);
+    for (auto &kv : ctx->finished) lst_free_output(kv.second);
     (void)hipSetDevice(ctx->device);
     for (auto &s : ctx->slots) destroy_slot(*s);
     if (ctx->plain) destroy_slot(*ctx->plain);

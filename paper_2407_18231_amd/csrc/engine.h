@@ -52,6 +52,9 @@ struct DevGeom {
     const Surface *surf;        // n_surf
     const float2 *mod_phi;      // n_mod: azimuth centre and half-width (with margin)
     const float4 *mod_ext;      // 2 per module: accepted extent of a hit, sensor positions
+    const uint32_t *run_begin;  // n_mod + 1: segment-walk runs of each module's edges
+    const uint4 *run;           // (first destination, class | length << 24, azimuth centre, pitch)
+    const float *run_win;       // window of each run (radians)
     uint32_t hist_slice;        // hit histogram in LDS: (module, sensor) bins per slice
 };
 
@@ -285,6 +288,11 @@ inline BlockLayout served_block_layout(uint32_t n_hits, uint32_t n_pls)
     return l;
 }
 void launch_unpack(Launcher &L, const Batch &b, const Totals *t, const char *raw, const unsigned long long *raw_off);
+// the output image of the staged batch (event table, cleaning counts, then
+// every event's lists in the layout of lst_event_out) at img, head words of
+// table and counts first; nothing is written at or past cap words
+void launch_pack(Launcher &L, const Batch &b, const Totals *t, uint32_t *img, uint32_t n_ev, uint64_t head,
+                 uint64_t cap, bool clean, uint64_t n_items);
 void launch_event_out(Launcher &L, const Batch &b, const Totals *t, const EventOut &o, uint64_t n_items);
 void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, const Consts &c, int stats);
 

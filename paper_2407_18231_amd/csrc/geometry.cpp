@@ -12,6 +12,7 @@
 // asin(x) / x the arc/chord ratio.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <map>
 #include <tuple>
 
@@ -53,6 +54,13 @@ double wrap2pi(double x)
     return x;
 }
 
+// x - 2 pi k in (-pi, pi]
+double wrap_pi(double x)
+{
+    x = wrap2pi(x);
+    return x > kPi ? x - kTwoPi : x;
+}
+
 // smallest azimuth distance between arcs [a0, a1] and [b0, b1]
 double arc_gap(double a0, double a1, double b0, double b1)
 {
@@ -71,6 +79,8 @@ struct ZoneKey {
 };
 
 }  // namespace
+
+float ls_reach(const LsClass &k) { return (float)(std::asin(std::min(1.0, (double)k.S)) + 2e-5); }
 
 lst_status build_geometry(const lst_params &p, const lst_module_desc *m, uint32_t n,
                           Geometry &g, std::string &err)
@@ -373,6 +383,58 @@ lst_status build_geometry(const lst_params &p, const lst_module_desc *m, uint32_
         if (c > kPi) c -= kTwoPi;
         g.mod_phi[2 * (size_t)B] = (float)c;
         g.mod_phi[2 * (size_t)B + 1] = (float)(0.5 * (b.phi_max - b.phi_min) + mphiB);
+    }
+
+    // segment-walk runs.  Module k of a run (destination first + k) has its
+    // azimuth centre within dev of phi0 + k * pitch (binary32 values as
+    // stored, the difference taken in binary64); the window is the largest
+    // half-width plus the class's reach plus dev plus 1e-4 for the binary32
+    // arithmetic of the run test, so every module the per-module reach test
+    // accepts lies in the run's accepted index range.  Runs end where the
+    // destinations stop being consecutive, the class changes, a centre
+    // strays by more than 1e-3 from the pitch, or the span plus the window
+    // nears half a turn (the run test takes no wrap-around past the span).
+    g.run_begin.assign(n + 1, 0);
+    g.run_rec.clear();
+    g.run_win.clear();
+    for (uint32_t A = 0; A < n; A++) {
+        const uint32_t e0 = g.edge_begin[A], e1 = g.edge_begin[A + 1];
+        for (uint32_t i = e0; i < e1;) {
+            const uint32_t first = g.edge_dst[i], cid = g.edge_cls[i];
+            const float reach = ls_reach(g.classes[cid]);
+            const double c0 = g.mod_phi[2 * (size_t)first];
+            double hw = g.mod_phi[2 * (size_t)first + 1];
+            double pitch = 0.0, u = 0.0;   // unwrapped centre of the last module, relative to c0
+            uint32_t len = 1;
+            while (i + len < e1 && len < 255u && g.edge_dst[i + len] == first + len && g.edge_cls[i + len] == cid) {
+                const uint32_t B = first + len;
+                const double step = wrap_pi(g.mod_phi[2 * (size_t)B] - g.mod_phi[2 * (size_t)B - 2]);
+                if (len == 1) {
+                    if (std::fabs(step) < 1e-4 || std::fabs(step) > 0.5) break;
+                    pitch = step;
+                } else if (std::fabs(u + step - len * pitch) > 1e-3) {
+                    break;
+                }
+                const double hwb = std::max(hw, (double)g.mod_phi[2 * (size_t)B + 1]);
+                if (std::fabs(u + step) + hwb + reach + 2e-3 > 3.0) break;
+                u += step;
+                hw = hwb;
+                len++;
+            }
+            if (len > 1) pitch = u / (len - 1);
+            const float phi0f = (float)c0, pitchf = (float)pitch;
+            double dev = 0.0;
+            for (uint32_t k = 1; k < len; k++)
+                dev = std::max(dev, std::fabs(wrap_pi(g.mod_phi[2 * (size_t)(first + k)] -
+                                                      ((double)phi0f + k * (double)pitchf))));
+            uint32_t rec[4] = {first, cid | (len << 24), 0u, 0u};
+            std::memcpy(&rec[2], &phi0f, 4);
+            std::memcpy(&rec[3], &pitchf, 4);
+            g.run_rec.insert(g.run_rec.end(), rec, rec + 4);
+            g.run_win.push_back((float)(hw + reach + dev + 1e-4));
+            i += len;
+        }
+        g.run_begin[A + 1] = (uint32_t)g.run_win.size();
     }
 
     // extent of every module as the ingest check reads it: azimuth centre in

@@ -395,72 +395,32 @@ __global__ void k_hit_scatter(const Batch b, const Totals *t)
     }
 }
 
-// per (event, module, sensor) bin: restore input order (the scatter used
-// atomic slots) and write the sorted SoA with r = sqrt(x^2 + y^2).  Bins of
-// up to four hits sort in registers.  Each hit is checked against the input
-// contract here, where its module's extent is loaded once per bin; a hit
-// outside fails its event (its lists are not used).
+// per sorted position: the hit there takes its place in input order within
+// its (event, module, sensor) bin -- the scatter used atomic slots -- as the
+// number of the bin's hits with a smaller input index, and is written to the
+// sorted SoA with r = sqrt(x^2 + y^2).  Each hit is checked against the input
+// contract (its module's extent); a hit outside fails its event (its lists
+// are not used).
 __global__ void k_hit_gather(const Batch b, Totals *t, const float4 *__restrict__ ext, uint32_t n_mod)
 {
-    const uint32_t nb = t->n_bins;
-    GRID_STRIDE(bin, nb) {
+    const uint32_t n = t->n_sorted;
+    GRID_STRIDE(i, n) {
+        const float4 v = b.hrec[i];
+        const uint32_t h = __float_as_uint(v.w);
+        const uint32_t bin = b.hbin[h];
         const uint32_t beg = b.bin_off[bin], end = b.bin_off[bin + 1];
-        if (beg == end) continue;
+        uint32_t pos = beg;
+        for (uint32_t j = beg; j < end; j++) pos += __float_as_uint(b.hrec[j].w) < h ? 1u : 0u;
         const uint32_t e = bin / (2u * n_mod);
-        const uint32_t h0 = b.ev_hit_off[e];
         const uint32_t local = bin - e * 2u * n_mod, m = local >> 1, sn = local & 1u;
-        const float4 ea = ext[2 * m], es = ext[2 * m + 1];
-        bool outside = false;
-        auto put = [&](uint32_t i, const float4 v) {
-            const float r = sqrtf(v.x * v.x + v.y * v.y);
-            outside = outside || !hit_inside(ea, es, sn, v.x, v.y, v.z, r);
-            b.hpos[i] = make_float4(v.x, v.y, v.z, r);
-            b.hin[i] = __float_as_uint(v.w) - h0;
-            b.hbin_s[i] = bin;
-        };
-        if (end - beg <= 4u) {
-            float4 v[4];
-#pragma unroll
-            for (uint32_t k = 0; k < 4; k++)
-                v[k] = beg + k < end ? b.hrec[beg + k] : make_float4(0.f, 0.f, 0.f, __uint_as_float(0xFFFFFFFFu));
-            // sorting network on the input index (padding, with the largest
-            // key, sorts last and is not written)
-            auto cswap = [&](int i, int j) {
-                if (__float_as_uint(v[i].w) > __float_as_uint(v[j].w)) {
-                    const float4 tmp = v[i];
-                    v[i] = v[j];
-                    v[j] = tmp;
-                }
-            };
-            cswap(0, 1);
-            cswap(2, 3);
-            cswap(0, 2);
-            cswap(1, 3);
-            cswap(1, 2);
-#pragma unroll
-            for (uint32_t k = 0; k < 4; k++)
-                if (beg + k < end) put(beg + k, v[k]);
-            if (outside) {
-                atomicOr(&t->err, kErrOutside);
-                atomicOr(&b.ev_err[e], kErrOutside);
-            }
-            continue;
-        }
-        for (uint32_t i = beg + 1; i < end; i++) {
-            const float4 v = b.hrec[i];
-            const uint32_t key = __float_as_uint(v.w);
-            uint32_t j = i;
-            while (j > beg && __float_as_uint(b.hrec[j - 1].w) > key) {
-                b.hrec[j] = b.hrec[j - 1];
-                j--;
-            }
-            b.hrec[j] = v;
-        }
-        for (uint32_t i = beg; i < end; i++) put(i, b.hrec[i]);
-        if (outside) {
+        const float r = sqrtf(v.x * v.x + v.y * v.y);
+        if (!hit_inside(ext[2 * m], ext[2 * m + 1], sn, v.x, v.y, v.z, r)) {
             atomicOr(&t->err, kErrOutside);
             atomicOr(&b.ev_err[e], kErrOutside);
         }
+        b.hpos[pos] = make_float4(v.x, v.y, v.z, r);
+        b.hin[pos] = h - b.ev_hit_off[e];
+        b.hbin_s[pos] = bin;
     }
 }
 
@@ -663,6 +623,38 @@ __device__ inline bool in_reach(float pha, const float2 mp, float reach)
     return d <= mp.y + reach;
 }
 
+// Modules [k0, k1) of a segment-walk run (destinations first + k, k below
+// its length) that can hold a partner of an inner anchor at azimuth pha: the
+// indices k with |delta - k * pitch| <= window, delta the anchor's azimuth
+// relative to the run's first module.  The window covers every module the
+// per-module reach test accepts (it holds the largest half-width, the reach,
+// the centres' deviation from the pitch and room for this arithmetic), and
+// a run spans less than half a turn with its window, so no wrap-around
+// beyond delta's is needed.  k1 == k0: none.
+__device__ inline uint2 run_range(const uint4 r, float win, float pha)
+{
+    const float len = (float)(r.y >> 24);
+    float d = pha - __uint_as_float(r.z);
+    if (d > kPiF) d -= 2.0f * kPiF;
+    else if (d < -kPiF) d += 2.0f * kPiF;
+    float k0, k1;
+    if (r.y >> 24 == 1u) {
+        k0 = 0.0f;
+        k1 = fabsf(d) <= win ? 1.0f : 0.0f;
+    } else {
+        const float p = __uint_as_float(r.w);
+        float t0 = (d - win) / p, t1 = (d + win) / p;
+        if (p < 0.0f) {
+            const float x = t0;
+            t0 = t1;
+            t1 = x;
+        }
+        k0 = fminf(fmaxf(ceilf(t0), 0.0f), len);
+        k1 = fmaxf(fminf(floorf(t1) + 1.0f, len), k0);
+    }
+    return make_uint2((uint32_t)k0, (uint32_t)k1);
+}
+
 __device__ inline bool ls_cut(const LsK &k, const Consts &c, bool bend,
                               float xa, float ya, float za, float ra, float beta_a,
                               float xb, float yb, float zb, float rb)
@@ -722,31 +714,33 @@ __device__ inline bool ls_cut(const LsK &k, const Consts &c, bool bend,
 }
 
 // Large batches: the 64 inner MDs of a wave (one per lane) step through
-// their modules' edges in groups of 6 together.  For each group a lane loads
-// its edges' MD ranges and stores them in LDS; the wave pools the
-// candidates (every MD of every edge of the group, lane by lane in (edge,
+// their modules' segment-walk runs (edges to consecutive destination modules
+// of one class, evenly spaced in azimuth) in groups of 6 together.  For each
+// run a lane computes which of its modules are within azimuth reach of its
+// anchor (an index range, from the run's record alone) and loads that range's
+// MDs (two MD offsets: consecutive modules hold consecutive MDs), storing the
+// ranges in LDS; a group thus costs two round trips (the run records, then
+// the MD offsets) whatever the number of edges in it.  The wave pools the
+// candidates (every MD of every run of the group, lane by lane in (run,
 // outer MD) order) and the lanes take them 64 at a time, so the cut
 // arithmetic runs on full waves however the degrees and MD counts are
-// spread.  The group's loads go out together (edge records, then every
-// edge's destination extent, class reach and MD range), two round trips per
-// group.  A candidate finds its owner lane from a mark each owner leaves in
+// spread.  A candidate finds its owner lane from a mark each owner leaves in
 // LDS at its first candidate of the step, spread to the following
 // candidates by a prefix maximum in registers (row shifts and broadcasts, no
-// chain of lane shuffles); its edge in the owner's group comes from LDS and
+// chain of lane shuffles); its run in the owner's group comes from LDS and
 // the owner's anchor by lane shuffles.  Survivors go to the block's region of
 // an unordered segment list with their place in the owner's list (its
-// earlier survivors plus those before it in the same 64); edges are sorted by
-// destination module, so that place is the canonical one.  The rounds are
-// bound by the latency of the outer MD and class loads; a step takes two
-// rounds, both rounds' loads issued before either cut.
-// kEdgeGroup edges per group; at least kMinWaves waves per SIMD (1: the
+// earlier survivors plus those before it in the same 64); runs follow the
+// edges' order by destination module, so that place is the canonical one.
+// A step takes two rounds, both rounds' loads issued before either cut.
+// kEdgeGroup runs per group; at least kMinWaves waves per SIMD (1: the
 // compiler's register choice).  Instantiated for the groups and occupancies
 // the tuner may pick (lst_params.ls_group, ls_waves).
 template <int kEdgeGroup, int kMinWaves>
 __global__ __launch_bounds__(256, kMinWaves) void k_ls(const Batch b, Totals *t, const DevGeom g, const Consts c,
                                                        uint32_t nsub, int stats)
 {
-    constexpr uint32_t kF = 3 * kEdgeGroup;          // per lane and edge of the group: first outer MD, running count, class
+    constexpr uint32_t kF = 3 * kEdgeGroup;          // per lane and run of the group: first outer MD, running count, class
     __shared__ uint32_t s_grp[4][kF][64];
     __shared__ uint32_t s_mark[4][128];               // owner lane + 1 at each owner's first candidate of a step
     __shared__ uint32_t s_n;                          // appends to this block's region
@@ -771,8 +765,8 @@ __global__ __launch_bounds__(256, kMinWaves) void k_ls(const Batch b, Totals *t,
             const uint32_t u = b.md_u[a] & kUnitMask;
             const uint32_t m = u % n_mod;
             ubase = u - m;
-            e0 = g.edge_begin[m];
-            e1 = g.edge_begin[m + 1];
+            e0 = g.run_begin[m];
+            e1 = g.run_begin[m + 1];
             const float4 pa = b.md_pos[a];
             xa = pa.x;
             ya = pa.y;
@@ -784,36 +778,37 @@ __global__ __launch_bounds__(256, kMinWaves) void k_ls(const Batch b, Totals *t,
         uint32_t run = 0;                             // segments of this lane's MD so far
         for (uint32_t eb = e0;; eb += kEdgeGroup) {
             if (__ballot(eb < e1) == 0ull) break;
-            // this lane's group: MD ranges of up to kEdgeGroup edges, to LDS.
-            // The loads of all the group's edges go out together (edges past
-            // the lane's last load a valid edge and are dropped after), then
-            // the destination's azimuth extent, the class's reach and the MD
-            // range of every edge together: two round trips per group.
-            uint2 ed[kEdgeGroup];
+            // this lane's group: MD ranges of up to kEdgeGroup runs, to LDS.
+            // The loads of all the group's run records go out together (runs
+            // past the lane's last load a valid run and are dropped after),
+            // then the MD offsets of every run's range in reach together.
+            uint4 rr[kEdgeGroup];
+            float rw[kEdgeGroup];
 #pragma unroll
-            for (int j = 0; j < kEdgeGroup; j++) ed[j] = g.edge[min(eb + j, e1 > e0 ? e1 - 1u : 0u)];
-            float2 mp[kEdgeGroup];
-            float rch[kEdgeGroup];
+            for (int j = 0; j < kEdgeGroup; j++) {
+                const uint32_t r = min(eb + j, e1 > e0 ? e1 - 1u : 0u);
+                rr[j] = g.run[r];
+                rw[j] = g.run_win[r];
+            }
             uint32_t lo[kEdgeGroup], hi[kEdgeGroup];
 #pragma unroll
             for (int j = 0; j < kEdgeGroup; j++) {
-                mp[j] = g.mod_phi[ed[j].x];
-                rch[j] = g.cls[ed[j].y].b.z;
-                lo[j] = b.md_off[ubase + ed[j].x];
-                hi[j] = b.md_off[ubase + ed[j].x + 1];
+                const uint2 kr = run_range(rr[j], rw[j], pha);
+                lo[j] = b.md_off[ubase + rr[j].x + kr.x];
+                hi[j] = b.md_off[ubase + rr[j].x + kr.y];
             }
             uint32_t T = 0;
 #pragma unroll
             for (int j = 0; j < kEdgeGroup; j++) {
                 uint32_t bq = 0, eq = 0;
-                if (eb + j < e1 && in_reach(pha, mp[j], rch[j])) {
+                if (eb + j < e1) {
                     bq = min(lo[j], b.cap_md);
                     eq = max(min(hi[j], b.cap_md), bq);
                 }
                 T += eq - bq;
                 s_grp[wv][j][lane] = bq;
                 s_grp[wv][kEdgeGroup + j][lane] = T;  // cum[j + 1]
-                s_grp[wv][2 * kEdgeGroup + j][lane] = ed[j].y;
+                s_grp[wv][2 * kEdgeGroup + j][lane] = rr[j].y & 0xFFFFFFu;
             }
             wave_lds_sync();
             const uint32_t incl = wave_incl_scan(T);
@@ -840,7 +835,7 @@ __global__ __launch_bounds__(256, kMinWaves) void k_ls(const Batch b, Totals *t,
                     const uint32_t m = wave_incl_max(max(mk2[r], carry));
                     carry = (uint32_t)__builtin_amdgcn_readlane((int)m, 63);
                     const uint32_t ow = m - 1u;
-                    // edge j of the owner's group: the last with cum[j] <= tt
+                    // run j of the owner's group: the last with cum[j] <= tt
                     // (lanes past the total read valid LDS and load entry 0)
                     const uint32_t tt = ci - __shfl(off, ow);
                     uint32_t j = 0, cj = 0;
@@ -2210,7 +2205,7 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     L.launch_lds("hit_hist", k_hit_hist, gh, dim3(kHistBlock), g.hist_slice * 4u, b, t, n_mod, g.hist_slice);
     L.scan(b.bin_cnt, b.bin_off, &t->n_bins, b.cap_ev * 2u * n_mod, &t->n_sorted, "scan_hits");
     L.launch("hit_scatter", k_hit_scatter, grid_for(b.cap_hits), blk, b, (const Totals *)t);
-    L.launch("hit_gather", k_hit_gather, grid_for((uint64_t)b.cap_ev * 2 * n_mod), blk, b, t, g.mod_ext, n_mod);
+    L.launch("hit_gather", k_hit_gather, grid_for(b.cap_hits), blk, b, t, g.mod_ext, n_mod);
     // a2: mini-doublets
     L.stage = LST_STAGE_MD;
     // small batches: count and fill in place for latency; large ones: pooled walk
@@ -2387,6 +2382,184 @@ __global__ void k_unpack(const Batch b, const Totals *t, const char *__restrict_
         for (uint32_t w = 0; w < 5u; w++) b.in_par[5u * (size_t)p + w] = pp[w];
         for (uint32_t w = 0; w < 15u; w++) b.in_cov[15u * (size_t)p + w] = pc[w];
     }
+}
+
+// Output image of a batch, in 32-bit words: the event table ((n_ev + 1) rows),
+// then per event the number of kept candidates of the duplicate cleaning,
+// then each event's lists in the layout of lst_event_out with event-local
+// indices: MD, LS, T3, T5, pT3, pT5 pairs, the track-candidate pairs (every
+// pT5, then the kept pT3, T5 and seed entries), the T3 curvatures and, with
+// the cleaning, the candidates it keeps.  The host copies a batch's outputs
+// in one transfer and hands each event pointers into it.
+__device__ inline uint64_t image_words_before(const uint32_t *r, bool clean)
+{
+    // r holds the first index of every list of an event: the words of the
+    // images of all events before it, up to those of event 0
+    const uint64_t pairs = (uint64_t)r[2] + r[3] + r[4] + r[5] + r[6] + 2ull * r[7] + r[8] + r[9] + r[10];
+    return 2ull * pairs + r[4] + (clean ? 2ull * ((uint64_t)r[7] + r[8] + r[9] + r[10]) : 0ull);
+}
+
+struct EventImage {
+    uint32_t *md, *ls, *t3, *t5, *pt3, *pt5, *tc, *kappa, *tcc;
+    uint32_t cp5, c3, c5;   // pT5s, and track candidates from pT3s and from T5s
+};
+
+__device__ inline EventImage event_image(uint32_t *img, uint64_t head, const uint32_t *tab, uint32_t e, bool clean)
+{
+    const uint32_t *r0 = tab + (size_t)e * kEvTabCols, *r1 = r0 + kEvTabCols;
+    EventImage m;
+    const uint32_t cmd = r1[2] - r0[2], cls = r1[3] - r0[3], ct3 = r1[4] - r0[4], ct5 = r1[5] - r0[5];
+    const uint32_t cp3 = r1[6] - r0[6];
+    m.cp5 = r1[7] - r0[7];
+    m.c3 = r1[8] - r0[8];
+    m.c5 = r1[9] - r0[9];
+    const uint32_t ctc = m.cp5 + m.c3 + m.c5 + (r1[10] - r0[10]);
+    m.md = img + head + (image_words_before(r0, clean) - image_words_before(tab, clean));
+    m.ls = m.md + 2u * cmd;
+    m.t3 = m.ls + 2u * cls;
+    m.t5 = m.t3 + 2u * ct3;
+    m.pt3 = m.t5 + 2u * ct5;
+    m.pt5 = m.pt3 + 2u * cp3;
+    m.tc = m.pt5 + 2u * m.cp5;
+    m.kappa = m.tc + 2u * ctc;
+    m.tcc = m.kappa + ct3;
+    return m;
+}
+
+// The blocks of row y take event y and stride over its entries, list by
+// list (consecutive threads, consecutive entries); row 0 also copies the
+// event table.  Nothing is written at or past cap words.
+__global__ void k_pack(const Batch b, const Totals *t, uint32_t *__restrict__ img, uint64_t head, uint64_t cap,
+                       uint32_t clean)
+{
+    const uint32_t n_ev = t->n_ev;
+    const uint32_t e = blockIdx.y;
+    if (e >= n_ev) return;
+    const uint32_t *tab = b.ev_tab;
+    const uint32_t stride = gridDim.x * blockDim.x, first = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e == 0u) {
+        const uint32_t n_tab = (n_ev + 1u) * kEvTabCols;
+        for (uint32_t q = first; q < n_tab; q += stride)
+            if (q < cap) img[q] = tab[q];
+    }
+    const uint32_t *r0 = tab + (size_t)e * kEvTabCols, *r1 = r0 + kEvTabCols;
+    const EventImage m = event_image(img, head, tab, e, clean != 0u);
+    const uint32_t md0 = r0[2], ls0 = r0[3], t30 = r0[4], t50 = r0[5], p30 = r0[6], p50 = r0[7], pls0 = r0[1];
+    const uint32_t cmd = r1[2] - md0, cls = r1[3] - ls0, ct3 = r1[4] - t30, ct5 = r1[5] - t50;
+    const uint32_t cp3 = r1[6] - p30, cp = r1[10] - r0[10];
+    // entry q of the event: [md | ls | t3 | t5 | pt3 | pt5 | pT5 candidates |
+    // candidates from pT3s, T5s, seeds | curvatures]
+    const uint32_t b1 = cmd, b2 = b1 + cls, b3 = b2 + ct3, b4 = b3 + ct5, b5 = b4 + cp3, b6 = b5 + m.cp5;
+    const uint32_t b7 = b6 + m.cp5, b8 = b7 + m.c3, b9 = b8 + m.c5, b10 = b9 + cp, b11 = b10 + ct3;
+    for (uint32_t q = first; q < b11; q += stride) {
+        uint32_t *d;
+        uint32_t x, y;
+        if (q < b1) {
+            const uint32_t k = md0 + q;
+            d = m.md + 2u * q; x = b.md_hlo[k]; y = b.md_hup[k];
+        } else if (q < b2) {
+            const uint32_t i = q - b1, k = ls0 + i;
+            d = m.ls + 2u * i; x = b.ls_a[k] - md0; y = b.ls_b[k] - md0;
+        } else if (q < b3) {
+            const uint32_t i = q - b2, k = t30 + i;
+            d = m.t3 + 2u * i; x = b.t3_l1[k] - ls0; y = b.t3_l2[k] - ls0;
+        } else if (q < b4) {
+            const uint32_t i = q - b3, k = t50 + i;
+            d = m.t5 + 2u * i; x = b.t5_u[k] - t30; y = b.t5_w[k] - t30;
+        } else if (q < b5) {
+            const uint32_t i = q - b4, k = p30 + i;
+            d = m.pt3 + 2u * i; x = b.pt3_p[k] - pls0; y = b.pt3_o[k] - t30;
+        } else if (q < b6) {
+            const uint32_t i = q - b5, k = p50 + i;
+            d = m.pt5 + 2u * i; x = b.pt5_p[k] - pls0; y = b.pt5_o[k] - t50;
+        } else if (q < b7) {
+            const uint32_t i = q - b6;
+            d = m.tc + 2u * i; x = LST_TC_PT5; y = i;
+        } else if (q < b10) {
+            // index relative to the event's first object of the candidate's kind
+            const uint32_t i = q - b7;
+            uint32_t k, base;
+            if (q < b8) { k = r0[8] + i; base = p30; }
+            else if (q < b9) { k = r0[9] + (q - b8); base = t50; }
+            else { k = r0[10] + (q - b9); base = pls0; }
+            d = m.tc + 2u * (m.cp5 + i); x = b.tc_type[k]; y = b.tc_idx[k] - base;
+        } else {
+            const uint32_t i = q - b10;
+            d = m.kappa + i;
+            if ((uint64_t)(d - img) < cap) *d = __float_as_uint(b.t3_ks[t30 + i].x);
+            continue;
+        }
+        if ((uint64_t)(d - img) + 1u < cap) {
+            d[0] = x;
+            d[1] = y;
+        }
+    }
+}
+
+// Duplicate cleaning: the kept candidates of each event, in the order of its
+// track-candidate list, and their number (one block per event).
+__global__ void __launch_bounds__(256) k_pack_tcc(const Batch b, const Totals *t, uint32_t *__restrict__ img,
+                                                  uint64_t head, uint64_t cap)
+{
+    __shared__ uint32_t s_cnt[4];
+    const uint32_t n_ev = t->n_ev;
+    const uint32_t e = blockIdx.x;
+    if (e >= n_ev) return;
+    const uint32_t *tab = b.ev_tab;
+    const uint32_t *r0 = tab + (size_t)e * kEvTabCols, *r1 = r0 + kEvTabCols;
+    const uint32_t np5 = tab[(size_t)n_ev * kEvTabCols + 7];
+    const EventImage m = event_image(img, head, tab, e, true);
+    const uint32_t ctc = m.cp5 + m.c3 + m.c5 + (r1[10] - r0[10]);
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    uint32_t kept = 0;
+    for (uint32_t j0 = 0; j0 < ctc; j0 += 256u) {
+        const uint32_t j = j0 + threadIdx.x;
+        bool keep = false;
+        uint32_t x = 0, y = 0;
+        if (j < ctc) {
+            if (j < m.cp5) {
+                keep = b.tcc_keep[r0[7] + j] != 0;
+                x = LST_TC_PT5;
+                y = j;
+            } else {
+                uint32_t r = j - m.cp5, col = 8u;
+                if (r >= m.c3) { r -= m.c3; col = 9u; }
+                if (col == 9u && r >= m.c5) { r -= m.c5; col = 10u; }
+                const uint32_t k = r0[col] + r;
+                const uint32_t base = col == 8u ? r0[6] : col == 9u ? r0[5] : r0[1];
+                keep = b.tcc_keep[np5 + k] != 0;
+                x = b.tc_type[k];
+                y = b.tc_idx[k] - base;
+            }
+        }
+        const unsigned long long bal = __ballot(keep);
+        if (lane == 0) s_cnt[wv] = (uint32_t)__popcll(bal);
+        __syncthreads();
+        uint32_t before = kept;
+        for (uint32_t w = 0; w < wv; w++) before += s_cnt[w];
+        before += (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+        if (keep) {
+            uint32_t *d = m.tcc + 2u * before;
+            if ((uint64_t)(d - img) + 1u < cap) {
+                d[0] = x;
+                d[1] = y;
+            }
+        }
+        kept += s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+        __syncthreads();
+    }
+    const uint64_t at = (uint64_t)(n_ev + 1) * kEvTabCols + e;
+    if (threadIdx.x == 0 && at < cap) img[at] = kept;
+}
+
+void launch_pack(Launcher &L, const Batch &b, const Totals *t, uint32_t *img, uint32_t n_ev, uint64_t head,
+                 uint64_t cap, bool clean, uint64_t n_items)
+{
+    // blocks per event: enough for the average event's entries, at most 64
+    const uint64_t per_ev = n_ev ? n_items / n_ev : 0;
+    const uint32_t bx = (uint32_t)std::min<uint64_t>(64, std::max<uint64_t>(1, per_ev / (256 * 8)));
+    if (n_ev) L.launch("pack", k_pack, dim3(bx, n_ev), dim3(256), b, t, img, head, cap, clean ? 1u : 0u);
+    if (clean && n_ev) L.launch("pack_tcc", k_pack_tcc, dim3(n_ev), dim3(256), b, t, img, head, cap);
 }
 
 void launch_unpack(Launcher &L, const Batch &b, const Totals *t, const char *raw, const unsigned long long *raw_off)

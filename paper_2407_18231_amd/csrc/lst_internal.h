@@ -35,6 +35,10 @@ struct LsClass {
 };
 static_assert(sizeof(LsClass) == 64, "LsClass layout");
 
+// Largest azimuth difference of a segment's anchors for a class, asin(S),
+// with room for the binary32 arithmetic of the per-segment reach test.
+float ls_reach(const LsClass &k);
+
 // Surfaces (barrel layers, disks) as seen by the seed lookup.
 struct Surface {
     uint32_t kind;           // LST_BARREL / LST_ENDCAP
@@ -52,7 +56,7 @@ struct Consts {
     uint32_t nkb;            // curvature bins of the seed-lookup buckets (per resolution class)
     float kspan;             // curvature bins cover [-kspan, kspan]
     float sk_cls[3];         // resolution classes: sigma_kappa <= sk_cls[i]; larger ones go to the wide bin
-    uint32_t ls_group;       // segment walk: edges per group (4, 6, 8)
+    uint32_t ls_group;       // segment walk: runs of edges per group (4, 6, 8)
     uint32_t ls_waves;       // segment walk: minimum waves per SIMD (0: the compiler's choice, 6, 8)
 };
 
@@ -66,6 +70,13 @@ struct Geometry {
     std::vector<uint32_t> edge_dst;   // per edge: destination module
     std::vector<uint32_t> edge_cls;   // per edge: class id
     std::vector<LsClass> classes;
+    // segment-walk runs: edges of a module to consecutive destinations of
+    // one class with evenly spaced azimuth centres, one record per run
+    // (first destination, class | length << 24, azimuth centre of the first
+    // module, pitch) and its window (radians)
+    std::vector<uint32_t> run_begin;  // n_mod + 1
+    std::vector<uint32_t> run_rec;    // 4 per run
+    std::vector<float> run_win;       // per run
     // per module: azimuth centre in (-pi, pi] and half-width, widened by the
     // connection map's hit-position margin (radians)
     std::vector<float> mod_phi;

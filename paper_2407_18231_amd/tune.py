@@ -5,8 +5,8 @@ Two choices change only the speed, never the lists:
     row and curvature bins per resolution class (lst_params.n_phi_bins,
     n_kappa_bins) -- finer bins mean fewer candidate entries per seed but
     more bucket offsets to load, scan and clear;
-  * the segment walk's tile: edges per group (ls_group 4 / 6 / 8, i.e. how
-    many MD ranges a lane loads per step) and its occupancy (ls_waves: the
+  * the segment walk's tile: runs of edges per group (ls_group 4 / 6 / 8,
+    i.e. how many MD ranges a lane loads per step) and its occupancy (ls_waves: the
     compiler's register choice, or at least 6 or 8 waves per SIMD).
 The tuner times the bucket grid first, then the segment-walk variants at the
 best grid, each on a batch on the device (hipGraph replays of the whole

@@ -259,3 +259,25 @@ def test_served_pu300_stress_batches_of_32(g):
         same(a, o)
     for i in (0, 31):
         check_parity(g, evs[i], outs[i])
+
+
+def test_outputs_outlive_context_and_each_other(g, ctx):
+    """The outputs of one batch share a pinned buffer: freeing one leaves the
+    others whole, and they stay readable after the context is destroyed."""
+    import ctypes as C
+    evs = [s.gen_event(g, s.config_pu(100), s.event_seed(2, 40 + i)) for i in range(3)]
+    ref = [ctx.run_event(ev) for ev in evs]
+    c = lst.Context(max_batch=4)
+    c.load_geometry(g)
+    es = [lst.EventIn(ev) for ev in evs]
+    arr = (lst.lst_event_in * 3)(*[e.c for e in es])
+    outs = (C.POINTER(lst.lst_event_out) * 3)()
+    c._check(c.L.lst_run_batch(c.h, arr, 3, outs))
+    L = c.L
+    c.close()
+    L.lst_free_output(outs[1])
+    for k in (2, 0):
+        got = lst._out_to_dict(outs[k].contents)
+        same(ref[k], got)
+        assert np.array_equal(ref[k]["t3_kappa"].view(np.uint32), got["t3_kappa"].view(np.uint32))
+        L.lst_free_output(outs[k])
