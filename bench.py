@@ -179,11 +179,16 @@ def main():
     ap.add_argument("--graph", action="store_true", help="with --chain-only: replay the captured graph")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="counter calibration: one device-to-device copy of MB megabytes (torch)")
+    ap.add_argument("--link-probe", action="store_true",
+                    help="host link bandwidth of large pinned copies, each way and both at once")
     ap.add_argument("--served-only", type=int, default=0, metavar="N",
                     help="trace runs: N events (PU ~ U[140, 200]) submitted back to back to the served path")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.link_probe:
+        log("host link:", link_probe())
         return
     if args.served_only:
         from paper_2407_18231_amd import lst, synth
@@ -353,6 +358,9 @@ def main():
         result["served"] = served(g, pool4)
         result["served_pu300_stress"] = served_stress(g, pool5)
         log("served stress:", result["served_pu300_stress"])
+        # what the served path moves per event crosses this link both ways
+        result["host_link"] = link_probe()
+        log("host link:", result["host_link"])
     ctx.close()
 
     if not args.no_cpu:
@@ -388,6 +396,21 @@ def copy_probe(mb: int):
     b.copy_(a)
     torch.cuda.synchronize()
     log(f"copied {mb} MiB")
+
+
+def link_probe():
+    """Host link bandwidth (GB/s) between pinned host memory and the device
+    as the served path uses it (paper_2407_18231_amd/csrc/link_probe.hip, run
+    as a separate process): one 96 MiB copy and the same bytes in 1100 KiB
+    pieces, host to device, device to host, and both directions at once."""
+    import subprocess
+    exe = os.path.join(ROOT, "paper_2407_18231_amd", "link_probe")
+    if not os.path.exists(exe):
+        return None
+    out = subprocess.run([exe, "96", "1100"], capture_output=True, text=True, timeout=120)
+    if out.returncode != 0:
+        return None
+    return json.loads(out.stdout.strip().splitlines()[-1])
 
 
 _INPUT_KEYS = ("x", "y", "z", "module", "sensor", "pls_par", "pls_cov")

@@ -13,6 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblst.so")
 PROBE = os.path.join(HERE, "sync_probe")
+LINK_PROBE = os.path.join(HERE, "link_probe")
 SOURCES = ["geometry.cpp", "kernels.hip", "api.hip"]
 
 FLAGS = [
@@ -75,6 +76,13 @@ def build(verbose: bool = False) -> str:
         print(" ".join(probe), flush=True)
     subprocess.check_call(probe)
     os.replace(PROBE + ".tmp", PROBE)
+    # the host-link probe (bench.py runs it too)
+    link = [hipcc, "--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+            "-packed-fp32-ops", os.path.join(CSRC, "link_probe.hip"), "-o", LINK_PROBE + ".tmp"]
+    if verbose:
+        print(" ".join(link), flush=True)
+    subprocess.check_call(link)
+    os.replace(LINK_PROBE + ".tmp", LINK_PROBE)
     return LIB
 
 

@@ -52,6 +52,44 @@ Caps plan_caps(uint32_t n_ev, uint64_t hits, uint64_t pls)
     return c;
 }
 
+// Capacities of the walks' sub-lists: an even share of the list's capacity
+// per walk block plus the slack of that walk (never smaller than before).
+void plan_sublists(Batch &b)
+{
+    auto at_least = [](uint32_t &cap, uint64_t want) { cap = std::max(cap, clamp32(want)); };
+    at_least(b.cap_mds, (uint64_t)b.cap_md + (uint64_t)walk_blocks(b.cap_hits) * kRegionSlack);
+    at_least(b.cap_lss, (uint64_t)b.cap_ls + (uint64_t)walk_blocks(b.cap_md) * kRegionSlack);
+    at_least(b.cap_t3s, (uint64_t)b.cap_t3 + (uint64_t)walk_blocks(b.cap_ls) * kRegionSlackT3);
+    at_least(b.cap_t5s, (uint64_t)b.cap_t5 + (uint64_t)walk_blocks(b.cap_t3) * kRegionSlackT5);
+}
+
+// After a run: a quarter more room for every list (or sub-list) whose
+// count (or largest region, times the regions) exceeded its capacity.
+// True when anything grew (the batch must run again).
+bool grow_caps(Batch &b, const Totals &t)
+{
+    auto grow = [](uint32_t need, uint32_t &cap) {
+        if (need <= cap) return false;
+        cap = clamp32((uint64_t)need + need / 4 + 1024);
+        return true;
+    };
+    bool g = false;
+    g |= grow(t.n_md, b.cap_md);
+    g |= grow(t.n_ls, b.cap_ls);
+    g |= grow(t.n_t3, b.cap_t3);
+    g |= grow(t.n_t5, b.cap_t5);
+    g |= grow(t.n_mds, b.cap_mds);
+    g |= grow(t.n_lss, b.cap_lss);
+    g |= grow(t.n_t3s, b.cap_t3s);
+    g |= grow(t.n_t5s, b.cap_t5s);
+    g |= grow(t.n_pt3, b.cap_pt3);
+    g |= grow(t.n_pt5, b.cap_pt5);
+    g |= grow(t.n_ptc3, b.cap_ptc3);
+    g |= grow(t.n_ptc5, b.cap_ptc5);
+    if (g) plan_sublists(b);
+    return g;
+}
+
 // Sub-allocates the device arena; with base == nullptr only sums the sizes.
 struct Carver {
     char *base;
@@ -96,7 +134,7 @@ void carve_work(Carver &cv, Batch &b, uint32_t n_mod, uint32_t n_surf, uint32_t 
     b.hbin_s = cv.take<uint32_t>(b.cap_hits);
     b.md_cnt = cv.take<uint32_t>((size_t)b.cap_hits + 1);
     b.md_hoff = cv.take<uint32_t>((size_t)b.cap_hits + 1);
-    b.mds = cv.take<uint4>(b.cap_md);
+    b.mds = cv.take<uint4>(b.cap_mds);
     b.mds_sub = cv.take<uint32_t>(kSubLists);
     b.mds_soff = cv.take<uint32_t>(kSubLists + 1);
     b.md_off = cv.take<uint32_t>(units + 1);
@@ -110,20 +148,20 @@ void carve_work(Carver &cv, Batch &b, uint32_t n_mod, uint32_t n_surf, uint32_t 
     b.ls_a = cv.take<uint32_t>(b.cap_ls);
     b.ls_b = cv.take<uint32_t>(b.cap_ls);
     b.ls_keep = cv.take<uint32_t>((size_t)b.cap_md * kKeepLs);
-    b.lss_a = cv.take<uint32_t>(b.cap_ls);
-    b.lss_b = cv.take<uint32_t>(b.cap_ls);
-    b.lss_j = cv.take<uint32_t>(b.cap_ls);
+    b.lss_a = cv.take<uint32_t>(b.cap_lss);
+    b.lss_b = cv.take<uint32_t>(b.cap_lss);
+    b.lss_j = cv.take<uint32_t>(b.cap_lss);
     b.lss_sub = cv.take<uint32_t>(kSubLists);
     b.lss_soff = cv.take<uint32_t>(kSubLists + 1);
     b.t3_cnt = cv.take<uint32_t>((size_t)b.cap_ls + 1);
     b.t3_off = cv.take<uint32_t>((size_t)b.cap_ls + 1);
     b.t3_l1 = cv.take<uint32_t>(b.cap_t3);
     b.t3_l2 = cv.take<uint32_t>(b.cap_t3);
-    b.t3s_l1 = cv.take<uint32_t>(b.cap_t3);
-    b.t3s_l2 = cv.take<uint32_t>(b.cap_t3);
-    b.t3s_j = cv.take<uint32_t>(b.cap_t3);
-    b.t3s_ac = cv.take<uint2>(b.cap_t3);
-    b.t3s_ks = cv.take<float2>(b.cap_t3);
+    b.t3s_l1 = cv.take<uint32_t>(b.cap_t3s);
+    b.t3s_l2 = cv.take<uint32_t>(b.cap_t3s);
+    b.t3s_j = cv.take<uint32_t>(b.cap_t3s);
+    b.t3s_ac = cv.take<uint2>(b.cap_t3s);
+    b.t3s_ks = cv.take<float2>(b.cap_t3s);
     b.t3s_sub = cv.take<uint32_t>(kSubLists);
     b.t3s_soff = cv.take<uint32_t>(kSubLists + 1);
     b.t3_ac = cv.take<uint2>(b.cap_t3);
@@ -133,10 +171,10 @@ void carve_work(Carver &cv, Batch &b, uint32_t n_mod, uint32_t n_surf, uint32_t 
     b.t5_u = cv.take<uint32_t>(b.cap_t5);
     b.t5_w = cv.take<uint32_t>(b.cap_t5);
     b.t5_ks = cv.take<float2>(b.cap_t5);
-    b.t5s_u = cv.take<uint32_t>(b.cap_t5);
-    b.t5s_w = cv.take<uint32_t>(b.cap_t5);
-    b.t5s_j = cv.take<uint32_t>(b.cap_t5);
-    b.t5s_ks = cv.take<float2>(b.cap_t5);
+    b.t5s_u = cv.take<uint32_t>(b.cap_t5s);
+    b.t5s_w = cv.take<uint32_t>(b.cap_t5s);
+    b.t5s_j = cv.take<uint32_t>(b.cap_t5s);
+    b.t5s_ks = cv.take<float2>(b.cap_t5s);
     b.t5s_sub = cv.take<uint32_t>(kSubLists);
     b.t5s_soff = cv.take<uint32_t>(kSubLists + 1);
     b.bk3_cnt = cv.take<uint32_t>(bk + 1);
@@ -209,8 +247,7 @@ struct Slot {
     hipStream_t side = nullptr;
     char *h_stage = nullptr;
     size_t stage_bytes = 0;
-    uint32_t *img = nullptr;            // device output image of the batch (in the work arena)
-    size_t img_words = 0;
+    size_t img_words = 0;               // largest output image the list capacities allow
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     bool graph_valid = false;
@@ -255,6 +292,7 @@ struct PinnedPool {
     std::mutex mu;
     std::map<size_t, std::vector<char *>> free_blocks;
     std::vector<char *> all;
+    unsigned flags = hipHostMallocDefault;   // hipHostMalloc flags of new blocks
     static size_t size_class(size_t bytes)
     {
         size_t c = 64 << 10;
@@ -279,7 +317,7 @@ struct PinnedPool {
         }
         char *p = nullptr;
         cls = size_class(bytes + headroom);
-        if (hipHostMalloc((void **)&p, cls, hipHostMallocDefault) != hipSuccess) return nullptr;
+        if (hipHostMalloc((void **)&p, cls, flags) != hipSuccess) return nullptr;
         std::lock_guard<std::mutex> g(mu);
         all.push_back(p);
         return p;
@@ -329,11 +367,87 @@ lst_event_out *new_out()
     return b ? &b->pub : nullptr;
 }
 
+// Pinned chunks that submitted events are appended to, one after the other,
+// so that the events of a micro-batch lie (nearly) back to back and reach the
+// device in a few large copies instead of one copy per event.  A chunk goes
+// back to the free list once none of its events is held and it is no longer
+// the one being appended to; an event larger than a chunk gets one of its
+// own.
+struct InChunk {
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+    uint32_t live = 0;       // events in the chunk not yet released
+};
+
+struct InChunks {
+    static constexpr size_t kChunk = 64ull << 20;
+    static constexpr size_t kAlign = 256;
+    std::mutex mu;
+    std::vector<InChunk *> all, free_list;
+    InChunk *open = nullptr;
+    // room for an event block: its chunk and offset; false if pinned memory
+    // cannot be had
+    bool get(size_t bytes, InChunk *&c, size_t &off)
+    {
+        std::lock_guard<std::mutex> g(mu);
+        const size_t need = (bytes + kAlign - 1) / kAlign * kAlign;
+        if (!open || open->used + need > open->cap) {
+            InChunk *old = open;
+            open = nullptr;
+            if (old && old->live == 0) { old->used = 0; free_list.push_back(old); }
+            const size_t cap = std::max(kChunk, need);
+            for (size_t i = 0; i < free_list.size(); i++)
+                if (free_list[i]->cap >= cap) {
+                    open = free_list[i];
+                    free_list.erase(free_list.begin() + (long)i);
+                    break;
+                }
+            if (!open) {
+                InChunk *n = new (std::nothrow) InChunk;
+                if (!n) return false;
+                if (hipHostMalloc((void **)&n->base, cap, hipHostMallocDefault) != hipSuccess) {
+                    delete n;
+                    return false;
+                }
+                n->cap = cap;
+                all.push_back(n);
+                open = n;
+            }
+            open->used = 0;
+        }
+        c = open;
+        off = open->used;
+        open->used += need;
+        open->live++;
+        return true;
+    }
+    void put(InChunk *c)
+    {
+        if (!c) return;
+        std::lock_guard<std::mutex> g(mu);
+        if (--c->live == 0 && c != open) {
+            c->used = 0;
+            free_list.push_back(c);
+        }
+    }
+    void release()
+    {
+        for (InChunk *c : all) {
+            (void)hipHostFree(c->base);
+            delete c;
+        }
+        all.clear();
+        free_list.clear();
+        open = nullptr;
+    }
+    ~InChunks() { release(); }
+};
+
 struct ServedEvent {
     uint64_t ticket;
     uint32_t n_hits = 0, n_pls = 0;
-    char *blk = nullptr;        // pinned block (served_block_layout)
-    size_t blk_cls = 0;
+    InChunk *chunk = nullptr;   // pinned chunk holding the event's block (served_block_layout)
+    size_t blk_off = 0;         // the block's offset in the chunk
     size_t blk_bytes = 0;
     uint64_t footprint;
     std::chrono::steady_clock::time_point t_submit;
@@ -361,8 +475,14 @@ struct lst_ctx {
     // completion threads (a slot launched); done_cv: pollers (outputs ready)
     std::condition_variable q_cv, slot_cv, done_cv;
     std::deque<std::unique_ptr<ServedEvent>> waiting;
-    PinnedPool pinned;
-    std::shared_ptr<PinnedPool> out_pool = std::make_shared<PinnedPool>();   // output batches
+    InChunks in_chunks;                 // submitted events
+    // output batches: mapped and coherent, so that the pack kernel writes
+    // them over the host link itself (no device-to-host copy)
+    std::shared_ptr<PinnedPool> out_pool = [] {
+        auto p = std::make_shared<PinnedPool>();
+        p->flags = hipHostMallocMapped | hipHostMallocCoherent;
+        return p;
+    }();
     std::vector<int> slot_state;        // 0 free, 1 being staged, 2 launched
     std::vector<uint64_t> slot_mem;
     std::vector<std::vector<std::unique_ptr<ServedEvent>>> held;
@@ -414,7 +534,6 @@ void free_slot_arenas(Slot &s)
     if (s.in_arena) { (void)hipFree(s.in_arena); s.in_arena = nullptr; }
     if (s.work_arena) { (void)hipFree(s.work_arena); s.work_arena = nullptr; }
     if (s.h_stage) { (void)hipHostFree(s.h_stage); s.h_stage = nullptr; }
-    s.img = nullptr;   // part of the work arena
     s.in_bytes = s.work_bytes = s.stage_bytes = s.img_words = 0;
 }
 
@@ -485,6 +604,7 @@ lst_status ensure_inputs(lst_ctx *ctx, Slot &s, uint32_t n_ev, uint64_t hits, ui
     b.cap_ev = c.ev; b.cap_hits = std::max<uint32_t>(c.hits, 1); b.cap_pls = std::max<uint32_t>(c.pls, 1);
     b.cap_md = c.md; b.cap_ls = c.ls; b.cap_t3 = c.t3; b.cap_t5 = c.t5; b.cap_pt3 = c.pt3; b.cap_pt5 = c.pt5;
     b.cap_ptc3 = c.ptc3; b.cap_ptc5 = c.ptc5;
+    lst::plan_sublists(b);
     b.cap_tc = b.cap_pt3 + b.cap_t5 + b.cap_pls;
     lst::Carver ci{nullptr};
     lst::carve_inputs(ci, b);
@@ -506,15 +626,14 @@ lst_status ensure_work(lst_ctx *ctx, Slot &s)
     const lst::Consts &c = ctx->geom.c;
     lst::Carver cw{nullptr};
     lst::carve_work(cw, b, c.n_mod, c.n_surf, c.nphi, c.nkb);
-    // the output image of the batch follows the lists, sized for their
-    // capacities (download never allocates)
+    // the largest output image the list capacities allow (download checks
+    // the image it writes against it)
     const bool clean = (c.flags & LST_FLAG_TC_CLEAN) != 0u;
     const uint64_t img_words = (uint64_t)(b.cap_ev + 1) * lst::kEvTabCols + b.cap_ev +
                                2ull * ((uint64_t)b.cap_md + b.cap_ls + b.cap_t3 + b.cap_t5 + b.cap_pt3 +
                                        2ull * b.cap_pt5 + b.cap_tc) +
                                b.cap_t3 + (clean ? 2ull * ((uint64_t)b.cap_pt5 + b.cap_tc) : 0ull);
-    const size_t img_at = lst::align_up(cw.off);
-    s.work_bytes = img_at + 4 * img_words;
+    s.work_bytes = cw.off;
     hipError_t e = hipMalloc(&s.work_arena, s.work_bytes);
     if (e != hipSuccess) {
         s.work_arena = nullptr;
@@ -527,7 +646,6 @@ lst_status ensure_work(lst_ctx *ctx, Slot &s)
     }
     lst::Carver cw2{(char *)s.work_arena};
     lst::carve_work(cw2, b, c.n_mod, c.n_surf, c.nphi, c.nkb);
-    s.img = (uint32_t *)((char *)s.work_arena + img_at);
     s.img_words = img_words;
     s.graph_valid = false;
     return LST_OK;
@@ -654,26 +772,7 @@ lst_status enqueue(lst_ctx *ctx, Slot &s, bool use_graph, bool timing, bool stat
 
 // After the chain: fetch the counters; grow the work arena where a list
 // overflowed (the caller re-runs).  Returns 1 when a re-run is needed.
-int overflowed(Slot &s)
-{
-    const lst::Totals &t = *s.h_tot;
-    Batch &b = s.b;
-    auto grow = [](uint32_t need, uint32_t &cap) {
-        if (need <= cap) return false;
-        cap = lst::clamp32((uint64_t)need + need / 4 + 1024);
-        return true;
-    };
-    bool g = false;
-    g |= grow(std::max(t.n_md, t.n_mds), b.cap_md);
-    g |= grow(std::max(t.n_ls, t.n_lss), b.cap_ls);
-    g |= grow(std::max(t.n_t3, t.n_t3s), b.cap_t3);
-    g |= grow(std::max(t.n_t5, t.n_t5s), b.cap_t5);
-    g |= grow(t.n_pt3, b.cap_pt3);
-    g |= grow(t.n_pt5, b.cap_pt5);
-    g |= grow(t.n_ptc3, b.cap_ptc3);
-    g |= grow(t.n_ptc5, b.cap_ptc5);
-    return g ? 1 : 0;
-}
+int overflowed(Slot &s) { return lst::grow_caps(s.b, *s.h_tot) ? 1 : 0; }
 
 // Elapsed times of the timed launches since the last drain: per launch name
 // into the context's kernel table, per stage into the slot's stage times.
@@ -738,7 +837,6 @@ lst_status run_staged(lst_ctx *ctx, Slot &s, bool use_graph, bool stage_times, b
         if (s.graph) { (void)hipGraphDestroy(s.graph); s.graph = nullptr; }
         s.graph_valid = false;
         if (s.work_arena) { (void)hipFree(s.work_arena); s.work_arena = nullptr; }
-        s.img = nullptr;
         st = ensure_work(ctx, s);
         if (st != LST_OK) return st;
     }
@@ -759,7 +857,7 @@ lst_status download(lst_ctx *ctx, Slot &s, lst_event_out **outs)
     const uint64_t head = n_tab + n;
     const uint64_t pairs = (uint64_t)t.n_md + t.n_ls + t.n_t3 + t.n_t5 + t.n_pt3 + 2ull * t.n_pt5 + t.n_tc;
     const uint64_t words = head + 2 * pairs + t.n_t3 + (clean ? 2ull * ((uint64_t)t.n_pt5 + t.n_tc) : 0ull);
-    if (!s.img || words > s.img_words) {
+    if (words > s.img_words) {
         fail(ctx, "output image larger than the list capacities");
         return LST_ERR_DEVICE;
     }
@@ -774,13 +872,17 @@ lst_status download(lst_ctx *ctx, Slot &s, lst_event_out **outs)
         return set_err(ctx, LST_ERR_OOM, "pinned allocation of outputs failed");
     }
     ob->refs = 1;   // held while the outputs are made
+    // the pack kernel writes the image straight into the mapped host buffer
+    void *dimg = nullptr;
+    hipError_t he = hipHostGetDevicePointer(&dimg, ob->buf, 0);
     s.L.on_side(false);
     s.L.timing = false;
     s.L.err = hipSuccess;
     const uint64_t items = n_tab + pairs + t.n_t3;   // one per pair, curvature and table word
-    lst::launch_pack(s.L, s.b, s.d_tot, s.img, n, head, words, clean, items);
-    hipError_t he = s.L.err;
-    if (he == hipSuccess) he = hipMemcpyAsync(ob->buf, s.img, 4 * words, hipMemcpyDeviceToHost, s.stream);
+    if (he == hipSuccess) {
+        lst::launch_pack(s.L, s.b, s.d_tot, (uint32_t *)dimg, n, head, words, clean, items);
+        he = s.L.err;
+    }
     if (he == hipSuccess) he = hipStreamSynchronize(s.stream);
     if (he != hipSuccess) {
         ob->unref();
@@ -906,6 +1008,28 @@ lst_status stage_served(lst_ctx *ctx, Slot &s, const std::vector<std::unique_ptr
     lst_status st = ensure_inputs(ctx, s, n, hits, pls);
     if (st == LST_OK) st = ensure_work(ctx, s);
     if (st != LST_OK) return st;
+    // one copy per chunk the batch touches: the span from its first to the
+    // end of its last block there (blocks of other batches in between are
+    // copied along and not used)
+    struct Span { InChunk *c; size_t lo, hi, at; };
+    std::vector<Span> spans;
+    for (const auto &e : evs) {
+        if (!e->blk_bytes) continue;
+        Span *sp = nullptr;
+        for (Span &x : spans)
+            if (x.c == e->chunk) sp = &x;
+        if (!sp) {
+            spans.push_back(Span{e->chunk, e->blk_off, e->blk_off + e->blk_bytes, 0});
+        } else {
+            sp->lo = std::min(sp->lo, e->blk_off);
+            sp->hi = std::max(sp->hi, e->blk_off + e->blk_bytes);
+        }
+    }
+    raw = 0;
+    for (Span &x : spans) {
+        x.at = raw;
+        raw += (x.hi - x.lo + 255) / 256 * 256;
+    }
     if (raw > s.raw_cap) {
         if (s.raw) (void)hipFree(s.raw);
         s.raw = nullptr;
@@ -928,16 +1052,17 @@ lst_status stage_served(lst_ctx *ctx, Slot &s, const std::vector<std::unique_ptr
     s.n_ev = n;
     s.hit_off.assign(n + 1, 0);
     s.pls_off.assign(n + 1, 0);
-    uint64_t at = 0;
+    for (const Span &x : spans)
+        HIP_TRY(hipMemcpyAsync(s.raw + x.at, x.c->base + x.lo, x.hi - x.lo, hipMemcpyHostToDevice, s.stream));
     for (uint32_t i = 0; i < n; i++) {
         s.hit_off[i + 1] = s.hit_off[i] + evs[i]->n_hits;
         s.pls_off[i + 1] = s.pls_off[i] + evs[i]->n_pls;
-        s.h_rawoff[i] = at;
+        s.h_rawoff[i] = 0;
         if (evs[i]->blk_bytes)
-            HIP_TRY(hipMemcpyAsync(s.raw + at, evs[i]->blk, evs[i]->blk_bytes, hipMemcpyHostToDevice, s.stream));
-        at += evs[i]->blk_bytes;
+            for (const Span &x : spans)
+                if (x.c == evs[i]->chunk) s.h_rawoff[i] = x.at + (evs[i]->blk_off - x.lo);
     }
-    s.h_rawoff[n] = at;
+    s.h_rawoff[n] = raw;
     HIP_TRY(hipMemcpyAsync(s.d_rawoff, s.h_rawoff, 8ull * (n + 1), hipMemcpyHostToDevice, s.stream));
     char *hs = s.h_stage;
     const size_t hoff_at = (char *)b.ev_hit_off - (char *)s.in_arena;
@@ -1012,7 +1137,7 @@ void admit_main(lst_ctx *ctx)
         lk.lock();
         if (st != LST_OK) {
             for (auto &se : take) {
-                ctx->pinned.put(se->blk, se->blk_cls);
+                ctx->in_chunks.put(se->chunk);
                 lst_event_out *o = new_out();
                 if (o) { o->status = (uint32_t)st; o->ticket = se->ticket; }
                 ctx->finished[se->ticket] = o;
@@ -1054,7 +1179,6 @@ void complete_main(lst_ctx *ctx, uint32_t i)
         std::vector<lst_event_out *> outs(s.n_ev, nullptr);
         if (st == LST_OK && overflowed(s)) {
             if (s.work_arena) { (void)hipFree(s.work_arena); s.work_arena = nullptr; }
-            s.img = nullptr;
             if (s.gexec) { (void)hipGraphExecDestroy(s.gexec); s.gexec = nullptr; }
             if (s.graph) { (void)hipGraphDestroy(s.graph); s.graph = nullptr; }
             s.graph_valid = false;
@@ -1068,8 +1192,8 @@ void complete_main(lst_ctx *ctx, uint32_t i)
         const auto now = std::chrono::steady_clock::now();
         auto &held = ctx->held[i];
         for (auto &se : held) {
-            ctx->pinned.put(se->blk, se->blk_cls);
-            se->blk = nullptr;
+            ctx->in_chunks.put(se->chunk);
+            se->chunk = nullptr;
         }
         lk.lock();
         for (uint32_t e = 0; e < s.n_ev; e++) {
@@ -1491,17 +1615,18 @@ lst_status lst_submit(lst_ctx *ctx, const lst_event_in *ev, uint64_t *ticket)
     const lst::BlockLayout lay = lst::served_block_layout(ev->n_hits, ev->n_pls);
     se->blk_bytes = lay.bytes;
     if (lay.bytes) {
-        se->blk = ctx->pinned.get(lay.bytes, se->blk_cls);
-        if (!se->blk) return set_err(ctx, LST_ERR_OOM, "pinned host allocation failed");
+        if (!ctx->in_chunks.get(lay.bytes, se->chunk, se->blk_off))
+            return set_err(ctx, LST_ERR_OOM, "pinned host allocation failed");
+        char *blk = se->chunk->base + se->blk_off;
         const void *src[7] = {ev->x, ev->y, ev->z, ev->module, ev->sensor, ev->pls_par, ev->pls_cov};
         const size_t sz[7] = {4ull * ev->n_hits, 4ull * ev->n_hits, 4ull * ev->n_hits, 4ull * ev->n_hits,
                               ev->n_hits, 20ull * ev->n_pls, 60ull * ev->n_pls};
         for (int i = 0; i < 7; i++)
-            if (sz[i]) std::memcpy(se->blk + lay.off[i], src[i], sz[i]);
+            if (sz[i]) std::memcpy(blk + lay.off[i], src[i], sz[i]);
     }
     se->t_submit = std::chrono::steady_clock::now();
     std::lock_guard<std::mutex> g(ctx->q_mu);
-    auto give_back = [&] { ctx->pinned.put(se->blk, se->blk_cls); se->blk = nullptr; };
+    auto give_back = [&] { ctx->in_chunks.put(se->chunk); se->chunk = nullptr; };
     const uint64_t budget = ctx->p.mem_budget ? ctx->p.mem_budget : (32ull << 30);
     const uint64_t f = predict_footprint(ev->n_hits, ev->n_pls, ctx->geom.c);
     if (f > budget) { give_back(); return set_err(ctx, LST_ERR_TOO_LARGE, "event above the device memory budget"); }
@@ -1591,6 +1716,7 @@ lst_status lst_run_event_noalloc(lst_ctx *ctx, const lst_event_in *ev, lst_event
     lst::Caps c = lst::plan_caps(1, ev->n_hits, ev->n_pls);
     b.cap_md = c.md; b.cap_ls = c.ls; b.cap_t3 = c.t3; b.cap_t5 = c.t5;
     b.cap_pt3 = c.pt3; b.cap_pt5 = c.pt5; b.cap_ptc3 = c.ptc3; b.cap_ptc5 = c.ptc5;
+    lst::plan_sublists(b);
     lst::Launcher L;
     L.stream = sm;
     L.side = nullptr;
@@ -1618,21 +1744,7 @@ lst_status lst_run_event_noalloc(lst_ctx *ctx, const lst_event_in *ev, lst_event
         st = input_error(ctx, tot.err);
         if (st != LST_OK) return st;
         // a list that overflowed: larger capacities inside the same workspace
-        auto grow = [](uint32_t need, uint32_t &cap) {
-            if (need <= cap) return false;
-            cap = lst::clamp32((uint64_t)need + need / 4 + 1024);
-            return true;
-        };
-        bool g = false;
-        g |= grow(std::max(tot.n_md, tot.n_mds), b.cap_md);
-        g |= grow(std::max(tot.n_ls, tot.n_lss), b.cap_ls);
-        g |= grow(std::max(tot.n_t3, tot.n_t3s), b.cap_t3);
-        g |= grow(std::max(tot.n_t5, tot.n_t5s), b.cap_t5);
-        g |= grow(tot.n_pt3, b.cap_pt3);
-        g |= grow(tot.n_pt5, b.cap_pt5);
-        g |= grow(tot.n_ptc3, b.cap_ptc3);
-        g |= grow(tot.n_ptc5, b.cap_ptc5);
-        if (!g) break;
+        if (!lst::grow_caps(b, tot)) break;
     }
     out->n_md = tot.n_md; out->n_ls = tot.n_ls; out->n_t3 = tot.n_t3; out->n_t5 = tot.n_t5;
     out->n_pt3 = tot.n_pt3; out->n_pt5 = tot.n_pt5; out->n_tc = tot.n_pt5 + tot.n_tc;
@@ -1686,13 +1798,13 @@ void lst_destroy(lst_ctx *ctx)
     }
     for (auto &th : ctx->completers)
         if (th.joinable()) th.join();
-    for (auto &kv : ctx->waiting) ctx->pinned.put(kv->blk, kv->blk_cls);
+    for (auto &kv : ctx->waiting) ctx->in_chunks.put(kv->chunk);
     for (auto &kv : ctx->finished) lst_free_output(kv.second);
     (void)hipSetDevice(ctx->device);
     for (auto &s : ctx->slots) destroy_slot(*s);
     if (ctx->plain) destroy_slot(*ctx->plain);
     if (ctx->geom_mem) (void)hipFree(ctx->geom_mem);
-    ctx->pinned.release();
+    ctx->in_chunks.release();
     delete ctx;
 }
 

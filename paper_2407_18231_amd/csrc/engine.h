@@ -30,6 +30,20 @@ constexpr uint32_t kKeepLs = 8;
 // (at most kSubLists): a block counts its appends in LDS and publishes the
 // count when it ends, so appends never wait on a global atomic.
 constexpr uint32_t kSubLists = kMaxGrid;
+// Entries per walk block in those regions beyond an even share of the
+// list's capacity: the blocks of a small batch take one tile of 256 owners
+// each, and a dense tile holds a few times the average (a PU200 event's
+// densest tile of 256 T3s has up to ≈ 530 T5s against an average of 20).
+constexpr uint32_t kRegionSlack = 256;       // MD and LS regions
+constexpr uint32_t kRegionSlackT3 = 512;
+constexpr uint32_t kRegionSlackT5 = 1024;
+
+// blocks of a walk over `units` owners (256 per block, at most kMaxGrid)
+inline uint32_t walk_blocks(uint64_t units)
+{
+    const uint64_t g = (units + 255) / 256;
+    return (uint32_t)(g < 1 ? 1 : (g > kMaxGrid ? kMaxGrid : g));
+}
 
 // Device copy of the geometry (read-only).
 // Device copy of a line-segment class (LsClass), 32 bytes:
@@ -53,8 +67,8 @@ struct DevGeom {
     const float2 *mod_phi;      // n_mod: azimuth centre and half-width (with margin)
     const float4 *mod_ext;      // 2 per module: accepted extent of a hit, sensor positions
     const uint32_t *run_begin;  // n_mod + 1: segment-walk runs of each module's edges
-    const uint4 *run;           // (first destination, class | length << 24, azimuth centre, pitch)
-    const float *run_win;       // window of each run (radians)
+    const uint4 *run;           // (first destination, class | length << 24, azimuth centre, 1 / pitch)
+    const float *run_win;       // window of each run (radians; module indices for runs of several modules)
     uint32_t hist_slice;        // hit histogram in LDS: (module, sensor) bins per slice
 };
 
@@ -80,6 +94,8 @@ struct Totals {
 // nothing past it and the host re-runs the batch with larger arrays.
 struct Batch {
     uint32_t cap_ev, cap_hits, cap_pls, cap_md, cap_ls, cap_t3, cap_t5, cap_pt3, cap_pt5, cap_tc;
+    // the walks' unordered sub-lists (one region of cap / blocks per walk block)
+    uint32_t cap_mds, cap_lss, cap_t3s, cap_t5s;
     uint32_t cap_ptc3, cap_ptc5;
     // inputs (event-major concatenation)
     float *in_x, *in_y, *in_z;

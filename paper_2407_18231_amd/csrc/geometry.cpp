@@ -389,8 +389,9 @@ lst_status build_geometry(const lst_params &p, const lst_module_desc *m, uint32_
     // azimuth centre within dev of phi0 + k * pitch (binary32 values as
     // stored, the difference taken in binary64); the window is the largest
     // half-width plus the class's reach plus dev plus 1e-4 for the binary32
-    // arithmetic of the run test, so every module the per-module reach test
-    // accepts lies in the run's accepted index range.  Runs end where the
+    // arithmetic of the run test (stored in module indices, i.e. divided by
+    // the pitch, for runs of more than one module), so every module the
+    // per-module reach test accepts lies in the run's accepted index range.  Runs end where the
     // destinations stop being consecutive, the class changes, a centre
     // strays by more than 1e-3 from the pitch, or the span plus the window
     // nears half a turn (the run test takes no wrap-around past the span).
@@ -422,16 +423,21 @@ lst_status build_geometry(const lst_params &p, const lst_module_desc *m, uint32_
                 len++;
             }
             if (len > 1) pitch = u / (len - 1);
-            const float phi0f = (float)c0, pitchf = (float)pitch;
+            // the run test uses the inverse pitch as stored: the pitch it
+            // implies is 1 / invf, and the deviations are taken from it
+            const float phi0f = (float)c0, invf = len > 1 ? (float)(1.0 / pitch) : 0.0f;
+            const double pitch_used = len > 1 ? 1.0 / (double)invf : 0.0;
             double dev = 0.0;
             for (uint32_t k = 1; k < len; k++)
                 dev = std::max(dev, std::fabs(wrap_pi(g.mod_phi[2 * (size_t)(first + k)] -
-                                                      ((double)phi0f + k * (double)pitchf))));
+                                                      ((double)phi0f + k * pitch_used))));
             uint32_t rec[4] = {first, cid | (len << 24), 0u, 0u};
             std::memcpy(&rec[2], &phi0f, 4);
-            std::memcpy(&rec[3], &pitchf, 4);
+            std::memcpy(&rec[3], &invf, 4);
             g.run_rec.insert(g.run_rec.end(), rec, rec + 4);
-            g.run_win.push_back((float)(hw + reach + dev + 1e-4));
+            // window in radians for a single module, else in module indices
+            const double win = hw + reach + dev + 1e-4;
+            g.run_win.push_back((float)(len > 1 ? win * std::fabs((double)invf) : win));
             i += len;
         }
         g.run_begin[A + 1] = (uint32_t)g.run_win.size();

@@ -460,7 +460,7 @@ __global__ __launch_bounds__(256) void k_md(const Batch b, Totals *t, const DevG
     const uint32_t n_mod = c.n_mod;
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     const unsigned long long below = (1ull << lane) - 1ull;
-    const uint32_t cap = b.cap_md / nsub;
+    const uint32_t cap = b.cap_mds / nsub;
     uint4 *out = b.mds + (size_t)blockIdx.x * cap;
     if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
@@ -580,7 +580,7 @@ __global__ __launch_bounds__(256) void k_md_place(const Batch b, const Totals *t
     for (uint32_t i = threadIdx.x; i <= nsub; i += blockDim.x) s_off[i] = b.mds_soff[i];
     __syncthreads();
     const uint32_t n = s_off[nsub];
-    const uint32_t subcap = b.cap_md / nsub;
+    const uint32_t subcap = b.cap_mds / nsub;
     GRID_STRIDE(jj, n) {
         const uint4 r = b.mds[pair_slot(s_off, jj, subcap, nsub)];
         const uint32_t k = b.md_hoff[r.x] + r.y;
@@ -625,12 +625,13 @@ __device__ inline bool in_reach(float pha, const float2 mp, float reach)
 
 // Modules [k0, k1) of a segment-walk run (destinations first + k, k below
 // its length) that can hold a partner of an inner anchor at azimuth pha: the
-// indices k with |delta - k * pitch| <= window, delta the anchor's azimuth
-// relative to the run's first module.  The window covers every module the
-// per-module reach test accepts (it holds the largest half-width, the reach,
-// the centres' deviation from the pitch and room for this arithmetic), and
-// a run spans less than half a turn with its window, so no wrap-around
-// beyond delta's is needed.  k1 == k0: none.
+// indices k with |delta * inv_pitch - k| <= window (in module indices),
+// delta the anchor's azimuth relative to the run's first module; a run of
+// one module takes |delta| <= window (radians).  The window covers every
+// module the per-module reach test accepts (it holds the largest
+// half-width, the reach, the centres' deviation from the pitch and room for
+// this arithmetic), and a run spans less than half a turn with its window,
+// so no wrap-around beyond delta's is needed.  k1 == k0: none.
 __device__ inline uint2 run_range(const uint4 r, float win, float pha)
 {
     const float len = (float)(r.y >> 24);
@@ -642,15 +643,9 @@ __device__ inline uint2 run_range(const uint4 r, float win, float pha)
         k0 = 0.0f;
         k1 = fabsf(d) <= win ? 1.0f : 0.0f;
     } else {
-        const float p = __uint_as_float(r.w);
-        float t0 = (d - win) / p, t1 = (d + win) / p;
-        if (p < 0.0f) {
-            const float x = t0;
-            t0 = t1;
-            t1 = x;
-        }
-        k0 = fminf(fmaxf(ceilf(t0), 0.0f), len);
-        k1 = fmaxf(fminf(floorf(t1) + 1.0f, len), k0);
+        const float tc = d * __uint_as_float(r.w);
+        k0 = fminf(fmaxf(ceilf(tc - win), 0.0f), len);
+        k1 = fmaxf(fminf(floorf(tc + win) + 1.0f, len), k0);
     }
     return make_uint2((uint32_t)k0, (uint32_t)k1);
 }
@@ -749,7 +744,7 @@ __global__ __launch_bounds__(256, kMinWaves) void k_ls(const Batch b, Totals *t,
     const bool bend = (c.flags & LST_FLAG_BEND) != 0u;
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     const unsigned long long below = (1ull << lane) - 1ull;
-    const uint32_t cap = b.cap_ls / nsub;
+    const uint32_t cap = b.cap_lss / nsub;
     uint32_t *sa = b.lss_a + (size_t)blockIdx.x * cap;
     uint32_t *sb = b.lss_b + (size_t)blockIdx.x * cap;
     uint32_t *sj = b.lss_j + (size_t)blockIdx.x * cap;
@@ -907,7 +902,7 @@ __global__ __launch_bounds__(256) void k_ls_place(const Batch b, uint32_t nsub)
     for (uint32_t i = threadIdx.x; i <= nsub; i += blockDim.x) s_off[i] = b.lss_soff[i];
     __syncthreads();
     const uint32_t n = s_off[nsub];
-    const uint32_t subcap = b.cap_ls / nsub;
+    const uint32_t subcap = b.cap_lss / nsub;
     GRID_STRIDE(j, n) {
         const uint32_t i = pair_slot(s_off, j, subcap, nsub);
         const uint32_t a = b.lss_a[i];
@@ -1169,7 +1164,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     const uint32_t n = min(t->n_ls, b.cap_ls);
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     const unsigned long long below = (1ull << lane) - 1ull;
-    const uint32_t cap = b.cap_t3 / nsub;
+    const uint32_t cap = b.cap_t3s / nsub;
     const size_t sb0 = (size_t)blockIdx.x * cap;
     if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
@@ -1260,7 +1255,7 @@ __global__ __launch_bounds__(256) void k_t3_place(const Batch b, const DevGeom g
     for (uint32_t i = threadIdx.x; i <= nsub; i += blockDim.x) s_off[i] = b.t3s_soff[i];
     __syncthreads();
     const uint32_t n = s_off[nsub];
-    const uint32_t subcap = b.cap_t3 / nsub;
+    const uint32_t subcap = b.cap_t3s / nsub;
     // whole waves per step (the bucket slots are drawn per wave)
     for (uint32_t jb = blockIdx.x * blockDim.x; jb < n; jb += gridDim.x * blockDim.x) {
         const uint32_t j = jb + threadIdx.x;
@@ -1306,7 +1301,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     const uint32_t n = min(t->n_t3, b.cap_t3);
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     const unsigned long long below = (1ull << lane) - 1ull;
-    const uint32_t cap = b.cap_t5 / nsub;
+    const uint32_t cap = b.cap_t5s / nsub;
     const size_t sb0 = (size_t)blockIdx.x * cap;
     if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
@@ -1393,7 +1388,7 @@ __global__ __launch_bounds__(256) void k_t5_place(const Batch b, const DevGeom g
     for (uint32_t i = threadIdx.x; i <= nsub; i += blockDim.x) s_off[i] = b.t5s_soff[i];
     __syncthreads();
     const uint32_t n = s_off[nsub];
-    const uint32_t subcap = b.cap_t5 / nsub;
+    const uint32_t subcap = b.cap_t5s / nsub;
     // whole waves per step (the bucket slots are drawn per wave)
     for (uint32_t jb = blockIdx.x * blockDim.x; jb < n; jb += gridDim.x * blockDim.x) {
         const uint32_t j = jb + threadIdx.x;
@@ -2142,13 +2137,7 @@ void Launcher::scan(const uint32_t *in, uint32_t *out, const uint32_t *n_ptr, ui
     launch(name, k_scan_down, dim3(nb), dim3(kScanBlock), in, n_ptr, cap, (const uint32_t *)pt, out, total);
 }
 
-static inline dim3 grid_for(uint64_t units)
-{
-    uint64_t g = (units + 255) / 256;
-    if (g < 1) g = 1;
-    if (g > kMaxGrid) g = kMaxGrid;
-    return dim3((unsigned)g);
-}
+static inline dim3 grid_for(uint64_t units) { return dim3(walk_blocks(units)); }
 
 using LsWalk = void (*)(const Batch, Totals *, const DevGeom, const Consts, uint32_t, int);
 
@@ -2218,7 +2207,7 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     } else {
         const uint32_t nsub_md = gmd.x;
         L.launch("md_walk", k_md, gmd, blk, b, t, g, c, nsub_md, stats);
-        L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.mds_sub, b.mds_soff, b.cap_md, nsub_md, &t->n_mds);
+        L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.mds_sub, b.mds_soff, b.cap_mds, nsub_md, &t->n_mds);
         L.scan(b.md_cnt, b.md_hoff, &t->n_sorted, b.cap_hits, &t->n_md, "scan_md");
         L.launch("md_place", k_md_place, grid_for(std::max<uint64_t>(b.cap_md, (uint64_t)b.cap_ev * n_mod + 1)), blk,
                  b, (const Totals *)t, g, c, nsub_md);
@@ -2234,7 +2223,7 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
         const dim3 gls = grid_for(b.cap_md);
         const uint32_t nsub_ls = gls.x;
         L.launch("ls_walk", ls_walk_kernel(c.ls_group, c.ls_waves), gls, blk, b, t, g, c, nsub_ls, stats);
-        L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.lss_sub, b.lss_soff, b.cap_ls, nsub_ls,
+        L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.lss_sub, b.lss_soff, b.cap_lss, nsub_ls,
                  &t->n_lss);
         L.scan(b.ls_cnt, b.ls_off, &t->n_md, b.cap_md, &t->n_ls, "scan_ls");
         L.launch("ls_place", k_ls_place, grid_for(b.cap_ls), blk, b, nsub_ls);
@@ -2244,7 +2233,7 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     const dim3 gt3 = grid_for(b.cap_ls);
     const uint32_t nsub_t3 = gt3.x;
     L.launch("t3_walk", k_t3, gt3, blk, b, t, c, nsub_t3, stats);
-    L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.t3s_sub, b.t3s_soff, b.cap_t3, nsub_t3,
+    L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.t3s_sub, b.t3s_soff, b.cap_t3s, nsub_t3,
              &t->n_t3s);
     L.scan(b.t3_cnt, b.t3_off, &t->n_ls, b.cap_ls, &t->n_t3, "scan_t3");
     L.wait(0);                           // the placement counts into the cleared T3 buckets
@@ -2257,7 +2246,7 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     const dim3 gt5 = grid_for(b.cap_t3);
     const uint32_t nsub_t5 = gt5.x;
     L.launch("t5_walk", k_t5, gt5, blk, b, t, c, nsub_t5, stats);
-    L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.t5s_sub, b.t5s_soff, b.cap_t5, nsub_t5,
+    L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.t5s_sub, b.t5s_soff, b.cap_t5s, nsub_t5,
              &t->n_t5s);
     L.scan(b.t5_cnt, b.t5_off, &t->n_t3, b.cap_t3, &t->n_t5, "scan_t5");
     L.launch("t5_place", k_t5_place, grid_for(b.cap_t5), blk, b, g, c, nsub_t5);

@@ -73,7 +73,8 @@ struct Geometry {
     // segment-walk runs: edges of a module to consecutive destinations of
     // one class with evenly spaced azimuth centres, one record per run
     // (first destination, class | length << 24, azimuth centre of the first
-    // module, pitch) and its window (radians)
+    // module, 1 / pitch) and its window (radians for a run of one module,
+    // module indices otherwise)
     std::vector<uint32_t> run_begin;  // n_mod + 1
     std::vector<uint32_t> run_rec;    // 4 per run
     std::vector<float> run_win;       // per run

@@ -122,15 +122,44 @@ def test_stage_times(g, ctx):
     assert res["n_flag_regrow"] == 0 and res["batch_events"] == 1
 
 
+def dense_cluster(g, ev, module=0, n=150, seed=5):
+    """ev plus n hits on each sensor of one barrel module, all at nearly the
+    same place: every lower hit pairs with every upper one (n * n MDs, far
+    more than the capacities planned from the event's size)."""
+    rng = np.random.default_rng(seed)
+    assert g.kind[module] == s.BARREL
+    phi = 0.5 * (g.phi_min[module] + g.phi_max[module]) + rng.uniform(-5e-4, 5e-4, 2 * n)
+    z = 0.5 * (g.c_min[module] + g.c_max[module]) + rng.uniform(-0.3, 0.3, 2 * n)
+    sen = np.repeat(np.array([0, 1], np.uint8), n)
+    r = np.where(sen == 0, g.s_lo[module], g.s_hi[module])
+    out = dict(ev)
+    out["x"] = np.concatenate([ev["x"], (r * np.cos(phi)).astype(np.float32)])
+    out["y"] = np.concatenate([ev["y"], (r * np.sin(phi)).astype(np.float32)])
+    out["z"] = np.concatenate([ev["z"], z.astype(np.float32)])
+    out["module"] = np.concatenate([ev["module"], np.full(2 * n, module, np.uint32)])
+    out["sensor"] = np.concatenate([ev["sensor"], sen])
+    out["hit_track"] = np.concatenate([ev["hit_track"], np.full(2 * n, -1, np.int32)])
+    return out
+
+
 def test_regrow_count_reported(g):
+    """An event whose lists outgrow the capacities planned from its size (a
+    dense cluster: 150 hits on each sensor of one module, 22.5k MD
+    candidates) runs again with larger lists: n_flag_regrow counts the
+    re-runs, the lists match the oracle and equal those of a second run,
+    which needs none."""
     small = s.gen_event(g, s.config_pu(20), 1)
-    big = s.gen_event(g, s.config_pu(300, noise_frac=0.4), 2)
+    ev = dense_cluster(g, small)
     with lst.Context() as c:
         c.load_geometry(g)
         assert c.run_event(small)["n_flag_regrow"] == 0
-        r = c.run_event(big)
+        r = c.run_event(ev)
         assert r["n_flag_regrow"] >= 1
-        assert c.run_event(big)["n_flag_regrow"] == 0
+        assert len(r["md"]) > 20_000
+        r2 = c.run_event(ev)
+        assert r2["n_flag_regrow"] == 0
+        same(r, r2)
+    check_parity(g, ev, r)
 
 
 def test_caller_stream(g, ctx):
@@ -249,10 +278,13 @@ def test_served_pu300_stress_batches_of_32(g):
     event's run alone and sampled ones match the oracle."""
     evs = [s.gen_event(g, s.config_pu(300, noise_frac=0.4, fake_frac=0.05), s.event_seed(5, 10 + i))
            for i in range(32)]
-    with lst.Context(max_batch=32, n_slots=2) as c:
+    with lst.Context(max_batch=32, n_slots=1) as c:
         c.load_geometry(g)
         alone = [c.run_event(ev) for ev in evs]
-        tickets = [c.submit(ev) for ev in evs]
+        # marshalled first, so that the submissions follow each other closely
+        # and queue up behind the first micro-batch (one device slot)
+        ins = [lst.EventIn(ev) for ev in evs]
+        tickets = [c.submit_in(e) for e in ins]
         outs = [c.poll(t, -1) for t in tickets]
     assert max(o["batch_events"] for o in outs) > 1
     for a, o in zip(alone, outs):
