@@ -17,7 +17,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lst_oracle.c")
-_LIB = os.path.join(_HERE, "liblst_oracle.so")
+# LST_ORACLE_LIB: a build of the same source to load instead (the sanitizer
+# tests load one built with the address and undefined-behaviour sanitizers)
+_LIB = os.environ.get("LST_ORACLE_LIB") or os.path.join(_HERE, "liblst_oracle.so")
 
 ST_ACC = 1
 ST_FLAG = 2
