@@ -62,9 +62,11 @@ def build(verbose: bool = False) -> str:
     tdir = _torch_hip_dir()
     if tdir:
         link = ["g++", "-shared", "-o", tmp, *objs, "-L" + tdir, "-l:libamdhip64.so",
+                "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx",
                 "-Wl,-rpath," + tdir + ":/opt/rocm/lib", "-lpthread"]
     else:
-        link = [hipcc, "--offload-arch=gfx950", "-shared", "-o", tmp, *objs, "-lpthread"]
+        link = [hipcc, "--offload-arch=gfx950", "-shared", "-o", tmp, *objs, "-L/opt/rocm/lib",
+                "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib", "-lpthread"]
     if verbose:
         print(" ".join(link), flush=True)
     subprocess.check_call(link)

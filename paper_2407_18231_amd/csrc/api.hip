@@ -17,6 +17,8 @@
 #include <thread>
 #include <unordered_map>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "engine.h"
 #include "lst.h"
 
@@ -359,6 +361,15 @@ struct OutBatch {
 struct OutBox {
     lst_event_out pub;       // first member: the caller's pointer is its address
     OutBatch *batch;         // buffer the lists point into (null: no lists)
+};
+
+// A host-side range for tracing tools (rocprofv3 --marker-trace) around a
+// call that enqueues or collects device work; nearly free without a tool.
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
 };
 
 lst_event_out *new_out()
@@ -849,6 +860,7 @@ lst_status run_staged(lst_ctx *ctx, Slot &s, bool use_graph, bool stage_times, b
 // into a pinned buffer, and each event's output points into that buffer.
 lst_status download(lst_ctx *ctx, Slot &s, lst_event_out **outs)
 {
+    TraceRange trace_("lst: outputs to host");
     const uint32_t n = s.n_ev;
     for (uint32_t e = 0; e < n; e++) outs[e] = nullptr;
     const lst::Totals &t = *s.h_tot;
@@ -997,6 +1009,7 @@ namespace {
 // kernel, then the captured chain.
 lst_status stage_served(lst_ctx *ctx, Slot &s, const std::vector<std::unique_ptr<ServedEvent>> &evs)
 {
+    TraceRange trace_("lst: stage served micro-batch");
     const uint32_t n = (uint32_t)evs.size();
     uint64_t hits = 0, pls = 0, raw = 0;
     for (const auto &e : evs) {
@@ -1287,6 +1300,7 @@ lst_status lst_create(const lst_params *p, lst_ctx **out)
 
 lst_status lst_load_geometry(lst_ctx *ctx, const lst_module_desc *m, uint32_t n)
 {
+    TraceRange trace_("lst_load_geometry");
     lst_status st = check_ctx(ctx, false);
     if (st != LST_OK) return st;
     std::lock_guard<std::mutex> g(ctx->run_mu);
@@ -1452,6 +1466,7 @@ void lst_free_map(uint32_t *begin, uint32_t *dst)
 
 lst_status lst_run_batch(lst_ctx *ctx, const lst_event_in *evs, uint32_t n, lst_event_out **outs)
 {
+    TraceRange trace_("lst_run_batch");
     lst_status st = check_ctx(ctx, true);
     if (st != LST_OK) return st;
     if (!evs || !outs || n == 0) return set_err(ctx, LST_ERR_INVALID_ARG, "no events");
@@ -1499,6 +1514,7 @@ lst_status lst_batch_upload(lst_ctx *ctx, const lst_event_in *evs, uint32_t n)
 
 lst_status lst_batch_execute(lst_ctx *ctx, uint32_t repeats, int32_t use_graph, int32_t timing, double *ms)
 {
+    TraceRange trace_("lst_batch_execute");
     lst_status st = check_ctx(ctx, true);
     if (st != LST_OK) return st;
     if (!ctx->plain || !ctx->plain->n_ev) return set_err(ctx, LST_ERR_INVALID_ARG, "no staged batch");
@@ -1600,6 +1616,7 @@ lst_status lst_batch_counts(lst_ctx *ctx, uint64_t counts[15])
 
 lst_status lst_submit(lst_ctx *ctx, const lst_event_in *ev, uint64_t *ticket)
 {
+    TraceRange trace_("lst_submit");
     lst_status st = check_ctx(ctx, true);
     if (st != LST_OK) return st;
     if (!ev || !ticket) return LST_ERR_INVALID_ARG;
@@ -1681,6 +1698,7 @@ lst_status lst_poll(lst_ctx *ctx, uint64_t ticket, int64_t timeout_us, lst_event
 
 lst_status lst_run_event_noalloc(lst_ctx *ctx, const lst_event_in *ev, lst_event_dev_out *out, void *stream)
 {
+    TraceRange trace_("lst_run_event_noalloc");
     lst_status st = check_ctx(ctx, true);
     if (st != LST_OK) return st;
     if (!ev || !out) return set_err(ctx, LST_ERR_INVALID_ARG, "null event or output");

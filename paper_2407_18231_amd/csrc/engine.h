@@ -197,6 +197,7 @@ struct Launcher {
     std::vector<hipEvent_t> pool;
     size_t used = 0;
     int stage = 0;                      // stage of the chain the next launches belong to (LST_STAGE_*)
+    bool range_open = false;            // a tracing range for the stage being enqueued is open
     struct Rec {
         const char *name;
         int stage;
@@ -238,6 +239,10 @@ struct Launcher {
         if (e != hipSuccess && err == hipSuccess) err = e;
     }
     void on_side(bool s) { cur = (s && side) ? side : stream; }
+    // the stage the next launches belong to; a host-side tracing range
+    // (rocprofv3 --marker-trace) brackets the enqueueing of each stage
+    void set_stage(int st);
+    void end_stages();
 
     template <typename... KArgs, typename... Args>
     void launch(const char *name, void (*kernel)(KArgs...), dim3 grid, dim3 block, Args... args)

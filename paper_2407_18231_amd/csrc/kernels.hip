@@ -18,6 +18,8 @@
 // (no contraction: built with -ffp-contract=off), pixel-seed cuts in binary64.
 #include <hip/hip_runtime.h>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "engine.h"
 
 namespace lst {
@@ -2158,6 +2160,25 @@ static LsWalk ls_walk_kernel(uint32_t group, uint32_t waves)
     }
 }
 
+static const char *const kStageRange[LST_N_STAGES] = {"lst stage: ingest",     "lst stage: mini-doublets",
+                                                      "lst stage: line segments", "lst stage: T3",
+                                                      "lst stage: T5",          "lst stage: seed lookup",
+                                                      "lst stage: pT3/pT5",     "lst stage: track candidates"};
+
+void Launcher::set_stage(int st)
+{
+    stage = st;
+    if (range_open) roctxRangePop();
+    range_open = st >= 0 && st < LST_N_STAGES;
+    if (range_open) roctxRangePushA(kStageRange[st]);
+}
+
+void Launcher::end_stages()
+{
+    if (range_open) roctxRangePop();
+    range_open = false;
+}
+
 void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, const Consts &c, int stats)
 {
     const dim3 blk(256);
@@ -2171,11 +2192,11 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     // buckets and pT5, run on the side stream alongside the main chain; the
     // track-candidate selection waits for both.
     L.on_side(false);
-    L.stage = LST_STAGE_INGEST;
+    L.set_stage(LST_STAGE_INGEST);
     launch_setup(L, b, t, c);
     L.fork(0);
     L.on_side(true);
-    L.stage = LST_STAGE_SEED_LOOKUP;
+    L.set_stage(LST_STAGE_SEED_LOOKUP);
     L.launch("pls_prep", k_pls_prep, grid_for(b.cap_pls), blk, b, t, c);
     L.launch("road", k_road, grid_for(cap_pu), blk, b, (const Totals *)t, g, c);
     // counters of later stages that need clearing
@@ -2188,7 +2209,7 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     L.mark(0);                           // the main stream waits for this only before its seed-lookup stage
     L.on_side(false);
     // a1: hit ingest & sort by (event, module, sensor)
-    L.stage = LST_STAGE_INGEST;
+    L.set_stage(LST_STAGE_INGEST);
     const uint32_t n_sl = (2u * n_mod + g.hist_slice - 1u) / g.hist_slice;
     const dim3 gh((unsigned)std::min<uint64_t>((uint64_t)b.cap_ev * n_sl, kMaxGrid));
     L.launch_lds("hit_hist", k_hit_hist, gh, dim3(kHistBlock), g.hist_slice * 4u, b, t, n_mod, g.hist_slice);
@@ -2196,7 +2217,7 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     L.launch("hit_scatter", k_hit_scatter, grid_for(b.cap_hits), blk, b, (const Totals *)t);
     L.launch("hit_gather", k_hit_gather, grid_for(b.cap_hits), blk, b, t, g.mod_ext, n_mod);
     // a2: mini-doublets
-    L.stage = LST_STAGE_MD;
+    L.set_stage(LST_STAGE_MD);
     // small batches: count and fill in place for latency; large ones: pooled walk
     const dim3 gmd = grid_for(b.cap_hits);
     if (b.cap_md <= kLsWaveMaxMd) {
@@ -2213,7 +2234,7 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
                  b, (const Totals *)t, g, c, nsub_md);
     }
     // a3: line segments over the connection map
-    L.stage = LST_STAGE_LS;
+    L.set_stage(LST_STAGE_LS);
     // small batches: 32 lanes per MD for latency; large ones: pooled walk
     if (b.cap_md <= kLsWaveMaxMd) {
         L.launch("ls_count", k_ls_wave<false>, grid_for(32ull * b.cap_md), blk, b, t, g, c, stats);
@@ -2229,7 +2250,7 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
         L.launch("ls_place", k_ls_place, grid_for(b.cap_ls), blk, b, nsub_ls);
     }
     // a4: T3
-    L.stage = LST_STAGE_T3;
+    L.set_stage(LST_STAGE_T3);
     const dim3 gt3 = grid_for(b.cap_ls);
     const uint32_t nsub_t3 = gt3.x;
     L.launch("t3_walk", k_t3, gt3, blk, b, t, c, nsub_t3, stats);
@@ -2242,7 +2263,7 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     // side: a5 T5, its seed-lookup buckets (a6) and pT5 (a7)
     L.fork(1);
     L.on_side(true);
-    L.stage = LST_STAGE_T5;
+    L.set_stage(LST_STAGE_T5);
     const dim3 gt5 = grid_for(b.cap_t3);
     const uint32_t nsub_t5 = gt5.x;
     L.launch("t5_walk", k_t5, gt5, blk, b, t, c, nsub_t5, stats);
@@ -2250,11 +2271,11 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
              &t->n_t5s);
     L.scan(b.t5_cnt, b.t5_off, &t->n_t3, b.cap_t3, &t->n_t5, "scan_t5");
     L.launch("t5_place", k_t5_place, grid_for(b.cap_t5), blk, b, g, c, nsub_t5);
-    L.stage = LST_STAGE_SEED_LOOKUP;
+    L.set_stage(LST_STAGE_SEED_LOOKUP);
     L.scan(b.bk5_cnt, b.bk5_off, &t->n_bk, cap_bk, &t->n_bk5, "scan_bucket");
     L.launch("bucket_scatter", k_bucket_scatter<1>, grid_for(b.cap_t5), blk, b, (const Totals *)t);
     L.launch("pt5c_walk", k_ptc<1>, gwalk, blk, b, t, c, nsub, stats);
-    L.stage = LST_STAGE_PT;
+    L.set_stage(LST_STAGE_PT);
     L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.ptc5_sub, b.ptc5_soff, b.cap_ptc5, nsub,
              &t->n_ptc5);
     L.launch("pt5_eval", k_pt_eval<1>, dim3(nsub), blk, b, c, nsub);
@@ -2265,11 +2286,11 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
 
     // main: the T3 seed-lookup buckets (a6) and pT3 (a7)
     L.on_side(false);
-    L.stage = LST_STAGE_SEED_LOOKUP;
+    L.set_stage(LST_STAGE_SEED_LOOKUP);
     L.scan(b.bk3_cnt, b.bk3_off, &t->n_bk, cap_bk, &t->n_bk3, "scan_bucket");
     L.launch("bucket_scatter", k_bucket_scatter<0>, grid_for(b.cap_t3), blk, b, (const Totals *)t);
     L.launch("pt3c_walk", k_ptc<0>, gwalk, blk, b, t, c, nsub, stats);
-    L.stage = LST_STAGE_PT;
+    L.set_stage(LST_STAGE_PT);
     L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.ptc3_sub, b.ptc3_soff, b.cap_ptc3, nsub,
              &t->n_ptc3);
     L.launch("pt3_eval", k_pt_eval<0>, dim3(nsub), blk, b, c, nsub);
@@ -2280,7 +2301,7 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     // a8: track candidates, once both branches are done
     L.mark(1);
     L.wait(1);
-    L.stage = LST_STAGE_TC;
+    L.set_stage(LST_STAGE_TC);
     L.launch("tc_keep", k_tc_keep, grid_for((uint64_t)b.cap_pt3 + b.cap_t5 + b.cap_pls), blk, b, t);
     L.scan(b.tc_cnt, b.tc_off, &t->n_tcu, b.cap_pt3 + b.cap_t5 + b.cap_pls, &t->n_tc, "scan_tc");
     L.launch("tc_write", k_tc_write, grid_for((uint64_t)b.cap_pt3 + b.cap_t5 + b.cap_pls), blk, b,
@@ -2294,6 +2315,7 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
         L.launch("tcc_decide", k_tcc_decide, grid_for(cap_tcc), blk, b, (const Totals *)t);
     }
     L.launch("event_table", k_event_table, grid_for(b.cap_ev + 1), blk, b, (const Totals *)t, c);
+    L.end_stages();
 }
 
 __global__ void k_event_init(Totals *t, uint32_t *__restrict__ hit_off, uint32_t *__restrict__ pls_off,
@@ -2544,9 +2566,10 @@ __global__ void __launch_bounds__(256) k_pack_tcc(const Batch b, const Totals *t
 void launch_pack(Launcher &L, const Batch &b, const Totals *t, uint32_t *img, uint32_t n_ev, uint64_t head,
                  uint64_t cap, bool clean, uint64_t n_items)
 {
-    // blocks per event: enough for the average event's entries, at most 64
-    const uint64_t per_ev = n_ev ? n_items / n_ev : 0;
-    const uint32_t bx = (uint32_t)std::min<uint64_t>(64, std::max<uint64_t>(1, per_ev / (256 * 8)));
+    // the image goes over the host link (≈ 55 GB/s), which 256 blocks keep
+    // busy; the rest of the device stays free for the other slot's chain
+    (void)n_items;
+    const uint32_t bx = std::max<uint32_t>(1u, 256u / std::max<uint32_t>(n_ev, 1u));
     if (n_ev) L.launch("pack", k_pack, dim3(bx, n_ev), dim3(256), b, t, img, head, cap, clean ? 1u : 0u);
     if (clean && n_ev) L.launch("pack_tcc", k_pack_tcc, dim3(n_ev), dim3(256), b, t, img, head, cap);
 }
