@@ -219,6 +219,18 @@ lst_status lst_create(const lst_params *p, lst_ctx **out);
  * call.  Errors: INVALID_ARG, BAD_GEOMETRY, OOM, DEVICE. */
 lst_status lst_load_geometry(lst_ctx *ctx, const lst_module_desc *m, uint32_t n);
 
+/* Cache of the host-side tables lst_load_geometry builds (window constants,
+ * connection map, segment-walk runs, seed-lookup surfaces; ≈ 1 s for 12 800
+ * modules): with a directory set, a load reads them from a blob there that
+ * was built from exactly the same module table and parameters, and
+ * otherwise builds them and writes such a blob (named by a hash of the
+ * inputs; the blob holds the inputs and is used only when they match byte
+ * for byte).  dir NULL or "": no cache.  A blob that cannot be read or
+ * written is ignored.  Errors: INVALID_ARG. */
+lst_status lst_set_geometry_cache(lst_ctx *ctx, const char *dir);
+/* 1 when the geometry loaded last came from the cache, else 0. */
+int32_t lst_geometry_from_cache(const lst_ctx *ctx);
+
 /* The connection map in CSR form: module A connects to dst[begin[A] ..
  * begin[A+1]).  Pointers into library-owned host memory, valid until the next
  * lst_load_geometry or lst_destroy.  Errors: NO_GEOMETRY. */

@@ -473,6 +473,8 @@ struct lst_ctx {
     std::string last_error;
     bool has_geom = false;
     lst::Geometry geom;
+    std::string geom_cache;             // directory of the geometry cache (empty: none)
+    bool geom_from_cache = false;       // the loaded tables came from the cache
     lst::DevGeom dg{};
     void *geom_mem = nullptr;
     std::unique_ptr<lst::Slot> plain;   // per-event / batched / device-resident path
@@ -1307,7 +1309,8 @@ lst_status lst_load_geometry(lst_ctx *ctx, const lst_module_desc *m, uint32_t n)
     HIP_TRY(hipSetDevice(ctx->device));
     lst::Geometry geom;
     std::string err;
-    st = lst::build_geometry(ctx->p, m, n, geom, err);
+    bool from_cache = false;
+    st = lst::build_geometry_cached(ctx->p, m, n, ctx->geom_cache, geom, err, from_cache);
     if (st != LST_OK) return set_err(ctx, st, err);
     // every bin, unit and bucket index of a batch of max_batch events is a
     // 32-bit number on the device
@@ -1418,6 +1421,7 @@ lst_status lst_load_geometry(lst_ctx *ctx, const lst_module_desc *m, uint32_t n)
         (uint32_t)std::min<int64_t>((int64_t)lds_max / 4 / 256 * 256, 2 * (int64_t)geom.n_mod);
     ctx->geom = std::move(geom);
     ctx->has_geom = true;
+    ctx->geom_from_cache = from_cache;
     // arenas depend on the module count
     if (ctx->plain) free_slot_arenas(*ctx->plain);
     for (auto &s : ctx->slots) free_slot_arenas(*s);
@@ -1433,6 +1437,16 @@ lst_status lst_get_connection_map(lst_ctx *ctx, const uint32_t **begin, const ui
     *n_edges = (uint32_t)ctx->geom.edge_dst.size();
     return LST_OK;
 }
+
+lst_status lst_set_geometry_cache(lst_ctx *ctx, const char *dir)
+{
+    if (!ctx) return LST_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> g(ctx->run_mu);
+    ctx->geom_cache = dir ? dir : "";
+    return LST_OK;
+}
+
+int32_t lst_geometry_from_cache(const lst_ctx *ctx) { return ctx && ctx->geom_from_cache ? 1 : 0; }
 
 lst_status lst_build_connection_map(const lst_params *p, const lst_module_desc *m, uint32_t n,
                                     uint32_t **begin, uint32_t **dst, uint32_t *n_edges)

@@ -12,9 +12,13 @@
 // asin(x) / x the arc/chord ratio.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
+#include <string>
 #include <tuple>
+
+#include <unistd.h>
 
 #include "lst_internal.h"
 
@@ -490,6 +494,159 @@ lst_status build_geometry(const lst_params &p, const lst_module_desc *m, uint32_
     }
     for (uint32_t s = 0; s < n_surf; s++)
         if (!seen[s]) { g.surfaces[s].kind = 2; }   // empty surface
+    return LST_OK;
+}
+
+// ---- geometry cache ---------------------------------------------------------
+//
+// Blob: magic, the key (the parameters with the stream pointer cleared, then
+// the module table, byte for byte), then every table of the Geometry.  The
+// file name carries a 64-bit FNV-1a hash of the key; a blob is used only when
+// its key equals the inputs' exactly and it parses to its last byte.
+
+namespace {
+
+constexpr char kBlobMagic[8] = {'L', 'S', 'T', 'G', 'E', 'O', '0', '1'};
+
+uint64_t fnv1a64(const std::string &s)
+{
+    uint64_t h = 1469598103934665603ull;
+    for (unsigned char c : s) {
+        h ^= c;
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+struct BlobWriter {
+    std::string out;
+    template <typename T>
+    void pod(const T &v) { out.append(reinterpret_cast<const char *>(&v), sizeof(T)); }
+    template <typename T>
+    void vec(const std::vector<T> &v)
+    {
+        pod<uint64_t>(v.size());
+        if (!v.empty()) out.append(reinterpret_cast<const char *>(v.data()), v.size() * sizeof(T));
+    }
+};
+
+struct BlobReader {
+    const char *p, *end;
+    bool ok = true;
+    template <typename T>
+    void pod(T &v)
+    {
+        if (!ok || (size_t)(end - p) < sizeof(T)) { ok = false; return; }
+        std::memcpy(&v, p, sizeof(T));
+        p += sizeof(T);
+    }
+    template <typename T>
+    void vec(std::vector<T> &v)
+    {
+        uint64_t n = 0;
+        pod(n);
+        if (!ok || n > (uint64_t)(end - p) / sizeof(T)) { ok = false; return; }
+        v.resize(n);
+        if (n) std::memcpy(v.data(), p, n * sizeof(T));
+        p += n * sizeof(T);
+    }
+};
+
+// every table of the Geometry, in one order for writing and reading
+template <typename IO>
+void geometry_fields(IO &io, Geometry &g)
+{
+    io.pod(g.n_mod);
+    io.pod(g.nb);
+    io.pod(g.nd);
+    io.vec(g.kind);
+    io.vec(g.surf);
+    io.vec(g.mdc);
+    io.vec(g.edge_begin);
+    io.vec(g.edge_dst);
+    io.vec(g.edge_cls);
+    io.vec(g.classes);
+    io.vec(g.run_begin);
+    io.vec(g.run_rec);
+    io.vec(g.run_win);
+    io.vec(g.mod_phi);
+    io.vec(g.mod_ext);
+    io.vec(g.surfaces);
+    io.pod(g.c);
+}
+
+std::string geometry_key(const lst_params &p, const lst_module_desc *m, uint32_t n)
+{
+    lst_params q;
+    std::memcpy(&q, &p, sizeof q);
+    q.stream = nullptr;
+    std::string key(reinterpret_cast<const char *>(&q), sizeof q);
+    key.append(reinterpret_cast<const char *>(m), (size_t)n * sizeof(lst_module_desc));
+    return key;
+}
+
+bool read_file(const std::string &path, std::string &data)
+{
+    FILE *f = std::fopen(path.c_str(), "rb");
+    if (!f) return false;
+    bool ok = std::fseek(f, 0, SEEK_END) == 0;
+    const long sz = ok ? std::ftell(f) : -1;
+    ok = ok && sz >= 0 && std::fseek(f, 0, SEEK_SET) == 0;
+    if (ok) {
+        data.resize((size_t)sz);
+        ok = std::fread(&data[0], 1, data.size(), f) == data.size();
+    }
+    std::fclose(f);
+    return ok;
+}
+
+}  // namespace
+
+lst_status build_geometry_cached(const lst_params &p, const lst_module_desc *m, uint32_t n,
+                                 const std::string &dir, Geometry &g, std::string &err, bool &from_cache)
+{
+    from_cache = false;
+    if (dir.empty() || !m || n == 0) return build_geometry(p, m, n, g, err);
+    const std::string key = geometry_key(p, m, n);
+    char name[64];
+    std::snprintf(name, sizeof name, "/lst_geometry_%016llx.bin", (unsigned long long)fnv1a64(key));
+    const std::string path = dir + name;
+    std::string data;
+    if (read_file(path, data) && data.size() >= sizeof kBlobMagic + 8 &&
+        std::memcmp(data.data(), kBlobMagic, sizeof kBlobMagic) == 0) {
+        BlobReader r{data.data() + sizeof kBlobMagic, data.data() + data.size()};
+        uint64_t klen = 0;
+        r.pod(klen);
+        if (r.ok && klen == key.size() && (uint64_t)(r.end - r.p) >= klen && std::memcmp(r.p, key.data(), klen) == 0) {
+            r.p += klen;
+            Geometry h;
+            geometry_fields(r, h);
+            if (r.ok && r.p == r.end && h.n_mod == n) {
+                g = std::move(h);
+                from_cache = true;
+                return LST_OK;
+            }
+        }
+    }
+    const lst_status st = build_geometry(p, m, n, g, err);
+    if (st != LST_OK) return st;
+    BlobWriter w;
+    w.out.append(kBlobMagic, sizeof kBlobMagic);
+    w.pod<uint64_t>(key.size());
+    w.out += key;
+    geometry_fields(w, g);
+    // written beside, then renamed over the blob: readers never see a part
+    const std::string tmp = path + ".tmp" + std::to_string((long long)getpid()) + "_" +
+                            std::to_string((unsigned long long)(uintptr_t)&w);
+    FILE *f = std::fopen(tmp.c_str(), "wb");
+    if (f) {
+        const bool ok = std::fwrite(w.out.data(), 1, w.out.size(), f) == w.out.size();
+        if (std::fclose(f) == 0 && ok) {
+            if (std::rename(tmp.c_str(), path.c_str()) != 0) std::remove(tmp.c_str());
+        } else {
+            std::remove(tmp.c_str());
+        }
+    }
     return LST_OK;
 }
 

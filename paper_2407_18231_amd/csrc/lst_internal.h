@@ -93,4 +93,12 @@ struct Geometry {
 lst_status build_geometry(const lst_params &p, const lst_module_desc *m, uint32_t n,
                           Geometry &g, std::string &err);
 
+// As build_geometry, through a cache directory: the tables of a module list
+// and parameters are read from dir when a blob built from exactly the same
+// inputs is there (from_cache = true), otherwise built and written there
+// (a blob that cannot be read or written is ignored: the tables are built).
+// dir empty: build_geometry.
+lst_status build_geometry_cached(const lst_params &p, const lst_module_desc *m, uint32_t n,
+                                 const std::string &dir, Geometry &g, std::string &err, bool &from_cache);
+
 }  // namespace lst

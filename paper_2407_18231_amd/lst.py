@@ -102,6 +102,8 @@ def load(path: str = LIB_PATH):
         "lst_build_connection_map": (C.c_int32, [_P(lst_params), C.c_void_p, C.c_uint32,
                                                  _P(_P(C.c_uint32)), _P(_P(C.c_uint32)), _P(C.c_uint32)]),
         "lst_free_map": (None, [_P(C.c_uint32), _P(C.c_uint32)]),
+        "lst_set_geometry_cache": (C.c_int32, [C.c_void_p, C.c_char_p]),
+        "lst_geometry_from_cache": (C.c_int32, [C.c_void_p]),
         "lst_run_event": (C.c_int32, [C.c_void_p, _P(lst_event_in), _P(_P(lst_event_out))]),
         "lst_run_batch": (C.c_int32, [C.c_void_p, _P(lst_event_in), C.c_uint32, _P(_P(lst_event_out))]),
         "lst_submit": (C.c_int32, [C.c_void_p, _P(lst_event_in), _P(C.c_uint64)]),
@@ -276,6 +278,14 @@ class Context:
         m = module_table(geom)
         self._check(self.L.lst_load_geometry(self.h, _ptr(m), len(m)))
         self.n_mod = len(m)
+
+    def set_geometry_cache(self, directory):
+        """Directory of the geometry cache (None: none); see lst_set_geometry_cache."""
+        self._check(self.L.lst_set_geometry_cache(self.h, directory.encode() if directory else None))
+
+    @property
+    def geometry_from_cache(self) -> bool:
+        return bool(self.L.lst_geometry_from_cache(self.h))
 
     def connection_map(self):
         """(begin[n_mod+1], dst[n_edges]) of the loaded geometry."""

@@ -313,3 +313,22 @@ def test_outputs_outlive_context_and_each_other(g, ctx):
         same(ref[k], got)
         assert np.array_equal(ref[k]["t3_kappa"].view(np.uint32), got["t3_kappa"].view(np.uint32))
         L.lst_free_output(outs[k])
+
+
+def test_geometry_cache(g, tmp_path):
+    """A geometry read back from the cache gives the lists of the one built
+    from the module table."""
+    ev = s.gen_event(g, s.config_pu(100), s.event_seed(2, 50))
+    with lst.Context() as c:
+        c.set_geometry_cache(str(tmp_path))
+        c.load_geometry(g)
+        assert not c.geometry_from_cache
+        a = c.run_event(ev)
+    assert len(list(tmp_path.glob("lst_geometry_*.bin"))) == 1
+    with lst.Context() as c:
+        c.set_geometry_cache(str(tmp_path))
+        c.load_geometry(g)
+        assert c.geometry_from_cache
+        b = c.run_event(ev)
+    same(a, b)
+    assert np.array_equal(a["t3_kappa"].view(np.uint32), b["t3_kappa"].view(np.uint32))

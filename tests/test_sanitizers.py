@@ -1,7 +1,8 @@
 """CPU runs of the host code under the address and undefined-behaviour
 sanitizers: the oracle (built with them and loaded into a child process that
 preloads the sanitizer runtime) on a small and a contract-edge event, and
-the library's geometry builder (built with them into a small checker)."""
+the library's geometry builder and its cache (built with them into a small
+checker)."""
 import os
 import shutil
 import subprocess
@@ -65,8 +66,12 @@ def test_geometry_builder_under_sanitizers(tmp_path, name):
     g = synth.make_geometry(name)
     (tmp_path / "mods.bin").write_bytes(lst.module_table(g).tobytes())
     (tmp_path / "params.bin").write_bytes(bytes(lst.default_params()))
-    p = subprocess.run([exe, str(tmp_path / "mods.bin"), str(tmp_path / "params.bin")], capture_output=True,
-                       text=True, timeout=600, env=_env({}))
+    cache = tmp_path / "cache"
+    cache.mkdir()
+    p = subprocess.run([exe, str(tmp_path / "mods.bin"), str(tmp_path / "params.bin"), str(cache)],
+                       capture_output=True, text=True, timeout=600, env=_env({}))
     assert p.returncode == 0, (p.returncode, p.stdout[-2000:], p.stderr[-4000:])
     assert "runtime error" not in p.stderr, p.stderr[-4000:]
-    assert p.stdout.startswith(f"modules {len(g.kind)} ")
+    assert p.stdout.startswith("cache: miss, hit, miss for other parameters\n")
+    assert f"modules {len(g.kind)} " in p.stdout
+    assert len(list(cache.glob("lst_geometry_*.bin"))) == 2
