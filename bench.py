@@ -413,7 +413,7 @@ def link_probe():
     return json.loads(out.stdout.strip().splitlines()[-1])
 
 
-_INPUT_KEYS = ("x", "y", "z", "module", "sensor", "pls_par", "pls_cov")
+_INPUT_KEYS = ("x", "y", "z", "module", "sensor", "pls_par", "pls_cov", "pls_nhits")
 
 
 def _served_event(args):

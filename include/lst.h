@@ -105,6 +105,9 @@ typedef struct {
  * inner against outer T3 for a T5, relative to the summed resolutions),
  * then the smaller index in its own list.  Seed-only candidates are kept. */
 #define LST_FLAG_TC_CLEAN 4u
+/* Seed export (lst_event_out.seeds): besides the quads, the triplets (the
+ * "quads + triplets" configuration of the recovery iteration, Sec. 2). */
+#define LST_FLAG_SEEDS_TRIPLETS 8u
 
 /* Stages of the chain (Sec. 1: hits -> MD -> LS -> T3 -> T5; pLS linked into
  * pT3 / pT5; track candidates), the index of each in stage_ns */
@@ -162,6 +165,10 @@ typedef struct {
     const float *pls_cov;    /* 15 per seed: upper triangle of the 5x5 covariance, row major */
     uint32_t flags;          /* LST_DEVICE_PTRS */
     uint32_t pad;
+    /* pixel hits of each seed (3: triplet, >= 4: quad); NULL: every seed is a
+     * quad.  Used only to select the seeds the event exports (seeds in
+     * lst_event_out). */
+    const uint8_t *pls_nhits;
 } lst_event_in;
 
 #define LST_DEVICE_PTRS 1u
@@ -204,6 +211,13 @@ typedef struct {
     uint32_t n_tcc;          /* with LST_FLAG_TC_CLEAN: candidates kept by the duplicate cleaning */
     uint64_t footprint;      /* served path: predicted device bytes the event was admitted with */
     uint32_t *tcc;           /* (type, index) as in tc, the kept subset in tc order; NULL without the flag */
+    /* Seeds exported for a downstream seeded track finder (Sec. 2, Table 1:
+     * the recovery iteration seeded by LST pLS quads, or quads and
+     * triplets): the seeds that are track candidates on their own (linked to
+     * no T3 or T5), in increasing order, those with at least 4 pixel hits,
+     * and with LST_FLAG_SEEDS_TRIPLETS also those with 3. */
+    uint32_t n_seeds;
+    uint32_t *seeds;
 } lst_event_out;
 
 void lst_default_params(lst_params *p);

@@ -238,6 +238,27 @@ def run(geom, ev: dict, params: Params | None = None) -> dict:
     return out
 
 
+# ---------------------------------------------------------- seed export ---
+
+def export_seeds(res: dict, pls_nhits=None, triplets: bool = False):
+    """Seeds handed to a downstream seeded track finder (Sec. 2, Table 1: the
+    recovery iteration seeded by LST pLS quads, or by quads and triplets).
+    Reading: the seeds that are track candidates by themselves -- the pLS
+    entries of the candidate list, seeds linked to no T3 or T5 -- with at
+    least four pixel hits (quads), and with three as well (triplets) when
+    triplets is set; pls_nhits None: every seed a quad.  Returns the seed
+    indices in increasing order and, per entry, whether its candidate is
+    flagged (near a cut boundary)."""
+    tc = np.asarray(res["tc"]).reshape(-1, 2).astype(np.int64)
+    st = np.asarray(res.get("tc_st", np.zeros(len(tc), np.uint8)))
+    own = tc[:, 0] == 3
+    seeds, flag = tc[own, 1], st[own] == ST_FLAG
+    nh = np.full(seeds.size, 4) if pls_nhits is None else np.asarray(pls_nhits, np.int64)[seeds]
+    keep = (nh >= 4) | (triplets & (nh == 3))
+    order = np.argsort(seeds[keep], kind="stable")
+    return seeds[keep][order], flag[keep][order]
+
+
 # ----------------------------------------------------------------- keys ---
 
 def object_keys(md, ls, t3, t5, pt3, pt5, tc):

@@ -114,6 +114,7 @@ void carve_inputs(Carver &cv, Batch &b)
     b.in_sen = cv.take<uint8_t>(b.cap_hits);
     b.in_par = cv.take<float>(5ull * b.cap_pls);
     b.in_cov = cv.take<float>(15ull * b.cap_pls);
+    b.in_nhit = cv.take<uint8_t>(b.cap_pls);
     b.ev_hit_off = cv.take<uint32_t>(b.cap_ev + 1);
     b.ev_pls_off = cv.take<uint32_t>(b.cap_ev + 1);
 }
@@ -642,10 +643,10 @@ lst_status ensure_work(lst_ctx *ctx, Slot &s)
     // the largest output image the list capacities allow (download checks
     // the image it writes against it)
     const bool clean = (c.flags & LST_FLAG_TC_CLEAN) != 0u;
-    const uint64_t img_words = (uint64_t)(b.cap_ev + 1) * lst::kEvTabCols + b.cap_ev +
+    const uint64_t img_words = (uint64_t)(b.cap_ev + 1) * lst::kEvTabCols + 2ull * b.cap_ev +
                                2ull * ((uint64_t)b.cap_md + b.cap_ls + b.cap_t3 + b.cap_t5 + b.cap_pt3 +
                                        2ull * b.cap_pt5 + b.cap_tc) +
-                               b.cap_t3 + (clean ? 2ull * ((uint64_t)b.cap_pt5 + b.cap_tc) : 0ull);
+                               b.cap_t3 + (clean ? 2ull * ((uint64_t)b.cap_pt5 + b.cap_tc) : 0ull) + b.cap_tc;
     s.work_bytes = cw.off;
     hipError_t e = hipMalloc(&s.work_arena, s.work_bytes);
     if (e != hipSuccess) {
@@ -699,7 +700,7 @@ lst_status stage_inputs(lst_ctx *ctx, Slot &s, const lst_event_in *evs, uint32_t
     char *hs = s.h_stage;
     struct Arr { void *dev; size_t elt; int which; };
     const Arr arrs[] = {{b.in_x, 4, 0}, {b.in_y, 4, 1}, {b.in_z, 4, 2}, {b.in_mod, 4, 3},
-                        {b.in_sen, 1, 4}, {b.in_par, 20, 5}, {b.in_cov, 60, 6}};
+                        {b.in_sen, 1, 4}, {b.in_par, 20, 5}, {b.in_cov, 60, 6}, {b.in_nhit, 1, 7}};
     for (const Arr &a : arrs) {
         size_t base_off = (char *)a.dev - (char *)s.in_arena;
         const std::vector<uint32_t> &offs = a.which < 5 ? s.hit_off : s.pls_off;
@@ -710,8 +711,16 @@ lst_status stage_inputs(lst_ctx *ctx, Slot &s, const lst_event_in *evs, uint32_t
             const void *src = a.which == 0 ? (const void *)ev.x : a.which == 1 ? (const void *)ev.y
                             : a.which == 2 ? (const void *)ev.z : a.which == 3 ? (const void *)ev.module
                             : a.which == 4 ? (const void *)ev.sensor : a.which == 5 ? (const void *)ev.pls_par
-                            : (const void *)ev.pls_cov;
+                            : a.which == 6 ? (const void *)ev.pls_cov : (const void *)ev.pls_nhits;
             size_t at = (size_t)offs[i] * a.elt;
+            if (a.which == 7 && !src) {
+                // no hit counts given: every seed is a quad
+                if (ev.flags & LST_DEVICE_PTRS)
+                    HIP_TRY(hipMemsetAsync((char *)a.dev + at, 4, cnt, s.stream));
+                else
+                    std::memset(hs + base_off + at, 4, cnt);
+                continue;
+            }
             if (ev.flags & LST_DEVICE_PTRS) {
                 HIP_TRY(hipMemcpyAsync((char *)a.dev + at, src, cnt * a.elt, hipMemcpyDeviceToDevice, s.stream));
             } else {
@@ -867,10 +876,14 @@ lst_status download(lst_ctx *ctx, Slot &s, lst_event_out **outs)
     for (uint32_t e = 0; e < n; e++) outs[e] = nullptr;
     const lst::Totals &t = *s.h_tot;
     const bool clean = (ctx->geom.c.flags & LST_FLAG_TC_CLEAN) != 0u;
+    const bool triplets = (ctx->geom.c.flags & LST_FLAG_SEEDS_TRIPLETS) != 0u;
     const uint64_t n_tab = (uint64_t)(n + 1) * lst::kEvTabCols;
-    const uint64_t head = n_tab + n;
+    const uint64_t head = n_tab + 2ull * n;   // table, cleaning counts, seed counts
     const uint64_t pairs = (uint64_t)t.n_md + t.n_ls + t.n_t3 + t.n_t5 + t.n_pt3 + 2ull * t.n_pt5 + t.n_tc;
-    const uint64_t words = head + 2 * pairs + t.n_t3 + (clean ? 2ull * ((uint64_t)t.n_pt5 + t.n_tc) : 0ull);
+    // the seed-only candidates (room for the exported seeds) are some of
+    // the n_tc candidates: the image's size is known exactly only from its
+    // table, so the buffer is sized with all of them
+    const uint64_t words = head + 2 * pairs + t.n_t3 + (clean ? 2ull * ((uint64_t)t.n_pt5 + t.n_tc) : 0ull) + t.n_tc;
     if (words > s.img_words) {
         fail(ctx, "output image larger than the list capacities");
         return LST_ERR_DEVICE;
@@ -894,7 +907,7 @@ lst_status download(lst_ctx *ctx, Slot &s, lst_event_out **outs)
     s.L.err = hipSuccess;
     const uint64_t items = n_tab + pairs + t.n_t3;   // one per pair, curvature and table word
     if (he == hipSuccess) {
-        lst::launch_pack(s.L, s.b, s.d_tot, (uint32_t *)dimg, n, head, words, clean, items);
+        lst::launch_pack(s.L, s.b, s.d_tot, (uint32_t *)dimg, n, head, words, clean, triplets, items);
         he = s.L.err;
     }
     if (he == hipSuccess) he = hipStreamSynchronize(s.stream);
@@ -908,11 +921,11 @@ lst_status download(lst_ctx *ctx, Slot &s, lst_event_out **outs)
     // the image's size from the copied table must be the one the totals gave
     auto before = [&](const uint32_t *r) {
         const uint64_t p = (uint64_t)r[2] + r[3] + r[4] + r[5] + r[6] + 2ull * r[7] + r[8] + r[9] + r[10];
-        return 2 * p + r[4] + (clean ? 2ull * ((uint64_t)r[7] + r[8] + r[9] + r[10]) : 0ull);
+        return 2 * p + r[4] + (clean ? 2ull * ((uint64_t)r[7] + r[8] + r[9] + r[10]) : 0ull) + r[10];
     };
-    if (head + before(tab + n_tab - lst::kEvTabCols) - before(tab) != words) {
+    if (head + before(tab + n_tab - lst::kEvTabCols) - before(tab) > words) {
         ob->unref();
-        fail(ctx, "output image size differs from the list totals");
+        fail(ctx, "output image larger than the list totals allow");
         return LST_ERR_DEVICE;
     }
     uint32_t *lists = img + head;
@@ -950,7 +963,11 @@ lst_status download(lst_ctx *ctx, Slot &s, lst_event_out **outs)
             o->tcc = w;
             o->n_tcc = img[n_tab + e];
             if (o->n_tcc > ctc) { failed = true; break; }
+            w += 2 * ctc;
         }
+        o->seeds = w;
+        o->n_seeds = img[n_tab + n + e];
+        if (o->n_seeds > r1[10] - r0[10]) { failed = true; break; }
         o->status = LST_OK;
         std::memcpy(o->stage_ns, s.stage_ns, sizeof o->stage_ns);
         ob->refs.fetch_add(1, std::memory_order_relaxed);
@@ -1649,11 +1666,16 @@ lst_status lst_submit(lst_ctx *ctx, const lst_event_in *ev, uint64_t *ticket)
         if (!ctx->in_chunks.get(lay.bytes, se->chunk, se->blk_off))
             return set_err(ctx, LST_ERR_OOM, "pinned host allocation failed");
         char *blk = se->chunk->base + se->blk_off;
-        const void *src[7] = {ev->x, ev->y, ev->z, ev->module, ev->sensor, ev->pls_par, ev->pls_cov};
-        const size_t sz[7] = {4ull * ev->n_hits, 4ull * ev->n_hits, 4ull * ev->n_hits, 4ull * ev->n_hits,
-                              ev->n_hits, 20ull * ev->n_pls, 60ull * ev->n_pls};
+        const void *src[8] = {ev->x, ev->y, ev->z, ev->module, ev->sensor, ev->pls_par, ev->pls_cov, ev->pls_nhits};
+        const size_t sz[8] = {4ull * ev->n_hits, 4ull * ev->n_hits, 4ull * ev->n_hits, 4ull * ev->n_hits,
+                              ev->n_hits, 20ull * ev->n_pls, 60ull * ev->n_pls, ev->n_pls};
         for (int i = 0; i < 7; i++)
             if (sz[i]) std::memcpy(blk + lay.off[i], src[i], sz[i]);
+        // seed hit counts, or every seed a quad
+        if (sz[7]) {
+            if (src[7]) std::memcpy(blk + lay.off[7], src[7], sz[7]);
+            else std::memset(blk + lay.off[7], 4, sz[7]);
+        }
     }
     se->t_submit = std::chrono::steady_clock::now();
     std::lock_guard<std::mutex> g(ctx->q_mu);

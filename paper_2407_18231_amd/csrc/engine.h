@@ -102,6 +102,7 @@ struct Batch {
     uint32_t *in_mod;
     uint8_t *in_sen;
     float *in_par, *in_cov;
+    uint8_t *in_nhit;                   // pixel hits of each seed (seed export)
     uint32_t *ev_hit_off, *ev_pls_off;  // cap_ev + 1
     // a1: hits sorted by (event, module, sensor)
     uint32_t *bin_cnt, *bin_off, *hbin, *hrank;
@@ -288,20 +289,20 @@ struct EventOut {
 void launch_event_init(Launcher &L, const Batch &b, Totals *t, uint32_t n_hits, uint32_t n_pls);
 
 // Bytes of one served event's host block and the offsets of its parts
-// (x, y, z, module, sensor, seed parameters, seed covariance), every part
-// aligned to 16 bytes; k_unpack reads the same layout.
+// (x, y, z, module, sensor, seed parameters, seed covariance, seed pixel
+// hits), every part aligned to 16 bytes; k_unpack reads the same layout.
 struct BlockLayout {
-    size_t off[7];
+    size_t off[8];
     size_t bytes;
 };
 inline BlockLayout served_block_layout(uint32_t n_hits, uint32_t n_pls)
 {
     auto pad = [](size_t v) { return (v + 15) & ~(size_t)15; };
     BlockLayout l;
-    const size_t sz[7] = {4ull * n_hits, 4ull * n_hits, 4ull * n_hits, 4ull * n_hits, n_hits, 20ull * n_pls,
-                          60ull * n_pls};
+    const size_t sz[8] = {4ull * n_hits, 4ull * n_hits, 4ull * n_hits, 4ull * n_hits, n_hits, 20ull * n_pls,
+                          60ull * n_pls, n_pls};
     size_t at = 0;
-    for (int i = 0; i < 7; i++) {
+    for (int i = 0; i < 8; i++) {
         l.off[i] = at;
         at += pad(sz[i]);
     }
@@ -309,11 +310,12 @@ inline BlockLayout served_block_layout(uint32_t n_hits, uint32_t n_pls)
     return l;
 }
 void launch_unpack(Launcher &L, const Batch &b, const Totals *t, const char *raw, const unsigned long long *raw_off);
-// the output image of the staged batch (event table, cleaning counts, then
-// every event's lists in the layout of lst_event_out) at img, head words of
-// table and counts first; nothing is written at or past cap words
+// the output image of the staged batch (event table, cleaning and seed
+// counts, then every event's lists in the layout of lst_event_out) at img,
+// head words of table and counts first; nothing is written at or past cap
+// words
 void launch_pack(Launcher &L, const Batch &b, const Totals *t, uint32_t *img, uint32_t n_ev, uint64_t head,
-                 uint64_t cap, bool clean, uint64_t n_items);
+                 uint64_t cap, bool clean, bool triplets, uint64_t n_items);
 void launch_event_out(Launcher &L, const Batch &b, const Totals *t, const EventOut &o, uint64_t n_items);
 void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, const Consts &c, int stats);
 

@@ -2392,26 +2392,29 @@ __global__ void k_unpack(const Batch b, const Totals *t, const char *__restrict_
         const float *pc = reinterpret_cast<const float *>(par + pad16(20u * m)) + 15u * j;
         for (uint32_t w = 0; w < 5u; w++) b.in_par[5u * (size_t)p + w] = pp[w];
         for (uint32_t w = 0; w < 15u; w++) b.in_cov[15u * (size_t)p + w] = pc[w];
+        b.in_nhit[p] = reinterpret_cast<const uint8_t *>(par + pad16(20u * m) + pad16(60u * m))[j];
     }
 }
 
 // Output image of a batch, in 32-bit words: the event table ((n_ev + 1) rows),
 // then per event the number of kept candidates of the duplicate cleaning,
-// then each event's lists in the layout of lst_event_out with event-local
-// indices: MD, LS, T3, T5, pT3, pT5 pairs, the track-candidate pairs (every
-// pT5, then the kept pT3, T5 and seed entries), the T3 curvatures and, with
-// the cleaning, the candidates it keeps.  The host copies a batch's outputs
+// then per event the number of exported seeds, then each event's lists in
+// the layout of lst_event_out with event-local indices: MD, LS, T3, T5, pT3,
+// pT5 pairs, the track-candidate pairs (every pT5, then the kept pT3, T5 and
+// seed entries), the T3 curvatures, with the cleaning the candidates it
+// keeps, and the exported seeds.  The host copies a batch's outputs
 // in one transfer and hands each event pointers into it.
 __device__ inline uint64_t image_words_before(const uint32_t *r, bool clean)
 {
     // r holds the first index of every list of an event: the words of the
-    // images of all events before it, up to those of event 0
+    // images of all events before it, up to those of event 0 (the last term:
+    // room for the exported seeds, one word per seed-only candidate)
     const uint64_t pairs = (uint64_t)r[2] + r[3] + r[4] + r[5] + r[6] + 2ull * r[7] + r[8] + r[9] + r[10];
-    return 2ull * pairs + r[4] + (clean ? 2ull * ((uint64_t)r[7] + r[8] + r[9] + r[10]) : 0ull);
+    return 2ull * pairs + r[4] + (clean ? 2ull * ((uint64_t)r[7] + r[8] + r[9] + r[10]) : 0ull) + r[10];
 }
 
 struct EventImage {
-    uint32_t *md, *ls, *t3, *t5, *pt3, *pt5, *tc, *kappa, *tcc;
+    uint32_t *md, *ls, *t3, *t5, *pt3, *pt5, *tc, *kappa, *tcc, *seeds;
     uint32_t cp5, c3, c5;   // pT5s, and track candidates from pT3s and from T5s
 };
 
@@ -2434,6 +2437,7 @@ __device__ inline EventImage event_image(uint32_t *img, uint64_t head, const uin
     m.tc = m.pt5 + 2u * m.cp5;
     m.kappa = m.tc + 2u * ctc;
     m.tcc = m.kappa + ct3;
+    m.seeds = m.tcc + (clean ? 2u * ctc : 0u);
     return m;
 }
 
@@ -2563,8 +2567,51 @@ __global__ void __launch_bounds__(256) k_pack_tcc(const Batch b, const Totals *t
     if (threadIdx.x == 0 && at < cap) img[at] = kept;
 }
 
+// Seed export: the seed-only candidates of each event (in increasing seed
+// order) with at least 4 pixel hits, or with 3 as well when triplets are
+// exported, compacted per event (one block per event), and their number.
+__global__ void __launch_bounds__(256) k_pack_seeds(const Batch b, const Totals *t, uint32_t *__restrict__ img,
+                                                    uint64_t head, uint64_t cap, uint32_t clean, uint32_t triplets)
+{
+    __shared__ uint32_t s_cnt[4];
+    const uint32_t n_ev = t->n_ev;
+    const uint32_t e = blockIdx.x;
+    if (e >= n_ev) return;
+    const uint32_t *tab = b.ev_tab;
+    const uint32_t *r0 = tab + (size_t)e * kEvTabCols, *r1 = r0 + kEvTabCols;
+    const EventImage m = event_image(img, head, tab, e, clean != 0u);
+    const uint32_t cp = r1[10] - r0[10];
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    uint32_t kept = 0;
+    for (uint32_t j0 = 0; j0 < cp; j0 += 256u) {
+        const uint32_t j = j0 + threadIdx.x;
+        bool keep = false;
+        uint32_t seed = 0;
+        if (j < cp) {
+            const uint32_t g = b.tc_idx[r0[10] + j];   // the seed's index in the batch
+            const uint32_t nh = b.in_nhit[g];
+            keep = nh >= 4u || (triplets != 0u && nh == 3u);
+            seed = g - r0[1];
+        }
+        const unsigned long long bal = __ballot(keep);
+        if (lane == 0) s_cnt[wv] = (uint32_t)__popcll(bal);
+        __syncthreads();
+        uint32_t before = kept;
+        for (uint32_t w = 0; w < wv; w++) before += s_cnt[w];
+        before += (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+        if (keep) {
+            uint32_t *d = m.seeds + before;
+            if ((uint64_t)(d - img) < cap) *d = seed;
+        }
+        kept += s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+        __syncthreads();
+    }
+    const uint64_t at = (uint64_t)(n_ev + 1) * kEvTabCols + n_ev + e;
+    if (threadIdx.x == 0 && at < cap) img[at] = kept;
+}
+
 void launch_pack(Launcher &L, const Batch &b, const Totals *t, uint32_t *img, uint32_t n_ev, uint64_t head,
-                 uint64_t cap, bool clean, uint64_t n_items)
+                 uint64_t cap, bool clean, bool triplets, uint64_t n_items)
 {
     // the image goes over the host link (≈ 55 GB/s), which 256 blocks keep
     // busy; the rest of the device stays free for the other slot's chain
@@ -2572,6 +2619,9 @@ void launch_pack(Launcher &L, const Batch &b, const Totals *t, uint32_t *img, ui
     const uint32_t bx = std::max<uint32_t>(1u, 256u / std::max<uint32_t>(n_ev, 1u));
     if (n_ev) L.launch("pack", k_pack, dim3(bx, n_ev), dim3(256), b, t, img, head, cap, clean ? 1u : 0u);
     if (clean && n_ev) L.launch("pack_tcc", k_pack_tcc, dim3(n_ev), dim3(256), b, t, img, head, cap);
+    if (n_ev)
+        L.launch("pack_seeds", k_pack_seeds, dim3(n_ev), dim3(256), b, t, img, head, cap, clean ? 1u : 0u,
+                 triplets ? 1u : 0u);
 }
 
 void launch_unpack(Launcher &L, const Batch &b, const Totals *t, const char *raw, const unsigned long long *raw_off)

@@ -23,6 +23,7 @@ STATUS = {0: "OK", 1: "PENDING", -1: "INVALID_ARG", -2: "DEVICE", -3: "NO_GEOMET
 LST_FLAG_BEND = 1
 LST_FLAG_STAGE_TIMES = 2
 LST_FLAG_TC_CLEAN = 4
+LST_FLAG_SEEDS_TRIPLETS = 8
 STAGES = ("ingest", "md", "ls", "t3", "t5", "seed_lookup", "pt", "tc")
 LST_DEVICE_PTRS = 1
 TC_PT5, TC_PT3, TC_T5, TC_PLS = 0, 1, 2, 3
@@ -55,7 +56,7 @@ class lst_event_in(C.Structure):
                 ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p),
                 ("module", C.c_void_p), ("sensor", C.c_void_p),
                 ("pls_par", C.c_void_p), ("pls_cov", C.c_void_p),
-                ("flags", C.c_uint32), ("pad", C.c_uint32)]
+                ("flags", C.c_uint32), ("pad", C.c_uint32), ("pls_nhits", C.c_void_p)]
 
 
 class lst_event_out(C.Structure):
@@ -69,7 +70,8 @@ class lst_event_out(C.Structure):
                 ("latency_us", C.c_double), ("ticket", C.c_uint64),
                 ("n_flag_regrow", C.c_uint32), ("n_stage", C.c_uint32),
                 ("stage_ns", C.c_uint64 * len(STAGES)), ("batch_events", C.c_uint32),
-                ("n_tcc", C.c_uint32), ("footprint", C.c_uint64), ("tcc", C.POINTER(C.c_uint32))]
+                ("n_tcc", C.c_uint32), ("footprint", C.c_uint64), ("tcc", C.POINTER(C.c_uint32)),
+                ("n_seeds", C.c_uint32), ("seeds", C.POINTER(C.c_uint32))]
 
 
 _LISTS = ("md", "ls", "t3", "t5", "pt3", "pt5", "tc")
@@ -154,6 +156,8 @@ def default_params(**kw) -> lst_params:
             p.flags = (p.flags & ~LST_FLAG_STAGE_TIMES) | (LST_FLAG_STAGE_TIMES if v else 0)
         elif k == "tc_clean":
             p.flags = (p.flags & ~LST_FLAG_TC_CLEAN) | (LST_FLAG_TC_CLEAN if v else 0)
+        elif k == "seeds_triplets":
+            p.flags = (p.flags & ~LST_FLAG_SEEDS_TRIPLETS) | (LST_FLAG_SEEDS_TRIPLETS if v else 0)
         elif k == "stream":
             # a torch.cuda.Stream, or a raw hipStream_t handle
             p.stream = C.c_void_p(int(getattr(v, "cuda_stream", v)) if v is not None else None)
@@ -195,6 +199,10 @@ class EventIn:
                     t = name.contiguous()
                     self.keep.append(t)
                     setattr(self.c, f, C.c_void_p(t.data_ptr()))
+                if ev.get("pls_nhits") is not None:
+                    t = ev["pls_nhits"].contiguous()
+                    self.keep.append(t)
+                    self.c.pls_nhits = C.c_void_p(t.data_ptr())
             self.c.flags = LST_DEVICE_PTRS
             return
         x = np.ascontiguousarray(ev["x"], np.float32)
@@ -207,6 +215,10 @@ class EventIn:
         self.keep = [x, y, z, mod, sen, par, cov]
         self.c = lst_event_in(x.size, par.size // 5, _ptr(x), _ptr(y), _ptr(z), _ptr(mod),
                               _ptr(sen), _ptr(par), _ptr(cov), 0, 0)
+        if ev.get("pls_nhits") is not None:
+            nh = np.ascontiguousarray(ev["pls_nhits"], np.uint8)
+            self.keep.append(nh)
+            self.c.pls_nhits = _ptr(nh)
 
 
 def _is_torch(a):
@@ -228,6 +240,8 @@ def _out_to_dict(o: lst_event_out) -> dict:
     d["n_flag_regrow"] = o.n_flag_regrow
     d["batch_events"] = o.batch_events
     d["tcc"] = pairs(o.tcc, o.n_tcc) if o.tcc else None
+    d["seeds"] = (np.ctypeslib.as_array(o.seeds, shape=(o.n_seeds,)).copy()
+                  if o.n_seeds else np.zeros(0, np.uint32))
     d["footprint"] = o.footprint
     d["stage_ns"] = {name: int(o.stage_ns[i]) for i, name in enumerate(STAGES)}
     return d

@@ -313,7 +313,8 @@ def gen_event(geom: Geometry, cfg: EventConfig, seed: int) -> dict:
       hit_track (int32): generating track of each hit, -1 for noise;
       pls_par (float32 [n,5]: q/pT, phi0, cot(theta), d0, z0),
       pls_cov (float32 [n,15]: upper triangle of the 5x5 covariance, row
-        major), pls_track (int32, -1 for fakes);
+        major), pls_track (int32, -1 for fakes), pls_nhits (uint8: pixel
+        hits of each seed, 3 or 4);
       tracks (float64 [n,5]: q, pT, eta, phi0, vz).
     """
     rng = np.random.default_rng(seed)
@@ -374,8 +375,17 @@ def gen_event(geom: Geometry, cfg: EventConfig, seed: int) -> dict:
               sensor=sen[perm].astype(np.uint8), hit_track=tid[perm].astype(np.int32),
               tracks=trk)
     par, cov, ptid = gen_pls(trk, cfg, rng)
-    ev.update(pls_par=par, pls_cov=cov, pls_track=ptid)
+    ev.update(pls_par=par, pls_cov=cov, pls_track=ptid, pls_nhits=seed_pixel_hits(ptid, seed))
     return ev
+
+
+def seed_pixel_hits(pls_track: np.ndarray, seed: int) -> np.ndarray:
+    """Pixel hits of each seed: 4 (a quad) with probability 0.7 for a seed
+    from a track and 0.4 for a fake, else 3 (a triplet); drawn from a
+    generator of its own, so the rest of the event does not depend on it."""
+    rng = np.random.default_rng([seed, 0x5EED])
+    p_quad = np.where(pls_track >= 0, 0.7, 0.4)
+    return np.where(rng.random(pls_track.size) < p_quad, 4, 3).astype(np.uint8)
 
 
 def gen_pls(trk: np.ndarray, cfg: EventConfig, rng):

@@ -359,3 +359,44 @@ def test_tc_cleaning_parity(geo):
     with lst.Context() as c:
         c.load_geometry(g)
         assert c.run_event(evs[0])["tcc"] is None
+
+
+def _seed_set(seeds, excused):
+    return set(int(v) for v in seeds) - excused
+
+
+def test_seed_export(geo):
+    """Exported seeds (Sec. 2, Table 1: the recovery iteration seeded by LST
+    pLS quads, or quads and triplets) equal the oracle's selection from its
+    own candidate list, alone, in a batch, in the served mix and from device
+    pointers.  Seeds whose linking the oracle flags (a flagged pT3 or pT5, or
+    a flagged seed-only candidate) may differ."""
+    torch = pytest.importorskip("torch")
+    g = geo["pu200"]
+    evs = [s.gen_event(g, s.config_pu(200), s.event_seed(2, i)) for i in (0, 1)]
+    for ev in evs:
+        assert set(np.unique(ev["pls_nhits"]).tolist()) == {3, 4}
+    for triplets in (False, True):
+        with lst.Context(seeds_triplets=triplets, n_slots=1) as c:
+            c.load_geometry(g)
+            alone = [c.run_event(ev) for ev in evs]
+            batch = c.run_batch(evs)
+            served = [c.poll(c.submit(ev), -1) for ev in evs]
+            d = {k: torch.from_numpy(np.ascontiguousarray(evs[0][k])).to("cuda:0")
+                 for k in ("x", "y", "z", "sensor", "pls_par", "pls_cov", "pls_nhits")}
+            d["module"] = torch.from_numpy(evs[0]["module"].astype(np.int32)).to("cuda:0")
+            torch.cuda.synchronize()
+            dev = c.run_event(d)
+        assert np.array_equal(dev["seeds"], alone[0]["seeds"])
+        for ev, a, b, v in zip(evs, alone, batch, served):
+            assert np.array_equal(a["seeds"], b["seeds"]) and np.array_equal(a["seeds"], v["seeds"])
+            assert np.all(np.diff(a["seeds"].astype(np.int64)) > 0)
+            ores = oracle.run(g, ev)
+            want, flag = oracle.export_seeds(ores, ev["pls_nhits"], triplets)
+            excused = set(int(p) for p in want[flag])
+            for k in ("pt3", "pt5"):
+                excused |= set(int(p) for p in ores[k][ores[k + "_st"] == oracle.ST_FLAG][:, 0])
+            assert _seed_set(a["seeds"], excused) == _seed_set(want, excused)
+            assert len(want) > 100
+            nh = ev["pls_nhits"][a["seeds"].astype(np.int64)]
+            assert np.all(nh >= (3 if triplets else 4))

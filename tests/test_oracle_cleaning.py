@@ -100,3 +100,17 @@ def test_cleaning_cuts_duplicates_not_efficiency(pu200):
     assert before["duplicate_rate"] > 0.6 and after["duplicate_rate"] < before["duplicate_rate"] / 3
     assert after["efficiency"] > before["efficiency"] - 0.02
     assert after["fake_rate"] <= before["fake_rate"]
+
+
+def test_seed_export_selection():
+    """Seed export (Sec. 2, Table 1): only the seed-only candidates, quads by
+    default, triplets too on request, in seed order; a hand-made list."""
+    res = dict(tc=np.array([[0, 0], [3, 2], [1, 0], [3, 0], [3, 5], [2, 1], [3, 1]]),
+               tc_st=np.array([1, 1, 1, 1, 2, 1, 1], np.uint8))
+    nh = np.array([3, 2, 4, 4, 4, 5], np.uint8)
+    s, f = oracle.export_seeds(res, nh)
+    assert s.tolist() == [2, 5] and f.tolist() == [False, True]
+    s, f = oracle.export_seeds(res, nh, triplets=True)
+    assert s.tolist() == [0, 2, 5]
+    s, _ = oracle.export_seeds(res)          # no hit counts: every seed a quad
+    assert s.tolist() == [0, 1, 2, 5]
