@@ -361,6 +361,9 @@ def main():
         # what the served path moves per event crosses this link both ways
         result["host_link"] = link_probe()
         log("host link:", result["host_link"])
+        # ---- physics: truth-matched rates of the candidates --------------------
+        result["physics"] = physics(g, events[:16])
+        log("physics:", result["physics"])
     ctx.close()
 
     if not args.no_cpu:
@@ -396,6 +399,48 @@ def copy_probe(mb: int):
     b.copy_(a)
     torch.cuda.synchronize()
     log(f"copied {mb} MiB")
+
+
+def physics(g, events, n_displaced_events: int = 8):
+    """Truth-matched efficiency, fake and duplicate rates (Sec. 3: a track is
+    found by a candidate with more than 75% of its hits) of the benchmark's
+    PU200 events, for the candidate list and for the list after duplicate
+    cleaning; and the efficiency vs production radius of displaced tracks
+    (400 per event on a PU50 background, r_vertex up to 35 cm; Sec. 3,
+    Fig. 3 right)."""
+    from paper_2407_18231_amd import lst, metrics, synth
+    keys = ("efficiency", "fake_rate", "duplicate_rate")
+    with lst.Context(max_batch=len(events), tc_clean=True) as c:
+        c.load_geometry(g)
+        res = c.run_batch(events)
+        n_ev = len(events)
+        acc = {"all": dict.fromkeys(keys, 0.0), "cleaned": dict.fromkeys(keys, 0.0)}
+        n_tc = {"all": 0, "cleaned": 0}
+        for ev, r in zip(events, res):
+            for name, tc in (("all", r["tc"]), ("cleaned", r["tcc"])):
+                q = metrics.rates(ev, dict(r, tc=tc))
+                n_tc[name] += q["n_tc"]
+                for k in keys:
+                    acc[name][k] += q[k] / n_ev
+        disp = [synth.gen_event(g, synth.config_pu(50, n_displaced=400), synth.event_seed(8, i))
+                for i in range(n_displaced_events)]
+        dres = c.run_batch(disp)
+    bins = None
+    for ev, r in zip(disp, dres):
+        e = metrics.efficiency_vs_rv(ev, r)["bins"]
+        if bins is None:
+            bins = [dict(rv_cm=[b["rv_lo"], b["rv_hi"]], n_sim=0, found=0.0) for b in e]
+        for acc_b, b in zip(bins, e):
+            acc_b["n_sim"] += b["n_sim"]
+            acc_b["found"] += b["efficiency"] * b["n_sim"]
+    for b in bins:
+        b["efficiency"] = round(b.pop("found") / max(b["n_sim"], 1), 4)
+    return dict(events=f"{len(events)} PU200-like events of the benchmark batch",
+                candidates={k: dict({q: round(v, 4) for q, v in acc[k].items()},
+                                    candidates_per_event=round(n_tc[k] / len(events), 1)) for k in acc},
+                displaced=dict(events=f"{n_displaced_events} events: PU50 + 400 displaced tracks "
+                                      f"(pT 1-10 GeV, |eta| < 2, seeds 8000+i)",
+                               efficiency_vs_rv=bins))
 
 
 def link_probe():

@@ -100,3 +100,35 @@ def rates(ev: dict, res: dict, pt_min: float = 0.8, eta_max: float = 2.4) -> dic
                 fake_rate=float((m < 0).mean()) if n else 0.0,
                 duplicate_rate=float(dup.mean()) if n else 0.0,
                 by_type=by_type)
+
+
+def efficiency_vs_rv(ev: dict, res: dict, edges=(0.0, 1.0, 5.0, 10.0, 20.0, 35.0), pt_min: float = 0.8,
+                     eta_max: float = 2.4, displaced_only: bool = True) -> dict:
+    """Efficiency as a function of the production radius r_vertex (Sec. 3,
+    Fig. 3 right): per bin [edges[i], edges[i+1]) of ev["track_rv"], the
+    fraction of selected simulated tracks (pT > pt_min, |eta| < eta_max;
+    only those with r_vertex > 0 when displaced_only) matched by at least one
+    candidate, with the bin's track count; and the same for candidates of
+    each type."""
+    m = match(ev, res)
+    trk = ev["tracks"]
+    rv = ev.get("track_rv", np.zeros(trk.shape[0]))
+    sel = (trk[:, 1] > pt_min) & (np.abs(trk[:, 2]) < eta_max)
+    if displaced_only:
+        sel &= rv > 0
+    types = res["tc"][:, 0].astype(np.int64) if len(res["tc"]) else np.zeros(0, np.int64)
+    found_by = {}
+    for ti, name in enumerate(TYPES):
+        hit = np.zeros(trk.shape[0], bool)
+        t = m[(types == ti) & (m >= 0)]
+        hit[t] = True
+        found_by[name] = hit
+    found = np.zeros(trk.shape[0], bool)
+    found[m[m >= 0]] = True
+    out = []
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        b = sel & (rv >= lo) & (rv < hi)
+        n = int(b.sum())
+        out.append(dict(rv_lo=lo, rv_hi=hi, n_sim=n, efficiency=float(found[b].mean()) if n else 0.0,
+                        by_type={k: float(v[b].mean()) if n else 0.0 for k, v in found_by.items()}))
+    return dict(bins=out)

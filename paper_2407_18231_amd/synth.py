@@ -185,6 +185,14 @@ class EventConfig:
     pls_smear: bool = True
     # explicit track list (q, pt, eta, phi0, vz) overrides the random draw
     tracks: np.ndarray | None = None
+    # displaced tracks added to the random draw: production radius uniform
+    # in [0, rv_max] cm, pT uniform in [displaced_pt_lo, displaced_pt_hi],
+    # |eta| < displaced_eta_max; no pixel seed is drawn from them
+    n_displaced: int = 0
+    rv_max: float = 35.0
+    displaced_pt_lo: float = 1.0
+    displaced_pt_hi: float = 10.0
+    displaced_eta_max: float = 2.0
 
 
 def config_tiny(**kw) -> EventConfig:
@@ -253,8 +261,71 @@ def _module_of(geom: Geometry, surf: dict, phi, c):
     return np.where(ok, mod, -1)
 
 
-def propagate(geom: Geometry, trk: np.ndarray, B: float):
-    """True sensor crossings of prompt helices.
+def draw_displaced(cfg: EventConfig, rng):
+    """Displaced tracks: (q, pT, eta, phi0, vz) as for prompt ones (phi0 the
+    direction at the production point) and their production points: radius
+    uniform in [0, rv_max], azimuth within 0.3 rad of the direction (the
+    decay of a particle flying outward), z on the line from (0, 0, vz) along
+    the track's polar direction."""
+    n = cfg.n_displaced
+    q = np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    pt = rng.uniform(cfg.displaced_pt_lo, cfg.displaced_pt_hi, n)
+    eta = rng.uniform(-cfg.displaced_eta_max, cfg.displaced_eta_max, n)
+    phi0 = rng.uniform(0.0, 2 * math.pi, n)
+    vz = rng.normal(0.0, cfg.vz_sigma, n)
+    rv = rng.uniform(0.0, cfg.rv_max, n)
+    phv = phi0 + rng.uniform(-0.3, 0.3, n)
+    vtx = np.stack([rv * np.cos(phv), rv * np.sin(phv), vz + rv * np.sinh(eta)], axis=1)
+    return np.stack([q, pt, eta, phi0, vz], axis=1), vtx
+
+
+def _crossings_displaced(surf: dict, sensor: int, q, pt, eta, phi0, vtx, B: float):
+    """Sensor crossings of helices starting at vtx (x0, y0, z0) with
+    direction phi0: the first crossing along the track of the barrel radius
+    or disk plane, within half a turn."""
+    kappa = KAPPA_PER_T_GEV * B / pt
+    omega = -q * kappa
+    cot = np.sinh(eta)
+    x0, y0, z0 = vtx[:, 0], vtx[:, 1], vtx[:, 2]
+    cx = x0 - np.sin(phi0) / omega           # centre of the transverse circle
+    cy = y0 + np.cos(phi0) / omega
+    half = math.pi / np.abs(omega)           # arc length of half a turn
+    if surf["kind"] == BARREL:
+        r = surf["r_lo"] if sensor == 0 else surf["r_hi"]
+        # |P(s)|^2 = |C|^2 + R^2 + (2/omega)(cx sin u - cy cos u), u = phi0 + omega s
+        c2 = cx * cx + cy * cy
+        rad = 1.0 / (omega * omega)
+        cn = np.sqrt(c2)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            k = (r * r - c2 - rad) * omega / 2.0 / cn
+        ok = np.abs(k) <= 1.0
+        beta = np.arctan2(-cy, cx)             # cx sin u - cy cos u = cn sin(u + beta)
+        a1 = np.arcsin(np.clip(k, -1.0, 1.0))
+        s_best = np.full(q.shape, np.nan)
+        for u in (a1 - beta, math.pi - a1 - beta):
+            sv = np.mod((u - phi0) / omega, 2 * math.pi / np.abs(omega))
+            sv = np.where(sv < 1e-9, np.nan, sv)
+            s_best = np.fmin(s_best, sv)
+        s = np.where(ok & (s_best <= half), s_best, np.nan)
+        z = z0 + cot * s
+        valid = np.isfinite(s) & (np.abs(z) <= surf["half"])
+    else:
+        zp = surf["z_lo"] if sensor == 0 else surf["z_hi"]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            s = (zp - z0) / cot
+        valid = (s > 0) & (s <= half)
+        s = np.where(valid, s, np.nan)
+        z = np.full_like(s, zp)
+    u = phi0 + omega * s
+    x = cx + np.sin(u) / omega
+    y = cy - np.cos(u) / omega
+    return valid, x, y, z, s
+
+
+def propagate(geom: Geometry, trk: np.ndarray, B: float, vtx: np.ndarray | None = None):
+    """True sensor crossings of helices: prompt ones (from (0, 0, vz)) and,
+    for the tracks given production points vtx (rows of x0, y0, z0; NaN
+    rows: prompt), displaced ones.
 
     Returns a list over (surface, sensor) of dicts with arrays over tracks:
     valid mask, x, y, z, phi, r, s (transverse arc length), module id."""
@@ -262,6 +333,7 @@ def propagate(geom: Geometry, trk: np.ndarray, B: float):
     kappa = KAPPA_PER_T_GEV * B / pt
     omega = -q * kappa                      # dphi/ds
     cot = np.sinh(eta)
+    disp = np.zeros(q.shape, bool) if vtx is None else np.isfinite(vtx[:, 0])
     out = []
     for surf in geom.surfaces:
         for sensor in (0, 1):
@@ -286,6 +358,16 @@ def propagate(geom: Geometry, trk: np.ndarray, B: float):
             phi = phi0 + omega * s / 2.0
             x = rr * np.cos(phi)
             y = rr * np.sin(phi)
+            if disp.any():
+                dv, dx, dy, dz, ds = _crossings_displaced(surf, sensor, q[disp], pt[disp], eta[disp],
+                                                         phi0[disp], vtx[disp], B)
+                valid = valid.copy()
+                valid[disp] = dv
+                x = x.copy(); y = y.copy(); z = z.copy(); s = s.copy()
+                x[disp], y[disp], z[disp], s[disp] = dx, dy, dz, ds
+                rr = np.hypot(x, y)
+                phi = np.arctan2(y, x)
+                c = z if surf["kind"] == BARREL else rr
             mod = np.full(s.shape, -1, dtype=np.int64)
             if valid.any():
                 mod[valid] = _module_of(geom, surf, phi[valid], c[valid])
@@ -315,12 +397,18 @@ def gen_event(geom: Geometry, cfg: EventConfig, seed: int) -> dict:
       pls_cov (float32 [n,15]: upper triangle of the 5x5 covariance, row
         major), pls_track (int32, -1 for fakes), pls_nhits (uint8: pixel
         hits of each seed, 3 or 4);
-      tracks (float64 [n,5]: q, pT, eta, phi0, vz).
+      tracks (float64 [n,5]: q, pT, eta, phi0, vz), track_rv (float64 [n]:
+        production radius, 0 for prompt tracks).
     """
     rng = np.random.default_rng(seed)
     trk = draw_tracks(cfg, rng)
+    vtx = None
+    if cfg.n_displaced:
+        dtrk, dvtx = draw_displaced(cfg, rng)
+        vtx = np.concatenate([np.full((trk.shape[0], 3), np.nan), dvtx])
+        trk = np.concatenate([trk, dtrk])
     n_trk = trk.shape[0]
-    cr = propagate(geom, trk, cfg.B)
+    cr = propagate(geom, trk, cfg.B, vtx)
     xs, ys, zs, mods, sens, tids = [], [], [], [], [], []
     for c in cr:
         v = c["valid"].copy()
@@ -374,7 +462,9 @@ def gen_event(geom: Geometry, cfg: EventConfig, seed: int) -> dict:
               z=z[perm].astype(np.float32), module=mod[perm].astype(np.uint32),
               sensor=sen[perm].astype(np.uint8), hit_track=tid[perm].astype(np.int32),
               tracks=trk)
-    par, cov, ptid = gen_pls(trk, cfg, rng)
+    rv = np.zeros(n_trk) if vtx is None else np.where(np.isfinite(vtx[:, 0]), np.hypot(vtx[:, 0], vtx[:, 1]), 0.0)
+    ev["track_rv"] = rv
+    par, cov, ptid = gen_pls(trk, cfg, rng, prompt=rv == 0.0)
     ev.update(pls_par=par, pls_cov=cov, pls_track=ptid, pls_nhits=seed_pixel_hits(ptid, seed))
     return ev
 
@@ -388,7 +478,7 @@ def seed_pixel_hits(pls_track: np.ndarray, seed: int) -> np.ndarray:
     return np.where(rng.random(pls_track.size) < p_quad, 4, 3).astype(np.uint8)
 
 
-def gen_pls(trk: np.ndarray, cfg: EventConfig, rng):
+def gen_pls(trk: np.ndarray, cfg: EventConfig, rng, prompt: np.ndarray | None = None):
     """Pixel seeds: helix parameters plus covariance.  True seeds are drawn
     with replacement from tracks above pls_pt_min; fakes combine values drawn
     independently from the true seeds' marginals."""
@@ -397,7 +487,8 @@ def gen_pls(trk: np.ndarray, cfg: EventConfig, rng):
     tid = np.full(n, -1, dtype=np.int32)
     if n == 0:
         return par.astype(np.float32), np.zeros((0, 15), np.float32), tid
-    cand = np.nonzero(trk[:, 1] > cfg.pls_pt_min)[0]
+    ok = trk[:, 1] > cfg.pls_pt_min
+    cand = np.nonzero(ok if prompt is None else ok & prompt)[0]
     n_fake = int(round(cfg.pls_fake_frac * n)) if cand.size else n
     n_true = n - n_fake
     sel = rng.choice(cand, size=n_true, replace=True) if n_true else np.zeros(0, np.int64)

@@ -400,3 +400,18 @@ def test_seed_export(geo):
             assert len(want) > 100
             nh = ev["pls_nhits"][a["seeds"].astype(np.int64)]
             assert np.all(nh >= (3 if triplets else 4))
+
+
+def test_parity_displaced(ctx, geo):
+    """Displaced tracks (production radius up to 35 cm; Sec. 3, Fig. 3 right)
+    on a PU50 background: the lists match the oracle, and T5 candidates find
+    displaced tracks in every radius bin."""
+    from paper_2407_18231_amd import metrics
+    g = geo["pu200"]
+    ev = s.gen_event(g, s.config_pu(50, n_displaced=400), s.event_seed(8, 0))
+    res = ctx.run_event(ev)
+    check_canonical(res, ev)
+    check_parity(g, ev, res)
+    eff = metrics.efficiency_vs_rv(ev, res)
+    for b in eff["bins"]:
+        assert b["n_sim"] > 0 and b["by_type"]["T5"] > 0.1, b

@@ -54,3 +54,17 @@ def test_duplicates_and_seed_candidates():
     r = metrics.rates(ev, _res([list(range(10)), list(range(10))], extra_tc=[(3, 1), (3, 2)]))
     assert r["n_tc"] == 4
     assert r["duplicate_rate"] == 0.5 and r["fake_rate"] == 0.25 and r["efficiency"] == 1.0
+
+
+def test_efficiency_vs_rv_bins():
+    """Efficiency per production-radius bin: track 0 (r_vertex 3 cm) is
+    found by a T5, track 1 (12 cm) by nothing, track 2 (prompt, below the
+    pT cut) is not counted."""
+    ev = dict(_event(), track_rv=np.array([3.0, 12.0, 0.0]))
+    res = _res([list(range(10))])
+    r = metrics.efficiency_vs_rv(ev, res, edges=(0.0, 5.0, 20.0))
+    b0, b1 = r["bins"]
+    assert (b0["n_sim"], b0["efficiency"], b0["by_type"]["T5"]) == (1, 1.0, 1.0)
+    assert (b1["n_sim"], b1["efficiency"]) == (1, 0.0)
+    r = metrics.efficiency_vs_rv(ev, res, edges=(0.0, 5.0, 20.0), displaced_only=False, pt_min=0.5)
+    assert r["bins"][0]["n_sim"] == 2
