@@ -162,6 +162,35 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_down(const uint32_t *__rest
 #define GRID_STRIDE(i, n) \
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += gridDim.x * blockDim.x)
 
+// Grid-stride loop over [0, n) in which the blocks of each XCD take one
+// contiguous eighth (workgroups are dealt to the eight XCDs in turn), so
+// that the region of the output a kernel scatters into from that eighth
+// stays in one XCD's L2, where partial lines are merged before they go to
+// HBM.  Grids that are not a multiple of eight stride as usual.
+constexpr uint32_t kXcds = 8;
+struct XcdRange {
+    uint32_t first, end, stride;
+};
+__device__ inline XcdRange xcd_range(uint32_t n)
+{
+    const uint32_t g = gridDim.x;
+    if (g < kXcds || g % kXcds != 0u)
+        return {blockIdx.x * blockDim.x + threadIdx.x, n, g * blockDim.x};
+    const uint32_t x = blockIdx.x % kXcds;
+    const uint32_t part = (n + kXcds - 1u) / kXcds;
+    const uint32_t lo = min(x * part, n), hi = min(lo + part, n);
+    return {lo + (blockIdx.x / kXcds) * blockDim.x + threadIdx.x, hi, (g / kXcds) * blockDim.x};
+}
+#define XCD_STRIDE(i, n) \
+    for (XcdRange xr_ = xcd_range(n); xr_.first < xr_.end; xr_.first = xr_.end) \
+        for (uint32_t i = xr_.first; i < xr_.end; i += xr_.stride)
+// the same with whole blocks per step: jb is the block's first index (the
+// same on every lane); a lane's index jb + threadIdx.x is in range below
+// xb_.end
+#define XCD_STRIDE_BLOCKS(jb, n) \
+    for (XcdRange xb_ = xcd_range(n); xb_.first - threadIdx.x < xb_.end; xb_.first = xb_.end + threadIdx.x) \
+        for (uint32_t jb = xb_.first - threadIdx.x; jb < xb_.end; jb += xb_.stride)
+
 __device__ inline uint32_t find_event(const uint32_t *__restrict__ off, uint32_t n_ev, uint32_t i)
 {
     uint32_t lo = 0, hi = n_ev;
@@ -378,7 +407,7 @@ __global__ void k_hit_scatter(const Batch b, const Totals *t)
 {
     const uint32_t n = min(t->n_hits, b.cap_hits);
     const uint32_t nq = (n + kHitsPerThread - 1) / kHitsPerThread;
-    GRID_STRIDE(qd, nq) {
+    XCD_STRIDE(qd, nq) {
         const uint32_t h0 = qd * kHitsPerThread;
         uint32_t bin[kHitsPerThread], rank[kHitsPerThread], dst[kHitsPerThread];
         float4 v[kHitsPerThread];
@@ -406,7 +435,7 @@ __global__ void k_hit_scatter(const Batch b, const Totals *t)
 __global__ void k_hit_gather(const Batch b, Totals *t, const float4 *__restrict__ ext, uint32_t n_mod)
 {
     const uint32_t n = t->n_sorted;
-    GRID_STRIDE(i, n) {
+    XCD_STRIDE(i, n) {
         const float4 v = b.hrec[i];
         const uint32_t h = __float_as_uint(v.w);
         const uint32_t bin = b.hbin[h];
@@ -583,7 +612,7 @@ __global__ __launch_bounds__(256) void k_md_place(const Batch b, const Totals *t
     __syncthreads();
     const uint32_t n = s_off[nsub];
     const uint32_t subcap = b.cap_mds / nsub;
-    GRID_STRIDE(jj, n) {
+    XCD_STRIDE(jj, n) {
         const uint4 r = b.mds[pair_slot(s_off, jj, subcap, nsub)];
         const uint32_t k = b.md_hoff[r.x] + r.y;
         if (k < b.cap_md) {
@@ -905,7 +934,7 @@ __global__ __launch_bounds__(256) void k_ls_place(const Batch b, uint32_t nsub)
     __syncthreads();
     const uint32_t n = s_off[nsub];
     const uint32_t subcap = b.cap_lss / nsub;
-    GRID_STRIDE(j, n) {
+    XCD_STRIDE(j, n) {
         const uint32_t i = pair_slot(s_off, j, subcap, nsub);
         const uint32_t a = b.lss_a[i];
         const uint32_t k = b.ls_off[a] + b.lss_j[i];
@@ -1259,11 +1288,11 @@ __global__ __launch_bounds__(256) void k_t3_place(const Batch b, const DevGeom g
     const uint32_t n = s_off[nsub];
     const uint32_t subcap = b.cap_t3s / nsub;
     // whole waves per step (the bucket slots are drawn per wave)
-    for (uint32_t jb = blockIdx.x * blockDim.x; jb < n; jb += gridDim.x * blockDim.x) {
+    XCD_STRIDE_BLOCKS(jb, n) {
         const uint32_t j = jb + threadIdx.x;
         bool in = false;
         uint32_t k = 0, bk = 0;
-        if (j < n) {
+        if (j < xb_.end) {
             const uint32_t i = pair_slot(s_off, j, subcap, nsub);
             const uint32_t l1 = b.t3s_l1[i];
             k = b.t3_off[l1] + b.t3s_j[i];
@@ -1392,11 +1421,11 @@ __global__ __launch_bounds__(256) void k_t5_place(const Batch b, const DevGeom g
     const uint32_t n = s_off[nsub];
     const uint32_t subcap = b.cap_t5s / nsub;
     // whole waves per step (the bucket slots are drawn per wave)
-    for (uint32_t jb = blockIdx.x * blockDim.x; jb < n; jb += gridDim.x * blockDim.x) {
+    XCD_STRIDE_BLOCKS(jb, n) {
         const uint32_t j = jb + threadIdx.x;
         bool in = false;
         uint32_t k = 0, bk = 0;
-        if (j < n) {
+        if (j < xb_.end) {
             const uint32_t i = pair_slot(s_off, j, subcap, nsub);
             const uint32_t u = b.t5s_u[i];
             k = b.t5_off[u] + b.t5s_j[i];
@@ -1447,7 +1476,7 @@ __global__ void k_bucket_scatter(const Batch b, const Totals *t)
     const uint32_t *rank = kKind == 0 ? b.bk3_rank : b.bk5_rank;
     float4 *bks = kKind == 0 ? b.bk3_ks : b.bk5_ks;
     const float2 *ks = kKind == 0 ? b.t3_ks : b.t5_ks;
-    GRID_STRIDE(i, n) {
+    XCD_STRIDE(i, n) {
         const uint32_t pos = off[id[i]] + rank[i];
         const uint32_t a = kKind == 0 ? b.t3_ac[i].x : b.t3_ac[b.t5_u[i]].x;
         const float4 pa = b.md_pos[a];
