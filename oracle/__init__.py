@@ -89,10 +89,12 @@ class Params:
     n_sigma: float = 3.0
     flag_margin: float = 1e-5
     bend: bool = True
+    skip: bool = False   # segments may also bridge one surface
 
     def c(self) -> _Params:
         return _Params(self.B, self.pt_min, self.L, self.sig_rphi, self.sig_c,
-                       self.n_sigma, self.flag_margin, 1 if self.bend else 0)
+                       self.n_sigma, self.flag_margin,
+                       (1 if self.bend else 0) | (2 if self.skip else 0))
 
 
 _lib = None

@@ -10,7 +10,8 @@
  *
  * Structure (each stage is a plain loop nest over all candidates):
  *   MD : every (lower, upper) hit pair of a module               (Sec. 1, MD)
- *   LS : every MD pair whose modules lie on consecutive surfaces
+ *   LS : every MD pair whose modules lie on consecutive surfaces, or
+ *        with the skip-layer flag also on surfaces two steps apart
  *        (brute force over all module pairs, no connection map)  (Sec. 1, LS)
  *   T3 : every LS pair sharing the middle MD                     (Sec. 1, T3)
  *   T5 : every T3 pair sharing an MD (outer of the first = inner
@@ -62,7 +63,8 @@ typedef struct {
     double sig_c;       /* coarse resolution: z (barrel) / r (endcap) [cm] */
     double n_sigma;
     double flag_margin; /* relative margin for borderline candidates */
-    uint32_t flags;     /* bit 0: line-segment bend-consistency cut */
+    uint32_t flags;     /* bit 0: line-segment bend-consistency cut;
+                           bit 1: skip-layer links (a segment may bridge one surface) */
 } or_params;
 
 typedef struct {
@@ -288,6 +290,19 @@ static int is_next(surfinfo si, uint32_t s, uint32_t t)
     }
     uint32_t d = (s - si.nb) % si.nd;
     return d + 1 < si.nd && t == s + 1;
+}
+
+/* Surfaces whose modules a segment may join: the next ones, and with skip
+   also the next surfaces of those (a track that left no mini-doublet on the
+   surface in between is still linked; the paper's connection maps hold the
+   module pairs a charged particle can cross in turn, Sec. 1). */
+static int is_linked(surfinfo si, uint32_t s, uint32_t t, int skip)
+{
+    if (is_next(si, s, t)) return 1;
+    if (!skip) return 0;
+    for (uint32_t u = 0; u < si.nb + 2 * si.nd; u++)
+        if (is_next(si, s, u) && is_next(si, u, t)) return 1;
+    return 0;
 }
 
 /* ---------------------------------------------------------- the cuts ---- */
@@ -532,6 +547,7 @@ int or_run(const or_geom *g, const or_params *p, const or_event *ev, or_result *
     derive(g, p, &d);
     double fm = p->flag_margin;
     int bend = (int)(p->flags & 1u);
+    int skip = (int)((p->flags >> 1) & 1u);
     surfinfo si = surf_info(g);
     uint32_t nsurf = si.nb + 2 * si.nd;
     uint32_t nh = ev->n_hits;
@@ -587,7 +603,7 @@ int or_run(const or_geom *g, const or_params *p, const or_event *ev, or_result *
         anc[a].disk = g->kind[md_mod_v[a]] == OR_ENDCAP;
     }
 
-    /* ---- LS: all MD pairs on consecutive surfaces ---- */
+    /* ---- LS: all MD pairs on linked surfaces ---- */
     uint32_t *md_surf = (uint32_t *)malloc((nmd ? nmd : 1) * sizeof(uint32_t));
     for (uint32_t a = 0; a < nmd; a++) md_surf[a] = surface_of(g, si, md_mod_v[a]);
     uint32_t *surf_items;
@@ -596,7 +612,7 @@ int or_run(const or_geom *g, const or_params *p, const or_event *ev, or_result *
     for (uint32_t a = 0; a < nmd; a++) {
         uint32_t sa = md_surf[a], A = md_mod_v[a];
         for (uint32_t t = 0; t < nsurf; t++) {
-            if (!is_next(si, sa, t)) continue;
+            if (!is_linked(si, sa, t, skip)) continue;
             uint32_t lastB = UINT32_MAX;
             lsconst kc;
             memset(&kc, 0, sizeof kc);

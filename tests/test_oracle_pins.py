@@ -28,7 +28,7 @@ import pytest
 
 import oracle
 from paper_2407_18231_amd import synth as s
-from truth import truth_objects, _surface_ids, _is_next
+from truth import truth_objects, _surface_ids, _is_next, _is_linked
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "window_constants.txt")
 
@@ -71,7 +71,7 @@ def test_window_constants_closed_form():
 
 def _eff(g, ev, mask, params=None):
     kd = oracle.keyed(oracle.run(g, ev, params))
-    tr = truth_objects(g, ev, mask)
+    tr = truth_objects(g, ev, mask, skip=bool(params and params.skip))
     return {k: (len(tr[k] & {q for q, st in kd[k].items() if st & oracle.ST_ACC}), len(tr[k])) for k in tr}
 
 
@@ -101,6 +101,43 @@ def test_truth_smeared_efficiency():
     mask = np.abs(ev["tracks"][:, 4]) < 14.0
     for k, (found, tot) in _eff(g, ev, mask).items():
         assert found >= 0.99 * tot, (k, found, tot)
+
+
+def test_skip_layer_links():
+    """Skip-layer links: noiseless prompt tracks above threshold with 15% of
+    their hits dropped.  With the flag every true object of the two-step
+    chains is found (a segment across a surface where the track left no
+    mini-doublet included), the lists without the flag are a subset of those
+    with it, every segment joins surfaces one step apart without the flag and
+    at most two with it, and more tracks are covered by a T5."""
+    g = s.make_geometry("pu200")
+    cfg = s.config_pu(20, noise_frac=0.0, fake_frac=0.0, smear=False, ineff=0.15,
+                      pt_mode="uniform", pt_lo=0.81, pt_hi=20.0, n_tracks=300)
+    ev = s.gen_event(g, cfg, 23)
+    mask = np.abs(ev["tracks"][:, 4]) < 14.9
+    on = oracle.Params(skip=True)
+    for k, (found, tot) in _eff(g, ev, mask, on).items():
+        assert tot > 0 and found == tot, (k, found, tot)
+    r0, r1 = oracle.run(g, ev), oracle.run(g, ev, on)
+    k0, k1 = oracle.keyed(r0), oracle.keyed(r1)
+    for k in ("md", "ls", "t3", "t5"):
+        assert set(k0[k]) <= set(k1[k]), k
+    sid, nb, nd = _surface_ids(g)
+    md_surf = lambda r: sid[ev["module"][r["md"][:, 0]]]
+    for r, skip in ((r0, False), (r1, True)):
+        ms = md_surf(r)
+        pairs = {(int(ms[a]), int(ms[b])) for a, b in r["ls"][:, :2]}
+        assert all(_is_linked(nb, nd, a, b, skip) for a, b in pairs)
+    two = [p for p in {(int(a), int(b)) for a, b in md_surf(r1)[r1["ls"][:, :2]]}
+           if not _is_next(nb, nd, *p)]
+    assert len(two) > 5
+    # tracks with a true T5 (found by the oracle, checked above)
+    tid = ev["hit_track"]
+    tr0 = truth_objects(g, ev, mask)["t5"]
+    tr1 = truth_objects(g, ev, mask, skip=True)["t5"]
+    trk0 = {int(tid[q[0]]) for q in tr0}
+    trk1 = {int(tid[q[0]]) for q in tr1}
+    assert trk0 < trk1 and len(trk1) >= len(trk0) + 10, (len(trk0), len(trk1))
 
 
 def _tracks(n, pt, eta_lo, eta_hi, vz, seed):

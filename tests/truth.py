@@ -31,9 +31,19 @@ def _is_next(nb, nd, s, t):
     return d + 1 < nd and t == s + 1
 
 
-def truth_objects(geom, ev, track_mask=None):
+def _is_linked(nb, nd, s, t, skip):
+    """t is the next surface of s, or with skip the next of a next surface"""
+    if _is_next(nb, nd, s, t):
+        return True
+    return skip and any(_is_next(nb, nd, s, u) and _is_next(nb, nd, u, t)
+                        for u in range(nb + 2 * nd))
+
+
+def truth_objects(geom, ev, track_mask=None, skip=False):
     """Returns dict stage -> set of keys, for tracks selected by track_mask
-    (boolean array over tracks; default all)."""
+    (boolean array over tracks; default all).  With skip, segments may also
+    join a track's mini-doublets two surfaces apart, and every chain of such
+    segments is a true T3 / T5."""
     sid, nb, nd = _surface_ids(geom)
     tid = ev["hit_track"]
     mod = ev["module"].astype(np.int64)
@@ -67,6 +77,19 @@ def truth_objects(geom, ev, track_mask=None):
         per_track_mds[t] = mds
         for s, k in mds:
             out["md"].add(k)
+        if skip:
+            n = len(mds)
+            nxt = [[j for j in range(i + 1, n) if _is_linked(nb, nd, mds[i][0], mds[j][0], True)]
+                   for i in range(n)]
+            for i in range(n):
+                for j in nxt[i]:
+                    out["ls"].add(mds[i][1] + mds[j][1])
+                    for k in nxt[j]:
+                        out["t3"].add(mds[i][1] + mds[j][1] + mds[k][1])
+                        for l in nxt[k]:
+                            for m in nxt[l]:
+                                out["t5"].add(mds[i][1] + mds[j][1] + mds[k][1] + mds[l][1] + mds[m][1])
+            continue
         # chains of consecutive MDs on consecutive surfaces
         runs = []
         cur = []
