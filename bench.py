@@ -183,6 +183,8 @@ def main():
                     help="host link bandwidth of large pinned copies, each way and both at once")
     ap.add_argument("--served-only", type=int, default=0, metavar="N",
                     help="trace runs: N events (PU ~ U[140, 200]) submitted back to back to the served path")
+    ap.add_argument("--skip-only", action="store_true",
+                    help="only the skip-layer section (batch, objects, rates with and without the flag)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
@@ -220,6 +222,11 @@ def main():
         pool4 = served_events(5000)
         pool5 = served_events(256, 300.0, 300.0, 5, 0.4, 0.05)
         log(f"served pools: {len(pool4)} + {len(pool5)} events in {time.perf_counter() - t0:.1f} s")
+
+    if args.skip_only:
+        log("skip-layer links:", json.dumps(skip_layer(g, events, args.steps)))
+        log("physics:", json.dumps(physics(g, events[:16], 0)))
+        return
 
     ctx = lst.Context(max_batch=max(B, 64))
     ctx.load_geometry(g)
@@ -364,6 +371,8 @@ def main():
         # ---- physics: truth-matched rates of the candidates --------------------
         result["physics"] = physics(g, events[:16])
         log("physics:", result["physics"])
+        result["skip_layer"] = skip_layer(g, events, args.steps)
+        log("skip-layer links:", result["skip_layer"])
     ctx.close()
 
     if not args.no_cpu:
@@ -409,26 +418,16 @@ def physics(g, events, n_displaced_events: int = 8):
     (400 per event on a PU50 background, r_vertex up to 35 cm; Sec. 3,
     Fig. 3 right)."""
     from paper_2407_18231_amd import lst, metrics, synth
-    keys = ("efficiency", "fake_rate", "duplicate_rate")
     with lst.Context(max_batch=len(events), tc_clean=True) as c:
         c.load_geometry(g)
         res = c.run_batch(events)
-        n_ev = len(events)
-        acc = {"all": dict.fromkeys(keys, 0.0), "cleaned": dict.fromkeys(keys, 0.0)}
-        n_tc = {"all": 0, "cleaned": 0}
-        for ev, r in zip(events, res):
-            for name, tc in (("all", r["tc"]), ("cleaned", r["tcc"])):
-                q = metrics.rates(ev, dict(r, tc=tc))
-                n_tc[name] += q["n_tc"]
-                for k in keys:
-                    acc[name][k] += q[k] / n_ev
         disp = [synth.gen_event(g, synth.config_pu(50, n_displaced=400), synth.event_seed(8, i))
                 for i in range(n_displaced_events)]
-        dres = c.run_batch(disp)
-    bins = None
+        dres = c.run_batch(disp) if disp else []
+    bins = []
     for ev, r in zip(disp, dres):
         e = metrics.efficiency_vs_rv(ev, r)["bins"]
-        if bins is None:
+        if not bins:
             bins = [dict(rv_cm=[b["rv_lo"], b["rv_hi"]], n_sim=0, found=0.0) for b in e]
         for acc_b, b in zip(bins, e):
             acc_b["n_sim"] += b["n_sim"]
@@ -436,11 +435,52 @@ def physics(g, events, n_displaced_events: int = 8):
     for b in bins:
         b["efficiency"] = round(b.pop("found") / max(b["n_sim"], 1), 4)
     return dict(events=f"{len(events)} PU200-like events of the benchmark batch",
-                candidates={k: dict({q: round(v, 4) for q, v in acc[k].items()},
-                                    candidates_per_event=round(n_tc[k] / len(events), 1)) for k in acc},
+                candidates=_rates(events, res),
                 displaced=dict(events=f"{n_displaced_events} events: PU50 + 400 displaced tracks "
                                       f"(pT 1-10 GeV, |eta| < 2, seeds 8000+i)",
                                efficiency_vs_rv=bins))
+
+
+def _rates(events, res):
+    """Mean truth-matched rates over events, for the candidate list and the
+    list after duplicate cleaning; efficiency_ot counts a track found only
+    by a candidate with outer-tracker objects (pT5, pT3, T5)."""
+    from paper_2407_18231_amd import metrics
+    keys = ("efficiency", "efficiency_ot", "fake_rate", "duplicate_rate")
+    out = {}
+    for name, col in (("all", "tc"), ("cleaned", "tcc")):
+        acc, n_tc = dict.fromkeys(keys, 0.0), 0
+        for ev, r in zip(events, res):
+            q = metrics.rates(ev, dict(r, tc=r[col]))
+            n_tc += q["n_tc"]
+            for k in keys:
+                acc[k] += q[k] / len(events)
+        out[name] = dict({k: round(v, 4) for k, v in acc.items()},
+                         candidates_per_event=round(n_tc / len(events), 1))
+    return out
+
+
+def skip_layer(g, events, steps: int, n_physics: int = 16):
+    """Skip-layer links (segments may also bridge one surface): the benchmark
+    batch through a context with LST_FLAG_SKIP_LAYER, timed with hipGraph
+    replay as the batched path without the flag is (no duplicate cleaning),
+    its objects per event, and the truth-matched rates of its first n_physics
+    events with cleaning (compare physics.candidates, the same events without
+    the flag)."""
+    from paper_2407_18231_amd import lst
+    with lst.Context(max_batch=len(events), skip_layer=True) as c:
+        c.load_geometry(g)
+        c.batch_upload(events)
+        c.batch_execute(2, graph=True)
+        t1 = time.perf_counter()
+        c.batch_execute(steps, graph=True)
+        dt = (time.perf_counter() - t1) / steps
+    with lst.Context(max_batch=n_physics, tc_clean=True, skip_layer=True) as c:
+        c.load_geometry(g)
+        res = c.run_batch(events[:n_physics])
+    objs = {k: round(float(np.mean([len(r[k]) for r in res])), 1) for k in ("ls", "t3", "t5", "pt3", "pt5", "tc")}
+    return dict(batch=len(events), events_per_s=round(len(events) / dt, 1), ms_per_step=round(dt * 1e3, 4),
+                objects_per_event=objs, candidates=_rates(events[:n_physics], res))
 
 
 def link_probe():

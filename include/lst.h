@@ -108,6 +108,14 @@ typedef struct {
 /* Seed export (lst_event_out.seeds): besides the quads, the triplets (the
  * "quads + triplets" configuration of the recovery iteration, Sec. 2). */
 #define LST_FLAG_SEEDS_TRIPLETS 8u
+/* Skip-layer links: the connection map (Sec. 1: module pairs that charged
+ * particles cross in turn) also pairs each module with the modules of the
+ * surfaces two steps out -- the next surfaces of its next surfaces -- so a
+ * line segment may bridge a surface on which the track left no mini-doublet.
+ * Without it a module is paired with the next barrel layer, the first disk of
+ * either side (barrel) or the next disk of its side (endcap).  More segments,
+ * T3s and T5s, and candidates that the cleaning (LST_FLAG_TC_CLEAN) merges. */
+#define LST_FLAG_SKIP_LAYER 16u
 
 /* Stages of the chain (Sec. 1: hits -> MD -> LS -> T3 -> T5; pLS linked into
  * pT3 / pT5; track candidates), the index of each in stage_ns */

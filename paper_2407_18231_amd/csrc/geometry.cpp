@@ -279,7 +279,8 @@ lst_status build_geometry(const lst_params &p, const lst_module_desc *m, uint32_
 
     std::vector<std::vector<uint32_t>> by_surf(n_surf);
     for (uint32_t i = 0; i < n; i++) by_surf[g.surf[i]].push_back(i);
-    auto next_surfaces = [&](uint32_t s) {
+    // surfaces a prompt outgoing track crosses right after s
+    auto step = [&](uint32_t s) {
         std::vector<uint32_t> out;
         if (s < nb) {
             if (s + 1 < nb) out.push_back(s + 1);
@@ -288,6 +289,18 @@ lst_status build_geometry(const lst_params &p, const lst_module_desc *m, uint32_
             uint32_t d = (s - nb) % nd;
             if (d + 1 < nd) out.push_back(s + 1);
         }
+        return out;
+    };
+    // surfaces whose modules a segment from s may reach: one step, and with
+    // skip-layer links also two (each surface once, in increasing order)
+    const bool skip = (p.flags & LST_FLAG_SKIP_LAYER) != 0;
+    auto next_surfaces = [&](uint32_t s) {
+        std::vector<uint32_t> out = step(s);
+        if (skip)
+            for (uint32_t u : step(s))
+                for (uint32_t t : step(u)) out.push_back(t);
+        std::sort(out.begin(), out.end());
+        out.erase(std::unique(out.begin(), out.end()), out.end());
         return out;
     };
 

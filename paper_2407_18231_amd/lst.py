@@ -24,6 +24,7 @@ LST_FLAG_BEND = 1
 LST_FLAG_STAGE_TIMES = 2
 LST_FLAG_TC_CLEAN = 4
 LST_FLAG_SEEDS_TRIPLETS = 8
+LST_FLAG_SKIP_LAYER = 16
 STAGES = ("ingest", "md", "ls", "t3", "t5", "seed_lookup", "pt", "tc")
 LST_DEVICE_PTRS = 1
 TC_PT5, TC_PT3, TC_T5, TC_PLS = 0, 1, 2, 3
@@ -158,6 +159,8 @@ def default_params(**kw) -> lst_params:
             p.flags = (p.flags & ~LST_FLAG_TC_CLEAN) | (LST_FLAG_TC_CLEAN if v else 0)
         elif k == "seeds_triplets":
             p.flags = (p.flags & ~LST_FLAG_SEEDS_TRIPLETS) | (LST_FLAG_SEEDS_TRIPLETS if v else 0)
+        elif k == "skip_layer":
+            p.flags = (p.flags & ~LST_FLAG_SKIP_LAYER) | (LST_FLAG_SKIP_LAYER if v else 0)
         elif k == "stream":
             # a torch.cuda.Stream, or a raw hipStream_t handle
             p.stream = C.c_void_p(int(getattr(v, "cuda_stream", v)) if v is not None else None)

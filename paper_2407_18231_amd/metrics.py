@@ -89,6 +89,8 @@ def rates(ev: dict, res: dict, pt_min: float = 0.8, eta_max: float = 2.4) -> dic
     n = len(m)
     dup = np.array([t >= 0 and n_per_track[t] > 1 for t in m], bool)
     types = res["tc"][:, 0].astype(np.int64) if n else np.zeros(0, np.int64)
+    ot = m[(m >= 0) & (types != TYPES.index("pLS"))] if n else m[:0]
+    found_ot = np.bincount(ot, minlength=trk.shape[0])[sel] > 0 if ot.size else np.zeros(sel.size, bool)
     by_type = {}
     for ti, name in enumerate(TYPES):
         k = types == ti
@@ -97,6 +99,7 @@ def rates(ev: dict, res: dict, pt_min: float = 0.8, eta_max: float = 2.4) -> dic
                              duplicate=float(dup[k].mean()) if k.any() else 0.0)
     return dict(n_tc=n, n_sim=int(sel.size),
                 efficiency=float(found.mean()) if sel.size else 0.0,
+                efficiency_ot=float(found_ot.mean()) if sel.size else 0.0,
                 fake_rate=float((m < 0).mean()) if n else 0.0,
                 duplicate_rate=float(dup.mean()) if n else 0.0,
                 by_type=by_type)

@@ -23,8 +23,8 @@ OWN_FLOOR = 8
 ALL_FLOOR = 20
 
 
-def check_parity(geom, ev, res):
-    ores = oracle.run(geom, ev)
+def check_parity(geom, ev, res, params=None):
+    ores = oracle.run(geom, ev, params)
     kd = oracle.keyed(ores)
     fb = oracle.flag_breakdown(ores)
     got = lst.result_keys(res)

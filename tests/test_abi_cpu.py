@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 from paper_2407_18231_amd import lst, synth as s
-from truth import _surface_ids, _is_next
+from truth import _surface_ids, _is_next, _is_linked
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -80,6 +80,30 @@ def test_connection_map_holds_every_oracle_segment(lib, kind):
                   for t in set(range(nb + 2 * nd)) if _is_next(nb, nd, int(sid[a]), t)) if kind == "tiny" else None
     if n_pairs:
         assert dst.size < 0.5 * n_pairs
+
+
+def test_skip_layer_map_holds_every_oracle_segment(lib):
+    """With skip-layer links the map pairs modules on surfaces one or two
+    steps apart, holds every edge of the plain map and every segment the
+    oracle builds with the same links."""
+    g, ev = s.standard_event("pu200")
+    b0, d0 = lst.build_connection_map(g)
+    b1, d1 = lst.build_connection_map(g, lst.default_params(skip_layer=True))
+    sid, nb, nd = _surface_ids(g)
+    src0 = np.repeat(np.arange(g.n_mod), np.diff(b0))
+    src1 = np.repeat(np.arange(g.n_mod), np.diff(b1))
+    e0 = set(zip(src0.tolist(), d0.tolist()))
+    e1 = set(zip(src1.tolist(), d1.tolist()))
+    assert e0 < e1
+    surf = {(int(sid[a]), int(sid[b])) for a, b in e1}
+    assert all(_is_linked(nb, nd, a, b, True) for a, b in surf)
+    assert sum(1 for a, b in surf if not _is_next(nb, nd, a, b)) > 5
+    r = oracle.run(g, ev, oracle.Params(skip=True))
+    md_mod = ev["module"][r["md"][:, 0]]
+    pairs = {(int(md_mod[a]), int(md_mod[b])) for a, b in r["ls"]}
+    assert len(pairs - e0) > 100
+    missing = pairs - e1
+    assert not missing, list(missing)[:5]
 
 
 def test_bucket_granularity_params(lib, tmp_path):

@@ -59,6 +59,29 @@ def test_parity_pu200(ctx, geo, i):
     assert len(res["pt5"]) > 500 and len(res["ls"]) > 50_000
 
 
+def test_parity_skip_layer(geo):
+    """Skip-layer links (segments may bridge one surface): on a PU200 event
+    (10% hit inefficiency) the lists equal the oracle's with the same links,
+    the map holds the two-step edges, and a batch of three events equals the
+    events run one by one."""
+    g = geo["pu200"]
+    with lst.Context(skip_layer=True) as c:
+        c.load_geometry(g)
+        ev = s.gen_event(g, s.config_pu(200), s.event_seed(2, 0))
+        res = c.run_event(ev)
+        check_canonical(res, ev)
+        rep = check_parity(g, ev, res, oracle.Params(skip=True))
+        assert rep["ls"]["got"] > 120_000
+        evs = [s.gen_event(g, s.config_pu(200), s.event_seed(9, i)) for i in range(3)]
+        for e, rb in zip(evs, c.run_batch(evs)):
+            ra = c.run_event(e)
+            for k in STAGES:
+                assert np.array_equal(ra[k], rb[k]), k
+        begin, dst = c.connection_map()
+    begin0, dst0 = lst.build_connection_map(g)
+    assert len(dst) > len(dst0)
+
+
 def test_parity_pu300_stress(ctx, geo):
     g = geo["pu200"]
     ev = s.gen_event(g, s.config_pu(300, noise_frac=0.4, fake_frac=0.05), s.event_seed(5, 0))

@@ -54,6 +54,8 @@ def test_duplicates_and_seed_candidates():
     r = metrics.rates(ev, _res([list(range(10)), list(range(10))], extra_tc=[(3, 1), (3, 2)]))
     assert r["n_tc"] == 4
     assert r["duplicate_rate"] == 0.5 and r["fake_rate"] == 0.25 and r["efficiency"] == 1.0
+    # track 1 is found by its seed only: not by an outer-tracker candidate
+    assert r["efficiency_ot"] == 0.5
 
 
 def test_efficiency_vs_rv_bins():
