@@ -225,7 +225,7 @@ def main():
 
     if args.skip_only:
         log("skip-layer links:", json.dumps(skip_layer(g, events, args.steps)))
-        log("physics:", json.dumps(physics(g, events[:16], 0)))
+        log("physics:", json.dumps(physics(g, events[:16])))
         return
 
     ctx = lst.Context(max_batch=max(B, 64))
@@ -416,7 +416,7 @@ def physics(g, events, n_displaced_events: int = 8):
     PU200 events, for the candidate list and for the list after duplicate
     cleaning; and the efficiency vs production radius of displaced tracks
     (400 per event on a PU50 background, r_vertex up to 35 cm; Sec. 3,
-    Fig. 3 right)."""
+    Fig. 3 right), without and with skip-layer links."""
     from paper_2407_18231_amd import lst, metrics, synth
     with lst.Context(max_batch=len(events), tc_clean=True) as c:
         c.load_geometry(g)
@@ -424,21 +424,28 @@ def physics(g, events, n_displaced_events: int = 8):
         disp = [synth.gen_event(g, synth.config_pu(50, n_displaced=400), synth.event_seed(8, i))
                 for i in range(n_displaced_events)]
         dres = c.run_batch(disp) if disp else []
-    bins = []
-    for ev, r in zip(disp, dres):
-        e = metrics.efficiency_vs_rv(ev, r)["bins"]
-        if not bins:
-            bins = [dict(rv_cm=[b["rv_lo"], b["rv_hi"]], n_sim=0, found=0.0) for b in e]
-        for acc_b, b in zip(bins, e):
-            acc_b["n_sim"] += b["n_sim"]
-            acc_b["found"] += b["efficiency"] * b["n_sim"]
-    for b in bins:
-        b["efficiency"] = round(b.pop("found") / max(b["n_sim"], 1), 4)
+    with lst.Context(max_batch=max(len(disp), 1), skip_layer=True) as c:
+        c.load_geometry(g)
+        dres_skip = c.run_batch(disp) if disp else []
+
+    def rv_bins(results):
+        bins = []
+        for ev, r in zip(disp, results):
+            e = metrics.efficiency_vs_rv(ev, r)["bins"]
+            if not bins:
+                bins = [dict(rv_cm=[b["rv_lo"], b["rv_hi"]], n_sim=0, found=0.0) for b in e]
+            for acc_b, b in zip(bins, e):
+                acc_b["n_sim"] += b["n_sim"]
+                acc_b["found"] += b["efficiency"] * b["n_sim"]
+        for b in bins:
+            b["efficiency"] = round(b.pop("found") / max(b["n_sim"], 1), 4)
+        return bins
     return dict(events=f"{len(events)} PU200-like events of the benchmark batch",
                 candidates=_rates(events, res),
                 displaced=dict(events=f"{n_displaced_events} events: PU50 + 400 displaced tracks "
                                       f"(pT 1-10 GeV, |eta| < 2, seeds 8000+i)",
-                               efficiency_vs_rv=bins))
+                               efficiency_vs_rv=rv_bins(dres),
+                               efficiency_vs_rv_skip_layer=rv_bins(dres_skip)))
 
 
 def _rates(events, res):
