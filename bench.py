@@ -300,6 +300,18 @@ def main():
                   objects_per_event={k: round(counts[k] / B, 1) for k in ("md", "ls", "t3", "t5", "pt3", "pt5", "tc")})
 
     if not args.quick:
+        # ---- batched, end to end: host inputs in, host lists out ----------------
+        ins = [lst.EventIn(ev) for ev in events]
+        ctx.run_batch_in(ins, fetch=False)
+        t1 = time.perf_counter()
+        for _ in range(5):
+            ctx.run_batch_in(ins, fetch=False)
+        dt = (time.perf_counter() - t1) / 5
+        result["batched_e2e"] = dict(events_per_s=round(B / dt, 1), ms_per_call=round(dt * 1e3, 3),
+                                     path=f"lst_run_batch, {B} events per call: host inputs in, "
+                                          f"host lists out, the library call alone")
+        log("batched end to end:", result["batched_e2e"])
+        del ins
         # ---- plain path: one event per launch, on its own context ---------------
         ctx1 = lst.Context()
         ctx1.load_geometry(g)

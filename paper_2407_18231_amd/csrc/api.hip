@@ -674,6 +674,42 @@ lst_status check_event(lst_ctx *ctx, const lst_event_in &ev)
 }
 
 // Stage n events into the slot's input arena (async on the slot stream).
+// Copies of host-pointer inputs into the pinned stage.  A batch of 64
+// PU200-like events moves about 70 MB this way, which one thread copies out
+// of pageable memory at a fraction of what the host's memory gives, so
+// copies of more than 8 MiB in all are split by bytes over up to 8 threads
+// (the calling thread takes the first share).
+struct HostCopy { char *dst; const char *src; size_t n; };
+
+static void parallel_copy(const std::vector<HostCopy> &jobs)
+{
+    size_t total = 0;
+    for (const HostCopy &j : jobs) total += j.n;
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const unsigned nt = total < (size_t(8) << 20) ? 1u : std::min(8u, hw);
+    auto work = [&jobs, total, nt](unsigned t) {
+        const size_t share = (total + nt - 1) / nt;
+        const size_t lo = std::min(total, t * share), hi = std::min(total, lo + share);
+        size_t pos = 0;
+        for (const HostCopy &j : jobs) {
+            const size_t a = std::max(lo, pos), b = std::min(hi, pos + j.n);
+            if (a < b) std::memcpy(j.dst + (a - pos), j.src + (a - pos), b - a);
+            pos += j.n;
+            if (pos >= hi) break;
+        }
+    };
+    std::vector<std::thread> th;
+    for (unsigned t = 1; t < nt; t++) {
+        try {
+            th.emplace_back(work, t);
+        } catch (...) {
+            work(t);   // no thread to be had: copy this share here
+        }
+    }
+    work(0);
+    for (std::thread &x : th) x.join();
+}
+
 lst_status stage_inputs(lst_ctx *ctx, Slot &s, const lst_event_in *evs, uint32_t n)
 {
     uint64_t hits = 0, pls = 0;
@@ -701,6 +737,7 @@ lst_status stage_inputs(lst_ctx *ctx, Slot &s, const lst_event_in *evs, uint32_t
     struct Arr { void *dev; size_t elt; int which; };
     const Arr arrs[] = {{b.in_x, 4, 0}, {b.in_y, 4, 1}, {b.in_z, 4, 2}, {b.in_mod, 4, 3},
                         {b.in_sen, 1, 4}, {b.in_par, 20, 5}, {b.in_cov, 60, 6}, {b.in_nhit, 1, 7}};
+    std::vector<HostCopy> jobs;
     for (const Arr &a : arrs) {
         size_t base_off = (char *)a.dev - (char *)s.in_arena;
         const std::vector<uint32_t> &offs = a.which < 5 ? s.hit_off : s.pls_off;
@@ -724,10 +761,11 @@ lst_status stage_inputs(lst_ctx *ctx, Slot &s, const lst_event_in *evs, uint32_t
             if (ev.flags & LST_DEVICE_PTRS) {
                 HIP_TRY(hipMemcpyAsync((char *)a.dev + at, src, cnt * a.elt, hipMemcpyDeviceToDevice, s.stream));
             } else {
-                std::memcpy(hs + base_off + at, src, cnt * a.elt);
+                jobs.push_back({hs + base_off + at, (const char *)src, cnt * a.elt});
             }
         }
     }
+    parallel_copy(jobs);
     // one host->device copy per array for the host-pointer events
     for (const Arr &a : arrs) {
         size_t base_off = (char *)a.dev - (char *)s.in_arena;

@@ -2090,38 +2090,69 @@ __global__ void k_tcc_fill(const Batch b, const Totals *t)
     }
 }
 
+// Duplicate decision: a candidate is dropped when one that ranks higher
+// shares more than half of the smaller of the two MD sets.  kTccLanes lanes
+// take one candidate and split the concatenated candidate lists of its MDs
+// between them: a well-measured track leaves tens of candidates on each of
+// its MDs, and one lane per candidate left the chip a wave or two per SIMD
+// each walking those lists one dependent load after the other.  The group
+// stops once any of its lanes has found a reason to drop.
+constexpr uint32_t kTccLanes = 16;
+
 __global__ void k_tcc_decide(const Batch b, const Totals *t)
 {
     const uint32_t n5 = min(t->n_pt5, b.cap_pt5);
     const uint32_t n = n5 + min(t->n_tc, b.cap_tc);
-    GRID_STRIDE(i, n) {
-        const uint32_t nm = b.tcc_nm[i];
-        bool keep = true;
+    const uint32_t lane = threadIdx.x % kTccLanes;
+    const uint32_t gbase = (threadIdx.x & 63u) & ~(kTccLanes - 1u);
+    const uint64_t gmask = ((1ull << kTccLanes) - 1ull) << gbase;
+    const uint32_t groups = gridDim.x * (blockDim.x / kTccLanes);
+    for (uint32_t i = (blockIdx.x * blockDim.x + threadIdx.x) / kTccLanes; i < n; i += groups) {
+        const uint32_t nm = b.tcc_nm[i];   // the same in every lane of the group
+        bool drop = false;
         if (nm) {
-            uint32_t m[5];
-            for (uint32_t k = 0; k < 5u; k++) m[k] = b.tcc_md[5 * (size_t)i + k];
+            uint32_t m[5], beg[5], pre[5];
+            uint32_t total = 0;
+#pragma unroll
+            for (uint32_t k = 0; k < 5u; k++) {
+                m[k] = k < nm ? b.tcc_md[5 * (size_t)i + k] : 0xFFFFFFFFu;
+                beg[k] = k < nm ? b.md_tcc_off[m[k]] : 0u;
+                const uint32_t deg = k < nm ? b.md_tcc_off[m[k] + 1] - beg[k] : 0u;
+                pre[k] = total;
+                total += deg;
+            }
             const uint32_t ti = tcc_type(b, n5, i), xi = tcc_index(b, n5, i);
             const double qi = b.tcc_q[i];
-            for (uint32_t k = 0; k < nm && keep; k++) {
-                const uint32_t e = b.md_tcc_off[m[k] + 1];
-                for (uint32_t s = b.md_tcc_off[m[k]]; s < e && keep; s++) {
+            for (uint32_t base = 0; base < total; base += kTccLanes) {
+                const uint32_t p = base + lane;
+                if (p < total && !drop) {
+                    uint32_t s = beg[0] + p;
+#pragma unroll
+                    for (uint32_t k = 1; k < 5u; k++)
+                        if (k < nm && p >= pre[k]) s = beg[k] + (p - pre[k]);
                     const uint32_t j = b.md_tcc[s];
-                    if (j == i) continue;
-                    const uint32_t tj = tcc_type(b, n5, j);
-                    const double qj = b.tcc_q[j];
-                    const bool better = tj < ti || (tj == ti && (qj < qi || (qj == qi && tcc_index(b, n5, j) < xi)));
-                    if (!better) continue;
-                    const uint32_t nj = b.tcc_nm[j];
-                    uint32_t shared = 0;
-                    for (uint32_t y = 0; y < nj; y++) {
-                        const uint32_t mj = b.tcc_md[5 * (size_t)j + y];
-                        for (uint32_t x = 0; x < nm; x++) shared += mj == m[x] ? 1u : 0u;
+                    if (j != i) {
+                        const uint32_t tj = tcc_type(b, n5, j);
+                        const double qj = b.tcc_q[j];
+                        const bool better =
+                            tj < ti || (tj == ti && (qj < qi || (qj == qi && tcc_index(b, n5, j) < xi)));
+                        if (better) {
+                            const uint32_t nj = b.tcc_nm[j];
+                            uint32_t shared = 0;
+                            for (uint32_t y = 0; y < nj; y++) {
+                                const uint32_t mj = b.tcc_md[5 * (size_t)j + y];
+#pragma unroll
+                                for (uint32_t x = 0; x < 5u; x++) shared += mj == m[x] ? 1u : 0u;
+                            }
+                            drop = 2u * shared > min(nm, nj);
+                        }
                     }
-                    if (2u * shared > min(nm, nj)) keep = false;
                 }
+                if (__ballot(drop) & gmask) break;
             }
         }
-        b.tcc_keep[i] = keep ? 1u : 0u;
+        const bool any = (__ballot(drop) & gmask) != 0;
+        if (lane == 0) b.tcc_keep[i] = any ? 0u : 1u;
     }
 }
 
@@ -2341,7 +2372,7 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
         L.launch("tcc_prep", k_tcc_prep, grid_for(cap_tcc), blk, b, (const Totals *)t);
         L.scan(b.md_tcc_cnt, b.md_tcc_off, &t->n_md, b.cap_md, &t->n_tccm, "scan_tcc");
         L.launch("tcc_fill", k_tcc_fill, grid_for(cap_tcc), blk, b, (const Totals *)t);
-        L.launch("tcc_decide", k_tcc_decide, grid_for(cap_tcc), blk, b, (const Totals *)t);
+        L.launch("tcc_decide", k_tcc_decide, grid_for(cap_tcc * kTccLanes), blk, b, (const Totals *)t);
     }
     L.launch("event_table", k_event_table, grid_for(b.cap_ev + 1), blk, b, (const Totals *)t, c);
     L.end_stages();

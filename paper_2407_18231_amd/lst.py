@@ -333,15 +333,20 @@ class Context:
             self.L.lst_free_output(o)
 
     def run_batch(self, evs: list) -> list:
-        es = [EventIn(ev) for ev in evs]
+        return self.run_batch_in([EventIn(ev) for ev in evs])
+
+    def run_batch_in(self, es: list, fetch: bool = True):
+        """lst_run_batch of events already marshalled (EventIn); fetch=False
+        drops the lists (timing of the library call alone)."""
         arr = (lst_event_in * len(es))(*[e.c for e in es])
         outs = (_P(lst_event_out) * len(es))()
         self._check(self.L.lst_run_batch(self.h, arr, len(es), outs))
         res = []
         for o in outs:
-            res.append(_out_to_dict(o.contents))
+            if fetch:
+                res.append(_out_to_dict(o.contents))
             self.L.lst_free_output(o)
-        return res
+        return res if fetch else None
 
     def submit(self, ev: dict) -> int:
         e = EventIn(ev)

@@ -338,13 +338,13 @@ def _md_pairs(key):
     return {(hits[i], hits[i + 1]) for i in range(0, len(hits), 2)}
 
 
-def _oracle_cleaned(geom, ev):
+def _oracle_cleaned(geom, ev, params=None):
     """The oracle's accepted candidates and the subset its duplicate cleaning
     keeps, as keys, and the candidates whose cleaning may depend on a
     borderline one: the flagged candidates and every candidate sharing an MD
     with one of them (a device that kept or dropped the flagged candidate
     may rank its neighbours differently)."""
-    ores = oracle.run(geom, ev)
+    ores = oracle.run(geom, ev, params)
     ks = oracle.object_keys(ores["md"], ores["ls"], ores["t3"], ores["t5"], ores["pt3"], ores["pt5"],
                             ores["tc"])["tc"]
     st = ores["tc_st"]
@@ -382,6 +382,27 @@ def test_tc_cleaning_parity(geo):
     with lst.Context() as c:
         c.load_geometry(g)
         assert c.run_event(evs[0])["tcc"] is None
+
+
+def test_tc_cleaning_parity_skip_layer(geo):
+    """Duplicate cleaning with skip-layer links, where one track leaves tens
+    of candidates on each of its MDs: the kept subset equals the oracle's
+    with the same links, per event and in a batch."""
+    g = geo["pu200"]
+    evs = [s.gen_event(g, s.config_pu(200), s.event_seed(2, i)) for i in (3, 4)]
+    with lst.Context(tc_clean=True, skip_layer=True, max_batch=4) as c:
+        c.load_geometry(g)
+        singles = [c.run_event(ev) for ev in evs]
+        batch = c.run_batch(evs)
+    for ev, r, rb in zip(evs, singles, batch):
+        acc, kept, flagged, affected = _oracle_cleaned(g, ev, oracle.Params(skip=True))
+        got = lst.result_keys(r)
+        print("candidates", len(acc), "kept", len(kept), "flagged", len(flagged), "affected", len(affected), flush=True)
+        assert len(affected) <= 0.02 * len(acc)
+        assert set(got["tc"]) - flagged == set(acc) - flagged
+        assert set(got["tcc"]) - affected == set(kept) - affected
+        assert np.array_equal(r["tcc"], rb["tcc"])
+        assert len(kept) < 0.25 * len(acc)
 
 
 def _seed_set(seeds, excused):
