@@ -140,6 +140,36 @@ def test_skip_layer_links():
     assert trk0 < trk1 and len(trk1) >= len(trk0) + 10, (len(trk0), len(trk1))
 
 
+def test_displaced_tracks_window_losses():
+    """Displaced tracks (production radius up to 35 cm) through the windows
+    derived for prompt tracks: near the beam line the windows keep every
+    true object; far out they keep every true MD but lose a part of the
+    segments and T5s (the segment azimuth window assumes a track from the
+    beam line).  Three events of 400 displaced tracks each, no pileup."""
+    g = s.make_geometry("pu200")
+    cfg = s.config_pu(0, n_displaced=400)
+    edges = (0.0, 5.0, 10.0, 35.0)
+    acc = {}
+    for seed in range(3):
+        ev = s.gen_event(g, cfg, 9000 + seed)
+        rv = ev["track_rv"]
+        kd = oracle.keyed(oracle.run(g, ev))
+        for lo, hi in zip(edges[:-1], edges[1:]):
+            tr = truth_objects(g, ev, (rv > 0) & (rv >= lo) & (rv < hi))
+            for k in ("md", "ls", "t5"):
+                found = {q for q, st in kd[k].items() if st & oracle.ST_ACC}
+                a = acc.setdefault((lo, k), [0, 0])
+                a[0] += len(tr[k] & found)
+                a[1] += len(tr[k])
+    eff = {key: f / t for key, (f, t) in acc.items()}
+    print({f"{lo:g}-{k}": round(v, 3) for (lo, k), v in sorted(eff.items())})
+    for k in ("md", "ls", "t5"):
+        assert eff[(0.0, k)] >= 0.97, k
+    assert eff[(10.0, "md")] >= 0.98
+    assert 0.5 <= eff[(10.0, "t5")] < 0.95
+    assert eff[(10.0, "ls")] < eff[(0.0, "ls")]
+
+
 def _tracks(n, pt, eta_lo, eta_hi, vz, seed):
     rng = np.random.default_rng(seed)
     q = np.where(rng.random(n) < 0.5, -1.0, 1.0)
