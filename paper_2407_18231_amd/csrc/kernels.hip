@@ -18,6 +18,8 @@
 // (no contraction: built with -ffp-contract=off), pixel-seed cuts in binary64.
 #include <hip/hip_runtime.h>
 
+#include <functional>
+
 #include <rocprofiler-sdk-roctx/roctx.h>
 
 #include "engine.h"
@@ -2320,43 +2322,75 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     L.wait(0);                           // the placement counts into the cleared T3 buckets
     L.launch("t3_place", k_t3_place, grid_for(b.cap_t3), blk, b, g, c, nsub_t3);
 
-    // side: a5 T5, its seed-lookup buckets (a6) and pT5 (a7)
+    // Two branches after the T3 placement: on the side stream a5 T5, its
+    // seed-lookup buckets (a6) and pT5 (a7); on the main stream the T3
+    // buckets (a6) and pT3 (a7), the longer of the two.  Every launch costs
+    // the host a few microseconds to enqueue (also when a captured graph is
+    // replayed, node after node), so the two branches' launches are enqueued
+    // in turn, the main branch's first: enqueued one branch after the other,
+    // the second started only once the first branch's dozen launches were
+    // queued, 50-75 us after the placement.
     L.fork(1);
-    L.on_side(true);
-    L.set_stage(LST_STAGE_T5);
-    const dim3 gt5 = grid_for(b.cap_t3);
-    const uint32_t nsub_t5 = gt5.x;
-    L.launch("t5_walk", k_t5, gt5, blk, b, t, c, nsub_t5, stats);
-    L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.t5s_sub, b.t5s_soff, b.cap_t5s, nsub_t5,
-             &t->n_t5s);
-    L.scan(b.t5_cnt, b.t5_off, &t->n_t3, b.cap_t3, &t->n_t5, "scan_t5");
-    L.launch("t5_place", k_t5_place, grid_for(b.cap_t5), blk, b, g, c, nsub_t5);
-    L.set_stage(LST_STAGE_SEED_LOOKUP);
-    L.scan(b.bk5_cnt, b.bk5_off, &t->n_bk, cap_bk, &t->n_bk5, "scan_bucket");
-    L.launch("bucket_scatter", k_bucket_scatter<1>, grid_for(b.cap_t5), blk, b, (const Totals *)t);
-    L.launch("pt5c_walk", k_ptc<1>, gwalk, blk, b, t, c, nsub, stats);
-    L.set_stage(LST_STAGE_PT);
-    L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.ptc5_sub, b.ptc5_soff, b.cap_ptc5, nsub,
-             &t->n_ptc5);
-    L.launch("pt5_eval", k_pt_eval<1>, dim3(nsub), blk, b, c, nsub);
-    L.scan(b.pt5_cnt, b.pt5_off, &t->n_pls, b.cap_pls, &t->n_pt5, "scan_pt");
-    L.launch("pt_place", k_pt_place<1>, dim3(nsub), blk, b, nsub);
-    L.launch("zero8", k_zero_u8, grid_for(b.cap_t5), blk, b.t5_used, &t->n_t5, b.cap_t5);
-    L.launch("pt_order", k_pt_order<1>, grid_for(b.cap_pt5), blk, b, (const Totals *)t);
-
-    // main: the T3 seed-lookup buckets (a6) and pT3 (a7)
+    struct Op {
+        int stage;
+        std::function<void()> run;
+    };
+    const Op side_ops[] = {
+        {LST_STAGE_T5, [&] { L.launch("t5_walk", k_t5, grid_for(b.cap_t3), blk, b, t, c, grid_for(b.cap_t3).x, stats); }},
+        {LST_STAGE_T5,
+         [&] {
+             L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.t5s_sub, b.t5s_soff, b.cap_t5s,
+                      grid_for(b.cap_t3).x, &t->n_t5s);
+         }},
+        {LST_STAGE_T5, [&] { L.scan(b.t5_cnt, b.t5_off, &t->n_t3, b.cap_t3, &t->n_t5, "scan_t5"); }},
+        {LST_STAGE_T5,
+         [&] { L.launch("t5_place", k_t5_place, grid_for(b.cap_t5), blk, b, g, c, grid_for(b.cap_t3).x); }},
+        {LST_STAGE_SEED_LOOKUP, [&] { L.scan(b.bk5_cnt, b.bk5_off, &t->n_bk, cap_bk, &t->n_bk5, "scan_bucket"); }},
+        {LST_STAGE_SEED_LOOKUP,
+         [&] { L.launch("bucket_scatter", k_bucket_scatter<1>, grid_for(b.cap_t5), blk, b, (const Totals *)t); }},
+        {LST_STAGE_SEED_LOOKUP, [&] { L.launch("pt5c_walk", k_ptc<1>, gwalk, blk, b, t, c, nsub, stats); }},
+        {LST_STAGE_PT,
+         [&] {
+             L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.ptc5_sub, b.ptc5_soff, b.cap_ptc5, nsub,
+                      &t->n_ptc5);
+         }},
+        {LST_STAGE_PT, [&] { L.launch("pt5_eval", k_pt_eval<1>, dim3(nsub), blk, b, c, nsub); }},
+        {LST_STAGE_PT, [&] { L.scan(b.pt5_cnt, b.pt5_off, &t->n_pls, b.cap_pls, &t->n_pt5, "scan_pt"); }},
+        {LST_STAGE_PT, [&] { L.launch("pt_place", k_pt_place<1>, dim3(nsub), blk, b, nsub); }},
+        {LST_STAGE_PT, [&] { L.launch("zero8", k_zero_u8, grid_for(b.cap_t5), blk, b.t5_used, &t->n_t5, b.cap_t5); }},
+        {LST_STAGE_PT,
+         [&] { L.launch("pt_order", k_pt_order<1>, grid_for(b.cap_pt5), blk, b, (const Totals *)t); }},
+    };
+    const Op main_ops[] = {
+        {LST_STAGE_SEED_LOOKUP, [&] { L.scan(b.bk3_cnt, b.bk3_off, &t->n_bk, cap_bk, &t->n_bk3, "scan_bucket"); }},
+        {LST_STAGE_SEED_LOOKUP,
+         [&] { L.launch("bucket_scatter", k_bucket_scatter<0>, grid_for(b.cap_t3), blk, b, (const Totals *)t); }},
+        {LST_STAGE_SEED_LOOKUP, [&] { L.launch("pt3c_walk", k_ptc<0>, gwalk, blk, b, t, c, nsub, stats); }},
+        {LST_STAGE_PT,
+         [&] {
+             L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.ptc3_sub, b.ptc3_soff, b.cap_ptc3, nsub,
+                      &t->n_ptc3);
+         }},
+        {LST_STAGE_PT, [&] { L.launch("pt3_eval", k_pt_eval<0>, dim3(nsub), blk, b, c, nsub); }},
+        {LST_STAGE_PT, [&] { L.scan(b.pt3_cnt, b.pt3_off, &t->n_pls, b.cap_pls, &t->n_pt3, "scan_pt"); }},
+        {LST_STAGE_PT, [&] { L.launch("pt_place", k_pt_place<0>, dim3(nsub), blk, b, nsub); }},
+        {LST_STAGE_PT,
+         [&] { L.launch("pt_order", k_pt_order<0>, grid_for(b.cap_pt3), blk, b, (const Totals *)t); }},
+    };
+    const size_t n_side = sizeof(side_ops) / sizeof(side_ops[0]), n_main = sizeof(main_ops) / sizeof(main_ops[0]);
+    for (size_t k = 0; k < std::max(n_side, n_main); k++) {
+        if (k < n_main) {
+            L.on_side(false);
+            L.set_stage(main_ops[k].stage);
+            main_ops[k].run();
+        }
+        if (k < n_side) {
+            L.on_side(true);
+            L.set_stage(side_ops[k].stage);
+            side_ops[k].run();
+        }
+    }
     L.on_side(false);
-    L.set_stage(LST_STAGE_SEED_LOOKUP);
-    L.scan(b.bk3_cnt, b.bk3_off, &t->n_bk, cap_bk, &t->n_bk3, "scan_bucket");
-    L.launch("bucket_scatter", k_bucket_scatter<0>, grid_for(b.cap_t3), blk, b, (const Totals *)t);
-    L.launch("pt3c_walk", k_ptc<0>, gwalk, blk, b, t, c, nsub, stats);
-    L.set_stage(LST_STAGE_PT);
-    L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.ptc3_sub, b.ptc3_soff, b.cap_ptc3, nsub,
-             &t->n_ptc3);
-    L.launch("pt3_eval", k_pt_eval<0>, dim3(nsub), blk, b, c, nsub);
-    L.scan(b.pt3_cnt, b.pt3_off, &t->n_pls, b.cap_pls, &t->n_pt3, "scan_pt");
-    L.launch("pt_place", k_pt_place<0>, dim3(nsub), blk, b, nsub);
-    L.launch("pt_order", k_pt_order<0>, grid_for(b.cap_pt3), blk, b, (const Totals *)t);
 
     // a8: track candidates, once both branches are done
     L.mark(1);
