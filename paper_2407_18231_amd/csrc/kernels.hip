@@ -2257,27 +2257,45 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     L.set_stage(LST_STAGE_INGEST);
     launch_setup(L, b, t, c);
     L.fork(0);
-    L.on_side(true);
-    L.set_stage(LST_STAGE_SEED_LOOKUP);
-    L.launch("pls_prep", k_pls_prep, grid_for(b.cap_pls), blk, b, t, c);
-    L.launch("road", k_road, grid_for(cap_pu), blk, b, (const Totals *)t, g, c);
-    // counters of later stages that need clearing
-    L.launch("zero", k_zero_u32, grid_for((uint64_t)cap_bk + 1), blk, b.bk3_cnt, &t->n_bk, cap_bk, 1u);
-    L.launch("zero", k_zero_u32, grid_for((uint64_t)cap_bk + 1), blk, b.bk5_cnt, &t->n_bk, cap_bk, 1u);
-    L.launch("zero", k_zero_u32, grid_for((uint64_t)b.cap_pls + 1), blk, b.pt3_cnt, &t->n_pls, b.cap_pls, 1u);
-    L.launch("zero", k_zero_u32, grid_for((uint64_t)b.cap_pls + 1), blk, b.pt5_cnt, &t->n_pls, b.cap_pls, 1u);
-    L.launch("zero8", k_zero_u8, grid_for(b.cap_pls), blk, b.pls_used5, &t->n_pls, b.cap_pls);
-    L.launch("zero8", k_zero_u8, grid_for(b.cap_pls), blk, b.pls_used3, &t->n_pls, b.cap_pls);
-    L.mark(0);                           // the main stream waits for this only before its seed-lookup stage
-    L.on_side(false);
-    // a1: hit ingest & sort by (event, module, sensor)
-    L.set_stage(LST_STAGE_INGEST);
+    // Side: the seed quantities and roads, and the counters of later stages
+    // that need clearing; main: a1, hit ingest and sort by (event, module,
+    // sensor).  Enqueued in turn, the main stream's first (the enqueueing
+    // costs of the branches after the T3 placement, below, hold here too).
     const uint32_t n_sl = (2u * n_mod + g.hist_slice - 1u) / g.hist_slice;
     const dim3 gh((unsigned)std::min<uint64_t>((uint64_t)b.cap_ev * n_sl, kMaxGrid));
-    L.launch_lds("hit_hist", k_hit_hist, gh, dim3(kHistBlock), g.hist_slice * 4u, b, t, n_mod, g.hist_slice);
-    L.scan(b.bin_cnt, b.bin_off, &t->n_bins, b.cap_ev * 2u * n_mod, &t->n_sorted, "scan_hits");
-    L.launch("hit_scatter", k_hit_scatter, grid_for(b.cap_hits), blk, b, (const Totals *)t);
-    L.launch("hit_gather", k_hit_gather, grid_for(b.cap_hits), blk, b, t, g.mod_ext, n_mod);
+    const std::function<void()> ingest_ops[] = {
+        [&] {
+            L.launch_lds("hit_hist", k_hit_hist, gh, dim3(kHistBlock), g.hist_slice * 4u, b, t, n_mod,
+                         g.hist_slice);
+        },
+        [&] { L.scan(b.bin_cnt, b.bin_off, &t->n_bins, b.cap_ev * 2u * n_mod, &t->n_sorted, "scan_hits"); },
+        [&] { L.launch("hit_scatter", k_hit_scatter, grid_for(b.cap_hits), blk, b, (const Totals *)t); },
+        [&] { L.launch("hit_gather", k_hit_gather, grid_for(b.cap_hits), blk, b, t, g.mod_ext, n_mod); },
+    };
+    const std::function<void()> seed_ops[] = {
+        [&] { L.launch("pls_prep", k_pls_prep, grid_for(b.cap_pls), blk, b, t, c); },
+        [&] { L.launch("road", k_road, grid_for(cap_pu), blk, b, (const Totals *)t, g, c); },
+        [&] {
+            L.launch("zero", k_zero_u32, grid_for((uint64_t)cap_bk + 1), blk, b.bk3_cnt, &t->n_bk, cap_bk, 1u);
+            L.launch("zero", k_zero_u32, grid_for((uint64_t)cap_bk + 1), blk, b.bk5_cnt, &t->n_bk, cap_bk, 1u);
+        },
+        [&] {
+            L.launch("zero", k_zero_u32, grid_for((uint64_t)b.cap_pls + 1), blk, b.pt3_cnt, &t->n_pls, b.cap_pls, 1u);
+            L.launch("zero", k_zero_u32, grid_for((uint64_t)b.cap_pls + 1), blk, b.pt5_cnt, &t->n_pls, b.cap_pls, 1u);
+            L.launch("zero8", k_zero_u8, grid_for(b.cap_pls), blk, b.pls_used5, &t->n_pls, b.cap_pls);
+            L.launch("zero8", k_zero_u8, grid_for(b.cap_pls), blk, b.pls_used3, &t->n_pls, b.cap_pls);
+        },
+    };
+    for (size_t k = 0; k < 4; k++) {
+        L.on_side(false);
+        L.set_stage(LST_STAGE_INGEST);
+        ingest_ops[k]();
+        L.on_side(true);
+        L.set_stage(LST_STAGE_SEED_LOOKUP);
+        seed_ops[k]();
+    }
+    L.mark(0);                           // the main stream waits for this only before its seed-lookup stage
+    L.on_side(false);
     // a2: mini-doublets
     L.set_stage(LST_STAGE_MD);
     // small batches: count and fill in place for latency; large ones: pooled walk
