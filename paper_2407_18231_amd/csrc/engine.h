@@ -274,6 +274,11 @@ struct Launcher {
 
     void scan(const uint32_t *in, uint32_t *out, const uint32_t *n_ptr, uint32_t cap, uint32_t *total,
               const char *name);
+    // scan() whose first pass also turns a walk's sub-list sizes into region
+    // offsets (soff[0..nsub], need: the capacity the sub-lists needed)
+    void scan_sub(const uint32_t *in, uint32_t *out, const uint32_t *n_ptr, uint32_t cap, uint32_t *total,
+                  const char *name, const uint32_t *sub, uint32_t *soff, uint32_t cap_total, uint32_t nsub,
+                  uint32_t *need);
 };
 
 void launch_setup(Launcher &L, const Batch &b, Totals *t, const Consts &c);

@@ -82,13 +82,12 @@ __device__ inline uint32_t scan_chunk(uint32_t n, uint32_t nb)
 // values, four per thread as one 16-byte load); then every block sums the
 // partial sums of the blocks before it (at most kScanGrid, from L2) for its
 // carry and scans its chunk again, and the last block writes the total.
-__global__ __launch_bounds__(kScanBlock) void k_scan_up(const uint32_t *__restrict__ in,
-                                                        const uint32_t *n_ptr, uint32_t cap,
-                                                        uint32_t *__restrict__ part)
+__device__ inline void scan_up_block(const uint32_t *__restrict__ in, const uint32_t *n_ptr, uint32_t cap,
+                                     uint32_t *__restrict__ part, uint32_t nblocks, uint32_t bid)
 {
     const uint32_t n = min(*n_ptr, cap);
-    const uint32_t chunk = scan_chunk(n, gridDim.x);
-    const uint32_t start = min(blockIdx.x * chunk, n);
+    const uint32_t chunk = scan_chunk(n, nblocks);
+    const uint32_t start = min(bid * chunk, n);
     const uint32_t end = min(start + chunk, n);
     uint32_t s = 0;
     for (uint32_t base = start; base < end; base += kScanTile) {
@@ -104,7 +103,14 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_up(const uint32_t *__restri
     }
     uint32_t tot;
     block_excl_scan(s, tot);
-    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+    if (threadIdx.x == 0) part[bid] = tot;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_up(const uint32_t *__restrict__ in,
+                                                        const uint32_t *n_ptr, uint32_t cap,
+                                                        uint32_t *__restrict__ part)
+{
+    scan_up_block(in, n_ptr, cap, part, gridDim.x, blockIdx.x);
 }
 
 __global__ __launch_bounds__(kScanBlock) void k_scan_down(const uint32_t *__restrict__ in,
@@ -1847,9 +1853,8 @@ __global__ __launch_bounds__(256) void k_ptc(const Batch b, Totals *t, const Con
 // run of consecutive regions) to dense offsets soff[0..nsub].  need receives
 // the total or, when a region overflowed, the list capacity that holds it
 // (the host then grows the list and runs the batch again).
-__global__ __launch_bounds__(256) void k_sub_offsets(const uint32_t *__restrict__ sub,
-                                                     uint32_t *__restrict__ soff, uint32_t cap_total,
-                                                     uint32_t nsub, uint32_t *need)
+__device__ inline void sub_offsets_block(const uint32_t *__restrict__ sub, uint32_t *__restrict__ soff,
+                                         uint32_t cap_total, uint32_t nsub, uint32_t *need)
 {
     __shared__ uint32_t s_max;
     const uint32_t cap = cap_total / nsub;
@@ -1875,6 +1880,29 @@ __global__ __launch_bounds__(256) void k_sub_offsets(const uint32_t *__restrict_
         soff[nsub] = tot;
         *need = s_max > cap ? (uint32_t)min(0xFFFFFFF0ull, (unsigned long long)s_max * nsub) : tot;
     }
+}
+
+__global__ __launch_bounds__(256) void k_sub_offsets(const uint32_t *__restrict__ sub,
+                                                     uint32_t *__restrict__ soff, uint32_t cap_total,
+                                                     uint32_t nsub, uint32_t *need)
+{
+    sub_offsets_block(sub, soff, cap_total, nsub, need);
+}
+
+// The first pass of a scan (blocks 0 .. gridDim.x - 2) and, in the last
+// block, the region offsets of a walk's sub-lists: both read only what the
+// walk wrote, so one launch does both (one kernel boundary fewer per stage).
+__global__ __launch_bounds__(kScanBlock) void k_scan_up_sub(const uint32_t *__restrict__ in,
+                                                            const uint32_t *n_ptr, uint32_t cap,
+                                                            uint32_t *__restrict__ part,
+                                                            const uint32_t *__restrict__ sub,
+                                                            uint32_t *__restrict__ soff, uint32_t cap_total,
+                                                            uint32_t nsub, uint32_t *need)
+{
+    if (blockIdx.x == gridDim.x - 1u)
+        sub_offsets_block(sub, soff, cap_total, nsub, need);
+    else
+        scan_up_block(in, n_ptr, cap, part, gridDim.x - 1u, blockIdx.x);
 }
 
 // full seed cuts, one thread per pair; an accepted pair draws its rank
@@ -2201,6 +2229,18 @@ void Launcher::scan(const uint32_t *in, uint32_t *out, const uint32_t *n_ptr, ui
     launch(name, k_scan_down, dim3(nb), dim3(kScanBlock), in, n_ptr, cap, (const uint32_t *)pt, out, total);
 }
 
+void Launcher::scan_sub(const uint32_t *in, uint32_t *out, const uint32_t *n_ptr, uint32_t cap, uint32_t *total,
+                        const char *name, const uint32_t *sub, uint32_t *soff, uint32_t cap_total, uint32_t nsub,
+                        uint32_t *need)
+{
+    const uint32_t nb = (uint32_t)std::max<uint64_t>(
+        1u, std::min<uint64_t>(kScanGrid, ((uint64_t)cap + kScanTile - 1) / kScanTile));
+    uint32_t *pt = (side && cur == side) ? part_side : part;
+    launch(name, k_scan_up_sub, dim3(nb + 1), dim3(kScanBlock), in, n_ptr, cap, pt, sub, soff, cap_total, nsub,
+           need);
+    launch(name, k_scan_down, dim3(nb), dim3(kScanBlock), in, n_ptr, cap, (const uint32_t *)pt, out, total);
+}
+
 static inline dim3 grid_for(uint64_t units) { return dim3(walk_blocks(units)); }
 
 using LsWalk = void (*)(const Batch, Totals *, const DevGeom, const Consts, uint32_t, int);
@@ -2308,8 +2348,8 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     } else {
         const uint32_t nsub_md = gmd.x;
         L.launch("md_walk", k_md, gmd, blk, b, t, g, c, nsub_md, stats);
-        L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.mds_sub, b.mds_soff, b.cap_mds, nsub_md, &t->n_mds);
-        L.scan(b.md_cnt, b.md_hoff, &t->n_sorted, b.cap_hits, &t->n_md, "scan_md");
+        L.scan_sub(b.md_cnt, b.md_hoff, &t->n_sorted, b.cap_hits, &t->n_md, "scan_md", b.mds_sub, b.mds_soff,
+                   b.cap_mds, nsub_md, &t->n_mds);
         L.launch("md_place", k_md_place, grid_for(std::max<uint64_t>(b.cap_md, (uint64_t)b.cap_ev * n_mod + 1)), blk,
                  b, (const Totals *)t, g, c, nsub_md);
     }
@@ -2324,9 +2364,8 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
         const dim3 gls = grid_for(b.cap_md);
         const uint32_t nsub_ls = gls.x;
         L.launch("ls_walk", ls_walk_kernel(c.ls_group, c.ls_waves), gls, blk, b, t, g, c, nsub_ls, stats);
-        L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.lss_sub, b.lss_soff, b.cap_lss, nsub_ls,
-                 &t->n_lss);
-        L.scan(b.ls_cnt, b.ls_off, &t->n_md, b.cap_md, &t->n_ls, "scan_ls");
+        L.scan_sub(b.ls_cnt, b.ls_off, &t->n_md, b.cap_md, &t->n_ls, "scan_ls", b.lss_sub, b.lss_soff, b.cap_lss,
+                   nsub_ls, &t->n_lss);
         L.launch("ls_place", k_ls_place, grid_for(b.cap_ls), blk, b, nsub_ls);
     }
     // a4: T3
@@ -2334,9 +2373,8 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
     const dim3 gt3 = grid_for(b.cap_ls);
     const uint32_t nsub_t3 = gt3.x;
     L.launch("t3_walk", k_t3, gt3, blk, b, t, c, nsub_t3, stats);
-    L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.t3s_sub, b.t3s_soff, b.cap_t3s, nsub_t3,
-             &t->n_t3s);
-    L.scan(b.t3_cnt, b.t3_off, &t->n_ls, b.cap_ls, &t->n_t3, "scan_t3");
+    L.scan_sub(b.t3_cnt, b.t3_off, &t->n_ls, b.cap_ls, &t->n_t3, "scan_t3", b.t3s_sub, b.t3s_soff, b.cap_t3s,
+               nsub_t3, &t->n_t3s);
     L.wait(0);                           // the placement counts into the cleared T3 buckets
     L.launch("t3_place", k_t3_place, grid_for(b.cap_t3), blk, b, g, c, nsub_t3);
 
@@ -2357,10 +2395,9 @@ void enqueue_chain(Launcher &L, const Batch &b, Totals *t, const DevGeom &g, con
         {LST_STAGE_T5, [&] { L.launch("t5_walk", k_t5, grid_for(b.cap_t3), blk, b, t, c, grid_for(b.cap_t3).x, stats); }},
         {LST_STAGE_T5,
          [&] {
-             L.launch("sub_offsets", k_sub_offsets, dim3(1), blk, b.t5s_sub, b.t5s_soff, b.cap_t5s,
-                      grid_for(b.cap_t3).x, &t->n_t5s);
+             L.scan_sub(b.t5_cnt, b.t5_off, &t->n_t3, b.cap_t3, &t->n_t5, "scan_t5", b.t5s_sub, b.t5s_soff,
+                        b.cap_t5s, grid_for(b.cap_t3).x, &t->n_t5s);
          }},
-        {LST_STAGE_T5, [&] { L.scan(b.t5_cnt, b.t5_off, &t->n_t3, b.cap_t3, &t->n_t5, "scan_t5"); }},
         {LST_STAGE_T5,
          [&] { L.launch("t5_place", k_t5_place, grid_for(b.cap_t5), blk, b, g, c, grid_for(b.cap_t3).x); }},
         {LST_STAGE_SEED_LOOKUP, [&] { L.scan(b.bk5_cnt, b.bk5_off, &t->n_bk, cap_bk, &t->n_bk5, "scan_bucket"); }},
